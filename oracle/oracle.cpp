@@ -1,0 +1,435 @@
+// FP64 CPU oracle for the vortex-particle hot path — TEST INFRASTRUCTURE ONLY.
+//
+// This file is the plain, slow reference against which the HIP library is checked.
+// Only the test-suite, the smoke check and the benchmark's CPU-baseline leg load it;
+// the product path never links or calls it, and it shares no code, header or constant
+// with the GPU library.
+//
+// What it computes (paper: Fu & Laurendeau, "Nonlinear Unsteady Vortex-Lattice
+// Vortex-Particle Method with Adaptive Wake Conversion", Sec. II.B, Eqs. 2-5, and
+// Sec. II.A for the Vatistas-cored segments):
+//
+//   * particle field  w(x) = sum_j Gamma_j zeta_sigma(x - x_j)                 (Eq. 2)
+//     with the 3-D Gaussian zeta_sigma(rho) = (2 pi sigma^2)^(-3/2) exp(-rho^2/2) (Eq. 3)
+//   * velocity (Biot-Savart of that field, Eq. 4's right-hand side)
+//         u_i = sum_{j != i} g(s) Gamma_j x r,  r = x_i - x_j, s = |r|
+//         g(s) = q(rho) / (4 pi s^3),  q(rho) = erf(rho/sqrt2) - c0 rho exp(-rho^2/2)
+//     q is the fraction of a unit Gaussian blob inside radius rho, c0 = sqrt(2/pi).
+//   * stretching, transposed scheme (first term of Eq. 5, (Gamma_i . grad^T) u):
+//         dGamma_i/dt = sum_{j != i} [ g Gamma_i x Gamma_j + h (Gamma_i . (Gamma_j x r)) r ]
+//     h(s) = g'(s)/s.  Classical option (Gamma_i . grad) u:
+//         sum_{j != i} [ g Gamma_j x Gamma_i + h (r . Gamma_i) (Gamma_j x r) ]
+//     The viscous term of Eq. 5 is not part of this path (nu = 0).
+//   * straight-segment velocity with a Vatistas core (Sec. II.A): finite-segment
+//     Biot-Savart multiplied by d^2 / (d^(2n) + rc^(2n))^(1/n), d = distance to the line.
+//   * low-storage third-order Runge-Kutta (Williamson 2N-storage, Sec. II.B) for
+//     (x_i, Gamma_i), and the loss L = sum_c (u_c . z)^2 on control points.
+//   * forward-mode tangents of all of the above on dual numbers (gradient oracle).
+//
+// Kernel weights are evaluated exactly as defined: for rho >= 1 the closed form with
+// std::erf/std::exp; for rho < 1 the Taylor series of q(rho)/rho^3 (and of the derived
+// weights) in rho^2, because the closed form cancels catastrophically there.  There is
+// no far-field shortcut.  Per-target sums use Neumaier compensation, and the file is
+// compiled with -ffp-contract=off.
+//
+// Readings where the paper is silent (see the design notes): source-sigma rule by
+// default, symmetric rule sigma_ij^2 = (sigma_i^2 + sigma_j^2)/2 as an option; self pair
+// excluded by index; Vatistas exponent n given by the caller (2 by default); segments
+// with a vanishing arm or length contribute nothing.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <omp.h>
+
+namespace {
+
+const double kPi = 3.14159265358979323846264338327950288;
+const double kC0 = 0.79788456080286535587989211986876373;  // sqrt(2/pi)
+const double kInvSqrt2 = 0.70710678118654752440084436210484903;
+const double kTwoOverSqrtPi = 1.12837916709551257389615890312154517;
+
+// ---------------------------------------------------------------- dual numbers
+// Forward-mode scalar: value v and one directional derivative d.
+struct Dual {
+    double v, d;
+    Dual() : v(0), d(0) {}
+    Dual(double a) : v(a), d(0) {}
+    Dual(double a, double b) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+    return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+}
+inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+inline bool operator<(Dual a, double b) { return a.v < b; }
+inline double val(double a) { return a; }
+inline double val(Dual a) { return a.v; }
+inline Dual dsqrt(Dual a) { double s = std::sqrt(a.v); return Dual(s, s > 0 ? a.d / (2 * s) : 0.0); }
+inline double dsqrt(double a) { return std::sqrt(a); }
+inline Dual dexp(Dual a) { double e = std::exp(a.v); return Dual(e, e * a.d); }
+inline double dexp(double a) { return std::exp(a); }
+inline Dual derf(Dual a) { return Dual(std::erf(a.v), kTwoOverSqrtPi * std::exp(-a.v * a.v) * a.d); }
+inline double derf(double a) { return std::erf(a); }
+inline Dual dpow(Dual a, double p) {  // a > 0
+    double r = std::pow(a.v, p);
+    return Dual(r, p * std::pow(a.v, p - 1.0) * a.d);
+}
+inline double dpow(double a, double p) { return std::pow(a, p); }
+
+// ---------------------------------------------------------------- compensated sum
+// Neumaier's variant of Kahan summation, applied separately to value and tangent.
+struct Neumaier {
+    double s = 0, c = 0;
+    void add(double x) {
+        double t = s + x;
+        if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+    }
+    double get() const { return s + c; }
+};
+template <class T> struct Acc;
+template <> struct Acc<double> {
+    Neumaier a;
+    void add(double x) { a.add(x); }
+    double get() const { return a.get(); }
+};
+template <> struct Acc<Dual> {
+    Neumaier a, b;
+    void add(Dual x) { a.add(x.v); b.add(x.d); }
+    Dual get() const { return Dual(a.get(), b.get()); }
+};
+
+template <class T> struct V3 { T x, y, z; };
+template <class T> inline V3<T> cross(const V3<T>& a, const V3<T>& b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class T> inline T dot(const V3<T>& a, const V3<T>& b) {
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <class T> inline V3<T> sub(const V3<T>& a, const V3<T>& b) {
+    return {a.x - b.x, a.y - b.y, a.z - b.z};
+}
+
+// ---------------------------------------------------------------- kernel weights
+// Dimensionless weights of the Gaussian blob as functions of rho (Eq. 3):
+//   Gw = q/rho^3,  Hw = (rho q' - 3 q)/rho^5,  Kw = (rho^2 q'' - 7 rho q' + 15 q)/rho^7
+// so that g = Gw/(4 pi sigma^3), h = g'/s = Hw/(4 pi sigma^5), k = h'/s = Kw/(4 pi sigma^7).
+// For rho < 1 the Taylor series in t = rho^2 (20 terms); otherwise the closed form.
+// Taylor series: q(rho) = c0 sum_n (-1)^n rho^(2n+3) / ((2n+3) 2^n n!).
+const int kSeriesTerms = 20;
+
+template <class T>
+void weights(T rho, T* Gw, T* Hw, T* Kw) {
+    if (rho < 1.0) {
+        T t = rho * rho;
+        T sg(0.0), sh(0.0), sk(0.0);
+        // a_n = 1 / (2^n n!)
+        double a[kSeriesTerms + 1];
+        a[0] = 1.0;
+        for (int n = 1; n <= kSeriesTerms; ++n) a[n] = a[n - 1] / (2.0 * n);
+        // Sum from the highest term down (terms decrease in magnitude for t < 1).
+        for (int n = kSeriesTerms; n >= 0; --n) {
+            double sgn = (n % 2) ? -1.0 : 1.0;
+            double cg = sgn * a[n] / (2 * n + 3);
+            sg = sg * t + T(cg);
+            if (n >= 1) sh = sh * t + T(cg * 2.0 * n);
+            if (n >= 2) sk = sk * t + T(cg * 4.0 * n * (n - 1));
+        }
+        *Gw = T(kC0) * sg;
+        *Hw = T(kC0) * sh;
+        *Kw = T(kC0) * sk;
+    } else {
+        T e = dexp(T(-0.5) * rho * rho);
+        T q = derf(rho * T(kInvSqrt2)) - T(kC0) * rho * e;
+        T r2 = rho * rho;
+        T r3 = r2 * rho;
+        T r5 = r3 * r2;
+        T r7 = r5 * r2;
+        *Gw = q / r3;
+        *Hw = (T(kC0) * r3 * e - T(3.0) * q) / r5;
+        *Kw = (T(15.0) * q - T(kC0) * e * (T(5.0) * r3 + r5)) / r7;
+    }
+}
+
+// g, h (and k) at separation s for core size sigma.
+template <class T>
+void ghk(T s, T sigma, T* g, T* h, T* k) {
+    T rho = s / sigma;
+    T Gw, Hw, Kw;
+    weights(rho, &Gw, &Hw, &Kw);
+    T s2 = sigma * sigma;
+    T s3 = s2 * sigma;
+    T s5 = s3 * s2;
+    T s7 = s5 * s2;
+    T f = T(1.0 / (4.0 * kPi));
+    *g = f * Gw / s3;
+    *h = f * Hw / s5;
+    if (k) *k = f * Kw / s7;
+}
+
+template <class T> inline V3<T> load3(const T* a, int64_t ld, int64_t i) {
+    return {a[i], a[ld + i], a[2 * ld + i]};
+}
+
+// ---------------------------------------------------------------- particle sums
+// u_t and dGamma_t/dt at every target t from every source j (Eqs. 2-5).
+// Arrays are [3][n] (component-major).  gam_t == nullptr: velocity only.
+// excl[t] = index of the source that is the same particle as target t (skipped), or -1.
+template <class T>
+void eval_pairs(int64_t ns, const T* xs, const T* gs, const double* sgs,
+                int64_t nt, const T* xt, const T* gt, const double* sgt,
+                const int64_t* excl, int scheme, int sigma_rule, T* u, T* dg) {
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < nt; ++t) {
+        V3<T> xi = load3(xt, nt, t);
+        V3<T> Gi = {T(0.0), T(0.0), T(0.0)};
+        if (gt) Gi = load3(gt, nt, t);
+        Acc<T> au[3], ad[3];
+        for (int64_t j = 0; j < ns; ++j) {
+            if (excl && excl[t] == j) continue;
+            V3<T> xj = load3(xs, ns, j);
+            V3<T> Gj = load3(gs, ns, j);
+            V3<T> r = sub(xi, xj);
+            T s = dsqrt(dot(r, r));
+            double sig = sgs[j];
+            if (sigma_rule == 1) sig = std::sqrt(0.5 * (sgt[t] * sgt[t] + sgs[j] * sgs[j]));
+            T g, h;
+            ghk<T>(s, T(sig), &g, &h, nullptr);
+            V3<T> v = cross(Gj, r);
+            au[0].add(g * v.x);
+            au[1].add(g * v.y);
+            au[2].add(g * v.z);
+            if (gt) {
+                V3<T> term;
+                if (scheme == 0) {  // transposed
+                    V3<T> c = cross(Gi, Gj);
+                    T tau = dot(Gi, v);
+                    term = {g * c.x + h * tau * r.x, g * c.y + h * tau * r.y, g * c.z + h * tau * r.z};
+                } else {  // classical
+                    V3<T> c = cross(Gj, Gi);
+                    T rg = dot(r, Gi);
+                    term = {g * c.x + h * rg * v.x, g * c.y + h * rg * v.y, g * c.z + h * rg * v.z};
+                }
+                ad[0].add(term.x);
+                ad[1].add(term.y);
+                ad[2].add(term.z);
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            u[c * nt + t] = au[c].get();
+            if (gt) dg[c * nt + t] = ad[c].get();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- segments
+// Velocity at targets induced by straight vortex segments A->B with circulation gam
+// (Sec. II.A: Biot-Savart of the vortex-ring edges with the Vatistas core).
+template <class T>
+void eval_segments(int64_t nseg, const double* A, const double* B, const double* gam,
+                   double rc, int vn, int64_t nt, const T* xt, T* u) {
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < nt; ++t) {
+        V3<T> P = load3(xt, nt, t);
+        Acc<T> au[3];
+        for (int64_t k = 0; k < nseg; ++k) {
+            V3<T> a = {T(A[k]), T(A[nseg + k]), T(A[2 * nseg + k])};
+            V3<T> b = {T(B[k]), T(B[nseg + k]), T(B[2 * nseg + k])};
+            V3<T> r1 = sub(P, a), r2 = sub(P, b), r0 = sub(b, a);
+            T L0 = dsqrt(dot(r0, r0)), L1 = dsqrt(dot(r1, r1)), L2 = dsqrt(dot(r2, r2));
+            double eps = 1e-12 * std::fmax(val(L0), 1.0);
+            if (val(L0) < eps || val(L1) < eps || val(L2) < eps) continue;
+            V3<T> c = cross(r1, r2);
+            T c2 = dot(c, c);
+            T L02 = L0 * L0;
+            T d2 = c2 / L02;
+            T den;
+            if (rc == 0.0) den = c2;
+            else if (vn == 1) den = L02 * (d2 + T(rc * rc));
+            else den = L02 * dpow(dpow(d2, double(vn)) + T(std::pow(rc * rc, double(vn))), 1.0 / vn);
+            if (val(den) == 0.0) continue;
+            V3<T> e = {r1.x / L1 - r2.x / L2, r1.y / L1 - r2.y / L2, r1.z / L1 - r2.z / L2};
+            T f = T(gam[k] / (4.0 * kPi)) * dot(r0, e) / den;
+            au[0].add(f * c.x);
+            au[1].add(f * c.y);
+            au[2].add(f * c.z);
+        }
+        for (int c = 0; c < 3; ++c) u[c * nt + t] = au[c].get();
+    }
+}
+
+// ---------------------------------------------------------------- RK3 program
+// Williamson's low-storage third-order scheme, 2N-storage form:
+//   Q <- a_k Q + dt F(Y);  Y <- Y + b_k Q,   k = 1..3,
+// a = (0, -5/9, -153/128), b = (1/3, 15/16, 8/15), Y = (x, Gamma), F = (u, dGamma/dt).
+const double kRkA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+const double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+template <class T>
+void rk3_program(int64_t n, T* x, T* G, const double* sig, int nsteps, double dt, int scheme,
+                 int sigma_rule, int64_t m, const double* y, T* uc, T* loss) {
+    std::vector<T> qx(3 * n), qg(3 * n), fx(3 * n), fg(3 * n);
+    std::vector<int64_t> excl(n);
+    for (int64_t i = 0; i < n; ++i) excl[i] = i;
+    for (int step = 0; step < nsteps; ++step) {
+        for (int64_t i = 0; i < 3 * n; ++i) { qx[i] = T(0.0); qg[i] = T(0.0); }
+        for (int k = 0; k < 3; ++k) {
+            eval_pairs<T>(n, x, G, sig, n, x, G, sig, excl.data(), scheme, sigma_rule,
+                          fx.data(), fg.data());
+            for (int64_t i = 0; i < 3 * n; ++i) {
+                qx[i] = T(kRkA[k]) * qx[i] + T(dt) * fx[i];
+                qg[i] = T(kRkA[k]) * qg[i] + T(dt) * fg[i];
+                x[i] = x[i] + T(kRkB[k]) * qx[i];
+                G[i] = G[i] + T(kRkB[k]) * qg[i];
+            }
+        }
+    }
+    if (m > 0) {
+        std::vector<T> yt(3 * m);
+        for (int64_t i = 0; i < 3 * m; ++i) yt[i] = T(y[i]);
+        eval_pairs<T>(n, x, G, sig, m, yt.data(), nullptr, nullptr, nullptr, 0, 0, uc, nullptr);
+        Acc<T> l;
+        for (int64_t c = 0; c < m; ++c) l.add(uc[2 * m + c] * uc[2 * m + c]);
+        *loss = l.get();
+    } else {
+        *loss = T(0.0);
+    }
+}
+
+template <class T> void set_threads(int nth) {
+    if (nth > 0) omp_set_num_threads(nth);
+}
+
+}  // namespace
+
+// ================================================================ C entry points
+// All arrays are component-major [3][n] double.  Return 0 on success, nonzero on a bad
+// argument.  nthreads <= 0 keeps the OpenMP default.
+extern "C" {
+
+int orc_weights(double rho, double* Gw, double* Hw, double* Kw) {
+    if (!(rho >= 0.0)) return 1;
+    weights<double>(rho, Gw, Hw, Kw);
+    return 0;
+}
+
+int orc_ghk(double s, double sigma, double* g, double* h, double* k) {
+    if (!(s >= 0.0) || !(sigma > 0.0)) return 1;
+    ghk<double>(s, sigma, g, h, k);
+    return 0;
+}
+
+int orc_eval(int64_t ns, const double* xs, const double* gs, const double* sgs, int64_t nt,
+             const double* xt, const double* gt, const double* sgt, const int64_t* excl,
+             int scheme, int sigma_rule, double* u, double* dg, int nthreads) {
+    if (ns < 0 || nt < 0 || !xs || !gs || !sgs || !xt || !u) return 1;
+    if (gt && !dg) return 1;
+    if (sigma_rule == 1 && !sgt) return 1;
+    if (scheme < 0 || scheme > 1 || sigma_rule < 0 || sigma_rule > 1) return 1;
+    set_threads<double>(nthreads);
+    eval_pairs<double>(ns, xs, gs, sgs, nt, xt, gt, sgt, excl, scheme, sigma_rule, u, dg);
+    return 0;
+}
+
+// Tangent of orc_eval: (xs_d, gs_d) is the direction on the sources, (xt_d, gt_d) on
+// the targets; with self evaluation pass the same direction for both.
+int orc_eval_jvp(int64_t ns, const double* xs, const double* gs, const double* sgs,
+                 const double* xs_d, const double* gs_d, int64_t nt, const double* xt,
+                 const double* gt, const double* sgt, const double* xt_d, const double* gt_d,
+                 const int64_t* excl, int scheme, int sigma_rule, double* u, double* dg,
+                 double* u_d, double* dg_d, int nthreads) {
+    if (ns < 0 || nt < 0 || !xs || !gs || !sgs || !xt || !u || !xs_d || !gs_d || !xt_d || !u_d)
+        return 1;
+    if (gt && (!dg || !gt_d || !dg_d)) return 1;
+    if (sigma_rule == 1 && !sgt) return 1;
+    set_threads<double>(nthreads);
+    std::vector<Dual> Xs(3 * ns), Gs(3 * ns), Xt(3 * nt), Gt(gt ? 3 * nt : 0), U(3 * nt),
+        D(gt ? 3 * nt : 0);
+    for (int64_t i = 0; i < 3 * ns; ++i) { Xs[i] = Dual(xs[i], xs_d[i]); Gs[i] = Dual(gs[i], gs_d[i]); }
+    for (int64_t i = 0; i < 3 * nt; ++i) {
+        Xt[i] = Dual(xt[i], xt_d[i]);
+        if (gt) Gt[i] = Dual(gt[i], gt_d[i]);
+    }
+    eval_pairs<Dual>(ns, Xs.data(), Gs.data(), sgs, nt, Xt.data(), gt ? Gt.data() : nullptr, sgt,
+                     excl, scheme, sigma_rule, U.data(), gt ? D.data() : nullptr);
+    for (int64_t i = 0; i < 3 * nt; ++i) {
+        u[i] = U[i].v; u_d[i] = U[i].d;
+        if (gt) { dg[i] = D[i].v; dg_d[i] = D[i].d; }
+    }
+    return 0;
+}
+
+int orc_segments(int64_t nseg, const double* A, const double* B, const double* gam, double rc,
+                 int vn, int64_t nt, const double* xt, double* u, int nthreads) {
+    if (nseg < 0 || nt < 0 || !xt || !u || (nseg > 0 && (!A || !B || !gam))) return 1;
+    if (!(rc >= 0.0) || vn < 1) return 1;
+    set_threads<double>(nthreads);
+    eval_segments<double>(nseg, A, B, gam, rc, vn, nt, xt, u);
+    return 0;
+}
+
+// Runs nsteps RK3 steps from (x, G) in place, then the control-point velocity uc [3][m]
+// and the loss sum_c uc_z^2.
+int orc_rk3_program(int64_t n, double* x, double* G, const double* sig, int nsteps, double dt,
+                    int scheme, int sigma_rule, int64_t m, const double* y, double* uc,
+                    double* loss, int nthreads) {
+    if (n < 0 || m < 0 || nsteps < 0 || !x || !G || !sig || !loss || (m > 0 && (!y || !uc)))
+        return 1;
+    set_threads<double>(nthreads);
+    rk3_program<double>(n, x, G, sig, nsteps, dt, scheme, sigma_rule, m, y, uc, loss);
+    return 0;
+}
+
+// Directional derivative of the program's loss along (xd, Gd) at (x, G); x and G are left
+// unchanged.  Returns loss and dloss.
+int orc_rk3_program_jvp(int64_t n, const double* x, const double* G, const double* sig,
+                        const double* xd, const double* Gd, int nsteps, double dt, int scheme,
+                        int sigma_rule, int64_t m, const double* y, double* loss,
+                        double* dloss, int nthreads) {
+    if (n < 0 || m < 0 || nsteps < 0 || !x || !G || !sig || !xd || !Gd || !loss || !dloss)
+        return 1;
+    if (m > 0 && !y) return 1;
+    set_threads<double>(nthreads);
+    std::vector<Dual> X(3 * n), Gm(3 * n), UC(3 * (m > 0 ? m : 1));
+    for (int64_t i = 0; i < 3 * n; ++i) { X[i] = Dual(x[i], xd[i]); Gm[i] = Dual(G[i], Gd[i]); }
+    Dual L;
+    rk3_program<Dual>(n, X.data(), Gm.data(), sig, nsteps, dt, scheme, sigma_rule, m, y, UC.data(), &L);
+    *loss = L.v;
+    *dloss = L.d;
+    return 0;
+}
+
+// FP64 diagnostics of one evaluation (invariants of Eq. 1):
+// out[0..2] = sum Gamma_i, out[3..5] = sum dGamma_i/dt, out[6..8] = impulse 1/2 sum x_i x Gamma_i,
+// out[9..11] = its rate 1/2 sum (u_i x Gamma_i + x_i x dGamma_i/dt), out[12] = number of
+// non-finite entries among x, Gamma, u, dGamma/dt.
+int orc_diagnostics(int64_t n, const double* x, const double* G, const double* u, const double* dg,
+                    double* out) {
+    if (n < 0 || !x || !G || !u || !dg || !out) return 1;
+    Neumaier acc[12];
+    int64_t bad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        V3<double> xi = load3(x, n, i), Gi = load3(G, n, i), ui = load3(u, n, i), di = load3(dg, n, i);
+        V3<double> p = cross(xi, Gi);
+        V3<double> a = cross(ui, Gi);
+        V3<double> b = cross(xi, di);
+        double vals[12] = {Gi.x, Gi.y, Gi.z, di.x, di.y, di.z, 0.5 * p.x, 0.5 * p.y, 0.5 * p.z,
+                           0.5 * (a.x + b.x), 0.5 * (a.y + b.y), 0.5 * (a.z + b.z)};
+        for (int c = 0; c < 12; ++c) acc[c].add(vals[c]);
+        const double* all[4] = {x, G, u, dg};
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c)
+                if (!std::isfinite(all[k][c * n + i])) ++bad;
+    }
+    for (int c = 0; c < 12; ++c) out[c] = acc[c].get();
+    out[12] = double(bad);
+    return 0;
+}
+
+}  // extern "C"

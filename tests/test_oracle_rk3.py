@@ -1,0 +1,92 @@
+"""Pins for the oracle's time integration (low-storage RK3 of Sec. II.B) and its tangent.
+
+A co-rotating pair of parallel blobs has a closed-form motion (rigid rotation about the
+midpoint at a rate fixed by g(d)); the program must converge to it at third order.  The
+dual-number tangent of the whole program is checked by central differences.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _pair(d=0.04, gz=2e-3, sigma=0.03):
+    x = np.array([[-d / 2, d / 2], [0.0, 0.0], [0.0, 0.0]])
+    g = np.array([[0.0, 0.0], [0.0, 0.0], [gz, gz]])
+    return x, g, np.full(2, sigma)
+
+
+def test_corotating_pair_third_order():
+    x0, g0, s = _pair()
+    d = 0.04
+    gd, _, _ = oracle.ghk(d, 0.03)
+    omega = 2 * gd * 2e-3          # |u| = g d |Gamma| on a circle of radius d/2
+    T = 2.0 / omega                # about a third of a turn
+    errs = []
+    for nsteps in (8, 16, 32):
+        x, g, _, _ = oracle.rk3_program(x0, g0, s, nsteps, T / nsteps)
+        ang = omega * T
+        exact = np.array([[-d / 2 * math.cos(ang), d / 2 * math.cos(ang)],
+                          [-d / 2 * math.sin(ang), d / 2 * math.sin(ang)], [0.0, 0.0]])
+        assert np.array_equal(g, g0)  # parallel filaments do not stretch each other
+        errs.append(np.abs(x - exact).max())
+    assert 7.0 < errs[0] / errs[1] < 9.0 and 7.0 < errs[1] / errs[2] < 9.0
+
+
+# Butcher form of the 2N-storage coefficients A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15),
+# obtained by expanding the three register updates by hand.
+BUTCHER_A = ((0.0, 0.0), (1.0 / 3.0, 0.0), (-3.0 / 16.0, 15.0 / 16.0))
+BUTCHER_B = (1.0 / 6.0, 3.0 / 10.0, 8.0 / 15.0)
+
+
+def test_butcher_form_has_third_order():
+    """The four order conditions up to third order hold for the expanded tableau."""
+    c = [sum(row) for row in BUTCHER_A]
+    b = BUTCHER_B
+    assert sum(b) == pytest.approx(1.0, abs=1e-15)
+    assert sum(bi * ci for bi, ci in zip(b, c)) == pytest.approx(0.5, abs=1e-15)
+    assert sum(bi * ci * ci for bi, ci in zip(b, c)) == pytest.approx(1.0 / 3.0, abs=1e-15)
+    assert b[2] * BUTCHER_A[2][1] * c[1] == pytest.approx(1.0 / 6.0, abs=1e-15)
+
+
+def test_single_step_is_williamson_rk3():
+    """One program step equals the three-stage Butcher form evaluated with the oracle's RHS."""
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-0.05, 0.05, (3, 5))
+    g = rng.normal(0, 1e-3, (3, 5))
+    s = np.full(5, 0.03)
+    dt = 0.7
+
+    def F(x, g):
+        return oracle.eval_pairs(x, g, s)
+
+    A, b = BUTCHER_A, BUTCHER_B
+    k1 = F(x, g)
+    k2 = F(x + dt * A[1][0] * k1[0], g + dt * A[1][0] * k1[1])
+    k3 = F(x + dt * (A[2][0] * k1[0] + A[2][1] * k2[0]), g + dt * (A[2][0] * k1[1] + A[2][1] * k2[1]))
+    xe = x + dt * (b[0] * k1[0] + b[1] * k2[0] + b[2] * k3[0])
+    ge = g + dt * (b[0] * k1[1] + b[1] * k2[1] + b[2] * k3[1])
+    x1, g1, _, _ = oracle.rk3_program(x, g, s, 1, dt)
+    assert np.allclose(x1, xe, rtol=1e-13, atol=1e-16)
+    assert np.allclose(g1, ge, rtol=1e-12, atol=1e-18)
+
+
+def test_program_tangent_matches_central_differences():
+    rng = np.random.default_rng(6)
+    n = 24
+    x = rng.uniform(-0.1, 0.1, (3, n))
+    g = rng.normal(0, 1e-3, (3, n))
+    s = np.full(n, 0.04)
+    y = rng.uniform(-0.1, 0.1, (3, 5))
+    xd = rng.normal(size=x.shape)
+    gd = rng.normal(size=g.shape) * 1e-3
+    dt, nsteps = 0.5, 3
+    L, dL = oracle.rk3_program_jvp(x, g, s, xd, gd, nsteps, dt, y)
+    h = 1e-6
+    Lp = oracle.rk3_program(x + h * xd, g + h * gd, s, nsteps, dt, y)[3]
+    Lm = oracle.rk3_program(x - h * xd, g - h * gd, s, nsteps, dt, y)[3]
+    _, _, _, L0 = oracle.rk3_program(x, g, s, nsteps, dt, y)
+    assert L == pytest.approx(L0, rel=1e-15)
+    assert dL == pytest.approx((Lp - Lm) / (2 * h), rel=1e-6)

@@ -1,0 +1,99 @@
+"""Pins for the oracle's straight-segment velocity with the Vatistas core (Sec. II.A).
+
+The finite-segment Biot-Savart part is checked by quadrature of the line integral and by
+the centre of a square vortex ring; the Vatistas factor by the swirl profile of a long
+straight vortex; plus orientation, additivity and the far-field particle limit (Eq. 6
+with one particle per element).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute_mp
+
+
+def _seg(a, b):
+    return np.array(a, dtype=float).reshape(3, 1), np.array(b, dtype=float).reshape(3, 1)
+
+
+@pytest.mark.parametrize("p", [(0.3, 0.2, 0.1), (-0.5, 0.05, 0.0), (1.5, -0.2, 0.7), (0.5, 0.0, 1e-3)])
+def test_singular_segment_by_quadrature(p):
+    a, b = _seg((0.0, 0.0, 0.0), (1.0, 0.2, -0.1))
+    u = oracle.segments(a, b, [0.7], np.array(p).reshape(3, 1), core_radius=0.0)
+    ub = brute_mp.segment_velocity_singular(a[:, 0], b[:, 0], 0.7, p)
+    assert np.allclose(u[:, 0], ub, rtol=1e-13, atol=1e-15 * np.abs(ub).max())
+
+
+def test_square_ring_centre():
+    """Centre of a square ring of side a and circulation G: |u| = 2 sqrt(2) G / (pi a), along the normal."""
+    side, G = 0.4, 1.3
+    c = [(0, 0, 0), (side, 0, 0), (side, side, 0), (0, side, 0)]
+    A = np.array([c[0], c[1], c[2], c[3]]).T
+    B = np.array([c[1], c[2], c[3], c[0]]).T
+    u = oracle.segments(A, B, [G] * 4, np.array([[side / 2], [side / 2], [0.0]]), core_radius=0.0)
+    assert u[2, 0] == pytest.approx(2 * math.sqrt(2) * G / (math.pi * side), rel=1e-14)
+    assert abs(u[0, 0]) < 1e-14 and abs(u[1, 0]) < 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+@pytest.mark.parametrize("d", [0.002, 0.02, 0.05, 0.3])
+def test_long_segment_vatistas_profile(n, d):
+    """Far from its ends a segment is an infinite line vortex with the Vatistas swirl
+    G d / (2 pi (rc^(2n) + d^(2n))^(1/n))."""
+    rc, G = 0.02, 0.5
+    a, b = _seg((-1e5, 0, 0), (1e5, 0, 0))
+    u = oracle.segments(a, b, [G], np.array([[0.0], [d], [0.0]]), core_radius=rc, vatistas_n=n)
+    expect = G * d / (2 * math.pi * (rc ** (2 * n) + d ** (2 * n)) ** (1.0 / n))
+    assert np.linalg.norm(u[:, 0]) == pytest.approx(expect, rel=1e-9)
+    assert u[2, 0] == pytest.approx(expect, rel=1e-9)  # right-handed about +x at +y gives +z
+
+
+def test_swapping_ends_negates():
+    rng = np.random.default_rng(3)
+    A, B = rng.normal(size=(3, 20)), rng.normal(size=(3, 20))
+    g = rng.normal(0.5, 0.1, 20)
+    P = rng.normal(size=(3, 30))
+    u1 = oracle.segments(A, B, g, P, core_radius=0.05)
+    u2 = oracle.segments(B, A, g, P, core_radius=0.05)
+    assert np.allclose(u1, -u2, rtol=1e-14, atol=1e-16)
+
+
+@pytest.mark.parametrize("rc", [0.0, 0.03])
+def test_collinear_split_is_additive(rc):
+    """The core factor depends only on the distance to the line, so splitting a segment at an
+    interior point leaves the velocity unchanged."""
+    a, b = np.array([0.1, -0.2, 0.3]), np.array([0.7, 0.4, -0.1])
+    m = a + 0.37 * (b - a)
+    P = np.random.default_rng(4).normal(scale=0.5, size=(3, 16))
+    whole = oracle.segments(a.reshape(3, 1), b.reshape(3, 1), [0.9], P, core_radius=rc)
+    parts = oracle.segments(np.stack([a, m], 1), np.stack([m, b], 1), [0.9, 0.9], P, core_radius=rc)
+    assert np.allclose(whole, parts, rtol=1e-12, atol=1e-15)
+
+
+def test_far_field_is_a_particle():
+    """Far away, a segment acts like one point vortex Gamma_s dl at its midpoint (Eq. 6 with
+    one particle); the relative gap closes as (|dl|/s)^2."""
+    a, b = np.array([0.0, 0.0, 0.0]), np.array([0.1, 0.05, 0.02])
+    mid, dl = 0.5 * (a + b), b - a
+    direction = np.array([0.3, 0.8, -0.52])
+    direction /= np.linalg.norm(direction)
+    gaps = []
+    for dist in (1.0, 2.0, 4.0):
+        P = mid + dist * direction
+        u = oracle.segments(a.reshape(3, 1), b.reshape(3, 1), [0.8], P.reshape(3, 1), core_radius=0.01)[:, 0]
+        r = P - mid
+        up = 0.8 * np.cross(dl, r) / (4 * math.pi * np.linalg.norm(r) ** 3)
+        gaps.append(np.linalg.norm(u - up) / np.linalg.norm(up))
+    assert 3.6 < gaps[0] / gaps[1] < 4.4 and 3.6 < gaps[1] / gaps[2] < 4.4
+
+
+def test_degenerate_segments_contribute_nothing():
+    """Zero-length segments and targets on an end point give zero; a target on the line
+    with a core gives zero."""
+    A = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    B = np.array([[0.0, 1.0, 1.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    P = np.array([[0.0, 0.5, 1.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    u = oracle.segments(A, B, [1.0, 1.0, 1.0], P, core_radius=0.02)
+    assert np.all(u == 0)
