@@ -1,0 +1,204 @@
+/* vpm.h — C ABI of libvpm: the vortex-particle hot path on one AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, by direct all-pairs summation on the GPU, the right-hand side of
+ * the vortex-particle equations of Fu & Laurendeau, "Nonlinear Unsteady Vortex-Lattice
+ * Vortex-Particle Method with Adaptive Wake Conversion for Rotorcraft Aerodynamics":
+ *
+ *   particle field   w(x) = sum_j Gamma_j zeta_sigma(x - x_j)              Sec. II.B, Eq. 2
+ *   Gaussian blob    zeta_sigma(rho) = (2 pi sigma^2)^(-3/2) exp(-rho^2/2)  Eq. 3
+ *   convection       dx_i/dt = u_i                                          Eq. 4
+ *   stretching       dGamma_i/dt = (Gamma_i . grad^T) u_i  (inviscid part)  Eq. 5
+ *
+ * with u_i = sum_{j != i} g(|r|) Gamma_j x r, r = x_i - x_j, g(s) = q(s/sigma)/(4 pi s^3),
+ * q(rho) = erf(rho/sqrt 2) - sqrt(2/pi) rho exp(-rho^2/2) (the Biot-Savart law of the field
+ * of Eq. 2), and the stretching
+ *   transposed: sum_{j != i} [ g Gamma_i x Gamma_j + h (Gamma_i . (Gamma_j x r)) r ],
+ *   classical:  sum_{j != i} [ g Gamma_j x Gamma_i + h (r . Gamma_i) (Gamma_j x r) ],
+ * h(s) = g'(s)/s.  It also evaluates the velocity that straight vortex segments (vortex-ring
+ * edges of the lattice, Sec. II.A) induce with a Vatistas core, a hand-written adjoint of
+ * the particle sums, one stage of the low-storage third-order Runge-Kutta scheme used to
+ * advance (x_i, Gamma_i) (Sec. II.B) and its adjoint, and FP64 invariant diagnostics.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Device arrays are owned by the caller; the library never frees or keeps them.
+ *  - A 3-vector array is component-major [3][ld]: component c of item i is at p[c*ld + i],
+ *    ld >= the item count.  Scalars per item (sigma, segment circulation) are [n].
+ *  - dtype VPM_F64: every float array is double and the sums run in FP64.
+ *    dtype VPM_F32C: every float array is float; pair arithmetic is FP32 and each target's
+ *    sums are carried as compensated (two-sum) FP32 pairs across source tiles.
+ *  - Units are SI: x in m, Gamma in m^3/s, sigma in m, segment circulation in m^2/s.
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*; NULL = the null
+ *    stream).  Results are valid once the stream is synchronised.  Calls that overlap in
+ *    time must not share output buffers.
+ *  - Arguments are validated on the host before any HIP call; a bad argument returns its
+ *    status and launches nothing.  A launch failure returns VPM_ERR_HIP.  The library
+ *    prints nothing and never aborts.
+ *  - The library allocates no device memory per call.  Where scratch is needed the caller
+ *    passes `workspace` of at least the size the matching *_workspace_size call returns.
+ */
+#ifndef VPM_H
+#define VPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum vpm_status {
+    VPM_OK = 0,
+    VPM_ERR_NULL = 1,        /* a required pointer is NULL */
+    VPM_ERR_SIZE = 2,        /* a count < 0, ld < count, or a size above the supported range */
+    VPM_ERR_DTYPE = 3,       /* dtype is not VPM_F64 / VPM_F32C */
+    VPM_ERR_ENUM = 4,        /* scheme, sigma rule, stage or Vatistas exponent out of range */
+    VPM_ERR_ALIAS = 5,       /* an output overlaps an input or another output */
+    VPM_ERR_OFFSETS = 6,     /* batch offsets not starting at 0, decreasing, or mismatched */
+    VPM_ERR_WORKSPACE = 7,   /* workspace NULL or smaller than required */
+    VPM_ERR_HIP = 8,         /* the HIP runtime reported an error */
+    VPM_ERR_INPUT = 9,       /* reserved: invalid input values found on the device */
+    VPM_ERR_UNSUPPORTED = 10 /* valid combination that this library does not implement */
+} vpm_status;
+
+typedef enum vpm_dtype { VPM_F64 = 0, VPM_F32C = 1 } vpm_dtype;
+
+/* Eq. 5 writes (Gamma . grad^T) u: the transposed scheme is the default reading. */
+typedef enum vpm_scheme { VPM_STRETCH_TRANSPOSED = 0, VPM_STRETCH_CLASSICAL = 1 } vpm_scheme;
+
+/* Core size of a pair.  SOURCE: sigma_j of the source particle (the literal field of Eq. 2;
+ * the only rule for targets that carry no sigma).  SYMMETRIC: sigma_ij^2 = (sigma_i^2 +
+ * sigma_j^2)/2, which makes the pair terms antisymmetric when cores differ. */
+typedef enum vpm_sigma_rule { VPM_SIGMA_SOURCE = 0, VPM_SIGMA_SYMMETRIC = 1 } vpm_sigma_rule;
+
+typedef struct vpm_options {
+    int32_t scheme;      /* vpm_scheme */
+    int32_t sigma_rule;  /* vpm_sigma_rule */
+    int32_t self;        /* 1: the targets are the sources (target t is source t of the same
+                            batch) and the pair j == t is skipped; target arrays may be NULL */
+    int32_t accumulate;  /* 1: outputs += result; 0: outputs = result */
+    int32_t variant;     /* 0: tuned/default kernel shape; k > 0: variant k of
+                            vpm_variant_count() (used by the tuner and the tests) */
+    int32_t reserved[3]; /* must be 0 */
+} vpm_options;
+
+/* ---------------------------------------------------------------------------------------
+ * vpm_eval_velocity_stretching — u_t and dGamma_t/dt at every target from every source of
+ * its batch (Eqs. 2-5 as above; the viscous term of Eq. 5 is not included).
+ *
+ *  dtype            VPM_F64 or VPM_F32C.
+ *  n_batch          number of independent particle sets (wakes), >= 1.
+ *  src_off,tgt_off  host int64[n_batch+1]; batch b owns sources [src_off[b], src_off[b+1])
+ *                   and targets [tgt_off[b], tgt_off[b+1]).  Must start at 0 and not
+ *                   decrease.  tgt_off may be NULL with opt->self (then equals src_off).
+ *  x_src [3][ld_src], gamma_src [3][ld_src], sigma_src [ld_src]: source particles; every
+ *                   sigma must be > 0.
+ *  x_tgt [3][ld_tgt], gamma_tgt [3][ld_tgt], sigma_tgt [ld_tgt]: targets.  gamma_tgt NULL:
+ *                   velocity only (e.g. blade control points), dgamma_out must be NULL too.
+ *                   sigma_tgt is read only with VPM_SIGMA_SYMMETRIC.  With opt->self the
+ *                   target pointers must be NULL or equal to the source pointers.
+ *  tgt_exclude      NULL, or device int32[n_tgt]: for target t the index (global, into the
+ *                   source arrays) of one source to skip, -1 for none.  Used to evaluate a
+ *                   subset of particles as targets without their self pair.  Ignored with
+ *                   opt->self.
+ *  u_out [3][ld_out], dgamma_out [3][ld_out]: results; must not overlap any input.
+ *  opt              NULL = defaults (transposed, source rule, self = 0, overwrite).
+ *  workspace        device scratch of vpm_workspace_size(...) bytes (0 for n_batch == 1).
+ * Returns VPM_OK or the first violated condition. */
+vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                                        const int64_t* tgt_off, const void* x_src,
+                                        const void* gamma_src, const void* sigma_src,
+                                        int64_t ld_src, const void* x_tgt, const void* gamma_tgt,
+                                        const void* sigma_tgt, int64_t ld_tgt,
+                                        const int32_t* tgt_exclude, void* u_out, void* dgamma_out,
+                                        int64_t ld_out, const vpm_options* opt, void* workspace,
+                                        size_t ws_bytes, void* stream);
+
+/* Bytes of workspace vpm_eval_velocity_stretching needs for this batch layout (0 when
+ * n_batch == 1).  Returns 0 also for invalid offsets; the evaluation then reports them. */
+size_t vpm_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                          const int64_t* tgt_off, const vpm_options* opt);
+
+/* ---------------------------------------------------------------------------------------
+ * vpm_eval_segments — velocity at n_tgt points induced by n_seg straight vortex segments
+ * a->b of circulation gamma_seg (vortex-ring edges and wake lines, Sec. II.A), with the
+ * Vatistas core of radius core_radius and exponent vatistas_n:
+ *   u(P) += gamma/(4 pi) (r1 x r2) [r0 . (r1/|r1| - r2/|r2|)] / (|r0|^2 (d^2n + rc^2n)^(1/n))
+ * r1 = P - a, r2 = P - b, r0 = b - a, d = |r1 x r2| / |r0| (distance to the line).  A segment
+ * whose length or either arm is below 1e-12 max(|r0|, 1 m) contributes nothing, and so does
+ * a point with a zero denominator (on the line with core_radius == 0).
+ *  a, b [3][ld_seg], gamma_seg [ld_seg]; x_tgt [3][ld_tgt]; u_out [3][ld_out].
+ *  core_radius >= 0 (m); vatistas_n >= 1 (2 is the usual choice).
+ *  accumulate: 1 = u_out += result, 0 = u_out = result. */
+vpm_status vpm_eval_segments(int32_t dtype, int64_t n_seg, const void* a, const void* b,
+                             const void* gamma_seg, int64_t ld_seg, double core_radius,
+                             int32_t vatistas_n, int64_t n_tgt, const void* x_tgt, int64_t ld_tgt,
+                             void* u_out, int64_t ld_out, int32_t accumulate, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * vpm_backward — vector-Jacobian product of vpm_eval_velocity_stretching (transposed
+ * scheme, n_batch == 1): given seeds u_bar [3][ld_tgt] and dgamma_bar [3][ld_tgt] on the
+ * outputs, ADD dL/dx and dL/dGamma to the gradient arrays.  sigma is not differentiated.
+ *  With opt->self: sources are targets; the gradients are x_src_bar and gamma_src_bar, each
+ *  particle gathering its contributions both as target and as source.  x_tgt_bar and
+ *  gamma_tgt_bar must be NULL.
+ *  Without self: x_src_bar/gamma_src_bar receive the source gradients (required);
+ *  x_tgt_bar/gamma_tgt_bar receive the target gradients (both NULL to skip).
+ *  dgamma_bar NULL: only velocities are seeded (gamma_tgt may then be NULL).
+ * Gradient arrays are [3][ld_src] / [3][ld_tgt] and must not overlap inputs. */
+vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                        const int64_t* tgt_off, const void* x_src, const void* gamma_src,
+                        const void* sigma_src, int64_t ld_src, const void* x_tgt,
+                        const void* gamma_tgt, const void* sigma_tgt, int64_t ld_tgt,
+                        const void* u_bar, const void* dgamma_bar, void* x_src_bar,
+                        void* gamma_src_bar, void* x_tgt_bar, void* gamma_tgt_bar,
+                        const vpm_options* opt, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * vpm_rk3_stage — stage k (0, 1, 2) of Williamson's low-storage third-order Runge-Kutta
+ * scheme (Sec. II.B) on Y = (x, Gamma) with register Q = (qx, qg) and F = (u, dgamma):
+ *     Q <- A_k Q + dt F;   Y <- Y + B_k Q,
+ * A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15).  All arrays [3][ld], n items, in place. */
+vpm_status vpm_rk3_stage(int32_t dtype, int32_t stage, int64_t n, double dt, void* x, void* gamma,
+                         void* qx, void* qg, const void* u, const void* dgamma, int64_t ld,
+                         void* stream);
+
+/* vpm_rk3_stage_backward — adjoint of vpm_rk3_stage.  In: x_bar, gamma_bar (adjoint of Y
+ * after the stage), qx_bar, qg_bar (adjoint of Q after the stage).  Out, in place: qx_bar,
+ * qg_bar become the adjoint of Q before the stage; u_seed, dgamma_seed receive dt (Q_bar +
+ * B_k Y_bar), the seeds to pass to vpm_backward at the stage's input state, whose result is
+ * added to x_bar, gamma_bar.  x_bar, gamma_bar are read only. */
+vpm_status vpm_rk3_stage_backward(int32_t dtype, int32_t stage, int64_t n, double dt,
+                                  const void* x_bar, const void* gamma_bar, void* qx_bar,
+                                  void* qg_bar, void* u_seed, void* dgamma_seed, int64_t ld,
+                                  void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * vpm_diagnostics — FP64 invariants of one evaluation, reduced on the GPU (for the
+ * vorticity-conservation check of Eq. 1): out (device double[13]) receives
+ *   [0..2] sum_i Gamma_i, [3..5] sum_i dGamma_i/dt, [6..8] linear impulse 1/2 sum x_i x Gamma_i,
+ *   [9..11] its rate 1/2 sum (u_i x Gamma_i + x_i x dGamma_i/dt), [12] number of non-finite
+ *   entries among x, Gamma, u, dGamma/dt.
+ * Inputs [3][ld] of dtype; workspace of vpm_diagnostics_workspace_size() bytes. */
+vpm_status vpm_diagnostics(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* u,
+                           const void* dgamma, int64_t ld, double* out, void* workspace,
+                           size_t ws_bytes, void* stream);
+size_t vpm_diagnostics_workspace_size(void);
+
+/* ---------------------------------------------------------------------------------------
+ * Kernel-shape variants of the FP32C particle kernel (targets per lane x workgroup size),
+ * for the tuner and the tests.  vpm_variant_info fills targets-per-lane and workgroup size
+ * of variant k (1-based); returns VPM_ERR_ENUM for an unknown k. */
+int32_t vpm_variant_count(void);
+vpm_status vpm_variant_info(int32_t k, int32_t* targets_per_lane, int32_t* workgroup);
+
+/* Human-readable name of a status code (static string). */
+const char* vpm_status_string(int32_t status);
+
+/* Library version string (static). */
+const char* vpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VPM_H */

@@ -1,0 +1,303 @@
+"""paper_2511_11430_amd — the vortex-particle hot path of Fu & Laurendeau's NL-UVLM-VPM
+rotor solver (Sec. II.A-B) on one AMD Instinct MI355X.
+
+The compute runs in libvpm.so (HIP kernels for gfx950, C ABI in include/vpm.h).  This
+module is the thin Python binding: each ``vpm_*`` function has the name of the C entry
+point it calls, takes torch CUDA tensors of shape (3, n) (component-major, unit stride
+along n) or (n,), allocates the outputs it is not given, and passes pointers and the
+current torch stream.  It computes nothing itself.
+
+dtype follows the tensors: float64 -> the FP64 path, float32 -> the FP32-compensated path.
+"""
+import ctypes
+
+from . import _lib
+
+F64, F32C = 0, 1
+TRANSPOSED, CLASSICAL = 0, 1
+SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
+
+__all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_backward", "vpm_rk3_stage",
+           "vpm_rk3_stage_backward", "vpm_diagnostics", "vpm_workspace_size", "vpm_variant_count",
+           "vpm_variant_info", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
+           "SIGMA_SYMMETRIC"]
+
+
+class VpmError(RuntimeError):
+    """A libvpm call returned a non-zero status."""
+
+    def __init__(self, fn, status):
+        msg = _lib.load().vpm_status_string(status).decode()
+        super().__init__(f"{fn}: {msg} (status {status})")
+        self.status = status
+
+
+def _check(fn, status):
+    if status != 0:
+        raise VpmError(fn, status)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32C
+    raise TypeError(f"unsupported dtype {t.dtype}; use float32 or float64")
+
+
+def _vec(t, name, n=None, dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dim() != 2 or t.shape[0] != 3 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError(f"{name} must have shape (3, n) with unit stride along n")
+    if n is not None and t.shape[1] != n:
+        raise ValueError(f"{name} has {t.shape[1]} items, expected {n}")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    return t
+
+
+def _scal(t, name, n=None, dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dim() != 1 or (t.shape[0] > 1 and t.stride(0) != 1):
+        raise ValueError(f"{name} must be a contiguous 1-D CUDA tensor")
+    if n is not None and t.shape[0] != n:
+        raise ValueError(f"{name} has {t.shape[0]} items, expected {n}")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    return t
+
+
+def _ld(t):
+    return int(t.stride(0)) if t is not None and t.shape[1] > 0 else (t.shape[1] if t is not None else 0)
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _offsets(off):
+    arr = (ctypes.c_int64 * len(off))(*[int(v) for v in off])
+    return arr
+
+
+def _opts(scheme=TRANSPOSED, sigma_rule=SIGMA_SOURCE, self_eval=0, accumulate=0, variant=0):
+    o = _lib.VpmOptions()
+    o.scheme, o.sigma_rule, o.self_, o.accumulate, o.variant = int(scheme), int(sigma_rule), int(self_eval), \
+        int(accumulate), int(variant)
+    return o
+
+
+def vpm_workspace_size(dtype, src_off, tgt_off=None, self_eval=True, variant=0):
+    """Workspace bytes of a (batched) evaluation; see include/vpm.h."""
+    lib = _lib.load()
+    so = _offsets(src_off)
+    to = None if tgt_off is None else _offsets(tgt_off)
+    o = _opts(self_eval=int(self_eval), variant=variant)
+    return int(lib.vpm_workspace_size(int(dtype), len(src_off) - 1, so, to, ctypes.byref(o)))
+
+
+def vpm_eval_velocity_stretching(x_src, gamma_src, sigma_src, x_tgt=None, gamma_tgt=None, sigma_tgt=None, *,
+                                 tgt_exclude=None, u_out=None, dgamma_out=None, velocity_only=False,
+                                 scheme=TRANSPOSED, sigma_rule=SIGMA_SOURCE, accumulate=False, variant=0,
+                                 src_off=None, tgt_off=None, workspace=None, stream=None):
+    """u and dGamma/dt at the targets (Eqs. 2-5).  ``x_tgt`` None: the targets are the
+    sources (self evaluation, self pair skipped).  ``gamma_tgt`` None with explicit targets,
+    or ``velocity_only``: velocity only (dgamma returned as None).  ``src_off``/``tgt_off``:
+    batch offsets (lists) for many independent sets in one persistent launch.
+    Returns (u, dgamma)."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x_src)
+    tdt = x_src.dtype
+    _vec(x_src, "x_src", dtype=tdt)
+    n_src = x_src.shape[1]
+    _vec(gamma_src, "gamma_src", n_src, tdt)
+    _scal(sigma_src, "sigma_src", n_src, tdt)
+    self_eval = x_tgt is None
+    if self_eval:
+        n_tgt = n_src
+        stretch = not velocity_only
+    else:
+        _vec(x_tgt, "x_tgt", dtype=tdt)
+        n_tgt = x_tgt.shape[1]
+        _vec(gamma_tgt, "gamma_tgt", n_tgt, tdt)
+        _scal(sigma_tgt, "sigma_tgt", n_tgt, tdt)
+        stretch = gamma_tgt is not None and not velocity_only
+    dev = x_src.device
+    if u_out is None:
+        u_out = torch.empty((3, n_tgt), dtype=tdt, device=dev)
+    if stretch and dgamma_out is None:
+        dgamma_out = torch.empty((3, n_tgt), dtype=tdt, device=dev)
+    if not stretch:
+        dgamma_out = None
+    _vec(u_out, "u_out", n_tgt, tdt)
+    _vec(dgamma_out, "dgamma_out", n_tgt, tdt)
+    if tgt_exclude is not None:
+        _scal(tgt_exclude, "tgt_exclude", n_tgt, torch.int32)
+    if src_off is None:
+        src_off = [0, n_src]
+    if tgt_off is None and not self_eval:
+        tgt_off = [0, n_tgt]
+    n_batch = len(src_off) - 1
+    so = _offsets(src_off)
+    to = None if tgt_off is None else _offsets(tgt_off)
+    o = _opts(scheme, sigma_rule, self_eval, accumulate, variant)
+    ws_need = int(lib.vpm_workspace_size(dt, n_batch, so, to, ctypes.byref(o)))
+    if ws_need and workspace is None:
+        workspace = torch.empty(ws_need, dtype=torch.uint8, device=dev)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    ld_src = _ld(x_src)
+    ld_tgt = 0 if self_eval else _ld(x_tgt)
+    st = lib.vpm_eval_velocity_stretching(
+        dt, n_batch, so, to, _p(x_src), _p(gamma_src), _p(sigma_src), ld_src,
+        None if self_eval else _p(x_tgt), None if self_eval else _p(gamma_tgt),
+        None if self_eval else _p(sigma_tgt), ld_tgt, _p(tgt_exclude), _p(u_out), _p(dgamma_out),
+        _ld(u_out), ctypes.byref(o), _p(workspace), ws_bytes, _stream(stream))
+    _check("vpm_eval_velocity_stretching", st)
+    return u_out, dgamma_out
+
+
+def vpm_eval_segments(a, b, gamma_seg, x_tgt, core_radius, vatistas_n=2, *, u_out=None, accumulate=False,
+                      stream=None):
+    """Velocity at x_tgt induced by straight vortex segments a->b (Vatistas core, Sec. II.A)."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x_tgt)
+    tdt = x_tgt.dtype
+    _vec(x_tgt, "x_tgt", dtype=tdt)
+    n_tgt = x_tgt.shape[1]
+    _vec(a, "a", dtype=tdt)
+    n_seg = a.shape[1]
+    _vec(b, "b", n_seg, tdt)
+    _scal(gamma_seg, "gamma_seg", n_seg, tdt)
+    if a.shape[1] > 0 and (b.stride(0) != a.stride(0)):
+        raise ValueError("a and b must share one leading dimension")
+    if u_out is None:
+        u_out = torch.empty((3, n_tgt), dtype=tdt, device=x_tgt.device)
+    _vec(u_out, "u_out", n_tgt, tdt)
+    st = lib.vpm_eval_segments(dt, n_seg, _p(a), _p(b), _p(gamma_seg), _ld(a) if n_seg else 0,
+                               float(core_radius), int(vatistas_n), n_tgt, _p(x_tgt), _ld(x_tgt), _p(u_out),
+                               _ld(u_out), int(accumulate), _stream(stream))
+    _check("vpm_eval_segments", st)
+    return u_out
+
+
+def vpm_backward(x_src, gamma_src, sigma_src, u_bar, dgamma_bar=None, x_tgt=None, gamma_tgt=None,
+                 sigma_tgt=None, *, x_src_bar=None, gamma_src_bar=None, x_tgt_bar=None, gamma_tgt_bar=None,
+                 want_target_grads=False, sigma_rule=SIGMA_SOURCE, stream=None):
+    """Vector-Jacobian product of :func:`vpm_eval_velocity_stretching` (transposed scheme).
+    Gradients are accumulated into the given arrays (zero-initialised when allocated here).
+    Returns (x_src_bar, gamma_src_bar, x_tgt_bar, gamma_tgt_bar)."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x_src)
+    tdt = x_src.dtype
+    n_src = x_src.shape[1]
+    _vec(x_src, "x_src", dtype=tdt)
+    _vec(gamma_src, "gamma_src", n_src, tdt)
+    _scal(sigma_src, "sigma_src", n_src, tdt)
+    self_eval = x_tgt is None
+    n_tgt = n_src if self_eval else x_tgt.shape[1]
+    if not self_eval:
+        _vec(x_tgt, "x_tgt", dtype=tdt)
+        _vec(gamma_tgt, "gamma_tgt", n_tgt, tdt)
+        _scal(sigma_tgt, "sigma_tgt", n_tgt, tdt)
+    _vec(u_bar, "u_bar", n_tgt, tdt)
+    _vec(dgamma_bar, "dgamma_bar", n_tgt, tdt)
+    dev = x_src.device
+    if x_src_bar is None:
+        x_src_bar = torch.zeros((3, n_src), dtype=tdt, device=dev)
+    if gamma_src_bar is None:
+        gamma_src_bar = torch.zeros((3, n_src), dtype=tdt, device=dev)
+    if not self_eval and want_target_grads:
+        if x_tgt_bar is None:
+            x_tgt_bar = torch.zeros((3, n_tgt), dtype=tdt, device=dev)
+        if gamma_tgt_bar is None and dgamma_bar is not None:
+            gamma_tgt_bar = torch.zeros((3, n_tgt), dtype=tdt, device=dev)
+    so = _offsets([0, n_src])
+    to = None if self_eval else _offsets([0, n_tgt])
+    o = _opts(TRANSPOSED, sigma_rule, self_eval, 1, 0)
+    st = lib.vpm_backward(dt, 1, so, to, _p(x_src), _p(gamma_src), _p(sigma_src), _ld(x_src),
+                          None if self_eval else _p(x_tgt), None if self_eval else _p(gamma_tgt),
+                          None if self_eval else _p(sigma_tgt), 0 if self_eval else _ld(x_tgt), _p(u_bar),
+                          _p(dgamma_bar), _p(x_src_bar), _p(gamma_src_bar), _p(x_tgt_bar), _p(gamma_tgt_bar),
+                          ctypes.byref(o), None, 0, _stream(stream))
+    _check("vpm_backward", st)
+    return x_src_bar, gamma_src_bar, x_tgt_bar, gamma_tgt_bar
+
+
+def vpm_rk3_stage(stage, dt_step, x, gamma, qx, qg, u, dgamma, *, stream=None):
+    """One low-storage RK3 stage in place: Q <- A_k Q + dt F, Y <- Y + B_k Q (Sec. II.B)."""
+    lib = _lib.load()
+    dt = _code(x)
+    n = x.shape[1]
+    for t, nm in ((x, "x"), (gamma, "gamma"), (qx, "qx"), (qg, "qg"), (u, "u"), (dgamma, "dgamma")):
+        _vec(t, nm, n, x.dtype)
+        if n and t.stride(0) != x.stride(0):
+            raise ValueError("all stage arrays must share one leading dimension")
+    st = lib.vpm_rk3_stage(dt, int(stage), n, float(dt_step), _p(x), _p(gamma), _p(qx), _p(qg), _p(u),
+                           _p(dgamma), _ld(x), _stream(stream))
+    _check("vpm_rk3_stage", st)
+
+
+def vpm_rk3_stage_backward(stage, dt_step, x_bar, gamma_bar, qx_bar, qg_bar, u_seed, dgamma_seed, *, stream=None):
+    """Adjoint of one RK3 stage (see include/vpm.h)."""
+    lib = _lib.load()
+    dt = _code(x_bar)
+    n = x_bar.shape[1]
+    for t, nm in ((x_bar, "x_bar"), (gamma_bar, "gamma_bar"), (qx_bar, "qx_bar"), (qg_bar, "qg_bar"),
+                  (u_seed, "u_seed"), (dgamma_seed, "dgamma_seed")):
+        _vec(t, nm, n, x_bar.dtype)
+        if n and t.stride(0) != x_bar.stride(0):
+            raise ValueError("all stage arrays must share one leading dimension")
+    st = lib.vpm_rk3_stage_backward(dt, int(stage), n, float(dt_step), _p(x_bar), _p(gamma_bar), _p(qx_bar),
+                                    _p(qg_bar), _p(u_seed), _p(dgamma_seed), _ld(x_bar), _stream(stream))
+    _check("vpm_rk3_stage_backward", st)
+
+
+def vpm_diagnostics(x, gamma, u, dgamma, *, out=None, workspace=None, stream=None):
+    """FP64 invariants reduced on the GPU; returns a float64 CUDA tensor of 13 values
+    (sum Gamma, sum dGamma/dt, impulse, impulse rate, non-finite count)."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x)
+    n = x.shape[1]
+    for t, nm in ((x, "x"), (gamma, "gamma"), (u, "u"), (dgamma, "dgamma")):
+        _vec(t, nm, n, x.dtype)
+        if n and t.stride(0) != x.stride(0):
+            raise ValueError("all arrays must share one leading dimension")
+    if out is None:
+        out = torch.empty(13, dtype=torch.float64, device=x.device)
+    need = int(lib.vpm_diagnostics_workspace_size())
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    st = lib.vpm_diagnostics(dt, n, _p(x), _p(gamma), _p(u), _p(dgamma), _ld(x), _p(out), _p(workspace),
+                             workspace.numel() * workspace.element_size(), _stream(stream))
+    _check("vpm_diagnostics", st)
+    return out
+
+
+def vpm_variant_count():
+    return int(_lib.load().vpm_variant_count())
+
+
+def vpm_variant_info(k):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check("vpm_variant_info", _lib.load().vpm_variant_info(int(k), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value

@@ -1,0 +1,138 @@
+// Device-side arithmetic shared by the libvpm kernels (gfx950 only).
+//
+// Kernel weights of the Gaussian blob (Fu & Laurendeau, Sec. II.B, Eq. 3).  With
+// rho = s/sigma and q(rho) = erf(rho/sqrt2) - c0 rho exp(-rho^2/2), c0 = sqrt(2/pi):
+//   g(s) = q / (4 pi s^3)                      velocity weight
+//   h(s) = g'(s)/s = (rho q' - 3 q)/(4 pi s^5)  gradient weight (stretching)
+//   k(s) = h'(s)/s = (rho^2 q'' - 7 rho q' + 15 q)/(4 pi s^7)   (adjoint only)
+// The kernels carry 4 pi g, -(4 pi/3) h and (4 pi/15) k, which are exactly s^-3, s^-5, s^-7
+// outside the core (rho >= RHO_FAR, where the blob is a point vortex to working precision),
+// and apply 1/(4 pi) and the integer factors once per target.
+//
+// Inside the core:
+//   rho < 1:  Taylor series in t = rho^2 (the closed form cancels there).  From
+//             q = c0 sum_n (-1)^n rho^(2n+3) / ((2n+3) 2^n n!):
+//               q/rho^3              = c0 sum_{n>=0} a_n t^n,          a_n = (-1)^n/((2n+3) 2^n n!)
+//               (rho q'-3q)/rho^5    = c0 sum_{n>=1} 2n a_n t^(n-1)
+//               (rho^2 q''-7 rho q'+15 q)/rho^7 = c0 sum_{n>=2} 4n(n-1) a_n t^(n-2)
+//   rho >= 1: closed form with erf and exp (cancellation at most ~10x there).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vpm {
+
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+constexpr double kC0D = 0.79788456080286535587989211986876373;      // sqrt(2/pi)
+constexpr double kInvSqrt2D = 0.70710678118654752440084436210484903;
+constexpr double kInv4PiD = 1.0 / (4.0 * kPiD);
+
+// a_n = (-1)^n / ((2n+3) 2^n n!)
+constexpr double series_a(int n) {
+    double a = 1.0;
+    for (int k = 1; k <= n; ++k) a /= (2.0 * k);
+    return ((n & 1) ? -a : a) / (2 * n + 3);
+}
+
+// Horner evaluation of sum_{n=N0}^{NMAX} w(n) a_n t^(n-N0), coefficients folded at compile time.
+// W selects the weight: 0 -> 1, 1 -> 2n, 2 -> 4n(n-1).
+template <int W>
+constexpr double series_w(int n) {
+    return W == 0 ? series_a(n) : (W == 1 ? 2.0 * n * series_a(n) : 4.0 * n * (n - 1) * series_a(n));
+}
+template <typename T, int W, int N, int NMAX>
+struct Horner {
+    static __device__ __forceinline__ T eval(T t) {
+        constexpr double c = series_w<W>(N);
+        if constexpr (N == NMAX) {
+            return T(c);
+        } else {
+            return Horner<T, W, N + 1, NMAX>::eval(t) * t + T(c);
+        }
+    }
+};
+
+// Precision-dependent constants.
+template <typename T> struct Prec;
+template <> struct Prec<float> {
+    // Beyond rho = 7 the dropped terms of g and h are below 2.1e-9 relative (< FP32 half ulp).
+    static constexpr float kFarRho2 = 49.0f;
+    static constexpr int kTermsG = 9;   // n = 0..8: truncation < 2.5e-8 relative at rho = 1
+    static constexpr int kTermsH = 10;  // n = 1..9
+    static constexpr int kTermsK = 11;  // n = 2..10
+};
+template <> struct Prec<double> {
+    // Beyond rho = 9.5 the dropped terms are below 1e-16 relative.
+    static constexpr double kFarRho2 = 90.25;
+    static constexpr int kTermsG = 17;  // n = 0..16
+    static constexpr int kTermsH = 18;
+    static constexpr int kTermsK = 19;
+};
+
+__device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_fast(double x) { return rsqrt(x); }
+__device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float dexp(float x) { return expf(x); }
+__device__ __forceinline__ double dexp(double x) { return exp(x); }
+__device__ __forceinline__ float derf(float x) { return erff(x); }
+__device__ __forceinline__ double derf(double x) { return erf(x); }
+
+// In-core weights.  Inputs: s2 = |r|^2, isig2 = 1/sigma^2, Gf = s^-3 and Hf = s^-5 (valid when
+// s > 0).  Outputs G = 4 pi g and Hn = -(4 pi/3) h.
+template <typename T>
+__device__ __forceinline__ void core_weights(T s2, T isig2, T Gf, T Hf, T& G, T& Hn) {
+    const T t = s2 * isig2;
+    if (t < T(1)) {
+        const T isig = dsqrt(isig2);
+        const T isig3 = isig * isig2;
+        const T isig5 = isig3 * isig2;
+        const T gw = Horner<T, 0, 0, Prec<T>::kTermsG - 1>::eval(t);
+        const T hw = Horner<T, 1, 1, Prec<T>::kTermsH>::eval(t);
+        G = T(kC0D) * gw * isig3;
+        Hn = T(-kC0D / 3.0) * hw * isig5;
+    } else {
+        const T rho = dsqrt(t);
+        const T e = dexp(T(-0.5) * t);
+        const T q = derf(rho * T(kInvSqrt2D)) - T(kC0D) * rho * e;
+        G = q * Gf;
+        Hn = (q - T(kC0D / 3.0) * rho * t * e) * Hf;
+    }
+}
+
+// Same, also returning Kn = (4 pi/15) k (adjoint); Kf = s^-7.
+template <typename T>
+__device__ __forceinline__ void core_weights3(T s2, T isig2, T Gf, T Hf, T Kf, T& G, T& Hn, T& Kn) {
+    const T t = s2 * isig2;
+    if (t < T(1)) {
+        const T isig = dsqrt(isig2);
+        const T isig3 = isig * isig2;
+        const T isig5 = isig3 * isig2;
+        const T isig7 = isig5 * isig2;
+        const T gw = Horner<T, 0, 0, Prec<T>::kTermsG - 1>::eval(t);
+        const T hw = Horner<T, 1, 1, Prec<T>::kTermsH>::eval(t);
+        const T kw = Horner<T, 2, 2, Prec<T>::kTermsK>::eval(t);
+        G = T(kC0D) * gw * isig3;
+        Hn = T(-kC0D / 3.0) * hw * isig5;
+        Kn = T(kC0D / 15.0) * kw * isig7;
+    } else {
+        const T rho = dsqrt(t);
+        const T e = dexp(T(-0.5) * t);
+        const T q = derf(rho * T(kInvSqrt2D)) - T(kC0D) * rho * e;
+        const T r3e = rho * t * e;  // rho^3 e
+        G = q * Gf;
+        Hn = (q - T(kC0D / 3.0) * r3e) * Hf;
+        // 15 q - c0 e (5 rho^3 + rho^5)
+        Kn = (q - T(kC0D / 15.0) * r3e * (T(5) + t)) * Kf;
+    }
+}
+
+// Knuth's TwoSum: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+}  // namespace vpm

@@ -1,0 +1,385 @@
+// Particle-to-particle velocity and stretching by direct summation (Fu & Laurendeau,
+// Sec. II.B, Eqs. 2-5), for one MI355X (gfx950).
+//
+// Layout and schedule
+//  - Each workgroup owns WG*K consecutive targets of one particle set; lane l holds targets
+//    l, l+WG, ..., l+(K-1)WG (coalesced loads and stores for every k).
+//  - Sources stream through LDS in tiles of WG particles.  Each lane stages one source and
+//    precomputes what every pair needs (x, Gamma, 1/sigma^2 and the far-field cut), so the
+//    inner loop reads a source with two 16-byte LDS loads that all lanes share (broadcast),
+//    and uses it for K register-resident targets.
+//  - A pair takes the point-vortex weights (s^-3, s^-5) unless it lies inside RHO_FAR cores,
+//    where the in-core weights replace them (series or erf/exp; core_weights).  The branch is
+//    skipped by a whole wavefront when none of its lanes is in a core, which is the common case
+//    for spatially ordered wakes.
+//  - FP32 (VPM_F32C): each target's 9 partial sums (u, A = sum G Gamma_j, B) are plain FP32
+//    within a tile and folded into (hi, lo) two-sum pairs after every tile, so the error does
+//    not grow with N.  The per-target epilogue runs in FP64.
+//  - FP64 (VPM_F64): the same schedule with K = 1 and plain FP64 sums.
+//  - Stretching is assembled per target from A and B:
+//      transposed: dGamma_i/dt = (Gamma_i x A - 3 B)/(4 pi),  B = sum Hn (Gamma_i . (Gamma_j x r)) r
+//      classical:  dGamma_i/dt = (-Gamma_i x A - 3 B)/(4 pi), B = sum Hn (r . Gamma_i) (Gamma_j x r)
+//    with A = sum G Gamma_j, G = 4 pi g, Hn = -(4 pi/3) h.
+//  - The self pair (and a caller-chosen source per target) is skipped by index; only tiles that
+//    contain such a source run the checked inner loop.
+//  - Many independent sets run in one persistent launch: each workgroup pops (set, target
+//    block) items from a queue ordered by decreasing cost (longest-processing-time first).
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "vpm_internal.h"
+
+namespace vpm {
+
+template <typename T>
+struct SrcTile {
+    // p = (x, y, z, 1/sigma^2), q = (Gamma_x, Gamma_y, Gamma_z, cut) with cut = RHO_FAR^2 sigma^2
+    // for the source rule and RHO_FAR^2 sigma^2 / 2 for the symmetric rule.
+    using V4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
+};
+
+// One pair: accumulate into the tile partials of one target.
+template <typename T, int MODE, bool SYM, bool CHECK>
+__device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, const T pw, const T qx,
+                                         const T qy, const T qz, const T qw, const T xi0,
+                                         const T xi1, const T xi2, const T gi0, const T gi1,
+                                         const T gi2, const T cut_i, const int64_t jglob,
+                                         const int64_t ex, T* pu, T* pA, T* pB) {
+    const T rx = xi0 - px;
+    const T ry = xi1 - py;
+    const T rz = xi2 - pz;
+    const T s2 = rx * rx + ry * ry + rz * rz;
+    const T rinv = rsqrt_fast(s2);
+    const T rinv2 = rinv * rinv;
+    T G = rinv2 * rinv;
+    T Hn = G * rinv2;
+    const T cut = SYM ? (qw + cut_i) : qw;
+    if (s2 < cut) {
+        // symmetric rule: 1/sigma_ij^2 = RHO_FAR^2 / cut
+        const T isig2 = SYM ? T(Prec<T>::kFarRho2) / cut : pw;
+        core_weights<T>(s2, isig2, G, Hn, G, Hn);
+    }
+    if (CHECK) {
+        if (jglob == ex) {
+            G = T(0);
+            Hn = T(0);
+        }
+    }
+    const T vx = qy * rz - qz * ry;
+    const T vy = qz * rx - qx * rz;
+    const T vz = qx * ry - qy * rx;
+    pu[0] += G * vx;
+    pu[1] += G * vy;
+    pu[2] += G * vz;
+    if (MODE != kModeVelocity) {
+        pA[0] += G * qx;
+        pA[1] += G * qy;
+        pA[2] += G * qz;
+        if (MODE == kModeTransposed) {
+            const T tau = gi0 * vx + gi1 * vy + gi2 * vz;
+            const T w = Hn * tau;
+            pB[0] += w * rx;
+            pB[1] += w * ry;
+            pB[2] += w * rz;
+        } else {
+            const T rg = rx * gi0 + ry * gi1 + rz * gi2;
+            const T w = Hn * rg;
+            pB[0] += w * vx;
+            pB[1] += w * vy;
+            pB[2] += w * vz;
+        }
+    }
+}
+
+template <typename T, int K, int WG, int MODE, bool SYM>
+struct FwdBlock {
+    static constexpr bool kComp = std::is_same<T, float>::value;
+    static constexpr int kNacc = (MODE == kModeVelocity) ? 3 : 9;
+    using V4 = typename SrcTile<T>::V4;
+
+    // Process targets [t0, t1) (at most WG*K of them) against sources [s0, s1) of one set.
+    // self_shift: with self evaluation, target t is source t + self_shift (else ignored).
+    static __device__ void run(const FwdArgs& a, int64_t s0, int64_t s1, int64_t t0, int64_t t1,
+                               int64_t self_shift, V4* lp, V4* lq) {
+        const T* __restrict__ xs = static_cast<const T*>(a.xs);
+        const T* __restrict__ gs = static_cast<const T*>(a.gs);
+        const T* __restrict__ ss = static_cast<const T*>(a.ss);
+        const T* __restrict__ xt = static_cast<const T*>(a.xt);
+        const T* __restrict__ gt = static_cast<const T*>(a.gt);
+        const T* __restrict__ st = static_cast<const T*>(a.st);
+        const int tid = threadIdx.x;
+        const T far2 = T(Prec<T>::kFarRho2);
+
+        T xi[K][3], gi[K][3], cut_i[K];
+        int64_t ex[K];
+        bool valid[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t t = t0 + tid + int64_t(k) * WG;
+            valid[k] = t < t1;
+            const int64_t tt = valid[k] ? t : t0;
+            xi[k][0] = xt[tt];
+            xi[k][1] = xt[a.ldt + tt];
+            xi[k][2] = xt[2 * a.ldt + tt];
+            if (MODE != kModeVelocity) {
+                gi[k][0] = gt[tt];
+                gi[k][1] = gt[a.ldt + tt];
+                gi[k][2] = gt[2 * a.ldt + tt];
+            } else {
+                gi[k][0] = gi[k][1] = gi[k][2] = T(0);
+            }
+            if (SYM) {
+                const T sg = st[tt];
+                cut_i[k] = T(0.5) * far2 * sg * sg;
+            } else {
+                cut_i[k] = T(0);
+            }
+            if (a.self) ex[k] = valid[k] ? t + self_shift : -2;
+            else if (a.excl) ex[k] = valid[k] ? int64_t(a.excl[tt]) : -2;
+            else ex[k] = -2;
+        }
+
+        T acc[K][kNacc];   // tile partials
+        T hi[K][kNacc];    // compensated totals (FP32 path)
+        T lo[K][kNacc];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < kNacc; ++c) {
+                acc[k][c] = T(0);
+                hi[k][c] = T(0);
+                lo[k][c] = T(0);
+            }
+
+        for (int64_t j0 = s0; j0 < s1; j0 += WG) {
+            const int cnt = int((s1 - j0) < WG ? (s1 - j0) : WG);
+            __syncthreads();
+            if (tid < cnt) {
+                const int64_t j = j0 + tid;
+                const T sg = ss[j];
+                V4 p, q;
+                p.x = xs[j];
+                p.y = xs[a.lds + j];
+                p.z = xs[2 * a.lds + j];
+                p.w = T(1) / (sg * sg);
+                q.x = gs[j];
+                q.y = gs[a.lds + j];
+                q.z = gs[2 * a.lds + j];
+                q.w = SYM ? T(0.5) * far2 * sg * sg : far2 * sg * sg;
+                lp[tid] = p;
+                lq[tid] = q;
+            }
+            // Does any of this workgroup's targets skip a source in this tile?
+            bool mine = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) mine |= (ex[k] >= j0 && ex[k] < j0 + cnt);
+            const bool check = __syncthreads_or(mine);
+            if (check) {
+                tile<true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
+            } else {
+                tile<false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
+            }
+            if constexpr (kComp) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < kNacc; ++c) {
+                        T s, e;
+                        two_sum(hi[k][c], acc[k][c], s, e);
+                        hi[k][c] = s;
+                        lo[k][c] += e;
+                        acc[k][c] = T(0);
+                    }
+            }
+        }
+
+        // Epilogue in FP64: u = U/(4 pi); stretching from A and B.
+        T* __restrict__ uo = static_cast<T*>(a.u);
+        T* __restrict__ dgo = static_cast<T*>(a.dg);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!valid[k]) continue;
+            const int64_t t = t0 + tid + int64_t(k) * WG;
+            double tot[kNacc];
+#pragma unroll
+            for (int c = 0; c < kNacc; ++c)
+                tot[c] = kComp ? double(hi[k][c]) + double(lo[k][c]) : double(acc[k][c]);
+            const int64_t o = t;  // outputs are indexed like the targets
+            double res[6];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) res[c] = kInv4PiD * tot[c];
+            if (MODE != kModeVelocity) {
+                const double g0 = gi[k][0], g1 = gi[k][1], g2 = gi[k][2];
+                const double A0 = tot[3], A1 = tot[4], A2 = tot[5];
+                double c0 = g1 * A2 - g2 * A1;
+                double c1 = g2 * A0 - g0 * A2;
+                double c2 = g0 * A1 - g1 * A0;
+                if (MODE == kModeClassical) {
+                    c0 = -c0;
+                    c1 = -c1;
+                    c2 = -c2;
+                }
+                res[3] = kInv4PiD * (c0 - 3.0 * tot[6]);
+                res[4] = kInv4PiD * (c1 - 3.0 * tot[7]);
+                res[5] = kInv4PiD * (c2 - 3.0 * tot[8]);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T* dst = uo + c * a.ldo + o;
+                *dst = a.accumulate ? T(double(*dst) + res[c]) : T(res[c]);
+            }
+            if (MODE != kModeVelocity) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    T* dst = dgo + c * a.ldo + o;
+                    *dst = a.accumulate ? T(double(*dst) + res[3 + c]) : T(res[3 + c]);
+                }
+            }
+        }
+    }
+
+    template <bool CHECK>
+    static __device__ __forceinline__ void tile(const V4* lp, const V4* lq, int cnt, int64_t j0,
+                                                T (&xi)[K][3], T (&gi)[K][3], T (&cut_i)[K],
+                                                int64_t (&ex)[K], T (&acc)[K][kNacc]) {
+#pragma unroll 2
+        for (int jj = 0; jj < cnt; ++jj) {
+            const V4 p = lp[jj];
+            const V4 q = lq[jj];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                pair_fwd<T, MODE, SYM, CHECK>(p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, xi[k][0],
+                                              xi[k][1], xi[k][2], gi[k][0], gi[k][1], gi[k][2],
+                                              cut_i[k], j0 + jj, ex[k], &acc[k][0],
+                                              &acc[k][kNacc > 3 ? 3 : 0],
+                                              &acc[k][kNacc > 3 ? 6 : 0]);
+            }
+        }
+    }
+};
+
+// One workgroup per target block of a single particle set.
+template <typename T, int K, int WG, int MODE, bool SYM>
+__global__ __launch_bounds__(WG) void k_pair_fwd(FwdArgs a) {
+    using B = FwdBlock<T, K, WG, MODE, SYM>;
+    __shared__ typename B::V4 lp[WG];
+    __shared__ typename B::V4 lq[WG];
+    const int64_t t0 = a.tgt_begin + int64_t(blockIdx.x) * (WG * K);
+    int64_t t1 = t0 + WG * K;
+    if (t1 > a.tgt_end) t1 = a.tgt_end;
+    B::run(a, a.src_begin, a.src_end, t0, t1, a.src_begin - a.tgt_begin, lp, lq);
+}
+
+// Persistent workgroups over a queue of (set, target block) items in decreasing cost order.
+// Every workgroup leaves the loop once the shared counter passes the item count.
+template <typename T, int K, int WG, int MODE, bool SYM>
+__global__ __launch_bounds__(WG) void k_pair_fwd_batched(FwdArgs a, BatchQueue bq) {
+    using B = FwdBlock<T, K, WG, MODE, SYM>;
+    __shared__ typename B::V4 lp[WG];
+    __shared__ typename B::V4 lq[WG];
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(bq.counter, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= bq.n_items) break;
+        const int2 it = bq.items[item];
+        const int b = it.x;
+        const int64_t s0 = bq.src_off[b], s1 = bq.src_off[b + 1];
+        const int64_t tb0 = bq.tgt_off[b], tb1 = bq.tgt_off[b + 1];
+        const int64_t t0 = tb0 + int64_t(it.y) * (WG * K);
+        int64_t t1 = t0 + WG * K;
+        if (t1 > tb1) t1 = tb1;
+        B::run(a, s0, s1, t0, t1, s0 - tb0, lp, lq);
+    }
+}
+
+// ------------------------------------------------------------------ host-side launchers
+namespace {
+
+template <typename T, int K, int WG, int MODE, bool SYM>
+hipError_t launch_one(const FwdArgs& a, const BatchQueue* bq, int grid, hipStream_t st) {
+    if (bq) {
+        hipLaunchKernelGGL((k_pair_fwd_batched<T, K, WG, MODE, SYM>), dim3(grid), dim3(WG), 0, st, a, *bq);
+    } else {
+        hipLaunchKernelGGL((k_pair_fwd<T, K, WG, MODE, SYM>), dim3(grid), dim3(WG), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int K, int WG, int MODE, bool SYM>
+int occupancy_one(bool batched) {
+    int nb = 0;
+    hipError_t e;
+    if (batched)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_fwd_batched<T, K, WG, MODE, SYM>, WG, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_fwd<T, K, WG, MODE, SYM>, WG, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+template <typename T, int K, int WG>
+hipError_t dispatch_mode(int mode, bool sym, const FwdArgs& a, const BatchQueue* bq, int grid,
+                         hipStream_t st) {
+    if (mode == kModeTransposed)
+        return sym ? launch_one<T, K, WG, kModeTransposed, true>(a, bq, grid, st)
+                   : launch_one<T, K, WG, kModeTransposed, false>(a, bq, grid, st);
+    if (mode == kModeClassical)
+        return sym ? launch_one<T, K, WG, kModeClassical, true>(a, bq, grid, st)
+                   : launch_one<T, K, WG, kModeClassical, false>(a, bq, grid, st);
+    return sym ? launch_one<T, K, WG, kModeVelocity, true>(a, bq, grid, st)
+               : launch_one<T, K, WG, kModeVelocity, false>(a, bq, grid, st);
+}
+
+template <typename T, int K, int WG>
+int occupancy_mode(int mode, bool sym, bool batched) {
+    if (mode == kModeTransposed)
+        return sym ? occupancy_one<T, K, WG, kModeTransposed, true>(batched)
+                   : occupancy_one<T, K, WG, kModeTransposed, false>(batched);
+    if (mode == kModeClassical)
+        return sym ? occupancy_one<T, K, WG, kModeClassical, true>(batched)
+                   : occupancy_one<T, K, WG, kModeClassical, false>(batched);
+    return sym ? occupancy_one<T, K, WG, kModeVelocity, true>(batched)
+               : occupancy_one<T, K, WG, kModeVelocity, false>(batched);
+}
+
+}  // namespace
+
+// FP32C variants: (targets per lane, workgroup size).  Index 0 is variant 1.
+const FwdVariant kF32Variants[kNumF32Variants] = {
+    {2, 256}, {1, 256}, {4, 256}, {2, 128}, {4, 128}, {1, 128}, {2, 64}, {4, 64},
+};
+
+hipError_t launch_pair_fwd(int dtype, int variant, int mode, bool sym, const FwdArgs& a,
+                           const BatchQueue* bq, int grid, hipStream_t st) {
+    if (dtype == kDtypeF64) return dispatch_mode<double, 1, 256>(mode, sym, a, bq, grid, st);
+    switch (variant) {
+        case 0: return dispatch_mode<float, 2, 256>(mode, sym, a, bq, grid, st);
+        case 1: return dispatch_mode<float, 1, 256>(mode, sym, a, bq, grid, st);
+        case 2: return dispatch_mode<float, 4, 256>(mode, sym, a, bq, grid, st);
+        case 3: return dispatch_mode<float, 2, 128>(mode, sym, a, bq, grid, st);
+        case 4: return dispatch_mode<float, 4, 128>(mode, sym, a, bq, grid, st);
+        case 5: return dispatch_mode<float, 1, 128>(mode, sym, a, bq, grid, st);
+        case 6: return dispatch_mode<float, 2, 64>(mode, sym, a, bq, grid, st);
+        case 7: return dispatch_mode<float, 4, 64>(mode, sym, a, bq, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int pair_fwd_occupancy(int dtype, int variant, int mode, bool sym, bool batched) {
+    if (dtype == kDtypeF64) return occupancy_mode<double, 1, 256>(mode, sym, batched);
+    switch (variant) {
+        case 0: return occupancy_mode<float, 2, 256>(mode, sym, batched);
+        case 1: return occupancy_mode<float, 1, 256>(mode, sym, batched);
+        case 2: return occupancy_mode<float, 4, 256>(mode, sym, batched);
+        case 3: return occupancy_mode<float, 2, 128>(mode, sym, batched);
+        case 4: return occupancy_mode<float, 4, 128>(mode, sym, batched);
+        case 5: return occupancy_mode<float, 1, 128>(mode, sym, batched);
+        case 6: return occupancy_mode<float, 2, 64>(mode, sym, batched);
+        case 7: return occupancy_mode<float, 4, 64>(mode, sym, batched);
+        default: return 0;
+    }
+}
+
+}  // namespace vpm

@@ -1,0 +1,180 @@
+// Memory-bound helpers: one stage of the low-storage third-order Runge-Kutta scheme used to
+// advance particle positions and strengths (Fu & Laurendeau, Sec. II.B; Williamson's
+// 2N-storage form) and its adjoint, and FP64 invariant diagnostics of an evaluation
+// (total vorticity and linear impulse, the conserved quantities of Eq. 1).
+#include <hip/hip_runtime.h>
+
+#include "vpm_internal.h"
+
+namespace vpm {
+
+namespace {
+
+// 2N-storage coefficients: Q <- A_k Q + dt F; Y <- Y + B_k Q.
+__constant__ double kRkA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+__constant__ double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+// The six component arrays (x, Gamma) are processed as one flat index space of 6 n items.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rk3_stage(int stage, int64_t n, T dt, T* x, T* g, T* qx,
+                                                   T* qg, const T* u, const T* dg, int64_t ld) {
+    const T A = T(kRkA[stage]);
+    const T B = T(kRkB[stage]);
+    const int64_t total = 6 * n;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t c = i / n;
+        const int64_t e = i - c * n;
+        const int64_t off = (c % 3) * ld + e;
+        T* y = c < 3 ? x : g;
+        T* q = c < 3 ? qx : qg;
+        const T* f = c < 3 ? u : dg;
+        const T qn = A * q[off] + dt * f[off];
+        q[off] = qn;
+        y[off] = y[off] + B * qn;
+    }
+}
+
+// Adjoint: qtot = Qbar + B_k Ybar;  seed = dt qtot;  Qbar <- A_k qtot.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rk3_stage_bwd(int stage, int64_t n, T dt, const T* xb,
+                                                       const T* gb, T* qxb, T* qgb, T* us, T* ds,
+                                                       int64_t ld) {
+    const T A = T(kRkA[stage]);
+    const T B = T(kRkB[stage]);
+    const int64_t total = 6 * n;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t c = i / n;
+        const int64_t e = i - c * n;
+        const int64_t off = (c % 3) * ld + e;
+        const T* yb = c < 3 ? xb : gb;
+        T* qb = c < 3 ? qxb : qgb;
+        T* sd = c < 3 ? us : ds;
+        const T qt = qb[off] + B * yb[off];
+        sd[off] = dt * qt;
+        qb[off] = A * qt;
+    }
+}
+
+// Per-block FP64 partial sums (each lane sums its strided items, then a tree over the block),
+// written to partials[block][kDiagSlots].
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_partial(int64_t n, const T* x, const T* g, const T* u,
+                                                      const T* dg, int64_t ld, double* partials) {
+    double s[13];
+#pragma unroll
+    for (int c = 0; c < 13; ++c) s[c] = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const double x0 = x[i], x1 = x[ld + i], x2 = x[2 * ld + i];
+        const double g0 = g[i], g1 = g[ld + i], g2 = g[2 * ld + i];
+        const double u0 = u[i], u1 = u[ld + i], u2 = u[2 * ld + i];
+        const double d0 = dg[i], d1 = dg[ld + i], d2 = dg[2 * ld + i];
+        s[0] += g0;
+        s[1] += g1;
+        s[2] += g2;
+        s[3] += d0;
+        s[4] += d1;
+        s[5] += d2;
+        s[6] += 0.5 * (x1 * g2 - x2 * g1);
+        s[7] += 0.5 * (x2 * g0 - x0 * g2);
+        s[8] += 0.5 * (x0 * g1 - x1 * g0);
+        s[9] += 0.5 * ((u1 * g2 - u2 * g1) + (x1 * d2 - x2 * d1));
+        s[10] += 0.5 * ((u2 * g0 - u0 * g2) + (x2 * d0 - x0 * d2));
+        s[11] += 0.5 * ((u0 * g1 - u1 * g0) + (x0 * d1 - x1 * d0));
+        const double vals[12] = {x0, x1, x2, g0, g1, g2, u0, u1, u2, d0, d1, d2};
+        int bad = 0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) bad += isfinite(vals[c]) ? 0 : 1;
+        s[12] += double(bad);
+    }
+    __shared__ double red[256][13];
+#pragma unroll
+    for (int c = 0; c < 13; ++c) red[threadIdx.x][c] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+#pragma unroll
+            for (int c = 0; c < 13; ++c) red[threadIdx.x][c] += red[threadIdx.x + w][c];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 13) partials[int64_t(blockIdx.x) * kDiagSlots + threadIdx.x] = red[0][threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(int nblocks, const double* partials, double* out) {
+    __shared__ double red[256];
+    for (int c = 0; c < 13; ++c) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partials[int64_t(b) * kDiagSlots + c];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[c] = red[0];
+        __syncthreads();
+    }
+}
+
+int grid_for(int64_t items) {
+    int64_t g = (items + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return int(g);
+}
+
+}  // namespace
+
+hipError_t launch_rk3_stage(int dtype, int stage, int64_t n, double dt, void* x, void* g, void* qx,
+                            void* qg, const void* u, const void* dg, int64_t ld, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int grid = grid_for(6 * n);
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_rk3_stage<double>, dim3(grid), dim3(256), 0, st, stage, n, dt,
+                           (double*)x, (double*)g, (double*)qx, (double*)qg, (const double*)u,
+                           (const double*)dg, ld);
+    else
+        hipLaunchKernelGGL(k_rk3_stage<float>, dim3(grid), dim3(256), 0, st, stage, n, float(dt),
+                           (float*)x, (float*)g, (float*)qx, (float*)qg, (const float*)u,
+                           (const float*)dg, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk3_stage_bwd(int dtype, int stage, int64_t n, double dt, const void* xb,
+                                const void* gb, void* qxb, void* qgb, void* us, void* ds,
+                                int64_t ld, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int grid = grid_for(6 * n);
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_rk3_stage_bwd<double>, dim3(grid), dim3(256), 0, st, stage, n, dt,
+                           (const double*)xb, (const double*)gb, (double*)qxb, (double*)qgb,
+                           (double*)us, (double*)ds, ld);
+    else
+        hipLaunchKernelGGL(k_rk3_stage_bwd<float>, dim3(grid), dim3(256), 0, st, stage, n,
+                           float(dt), (const float*)xb, (const float*)gb, (float*)qxb,
+                           (float*)qgb, (float*)us, (float*)ds, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(int dtype, int64_t n, const void* x, const void* g, const void* u,
+                              const void* dg, int64_t ld, double* out, double* partials,
+                              hipStream_t st) {
+    int nb = int((n + 255) / 256);
+    if (nb > kDiagBlocks) nb = kDiagBlocks;
+    if (nb < 1) nb = 1;
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_diag_partial<double>, dim3(nb), dim3(256), 0, st, n, (const double*)x,
+                           (const double*)g, (const double*)u, (const double*)dg, ld, partials);
+    else
+        hipLaunchKernelGGL(k_diag_partial<float>, dim3(nb), dim3(256), 0, st, n, (const float*)x,
+                           (const float*)g, (const float*)u, (const float*)dg, ld, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, nb, partials, out);
+    return hipGetLastError();
+}
+
+}  // namespace vpm

@@ -1,0 +1,553 @@
+// libvpm host layer: the C ABI declared in include/vpm.h.
+//
+// Every entry point validates its arguments on the host before it makes any HIP call, then
+// launches the kernels on the caller's stream and returns without synchronising.  The only
+// state kept across calls is a per-device property cache and one pinned staging buffer for
+// the batched work queue (both guarded by a mutex).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/vpm.h"
+#include "vpm_internal.h"
+
+namespace {
+
+using vpm::kDtypeF32C;
+using vpm::kDtypeF64;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t elem_size(int32_t dtype) { return dtype == kDtypeF64 ? sizeof(double) : sizeof(float); }
+
+bool dtype_ok(int32_t dtype) { return dtype == kDtypeF64 || dtype == kDtypeF32C; }
+
+// Byte range [lo, hi) covered by a [rows][ld] array of n used items per row.
+struct Range {
+    uintptr_t lo = 0, hi = 0;
+};
+Range span(const void* p, int rows, int64_t ld, int64_t n, size_t es) {
+    Range r;
+    if (!p || n <= 0) return r;
+    r.lo = reinterpret_cast<uintptr_t>(p);
+    r.hi = r.lo + (size_t(rows - 1) * size_t(ld) + size_t(n)) * es;
+    return r;
+}
+bool overlap(const Range& a, const Range& b) {
+    return a.hi > a.lo && b.hi > b.lo && a.lo < b.hi && b.lo < a.hi;
+}
+
+vpm_status check_offsets(int32_t n_batch, const int64_t* off) {
+    if (!off) return VPM_ERR_NULL;
+    if (off[0] != 0) return VPM_ERR_OFFSETS;
+    for (int32_t b = 0; b < n_batch; ++b)
+        if (off[b + 1] < off[b]) return VPM_ERR_OFFSETS;
+    return VPM_OK;
+}
+
+vpm_status check_options(const vpm_options& o) {
+    if (o.scheme != VPM_STRETCH_TRANSPOSED && o.scheme != VPM_STRETCH_CLASSICAL) return VPM_ERR_ENUM;
+    if (o.sigma_rule != VPM_SIGMA_SOURCE && o.sigma_rule != VPM_SIGMA_SYMMETRIC) return VPM_ERR_ENUM;
+    if (o.self != 0 && o.self != 1) return VPM_ERR_ENUM;
+    if (o.accumulate != 0 && o.accumulate != 1) return VPM_ERR_ENUM;
+    if (o.variant < 0 || o.variant > vpm::kNumF32Variants) return VPM_ERR_ENUM;
+    for (int i = 0; i < 3; ++i)
+        if (o.reserved[i] != 0) return VPM_ERR_ENUM;
+    return VPM_OK;
+}
+
+vpm_options default_options() {
+    vpm_options o;
+    std::memset(&o, 0, sizeof(o));
+    return o;
+}
+
+vpm_status hip_status(hipError_t e) { return e == hipSuccess ? VPM_OK : VPM_ERR_HIP; }
+
+// ------------------------------------------------------------------ device properties
+struct DeviceInfo {
+    int cus = 0;
+};
+std::mutex g_mutex;
+std::vector<DeviceInfo> g_devices;
+
+hipError_t device_info(DeviceInfo& out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (int(g_devices.size()) <= dev) g_devices.resize(dev + 1);
+    if (g_devices[dev].cus == 0) {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        g_devices[dev].cus = cus;
+    }
+    out = g_devices[dev];
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ batched work queue
+// Workspace layout: [counter | pad][src_off][tgt_off][items], each part 256-byte aligned.
+// The smallest target block over all kernel shapes bounds the number of items.
+constexpr int64_t kMinTargetsPerBlock = 128;
+
+struct QueueLayout {
+    size_t off_src, off_tgt, off_items, total;
+    int64_t max_items;
+};
+QueueLayout queue_layout(int32_t n_batch, const int64_t* tgt_off, int64_t per_block) {
+    QueueLayout L;
+    int64_t items = 0;
+    for (int32_t b = 0; b < n_batch; ++b) items += (tgt_off[b + 1] - tgt_off[b] + per_block - 1) / per_block;
+    L.max_items = items;
+    L.off_src = kAlign;
+    L.off_tgt = L.off_src + align_up(sizeof(int64_t) * (n_batch + 1));
+    L.off_items = L.off_tgt + align_up(sizeof(int64_t) * (n_batch + 1));
+    L.total = L.off_items + align_up(sizeof(int2) * size_t(items > 0 ? items : 1));
+    return L;
+}
+
+// Pinned host staging for the queue, reused across calls; the event of the previous copy
+// is waited on before the buffer is rewritten.
+struct Staging {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+Staging g_stage;
+
+hipError_t stage_and_copy(const std::vector<unsigned char>& blob, void* dst, hipStream_t st) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    hipError_t e;
+    if (g_stage.pending) {
+        e = hipEventSynchronize(g_stage.done);
+        if (e != hipSuccess) return e;
+        g_stage.pending = false;
+    }
+    if (g_stage.bytes < blob.size()) {
+        if (g_stage.host) {
+            e = hipHostFree(g_stage.host);
+            if (e != hipSuccess) return e;
+            g_stage.host = nullptr;
+            g_stage.bytes = 0;
+        }
+        e = hipHostMalloc(&g_stage.host, blob.size(), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        g_stage.bytes = blob.size();
+    }
+    if (!g_stage.done) {
+        e = hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    std::memcpy(g_stage.host, blob.data(), blob.size());
+    e = hipMemcpyAsync(dst, g_stage.host, blob.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(g_stage.done, st);
+    if (e != hipSuccess) return e;
+    g_stage.pending = true;
+    return hipSuccess;
+}
+
+int fwd_mode(const vpm_options& o, bool stretch) {
+    if (!stretch) return vpm::kModeVelocity;
+    return o.scheme == VPM_STRETCH_CLASSICAL ? vpm::kModeClassical : vpm::kModeTransposed;
+}
+
+int64_t targets_per_block(int32_t dtype, int variant) {
+    if (dtype == kDtypeF64) return vpm::kF64TargetsPerBlock;
+    return int64_t(vpm::kF32Variants[variant].k) * vpm::kF32Variants[variant].wg;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vpm_status_string(int32_t s) {
+    switch (s) {
+        case VPM_OK: return "ok";
+        case VPM_ERR_NULL: return "required pointer is NULL";
+        case VPM_ERR_SIZE: return "invalid size or leading dimension";
+        case VPM_ERR_DTYPE: return "invalid dtype";
+        case VPM_ERR_ENUM: return "invalid option or enum value";
+        case VPM_ERR_ALIAS: return "output overlaps another argument";
+        case VPM_ERR_OFFSETS: return "invalid batch offsets";
+        case VPM_ERR_WORKSPACE: return "workspace missing or too small";
+        case VPM_ERR_HIP: return "HIP runtime error";
+        case VPM_ERR_INPUT: return "invalid input values";
+        case VPM_ERR_UNSUPPORTED: return "combination not supported";
+        default: return "unknown status";
+    }
+}
+
+const char* vpm_version(void) { return "libvpm 0.1 (gfx950)"; }
+
+int32_t vpm_variant_count(void) { return vpm::kNumF32Variants; }
+
+vpm_status vpm_variant_info(int32_t k, int32_t* tpl, int32_t* wg) {
+    if (k < 1 || k > vpm::kNumF32Variants) return VPM_ERR_ENUM;
+    if (!tpl || !wg) return VPM_ERR_NULL;
+    *tpl = vpm::kF32Variants[k - 1].k;
+    *wg = vpm::kF32Variants[k - 1].wg;
+    return VPM_OK;
+}
+
+size_t vpm_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                          const int64_t* tgt_off, const vpm_options* opt) {
+    if (!dtype_ok(dtype) || n_batch < 1 || !src_off) return 0;
+    vpm_options o = opt ? *opt : default_options();
+    if (o.self && !tgt_off) tgt_off = src_off;
+    if (!tgt_off) return 0;
+    if (check_offsets(n_batch, src_off) != VPM_OK || check_offsets(n_batch, tgt_off) != VPM_OK) return 0;
+    if (n_batch == 1) return 0;
+    return queue_layout(n_batch, tgt_off, kMinTargetsPerBlock).total;
+}
+
+vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                                        const int64_t* tgt_off, const void* x_src,
+                                        const void* gamma_src, const void* sigma_src,
+                                        int64_t ld_src, const void* x_tgt, const void* gamma_tgt,
+                                        const void* sigma_tgt, int64_t ld_tgt,
+                                        const int32_t* tgt_exclude, void* u_out, void* dgamma_out,
+                                        int64_t ld_out, const vpm_options* opt, void* workspace,
+                                        size_t ws_bytes, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n_batch < 1) return VPM_ERR_SIZE;
+    vpm_options o = opt ? *opt : default_options();
+    vpm_status s = check_options(o);
+    if (s != VPM_OK) return s;
+    if (!src_off) return VPM_ERR_NULL;
+    s = check_offsets(n_batch, src_off);
+    if (s != VPM_OK) return s;
+    if (o.self) {
+        if (tgt_off && tgt_off != src_off) {
+            for (int32_t b = 0; b <= n_batch; ++b)
+                if (tgt_off[b] != src_off[b]) return VPM_ERR_OFFSETS;
+        }
+        tgt_off = src_off;
+        if ((x_tgt && x_tgt != x_src) || (gamma_tgt && gamma_tgt != gamma_src) ||
+            (sigma_tgt && sigma_tgt != sigma_src))
+            return VPM_ERR_ALIAS;
+        if (ld_tgt != 0 && ld_tgt != ld_src) return VPM_ERR_SIZE;
+        x_tgt = x_src;
+        gamma_tgt = gamma_src;
+        sigma_tgt = sigma_src;
+        ld_tgt = ld_src;
+        tgt_exclude = nullptr;
+    } else {
+        if (!tgt_off) return VPM_ERR_NULL;
+        s = check_offsets(n_batch, tgt_off);
+        if (s != VPM_OK) return s;
+    }
+    const int64_t n_src = src_off[n_batch];
+    const int64_t n_tgt = tgt_off[n_batch];
+    if (n_src > INT32_MAX || n_tgt > INT32_MAX) return VPM_ERR_SIZE;
+    if (ld_src < n_src || ld_tgt < n_tgt || ld_out < n_tgt) return VPM_ERR_SIZE;
+    if (n_src > 0 && (!x_src || !gamma_src || !sigma_src)) return VPM_ERR_NULL;
+    if (n_tgt > 0 && (!x_tgt || !u_out)) return VPM_ERR_NULL;
+    const bool stretch = dgamma_out != nullptr;
+    if (stretch && !gamma_tgt) return VPM_ERR_NULL;
+    const bool sym = o.sigma_rule == VPM_SIGMA_SYMMETRIC;
+    if (sym && n_tgt > 0 && !sigma_tgt) return VPM_ERR_NULL;
+
+    const size_t es = elem_size(dtype);
+    const Range ru = span(u_out, 3, ld_out, n_tgt, es);
+    const Range rd = span(dgamma_out, 3, ld_out, n_tgt, es);
+    const Range ins[7] = {span(x_src, 3, ld_src, n_src, es),   span(gamma_src, 3, ld_src, n_src, es),
+                          span(sigma_src, 1, ld_src, n_src, es), span(x_tgt, 3, ld_tgt, n_tgt, es),
+                          span(gamma_tgt, 3, ld_tgt, n_tgt, es), span(sigma_tgt, 1, ld_tgt, n_tgt, es),
+                          span(tgt_exclude, 1, n_tgt, n_tgt, sizeof(int32_t))};
+    for (const Range& r : ins)
+        if (overlap(ru, r) || overlap(rd, r)) return VPM_ERR_ALIAS;
+    if (overlap(ru, rd)) return VPM_ERR_ALIAS;
+
+    int variant = o.variant > 0 ? o.variant - 1 : 0;
+    QueueLayout L{};
+    if (n_batch > 1) {
+        L = queue_layout(n_batch, tgt_off, kMinTargetsPerBlock);
+        if (!workspace) return VPM_ERR_WORKSPACE;
+        if (ws_bytes < L.total) return VPM_ERR_WORKSPACE;
+        if (overlap(span(workspace, 1, L.total, L.total, 1), ru) ||
+            overlap(span(workspace, 1, L.total, L.total, 1), rd))
+            return VPM_ERR_ALIAS;
+    }
+    if (n_tgt == 0) return VPM_OK;
+
+    // ---- launch (first HIP call)
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    vpm::FwdArgs a;
+    a.xs = x_src;
+    a.gs = gamma_src;
+    a.ss = sigma_src;
+    a.lds = ld_src;
+    a.xt = x_tgt;
+    a.gt = stretch ? gamma_tgt : nullptr;
+    a.st = sym ? sigma_tgt : nullptr;
+    a.ldt = ld_tgt;
+    a.excl = tgt_exclude;
+    a.u = u_out;
+    a.dg = dgamma_out;
+    a.ldo = ld_out;
+    a.src_begin = 0;
+    a.src_end = n_src;
+    a.tgt_begin = 0;
+    a.tgt_end = n_tgt;
+    a.self = o.self;
+    a.accumulate = o.accumulate;
+    const int mode = fwd_mode(o, stretch);
+    const int64_t per_block = targets_per_block(dtype, variant);
+
+    if (n_batch == 1) {
+        const int64_t grid = (n_tgt + per_block - 1) / per_block;
+        return hip_status(vpm::launch_pair_fwd(dtype, variant, mode, sym, a, nullptr, int(grid), st));
+    }
+
+    // Batched: LPT-ordered (set, block) items, staged into the workspace with the counter.
+    struct Item {
+        int b, blk;
+        int64_t cost;
+    };
+    std::vector<Item> items;
+    for (int32_t b = 0; b < n_batch; ++b) {
+        const int64_t nt = tgt_off[b + 1] - tgt_off[b];
+        const int64_t ns = src_off[b + 1] - src_off[b];
+        const int64_t nblk = (nt + per_block - 1) / per_block;
+        for (int64_t k = 0; k < nblk; ++k) {
+            const int64_t tk = std::min<int64_t>(per_block, nt - k * per_block);
+            items.push_back({b, int(k), (ns + 1) * tk});
+        }
+    }
+    if (items.empty()) return VPM_OK;
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    std::vector<unsigned char> blob(L.off_items + sizeof(int2) * items.size(), 0);
+    std::memcpy(blob.data() + L.off_src, src_off, sizeof(int64_t) * (n_batch + 1));
+    std::memcpy(blob.data() + L.off_tgt, tgt_off, sizeof(int64_t) * (n_batch + 1));
+    int2* it = reinterpret_cast<int2*>(blob.data() + L.off_items);
+    for (size_t i = 0; i < items.size(); ++i) {
+        it[i].x = items[i].b;
+        it[i].y = items[i].blk;
+    }
+    hipError_t e = stage_and_copy(blob, workspace, st);
+    if (e != hipSuccess) return VPM_ERR_HIP;
+    DeviceInfo di;
+    e = device_info(di);
+    if (e != hipSuccess) return VPM_ERR_HIP;
+    int occ = vpm::pair_fwd_occupancy(dtype, variant, mode, sym, true);
+    if (occ < 1) occ = 1;
+    int64_t grid = int64_t(di.cus) * occ;
+    if (grid > int64_t(items.size())) grid = int64_t(items.size());
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    vpm::BatchQueue q;
+    q.counter = reinterpret_cast<int*>(ws);
+    q.items = reinterpret_cast<const int2*>(ws + L.off_items);
+    q.src_off = reinterpret_cast<const int64_t*>(ws + L.off_src);
+    q.tgt_off = reinterpret_cast<const int64_t*>(ws + L.off_tgt);
+    q.n_items = int(items.size());
+    return hip_status(vpm::launch_pair_fwd(dtype, variant, mode, sym, a, &q, int(grid), st));
+}
+
+vpm_status vpm_eval_segments(int32_t dtype, int64_t n_seg, const void* a, const void* b,
+                             const void* gamma_seg, int64_t ld_seg, double core_radius,
+                             int32_t vatistas_n, int64_t n_tgt, const void* x_tgt, int64_t ld_tgt,
+                             void* u_out, int64_t ld_out, int32_t accumulate, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n_seg < 0 || n_tgt < 0 || ld_seg < n_seg || ld_tgt < n_tgt || ld_out < n_tgt) return VPM_ERR_SIZE;
+    if (n_seg > INT32_MAX || n_tgt > INT32_MAX) return VPM_ERR_SIZE;
+    if (n_seg > 0 && (!a || !b || !gamma_seg)) return VPM_ERR_NULL;
+    if (n_tgt > 0 && (!x_tgt || !u_out)) return VPM_ERR_NULL;
+    if (!(core_radius >= 0.0) || core_radius > 1e30) return VPM_ERR_SIZE;
+    if (vatistas_n < 1 || vatistas_n > 16) return VPM_ERR_ENUM;
+    if (accumulate != 0 && accumulate != 1) return VPM_ERR_ENUM;
+    const size_t es = elem_size(dtype);
+    const Range ru = span(u_out, 3, ld_out, n_tgt, es);
+    const Range ins[4] = {span(a, 3, ld_seg, n_seg, es), span(b, 3, ld_seg, n_seg, es),
+                          span(gamma_seg, 1, ld_seg, n_seg, es), span(x_tgt, 3, ld_tgt, n_tgt, es)};
+    for (const Range& r : ins)
+        if (overlap(ru, r)) return VPM_ERR_ALIAS;
+    if (n_tgt == 0) return VPM_OK;
+    vpm::SegArgs s;
+    s.a = a;
+    s.b = b;
+    s.gam = gamma_seg;
+    s.ld_seg = ld_seg;
+    s.n_seg = n_seg;
+    s.rc = core_radius;
+    s.vn = vatistas_n;
+    s.xt = x_tgt;
+    s.ldt = ld_tgt;
+    s.n_tgt = n_tgt;
+    s.u = u_out;
+    s.ldo = ld_out;
+    s.accumulate = accumulate;
+    return hip_status(vpm::launch_segments(dtype, s, static_cast<hipStream_t>(stream)));
+}
+
+vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                        const int64_t* tgt_off, const void* x_src, const void* gamma_src,
+                        const void* sigma_src, int64_t ld_src, const void* x_tgt,
+                        const void* gamma_tgt, const void* sigma_tgt, int64_t ld_tgt,
+                        const void* u_bar, const void* dgamma_bar, void* x_src_bar,
+                        void* gamma_src_bar, void* x_tgt_bar, void* gamma_tgt_bar,
+                        const vpm_options* opt, void* workspace, size_t ws_bytes, void* stream) {
+    (void)workspace;
+    (void)ws_bytes;
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n_batch < 1) return VPM_ERR_SIZE;
+    vpm_options o = opt ? *opt : default_options();
+    vpm_status s = check_options(o);
+    if (s != VPM_OK) return s;
+    if (!src_off) return VPM_ERR_NULL;
+    s = check_offsets(n_batch, src_off);
+    if (s != VPM_OK) return s;
+    if (n_batch != 1) return VPM_ERR_UNSUPPORTED;
+    if (o.scheme != VPM_STRETCH_TRANSPOSED) return VPM_ERR_UNSUPPORTED;
+    // Gradients are always accumulated (+=); opt->accumulate is not consulted.
+    if (o.self) {
+        if (tgt_off && tgt_off[1] != src_off[1]) return VPM_ERR_OFFSETS;
+        if ((x_tgt && x_tgt != x_src) || (gamma_tgt && gamma_tgt != gamma_src) ||
+            (sigma_tgt && sigma_tgt != sigma_src))
+            return VPM_ERR_ALIAS;
+        if (x_tgt_bar || gamma_tgt_bar) return VPM_ERR_ALIAS;
+        if (ld_tgt != 0 && ld_tgt != ld_src) return VPM_ERR_SIZE;
+        tgt_off = src_off;
+        x_tgt = x_src;
+        gamma_tgt = gamma_src;
+        sigma_tgt = sigma_src;
+        ld_tgt = ld_src;
+    } else {
+        if (!tgt_off) return VPM_ERR_NULL;
+        s = check_offsets(n_batch, tgt_off);
+        if (s != VPM_OK) return s;
+    }
+    const int64_t n_src = src_off[1];
+    const int64_t n_tgt = tgt_off[1];
+    if (n_src > INT32_MAX || n_tgt > INT32_MAX) return VPM_ERR_SIZE;
+    if (ld_src < n_src || ld_tgt < n_tgt) return VPM_ERR_SIZE;
+    const bool stretch = dgamma_bar != nullptr;
+    const bool sym = o.sigma_rule == VPM_SIGMA_SYMMETRIC;
+    if (n_src > 0 && (!x_src || !gamma_src || !sigma_src || !x_src_bar || !gamma_src_bar)) return VPM_ERR_NULL;
+    if (n_tgt > 0 && (!x_tgt || !u_bar)) return VPM_ERR_NULL;
+    if (n_tgt > 0 && stretch && !gamma_tgt) return VPM_ERR_NULL;
+    if (n_tgt > 0 && sym && !sigma_tgt) return VPM_ERR_NULL;
+    const bool want_tgt = !o.self && (x_tgt_bar || gamma_tgt_bar);
+    if (want_tgt && (!x_tgt_bar || (stretch && !gamma_tgt_bar))) return VPM_ERR_NULL;
+
+    const size_t es = elem_size(dtype);
+    const Range outs[4] = {span(x_src_bar, 3, ld_src, n_src, es), span(gamma_src_bar, 3, ld_src, n_src, es),
+                           span(x_tgt_bar, 3, ld_tgt, n_tgt, es), span(gamma_tgt_bar, 3, ld_tgt, n_tgt, es)};
+    const Range ins[8] = {span(x_src, 3, ld_src, n_src, es),    span(gamma_src, 3, ld_src, n_src, es),
+                          span(sigma_src, 1, ld_src, n_src, es),  span(x_tgt, 3, ld_tgt, n_tgt, es),
+                          span(gamma_tgt, 3, ld_tgt, n_tgt, es),  span(sigma_tgt, 1, ld_tgt, n_tgt, es),
+                          span(u_bar, 3, ld_tgt, n_tgt, es),      span(dgamma_bar, 3, ld_tgt, n_tgt, es)};
+    for (int i = 0; i < 4; ++i) {
+        for (const Range& r : ins)
+            if (overlap(outs[i], r)) return VPM_ERR_ALIAS;
+        for (int j = i + 1; j < 4; ++j)
+            if (overlap(outs[i], outs[j])) return VPM_ERR_ALIAS;
+    }
+    if (n_src == 0 && n_tgt == 0) return VPM_OK;
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    vpm::BwdArgs a;
+    if (o.self) {
+        a.xl = x_src; a.gl = gamma_src; a.sl = sigma_src; a.ubl = u_bar; a.sbl = dgamma_bar;
+        a.ldl = ld_src; a.nl = n_src;
+        a.xo = x_src; a.go = gamma_src; a.so = sigma_src; a.ubo = u_bar; a.sbo = dgamma_bar;
+        a.ldo = ld_src; a.no = n_src;
+        a.xbar = x_src_bar; a.gbar = gamma_src_bar; a.ldg = ld_src; a.self = 1;
+        return hip_status(vpm::launch_backward(dtype, true, true, stretch, sym, a, st));
+    }
+    // Sources' gradients: lane = source (role B), loop = targets.
+    a.xl = x_src; a.gl = gamma_src; a.sl = sigma_src; a.ubl = nullptr; a.sbl = nullptr;
+    a.ldl = ld_src; a.nl = n_src;
+    a.xo = x_tgt; a.go = gamma_tgt; a.so = sigma_tgt; a.ubo = u_bar; a.sbo = dgamma_bar;
+    a.ldo = ld_tgt; a.no = n_tgt;
+    a.xbar = x_src_bar; a.gbar = gamma_src_bar; a.ldg = ld_src; a.self = 0;
+    hipError_t e = vpm::launch_backward(dtype, false, true, stretch, sym, a, st);
+    if (e != hipSuccess) return VPM_ERR_HIP;
+    if (want_tgt) {
+        // Targets' gradients: lane = target (role A), loop = sources.
+        vpm::BwdArgs b;
+        b.xl = x_tgt; b.gl = gamma_tgt; b.sl = sigma_tgt; b.ubl = u_bar; b.sbl = dgamma_bar;
+        b.ldl = ld_tgt; b.nl = n_tgt;
+        b.xo = x_src; b.go = gamma_src; b.so = sigma_src; b.ubo = nullptr; b.sbo = nullptr;
+        b.ldo = ld_src; b.no = n_src;
+        b.xbar = x_tgt_bar; b.gbar = gamma_tgt_bar; b.ldg = ld_tgt; b.self = 0;
+        e = vpm::launch_backward(dtype, true, false, stretch, sym, b, st);
+        if (e != hipSuccess) return VPM_ERR_HIP;
+    }
+    return VPM_OK;
+}
+
+vpm_status vpm_rk3_stage(int32_t dtype, int32_t stage, int64_t n, double dt, void* x, void* gamma,
+                         void* qx, void* qg, const void* u, const void* dgamma, int64_t ld,
+                         void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (stage < 0 || stage > 2) return VPM_ERR_ENUM;
+    if (n < 0 || ld < n) return VPM_ERR_SIZE;
+    if (!(dt == dt)) return VPM_ERR_SIZE;
+    if (n > 0 && (!x || !gamma || !qx || !qg || !u || !dgamma)) return VPM_ERR_NULL;
+    const size_t es = elem_size(dtype);
+    const Range rs[6] = {span(x, 3, ld, n, es),  span(gamma, 3, ld, n, es), span(qx, 3, ld, n, es),
+                         span(qg, 3, ld, n, es), span(u, 3, ld, n, es),     span(dgamma, 3, ld, n, es)};
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j)
+            if (overlap(rs[i], rs[j])) return VPM_ERR_ALIAS;
+    if (n == 0) return VPM_OK;
+    return hip_status(vpm::launch_rk3_stage(dtype, stage, n, dt, x, gamma, qx, qg, u, dgamma, ld,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+vpm_status vpm_rk3_stage_backward(int32_t dtype, int32_t stage, int64_t n, double dt,
+                                  const void* x_bar, const void* gamma_bar, void* qx_bar,
+                                  void* qg_bar, void* u_seed, void* dgamma_seed, int64_t ld,
+                                  void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (stage < 0 || stage > 2) return VPM_ERR_ENUM;
+    if (n < 0 || ld < n) return VPM_ERR_SIZE;
+    if (!(dt == dt)) return VPM_ERR_SIZE;
+    if (n > 0 && (!x_bar || !gamma_bar || !qx_bar || !qg_bar || !u_seed || !dgamma_seed)) return VPM_ERR_NULL;
+    const size_t es = elem_size(dtype);
+    const Range rs[6] = {span(x_bar, 3, ld, n, es),  span(gamma_bar, 3, ld, n, es),
+                         span(qx_bar, 3, ld, n, es), span(qg_bar, 3, ld, n, es),
+                         span(u_seed, 3, ld, n, es), span(dgamma_seed, 3, ld, n, es)};
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j)
+            if (overlap(rs[i], rs[j])) return VPM_ERR_ALIAS;
+    if (n == 0) return VPM_OK;
+    return hip_status(vpm::launch_rk3_stage_bwd(dtype, stage, n, dt, x_bar, gamma_bar, qx_bar, qg_bar,
+                                                u_seed, dgamma_seed, ld, static_cast<hipStream_t>(stream)));
+}
+
+size_t vpm_diagnostics_workspace_size(void) {
+    return size_t(vpm::kDiagBlocks) * vpm::kDiagSlots * sizeof(double);
+}
+
+vpm_status vpm_diagnostics(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* u,
+                           const void* dgamma, int64_t ld, double* out, void* workspace,
+                           size_t ws_bytes, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n < 0 || ld < n) return VPM_ERR_SIZE;
+    if (!out) return VPM_ERR_NULL;
+    if (n > 0 && (!x || !gamma || !u || !dgamma)) return VPM_ERR_NULL;
+    if (!workspace || ws_bytes < vpm_diagnostics_workspace_size()) return VPM_ERR_WORKSPACE;
+    const Range ro = span(out, 1, 13, 13, sizeof(double));
+    const Range rw = span(workspace, 1, vpm_diagnostics_workspace_size(), vpm_diagnostics_workspace_size(), 1);
+    if (overlap(ro, rw)) return VPM_ERR_ALIAS;
+    const size_t es = elem_size(dtype);
+    const Range ins[4] = {span(x, 3, ld, n, es), span(gamma, 3, ld, n, es), span(u, 3, ld, n, es),
+                          span(dgamma, 3, ld, n, es)};
+    for (const Range& r : ins)
+        if (overlap(ro, r) || overlap(rw, r)) return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_diagnostics(dtype, n, x, gamma, u, dgamma, ld, out,
+                                              static_cast<double*>(workspace),
+                                              static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Internal interface between the libvpm host layer (vpm_api.cpp) and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace vpm {
+
+enum { kDtypeF64 = 0, kDtypeF32C = 1 };
+enum { kModeTransposed = 0, kModeClassical = 1, kModeVelocity = 2 };
+
+// Arguments of the particle-pair forward kernels.  Pointers are device pointers of the
+// kernel's element type; 3-vectors are [3][ld].
+struct FwdArgs {
+    const void* xs;
+    const void* gs;
+    const void* ss;
+    int64_t lds;
+    const void* xt;
+    const void* gt;
+    const void* st;
+    int64_t ldt;
+    const int32_t* excl;  // per-target source index to skip (or nullptr)
+    void* u;
+    void* dg;
+    int64_t ldo;
+    int64_t src_begin, src_end;  // single-set launch
+    int64_t tgt_begin, tgt_end;
+    int32_t self;
+    int32_t accumulate;
+};
+
+// Work queue of the persistent batched launch (lives in the caller's workspace).
+struct BatchQueue {
+    int* counter;            // zeroed before the launch
+    const int2* items;       // (set, target block), decreasing cost
+    const int64_t* src_off;  // [n_sets + 1]
+    const int64_t* tgt_off;  // [n_sets + 1]
+    int n_items;
+};
+
+struct FwdVariant {
+    int k;   // targets per lane
+    int wg;  // workgroup size
+};
+constexpr int kNumF32Variants = 8;
+extern const FwdVariant kF32Variants[kNumF32Variants];
+constexpr int kF64TargetsPerBlock = 256;
+
+// variant: 0-based index into kF32Variants (ignored for FP64).  bq == nullptr: one set,
+// grid = number of target blocks; otherwise persistent grid over bq.
+hipError_t launch_pair_fwd(int dtype, int variant, int mode, bool sym, const FwdArgs& a,
+                           const BatchQueue* bq, int grid, hipStream_t st);
+int pair_fwd_occupancy(int dtype, int variant, int mode, bool sym, bool batched);
+
+// ---------------------------------------------------------------- segments
+struct SegArgs {
+    const void* a;
+    const void* b;
+    const void* gam;
+    int64_t ld_seg;
+    int64_t n_seg;
+    double rc;
+    int32_t vn;
+    const void* xt;
+    int64_t ldt;
+    int64_t n_tgt;
+    void* u;
+    int64_t ldo;
+    int32_t accumulate;
+};
+hipError_t launch_segments(int dtype, const SegArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------- adjoint
+// Gather form: each lane owns one particle of the "lane set" and loops over the "loop set".
+//   role A: lane particle is the target (needs lane seeds); loop particles are sources.
+//   role B: lane particle is the source; loop particles are targets (needs loop seeds).
+struct BwdArgs {
+    const void* xl;  // lane set
+    const void* gl;
+    const void* sl;
+    const void* ubl;  // lane seeds (role A)
+    const void* sbl;
+    int64_t ldl;
+    int64_t nl;
+    const void* xo;  // loop set
+    const void* go;
+    const void* so;
+    const void* ubo;  // loop seeds (role B)
+    const void* sbo;
+    int64_t ldo;
+    int64_t no;
+    void* xbar;  // += gradients of the lane set
+    void* gbar;
+    int64_t ldg;
+    int32_t self;  // loop set == lane set, skip j == i
+};
+hipError_t launch_backward(int dtype, bool role_a, bool role_b, bool stretch, bool sym,
+                           const BwdArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------- RK3 and diagnostics
+hipError_t launch_rk3_stage(int dtype, int stage, int64_t n, double dt, void* x, void* g, void* qx,
+                            void* qg, const void* u, const void* dg, int64_t ld, hipStream_t st);
+hipError_t launch_rk3_stage_bwd(int dtype, int stage, int64_t n, double dt, const void* xb,
+                                const void* gb, void* qxb, void* qgb, void* us, void* ds,
+                                int64_t ld, hipStream_t st);
+constexpr int kDiagBlocks = 512;
+constexpr int kDiagSlots = 16;  // doubles per block partial (13 used)
+hipError_t launch_diagnostics(int dtype, int64_t n, const void* x, const void* g, const void* u,
+                              const void* dg, int64_t ld, double* out, double* partials,
+                              hipStream_t st);
+
+}  // namespace vpm

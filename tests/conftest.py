@@ -22,7 +22,7 @@ def gpu_available():
 
 
 @pytest.fixture(scope="session")
-def dev():
+def gpu():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

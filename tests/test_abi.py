@@ -1,0 +1,156 @@
+"""The C ABI without a GPU: the library loads, exports every entry point include/vpm.h
+declares, and rejects bad arguments on the host before any HIP call (fake device
+pointers are never dereferenced on these paths)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2511_11430_amd import _lib
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vpm.h")
+
+OK, NULL, SIZE, DTYPE, ENUM, ALIAS, OFFSETS, WORKSPACE, HIP, INPUT, UNSUPPORTED = range(11)
+F64, F32C = 0, 1
+
+
+def declared_functions():
+    text = open(HDR).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vpm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for n in ("vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_backward", "vpm_rk3_stage",
+              "vpm_rk3_stage_backward", "vpm_diagnostics", "vpm_workspace_size", "vpm_status_string"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_status_strings_and_version():
+    lib = _lib.load()
+    assert lib.vpm_status_string(0) == b"ok"
+    assert b"NULL" in lib.vpm_status_string(1)
+    assert lib.vpm_status_string(99) == b"unknown status"
+    assert b"gfx950" in lib.vpm_version()
+    assert lib.vpm_variant_count() == 8
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.vpm_variant_info(1, ctypes.byref(a), ctypes.byref(b)) == OK and (a.value, b.value) == (2, 256)
+    assert lib.vpm_variant_info(0, ctypes.byref(a), ctypes.byref(b)) == ENUM
+
+
+# Fake, distinct, never-dereferenced device addresses.
+def P(k):
+    return ctypes.c_void_p(0x100000 * (k + 1))
+
+
+def off(*v):
+    return (ctypes.c_int64 * len(v))(*v)
+
+
+def opts(**kw):
+    o = _lib.VpmOptions()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def evs(dtype=F32C, n_batch=1, so=None, to=None, xs=P(0), gs=P(1), ss=P(2), lds=100, xt=P(3), gt=P(4), st=P(5),
+        ldt=50, ex=None, u=P(6), dg=P(7), ldo=50, o=None, ws=None, wsb=0):
+    lib = _lib.load()
+    so = off(0, 100) if so is None else so
+    to = off(0, 50) if to is None else to
+    o = opts() if o is None else o
+    return lib.vpm_eval_velocity_stretching(dtype, n_batch, so, to, xs, gs, ss, lds, xt, gt, st, ldt, ex, u, dg, ldo,
+                                            ctypes.byref(o), ws, wsb, None)
+
+
+def test_eval_validation_paths():
+    assert evs(dtype=7) == DTYPE
+    assert evs(n_batch=0) == SIZE
+    lib = _lib.load()
+    o = opts()
+    assert lib.vpm_eval_velocity_stretching(F32C, 1, None, off(0, 50), P(0), P(1), P(2), 100, P(3), P(4), P(5), 50,
+                                            None, P(6), P(7), 50, ctypes.byref(o), None, 0, None) == NULL
+    assert evs(so=off(1, 100)) == OFFSETS
+    assert evs(n_batch=2, so=off(0, 60, 40), to=off(0, 20, 50)) == OFFSETS
+    assert evs(lds=99) == SIZE
+    assert evs(ldo=10) == SIZE
+    assert evs(xs=None) == NULL
+    assert evs(u=None) == NULL
+    assert evs(gt=None) == NULL                    # stretching needs target strengths
+    assert evs(o=opts(scheme=2)) == ENUM
+    assert evs(o=opts(sigma_rule=3)) == ENUM
+    assert evs(o=opts(variant=9)) == ENUM
+    o = opts()
+    o.reserved[1] = 1
+    assert evs(o=o) == ENUM
+    assert evs(o=opts(sigma_rule=1), st=None) == NULL
+    assert evs(u=P(0)) == ALIAS                     # output on an input
+    assert evs(dg=P(6)) == ALIAS                    # two outputs on one buffer
+    assert evs(o=opts(self_=1), to=off(0, 100), xt=P(9)) == ALIAS   # self with other targets
+    assert evs(o=opts(self_=1), to=off(0, 50)) == OFFSETS
+    assert evs(n_batch=2, so=off(0, 60, 100), to=off(0, 20, 50)) == WORKSPACE
+    # empty target set: nothing to launch, succeeds without touching the GPU
+    assert evs(to=off(0, 0), ldt=0) == OK
+
+
+def test_workspace_size():
+    lib = _lib.load()
+    o = opts()
+    assert lib.vpm_workspace_size(F32C, 1, off(0, 100), off(0, 100), ctypes.byref(o)) == 0
+    n = lib.vpm_workspace_size(F32C, 3, off(0, 1000, 3000, 9000), off(0, 1000, 3000, 9000), ctypes.byref(o))
+    assert n >= 256 + 2 * 32 + 8 * (9000 // 128)
+    assert lib.vpm_workspace_size(F32C, 2, off(0, 5, 3), off(0, 5, 3), ctypes.byref(o)) == 0
+
+
+def test_segments_validation():
+    lib = _lib.load()
+    f = lib.vpm_eval_segments
+    assert f(9, 10, P(0), P(1), P(2), 10, 0.02, 2, 5, P(3), 5, P(4), 5, 0, None) == DTYPE
+    assert f(F32C, -1, P(0), P(1), P(2), 10, 0.02, 2, 5, P(3), 5, P(4), 5, 0, None) == SIZE
+    assert f(F32C, 10, P(0), P(1), P(2), 9, 0.02, 2, 5, P(3), 5, P(4), 5, 0, None) == SIZE
+    assert f(F32C, 10, P(0), P(1), P(2), 10, -1.0, 2, 5, P(3), 5, P(4), 5, 0, None) == SIZE
+    assert f(F32C, 10, P(0), P(1), P(2), 10, 0.02, 0, 5, P(3), 5, P(4), 5, 0, None) == ENUM
+    assert f(F32C, 10, None, P(1), P(2), 10, 0.02, 2, 5, P(3), 5, P(4), 5, 0, None) == NULL
+    assert f(F32C, 10, P(0), P(1), P(2), 10, 0.02, 2, 5, P(3), 5, P(3), 5, 0, None) == ALIAS
+    assert f(F32C, 10, P(0), P(1), P(2), 10, 0.02, 2, 0, P(3), 0, P(4), 0, 0, None) == OK
+
+
+def test_backward_validation():
+    lib = _lib.load()
+    o = opts(self_=1)
+    b = lib.vpm_backward
+    args = lambda **k: [k.get("dt", F32C), k.get("nb", 1), k.get("so", off(0, 100)), None, P(0), P(1), P(2), 100,
+                        None, None, None, 0, P(3), P(4), k.get("xb", P(5)), P(6), None, None,
+                        ctypes.byref(k.get("o", o)), None, 0, None]
+    assert b(*args(dt=4)) == DTYPE
+    assert b(*args(nb=2, so=off(0, 50, 100))) == UNSUPPORTED
+    assert b(*args(o=opts(self_=1, scheme=1))) == UNSUPPORTED
+    assert b(*args(xb=None)) == NULL
+    assert b(*args(xb=P(0))) == ALIAS
+
+
+def test_rk3_and_diagnostics_validation():
+    lib = _lib.load()
+    r = lib.vpm_rk3_stage
+    assert r(F32C, 3, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 10, None) == ENUM
+    assert r(F32C, 0, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 9, None) == SIZE
+    assert r(F32C, 0, 10, 0.1, P(0), P(0), P(2), P(3), P(4), P(5), 10, None) == ALIAS
+    assert r(F32C, 0, 10, 0.1, None, P(1), P(2), P(3), P(4), P(5), 10, None) == NULL
+    assert r(F32C, 0, 0, 0.1, None, None, None, None, None, None, 0, None) == OK
+    rb = lib.vpm_rk3_stage_backward
+    assert rb(F32C, -1, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 10, None) == ENUM
+    d = lib.vpm_diagnostics
+    need = lib.vpm_diagnostics_workspace_size()
+    assert need >= 13 * 8
+    assert d(F32C, 10, P(0), P(1), P(2), P(3), 10, P(4), P(5), need - 1, None) == WORKSPACE
+    assert d(F32C, 10, P(0), P(1), P(2), P(3), 10, None, P(5), need, None) == NULL

@@ -1,0 +1,212 @@
+"""GPU parity of the forward particle sums (Eqs. 2-5) and the segment velocity (Sec. II.A)
+against the FP64 oracle: element-wise at sizes the oracle finishes in seconds (several tiles
+plus a ragged tail), and on sampled outputs at the benchmark's full sizes and launch shape."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2511_11430_amd as vpm
+from paper_2511_11430_amd import workloads as W
+
+from gpu_helpers import TOL, dev, host, prepare, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+KINDS = ["f64", "f32c"]
+
+
+def _random_set(n, seed, spread=0.3):
+    rng = np.random.default_rng([4242, seed])
+    x = rng.uniform(-spread, spread, (3, n))
+    g = rng.normal(0, 1e-3, (3, n))
+    s = rng.uniform(0.02, 0.06, n)
+    return x, g, s
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_config1_uniform_cube(kind, gpu):
+    c = W.config1()
+    x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], kind)
+    say(f"config1 {kind} N={x.shape[1]}")
+    u, d = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
+    uo, do = oracle.eval_pairs(x, g, s)
+    assert rel_l2(host(u), uo) <= TOL[kind]
+    assert rel_l2(host(d), do) <= TOL[kind]
+
+
+def dev_(a, kind):
+    return dev(a, kind)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n", [1, 2, 37, 300, 1537])
+@pytest.mark.parametrize("scheme,rule", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_ragged_sizes_schemes_rules(kind, n, scheme, rule, gpu):
+    x, g, s = prepare(_random_set(n, n), kind)
+    say(f"ragged {kind} n={n} scheme={scheme} rule={rule}")
+    u, d = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind), scheme=scheme,
+                                            sigma_rule=rule)
+    uo, do = oracle.eval_pairs(x, g, s, scheme=scheme, sigma_rule=rule)
+    if n == 1:
+        assert np.all(host(u) == 0) and np.all(host(d) == 0)
+        return
+    assert rel_l2(host(u), uo) <= TOL[kind]
+    assert rel_l2(host(d), do) <= TOL[kind]
+
+
+@pytest.mark.parametrize("variant", range(1, 9))
+def test_every_fp32_kernel_shape(variant, gpu):
+    x, g, s = prepare(_random_set(2111, 5), "f32c")
+    say(f"variant {variant}")
+    u, d = vpm.vpm_eval_velocity_stretching(dev_(x, "f32c"), dev_(g, "f32c"), dev_(s, "f32c"), variant=variant)
+    uo, do = oracle.eval_pairs(x, g, s)
+    assert rel_l2(host(u), uo) <= TOL["f32c"]
+    assert rel_l2(host(d), do) <= TOL["f32c"]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_empty_and_coincident(kind, gpu):
+    import torch
+    e = torch.zeros((3, 0), dtype=torch.float64 if kind == "f64" else torch.float32, device="cuda")
+    u, d = vpm.vpm_eval_velocity_stretching(e, e, e[0])
+    assert u.shape == (3, 0)
+    # two distinct particles at one point: no velocity, stretching g(0) Gamma_i x Gamma_j
+    x = np.zeros((3, 2))
+    g = np.array([[1e-3, 0.0], [0.0, 2e-3], [0.0, 0.0]])
+    s = np.full(2, 0.04)
+    u, d = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
+    uo, do = oracle.eval_pairs(x, g, s)
+    assert np.all(host(u) == 0)
+    assert rel_l2(host(d), do) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_accumulate_and_velocity_only(kind, gpu):
+    x, g, s = prepare(_random_set(700, 9), kind)
+    X, G, S = dev_(x, kind), dev_(g, kind), dev_(s, kind)
+    u, d = vpm.vpm_eval_velocity_stretching(X, G, S)
+    u2, d2 = vpm.vpm_eval_velocity_stretching(X, G, S, u_out=u.clone(), dgamma_out=d.clone(), accumulate=True)
+    uo, do = oracle.eval_pairs(x, g, s)
+    assert rel_l2(host(u2), 2 * uo) <= TOL[kind]
+    assert rel_l2(host(d2), 2 * do) <= TOL[kind]
+    uv, dv = vpm.vpm_eval_velocity_stretching(X, G, S, velocity_only=True)
+    assert dv is None and rel_l2(host(uv), uo) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_control_points_and_sampled_targets(kind, gpu):
+    c = W.config2(n=6000)
+    x, g, s, y = prepare([c["x"], c["gamma"], c["sigma"], c["ctrl"]], kind)
+    X, G, S = dev_(x, kind), dev_(g, kind), dev_(s, kind)
+    # blade control points: velocity only (source-core rule)
+    uc, dc = vpm.vpm_eval_velocity_stretching(X, G, S, dev_(y, kind))
+    assert dc is None
+    uco, _ = oracle.eval_pairs(x, g, s, x_tgt=y)
+    assert rel_l2(host(uc), uco) <= TOL[kind]
+    # a subset of the particles as explicit targets, each skipping itself
+    import torch
+    idx = np.sort(np.random.default_rng(3).choice(x.shape[1], 300, replace=False))
+    ex = torch.tensor(idx, dtype=torch.int32, device="cuda")
+    ut, dt_ = vpm.vpm_eval_velocity_stretching(X, G, S, dev_(x[:, idx], kind), dev_(g[:, idx], kind),
+                                               dev_(s[idx], kind), tgt_exclude=ex)
+    uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
+    assert rel_l2(host(ut), uo) <= TOL[kind]
+    assert rel_l2(host(dt_), do) <= TOL[kind]
+
+
+def _sampled_parity(c, kind, n_sample, seed):
+    x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], kind)
+    n = x.shape[1]
+    say(f"full-size self evaluation {kind} N={n}")
+    u, d = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
+    idx = np.sort(np.random.default_rng(seed).choice(n, n_sample, replace=False))
+    uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
+    U, D = host(u)[:, idx], host(d)[:, idx]
+    return rel_l2(U, uo), rel_l2(D, do)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_config2_full_size_sampled(kind, gpu):
+    eu, ed = _sampled_parity(W.config2(), kind, 512, 21)
+    say(f"config2 {kind}: rel-L2 u {eu:.3e} dgamma {ed:.3e}")
+    assert eu <= TOL[kind] and ed <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_config3_full_size_sampled(kind, gpu):
+    c = W.config3()
+    x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], kind)
+    say(f"config3 {kind} N={x.shape[1]}")
+    u, d = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
+    idx = c["sample"][:: 16]  # 256 of the 4096 seeded sample targets
+    uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
+    eu, ed = rel_l2(host(u)[:, idx], uo), rel_l2(host(d)[:, idx], do)
+    say(f"config3 {kind}: rel-L2 u {eu:.3e} dgamma {ed:.3e}")
+    assert eu <= TOL[kind] and ed <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("rc,vn", [(0.02, 2), (0.0, 2), (0.02, 1), (0.03, 3)])
+def test_segments(kind, rc, vn, gpu):
+    c = W.config2(n=3000)
+    a, b, gs, x = prepare([c["seg_a"], c["seg_b"], c["seg_gamma"], c["x"]], kind)
+    say(f"segments {kind} rc={rc} n={vn}")
+    u = vpm.vpm_eval_segments(dev_(a, kind), dev_(b, kind), dev_(gs, kind), dev_(x, kind), rc, vn)
+    uo = oracle.segments(a, b, gs, x, rc, vn)
+    assert rel_l2(host(u), uo) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_segments_full_size_on_particles_and_control_points(kind, gpu):
+    c = W.config2()
+    a, b, gs, x, y = prepare([c["seg_a"], c["seg_b"], c["seg_gamma"], c["x"], c["ctrl"]], kind)
+    u = vpm.vpm_eval_segments(dev_(a, kind), dev_(b, kind), dev_(gs, kind), dev_(x, kind), 0.02, 2)
+    idx = np.sort(np.random.default_rng(5).choice(x.shape[1], 2048, replace=False))
+    uo = oracle.segments(a, b, gs, x[:, idx], 0.02, 2)
+    assert rel_l2(host(u)[:, idx], uo) <= TOL[kind]
+    uc = vpm.vpm_eval_segments(dev_(a, kind), dev_(b, kind), dev_(gs, kind), dev_(y, kind), 0.02, 2)
+    assert rel_l2(host(uc), oracle.segments(a, b, gs, y, 0.02, 2)) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_batched_persistent_matches_single_launches(kind, gpu):
+    import torch
+    wakes = W.config5(scale=0.02)
+    xs = [prepare([w["x"], w["gamma"], w["sigma"]], kind) for w in wakes]
+    off = [0]
+    for x, _, _ in xs:
+        off.append(off[-1] + x.shape[1])
+    X = dev_(np.concatenate([x for x, _, _ in xs], 1), kind)
+    G = dev_(np.concatenate([g for _, g, _ in xs], 1), kind)
+    S = dev_(np.concatenate([s for _, _, s in xs], 0), kind)
+    say(f"batched {kind}: {len(wakes)} wakes, {off[-1]} particles")
+    u, d = vpm.vpm_eval_velocity_stretching(X, G, S, src_off=off)
+    torch.cuda.synchronize()
+    U, D = host(u), host(d)
+    for w in (0, 7, 31, 63):
+        lo, hi = off[w], off[w + 1]
+        u1, d1 = vpm.vpm_eval_velocity_stretching(X[:, lo:hi].contiguous(), G[:, lo:hi].contiguous(),
+                                                  S[lo:hi].contiguous())
+        # same kernel shape and summation order: identical results
+        assert np.array_equal(host(u1), U[:, lo:hi]) and np.array_equal(host(d1), D[:, lo:hi])
+        x, g, s = xs[w]
+        idx = np.arange(0, x.shape[1], max(1, x.shape[1] // 64))
+        uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
+        assert rel_l2(U[:, lo:hi][:, idx], uo) <= TOL[kind]
+        assert rel_l2(D[:, lo:hi][:, idx], do) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_diagnostics(kind, gpu):
+    x, g, s = prepare(_random_set(3000, 12), kind)
+    X, G, S = dev_(x, kind), dev_(g, kind), dev_(s, kind)
+    u, d = vpm.vpm_eval_velocity_stretching(X, G, S, sigma_rule=1)
+    out = vpm.vpm_diagnostics(X, G, u, d).cpu().numpy()
+    ref = oracle.diagnostics(x, g, host(u), host(d))
+    for k, sl in (("sum_gamma", slice(0, 3)), ("sum_dgamma", slice(3, 6)), ("impulse", slice(6, 9)),
+                  ("impulse_rate", slice(9, 12))):
+        assert np.allclose(out[sl], ref[k], rtol=1e-12, atol=1e-13 * np.abs(ref[k]).max() + 1e-300), k
+    assert out[12] == 0
+    # transposed scheme with symmetric cores conserves total vorticity on the GPU too
+    _, do = oracle.eval_pairs(x, g, s, sigma_rule=1)
+    scale = np.abs(do).sum()
+    assert np.abs(out[3:6]).max() <= (1e-13 if kind == "f64" else 1e-6) * scale
