@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Benchmark of the vortex-particle hot path on one MI355X.
+
+One step = one right-hand-side pass of the forward hot path over the forward-flight
+wake (N_p = 1,048,576 particles, 4 blades, advance ratio 0.15, 20 revolutions):
+  1. FP32-compensated particle velocity + transposed stretching, all pairs (Eqs. 2-5),
+  2. velocity of the 4x8x32 bound-ring lattice (4096 Vatistas-cored segments) on every
+     particle (Sec. II.A), accumulated into u,
+  3. velocity of the particles and the lattice at the 128 blade control points,
+  4. one low-storage RK3 stage update of (x, Gamma) (Sec. II.B),
+  5. FP64 invariant diagnostics (total vorticity, impulse, non-finite count).
+``value`` is particle-pair interactions per second of the whole step (N_p^2 / step time).
+
+Also measured (same JSON line): the plain FP64 GPU path on the same particles (speedup),
+the adjoint/forward time ratio on the 262,144-particle hover wake, the batched
+persistent launch of 64 uneven wakes vs 64 separate launches, the dominant kernel's
+roofline position, the error against the FP64 oracle on seeded sample targets, and the
+oracle's own throughput on the host cores (cpu_baseline).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--quick]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
+FLOP_PER_PAIR_VS = 45               # velocity + transposed stretching, point-vortex branch
+PAIR_KERNEL = "k_pair_fwd<float, 2, 256, transposed, source rule>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pair_fwd_f32c_forward_flight_1M.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("pair_forward.hip", "device_math.h", "vpm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2511_11430_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(launch_units):
+    """HBM bytes per launch from committed rocprofv3 --pmc counters, if the kernel source
+    has not changed since they were taken; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the FP64, adjoint and batching legs")
+    ap.add_argument("--n", type=int, default=1 << 20, help="particles (default: the full 1,048,576)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2511_11430_amd as vpm
+    from paper_2511_11430_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    # ------------------------------------------------------------------ inputs (resident in HBM)
+    log("generating the forward-flight wake")
+    c = W.config3(n=args.n)
+    f32 = lambda a: torch.tensor(np.ascontiguousarray(W.to_f32(a)), dtype=torch.float32, device=dev)
+    x0, g0, s = f32(c["x"]), f32(c["gamma"]), f32(c["sigma"])
+    sa, sb, sg = f32(c["seg_a"]), f32(c["seg_b"]), f32(c["seg_gamma"])
+    ctrl = f32(c["ctrl"])
+    N, S, M = x0.shape[1], sa.shape[1], ctrl.shape[1]
+    rc, vn = c["core_radius"], c["vatistas_n"]
+    x, g = x0.clone(), g0.clone()
+    u = torch.empty_like(x)
+    dg = torch.empty_like(x)
+    qx, qg = torch.zeros_like(x), torch.zeros_like(x)
+    uc = torch.empty((3, M), dtype=torch.float32, device=dev)
+    diag = torch.empty(13, dtype=torch.float64, device=dev)
+    diag_ws = torch.empty(vpm._lib.load().vpm_diagnostics_workspace_size(), dtype=torch.uint8, device=dev)
+    # source-split partials of the small control-point target set, allocated once
+    ctrl_ws = torch.empty(max(1, vpm.vpm_workspace_size(vpm.F32C, [0, N], [0, M], self_eval=False)),
+                          dtype=torch.uint8, device=dev)
+    dt = W.DT
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+
+    def step(i, timed):
+        # particle self-interaction (the dominant kernel), events on its own stream
+        if timed:
+            ev[i][0].record(stream)
+        vpm.vpm_eval_velocity_stretching(x, g, s, u_out=u, dgamma_out=dg)
+        if timed:
+            ev[i][1].record(stream)
+        vpm.vpm_eval_segments(sa, sb, sg, x, rc, vn, u_out=u, accumulate=True)
+        vpm.vpm_eval_velocity_stretching(x, g, s, ctrl, u_out=uc, workspace=ctrl_ws)
+        vpm.vpm_eval_segments(sa, sb, sg, ctrl, rc, vn, u_out=uc, accumulate=True)
+        vpm.vpm_rk3_stage(i % 3, dt, x, g, qx, qg, u, dg)
+        vpm.vpm_diagnostics(x, g, u, dg, out=diag, workspace=diag_ws)
+
+    log(f"warmup {args.warmup} step(s), N_p={N}")
+    for i in range(args.warmup):
+        step(i, False)
+    torch.cuda.synchronize()
+    x.copy_(x0)
+    g.copy_(g0)
+    qx.zero_()
+    qg.zero_()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} step(s)")
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    k_ms = float(np.mean(kernel_ms))
+    pairs = float(N) * float(N)
+    value = pairs / (ms_per_step * 1e-3) / 1e9
+    achieved = FLOP_PER_PAIR_VS * pairs / (k_ms * 1e-3) / 1e12
+    log(f"step {ms_per_step:.1f} ms, pair kernel {k_ms:.1f} ms, {value:.1f} Gpair/s")
+    nonfinite = int(diag[12].item())
+
+    result = {
+        "metric": "Gpair-interactions/s FP32-comp vs FP64 GPU at 1e-5 relL2; adjoint/fwd time",
+        "value": round(value, 2), "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": c["name"] + " + 4x8x32 bound-ring lattice (4096 segments) + 128 control points",
+                   "n_particles": N, "n_segments": S, "n_control_points": M, "scheme": "transposed",
+                   "sigma_rule": "source", "step": "particle RHS + segments + control points + RK3 stage + "
+                                                   "FP64 diagnostics"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": load_traffic(1), "kernel": PAIR_KERNEL, "kernel_ms": round(k_ms, 3),
+                     "flop_per_pair": FLOP_PER_PAIR_VS},
+        "nonfinite": nonfinite,
+    }
+
+    # ------------------------------------------------------------------ accuracy + CPU baseline
+    import oracle
+    xs_h, gs_h, ss_h = (W.to_f32(c[k]) for k in ("x", "gamma", "sigma"))
+    x.copy_(x0)
+    g.copy_(g0)
+    vpm.vpm_eval_velocity_stretching(x, g, s, u_out=u, dgamma_out=dg)
+    U, D = u.cpu().double().numpy(), dg.cpu().double().numpy()
+    threads = len(os.sched_getaffinity(0))
+    sample = c["sample"]
+    # calibrate the sample so the oracle runs ~15 s on the host cores
+    t = time.perf_counter()
+    oracle.eval_pairs(xs_h, gs_h, ss_h, x_tgt=xs_h[:, sample[:8]], gam_tgt=gs_h[:, sample[:8]], excl=sample[:8],
+                      nthreads=threads)
+    per_tgt = (time.perf_counter() - t) / 8
+    m = 64 if args.no_cpu_baseline else int(min(len(sample), max(64, 15.0 / max(per_tgt, 1e-6))))
+    idx = sample[:m]
+    log(f"oracle on {m} sample targets x {N} sources, {threads} threads")
+    t = time.perf_counter()
+    uo, do = oracle.eval_pairs(xs_h, gs_h, ss_h, x_tgt=xs_h[:, idx], gam_tgt=gs_h[:, idx], excl=idx,
+                               nthreads=threads)
+    t_or = time.perf_counter() - t
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    result["accuracy"] = {"rel_l2_u": rel(U[:, idx], uo), "rel_l2_dgamma": rel(D[:, idx], do),
+                          "sample_targets": m, "gate": 1e-5, "against": "FP64 oracle"}
+    if not args.no_cpu_baseline:
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next(ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
+        result["cpu_baseline"] = {"value": round(m * N / t_or / 1e9, 4), "unit": "Gpair/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"{m} seeded targets x {N} sources of the same wake, FP64 direct sums "
+                                            f"({t_or:.1f} s)", "cpu": cpu_model}
+
+    if not args.quick:
+        # ------------------------------------------------------------------ FP64 GPU path
+        x64, g64, s64 = (torch.tensor(np.ascontiguousarray(W.to_f32(c[k])), dtype=torch.float64, device=dev)
+                         for k in ("x", "gamma", "sigma"))
+        u64, d64 = torch.empty_like(x64), torch.empty_like(x64)
+        vpm.vpm_eval_velocity_stretching(x64, g64, s64, u_out=u64, dgamma_out=d64)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        vpm.vpm_eval_velocity_stretching(x64, g64, s64, u_out=u64, dgamma_out=d64)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        f64_ms = e0.elapsed_time(e1)
+        U64, D64 = u64.cpu().numpy(), d64.cpu().numpy()
+        result["fp64"] = {"kernel_ms": round(f64_ms, 2), "gpair_s": round(pairs / (f64_ms * 1e-3) / 1e9, 2),
+                          "speedup_f32c_over_f64": round(f64_ms / k_ms, 3),
+                          "rel_l2_u": rel(U64[:, idx], uo), "rel_l2_dgamma": rel(D64[:, idx], do),
+                          "gate": 1e-12}
+        del x64, g64, s64, u64, d64
+
+        # ------------------------------------------------------------------ adjoint / forward
+        c4 = W.config4()
+        xa, ga, sa4 = (torch.tensor(np.ascontiguousarray(W.to_f32(c4[k])), dtype=torch.float32, device=dev)
+                       for k in ("x", "gamma", "sigma"))
+        ua, da = torch.empty_like(xa), torch.empty_like(xa)
+        ub, db = torch.randn_like(xa), torch.randn_like(xa)
+        xb, gb = torch.zeros_like(xa), torch.zeros_like(xa)
+
+        def timed(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps
+
+        fwd_ms = timed(lambda: vpm.vpm_eval_velocity_stretching(xa, ga, sa4, u_out=ua, dgamma_out=da))
+        bwd_ms = timed(lambda: vpm.vpm_backward(xa, ga, sa4, ub, db, x_src_bar=xb, gamma_src_bar=gb))
+        result["adjoint"] = {"workload": c4["name"], "fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3),
+                             "bwd_over_fwd": round(bwd_ms / fwd_ms, 3), "target": 3.0}
+        del xa, ga, sa4, ua, da, ub, db, xb, gb
+
+        # ------------------------------------------------------------------ batched persistent
+        wakes = W.config5()
+        off = [0]
+        for w in wakes:
+            off.append(off[-1] + w["x"].shape[1])
+        cat = lambda k: np.concatenate([W.to_f32(w[k]) for w in wakes], axis=-1)
+        xw = torch.tensor(cat("x"), dtype=torch.float32, device=dev)
+        gw = torch.tensor(cat("gamma"), dtype=torch.float32, device=dev)
+        sw = torch.tensor(cat("sigma"), dtype=torch.float32, device=dev)
+        uw, dw = torch.empty_like(xw), torch.empty_like(xw)
+        ws = torch.empty(vpm.vpm_workspace_size(vpm.F32C, off), dtype=torch.uint8, device=dev)
+        views = [(xw[:, a:b], gw[:, a:b], sw[a:b], uw[:, a:b], dw[:, a:b]) for a, b in zip(off[:-1], off[1:])]
+
+        def separate():
+            for xv, gv, sv, uv, dv in views:
+                vpm.vpm_eval_velocity_stretching(xv, gv, sv, u_out=uv, dgamma_out=dv)
+
+        t_batched = timed(lambda: vpm.vpm_eval_velocity_stretching(xw, gw, sw, u_out=uw, dgamma_out=dw,
+                                                                    src_off=off, workspace=ws), reps=2)
+        t_sep = timed(separate, reps=2)
+        sq = float(sum((b - a) ** 2 for a, b in zip(off[:-1], off[1:])))
+        result["batched"] = {"n_wakes": len(wakes), "n_particles": off[-1], "sum_n_sq": sq,
+                             "persistent_ms": round(t_batched, 3), "separate_ms": round(t_sep, 3),
+                             "gpair_s": round(sq / (t_batched * 1e-3) / 1e9, 2),
+                             "speedup": round(t_sep / t_batched, 3)}
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -103,7 +103,11 @@ typedef struct vpm_options {
  *                   opt->self.
  *  u_out [3][ld_out], dgamma_out [3][ld_out]: results; must not overlap any input.
  *  opt              NULL = defaults (transposed, source rule, self = 0, overwrite).
- *  workspace        device scratch of vpm_workspace_size(...) bytes (0 for n_batch == 1).
+ *  workspace        device scratch of vpm_workspace_size(...) bytes.  Required for n_batch > 1
+ *                   (work queue).  For n_batch == 1 it holds per-chunk partial sums when the
+ *                   target set is too small to fill the GPU (the sources are then split into
+ *                   chunks); without it (NULL or smaller) such a set runs unsplit, correct but
+ *                   slower.  Must not overlap any other argument.
  * Returns VPM_OK or the first violated condition. */
 vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                                         const int64_t* tgt_off, const void* x_src,
@@ -114,8 +118,10 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
                                         int64_t ld_out, const vpm_options* opt, void* workspace,
                                         size_t ws_bytes, void* stream);
 
-/* Bytes of workspace vpm_eval_velocity_stretching needs for this batch layout (0 when
- * n_batch == 1).  Returns 0 also for invalid offsets; the evaluation then reports them. */
+/* Bytes of workspace vpm_eval_velocity_stretching uses for this layout and kernel shape
+ * (opt->variant): the work queue for n_batch > 1, the source-split partials for a small single
+ * target set, else 0.  Depends on sizes only (no HIP call).  Returns 0 also for invalid
+ * arguments; the evaluation then reports them. */
 size_t vpm_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                           const int64_t* tgt_off, const vpm_options* opt);
 

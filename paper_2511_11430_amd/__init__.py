@@ -161,6 +161,8 @@ def vpm_eval_velocity_stretching(x_src, gamma_src, sigma_src, x_tgt=None, gamma_
     ws_need = int(lib.vpm_workspace_size(dt, n_batch, so, to, ctypes.byref(o)))
     if ws_need and workspace is None:
         workspace = torch.empty(ws_need, dtype=torch.uint8, device=dev)
+    if workspace is not None and workspace.numel() == 0:
+        workspace = None
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     ld_src = _ld(x_src)
     ld_tgt = 0 if self_eval else _ld(x_tgt)

@@ -35,10 +35,20 @@ template <typename T>
 using V4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
 
 // 4 pi (g, h, k) for one pair from the far-field powers and, inside the core, the series/closed form.
-template <typename T>
-__device__ __forceinline__ void weights3(T s2, T isig2, T cut, T Gf, T Hf, T Kf, T& g, T& h, T& k) {
+// SYM: the pair core is sigma_ij with 1/sigma_ij^2 = RHO_FAR^2 / cut; otherwise isig = 1/sigma.
+template <typename T, bool SYM>
+__device__ __forceinline__ void weights3(T s2, T isig, T cut, T Gf, T Hf, T Kf, T& g, T& h, T& k) {
     T G = Gf, Hn = Hf, Kn = Kf;
-    if (s2 < cut) core_weights3<T>(s2, isig2, Gf, Hf, Kf, G, Hn, Kn);
+    if (s2 < cut) {
+        T is = isig, is2;
+        if (SYM) {
+            is2 = T(Prec<T>::kFarRho2) * rcp_fast(cut);
+            is = sqrt_fast(is2);
+        } else {
+            is2 = is * is;
+        }
+        core_weights3<T>(s2, is, is2, Gf, Hf, Kf, G, Hn, Kn);
+    }
     g = G;
     h = T(-3) * Hn;
     k = T(15) * Kn;
@@ -47,7 +57,7 @@ __device__ __forceinline__ void weights3(T s2, T isig2, T cut, T Gf, T Hf, T Kf,
 template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
 __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
     constexpr bool kComp = std::is_same<T, float>::value;
-    __shared__ V4<T> l0[WG];  // (x, y, z, 1/sigma^2)
+    __shared__ V4<T> l0[WG];  // (x, y, z, 1/sigma)
     __shared__ V4<T> l1[WG];  // (Gamma, cut)
     __shared__ V4<T> l2[RB ? WG : 1];  // ub_q
     __shared__ V4<T> l3[(RB && STR) ? WG : 1];  // Sb_q
@@ -77,7 +87,7 @@ __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
     }
     T sp = T(1);
     if (RB || SYM) sp = sl[pp];
-    const T isig2_p = T(1) / (sp * sp);
+    const T isig_p = T(1) / sp;
     const T cut_p = SYM ? T(0.5) * far2 * sp * sp : far2 * sp * sp;
     T up0 = T(0), up1 = T(0), up2 = T(0), sb0 = T(0), sb1 = T(0), sb2 = T(0);
     if (RA) {
@@ -104,7 +114,7 @@ __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
             // Gamma_q when q is a source or carries stretching seeds.
             const T sq = (RA || SYM) ? so[j] : T(1);
             V4<T> v0, v1;
-            v0.x = xo[j]; v0.y = xo[a.ldo + j]; v0.z = xo[2 * a.ldo + j]; v0.w = T(1) / (sq * sq);
+            v0.x = xo[j]; v0.y = xo[a.ldo + j]; v0.z = xo[2 * a.ldo + j]; v0.w = T(1) / sq;
             if (RA || STR) {
                 v1.x = go[j]; v1.y = go[a.ldo + j]; v1.z = go[2 * a.ldo + j];
             } else {
@@ -157,9 +167,8 @@ __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
             if (RA) {
                 // sigma_q (source rule) or sigma_pq
                 const T cut = SYM ? q1.w + cut_p : q1.w;
-                const T isig2 = SYM ? far2 / cut : q0.w;
                 T g, h, k;
-                weights3<T>(s2, isig2, cut, Gf, Hf, Kf, g, h, k);
+                weights3<T, SYM>(s2, q0.w, cut, Gf, Hf, Kf, g, h, k);
                 if (skip) g = h = k = T(0);
                 const T av = up0 * vx + up1 * vy + up2 * vz;
                 // g ub_p x Gamma_q
@@ -190,9 +199,8 @@ __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
                 const V4<T> q2 = l2[jj];
                 // sigma_p (source rule) or sigma_pq
                 const T cut = SYM ? q1.w + cut_p : cut_p;
-                const T isig2 = SYM ? far2 / cut : isig2_p;
                 T g, h, k;
-                weights3<T>(s2, isig2, cut, Gf, Hf, Kf, g, h, k);
+                weights3<T, SYM>(s2, isig_p, cut, Gf, Hf, Kf, g, h, k);
                 if (skip) g = h = k = T(0);
                 // Gamma_p x r
                 const T v2x = gp1 * rz - gp2 * ry;

@@ -70,8 +70,14 @@ template <> struct Prec<double> {
     static constexpr int kTermsK = 19;
 };
 
+// Hardware reciprocal square root / square root / reciprocal (about 1 ulp) for FP32; the
+// library's correctly rounded versions for FP64.
 __device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_fast(double x) { return rsqrt(x); }
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_fast(double x) { return sqrt(x); }
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_fast(double x) { return 1.0 / x; }
 __device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
@@ -79,13 +85,12 @@ __device__ __forceinline__ double dexp(double x) { return exp(x); }
 __device__ __forceinline__ float derf(float x) { return erff(x); }
 __device__ __forceinline__ double derf(double x) { return erf(x); }
 
-// In-core weights.  Inputs: s2 = |r|^2, isig2 = 1/sigma^2, Gf = s^-3 and Hf = s^-5 (valid when
-// s > 0).  Outputs G = 4 pi g and Hn = -(4 pi/3) h.
+// In-core weights.  Inputs: s2 = |r|^2, isig = 1/sigma, isig2 = 1/sigma^2, Gf = s^-3 and
+// Hf = s^-5 (valid when s > 0).  Outputs G = 4 pi g and Hn = -(4 pi/3) h.
 template <typename T>
-__device__ __forceinline__ void core_weights(T s2, T isig2, T Gf, T Hf, T& G, T& Hn) {
+__device__ __forceinline__ void core_weights(T s2, T isig, T isig2, T Gf, T Hf, T& G, T& Hn) {
     const T t = s2 * isig2;
     if (t < T(1)) {
-        const T isig = dsqrt(isig2);
         const T isig3 = isig * isig2;
         const T isig5 = isig3 * isig2;
         const T gw = Horner<T, 0, 0, Prec<T>::kTermsG - 1>::eval(t);
@@ -93,7 +98,7 @@ __device__ __forceinline__ void core_weights(T s2, T isig2, T Gf, T Hf, T& G, T&
         G = T(kC0D) * gw * isig3;
         Hn = T(-kC0D / 3.0) * hw * isig5;
     } else {
-        const T rho = dsqrt(t);
+        const T rho = sqrt_fast(t);
         const T e = dexp(T(-0.5) * t);
         const T q = derf(rho * T(kInvSqrt2D)) - T(kC0D) * rho * e;
         G = q * Gf;
@@ -103,10 +108,10 @@ __device__ __forceinline__ void core_weights(T s2, T isig2, T Gf, T Hf, T& G, T&
 
 // Same, also returning Kn = (4 pi/15) k (adjoint); Kf = s^-7.
 template <typename T>
-__device__ __forceinline__ void core_weights3(T s2, T isig2, T Gf, T Hf, T Kf, T& G, T& Hn, T& Kn) {
+__device__ __forceinline__ void core_weights3(T s2, T isig, T isig2, T Gf, T Hf, T Kf, T& G, T& Hn,
+                                              T& Kn) {
     const T t = s2 * isig2;
     if (t < T(1)) {
-        const T isig = dsqrt(isig2);
         const T isig3 = isig * isig2;
         const T isig5 = isig3 * isig2;
         const T isig7 = isig5 * isig2;
@@ -117,7 +122,7 @@ __device__ __forceinline__ void core_weights3(T s2, T isig2, T Gf, T Hf, T Kf, T
         Hn = T(-kC0D / 3.0) * hw * isig5;
         Kn = T(kC0D / 15.0) * kw * isig7;
     } else {
-        const T rho = dsqrt(t);
+        const T rho = sqrt_fast(t);
         const T e = dexp(T(-0.5) * t);
         const T q = derf(rho * T(kInvSqrt2D)) - T(kC0D) * rho * e;
         const T r3e = rho * t * e;  // rho^3 e

@@ -5,7 +5,7 @@
 //  - Each workgroup owns WG*K consecutive targets of one particle set; lane l holds targets
 //    l, l+WG, ..., l+(K-1)WG (coalesced loads and stores for every k).
 //  - Sources stream through LDS in tiles of WG particles.  Each lane stages one source and
-//    precomputes what every pair needs (x, Gamma, 1/sigma^2 and the far-field cut), so the
+//    precomputes what every pair needs (x, Gamma, 1/sigma and the far-field cut), so the
 //    inner loop reads a source with two 16-byte LDS loads that all lanes share (broadcast),
 //    and uses it for K register-resident targets.
 //  - A pair takes the point-vortex weights (s^-3, s^-5) unless it lies inside RHO_FAR cores,
@@ -33,7 +33,7 @@ namespace vpm {
 
 template <typename T>
 struct SrcTile {
-    // p = (x, y, z, 1/sigma^2), q = (Gamma_x, Gamma_y, Gamma_z, cut) with cut = RHO_FAR^2 sigma^2
+    // p = (x, y, z, 1/sigma), q = (Gamma_x, Gamma_y, Gamma_z, cut) with cut = RHO_FAR^2 sigma^2
     // for the source rule and RHO_FAR^2 sigma^2 / 2 for the symmetric rule.
     using V4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
 };
@@ -55,9 +55,16 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
     T Hn = G * rinv2;
     const T cut = SYM ? (qw + cut_i) : qw;
     if (s2 < cut) {
-        // symmetric rule: 1/sigma_ij^2 = RHO_FAR^2 / cut
-        const T isig2 = SYM ? T(Prec<T>::kFarRho2) / cut : pw;
-        core_weights<T>(s2, isig2, G, Hn, G, Hn);
+        // source rule: pw = 1/sigma_j; symmetric rule: 1/sigma_ij^2 = RHO_FAR^2 / cut
+        T isig, isig2;
+        if (SYM) {
+            isig2 = T(Prec<T>::kFarRho2) * rcp_fast(cut);
+            isig = sqrt_fast(isig2);
+        } else {
+            isig = pw;
+            isig2 = pw * pw;
+        }
+        core_weights<T>(s2, isig, isig2, G, Hn, G, Hn);
     }
     if (CHECK) {
         if (jglob == ex) {
@@ -91,6 +98,43 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
     }
 }
 
+// Per-target epilogue in FP64: u = U/(4 pi) and the stretching from A and B (tot holds U, A, B).
+template <typename T, int MODE>
+__device__ __forceinline__ void store_target(const FwdArgs& a, int64_t t, double g0, double g1, double g2,
+                                             const double* tot) {
+    double res[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) res[c] = kInv4PiD * tot[c];
+    if (MODE != kModeVelocity) {
+        const double A0 = tot[3], A1 = tot[4], A2 = tot[5];
+        double c0 = g1 * A2 - g2 * A1;
+        double c1 = g2 * A0 - g0 * A2;
+        double c2 = g0 * A1 - g1 * A0;
+        if (MODE == kModeClassical) {
+            c0 = -c0;
+            c1 = -c1;
+            c2 = -c2;
+        }
+        res[3] = kInv4PiD * (c0 - 3.0 * tot[6]);
+        res[4] = kInv4PiD * (c1 - 3.0 * tot[7]);
+        res[5] = kInv4PiD * (c2 - 3.0 * tot[8]);
+    }
+    T* __restrict__ uo = static_cast<T*>(a.u);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T* dst = uo + c * a.ldo + t;
+        *dst = a.accumulate ? T(double(*dst) + res[c]) : T(res[c]);
+    }
+    if (MODE != kModeVelocity) {
+        T* __restrict__ dgo = static_cast<T*>(a.dg);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T* dst = dgo + c * a.ldo + t;
+            *dst = a.accumulate ? T(double(*dst) + res[3 + c]) : T(res[3 + c]);
+        }
+    }
+}
+
 template <typename T, int K, int WG, int MODE, bool SYM>
 struct FwdBlock {
     static constexpr bool kComp = std::is_same<T, float>::value;
@@ -100,7 +144,7 @@ struct FwdBlock {
     // Process targets [t0, t1) (at most WG*K of them) against sources [s0, s1) of one set.
     // self_shift: with self evaluation, target t is source t + self_shift (else ignored).
     static __device__ void run(const FwdArgs& a, int64_t s0, int64_t s1, int64_t t0, int64_t t1,
-                               int64_t self_shift, V4* lp, V4* lq) {
+                               int64_t self_shift, V4* lp, V4* lq, int chunk_id) {
         const T* __restrict__ xs = static_cast<const T*>(a.xs);
         const T* __restrict__ gs = static_cast<const T*>(a.gs);
         const T* __restrict__ ss = static_cast<const T*>(a.ss);
@@ -161,7 +205,7 @@ struct FwdBlock {
                 p.x = xs[j];
                 p.y = xs[a.lds + j];
                 p.z = xs[2 * a.lds + j];
-                p.w = T(1) / (sg * sg);
+                p.w = T(1) / sg;
                 q.x = gs[j];
                 q.y = gs[a.lds + j];
                 q.z = gs[2 * a.lds + j];
@@ -193,9 +237,7 @@ struct FwdBlock {
             }
         }
 
-        // Epilogue in FP64: u = U/(4 pi); stretching from A and B.
-        T* __restrict__ uo = static_cast<T*>(a.u);
-        T* __restrict__ dgo = static_cast<T*>(a.dg);
+        // Epilogue in FP64 (or FP64 partials of one source chunk).
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (!valid[k]) continue;
@@ -204,36 +246,11 @@ struct FwdBlock {
 #pragma unroll
             for (int c = 0; c < kNacc; ++c)
                 tot[c] = kComp ? double(hi[k][c]) + double(lo[k][c]) : double(acc[k][c]);
-            const int64_t o = t;  // outputs are indexed like the targets
-            double res[6];
+            if (chunk_id >= 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) res[c] = kInv4PiD * tot[c];
-            if (MODE != kModeVelocity) {
-                const double g0 = gi[k][0], g1 = gi[k][1], g2 = gi[k][2];
-                const double A0 = tot[3], A1 = tot[4], A2 = tot[5];
-                double c0 = g1 * A2 - g2 * A1;
-                double c1 = g2 * A0 - g0 * A2;
-                double c2 = g0 * A1 - g1 * A0;
-                if (MODE == kModeClassical) {
-                    c0 = -c0;
-                    c1 = -c1;
-                    c2 = -c2;
-                }
-                res[3] = kInv4PiD * (c0 - 3.0 * tot[6]);
-                res[4] = kInv4PiD * (c1 - 3.0 * tot[7]);
-                res[5] = kInv4PiD * (c2 - 3.0 * tot[8]);
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                T* dst = uo + c * a.ldo + o;
-                *dst = a.accumulate ? T(double(*dst) + res[c]) : T(res[c]);
-            }
-            if (MODE != kModeVelocity) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    T* dst = dgo + c * a.ldo + o;
-                    *dst = a.accumulate ? T(double(*dst) + res[3 + c]) : T(res[3 + c]);
-                }
+                for (int c = 0; c < kNacc; ++c) a.part[(int64_t(chunk_id) * kNacc + c) * a.tgt_end + t] = tot[c];
+            } else {
+                store_target<T, MODE>(a, t, gi[k][0], gi[k][1], gi[k][2], tot);
             }
         }
     }
@@ -267,7 +284,36 @@ __global__ __launch_bounds__(WG) void k_pair_fwd(FwdArgs a) {
     const int64_t t0 = a.tgt_begin + int64_t(blockIdx.x) * (WG * K);
     int64_t t1 = t0 + WG * K;
     if (t1 > a.tgt_end) t1 = a.tgt_end;
-    B::run(a, a.src_begin, a.src_end, t0, t1, a.src_begin - a.tgt_begin, lp, lq);
+    int64_t s0 = a.src_begin, s1 = a.src_end;
+    int chunk_id = -1;
+    if (a.nchunk > 1) {
+        chunk_id = int(blockIdx.y);
+        s0 = a.src_begin + int64_t(blockIdx.y) * a.chunk;
+        s1 = s0 + a.chunk < a.src_end ? s0 + a.chunk : a.src_end;
+    }
+    B::run(a, s0, s1, t0, t1, a.src_begin - a.tgt_begin, lp, lq, chunk_id);
+}
+
+// Adds the per-chunk FP64 partials of every target in chunk order and stores the result.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_pair_fwd_finish(FwdArgs a) {
+    constexpr int kNacc = (MODE == kModeVelocity) ? 3 : 9;
+    const int64_t t = a.tgt_begin + int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (t >= a.tgt_end) return;
+    double tot[kNacc];
+#pragma unroll
+    for (int c = 0; c < kNacc; ++c) tot[c] = 0.0;
+    for (int ch = 0; ch < a.nchunk; ++ch)
+#pragma unroll
+        for (int c = 0; c < kNacc; ++c) tot[c] += a.part[(int64_t(ch) * kNacc + c) * a.tgt_end + t];
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    if (MODE != kModeVelocity) {
+        const T* gt = static_cast<const T*>(a.gt);
+        g0 = double(gt[t]);
+        g1 = double(gt[a.ldt + t]);
+        g2 = double(gt[2 * a.ldt + t]);
+    }
+    store_target<T, MODE>(a, t, g0, g1, g2, tot);
 }
 
 // Persistent workgroups over a queue of (set, target block) items in decreasing cost order.
@@ -291,7 +337,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd_batched(FwdArgs a, BatchQueue b
         const int64_t t0 = tb0 + int64_t(it.y) * (WG * K);
         int64_t t1 = t0 + WG * K;
         if (t1 > tb1) t1 = tb1;
-        B::run(a, s0, s1, t0, t1, s0 - tb0, lp, lq);
+        B::run(a, s0, s1, t0, t1, s0 - tb0, lp, lq, -1);
     }
 }
 
@@ -302,9 +348,14 @@ template <typename T, int K, int WG, int MODE, bool SYM>
 hipError_t launch_one(const FwdArgs& a, const BatchQueue* bq, int grid, hipStream_t st) {
     if (bq) {
         hipLaunchKernelGGL((k_pair_fwd_batched<T, K, WG, MODE, SYM>), dim3(grid), dim3(WG), 0, st, a, *bq);
-    } else {
-        hipLaunchKernelGGL((k_pair_fwd<T, K, WG, MODE, SYM>), dim3(grid), dim3(WG), 0, st, a);
+        return hipGetLastError();
     }
+    const int ny = a.nchunk > 1 ? a.nchunk : 1;
+    hipLaunchKernelGGL((k_pair_fwd<T, K, WG, MODE, SYM>), dim3(grid, ny), dim3(WG), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || ny == 1) return e;
+    const int64_t nt = a.tgt_end - a.tgt_begin;
+    hipLaunchKernelGGL((k_pair_fwd_finish<T, MODE>), dim3(int((nt + 255) / 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

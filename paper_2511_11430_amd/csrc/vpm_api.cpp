@@ -165,6 +165,41 @@ int64_t targets_per_block(int32_t dtype, int variant) {
     return int64_t(vpm::kF32Variants[variant].k) * vpm::kF32Variants[variant].wg;
 }
 
+// Source split for one small target set: when there are fewer target blocks than
+// kSplitBelow, the sources are cut into chunks (multiples of 256, at least kMinChunk) so that
+// about kSplitGoal workgroups run; partial sums go to the workspace.  Depends only on sizes.
+constexpr int64_t kSplitBelow = 1024;
+constexpr int64_t kSplitGoal = 2048;
+constexpr int64_t kMinChunk = 2048;
+constexpr int kMaxAcc = 9;
+
+struct SplitPlan {
+    int64_t nchunk = 1, chunk = 0;
+    size_t bytes = 0;
+};
+SplitPlan split_plan(int32_t dtype, int variant, int64_t n_src, int64_t n_tgt) {
+    SplitPlan p;
+    p.chunk = n_src;
+    const int64_t per_block = targets_per_block(dtype, variant);
+    const int64_t tblocks = (n_tgt + per_block - 1) / per_block;
+    if (tblocks == 0 || tblocks >= kSplitBelow) return p;
+    int64_t want = (kSplitGoal + tblocks - 1) / tblocks;
+    const int64_t most = n_src / kMinChunk;
+    if (want > most) want = most;
+    if (want < 2) return p;
+    int64_t chunk = (n_src + want - 1) / want;
+    chunk = (chunk + 255) / 256 * 256;
+    p.chunk = chunk;
+    p.nchunk = (n_src + chunk - 1) / chunk;
+    if (p.nchunk < 2) {
+        p.nchunk = 1;
+        p.chunk = n_src;
+        return p;
+    }
+    p.bytes = align_up(size_t(p.nchunk) * kMaxAcc * size_t(n_tgt) * sizeof(double));
+    return p;
+}
+
 }  // namespace
 
 extern "C" {
@@ -205,7 +240,11 @@ size_t vpm_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off
     if (o.self && !tgt_off) tgt_off = src_off;
     if (!tgt_off) return 0;
     if (check_offsets(n_batch, src_off) != VPM_OK || check_offsets(n_batch, tgt_off) != VPM_OK) return 0;
-    if (n_batch == 1) return 0;
+    if (check_options(o) != VPM_OK) return 0;
+    if (n_batch == 1) {
+        const int variant = o.variant > 0 ? o.variant - 1 : 0;
+        return split_plan(dtype, variant, src_off[1], tgt_off[1]).bytes;
+    }
     return queue_layout(n_batch, tgt_off, kMinTargetsPerBlock).total;
 }
 
@@ -268,14 +307,17 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
     if (overlap(ru, rd)) return VPM_ERR_ALIAS;
 
     int variant = o.variant > 0 ? o.variant - 1 : 0;
+    if (workspace && ws_bytes > 0) {
+        const Range rw = span(workspace, 1, int64_t(ws_bytes), int64_t(ws_bytes), 1);
+        if (overlap(rw, ru) || overlap(rw, rd)) return VPM_ERR_ALIAS;
+        for (const Range& r : ins)
+            if (overlap(rw, r)) return VPM_ERR_ALIAS;
+    }
     QueueLayout L{};
     if (n_batch > 1) {
         L = queue_layout(n_batch, tgt_off, kMinTargetsPerBlock);
         if (!workspace) return VPM_ERR_WORKSPACE;
         if (ws_bytes < L.total) return VPM_ERR_WORKSPACE;
-        if (overlap(span(workspace, 1, L.total, L.total, 1), ru) ||
-            overlap(span(workspace, 1, L.total, L.total, 1), rd))
-            return VPM_ERR_ALIAS;
     }
     if (n_tgt == 0) return VPM_OK;
 
@@ -300,10 +342,19 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
     a.tgt_end = n_tgt;
     a.self = o.self;
     a.accumulate = o.accumulate;
+    a.part = nullptr;
+    a.chunk = n_src;
+    a.nchunk = 1;
     const int mode = fwd_mode(o, stretch);
     const int64_t per_block = targets_per_block(dtype, variant);
 
     if (n_batch == 1) {
+        const SplitPlan sp = split_plan(dtype, variant, n_src, n_tgt);
+        if (sp.nchunk > 1 && workspace && ws_bytes >= sp.bytes) {
+            a.part = static_cast<double*>(workspace);
+            a.chunk = sp.chunk;
+            a.nchunk = int32_t(sp.nchunk);
+        }
         const int64_t grid = (n_tgt + per_block - 1) / per_block;
         return hip_status(vpm::launch_pair_fwd(dtype, variant, mode, sym, a, nullptr, int(grid), st));
     }

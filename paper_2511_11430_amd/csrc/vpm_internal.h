@@ -30,6 +30,12 @@ struct FwdArgs {
     int64_t tgt_begin, tgt_end;
     int32_t self;
     int32_t accumulate;
+    // Source split (one set only): nchunk > 1 launches a 2-D grid whose y index picks a chunk of
+    // `chunk` sources; each workgroup writes FP64 partial sums part[(ch * nacc + c) * n_tgt + t]
+    // and launch_pair_fwd then runs the finishing kernel that adds the chunks in order.
+    double* part;
+    int64_t chunk;
+    int32_t nchunk;
 };
 
 // Work queue of the persistent batched launch (lives in the caller's workspace).

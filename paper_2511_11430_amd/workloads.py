@@ -215,6 +215,10 @@ def config3(n=1 << 20, n_sample=4096):
     rng = _rng(3)
     w = forward_flight_wake(n, rng)
     w["sample"] = np.sort(_rng(3, 1).choice(n, size=min(n_sample, n), replace=False)).astype(np.int64)
+    # the 4 blades' bound rings (4 x 8 x 32 rings, 4096 segments) and 4 x 32 control points
+    lat = lattice(n_blades=4, wake_rows=0, rng=_rng(3, 2))
+    w.update({"seg_a": lat["a"], "seg_b": lat["b"], "seg_gamma": lat["gamma"], "core_radius": 0.02 * R,
+              "vatistas_n": 2, "ctrl": control_points(n_blades=4, panels=(4,))})
     w["name"] = f"forward-flight skewed wake N_p={n}, 4 blades, mu=0.15"
     return w
 

@@ -202,11 +202,41 @@ def test_diagnostics(kind, gpu):
     u, d = vpm.vpm_eval_velocity_stretching(X, G, S, sigma_rule=1)
     out = vpm.vpm_diagnostics(X, G, u, d).cpu().numpy()
     ref = oracle.diagnostics(x, g, host(u), host(d))
+    # Sums are compared against the scale of their terms (several of them cancel to ~0).
+    U, D = host(u), host(d)
+    scales = {"sum_gamma": np.abs(g).sum(), "sum_dgamma": np.abs(D).sum(),
+              "impulse": np.abs(x).max() * np.abs(g).sum(),
+              "impulse_rate": np.abs(U).max() * np.abs(g).sum() + np.abs(x).max() * np.abs(D).sum()}
     for k, sl in (("sum_gamma", slice(0, 3)), ("sum_dgamma", slice(3, 6)), ("impulse", slice(6, 9)),
                   ("impulse_rate", slice(9, 12))):
-        assert np.allclose(out[sl], ref[k], rtol=1e-12, atol=1e-13 * np.abs(ref[k]).max() + 1e-300), k
+        assert np.abs(out[sl] - ref[k]).max() <= 1e-14 * scales[k], k
     assert out[12] == 0
     # transposed scheme with symmetric cores conserves total vorticity on the GPU too
     _, do = oracle.eval_pairs(x, g, s, sigma_rule=1)
     scale = np.abs(do).sum()
     assert np.abs(out[3:6]).max() <= (1e-13 if kind == "f64" else 1e-6) * scale
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_source_split_for_small_target_sets(kind, gpu):
+    """Few targets, many sources: the sources are split into chunks whose FP64 partials are
+    added in order; same result as the unsplit launch (no workspace) and the oracle."""
+    import torch
+    x, g, s = prepare(_random_set(40000, 17, spread=0.5), kind)
+    X, G, S = dev_(x, kind), dev_(g, kind), dev_(s, kind)
+    idx = np.arange(0, 40000, 400)
+    ex = torch.tensor(idx, dtype=torch.int32, device="cuda")
+    xt, gt, st = dev_(x[:, idx], kind), dev_(g[:, idx], kind), dev_(s[idx], kind)
+    need = vpm.vpm_workspace_size(vpm.F64 if kind == "f64" else vpm.F32C, [0, 40000], [0, len(idx)],
+                                  self_eval=False)
+    assert need > 0
+    u1, d1 = vpm.vpm_eval_velocity_stretching(X, G, S, xt, gt, st, tgt_exclude=ex)
+    ws0 = torch.empty(0, dtype=torch.uint8, device="cuda")
+    u0, d0 = vpm.vpm_eval_velocity_stretching(X, G, S, xt, gt, st, tgt_exclude=ex, workspace=ws0)
+    uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
+    assert rel_l2(host(u1), uo) <= TOL[kind] and rel_l2(host(d1), do) <= TOL[kind]
+    assert rel_l2(host(u0), uo) <= TOL[kind] and rel_l2(host(d0), do) <= TOL[kind]
+    # velocity-only control points take the same split path
+    uc, _ = vpm.vpm_eval_velocity_stretching(X, G, S, xt)
+    uco, _ = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx])
+    assert rel_l2(host(uc), uco) <= TOL[kind]
