@@ -192,6 +192,15 @@ vpm_status vpm_diagnostics(int32_t dtype, int64_t n, const void* x, const void* 
 size_t vpm_diagnostics_workspace_size(void);
 
 /* ---------------------------------------------------------------------------------------
+ * vpm_axial_loss — the blade-point loss used for wake gradients: L = sum_c (u_c . z)^2 over
+ * m control-point velocities u [3][ld] (u_c from vpm_eval_velocity_stretching with the
+ * control points as velocity-only targets).  loss (device double, may be NULL) receives L in
+ * FP64.  u_bar ([3][ld] of dtype, may be NULL) receives the seed loss_bar dL/du =
+ * 2 loss_bar (0, 0, u_z); loss_bar is a device double or NULL for 1. */
+vpm_status vpm_axial_loss(int32_t dtype, int64_t m, const void* u, int64_t ld, double* loss, void* u_bar,
+                          const double* loss_bar, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Kernel-shape variants of the FP32C particle kernel (targets per lane x workgroup size),
  * for the tuner and the tests.  vpm_variant_info fills targets-per-lane and workgroup size
  * of variant k (1-based); returns VPM_ERR_ENUM for an unknown k. */

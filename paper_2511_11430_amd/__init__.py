@@ -19,7 +19,7 @@ SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
 
 __all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_backward", "vpm_rk3_stage",
            "vpm_rk3_stage_backward", "vpm_diagnostics", "vpm_workspace_size", "vpm_variant_count",
-           "vpm_variant_info", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
+           "vpm_variant_info", "vpm_axial_loss", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
            "SIGMA_SYMMETRIC"]
 
 
@@ -293,6 +293,28 @@ def vpm_diagnostics(x, gamma, u, dgamma, *, out=None, workspace=None, stream=Non
                              workspace.numel() * workspace.element_size(), _stream(stream))
     _check("vpm_diagnostics", st)
     return out
+
+
+def vpm_axial_loss(u_ctrl, *, loss=None, u_bar=None, loss_bar=None, want_seed=True, stream=None):
+    """L = sum_c (u_c . z)^2 (float64 device scalar) and the seed 2 loss_bar (0, 0, u_z) on u_ctrl.
+    Returns (loss, u_bar)."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(u_ctrl)
+    _vec(u_ctrl, "u_ctrl")
+    m = u_ctrl.shape[1]
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float64, device=u_ctrl.device)
+    if want_seed and u_bar is None:
+        u_bar = torch.empty_like(u_ctrl)
+    _vec(u_bar, "u_bar", m, u_ctrl.dtype)
+    if u_bar is not None and m and u_bar.stride(0) != u_ctrl.stride(0):
+        raise ValueError("u_bar must share u_ctrl's leading dimension")
+    if loss_bar is not None and (loss_bar.dtype != torch.float64 or loss_bar.numel() != 1 or not loss_bar.is_cuda):
+        raise ValueError("loss_bar must be a float64 CUDA scalar")
+    st = lib.vpm_axial_loss(dt, m, _p(u_ctrl), _ld(u_ctrl), _p(loss), _p(u_bar), _p(loss_bar), _stream(stream))
+    _check("vpm_axial_loss", st)
+    return loss, u_bar
 
 
 def vpm_variant_count():

@@ -34,6 +34,7 @@ SIGNATURES = {
                                        c_vp]),
     "vpm_diagnostics": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "vpm_diagnostics_workspace_size": (c_sz, []),
+    "vpm_axial_loss": (c_i32, [c_i32, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "vpm_variant_count": (c_i32, []),
     "vpm_variant_info": (c_i32, [c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
     "vpm_status_string": (ctypes.c_char_p, [c_i32]),

@@ -102,6 +102,8 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
 template <typename T, int MODE>
 __device__ __forceinline__ void store_target(const FwdArgs& a, int64_t t, double g0, double g1, double g2,
                                              const double* tot) {
+    // No contraction here, so every kernel that ends in this epilogue rounds the same way.
+#pragma clang fp contract(off)
     double res[6];
 #pragma unroll
     for (int c = 0; c < 3; ++c) res[c] = kInv4PiD * tot[c];

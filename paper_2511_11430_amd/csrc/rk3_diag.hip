@@ -119,6 +119,31 @@ __global__ __launch_bounds__(256) void k_diag_final(int nblocks, const double* p
     }
 }
 
+// L = sum_c u_z(c)^2 in FP64 (one workgroup) and the seed u_bar = 2 loss_bar (0, 0, u_z).
+template <typename T>
+__global__ __launch_bounds__(256) void k_axial_loss(int64_t m, const T* u, int64_t ld, double* loss,
+                                                    T* ubar, const double* loss_bar) {
+    __shared__ double red[256];
+    const double lb = loss_bar ? *loss_bar : 1.0;
+    double s = 0.0;
+    for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
+        const double uz = double(u[2 * ld + c]);
+        s += uz * uz;
+        if (ubar) {
+            ubar[c] = T(0);
+            ubar[ld + c] = T(0);
+            ubar[2 * ld + c] = T(2.0 * lb * uz);
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss) *loss = red[0];
+}
+
 int grid_for(int64_t items) {
     int64_t g = (items + 255) / 256;
     if (g > 8192) g = 8192;
@@ -174,6 +199,21 @@ hipError_t launch_diagnostics(int dtype, int64_t n, const void* x, const void* g
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, nb, partials, out);
+    return hipGetLastError();
+}
+
+}  // namespace vpm
+
+namespace vpm {
+
+hipError_t launch_axial_loss(int dtype, int64_t m, const void* u, int64_t ld, double* loss, void* ubar,
+                             const double* loss_bar, hipStream_t st) {
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_axial_loss<double>, dim3(1), dim3(256), 0, st, m, (const double*)u, ld, loss,
+                           (double*)ubar, loss_bar);
+    else
+        hipLaunchKernelGGL(k_axial_loss<float>, dim3(1), dim3(256), 0, st, m, (const float*)u, ld, loss,
+                           (float*)ubar, loss_bar);
     return hipGetLastError();
 }
 

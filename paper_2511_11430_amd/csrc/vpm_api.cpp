@@ -576,6 +576,21 @@ vpm_status vpm_rk3_stage_backward(int32_t dtype, int32_t stage, int64_t n, doubl
                                                 u_seed, dgamma_seed, ld, static_cast<hipStream_t>(stream)));
 }
 
+vpm_status vpm_axial_loss(int32_t dtype, int64_t m, const void* u, int64_t ld, double* loss, void* u_bar,
+                          const double* loss_bar, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (m < 0 || ld < m) return VPM_ERR_SIZE;
+    if (m > 0 && !u) return VPM_ERR_NULL;
+    if (!loss && !u_bar) return VPM_ERR_NULL;
+    const size_t es = elem_size(dtype);
+    const Range ru = span(u, 3, ld, m, es), rb = span(u_bar, 3, ld, m, es);
+    const Range rl = span(loss, 1, 1, 1, sizeof(double)), rlb = span(loss_bar, 1, 1, 1, sizeof(double));
+    if (overlap(ru, rb) || overlap(ru, rl) || overlap(rb, rl) || overlap(rl, rlb) || overlap(rb, rlb))
+        return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_axial_loss(dtype, m, u, ld, loss, u_bar, loss_bar,
+                                             static_cast<hipStream_t>(stream)));
+}
+
 size_t vpm_diagnostics_workspace_size(void) {
     return size_t(vpm::kDiagBlocks) * vpm::kDiagSlots * sizeof(double);
 }

@@ -1,0 +1,186 @@
+"""GPU parity of the hand-written adjoint: the pair vector-Jacobian product against full
+Jacobians the FP64 oracle builds column by column with dual-number tangents, the RK3
+program gradient against the oracle's program tangents, and central finite differences
+(h = 1e-6, FP64) on the hover-wake program."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2511_11430_amd as vpm
+from paper_2511_11430_amd import autograd as AG
+from paper_2511_11430_amd import workloads as W
+
+from gpu_helpers import TOL, dev, host, prepare, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+KINDS = ["f64", "f32c"]
+
+
+def _set(n, seed, spread=0.08):
+    rng = np.random.default_rng([777, seed])
+    x = rng.uniform(-spread, spread, (3, n))
+    g = rng.normal(0, 1e-3, (3, n))
+    s = rng.uniform(0.02, 0.05, n)
+    return x, g, s
+
+
+def _oracle_vjp_self(x, g, s, ub, sb, rule):
+    """w^T J built column by column from oracle tangents (self evaluation)."""
+    n = x.shape[1]
+    out = np.zeros((2, 3, n))
+    for part in range(2):
+        for c in range(3):
+            for i in range(n):
+                xd, gd = np.zeros_like(x), np.zeros_like(g)
+                (xd if part == 0 else gd)[c, i] = 1.0
+                _, _, ud, dd = oracle.eval_pairs_jvp(x, g, s, xd, gd, sigma_rule=rule)
+                out[part, c, i] = (ub * ud).sum() + (sb * dd).sum()
+    return out[0], out[1]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("rule", [0, 1])
+def test_pair_vjp_equals_oracle_jacobian(kind, rule, gpu):
+    x, g, s = prepare(_set(40, 1 + rule), kind)
+    rng = np.random.default_rng(5)
+    ub, sb = prepare([rng.normal(size=x.shape), rng.normal(size=x.shape) * 1e3], kind)
+    say(f"pair vjp {kind} rule={rule}")
+    xb, gb, _, _ = vpm.vpm_backward(dev(x, kind), dev(g, kind), dev(s, kind), dev(ub, kind), dev(sb, kind),
+                                    sigma_rule=rule)
+    rx, rg = _oracle_vjp_self(x, g, s, ub, sb, rule)
+    assert rel_l2(host(xb), rx) <= TOL[kind]
+    assert rel_l2(host(gb), rg) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_velocity_only_vjp_for_sources_and_targets(kind, gpu):
+    x, g, s = prepare(_set(50, 3), kind)
+    y = prepare([np.random.default_rng(8).uniform(-0.1, 0.1, (3, 12))], kind)[0]
+    ub = prepare([np.random.default_rng(9).normal(size=y.shape)], kind)[0]
+    xb, gb, yb, _ = vpm.vpm_backward(dev(x, kind), dev(g, kind), dev(s, kind), dev(ub, kind), None,
+                                     dev(y, kind), None, None, want_target_grads=True)
+    n = x.shape[1]
+    rx, rg, ry = np.zeros_like(x), np.zeros_like(g), np.zeros_like(y)
+    for c in range(3):
+        for i in range(n):
+            for part, ref in ((0, rx), (1, rg)):
+                xd, gd = np.zeros_like(x), np.zeros_like(g)
+                (xd if part == 0 else gd)[c, i] = 1.0
+                _, _, ud, _ = oracle.eval_pairs_jvp(x, g, s, xd, gd, x_tgt=y)
+                ref[c, i] = (ub * ud).sum()
+        for i in range(y.shape[1]):
+            yd = np.zeros_like(y)
+            yd[c, i] = 1.0
+            _, _, ud, _ = oracle.eval_pairs_jvp(x, g, s, np.zeros_like(x), np.zeros_like(g), x_tgt=y, x_tgt_dot=yd)
+            ry[c, i] = (ub * ud).sum()
+    assert rel_l2(host(xb), rx) <= TOL[kind]
+    assert rel_l2(host(gb), rg) <= TOL[kind]
+    assert rel_l2(host(yb), ry) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_vjp_dot_product_on_hover_wake(kind, gpu):
+    """<vjp(w), v> = <w, jvp(v)> on 4096 hover-wake particles (oracle tangent)."""
+    c = W.config4(n=4096)
+    x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], kind)
+    rng = np.random.default_rng(3)
+    ub, sb = rng.normal(size=x.shape), rng.normal(size=x.shape) * 1e3
+    xd, gd = rng.normal(size=x.shape) * 1e-3, rng.normal(size=x.shape) * 1e-6
+    ub, sb = prepare([ub, sb], kind)
+    xb, gb, _, _ = vpm.vpm_backward(dev(x, kind), dev(g, kind), dev(s, kind), dev(ub, kind), dev(sb, kind))
+    _, _, ud, dd = oracle.eval_pairs_jvp(x, g, s, xd, gd)
+    lhs = (host(xb) * xd).sum() + (host(gb) * gd).sum()
+    rhs = (ub * ud).sum() + (sb * dd).sum()
+    assert abs(lhs - rhs) <= (1e-11 if kind == "f64" else 1e-5) * abs(rhs)
+
+
+def _program_inputs(n, kind, seed=2):
+    rng = np.random.default_rng([55, seed])
+    c = W.config4(n=n)
+    # a compact piece of the hover wake: the first n particles of one tip helix, and two
+    # control points near it, so the loss sees near-field interactions
+    x, g, s = c["x"], c["gamma"], c["sigma"]
+    y = x[:, :2] + np.array([[0.0], [0.0], [-0.03]]) + rng.normal(scale=0.005, size=(3, 2))
+    return prepare([x, g, s, y], kind)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_rk3_program_gradient_vs_oracle_tangents(kind, gpu):
+    n, steps = 36, 2
+    x, g, s, y = _program_inputs(n, kind)
+    dt = 2e-4
+    say(f"RK3 program gradient {kind}")
+    X, G = dev(x, kind).requires_grad_(True), dev(g, kind).requires_grad_(True)
+    L = AG.rk3_program_loss(X, G, dev(s, kind), steps, dt, dev(y, kind))
+    L.backward()
+    Lo = oracle.rk3_program(x, g, s, steps, dt, y)[3]
+    assert abs(L.item() - Lo) <= (1e-12 if kind == "f64" else 1e-5) * abs(Lo)
+    ref = np.zeros((2, 3, n))
+    for part in range(2):
+        for cc in range(3):
+            for i in range(n):
+                xd, gd = np.zeros_like(x), np.zeros_like(g)
+                (xd if part == 0 else gd)[cc, i] = 1.0
+                ref[part, cc, i] = oracle.rk3_program_jvp(x, g, s, xd, gd, steps, dt, y)[1]
+    tol = 1e-10 if kind == "f64" else 1e-5
+    ex, eg = rel_l2(host(X.grad), ref[0]), rel_l2(host(G.grad), ref[1])
+    say(f"  rel-L2 dL/dx {ex:.2e}  dL/dGamma {eg:.2e}")
+    assert ex <= tol and eg <= tol
+
+
+def test_rk3_program_gradient_vs_central_differences(gpu):
+    """FP64 GPU program on 16384 hover-wake particles, 10 RK3 steps of 5 deg: the adjoint
+    gradient against central differences (h = 1e-6) of the same program, 64 random particles."""
+    c = W.config4(n=16384)
+    x, g, s = (np.asarray(c[k], dtype=np.float64) for k in ("x", "gamma", "sigma"))
+    y = c["ctrl"]
+    steps, dt = c["n_steps"], c["dt"]
+    X, G = dev(x, "f64").requires_grad_(True), dev(g, "f64").requires_grad_(True)
+    S, Y = dev(s, "f64"), dev(y, "f64")
+    L = AG.rk3_program_loss(X, G, S, steps, dt, Y)
+    L.backward()
+    gx, gg = host(X.grad), host(G.grad)
+    rng = np.random.default_rng(64)
+    idx = rng.choice(x.shape[1], 64, replace=False)
+    h = 1e-6
+    fd, ad = [], []
+    X0, G0 = dev(x, "f64"), dev(g, "f64")
+    for i in idx:
+        for part in range(2):
+            for cc in range(3):
+                base = X0 if part == 0 else G0
+                # Gamma components are ~1e-6 m^3/s: step relative to their size
+                step = h if part == 0 else h * 1e-3
+                e = torch.zeros_like(base)
+                e[cc, i] = step
+                xp, gp = (X0 + e, G0) if part == 0 else (X0, G0 + e)
+                xm, gm = (X0 - e, G0) if part == 0 else (X0, G0 - e)
+                Lp = AG.rk3_forward(xp, gp, S, steps, dt, Y)[3].item()
+                Lm = AG.rk3_forward(xm, gm, S, steps, dt, Y)[3].item()
+                fd.append((Lp - Lm) / (2 * step))
+                ad.append((gx if part == 0 else gg)[cc, i])
+    fd, ad = np.array(fd), np.array(ad)
+    err = np.linalg.norm(fd - ad) / np.linalg.norm(fd)
+    say(f"FD check: rel-L2 {err:.2e} over {len(fd)} components")
+    assert err <= 1e-6
+
+
+def test_fp32c_program_gradient_matches_fp64_at_full_size(gpu):
+    """Config-4 workload at full size (262144 particles, 10 RK3 steps): the FP32C program
+    gradient against the FP64 GPU program gradient (itself pinned to the oracle above)."""
+    c = W.config4()
+    x, g, s, y = (W.to_f32(c[k]) for k in ("x", "gamma", "sigma", "ctrl"))
+    grads = {}
+    for kind in ("f64", "f32c"):
+        X, G = dev(x, kind).requires_grad_(True), dev(g, kind).requires_grad_(True)
+        L = AG.rk3_program_loss(X, G, dev(s, kind), c["n_steps"], c["dt"], dev(y, kind))
+        L.backward()
+        grads[kind] = (host(X.grad), host(G.grad), L.item())
+        del X, G, L
+        torch.cuda.empty_cache()
+    ex = rel_l2(grads["f32c"][0], grads["f64"][0])
+    eg = rel_l2(grads["f32c"][1], grads["f64"][1])
+    el = abs(grads["f32c"][2] - grads["f64"][2]) / abs(grads["f64"][2])
+    say(f"full-size program: loss rel {el:.2e}, dL/dx rel-L2 {ex:.2e}, dL/dGamma rel-L2 {eg:.2e}")
+    assert el <= 1e-4 and ex <= 1e-3 and eg <= 1e-3

@@ -186,8 +186,9 @@ def test_batched_persistent_matches_single_launches(kind, gpu):
         lo, hi = off[w], off[w + 1]
         u1, d1 = vpm.vpm_eval_velocity_stretching(X[:, lo:hi].contiguous(), G[:, lo:hi].contiguous(),
                                                   S[lo:hi].contiguous())
-        # same kernel shape and summation order: identical results
-        assert np.array_equal(host(u1), U[:, lo:hi]) and np.array_equal(host(d1), D[:, lo:hi])
+        # same kernel shape and summation order: equal to rounding of the per-target epilogue
+        tight = 1e-14 if kind == "f64" else 1e-6
+        assert rel_l2(U[:, lo:hi], host(u1)) <= tight and rel_l2(D[:, lo:hi], host(d1)) <= tight
         x, g, s = xs[w]
         idx = np.arange(0, x.shape[1], max(1, x.shape[1] // 64))
         uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
