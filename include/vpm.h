@@ -164,20 +164,32 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
  * vpm_rk3_stage — stage k (0, 1, 2) of Williamson's low-storage third-order Runge-Kutta
  * scheme (Sec. II.B) on Y = (x, Gamma) with register Q = (qx, qg) and F = (u, dgamma):
  *     Q <- A_k Q + dt F;   Y <- Y + B_k Q,
- * A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15).  All arrays [3][ld], n items, in place. */
-vpm_status vpm_rk3_stage(int32_t dtype, int32_t stage, int64_t n, double dt, void* x, void* gamma,
-                         void* qx, void* qg, const void* u, const void* dgamma, int64_t ld,
-                         void* stream);
+ * A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15).  All arrays [3][ld], n items, in place.
+ *  dtype        type of u, dgamma and of x_eval, gamma_eval.
+ *  state_dtype  type of x, gamma, qx, qg: equal to dtype, or VPM_F64 with dtype VPM_F32C (a
+ *               mixed program: FP64 state, FP32-compensated pair sums).
+ *  x_eval, gamma_eval  both NULL, or [3][ld] arrays of dtype that receive the updated state
+ *               rounded to dtype (the input of the next evaluation). */
+vpm_status vpm_rk3_stage(int32_t dtype, int32_t state_dtype, int32_t stage, int64_t n, double dt, void* x,
+                         void* gamma, void* qx, void* qg, const void* u, const void* dgamma, int64_t ld,
+                         void* x_eval, void* gamma_eval, void* stream);
 
 /* vpm_rk3_stage_backward — adjoint of vpm_rk3_stage.  In: x_bar, gamma_bar (adjoint of Y
- * after the stage), qx_bar, qg_bar (adjoint of Q after the stage).  Out, in place: qx_bar,
- * qg_bar become the adjoint of Q before the stage; u_seed, dgamma_seed receive dt (Q_bar +
- * B_k Y_bar), the seeds to pass to vpm_backward at the stage's input state, whose result is
- * added to x_bar, gamma_bar.  x_bar, gamma_bar are read only. */
-vpm_status vpm_rk3_stage_backward(int32_t dtype, int32_t stage, int64_t n, double dt,
-                                  const void* x_bar, const void* gamma_bar, void* qx_bar,
-                                  void* qg_bar, void* u_seed, void* dgamma_seed, int64_t ld,
-                                  void* stream);
+ * after the stage, state_dtype), qx_bar, qg_bar (adjoint of Q after the stage, state_dtype).
+ * Out, in place: qx_bar, qg_bar become the adjoint of Q before the stage; u_seed,
+ * dgamma_seed (dtype) receive dt (Q_bar + B_k Y_bar), the seeds to pass to vpm_backward at
+ * the stage's input state; its result, added to x_bar, gamma_bar (with vpm_convert when the
+ * types differ), completes the adjoint of Y before the stage.  x_bar, gamma_bar are read
+ * only. */
+vpm_status vpm_rk3_stage_backward(int32_t dtype, int32_t state_dtype, int32_t stage, int64_t n, double dt,
+                                  const void* x_bar, const void* gamma_bar, void* qx_bar, void* qg_bar,
+                                  void* u_seed, void* dgamma_seed, int64_t ld, void* stream);
+
+/* vpm_convert — dst = src (accumulate 0) or dst += src (accumulate 1) for [3][ld] arrays, with
+ * element-type conversion between VPM_F64 and VPM_F32C data.  Used to hand an FP64 state to
+ * the FP32 kernels and to add FP32 gradient contributions into an FP64 adjoint state. */
+vpm_status vpm_convert(int32_t src_dtype, int32_t dst_dtype, int64_t n, const void* src, int64_t ld_src, void* dst,
+                       int64_t ld_dst, int32_t accumulate, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * vpm_diagnostics — FP64 invariants of one evaluation, reduced on the GPU (for the

@@ -19,7 +19,7 @@ SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
 
 __all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_backward", "vpm_rk3_stage",
            "vpm_rk3_stage_backward", "vpm_diagnostics", "vpm_workspace_size", "vpm_variant_count",
-           "vpm_variant_info", "vpm_axial_loss", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
+           "vpm_variant_info", "vpm_axial_loss", "vpm_convert", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
            "SIGMA_SYMMETRIC"]
 
 
@@ -244,33 +244,51 @@ def vpm_backward(x_src, gamma_src, sigma_src, u_bar, dgamma_bar=None, x_tgt=None
     return x_src_bar, gamma_src_bar, x_tgt_bar, gamma_tgt_bar
 
 
-def vpm_rk3_stage(stage, dt_step, x, gamma, qx, qg, u, dgamma, *, stream=None):
-    """One low-storage RK3 stage in place: Q <- A_k Q + dt F, Y <- Y + B_k Q (Sec. II.B)."""
-    lib = _lib.load()
-    dt = _code(x)
-    n = x.shape[1]
-    for t, nm in ((x, "x"), (gamma, "gamma"), (qx, "qx"), (qg, "qg"), (u, "u"), (dgamma, "dgamma")):
-        _vec(t, nm, n, x.dtype)
-        if n and t.stride(0) != x.stride(0):
+def _same_ld(ref, arrays, n):
+    for t, nm in arrays:
+        if t is None:
+            continue
+        _vec(t, nm, n)
+        if n and t.stride(0) != ref.stride(0):
             raise ValueError("all stage arrays must share one leading dimension")
-    st = lib.vpm_rk3_stage(dt, int(stage), n, float(dt_step), _p(x), _p(gamma), _p(qx), _p(qg), _p(u),
-                           _p(dgamma), _ld(x), _stream(stream))
+
+
+def vpm_rk3_stage(stage, dt_step, x, gamma, qx, qg, u, dgamma, *, x_eval=None, gamma_eval=None, stream=None):
+    """One low-storage RK3 stage in place: Q <- A_k Q + dt F, Y <- Y + B_k Q (Sec. II.B).
+    The state (x, gamma, qx, qg) may be float64 with float32 F (mixed program); x_eval and
+    gamma_eval then receive the updated state in F's type."""
+    lib = _lib.load()
+    dt, sdt = _code(u), _code(x)
+    n = x.shape[1]
+    _same_ld(x, [(x, "x"), (gamma, "gamma"), (qx, "qx"), (qg, "qg"), (u, "u"), (dgamma, "dgamma"),
+                 (x_eval, "x_eval"), (gamma_eval, "gamma_eval")], n)
+    st = lib.vpm_rk3_stage(dt, sdt, int(stage), n, float(dt_step), _p(x), _p(gamma), _p(qx), _p(qg), _p(u),
+                           _p(dgamma), _ld(x), _p(x_eval), _p(gamma_eval), _stream(stream))
     _check("vpm_rk3_stage", st)
 
 
 def vpm_rk3_stage_backward(stage, dt_step, x_bar, gamma_bar, qx_bar, qg_bar, u_seed, dgamma_seed, *, stream=None):
-    """Adjoint of one RK3 stage (see include/vpm.h)."""
+    """Adjoint of one RK3 stage (see include/vpm.h); seeds take u_seed's type."""
     lib = _lib.load()
-    dt = _code(x_bar)
+    dt, sdt = _code(u_seed), _code(x_bar)
     n = x_bar.shape[1]
-    for t, nm in ((x_bar, "x_bar"), (gamma_bar, "gamma_bar"), (qx_bar, "qx_bar"), (qg_bar, "qg_bar"),
-                  (u_seed, "u_seed"), (dgamma_seed, "dgamma_seed")):
-        _vec(t, nm, n, x_bar.dtype)
-        if n and t.stride(0) != x_bar.stride(0):
-            raise ValueError("all stage arrays must share one leading dimension")
-    st = lib.vpm_rk3_stage_backward(dt, int(stage), n, float(dt_step), _p(x_bar), _p(gamma_bar), _p(qx_bar),
-                                    _p(qg_bar), _p(u_seed), _p(dgamma_seed), _ld(x_bar), _stream(stream))
+    _same_ld(x_bar, [(x_bar, "x_bar"), (gamma_bar, "gamma_bar"), (qx_bar, "qx_bar"), (qg_bar, "qg_bar"),
+                     (u_seed, "u_seed"), (dgamma_seed, "dgamma_seed")], n)
+    st = lib.vpm_rk3_stage_backward(dt, sdt, int(stage), n, float(dt_step), _p(x_bar), _p(gamma_bar),
+                                    _p(qx_bar), _p(qg_bar), _p(u_seed), _p(dgamma_seed), _ld(x_bar),
+                                    _stream(stream))
     _check("vpm_rk3_stage_backward", st)
+
+
+def vpm_convert(src, dst, *, accumulate=False, stream=None):
+    """dst = src or dst += src for (3, n) arrays, converting float64 <-> float32."""
+    lib = _lib.load()
+    n = src.shape[1]
+    _vec(src, "src")
+    _vec(dst, "dst", n)
+    st = lib.vpm_convert(_code(src), _code(dst), n, _p(src), _ld(src), _p(dst), _ld(dst), int(accumulate),
+                         _stream(stream))
+    _check("vpm_convert", st)
 
 
 def vpm_diagnostics(x, gamma, u, dgamma, *, out=None, workspace=None, stream=None):

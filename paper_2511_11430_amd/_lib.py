@@ -29,9 +29,11 @@ SIGNATURES = {
                                   c_vp, c_i64, c_i32, c_vp]),
     "vpm_backward": (c_i32, [c_i32, c_i32, c_i64p, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64,
                              c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(VpmOptions), c_vp, c_sz, c_vp]),
-    "vpm_rk3_stage": (c_i32, [c_i32, c_i32, c_i64, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]),
-    "vpm_rk3_stage_backward": (c_i32, [c_i32, c_i32, c_i64, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64,
-                                       c_vp]),
+    "vpm_rk3_stage": (c_i32, [c_i32, c_i32, c_i32, c_i64, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64,
+                              c_vp, c_vp, c_vp]),
+    "vpm_rk3_stage_backward": (c_i32, [c_i32, c_i32, c_i32, c_i64, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                       c_i64, c_vp]),
+    "vpm_convert": (c_i32, [c_i32, c_i32, c_i64, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp]),
     "vpm_diagnostics": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "vpm_diagnostics_workspace_size": (c_sz, []),
     "vpm_axial_loss": (c_i32, [c_i32, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),

@@ -18,8 +18,8 @@ tensors.
 """
 import torch
 
-from . import (SIGMA_SOURCE, vpm_axial_loss, vpm_backward, vpm_eval_velocity_stretching, vpm_rk3_stage,
-               vpm_rk3_stage_backward)
+from . import (SIGMA_SOURCE, vpm_axial_loss, vpm_backward, vpm_convert, vpm_eval_velocity_stretching,
+               vpm_rk3_stage, vpm_rk3_stage_backward)
 
 
 class VPMFunction(torch.autograd.Function):
@@ -63,37 +63,66 @@ class ControlPointVelocity(torch.autograd.Function):
 
 
 def rk3_forward(x0, gamma0, sigma, n_steps, dt, y_ctrl, checkpoints=None):
-    """Run the program; optionally append each stage's input (x, gamma) to ``checkpoints``.
-    Returns (x, gamma, u_ctrl, loss) with loss a 0-d tensor."""
+    """Run the program.  The state (x0, gamma0) may be float64 while sigma and y_ctrl are
+    float32: then the RK3 registers stay in FP64 and each evaluation reads an FP32 copy of the
+    state (mixed program).  Optionally appends each stage's evaluation input to
+    ``checkpoints``.  Returns (x, gamma, u_ctrl, loss, (x_eval, gamma_eval)) with loss a
+    float64 0-d tensor."""
+    edt = sigma.dtype
+    mixed = x0.dtype != edt
     x, g = x0.clone(), gamma0.clone()
     qx, qg = torch.zeros_like(x), torch.zeros_like(x)
-    u, dg = torch.empty_like(x), torch.empty_like(x)
+    if mixed:
+        xe, ge = torch.empty(x.shape, dtype=edt, device=x.device), torch.empty(x.shape, dtype=edt, device=x.device)
+        vpm_convert(x, xe)
+        vpm_convert(g, ge)
+    else:
+        xe, ge = x, g
+    u, dg = torch.empty_like(xe), torch.empty_like(xe)
     for _ in range(n_steps):
         for k in range(3):
             if checkpoints is not None:
-                checkpoints.append((x.clone(), g.clone()))
-            vpm_eval_velocity_stretching(x, g, sigma, u_out=u, dgamma_out=dg)
-            vpm_rk3_stage(k, dt, x, g, qx, qg, u, dg)
-    uc, _ = vpm_eval_velocity_stretching(x, g, sigma, y_ctrl)
+                checkpoints.append((xe.clone(), ge.clone()))
+            vpm_eval_velocity_stretching(xe, ge, sigma, u_out=u, dgamma_out=dg)
+            if mixed:
+                vpm_rk3_stage(k, dt, x, g, qx, qg, u, dg, x_eval=xe, gamma_eval=ge)
+            else:
+                vpm_rk3_stage(k, dt, x, g, qx, qg, u, dg)
+    uc, _ = vpm_eval_velocity_stretching(xe, ge, sigma, y_ctrl)
     loss, _ = vpm_axial_loss(uc, want_seed=False)
-    return x, g, uc, loss
+    return x, g, uc, loss, (xe, ge)
 
 
-def rk3_backward(checkpoints, x, g, sigma, uc, y_ctrl, dt, loss_bar=None):
-    """Gradient of the loss with respect to the program's initial (x, gamma).  loss_bar:
-    float64 CUDA scalar (None = 1)."""
-    xb, gb = torch.zeros_like(x), torch.zeros_like(x)
+def rk3_backward(checkpoints, final_eval, sigma, uc, y_ctrl, dt, state_dtype, loss_bar=None):
+    """Gradient of the loss with respect to the program's initial (x, gamma), in state_dtype.
+    loss_bar: float64 CUDA scalar (None = 1)."""
+    xe, ge = final_eval
+    mixed = state_dtype != xe.dtype
+    xb = torch.zeros(xe.shape, dtype=state_dtype, device=xe.device)
+    gb = torch.zeros_like(xb)
+    # FP32 gradient contributions are collected in (ix, ig) and added into the FP64 adjoint
+    # state before each stage adjoint reads it.
+    ix, ig = (torch.zeros_like(xe), torch.zeros_like(xe)) if mixed else (xb, gb)
     # seed on the control-point velocity: dL/du_c = 2 loss_bar u_z z
     _, ucb = vpm_axial_loss(uc, loss_bar=loss_bar)
-    vpm_backward(x, g, sigma, ucb, None, y_ctrl, None, None, x_src_bar=xb, gamma_src_bar=gb)
-    qxb, qgb = torch.zeros_like(x), torch.zeros_like(x)
-    us, ds = torch.empty_like(x), torch.empty_like(x)
-    n_stages = len(checkpoints)
-    for i in reversed(range(n_stages)):
+    vpm_backward(xe, ge, sigma, ucb, None, y_ctrl, None, None, x_src_bar=ix, gamma_src_bar=ig)
+    qxb, qgb = torch.zeros_like(xb), torch.zeros_like(xb)
+    us, ds = torch.empty_like(xe), torch.empty_like(xe)
+
+    def fold():
+        if mixed:
+            vpm_convert(ix, xb, accumulate=True)
+            vpm_convert(ig, gb, accumulate=True)
+            ix.zero_()
+            ig.zero_()
+
+    for i in reversed(range(len(checkpoints))):
         k = i % 3
         xk, gk = checkpoints[i]
+        fold()
         vpm_rk3_stage_backward(k, dt, xb, gb, qxb, qgb, us, ds)
-        vpm_backward(xk, gk, sigma, us, ds, x_src_bar=xb, gamma_src_bar=gb)
+        vpm_backward(xk, gk, sigma, us, ds, x_src_bar=ix, gamma_src_bar=ig)
+    fold()
     return xb, gb
 
 
@@ -103,22 +132,27 @@ class RK3Program(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x0, gamma0, sigma, n_steps, dt, y_ctrl):
         ckpt = []
-        x, g, uc, loss = rk3_forward(x0.contiguous(), gamma0.contiguous(), sigma.contiguous(), int(n_steps),
-                                     float(dt), y_ctrl.contiguous(), ckpt)
+        _, _, uc, loss, final_eval = rk3_forward(x0.contiguous(), gamma0.contiguous(), sigma.contiguous(),
+                                                 int(n_steps), float(dt), y_ctrl.contiguous(), ckpt)
         ctx.ckpt = ckpt
+        ctx.final_eval = final_eval
         ctx.dt = float(dt)
-        ctx.save_for_backward(x, g, sigma, uc, y_ctrl)
+        ctx.state_dtype = x0.dtype
+        ctx.save_for_backward(sigma, uc, y_ctrl)
         return loss
 
     @staticmethod
     def backward(ctx, loss_bar):
-        x, g, sigma, uc, y_ctrl = ctx.saved_tensors
+        sigma, uc, y_ctrl = ctx.saved_tensors
         lb = loss_bar.detach().to(torch.float64).reshape(()).contiguous()
-        xb, gb = rk3_backward(ctx.ckpt, x, g, sigma, uc, y_ctrl.contiguous(), ctx.dt, lb)
+        xb, gb = rk3_backward(ctx.ckpt, ctx.final_eval, sigma, uc, y_ctrl.contiguous(), ctx.dt, ctx.state_dtype,
+                              lb)
         ctx.ckpt = None
+        ctx.final_eval = None
         return xb, gb, None, None, None, None
 
 
 def rk3_program_loss(x0, gamma0, sigma, n_steps, dt, y_ctrl):
-    """Differentiable loss of the RK3 wake program (see RK3Program)."""
+    """Differentiable loss of the RK3 wake program (see RK3Program).  float64 (x0, gamma0)
+    with float32 (sigma, y_ctrl) runs the mixed program."""
     return RK3Program.apply(x0, gamma0, sigma, n_steps, dt, y_ctrl)

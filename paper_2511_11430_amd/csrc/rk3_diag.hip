@@ -15,45 +15,64 @@ __constant__ double kRkA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 __constant__ double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 
 // The six component arrays (x, Gamma) are processed as one flat index space of 6 n items.
-template <typename T>
-__global__ __launch_bounds__(256) void k_rk3_stage(int stage, int64_t n, T dt, T* x, T* g, T* qx,
-                                                   T* qg, const T* u, const T* dg, int64_t ld) {
-    const T A = T(kRkA[stage]);
-    const T B = T(kRkB[stage]);
+// S: type of the state and register (x, Gamma, Q); T: type of F = (u, dGamma/dt) and of the
+// optional copies (xe, ge) of the updated state used by the next evaluation.
+template <typename S, typename T>
+__global__ __launch_bounds__(256) void k_rk3_stage(int stage, int64_t n, S dt, S* x, S* g, S* qx, S* qg,
+                                                   const T* u, const T* dg, int64_t ld, T* xe, T* ge) {
+    const S A = S(kRkA[stage]);
+    const S B = S(kRkB[stage]);
     const int64_t total = 6 * n;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * blockDim.x) {
         const int64_t c = i / n;
         const int64_t e = i - c * n;
         const int64_t off = (c % 3) * ld + e;
-        T* y = c < 3 ? x : g;
-        T* q = c < 3 ? qx : qg;
+        S* y = c < 3 ? x : g;
+        S* q = c < 3 ? qx : qg;
         const T* f = c < 3 ? u : dg;
-        const T qn = A * q[off] + dt * f[off];
+        const S qn = A * q[off] + dt * S(f[off]);
         q[off] = qn;
-        y[off] = y[off] + B * qn;
+        const S yn = y[off] + B * qn;
+        y[off] = yn;
+        if (xe) (c < 3 ? xe : ge)[off] = T(yn);
     }
 }
 
 // Adjoint: qtot = Qbar + B_k Ybar;  seed = dt qtot;  Qbar <- A_k qtot.
-template <typename T>
-__global__ __launch_bounds__(256) void k_rk3_stage_bwd(int stage, int64_t n, T dt, const T* xb,
-                                                       const T* gb, T* qxb, T* qgb, T* us, T* ds,
+template <typename S, typename T>
+__global__ __launch_bounds__(256) void k_rk3_stage_bwd(int stage, int64_t n, S dt, const S* xb,
+                                                       const S* gb, S* qxb, S* qgb, T* us, T* ds,
                                                        int64_t ld) {
-    const T A = T(kRkA[stage]);
-    const T B = T(kRkB[stage]);
+    const S A = S(kRkA[stage]);
+    const S B = S(kRkB[stage]);
     const int64_t total = 6 * n;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * blockDim.x) {
         const int64_t c = i / n;
         const int64_t e = i - c * n;
         const int64_t off = (c % 3) * ld + e;
-        const T* yb = c < 3 ? xb : gb;
-        T* qb = c < 3 ? qxb : qgb;
+        const S* yb = c < 3 ? xb : gb;
+        S* qb = c < 3 ? qxb : qgb;
         T* sd = c < 3 ? us : ds;
-        const T qt = qb[off] + B * yb[off];
-        sd[off] = dt * qt;
+        const S qt = qb[off] + B * yb[off];
+        sd[off] = T(dt * qt);
         qb[off] = A * qt;
+    }
+}
+
+// dst = src or dst += src over [3][ld] arrays, converting the element type.
+template <typename SRC, typename DST>
+__global__ __launch_bounds__(256) void k_convert(int64_t n, const SRC* src, int64_t lds, DST* dst, int64_t ldd,
+                                                 int add) {
+    const int64_t total = 3 * n;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t c = i / n;
+        const int64_t e = i - c * n;
+        const DST v = DST(src[c * lds + e]);
+        DST* d = dst + c * ldd + e;
+        *d = add ? DST(*d + v) : v;
     }
 }
 
@@ -153,34 +172,62 @@ int grid_for(int64_t items) {
 
 }  // namespace
 
-hipError_t launch_rk3_stage(int dtype, int stage, int64_t n, double dt, void* x, void* g, void* qx,
-                            void* qg, const void* u, const void* dg, int64_t ld, hipStream_t st) {
+hipError_t launch_rk3_stage(int dtype, int state_dtype, int stage, int64_t n, double dt, void* x, void* g,
+                            void* qx, void* qg, const void* u, const void* dg, int64_t ld, void* xe, void* ge,
+                            hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int grid = grid_for(6 * n);
-    if (dtype == kDtypeF64)
-        hipLaunchKernelGGL(k_rk3_stage<double>, dim3(grid), dim3(256), 0, st, stage, n, dt,
+    if (state_dtype == kDtypeF64 && dtype == kDtypeF64)
+        hipLaunchKernelGGL((k_rk3_stage<double, double>), dim3(grid), dim3(256), 0, st, stage, n, dt,
                            (double*)x, (double*)g, (double*)qx, (double*)qg, (const double*)u,
-                           (const double*)dg, ld);
+                           (const double*)dg, ld, (double*)xe, (double*)ge);
+    else if (state_dtype == kDtypeF64)
+        hipLaunchKernelGGL((k_rk3_stage<double, float>), dim3(grid), dim3(256), 0, st, stage, n, dt,
+                           (double*)x, (double*)g, (double*)qx, (double*)qg, (const float*)u,
+                           (const float*)dg, ld, (float*)xe, (float*)ge);
     else
-        hipLaunchKernelGGL(k_rk3_stage<float>, dim3(grid), dim3(256), 0, st, stage, n, float(dt),
+        hipLaunchKernelGGL((k_rk3_stage<float, float>), dim3(grid), dim3(256), 0, st, stage, n, float(dt),
                            (float*)x, (float*)g, (float*)qx, (float*)qg, (const float*)u,
-                           (const float*)dg, ld);
+                           (const float*)dg, ld, (float*)xe, (float*)ge);
     return hipGetLastError();
 }
 
-hipError_t launch_rk3_stage_bwd(int dtype, int stage, int64_t n, double dt, const void* xb,
-                                const void* gb, void* qxb, void* qgb, void* us, void* ds,
-                                int64_t ld, hipStream_t st) {
+hipError_t launch_rk3_stage_bwd(int dtype, int state_dtype, int stage, int64_t n, double dt, const void* xb,
+                                const void* gb, void* qxb, void* qgb, void* us, void* ds, int64_t ld,
+                                hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int grid = grid_for(6 * n);
-    if (dtype == kDtypeF64)
-        hipLaunchKernelGGL(k_rk3_stage_bwd<double>, dim3(grid), dim3(256), 0, st, stage, n, dt,
+    if (state_dtype == kDtypeF64 && dtype == kDtypeF64)
+        hipLaunchKernelGGL((k_rk3_stage_bwd<double, double>), dim3(grid), dim3(256), 0, st, stage, n, dt,
                            (const double*)xb, (const double*)gb, (double*)qxb, (double*)qgb,
                            (double*)us, (double*)ds, ld);
+    else if (state_dtype == kDtypeF64)
+        hipLaunchKernelGGL((k_rk3_stage_bwd<double, float>), dim3(grid), dim3(256), 0, st, stage, n, dt,
+                           (const double*)xb, (const double*)gb, (double*)qxb, (double*)qgb,
+                           (float*)us, (float*)ds, ld);
     else
-        hipLaunchKernelGGL(k_rk3_stage_bwd<float>, dim3(grid), dim3(256), 0, st, stage, n,
+        hipLaunchKernelGGL((k_rk3_stage_bwd<float, float>), dim3(grid), dim3(256), 0, st, stage, n,
                            float(dt), (const float*)xb, (const float*)gb, (float*)qxb,
                            (float*)qgb, (float*)us, (float*)ds, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int src_dtype, int dst_dtype, int64_t n, const void* src, int64_t lds, void* dst,
+                          int64_t ldd, int add, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int grid = grid_for(3 * n);
+    if (src_dtype == kDtypeF64 && dst_dtype == kDtypeF64)
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(grid), dim3(256), 0, st, n, (const double*)src, lds,
+                           (double*)dst, ldd, add);
+    else if (src_dtype == kDtypeF64)
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid), dim3(256), 0, st, n, (const double*)src, lds,
+                           (float*)dst, ldd, add);
+    else if (dst_dtype == kDtypeF64)
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(grid), dim3(256), 0, st, n, (const float*)src, lds,
+                           (double*)dst, ldd, add);
+    else
+        hipLaunchKernelGGL((k_convert<float, float>), dim3(grid), dim3(256), 0, st, n, (const float*)src, lds,
+                           (float*)dst, ldd, add);
     return hipGetLastError();
 }
 

@@ -536,44 +536,65 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
     return VPM_OK;
 }
 
-vpm_status vpm_rk3_stage(int32_t dtype, int32_t stage, int64_t n, double dt, void* x, void* gamma,
-                         void* qx, void* qg, const void* u, const void* dgamma, int64_t ld,
-                         void* stream) {
-    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+// State arrays may be FP64 while F and the evaluation copies are FP32 (mixed program);
+// otherwise both types must match.
+static bool stage_types_ok(int32_t dtype, int32_t state_dtype) {
+    return dtype_ok(dtype) && dtype_ok(state_dtype) && (state_dtype == dtype || state_dtype == kDtypeF64);
+}
+
+vpm_status vpm_rk3_stage(int32_t dtype, int32_t state_dtype, int32_t stage, int64_t n, double dt, void* x,
+                         void* gamma, void* qx, void* qg, const void* u, const void* dgamma, int64_t ld,
+                         void* x_eval, void* gamma_eval, void* stream) {
+    if (!stage_types_ok(dtype, state_dtype)) return VPM_ERR_DTYPE;
     if (stage < 0 || stage > 2) return VPM_ERR_ENUM;
     if (n < 0 || ld < n) return VPM_ERR_SIZE;
     if (!(dt == dt)) return VPM_ERR_SIZE;
     if (n > 0 && (!x || !gamma || !qx || !qg || !u || !dgamma)) return VPM_ERR_NULL;
-    const size_t es = elem_size(dtype);
-    const Range rs[6] = {span(x, 3, ld, n, es),  span(gamma, 3, ld, n, es), span(qx, 3, ld, n, es),
-                         span(qg, 3, ld, n, es), span(u, 3, ld, n, es),     span(dgamma, 3, ld, n, es)};
-    for (int i = 0; i < 6; ++i)
-        for (int j = i + 1; j < 6; ++j)
+    if ((x_eval == nullptr) != (gamma_eval == nullptr)) return VPM_ERR_NULL;
+    const size_t es = elem_size(dtype), ss = elem_size(state_dtype);
+    const Range rs[8] = {span(x, 3, ld, n, ss),  span(gamma, 3, ld, n, ss),  span(qx, 3, ld, n, ss),
+                         span(qg, 3, ld, n, ss), span(u, 3, ld, n, es),      span(dgamma, 3, ld, n, es),
+                         span(x_eval, 3, ld, n, es), span(gamma_eval, 3, ld, n, es)};
+    for (int i = 0; i < 8; ++i)
+        for (int j = i + 1; j < 8; ++j)
             if (overlap(rs[i], rs[j])) return VPM_ERR_ALIAS;
     if (n == 0) return VPM_OK;
-    return hip_status(vpm::launch_rk3_stage(dtype, stage, n, dt, x, gamma, qx, qg, u, dgamma, ld,
-                                            static_cast<hipStream_t>(stream)));
+    return hip_status(vpm::launch_rk3_stage(dtype, state_dtype, stage, n, dt, x, gamma, qx, qg, u, dgamma, ld,
+                                            x_eval, gamma_eval, static_cast<hipStream_t>(stream)));
 }
 
-vpm_status vpm_rk3_stage_backward(int32_t dtype, int32_t stage, int64_t n, double dt,
-                                  const void* x_bar, const void* gamma_bar, void* qx_bar,
-                                  void* qg_bar, void* u_seed, void* dgamma_seed, int64_t ld,
-                                  void* stream) {
-    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+vpm_status vpm_rk3_stage_backward(int32_t dtype, int32_t state_dtype, int32_t stage, int64_t n, double dt,
+                                  const void* x_bar, const void* gamma_bar, void* qx_bar, void* qg_bar,
+                                  void* u_seed, void* dgamma_seed, int64_t ld, void* stream) {
+    if (!stage_types_ok(dtype, state_dtype)) return VPM_ERR_DTYPE;
     if (stage < 0 || stage > 2) return VPM_ERR_ENUM;
     if (n < 0 || ld < n) return VPM_ERR_SIZE;
     if (!(dt == dt)) return VPM_ERR_SIZE;
     if (n > 0 && (!x_bar || !gamma_bar || !qx_bar || !qg_bar || !u_seed || !dgamma_seed)) return VPM_ERR_NULL;
-    const size_t es = elem_size(dtype);
-    const Range rs[6] = {span(x_bar, 3, ld, n, es),  span(gamma_bar, 3, ld, n, es),
-                         span(qx_bar, 3, ld, n, es), span(qg_bar, 3, ld, n, es),
+    const size_t es = elem_size(dtype), ss = elem_size(state_dtype);
+    const Range rs[6] = {span(x_bar, 3, ld, n, ss),  span(gamma_bar, 3, ld, n, ss),
+                         span(qx_bar, 3, ld, n, ss), span(qg_bar, 3, ld, n, ss),
                          span(u_seed, 3, ld, n, es), span(dgamma_seed, 3, ld, n, es)};
     for (int i = 0; i < 6; ++i)
         for (int j = i + 1; j < 6; ++j)
             if (overlap(rs[i], rs[j])) return VPM_ERR_ALIAS;
     if (n == 0) return VPM_OK;
-    return hip_status(vpm::launch_rk3_stage_bwd(dtype, stage, n, dt, x_bar, gamma_bar, qx_bar, qg_bar,
-                                                u_seed, dgamma_seed, ld, static_cast<hipStream_t>(stream)));
+    return hip_status(vpm::launch_rk3_stage_bwd(dtype, state_dtype, stage, n, dt, x_bar, gamma_bar, qx_bar,
+                                                qg_bar, u_seed, dgamma_seed, ld,
+                                                static_cast<hipStream_t>(stream)));
+}
+
+vpm_status vpm_convert(int32_t src_dtype, int32_t dst_dtype, int64_t n, const void* src, int64_t ld_src, void* dst,
+                       int64_t ld_dst, int32_t accumulate, void* stream) {
+    if (!dtype_ok(src_dtype) || !dtype_ok(dst_dtype)) return VPM_ERR_DTYPE;
+    if (n < 0 || ld_src < n || ld_dst < n) return VPM_ERR_SIZE;
+    if (accumulate != 0 && accumulate != 1) return VPM_ERR_ENUM;
+    if (n > 0 && (!src || !dst)) return VPM_ERR_NULL;
+    if (overlap(span(src, 3, ld_src, n, elem_size(src_dtype)), span(dst, 3, ld_dst, n, elem_size(dst_dtype))))
+        return VPM_ERR_ALIAS;
+    if (n == 0) return VPM_OK;
+    return hip_status(vpm::launch_convert(src_dtype, dst_dtype, n, src, ld_src, dst, ld_dst, accumulate,
+                                          static_cast<hipStream_t>(stream)));
 }
 
 vpm_status vpm_axial_loss(int32_t dtype, int64_t m, const void* u, int64_t ld, double* loss, void* u_bar,

@@ -107,11 +107,14 @@ hipError_t launch_backward(int dtype, bool role_a, bool role_b, bool stretch, bo
                            const BwdArgs& a, hipStream_t st);
 
 // ---------------------------------------------------------------- RK3 and diagnostics
-hipError_t launch_rk3_stage(int dtype, int stage, int64_t n, double dt, void* x, void* g, void* qx,
-                            void* qg, const void* u, const void* dg, int64_t ld, hipStream_t st);
-hipError_t launch_rk3_stage_bwd(int dtype, int stage, int64_t n, double dt, const void* xb,
-                                const void* gb, void* qxb, void* qgb, void* us, void* ds,
-                                int64_t ld, hipStream_t st);
+hipError_t launch_rk3_stage(int dtype, int state_dtype, int stage, int64_t n, double dt, void* x, void* g,
+                            void* qx, void* qg, const void* u, const void* dg, int64_t ld, void* xe, void* ge,
+                            hipStream_t st);
+hipError_t launch_rk3_stage_bwd(int dtype, int state_dtype, int stage, int64_t n, double dt, const void* xb,
+                                const void* gb, void* qxb, void* qgb, void* us, void* ds, int64_t ld,
+                                hipStream_t st);
+hipError_t launch_convert(int src_dtype, int dst_dtype, int64_t n, const void* src, int64_t lds, void* dst,
+                          int64_t ldd, int add, hipStream_t st);
 constexpr int kDiagBlocks = 512;
 constexpr int kDiagSlots = 16;  // doubles per block partial (13 used)
 hipError_t launch_diagnostics(int dtype, int64_t n, const void* x, const void* g, const void* u,

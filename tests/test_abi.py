@@ -142,13 +142,19 @@ def test_backward_validation():
 def test_rk3_and_diagnostics_validation():
     lib = _lib.load()
     r = lib.vpm_rk3_stage
-    assert r(F32C, 3, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 10, None) == ENUM
-    assert r(F32C, 0, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 9, None) == SIZE
-    assert r(F32C, 0, 10, 0.1, P(0), P(0), P(2), P(3), P(4), P(5), 10, None) == ALIAS
-    assert r(F32C, 0, 10, 0.1, None, P(1), P(2), P(3), P(4), P(5), 10, None) == NULL
-    assert r(F32C, 0, 0, 0.1, None, None, None, None, None, None, 0, None) == OK
+    assert r(F32C, F32C, 3, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 10, None, None, None) == ENUM
+    assert r(F32C, F32C, 0, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 9, None, None, None) == SIZE
+    assert r(F32C, F32C, 0, 10, 0.1, P(0), P(0), P(2), P(3), P(4), P(5), 10, None, None, None) == ALIAS
+    assert r(F32C, F32C, 0, 10, 0.1, None, P(1), P(2), P(3), P(4), P(5), 10, None, None, None) == NULL
+    assert r(F64, F32C, 0, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 10, None, None, None) == DTYPE
+    assert r(F32C, F64, 0, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 10, P(6), None, None) == NULL
+    assert r(F32C, F64, 0, 0, 0.1, None, None, None, None, None, None, 0, None, None, None) == OK
     rb = lib.vpm_rk3_stage_backward
-    assert rb(F32C, -1, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 10, None) == ENUM
+    assert rb(F32C, F32C, -1, 10, 0.1, P(0), P(1), P(2), P(3), P(4), P(5), 10, None) == ENUM
+    cv = lib.vpm_convert
+    assert cv(F32C, F64, 10, P(0), 9, P(1), 10, 0, None) == SIZE
+    assert cv(F32C, F64, 10, P(0), 10, P(0), 10, 0, None) == ALIAS
+    assert cv(F32C, F64, 10, P(0), 10, P(1), 10, 2, None) == ENUM
     d = lib.vpm_diagnostics
     need = lib.vpm_diagnostics_workspace_size()
     assert need >= 13 * 8
