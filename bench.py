@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the FP64, adjoint and batching legs")
     ap.add_argument("--n", type=int, default=1 << 20, help="particles (default: the full 1,048,576)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -145,6 +147,12 @@ def main():
     value = pairs / (ms_per_step * 1e-3) / 1e9
     achieved = FLOP_PER_PAIR_VS * pairs / (k_ms * 1e-3) / 1e12
     log(f"step {ms_per_step:.1f} ms, pair kernel {k_ms:.1f} ms, {value:.1f} Gpair/s")
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     nonfinite = int(diag[12].item())
 
     result = {

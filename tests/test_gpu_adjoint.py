@@ -120,7 +120,10 @@ def test_rk3_program_gradient_vs_oracle_tangents(kind, gpu):
     Lo = oracle.rk3_program(x, g, s, steps, dt, y)[3]
     el = abs(L.item() - Lo) / abs(Lo)
     say(f"  loss rel err {el:.2e}")
-    assert el <= {"f64": 1e-12, "mixed": 1e-6, "f32c": 1e-4}[kind]
+    # FP32 evaluation inputs quantise positions of ~1 m to 6e-8 m; at the 0.03 m control-point
+    # distance that alone is ~2e-6 relative in r and ~4e-6 in u (tolerance 1e-5).  FP32 state
+    # storage adds the rounding of each RK3 increment (1e-4).
+    assert el <= {"f64": 1e-12, "mixed": 1e-5, "f32c": 1e-4}[kind]
     ref = np.zeros((2, 3, n))
     for part in range(2):
         for cc in range(3):
@@ -128,7 +131,7 @@ def test_rk3_program_gradient_vs_oracle_tangents(kind, gpu):
                 xd, gd = np.zeros_like(x), np.zeros_like(g)
                 (xd if part == 0 else gd)[cc, i] = 1.0
                 ref[part, cc, i] = oracle.rk3_program_jvp(x, g, s, xd, gd, steps, dt, y)[1]
-    tol = {"f64": 1e-10, "mixed": 1e-6, "f32c": 1e-4}[kind]
+    tol = {"f64": 1e-10, "mixed": 1e-5, "f32c": 1e-4}[kind]
     ex, eg = rel_l2(host(X.grad), ref[0]), rel_l2(host(G.grad), ref[1])
     say(f"  rel-L2 dL/dx {ex:.2e}  dL/dGamma {eg:.2e}")
     assert ex <= tol and eg <= tol
@@ -189,4 +192,4 @@ def test_mixed_program_gradient_matches_fp64_at_full_size(gpu):
     eg = rel_l2(grads["mixed"][1], grads["f64"][1])
     el = abs(grads["mixed"][2] - grads["f64"][2]) / abs(grads["f64"][2])
     say(f"full-size program: loss rel {el:.2e}, dL/dx rel-L2 {ex:.2e}, dL/dGamma rel-L2 {eg:.2e}")
-    assert el <= 1e-5 and ex <= 1e-4 and eg <= 1e-4
+    assert el <= 1e-6 and ex <= 1e-6 and eg <= 1e-6
