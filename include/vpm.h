@@ -219,6 +219,14 @@ vpm_status vpm_axial_loss(int32_t dtype, int64_t m, const void* u, int64_t ld, d
 int32_t vpm_variant_count(void);
 vpm_status vpm_variant_info(int32_t k, int32_t* targets_per_lane, int32_t* workgroup);
 
+/* Kernel-shape plan used when opt->variant is 0 (FP32C only): for target counts in
+ * [n_lo, n_hi] (rounded out to powers of two), single-set (batched = 0) or batched
+ * (batched = 1, counted over all sets) launches use variant k (0 restores the default, 1).
+ * Written by the tuner; process-wide, thread-safe.  vpm_get_plan returns the variant a
+ * launch of n targets would use. */
+vpm_status vpm_set_plan(int32_t dtype, int32_t batched, int64_t n_lo, int64_t n_hi, int32_t variant);
+int32_t vpm_get_plan(int32_t dtype, int32_t batched, int64_t n);
+
 /* Human-readable name of a status code (static string). */
 const char* vpm_status_string(int32_t status);
 

@@ -19,7 +19,7 @@ SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
 
 __all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_backward", "vpm_rk3_stage",
            "vpm_rk3_stage_backward", "vpm_diagnostics", "vpm_workspace_size", "vpm_variant_count",
-           "vpm_variant_info", "vpm_axial_loss", "vpm_convert", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
+           "vpm_variant_info", "vpm_axial_loss", "vpm_convert", "vpm_set_plan", "vpm_get_plan", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
            "SIGMA_SYMMETRIC"]
 
 
@@ -333,6 +333,15 @@ def vpm_axial_loss(u_ctrl, *, loss=None, u_bar=None, loss_bar=None, want_seed=Tr
     st = lib.vpm_axial_loss(dt, m, _p(u_ctrl), _ld(u_ctrl), _p(loss), _p(u_bar), _p(loss_bar), _stream(stream))
     _check("vpm_axial_loss", st)
     return loss, u_bar
+
+
+def vpm_set_plan(batched, n_lo, n_hi, variant):
+    """Kernel shape for FP32C launches of n_lo..n_hi targets when no variant is given."""
+    _check("vpm_set_plan", _lib.load().vpm_set_plan(F32C, int(batched), int(n_lo), int(n_hi), int(variant)))
+
+
+def vpm_get_plan(batched, n):
+    return int(_lib.load().vpm_get_plan(F32C, int(batched), int(n)))
 
 
 def vpm_variant_count():

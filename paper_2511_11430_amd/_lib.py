@@ -39,6 +39,8 @@ SIGNATURES = {
     "vpm_axial_loss": (c_i32, [c_i32, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "vpm_variant_count": (c_i32, []),
     "vpm_variant_info": (c_i32, [c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
+    "vpm_set_plan": (c_i32, [c_i32, c_i32, c_i64, c_i64, c_i32]),
+    "vpm_get_plan": (c_i32, [c_i32, c_i32, c_i64]),
     "vpm_status_string": (ctypes.c_char_p, [c_i32]),
     "vpm_version": (ctypes.c_char_p, []),
 }
@@ -59,4 +61,7 @@ def load():
             fn.restype = res
             fn.argtypes = args
         _lib = lib
+        # kernel-shape plans from a matching tuning cache, if any
+        from . import tune
+        tune.apply_cache()
     return _lib

@@ -39,7 +39,18 @@ struct SrcTile {
 };
 
 // One pair: accumulate into the tile partials of one target.
-template <typename T, int MODE, bool SYM, bool CHECK>
+// Keeps a value opaque to the optimiser so that what is computed from it inside a rarely
+// taken branch is not hoisted to the hot path (emits no instruction).
+__device__ __forceinline__ float opaque(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ double opaque(double v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+template <typename T, int MODE, bool SYM, bool CHECK, bool NEAR>
 __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, const T pw, const T qx,
                                          const T qy, const T qz, const T qw, const T xi0,
                                          const T xi1, const T xi2, const T gi0, const T gi1,
@@ -54,15 +65,16 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
     T G = rinv2 * rinv;
     T Hn = G * rinv2;
     const T cut = SYM ? (qw + cut_i) : qw;
-    if (s2 < cut) {
+    // NEAR is false for source tiles that lie entirely outside every core of this block.
+    if (NEAR && s2 < cut) {
         // source rule: pw = 1/sigma_j; symmetric rule: 1/sigma_ij^2 = RHO_FAR^2 / cut
         T isig, isig2;
         if (SYM) {
-            isig2 = T(Prec<T>::kFarRho2) * rcp_fast(cut);
+            isig2 = T(Prec<T>::kFarRho2) * rcp_fast(opaque(cut));
             isig = sqrt_fast(isig2);
         } else {
-            isig = pw;
-            isig2 = pw * pw;
+            isig = opaque(pw);
+            isig2 = isig * isig;
         }
         core_weights<T>(s2, isig, isig2, G, Hn, G, Hn);
     }
@@ -96,6 +108,43 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
             pB[2] += w * vz;
         }
     }
+}
+
+// Workgroup-wide bounding box (lo, hi per component) and maximum cut: a shuffle reduction in
+// each wavefront, then the wavefront results through LDS (scratch: 7 values per wavefront).
+// Ends with a barrier; every thread receives the result.
+template <typename T>
+__device__ __forceinline__ void block_box(const T (&lo)[3], const T (&hi)[3], T cut, T (&olo)[3], T (&ohi)[3],
+                                          T& ocut, T* scratch) {
+    T v[7] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], cut};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            const T o = __shfl_xor(v[c], off, 64);
+            v[c] = c < 3 ? fmin(v[c], o) : fmax(v[c], o);
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+    const int nwave = (blockDim.x + 63) >> 6;
+    __syncthreads();  // previous readers of scratch are done
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) scratch[wave * 7 + c] = v[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] = scratch[c];
+    for (int w = 1; w < nwave; ++w) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] = c < 3 ? fmin(v[c], scratch[w * 7 + c]) : fmax(v[c], scratch[w * 7 + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        olo[c] = v[c];
+        ohi[c] = v[3 + c];
+    }
+    ocut = v[6];
 }
 
 // Per-target epilogue in FP64: u = U/(4 pi) and the stretching from A and B (tot holds U, A, B).
@@ -146,7 +195,7 @@ struct FwdBlock {
     // Process targets [t0, t1) (at most WG*K of them) against sources [s0, s1) of one set.
     // self_shift: with self evaluation, target t is source t + self_shift (else ignored).
     static __device__ void run(const FwdArgs& a, int64_t s0, int64_t s1, int64_t t0, int64_t t1,
-                               int64_t self_shift, V4* lp, V4* lq, int chunk_id) {
+                               int64_t self_shift, V4* lp, V4* lq, T* box_scratch, int chunk_id) {
         const T* __restrict__ xs = static_cast<const T*>(a.xs);
         const T* __restrict__ gs = static_cast<const T*>(a.gs);
         const T* __restrict__ ss = static_cast<const T*>(a.ss);
@@ -185,6 +234,28 @@ struct FwdBlock {
             else ex[k] = -2;
         }
 
+        // Bounding box of this workgroup's targets and their largest core cut (symmetric rule).
+        T blo[3], bhi[3], bcut;
+        {
+            T lo3[3], hi3[3], mc = T(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lo3[c] = xi[0][c];
+                hi3[c] = xi[0][c];
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!valid[k]) continue;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    lo3[c] = fmin(lo3[c], xi[k][c]);
+                    hi3[c] = fmax(hi3[c], xi[k][c]);
+                }
+                mc = fmax(mc, cut_i[k]);
+            }
+            block_box(lo3, hi3, mc, blo, bhi, bcut, box_scratch);
+        }
+
         T acc[K][kNacc];   // tile partials
         T hi[K][kNacc];    // compensated totals (FP32 path)
         T lo[K][kNacc];
@@ -200,6 +271,7 @@ struct FwdBlock {
         for (int64_t j0 = s0; j0 < s1; j0 += WG) {
             const int cnt = int((s1 - j0) < WG ? (s1 - j0) : WG);
             __syncthreads();
+            T slo[3], shi[3], scut = T(0);
             if (tid < cnt) {
                 const int64_t j = j0 + tid;
                 const T sg = ss[j];
@@ -214,16 +286,39 @@ struct FwdBlock {
                 q.w = SYM ? T(0.5) * far2 * sg * sg : far2 * sg * sg;
                 lp[tid] = p;
                 lq[tid] = q;
+                slo[0] = shi[0] = p.x;
+                slo[1] = shi[1] = p.y;
+                slo[2] = shi[2] = p.z;
+                scut = q.w;
+            } else {
+                // an empty slot: take the first source's position, which is already in the box
+                const T p0 = xs[j0], p1 = xs[a.lds + j0], p2 = xs[2 * a.lds + j0];
+                slo[0] = shi[0] = p0;
+                slo[1] = shi[1] = p1;
+                slo[2] = shi[2] = p2;
             }
+            T tlo[3], thi[3], tcut;
+            block_box(slo, shi, scut, tlo, thi, tcut, box_scratch);
             // Does any of this workgroup's targets skip a source in this tile?
             bool mine = false;
 #pragma unroll
             for (int k = 0; k < K; ++k) mine |= (ex[k] >= j0 && ex[k] < j0 + cnt);
             const bool check = __syncthreads_or(mine);
+            // Is some pair of this block and tile inside a core?  Box-to-box distance vs the
+            // largest cut.
+            T d2 = T(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T gap = fmax(fmax(tlo[c] - bhi[c], blo[c] - thi[c]), T(0));
+                d2 += gap * gap;
+            }
+            const bool near = d2 < (SYM ? tcut + bcut : tcut);
             if (check) {
-                tile<true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
+                if (near) tile<true, true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
+                else tile<true, false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
             } else {
-                tile<false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
+                if (near) tile<false, true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
+                else tile<false, false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
             }
             if constexpr (kComp) {
 #pragma unroll
@@ -257,7 +352,7 @@ struct FwdBlock {
         }
     }
 
-    template <bool CHECK>
+    template <bool CHECK, bool NEAR>
     static __device__ __forceinline__ void tile(const V4* lp, const V4* lq, int cnt, int64_t j0,
                                                 T (&xi)[K][3], T (&gi)[K][3], T (&cut_i)[K],
                                                 int64_t (&ex)[K], T (&acc)[K][kNacc]) {
@@ -267,7 +362,7 @@ struct FwdBlock {
             const V4 q = lq[jj];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                pair_fwd<T, MODE, SYM, CHECK>(p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, xi[k][0],
+                pair_fwd<T, MODE, SYM, CHECK, NEAR>(p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, xi[k][0],
                                               xi[k][1], xi[k][2], gi[k][0], gi[k][1], gi[k][2],
                                               cut_i[k], j0 + jj, ex[k], &acc[k][0],
                                               &acc[k][kNacc > 3 ? 3 : 0],
@@ -283,6 +378,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd(FwdArgs a) {
     using B = FwdBlock<T, K, WG, MODE, SYM>;
     __shared__ typename B::V4 lp[WG];
     __shared__ typename B::V4 lq[WG];
+    __shared__ T box[7 * (WG / 64)];
     const int64_t t0 = a.tgt_begin + int64_t(blockIdx.x) * (WG * K);
     int64_t t1 = t0 + WG * K;
     if (t1 > a.tgt_end) t1 = a.tgt_end;
@@ -293,7 +389,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd(FwdArgs a) {
         s0 = a.src_begin + int64_t(blockIdx.y) * a.chunk;
         s1 = s0 + a.chunk < a.src_end ? s0 + a.chunk : a.src_end;
     }
-    B::run(a, s0, s1, t0, t1, a.src_begin - a.tgt_begin, lp, lq, chunk_id);
+    B::run(a, s0, s1, t0, t1, a.src_begin - a.tgt_begin, lp, lq, box, chunk_id);
 }
 
 // Adds the per-chunk FP64 partials of every target in chunk order and stores the result.
@@ -325,6 +421,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd_batched(FwdArgs a, BatchQueue b
     using B = FwdBlock<T, K, WG, MODE, SYM>;
     __shared__ typename B::V4 lp[WG];
     __shared__ typename B::V4 lq[WG];
+    __shared__ T box[7 * (WG / 64)];
     __shared__ int item_s;
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(bq.counter, 1);
@@ -339,7 +436,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd_batched(FwdArgs a, BatchQueue b
         const int64_t t0 = tb0 + int64_t(it.y) * (WG * K);
         int64_t t1 = t0 + WG * K;
         if (t1 > tb1) t1 = tb1;
-        B::run(a, s0, s1, t0, t1, s0 - tb0, lp, lq, -1);
+        B::run(a, s0, s1, t0, t1, s0 - tb0, lp, lq, box, -1);
     }
 }
 

@@ -155,6 +155,26 @@ hipError_t stage_and_copy(const std::vector<unsigned char>& blob, void* dst, hip
     return hipSuccess;
 }
 
+// ------------------------------------------------------------------ kernel-shape plans
+// Tuned FP32C kernel shape per (single set / batched, ceil(log2(targets))) bucket, written by
+// vpm_set_plan (the tuner); 0 = not set, then variant 1.  Guarded by g_mutex.
+constexpr int kPlanBuckets = 40;
+int g_plan[2][kPlanBuckets] = {};
+
+int plan_bucket(int64_t n) {
+    int b = 0;
+    while (b < kPlanBuckets - 1 && (int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+// 0-based variant for an FP32C launch when the caller leaves opt->variant at 0.
+int choose_variant(const vpm_options& o, bool batched, int64_t n_tgt) {
+    if (o.variant > 0) return o.variant - 1;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    const int v = g_plan[batched ? 1 : 0][plan_bucket(n_tgt)];
+    return v > 0 ? v - 1 : 0;
+}
+
 int fwd_mode(const vpm_options& o, bool stretch) {
     if (!stretch) return vpm::kModeVelocity;
     return o.scheme == VPM_STRETCH_CLASSICAL ? vpm::kModeClassical : vpm::kModeTransposed;
@@ -233,6 +253,22 @@ vpm_status vpm_variant_info(int32_t k, int32_t* tpl, int32_t* wg) {
     return VPM_OK;
 }
 
+vpm_status vpm_set_plan(int32_t dtype, int32_t batched, int64_t n_lo, int64_t n_hi, int32_t variant) {
+    if (dtype != kDtypeF32C) return VPM_ERR_DTYPE;
+    if (batched != 0 && batched != 1) return VPM_ERR_ENUM;
+    if (variant < 0 || variant > vpm::kNumF32Variants) return VPM_ERR_ENUM;
+    if (n_lo < 0 || n_hi < n_lo) return VPM_ERR_SIZE;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    for (int b = plan_bucket(n_lo); b <= plan_bucket(n_hi); ++b) g_plan[batched][b] = variant;
+    return VPM_OK;
+}
+
+int32_t vpm_get_plan(int32_t dtype, int32_t batched, int64_t n) {
+    if (dtype != kDtypeF32C || (batched != 0 && batched != 1) || n < 0) return 0;
+    vpm_options o = default_options();
+    return choose_variant(o, batched == 1, n) + 1;
+}
+
 size_t vpm_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                           const int64_t* tgt_off, const vpm_options* opt) {
     if (!dtype_ok(dtype) || n_batch < 1 || !src_off) return 0;
@@ -242,7 +278,7 @@ size_t vpm_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off
     if (check_offsets(n_batch, src_off) != VPM_OK || check_offsets(n_batch, tgt_off) != VPM_OK) return 0;
     if (check_options(o) != VPM_OK) return 0;
     if (n_batch == 1) {
-        const int variant = o.variant > 0 ? o.variant - 1 : 0;
+        const int variant = choose_variant(o, false, tgt_off[1]);
         return split_plan(dtype, variant, src_off[1], tgt_off[1]).bytes;
     }
     return queue_layout(n_batch, tgt_off, kMinTargetsPerBlock).total;
@@ -306,7 +342,7 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
         if (overlap(ru, r) || overlap(rd, r)) return VPM_ERR_ALIAS;
     if (overlap(ru, rd)) return VPM_ERR_ALIAS;
 
-    int variant = o.variant > 0 ? o.variant - 1 : 0;
+    const int variant = choose_variant(o, n_batch > 1, n_tgt);
     if (workspace && ws_bytes > 0) {
         const Range rw = span(workspace, 1, int64_t(ws_bytes), int64_t(ws_bytes), 1);
         if (overlap(rw, ru) || overlap(rw, rd)) return VPM_ERR_ALIAS;

@@ -160,3 +160,17 @@ def test_rk3_and_diagnostics_validation():
     assert need >= 13 * 8
     assert d(F32C, 10, P(0), P(1), P(2), P(3), 10, P(4), P(5), need - 1, None) == WORKSPACE
     assert d(F32C, 10, P(0), P(1), P(2), P(3), 10, None, P(5), need, None) == NULL
+
+
+def test_plan_table():
+    lib = _lib.load()
+    assert lib.vpm_get_plan(F32C, 0, 1000) >= 1
+    assert lib.vpm_set_plan(F64, 0, 0, 10, 2) == DTYPE
+    assert lib.vpm_set_plan(F32C, 2, 0, 10, 2) == ENUM
+    assert lib.vpm_set_plan(F32C, 0, 0, 10, 9) == ENUM
+    assert lib.vpm_set_plan(F32C, 0, 10, 5, 2) == SIZE
+    old = lib.vpm_get_plan(F32C, 0, 3000)
+    assert lib.vpm_set_plan(F32C, 0, 2049, 4096, 3) == OK
+    assert lib.vpm_get_plan(F32C, 0, 3000) == 3
+    assert lib.vpm_get_plan(F32C, 0, 5000) != 3 or old == 3
+    assert lib.vpm_set_plan(F32C, 0, 2049, 4096, old) == OK
