@@ -10,18 +10,23 @@
 //   Gammabar_j    += g (r x ub_i + Sb_i x Gamma_i) + h c (r x Gamma_i)
 //
 // Gather form, no atomics: each lane owns one particle p of the "lane set" and loops over the
-// "loop set" q, collecting the terms where p is the target (role A, uses p's seeds) and where
-// p is the source (role B, uses q's seeds).  Written with r = x_p - x_q in both roles:
-//   role A: xbar_p += [(a+b) h + tau c k] r + g ub_p x Gamma_q + h c w + h tau Sb_p
-//           Gbar_p += g Gamma_q x Sb_p + h c v
-//   role B: a' = -ub_q.(Gamma_p x r), b' = -Sb_q.w, c' = -Sb_q.r  (tau is the same)
-//           xbar_p += [(a'+b') h' + tau c' k'] r - g' ub_q x Gamma_p + h' c' w - h' tau Sb_q
-//           Gbar_p += g' (Sb_q x Gamma_q - r x ub_q) + h' c' v
-// with v = Gamma_q x r, w = Gamma_p x Gamma_q.  Self evaluation uses both roles over the one
-// set and skips q == p; control-point targets use role B only (sources' gradients) or role A
-// only (targets' gradients).  Weights follow the core-size rule of the forward pass: role A
-// uses sigma_q (source rule), role B sigma_p; outside both cores they coincide.
-// The kernel carries 4 pi g, 4 pi h and 4 pi k and scales by 1/(4 pi) at the end.
+// "loop set" q, collecting the terms where p is the target (role A: weights gA, hA, kA from the
+// source core sigma_q, p's seeds) and where p is the source (role B: gB, hB, kB from sigma_p,
+// q's seeds).  With r = x_p - x_q, v = Gamma_q x r, R = r x ub_q, E_p = Sb_p x Gamma_p and
+// Z_q = Sb_q x Gamma_q:
+//   a = ub_p.v, a' = -Gamma_p.R, b = Gamma_q.E_p, b' = Gamma_p.Z_q, tau = Gamma_p.v,
+//   c = Sb_p.r, c' = -Sb_q.r, hcs = hA c + hB c'
+//   xbar_p += sum [(a+b) hA + tau c kA + (a'+b') hB + tau c' kB] r        (accumulator SR)
+//           + ub_p x sum gA Gamma_q                                         (A)
+//           + Gamma_p x sum (gB ub_q + hcs Gamma_q)                          (UW)
+//           + (sum hA tau) Sb_p - sum hB tau Sb_q                           (T, V)
+//   Gbar_p += (sum gA Gamma_q) x Sb_p + sum (gB (Z_q - R) + hcs v)           (A, Q)
+// Terms that are a per-particle vector times a sum over q are summed first and finished once
+// per particle, which is what keeps the pair cost near three forward pairs.  Outside every
+// core (decided per tile from bounding boxes) the two roles share one set of point-vortex
+// weights; inside, each role takes its own core.  The kernel carries 4 pi (g, h, k) and
+// scales by 1/(4 pi) at the end.  Per-particle sums are FP32 tile partials folded into two-sum
+// pairs (VPM_F32C) or plain FP64 (VPM_F64).
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
@@ -34,34 +39,179 @@ namespace {
 template <typename T>
 using V4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
 
-// 4 pi (g, h, k) for one pair from the far-field powers and, inside the core, the series/closed form.
-// SYM: the pair core is sigma_ij with 1/sigma_ij^2 = RHO_FAR^2 / cut; otherwise isig = 1/sigma.
+// Keeps a value opaque to the optimiser so that work derived from it inside the rare core
+// branch is not hoisted into the hot path (emits no instruction).
+__device__ __forceinline__ float opaque_b(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ double opaque_b(double v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// 4 pi (g, h, k) inside the core (s2 < cut); SYM: 1/sigma^2 = RHO_FAR^2 / cut.
 template <typename T, bool SYM>
-__device__ __forceinline__ void weights3(T s2, T isig, T cut, T Gf, T Hf, T Kf, T& g, T& h, T& k) {
-    T G = Gf, Hn = Hf, Kn = Kf;
-    if (s2 < cut) {
-        T is = isig, is2;
-        if (SYM) {
-            is2 = T(Prec<T>::kFarRho2) * rcp_fast(cut);
-            is = sqrt_fast(is2);
-        } else {
-            is2 = is * is;
-        }
-        core_weights3<T>(s2, is, is2, Gf, Hf, Kf, G, Hn, Kn);
+__device__ __forceinline__ void core3(T s2, T isig, T cut, T Gf, T Hf, T Kf, T& g, T& h, T& k) {
+    T is, is2;
+    if (SYM) {
+        is2 = T(Prec<T>::kFarRho2) * rcp_fast(opaque_b(cut));
+        is = sqrt_fast(is2);
+    } else {
+        is = opaque_b(isig);
+        is2 = is * is;
     }
+    T G, Hn, Kn;
+    core_weights3<T>(s2, is, is2, Gf, Hf, Kf, G, Hn, Kn);
     g = G;
     h = T(-3) * Hn;
     k = T(15) * Kn;
 }
 
+// Accumulator slots: 0-2 SR r, 3-5 A, 6-8 UW, 9-11 Q, and with stretching seeds 12-14 V, 15 T.
+template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
+struct Bwd {
+    static constexpr bool kComp = std::is_same<T, float>::value;
+    static constexpr int kN = STR ? 16 : 12;
+
+    template <bool CHECK, bool NEAR>
+    static __device__ __forceinline__ void tile(const V4<T>* l0, const V4<T>* l1, const V4<T>* l2, const V4<T>* l3,
+                                                const V4<T>* l4, int cnt, int64_t j0, int64_t p, const T (&xp)[3],
+                                                const T (&gp)[3], const T (&up)[3], const T (&sp)[3],
+                                                const T (&ep)[3], T isig_p, T cut_p, T (&acc)[kN]) {
+#pragma unroll 2
+        for (int jj = 0; jj < cnt; ++jj) {
+            const V4<T> q0 = l0[jj];  // x_q, 1/sigma_q
+            const V4<T> q1 = l1[jj];  // Gamma_q, cut_q
+            const T rx = xp[0] - q0.x, ry = xp[1] - q0.y, rz = xp[2] - q0.z;
+            const T s2 = rx * rx + ry * ry + rz * rz;
+            const T rinv = rsqrt_fast(s2);
+            const T rinv2 = rinv * rinv;
+            const T Gf = rinv2 * rinv;
+            const T Hf = Gf * rinv2;
+            const T Kf = Hf * rinv2;
+            T gA = Gf, hA = T(-3) * Hf, kA = T(15) * Kf;
+            T gB = gA, hB = hA, kB = kA;
+            if (NEAR) {
+                const T cutA = SYM ? q1.w + cut_p : q1.w;
+                const T cutB = SYM ? cutA : cut_p;
+                if (RA && s2 < cutA) core3<T, SYM>(s2, q0.w, cutA, Gf, Hf, Kf, gA, hA, kA);
+                if (RB && s2 < cutB) {
+                    if (SYM && RA) {  // one symmetric core for both roles
+                        gB = gA;
+                        hB = hA;
+                        kB = kA;
+                    } else {
+                        core3<T, SYM>(s2, isig_p, cutB, Gf, Hf, Kf, gB, hB, kB);
+                    }
+                }
+            }
+            if (CHECK && j0 + jj == p) gA = hA = kA = gB = hB = kB = T(0);
+            // v = Gamma_q x r
+            const T vx = q1.y * rz - q1.z * ry;
+            const T vy = q1.z * rx - q1.x * rz;
+            const T vz = q1.x * ry - q1.y * rx;
+            T sr = T(0);
+            if (RA) {
+                const T a = up[0] * vx + up[1] * vy + up[2] * vz;
+                sr = a * hA;
+                acc[3] += gA * q1.x;
+                acc[4] += gA * q1.y;
+                acc[5] += gA * q1.z;
+            }
+            if (RB) {
+                const V4<T> q2 = l2[jj];  // ub_q
+                // R = r x ub_q
+                const T Rx = ry * q2.z - rz * q2.y;
+                const T Ry = rz * q2.x - rx * q2.z;
+                const T Rz = rx * q2.y - ry * q2.x;
+                const T ap = -(gp[0] * Rx + gp[1] * Ry + gp[2] * Rz);
+                sr += ap * hB;
+                acc[6] += gB * q2.x;
+                acc[7] += gB * q2.y;
+                acc[8] += gB * q2.z;
+                acc[9] -= gB * Rx;
+                acc[10] -= gB * Ry;
+                acc[11] -= gB * Rz;
+            }
+            if (STR) {
+                const T tau = gp[0] * vx + gp[1] * vy + gp[2] * vz;
+                T hcs = T(0);
+                if (RA) {
+                    const T b = q1.x * ep[0] + q1.y * ep[1] + q1.z * ep[2];
+                    const T c = sp[0] * rx + sp[1] * ry + sp[2] * rz;
+                    sr += b * hA + tau * c * kA;
+                    hcs = hA * c;
+                    acc[15] += hA * tau;
+                }
+                if (RB) {
+                    const V4<T> q3 = l3[jj];  // Sb_q
+                    const V4<T> q4 = l4[jj];  // Z_q = Sb_q x Gamma_q
+                    const T bp = gp[0] * q4.x + gp[1] * q4.y + gp[2] * q4.z;
+                    const T cp = -(q3.x * rx + q3.y * ry + q3.z * rz);
+                    sr += bp * hB + tau * cp * kB;
+                    hcs += hB * cp;
+                    const T ht = hB * tau;
+                    acc[12] += ht * q3.x;
+                    acc[13] += ht * q3.y;
+                    acc[14] += ht * q3.z;
+                    acc[9] += gB * q4.x;
+                    acc[10] += gB * q4.y;
+                    acc[11] += gB * q4.z;
+                }
+                acc[6] += hcs * q1.x;
+                acc[7] += hcs * q1.y;
+                acc[8] += hcs * q1.z;
+                acc[9] += hcs * vx;
+                acc[10] += hcs * vy;
+                acc[11] += hcs * vz;
+            }
+            acc[0] += sr * rx;
+            acc[1] += sr * ry;
+            acc[2] += sr * rz;
+        }
+    }
+};
+
+// Workgroup bounding box (v[0..2] min, v[3..5] max) and largest cut (v[6]): a shuffle
+// reduction per wavefront, then LDS.  Ends with a barrier; every thread gets the result.
+template <typename T>
+__device__ __forceinline__ void box_reduce(T (&v)[7], T* scratch) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            const T o = __shfl_xor(v[c], off, 64);
+            v[c] = c < 3 ? fmin(v[c], o) : fmax(v[c], o);
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+    const int nwave = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) scratch[wave * 7 + c] = v[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] = scratch[c];
+    for (int w = 1; w < nwave; ++w) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] = c < 3 ? fmin(v[c], scratch[w * 7 + c]) : fmax(v[c], scratch[w * 7 + c]);
+    }
+}
+
 template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
 __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
-    constexpr bool kComp = std::is_same<T, float>::value;
-    __shared__ V4<T> l0[WG];  // (x, y, z, 1/sigma)
-    __shared__ V4<T> l1[WG];  // (Gamma, cut)
-    __shared__ V4<T> l2[RB ? WG : 1];  // ub_q
+    using B = Bwd<T, WG, RA, RB, STR, SYM>;
+    constexpr int kN = B::kN;
+    constexpr bool kComp = B::kComp;
+    __shared__ V4<T> l0[WG];                    // (x, y, z, 1/sigma)
+    __shared__ V4<T> l1[WG];                    // (Gamma, cut)
+    __shared__ V4<T> l2[RB ? WG : 1];           // ub_q
     __shared__ V4<T> l3[(RB && STR) ? WG : 1];  // Sb_q
     __shared__ V4<T> l4[(RB && STR) ? WG : 1];  // Sb_q x Gamma_q
+    __shared__ T box[7 * (WG / 64)];
     const T* __restrict__ xl = static_cast<const T*>(a.xl);
     const T* __restrict__ gl = static_cast<const T*>(a.gl);
     const T* __restrict__ sl = static_cast<const T*>(a.sl);
@@ -74,62 +224,71 @@ __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
     const T* __restrict__ sbo = static_cast<const T*>(a.sbo);
     const T far2 = T(Prec<T>::kFarRho2);
     const int tid = threadIdx.x;
-    const int64_t p = int64_t(blockIdx.x) * WG + tid;
+    const int64_t pb0 = int64_t(blockIdx.x) * WG;
+    const int64_t p = pb0 + tid;
     const bool valid = p < a.nl;
-    const int64_t pp = valid ? p : 0;
+    const int64_t pp = valid ? p : pb0;
 
-    const T xp0 = xl[pp], xp1 = xl[a.ldl + pp], xp2 = xl[2 * a.ldl + pp];
-    T gp0 = T(0), gp1 = T(0), gp2 = T(0);
+    T xp[3] = {xl[pp], xl[a.ldl + pp], xl[2 * a.ldl + pp]};
+    T gp[3] = {T(0), T(0), T(0)};
     if (RB || STR) {
-        gp0 = gl[pp];
-        gp1 = gl[a.ldl + pp];
-        gp2 = gl[2 * a.ldl + pp];
+        gp[0] = gl[pp];
+        gp[1] = gl[a.ldl + pp];
+        gp[2] = gl[2 * a.ldl + pp];
     }
-    T sp = T(1);
-    if (RB || SYM) sp = sl[pp];
-    const T isig_p = T(1) / sp;
-    const T cut_p = SYM ? T(0.5) * far2 * sp * sp : far2 * sp * sp;
-    T up0 = T(0), up1 = T(0), up2 = T(0), sb0 = T(0), sb1 = T(0), sb2 = T(0);
+    T sgp = T(1);
+    if (RB || SYM) sgp = sl[pp];
+    const T isig_p = T(1) / sgp;
+    // this particle's role-B core cut (source rule) or its half of the symmetric cut
+    const T cut_p = SYM ? T(0.5) * far2 * sgp * sgp : (RB ? far2 * sgp * sgp : T(0));
+    T up[3] = {T(0), T(0), T(0)}, sp[3] = {T(0), T(0), T(0)}, ep[3] = {T(0), T(0), T(0)};
     if (RA) {
-        up0 = ubl[pp];
-        up1 = ubl[a.ldl + pp];
-        up2 = ubl[2 * a.ldl + pp];
+        up[0] = ubl[pp];
+        up[1] = ubl[a.ldl + pp];
+        up[2] = ubl[2 * a.ldl + pp];
         if (STR) {
-            sb0 = sbl[pp];
-            sb1 = sbl[a.ldl + pp];
-            sb2 = sbl[2 * a.ldl + pp];
+            sp[0] = sbl[pp];
+            sp[1] = sbl[a.ldl + pp];
+            sp[2] = sbl[2 * a.ldl + pp];
+            ep[0] = sp[1] * gp[2] - sp[2] * gp[1];
+            ep[1] = sp[2] * gp[0] - sp[0] * gp[2];
+            ep[2] = sp[0] * gp[1] - sp[1] * gp[0];
         }
     }
+    // bounding box of this workgroup's lane particles and their largest cut
+    T bb[7] = {xp[0], xp[1], xp[2], xp[0], xp[1], xp[2], valid ? cut_p : T(0)};
+    box_reduce(bb, box);
 
-    T acc[6], hi[6], lo[6];
+    T acc[kN], hi[kN], lo[kN];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] = hi[c] = lo[c] = T(0);
+    for (int c = 0; c < kN; ++c) acc[c] = hi[c] = lo[c] = T(0);
 
     for (int64_t j0 = 0; j0 < a.no; j0 += WG) {
         const int cnt = int((a.no - j0) < WG ? (a.no - j0) : WG);
         __syncthreads();
+        // idle slots (tid >= cnt) read the tile's first particle, which keeps the box exact
+        const int64_t jl = j0 + (tid < cnt ? tid : 0);
+        // sigma_q is needed when q acts as a source (role A) or for the symmetric rule;
+        // Gamma_q when q is a source or carries stretching seeds.
+        const T sq = (RA || SYM) ? so[jl] : T(1);
+        V4<T> v0, v1;
+        v0.x = xo[jl]; v0.y = xo[a.ldo + jl]; v0.z = xo[2 * a.ldo + jl]; v0.w = T(1) / sq;
+        if (RA || STR) {
+            v1.x = go[jl]; v1.y = go[a.ldo + jl]; v1.z = go[2 * a.ldo + jl];
+        } else {
+            v1.x = v1.y = v1.z = T(0);
+        }
+        v1.w = SYM ? T(0.5) * far2 * sq * sq : (RA ? far2 * sq * sq : T(0));
         if (tid < cnt) {
-            const int64_t j = j0 + tid;
-            // sigma_q is needed when q acts as a source (role A) or for the symmetric rule;
-            // Gamma_q when q is a source or carries stretching seeds.
-            const T sq = (RA || SYM) ? so[j] : T(1);
-            V4<T> v0, v1;
-            v0.x = xo[j]; v0.y = xo[a.ldo + j]; v0.z = xo[2 * a.ldo + j]; v0.w = T(1) / sq;
-            if (RA || STR) {
-                v1.x = go[j]; v1.y = go[a.ldo + j]; v1.z = go[2 * a.ldo + j];
-            } else {
-                v1.x = v1.y = v1.z = T(0);
-            }
-            v1.w = SYM ? T(0.5) * far2 * sq * sq : far2 * sq * sq;
             l0[tid] = v0;
             l1[tid] = v1;
             if (RB) {
                 V4<T> v2;
-                v2.x = ubo[j]; v2.y = ubo[a.ldo + j]; v2.z = ubo[2 * a.ldo + j]; v2.w = T(0);
+                v2.x = ubo[jl]; v2.y = ubo[a.ldo + jl]; v2.z = ubo[2 * a.ldo + jl]; v2.w = T(0);
                 l2[tid] = v2;
                 if (STR) {
                     V4<T> v3, v4;
-                    v3.x = sbo[j]; v3.y = sbo[a.ldo + j]; v3.z = sbo[2 * a.ldo + j]; v3.w = T(0);
+                    v3.x = sbo[jl]; v3.y = sbo[a.ldo + jl]; v3.z = sbo[2 * a.ldo + jl]; v3.w = T(0);
                     v4.x = v3.y * v1.z - v3.z * v1.y;
                     v4.y = v3.z * v1.x - v3.x * v1.z;
                     v4.z = v3.x * v1.y - v3.y * v1.x;
@@ -139,110 +298,28 @@ __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
                 }
             }
         }
-        const int64_t pb0 = int64_t(blockIdx.x) * WG;
+        // tile box and its largest role-A cut; the reduction's barriers also publish the tile
+        T tb[7] = {v0.x, v0.y, v0.z, v0.x, v0.y, v0.z, tid < cnt ? v1.w : T(0)};
+        box_reduce(tb, box);
+        T d2 = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T gap = fmax(fmax(tb[c] - bb[3 + c], bb[c] - tb[3 + c]), T(0));
+            d2 += gap * gap;
+        }
+        const T reach = SYM ? tb[6] + bb[6] : fmax(tb[6], bb[6]);
+        const bool near = d2 < reach;
         const bool diag = a.self && (j0 < pb0 + WG) && (pb0 < j0 + cnt);
-        __syncthreads();
-        for (int jj = 0; jj < cnt; ++jj) {
-            const V4<T> q0 = l0[jj];
-            const V4<T> q1 = l1[jj];
-            const T rx = xp0 - q0.x, ry = xp1 - q0.y, rz = xp2 - q0.z;
-            const T s2 = rx * rx + ry * ry + rz * rz;
-            const T rinv = rsqrt_fast(s2);
-            const T rinv2 = rinv * rinv;
-            const T Gf = rinv2 * rinv;
-            const T Hf = Gf * rinv2;
-            const T Kf = Hf * rinv2;
-            const bool skip = diag && (j0 + jj == p);
-            // v = Gamma_q x r
-            const T vx = q1.y * rz - q1.z * ry;
-            const T vy = q1.z * rx - q1.x * rz;
-            const T vz = q1.x * ry - q1.y * rx;
-            T wx = T(0), wy = T(0), wz = T(0), tau = T(0);
-            if (STR) {
-                wx = gp1 * q1.z - gp2 * q1.y;
-                wy = gp2 * q1.x - gp0 * q1.z;
-                wz = gp0 * q1.y - gp1 * q1.x;
-                tau = gp0 * vx + gp1 * vy + gp2 * vz;
-            }
-            if (RA) {
-                // sigma_q (source rule) or sigma_pq
-                const T cut = SYM ? q1.w + cut_p : q1.w;
-                T g, h, k;
-                weights3<T, SYM>(s2, q0.w, cut, Gf, Hf, Kf, g, h, k);
-                if (skip) g = h = k = T(0);
-                const T av = up0 * vx + up1 * vy + up2 * vz;
-                // g ub_p x Gamma_q
-                const T ux = up1 * q1.z - up2 * q1.y;
-                const T uy = up2 * q1.x - up0 * q1.z;
-                const T uz = up0 * q1.y - up1 * q1.x;
-                if (STR) {
-                    const T b = sb0 * wx + sb1 * wy + sb2 * wz;
-                    const T c = sb0 * rx + sb1 * ry + sb2 * rz;
-                    const T sr = (av + b) * h + tau * c * k;
-                    const T hc = h * c;
-                    const T ht = h * tau;
-                    acc[0] += sr * rx + g * ux + hc * wx + ht * sb0;
-                    acc[1] += sr * ry + g * uy + hc * wy + ht * sb1;
-                    acc[2] += sr * rz + g * uz + hc * wz + ht * sb2;
-                    // g Gamma_q x Sb_p + h c v
-                    acc[3] += g * (q1.y * sb2 - q1.z * sb1) + hc * vx;
-                    acc[4] += g * (q1.z * sb0 - q1.x * sb2) + hc * vy;
-                    acc[5] += g * (q1.x * sb1 - q1.y * sb0) + hc * vz;
-                } else {
-                    const T sr = av * h;
-                    acc[0] += sr * rx + g * ux;
-                    acc[1] += sr * ry + g * uy;
-                    acc[2] += sr * rz + g * uz;
-                }
-            }
-            if (RB) {
-                const V4<T> q2 = l2[jj];
-                // sigma_p (source rule) or sigma_pq
-                const T cut = SYM ? q1.w + cut_p : cut_p;
-                T g, h, k;
-                weights3<T, SYM>(s2, isig_p, cut, Gf, Hf, Kf, g, h, k);
-                if (skip) g = h = k = T(0);
-                // Gamma_p x r
-                const T v2x = gp1 * rz - gp2 * ry;
-                const T v2y = gp2 * rx - gp0 * rz;
-                const T v2z = gp0 * ry - gp1 * rx;
-                const T ap = -(q2.x * v2x + q2.y * v2y + q2.z * v2z);
-                // ub_q x Gamma_p
-                const T ux = q2.y * gp2 - q2.z * gp1;
-                const T uy = q2.z * gp0 - q2.x * gp2;
-                const T uz = q2.x * gp1 - q2.y * gp0;
-                // r x ub_q
-                const T rux = ry * q2.z - rz * q2.y;
-                const T ruy = rz * q2.x - rx * q2.z;
-                const T ruz = rx * q2.y - ry * q2.x;
-                if (STR) {
-                    const V4<T> q3 = l3[jj];
-                    const V4<T> q4 = l4[jj];
-                    const T bp = -(q3.x * wx + q3.y * wy + q3.z * wz);
-                    const T cp = -(q3.x * rx + q3.y * ry + q3.z * rz);
-                    const T sr = (ap + bp) * h + tau * cp * k;
-                    const T hc = h * cp;
-                    const T ht = h * tau;
-                    acc[0] += sr * rx - g * ux + hc * wx - ht * q3.x;
-                    acc[1] += sr * ry - g * uy + hc * wy - ht * q3.y;
-                    acc[2] += sr * rz - g * uz + hc * wz - ht * q3.z;
-                    acc[3] += g * (q4.x - rux) + hc * vx;
-                    acc[4] += g * (q4.y - ruy) + hc * vy;
-                    acc[5] += g * (q4.z - ruz) + hc * vz;
-                } else {
-                    const T sr = ap * h;
-                    acc[0] += sr * rx - g * ux;
-                    acc[1] += sr * ry - g * uy;
-                    acc[2] += sr * rz - g * uz;
-                    acc[3] -= g * rux;
-                    acc[4] -= g * ruy;
-                    acc[5] -= g * ruz;
-                }
-            }
+        if (diag) {
+            if (near) B::template tile<true, true>(l0, l1, l2, l3, l4, cnt, j0, p, xp, gp, up, sp, ep, isig_p, cut_p, acc);
+            else B::template tile<true, false>(l0, l1, l2, l3, l4, cnt, j0, p, xp, gp, up, sp, ep, isig_p, cut_p, acc);
+        } else {
+            if (near) B::template tile<false, true>(l0, l1, l2, l3, l4, cnt, j0, p, xp, gp, up, sp, ep, isig_p, cut_p, acc);
+            else B::template tile<false, false>(l0, l1, l2, l3, l4, cnt, j0, p, xp, gp, up, sp, ep, isig_p, cut_p, acc);
         }
         if constexpr (kComp) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
+            for (int c = 0; c < kN; ++c) {
                 T s, e;
                 two_sum(hi[c], acc[c], s, e);
                 hi[c] = s;
@@ -252,14 +329,43 @@ __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
         }
     }
     if (!valid) return;
-    T* __restrict__ xb = static_cast<T*>(a.xbar);
-    T* __restrict__ gb = static_cast<T*>(a.gbar);
+    double t[16];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const double v = kInv4PiD * (kComp ? double(hi[c]) + double(lo[c]) : double(acc[c]));
-        if (c >= 3 && !(RB || STR)) continue;  // velocity-only target gradients touch x only
-        T* dst = (c < 3 ? xb : gb) + (c % 3) * a.ldg + p;
-        *dst = T(double(*dst) + v);
+    for (int c = 0; c < 16; ++c) t[c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < kN; ++c) t[c] = kComp ? double(hi[c]) + double(lo[c]) : double(acc[c]);
+    const double u0 = up[0], u1 = up[1], u2 = up[2];
+    const double g0 = gp[0], g1 = gp[1], g2 = gp[2];
+    const double s0 = sp[0], s1 = sp[1], s2 = sp[2];
+    // xbar = SR + ub_p x A + Gamma_p x UW + T Sb_p - V
+    double xb[3] = {t[0], t[1], t[2]};
+    xb[0] += u1 * t[5] - u2 * t[4] + g1 * t[8] - g2 * t[7];
+    xb[1] += u2 * t[3] - u0 * t[5] + g2 * t[6] - g0 * t[8];
+    xb[2] += u0 * t[4] - u1 * t[3] + g0 * t[7] - g1 * t[6];
+    // Gbar = A x Sb_p + Q
+    double gb[3] = {t[9], t[10], t[11]};
+    if (STR) {
+        xb[0] += t[15] * s0 - t[12];
+        xb[1] += t[15] * s1 - t[13];
+        xb[2] += t[15] * s2 - t[14];
+        gb[0] += t[4] * s2 - t[5] * s1;
+        gb[1] += t[5] * s0 - t[3] * s2;
+        gb[2] += t[3] * s1 - t[4] * s0;
+    }
+    T* __restrict__ xo_bar = static_cast<T*>(a.xbar);
+    T* __restrict__ go_bar = static_cast<T*>(a.gbar);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T* d = xo_bar + c * a.ldg + p;
+        *d = T(double(*d) + kInv4PiD * xb[c]);
+    }
+    // velocity-only target gradients touch x only
+    if (RB || STR) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T* d = go_bar + c * a.ldg + p;
+            *d = T(double(*d) + kInv4PiD * gb[c]);
+        }
     }
 }
 
