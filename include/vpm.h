@@ -213,9 +213,10 @@ vpm_status vpm_axial_loss(int32_t dtype, int64_t m, const void* u, int64_t ld, d
                           const double* loss_bar, void* stream);
 
 /* ---------------------------------------------------------------------------------------
- * Kernel-shape variants of the FP32C particle kernel (targets per lane x workgroup size),
- * for the tuner and the tests.  vpm_variant_info fills targets-per-lane and workgroup size
- * of variant k (1-based); returns VPM_ERR_ENUM for an unknown k. */
+ * Kernel-shape variants of the FP32C particle kernel (targets per lane x workgroup size x
+ * sources per inner-loop iteration), for the tuner and the tests.  vpm_variant_info fills
+ * targets-per-lane and workgroup size of variant k (1-based); returns VPM_ERR_ENUM for an
+ * unknown k. */
 int32_t vpm_variant_count(void);
 vpm_status vpm_variant_info(int32_t k, int32_t* targets_per_lane, int32_t* workgroup);
 

@@ -74,6 +74,79 @@ struct Bwd {
     static constexpr bool kComp = std::is_same<T, float>::value;
     static constexpr int kN = STR ? 16 : 12;
 
+    // Both roles with one set of weights (g, h, k): q1 = (Gamma_q, .), q2 = ub_q, q3 = Sb_q,
+    // q4 = Sb_q x Gamma_q (q3, q4 unused without stretching seeds).
+    static __device__ __forceinline__ void far_pair(const V4<T>& q1, const V4<T>& q2, const V4<T>& q3,
+                                                    const V4<T>& q4, T rx, T ry, T rz, T g, T h, T k,
+                                                    const T (&gp)[3], const T (&up)[3], const T (&sp)[3],
+                                                    const T (&ep)[3], T (&acc)[kN]) {
+        // v = Gamma_q x r,  R = r x ub_q
+        const T vx = q1.y * rz - q1.z * ry;
+        const T vy = q1.z * rx - q1.x * rz;
+        const T vz = q1.x * ry - q1.y * rx;
+        const T Rx = ry * q2.z - rz * q2.y;
+        const T Ry = rz * q2.x - rx * q2.z;
+        const T Rz = rx * q2.y - ry * q2.x;
+        acc[3] += g * q1.x;
+        acc[4] += g * q1.y;
+        acc[5] += g * q1.z;
+        acc[6] += g * q2.x;
+        acc[7] += g * q2.y;
+        acc[8] += g * q2.z;
+        T sr;
+        if (STR) {
+            // D = Z_q - R, so a' + b' = Gamma_p . D and the Q term is g D + hcc v
+            const T Dx = q4.x - Rx, Dy = q4.y - Ry, Dz = q4.z - Rz;
+            // s_ab = a + b + a' + b' = ub_p.v + Gamma_q.E_p + Gamma_p.D, one FMA chain
+            T s_ab = up[0] * vx;
+            s_ab = fma(up[1], vy, s_ab);
+            s_ab = fma(up[2], vz, s_ab);
+            s_ab = fma(q1.x, ep[0], s_ab);
+            s_ab = fma(q1.y, ep[1], s_ab);
+            s_ab = fma(q1.z, ep[2], s_ab);
+            s_ab = fma(gp[0], Dx, s_ab);
+            s_ab = fma(gp[1], Dy, s_ab);
+            s_ab = fma(gp[2], Dz, s_ab);
+            // c + c' = (Sb_p - Sb_q) . r
+            T cc = (sp[0] - q3.x) * rx;
+            cc = fma(sp[1] - q3.y, ry, cc);
+            cc = fma(sp[2] - q3.z, rz, cc);
+            T tau = gp[0] * vx;
+            tau = fma(gp[1], vy, tau);
+            tau = fma(gp[2], vz, tau);
+            sr = fma(k * tau, cc, h * s_ab);
+            const T hcc = h * cc;
+            const T ht = h * tau;
+            acc[15] += ht;
+            acc[12] += ht * q3.x;
+            acc[13] += ht * q3.y;
+            acc[14] += ht * q3.z;
+            acc[6] += hcc * q1.x;
+            acc[7] += hcc * q1.y;
+            acc[8] += hcc * q1.z;
+            acc[9] += g * Dx;
+            acc[10] += g * Dy;
+            acc[11] += g * Dz;
+            acc[9] += hcc * vx;
+            acc[10] += hcc * vy;
+            acc[11] += hcc * vz;
+        } else {
+            T s_ab = up[0] * vx;
+            s_ab = fma(up[1], vy, s_ab);
+            s_ab = fma(up[2], vz, s_ab);
+            s_ab = fma(-gp[0], Rx, s_ab);
+            s_ab = fma(-gp[1], Ry, s_ab);
+            s_ab = fma(-gp[2], Rz, s_ab);
+            sr = h * s_ab;
+            acc[9] -= g * Rx;
+            acc[10] -= g * Ry;
+            acc[11] -= g * Rz;
+        }
+        acc[0] += sr * rx;
+        acc[1] += sr * ry;
+        acc[2] += sr * rz;
+    }
+
     template <bool CHECK, bool NEAR>
     static __device__ __forceinline__ void tile(const V4<T>* l0, const V4<T>* l1, const V4<T>* l2, const V4<T>* l3,
                                                 const V4<T>* l4, int cnt, int64_t j0, int64_t p, const T (&xp)[3],
@@ -107,6 +180,23 @@ struct Bwd {
                 }
             }
             if (CHECK && j0 + jj == p) gA = hA = kA = gB = hB = kB = T(0);
+            if constexpr (!NEAR && !CHECK && RA && RB) {
+                // Outside every core both roles share (g, h, k): add the roles' terms before
+                // multiplying by the weights.
+                far_pair(q1, l2[jj], STR ? l3[jj] : q1, STR ? l4[jj] : q1, rx, ry, rz, gA, hA, kA, gp, up, sp, ep,
+                         acc);
+            } else {
+                pair_general(q1, jj, l2, l3, l4, rx, ry, rz, gA, hA, kA, gB, hB, kB, gp, up, sp, ep, acc);
+            }
+        }
+    }
+
+    // Both roles with their own weights (cores, excluded pairs, single-role launches).
+    static __device__ __forceinline__ void pair_general(const V4<T>& q1, int jj, const V4<T>* l2, const V4<T>* l3,
+                                                        const V4<T>* l4, T rx, T ry, T rz, T gA, T hA, T kA, T gB,
+                                                        T hB, T kB, const T (&gp)[3], const T (&up)[3],
+                                                        const T (&sp)[3], const T (&ep)[3], T (&acc)[kN]) {
+        {
             // v = Gamma_q x r
             const T vx = q1.y * rz - q1.z * ry;
             const T vy = q1.z * rx - q1.x * rz;
@@ -202,7 +292,7 @@ __device__ __forceinline__ void box_reduce(T (&v)[7], T* scratch) {
 }
 
 template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
-__global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
+__device__ __forceinline__ void backward_body(const BwdArgs& a) {
     using B = Bwd<T, WG, RA, RB, STR, SYM>;
     constexpr int kN = B::kN;
     constexpr bool kComp = B::kComp;
@@ -369,15 +459,34 @@ __global__ __launch_bounds__(WG) void k_backward(BwdArgs a) {
     }
 }
 
+// FP32: ask for 4 wavefronts per SIMD (<= 128 VGPRs; no spills at these shapes).  FP64 keeps
+// the compiler's choice: its accumulators need twice the registers.
+template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_backward_f32(BwdArgs a) {
+    backward_body<T, WG, RA, RB, STR, SYM>(a);
+}
+template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
+__global__ __launch_bounds__(WG) void k_backward_f64(BwdArgs a) {
+    backward_body<T, WG, RA, RB, STR, SYM>(a);
+}
+
+template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
+void launch_k(int grid, const BwdArgs& a, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value)
+        hipLaunchKernelGGL((k_backward_f32<T, WG, RA, RB, STR, SYM>), dim3(grid), dim3(WG), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_backward_f64<T, WG, RA, RB, STR, SYM>), dim3(grid), dim3(WG), 0, st, a);
+}
+
 template <typename T, int WG, bool RA, bool RB>
 hipError_t launch_rs(bool stretch, bool sym, const BwdArgs& a, hipStream_t st) {
     const int grid = int((a.nl + WG - 1) / WG);
     if (stretch) {
-        if (sym) hipLaunchKernelGGL((k_backward<T, WG, RA, RB, true, true>), dim3(grid), dim3(WG), 0, st, a);
-        else hipLaunchKernelGGL((k_backward<T, WG, RA, RB, true, false>), dim3(grid), dim3(WG), 0, st, a);
+        if (sym) launch_k<T, WG, RA, RB, true, true>(grid, a, st);
+        else launch_k<T, WG, RA, RB, true, false>(grid, a, st);
     } else {
-        if (sym) hipLaunchKernelGGL((k_backward<T, WG, RA, RB, false, true>), dim3(grid), dim3(WG), 0, st, a);
-        else hipLaunchKernelGGL((k_backward<T, WG, RA, RB, false, false>), dim3(grid), dim3(WG), 0, st, a);
+        if (sym) launch_k<T, WG, RA, RB, false, true>(grid, a, st);
+        else launch_k<T, WG, RA, RB, false, false>(grid, a, st);
     }
     return hipGetLastError();
 }

@@ -186,7 +186,7 @@ __device__ __forceinline__ void store_target(const FwdArgs& a, int64_t t, double
     }
 }
 
-template <typename T, int K, int WG, int MODE, bool SYM>
+template <typename T, int K, int WG, int MODE, bool SYM, int U>
 struct FwdBlock {
     static constexpr bool kComp = std::is_same<T, float>::value;
     static constexpr int kNacc = (MODE == kModeVelocity) ? 3 : 9;
@@ -356,7 +356,7 @@ struct FwdBlock {
     static __device__ __forceinline__ void tile(const V4* lp, const V4* lq, int cnt, int64_t j0,
                                                 T (&xi)[K][3], T (&gi)[K][3], T (&cut_i)[K],
                                                 int64_t (&ex)[K], T (&acc)[K][kNacc]) {
-#pragma unroll 2
+#pragma unroll U
         for (int jj = 0; jj < cnt; ++jj) {
             const V4 p = lp[jj];
             const V4 q = lq[jj];
@@ -373,9 +373,9 @@ struct FwdBlock {
 };
 
 // One workgroup per target block of a single particle set.
-template <typename T, int K, int WG, int MODE, bool SYM>
+template <typename T, int K, int WG, int MODE, bool SYM, int U>
 __global__ __launch_bounds__(WG) void k_pair_fwd(FwdArgs a) {
-    using B = FwdBlock<T, K, WG, MODE, SYM>;
+    using B = FwdBlock<T, K, WG, MODE, SYM, U>;
     __shared__ typename B::V4 lp[WG];
     __shared__ typename B::V4 lq[WG];
     __shared__ T box[7 * (WG / 64)];
@@ -416,9 +416,9 @@ __global__ __launch_bounds__(256) void k_pair_fwd_finish(FwdArgs a) {
 
 // Persistent workgroups over a queue of (set, target block) items in decreasing cost order.
 // Every workgroup leaves the loop once the shared counter passes the item count.
-template <typename T, int K, int WG, int MODE, bool SYM>
+template <typename T, int K, int WG, int MODE, bool SYM, int U>
 __global__ __launch_bounds__(WG) void k_pair_fwd_batched(FwdArgs a, BatchQueue bq) {
-    using B = FwdBlock<T, K, WG, MODE, SYM>;
+    using B = FwdBlock<T, K, WG, MODE, SYM, U>;
     __shared__ typename B::V4 lp[WG];
     __shared__ typename B::V4 lq[WG];
     __shared__ T box[7 * (WG / 64)];
@@ -443,14 +443,14 @@ __global__ __launch_bounds__(WG) void k_pair_fwd_batched(FwdArgs a, BatchQueue b
 // ------------------------------------------------------------------ host-side launchers
 namespace {
 
-template <typename T, int K, int WG, int MODE, bool SYM>
+template <typename T, int K, int WG, int MODE, bool SYM, int U>
 hipError_t launch_one(const FwdArgs& a, const BatchQueue* bq, int grid, hipStream_t st) {
     if (bq) {
-        hipLaunchKernelGGL((k_pair_fwd_batched<T, K, WG, MODE, SYM>), dim3(grid), dim3(WG), 0, st, a, *bq);
+        hipLaunchKernelGGL((k_pair_fwd_batched<T, K, WG, MODE, SYM, U>), dim3(grid), dim3(WG), 0, st, a, *bq);
         return hipGetLastError();
     }
     const int ny = a.nchunk > 1 ? a.nchunk : 1;
-    hipLaunchKernelGGL((k_pair_fwd<T, K, WG, MODE, SYM>), dim3(grid, ny), dim3(WG), 0, st, a);
+    hipLaunchKernelGGL((k_pair_fwd<T, K, WG, MODE, SYM, U>), dim3(grid, ny), dim3(WG), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || ny == 1) return e;
     const int64_t nt = a.tgt_end - a.tgt_begin;
@@ -458,76 +458,69 @@ hipError_t launch_one(const FwdArgs& a, const BatchQueue* bq, int grid, hipStrea
     return hipGetLastError();
 }
 
-template <typename T, int K, int WG, int MODE, bool SYM>
+template <typename T, int K, int WG, int MODE, bool SYM, int U>
 int occupancy_one(bool batched) {
     int nb = 0;
     hipError_t e;
     if (batched)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_fwd_batched<T, K, WG, MODE, SYM>, WG, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_fwd_batched<T, K, WG, MODE, SYM, U>, WG, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_fwd<T, K, WG, MODE, SYM>, WG, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_fwd<T, K, WG, MODE, SYM, U>, WG, 0);
     return e == hipSuccess ? nb : 0;
 }
 
-template <typename T, int K, int WG>
+template <typename T, int K, int WG, int U>
 hipError_t dispatch_mode(int mode, bool sym, const FwdArgs& a, const BatchQueue* bq, int grid,
                          hipStream_t st) {
     if (mode == kModeTransposed)
-        return sym ? launch_one<T, K, WG, kModeTransposed, true>(a, bq, grid, st)
-                   : launch_one<T, K, WG, kModeTransposed, false>(a, bq, grid, st);
+        return sym ? launch_one<T, K, WG, kModeTransposed, true, U>(a, bq, grid, st)
+                   : launch_one<T, K, WG, kModeTransposed, false, U>(a, bq, grid, st);
     if (mode == kModeClassical)
-        return sym ? launch_one<T, K, WG, kModeClassical, true>(a, bq, grid, st)
-                   : launch_one<T, K, WG, kModeClassical, false>(a, bq, grid, st);
-    return sym ? launch_one<T, K, WG, kModeVelocity, true>(a, bq, grid, st)
-               : launch_one<T, K, WG, kModeVelocity, false>(a, bq, grid, st);
+        return sym ? launch_one<T, K, WG, kModeClassical, true, U>(a, bq, grid, st)
+                   : launch_one<T, K, WG, kModeClassical, false, U>(a, bq, grid, st);
+    return sym ? launch_one<T, K, WG, kModeVelocity, true, U>(a, bq, grid, st)
+               : launch_one<T, K, WG, kModeVelocity, false, U>(a, bq, grid, st);
 }
 
-template <typename T, int K, int WG>
+template <typename T, int K, int WG, int U>
 int occupancy_mode(int mode, bool sym, bool batched) {
     if (mode == kModeTransposed)
-        return sym ? occupancy_one<T, K, WG, kModeTransposed, true>(batched)
-                   : occupancy_one<T, K, WG, kModeTransposed, false>(batched);
+        return sym ? occupancy_one<T, K, WG, kModeTransposed, true, U>(batched)
+                   : occupancy_one<T, K, WG, kModeTransposed, false, U>(batched);
     if (mode == kModeClassical)
-        return sym ? occupancy_one<T, K, WG, kModeClassical, true>(batched)
-                   : occupancy_one<T, K, WG, kModeClassical, false>(batched);
-    return sym ? occupancy_one<T, K, WG, kModeVelocity, true>(batched)
-               : occupancy_one<T, K, WG, kModeVelocity, false>(batched);
+        return sym ? occupancy_one<T, K, WG, kModeClassical, true, U>(batched)
+                   : occupancy_one<T, K, WG, kModeClassical, false, U>(batched);
+    return sym ? occupancy_one<T, K, WG, kModeVelocity, true, U>(batched)
+               : occupancy_one<T, K, WG, kModeVelocity, false, U>(batched);
 }
 
 }  // namespace
 
-// FP32C variants: (targets per lane, workgroup size).  Index 0 is variant 1.
+// FP32C variants: (targets per lane, workgroup size, source unroll).  Index 0 is variant 1.
 const FwdVariant kF32Variants[kNumF32Variants] = {
-    {2, 256}, {1, 256}, {4, 256}, {2, 128}, {4, 128}, {1, 128}, {2, 64}, {4, 64},
+    {2, 256, 2}, {1, 256, 2}, {1, 256, 4}, {2, 128, 2}, {2, 256, 4}, {1, 128, 2}, {1, 128, 4}, {1, 512, 2},
 };
+
+#define VPM_F32_VARIANTS(X) \
+    X(0, 2, 256, 2) X(1, 1, 256, 2) X(2, 1, 256, 4) X(3, 2, 128, 2) X(4, 2, 256, 4) X(5, 1, 128, 2) X(6, 1, 128, 4) X(7, 1, 512, 2)
 
 hipError_t launch_pair_fwd(int dtype, int variant, int mode, bool sym, const FwdArgs& a,
                            const BatchQueue* bq, int grid, hipStream_t st) {
-    if (dtype == kDtypeF64) return dispatch_mode<double, 1, 256>(mode, sym, a, bq, grid, st);
+    if (dtype == kDtypeF64) return dispatch_mode<double, 1, 256, 2>(mode, sym, a, bq, grid, st);
     switch (variant) {
-        case 0: return dispatch_mode<float, 2, 256>(mode, sym, a, bq, grid, st);
-        case 1: return dispatch_mode<float, 1, 256>(mode, sym, a, bq, grid, st);
-        case 2: return dispatch_mode<float, 4, 256>(mode, sym, a, bq, grid, st);
-        case 3: return dispatch_mode<float, 2, 128>(mode, sym, a, bq, grid, st);
-        case 4: return dispatch_mode<float, 4, 128>(mode, sym, a, bq, grid, st);
-        case 5: return dispatch_mode<float, 1, 128>(mode, sym, a, bq, grid, st);
-        case 6: return dispatch_mode<float, 2, 64>(mode, sym, a, bq, grid, st);
-        case 7: return dispatch_mode<float, 4, 64>(mode, sym, a, bq, grid, st);
+#define X(i, k, wg, u) case i: return dispatch_mode<float, k, wg, u>(mode, sym, a, bq, grid, st);
+        VPM_F32_VARIANTS(X)
+#undef X
         default: return hipErrorInvalidValue;
     }
 }
 
 int pair_fwd_occupancy(int dtype, int variant, int mode, bool sym, bool batched) {
-    if (dtype == kDtypeF64) return occupancy_mode<double, 1, 256>(mode, sym, batched);
+    if (dtype == kDtypeF64) return occupancy_mode<double, 1, 256, 2>(mode, sym, batched);
     switch (variant) {
-        case 0: return occupancy_mode<float, 2, 256>(mode, sym, batched);
-        case 1: return occupancy_mode<float, 1, 256>(mode, sym, batched);
-        case 2: return occupancy_mode<float, 4, 256>(mode, sym, batched);
-        case 3: return occupancy_mode<float, 2, 128>(mode, sym, batched);
-        case 4: return occupancy_mode<float, 4, 128>(mode, sym, batched);
-        case 5: return occupancy_mode<float, 1, 128>(mode, sym, batched);
-        case 6: return occupancy_mode<float, 2, 64>(mode, sym, batched);
-        case 7: return occupancy_mode<float, 4, 64>(mode, sym, batched);
+#define X(i, k, wg, u) case i: return occupancy_mode<float, k, wg, u>(mode, sym, batched);
+        VPM_F32_VARIANTS(X)
+#undef X
         default: return 0;
     }
 }

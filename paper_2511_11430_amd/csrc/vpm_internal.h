@@ -48,8 +48,9 @@ struct BatchQueue {
 };
 
 struct FwdVariant {
-    int k;   // targets per lane
-    int wg;  // workgroup size
+    int k;       // targets per lane
+    int wg;      // workgroup size
+    int unroll;  // sources per inner-loop iteration
 };
 constexpr int kNumF32Variants = 8;
 extern const FwdVariant kF32Variants[kNumF32Variants];
