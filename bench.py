@@ -32,7 +32,6 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
 FLOP_PER_PAIR_VS = 45               # velocity + transposed stretching, point-vortex branch
-PAIR_KERNEL = "k_pair_fwd<float, 2, 256, transposed, source rule>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pair_fwd_f32c_forward_flight_1M.json")
 
 
@@ -147,6 +146,9 @@ def main():
     value = pairs / (ms_per_step * 1e-3) / 1e9
     achieved = FLOP_PER_PAIR_VS * pairs / (k_ms * 1e-3) / 1e12
     log(f"step {ms_per_step:.1f} ms, pair kernel {k_ms:.1f} ms, {value:.1f} Gpair/s")
+    plan = vpm.vpm_get_plan(0, N)
+    tpl, wg = vpm.vpm_variant_info(plan)
+    pair_kernel = f"k_pair_fwd<float, {tpl} target(s)/lane, {wg} lanes, transposed, source rule> (shape {plan})"
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -166,7 +168,7 @@ def main():
                                                    "FP64 diagnostics"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": load_traffic(1), "kernel": PAIR_KERNEL, "kernel_ms": round(k_ms, 3),
+                     "traffic": load_traffic(1), "kernel": pair_kernel, "kernel_ms": round(k_ms, 3),
                      "flop_per_pair": FLOP_PER_PAIR_VS},
         "nonfinite": nonfinite,
     }
