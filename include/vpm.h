@@ -203,6 +203,14 @@ vpm_status vpm_diagnostics(int32_t dtype, int64_t n, const void* x, const void* 
                            size_t ws_bytes, void* stream);
 size_t vpm_diagnostics_workspace_size(void);
 
+/* vpm_validate_inputs — device-side check of a particle set before an evaluation: out (device
+ * double[13]) receives [0] the number of particles whose sigma is not finite and > 0, [1] the
+ * number of non-finite entries among x and Gamma; [2..12] are 0.  Nothing is modified; the
+ * caller decides (an evaluation on such inputs is not defined).  Workspace as for
+ * vpm_diagnostics. */
+vpm_status vpm_validate_inputs(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* sigma,
+                               int64_t ld, double* out, void* workspace, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * vpm_axial_loss — the blade-point loss used for wake gradients: L = sum_c (u_c . z)^2 over
  * m control-point velocities u [3][ld] (u_c from vpm_eval_velocity_stretching with the

@@ -19,7 +19,7 @@ SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
 
 __all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_backward", "vpm_rk3_stage",
            "vpm_rk3_stage_backward", "vpm_diagnostics", "vpm_workspace_size", "vpm_variant_count",
-           "vpm_variant_info", "vpm_axial_loss", "vpm_convert", "vpm_set_plan", "vpm_get_plan", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
+           "vpm_variant_info", "vpm_axial_loss", "vpm_convert", "vpm_validate_inputs", "vpm_set_plan", "vpm_get_plan", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
            "SIGMA_SYMMETRIC"]
 
 
@@ -310,6 +310,29 @@ def vpm_diagnostics(x, gamma, u, dgamma, *, out=None, workspace=None, stream=Non
     st = lib.vpm_diagnostics(dt, n, _p(x), _p(gamma), _p(u), _p(dgamma), _ld(x), _p(out), _p(workspace),
                              workspace.numel() * workspace.element_size(), _stream(stream))
     _check("vpm_diagnostics", st)
+    return out
+
+
+def vpm_validate_inputs(x, gamma, sigma, *, out=None, workspace=None, stream=None):
+    """Counts of invalid inputs on the GPU: returns a float64 CUDA tensor whose [0] is the
+    number of non-positive or non-finite sigma and [1] the number of non-finite x, Gamma."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x)
+    n = x.shape[1]
+    _vec(x, "x", dtype=x.dtype)
+    _vec(gamma, "gamma", n, x.dtype)
+    _scal(sigma, "sigma", n, x.dtype)
+    if n and gamma.stride(0) != x.stride(0):
+        raise ValueError("x and gamma must share one leading dimension")
+    if out is None:
+        out = torch.empty(13, dtype=torch.float64, device=x.device)
+    need = int(lib.vpm_diagnostics_workspace_size())
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    st = lib.vpm_validate_inputs(dt, n, _p(x), _p(gamma), _p(sigma), _ld(x), _p(out), _p(workspace),
+                                 workspace.numel() * workspace.element_size(), _stream(stream))
+    _check("vpm_validate_inputs", st)
     return out
 
 

@@ -36,6 +36,7 @@ SIGNATURES = {
     "vpm_convert": (c_i32, [c_i32, c_i32, c_i64, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp]),
     "vpm_diagnostics": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "vpm_diagnostics_workspace_size": (c_sz, []),
+    "vpm_validate_inputs": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "vpm_axial_loss": (c_i32, [c_i32, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "vpm_variant_count": (c_i32, []),
     "vpm_variant_info": (c_i32, [c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),

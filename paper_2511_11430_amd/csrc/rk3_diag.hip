@@ -163,6 +163,39 @@ __global__ __launch_bounds__(256) void k_axial_loss(int64_t m, const T* u, int64
     if (threadIdx.x == 0 && loss) *loss = red[0];
 }
 
+// Input check: per block, the number of particles with sigma <= 0 or non-finite sigma, and
+// the number of non-finite entries among x and Gamma (FP64 counts, summed by k_diag_final).
+template <typename T>
+__global__ __launch_bounds__(256) void k_validate_partial(int64_t n, const T* x, const T* g, const T* sg,
+                                                          int64_t ld, double* partials) {
+    double bad_sigma = 0.0, bad_vals = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const double s = sg[i];
+        bad_sigma += (isfinite(s) && s > 0.0) ? 0.0 : 1.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            bad_vals += isfinite(double(x[c * ld + i])) ? 0.0 : 1.0;
+            bad_vals += isfinite(double(g[c * ld + i])) ? 0.0 : 1.0;
+        }
+    }
+    __shared__ double red[256][2];
+    red[threadIdx.x][0] = bad_sigma;
+    red[threadIdx.x][1] = bad_vals;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            red[threadIdx.x][0] += red[threadIdx.x + w][0];
+            red[threadIdx.x][1] += red[threadIdx.x + w][1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kDiagSlots) {
+        const double v = threadIdx.x < 2 ? red[0][threadIdx.x] : 0.0;
+        partials[int64_t(blockIdx.x) * kDiagSlots + threadIdx.x] = v;
+    }
+}
+
 int grid_for(int64_t items) {
     int64_t g = (items + 255) / 256;
     if (g > 8192) g = 8192;
@@ -228,6 +261,23 @@ hipError_t launch_convert(int src_dtype, int dst_dtype, int64_t n, const void* s
     else
         hipLaunchKernelGGL((k_convert<float, float>), dim3(grid), dim3(256), 0, st, n, (const float*)src, lds,
                            (float*)dst, ldd, add);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(int dtype, int64_t n, const void* x, const void* g, const void* sg, int64_t ld,
+                           double* out, double* partials, hipStream_t st) {
+    int nb = int((n + 255) / 256);
+    if (nb > kDiagBlocks) nb = kDiagBlocks;
+    if (nb < 1) nb = 1;
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_validate_partial<double>, dim3(nb), dim3(256), 0, st, n, (const double*)x,
+                           (const double*)g, (const double*)sg, ld, partials);
+    else
+        hipLaunchKernelGGL(k_validate_partial<float>, dim3(nb), dim3(256), 0, st, n, (const float*)x,
+                           (const float*)g, (const float*)sg, ld, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, nb, partials, out);
     return hipGetLastError();
 }
 

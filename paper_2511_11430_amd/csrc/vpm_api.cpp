@@ -652,6 +652,24 @@ size_t vpm_diagnostics_workspace_size(void) {
     return size_t(vpm::kDiagBlocks) * vpm::kDiagSlots * sizeof(double);
 }
 
+vpm_status vpm_validate_inputs(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* sigma,
+                               int64_t ld, double* out, void* workspace, size_t ws_bytes, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n < 0 || ld < n) return VPM_ERR_SIZE;
+    if (!out) return VPM_ERR_NULL;
+    if (n > 0 && (!x || !gamma || !sigma)) return VPM_ERR_NULL;
+    if (!workspace || ws_bytes < vpm_diagnostics_workspace_size()) return VPM_ERR_WORKSPACE;
+    const Range ro = span(out, 1, 13, 13, sizeof(double));
+    const Range rw = span(workspace, 1, vpm_diagnostics_workspace_size(), vpm_diagnostics_workspace_size(), 1);
+    if (overlap(ro, rw)) return VPM_ERR_ALIAS;
+    const size_t es = elem_size(dtype);
+    const Range ins[3] = {span(x, 3, ld, n, es), span(gamma, 3, ld, n, es), span(sigma, 1, ld, n, es)};
+    for (const Range& r : ins)
+        if (overlap(ro, r) || overlap(rw, r)) return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_validate(dtype, n, x, gamma, sigma, ld, out, static_cast<double*>(workspace),
+                                           static_cast<hipStream_t>(stream)));
+}
+
 vpm_status vpm_diagnostics(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* u,
                            const void* dgamma, int64_t ld, double* out, void* workspace,
                            size_t ws_bytes, void* stream) {

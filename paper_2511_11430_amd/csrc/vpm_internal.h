@@ -122,6 +122,8 @@ hipError_t launch_diagnostics(int dtype, int64_t n, const void* x, const void* g
                               const void* dg, int64_t ld, double* out, double* partials,
                               hipStream_t st);
 
+hipError_t launch_validate(int dtype, int64_t n, const void* x, const void* g, const void* sg, int64_t ld,
+                           double* out, double* partials, hipStream_t st);
 hipError_t launch_axial_loss(int dtype, int64_t m, const void* u, int64_t ld, double* loss, void* ubar,
                              const double* loss_bar, hipStream_t st);
 

@@ -174,3 +174,14 @@ def test_plan_table():
     assert lib.vpm_get_plan(F32C, 0, 3000) == 3
     assert lib.vpm_get_plan(F32C, 0, 5000) != 3 or old == 3
     assert lib.vpm_set_plan(F32C, 0, 2049, 4096, old) == OK
+
+
+def test_validate_inputs_validation():
+    lib = _lib.load()
+    v = lib.vpm_validate_inputs
+    need = lib.vpm_diagnostics_workspace_size()
+    assert v(5, 10, P(0), P(1), P(2), 10, P(3), P(4), need, None) == DTYPE
+    assert v(F32C, 10, P(0), P(1), P(2), 9, P(3), P(4), need, None) == SIZE
+    assert v(F32C, 10, P(0), P(1), None, 10, P(3), P(4), need, None) == NULL
+    assert v(F32C, 10, P(0), P(1), P(2), 10, P(3), P(4), 8, None) == WORKSPACE
+    assert v(F32C, 10, P(0), P(1), P(2), 10, P(0), P(4), need, None) == ALIAS

@@ -193,3 +193,21 @@ def test_mixed_program_gradient_matches_fp64_at_full_size(gpu):
     el = abs(grads["mixed"][2] - grads["f64"][2]) / abs(grads["f64"][2])
     say(f"full-size program: loss rel {el:.2e}, dL/dx rel-L2 {ex:.2e}, dL/dGamma rel-L2 {eg:.2e}")
     assert el <= 1e-6 and ex <= 1e-6 and eg <= 1e-6
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("rule", [0, 1])
+def test_vjp_dot_product_varied_cores(kind, rule, gpu):
+    """Forward-flight wake (cores log-uniform in [0.01R, 0.05R]) at 8192 particles: the
+    adjoint's dot product against oracle tangents, source and symmetric core rules."""
+    c = W.config3(n=8192)
+    x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], kind)
+    rng = np.random.default_rng([4, rule])
+    ub, sb = prepare([rng.normal(size=x.shape), rng.normal(size=x.shape) * 1e3], kind)
+    xd, gd = rng.normal(size=x.shape) * 1e-3, rng.normal(size=x.shape) * 1e-6
+    xb, gb, _, _ = vpm.vpm_backward(dev(x, kind), dev(g, kind), dev(s, kind), dev(ub, kind), dev(sb, kind),
+                                    sigma_rule=rule)
+    _, _, ud, dd = oracle.eval_pairs_jvp(x, g, s, xd, gd, sigma_rule=rule)
+    lhs = (host(xb) * xd).sum() + (host(gb) * gd).sum()
+    rhs = (ub * ud).sum() + (sb * dd).sum()
+    assert abs(lhs - rhs) <= (1e-11 if kind == "f64" else 1e-5) * abs(rhs)

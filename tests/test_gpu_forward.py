@@ -241,3 +241,64 @@ def test_source_split_for_small_target_sets(kind, gpu):
     uc, _ = vpm.vpm_eval_velocity_stretching(X, G, S, xt)
     uco, _ = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx])
     assert rel_l2(host(uc), uco) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_permutation_invariance(kind, gpu):
+    """Shuffling the particles changes every tile and the summation order; results agree to
+    rounding (also a guard against LDS races: a missing barrier would not reproduce)."""
+    import torch
+    c = W.config2(n=20000)
+    x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], kind)
+    perm = np.random.default_rng(9).permutation(x.shape[1])
+    u1, d1 = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
+    u2, d2 = vpm.vpm_eval_velocity_stretching(dev_(x[:, perm], kind), dev_(g[:, perm], kind), dev_(s[perm], kind))
+    tight = 1e-13 if kind == "f64" else 2e-6
+    assert rel_l2(host(u2), host(u1)[:, perm]) <= tight
+    assert rel_l2(host(d2), host(d1)[:, perm]) <= tight
+    # and twice the same launch is bitwise identical (no order-dependent reduction)
+    u3, d3 = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
+    assert torch.equal(u1, u3) and torch.equal(d1, d3)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_batched_full_size_sampled(kind, gpu):
+    """All 64 wakes at full size (2.77M particles) in one persistent launch; 48 sampled
+    targets per wake against the oracle."""
+    wakes = W.config5()
+    parts = [prepare([w["x"], w["gamma"], w["sigma"]], kind) for w in wakes]
+    off = [0]
+    for x, _, _ in parts:
+        off.append(off[-1] + x.shape[1])
+    X = dev_(np.concatenate([p[0] for p in parts], 1), kind)
+    G = dev_(np.concatenate([p[1] for p in parts], 1), kind)
+    S = dev_(np.concatenate([p[2] for p in parts], 0), kind)
+    say(f"batched full size {kind}: {off[-1]} particles")
+    u, d = vpm.vpm_eval_velocity_stretching(X, G, S, src_off=off)
+    U, D = host(u), host(d)
+    del X, G, S, u, d
+    worst = 0.0
+    for w, (x, g, s) in enumerate(parts):
+        idx = np.sort(np.random.default_rng([31, w]).choice(x.shape[1], 48, replace=False))
+        uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
+        lo = off[w]
+        eu, ed = rel_l2(U[:, lo + idx], uo), rel_l2(D[:, lo + idx], do)
+        worst = max(worst, eu, ed)
+        assert eu <= TOL[kind] and ed <= TOL[kind], (w, eu, ed)
+    say(f"  worst per-wake rel-L2 {worst:.2e}")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_validate_inputs_flags_bad_particles(kind, gpu):
+    """Failure detection from the host side: planted bad values are counted on the GPU."""
+    x, g, s = prepare(_random_set(1000, 3), kind)
+    s = s.copy()
+    x = x.copy()
+    s[[5, 17]] = [0.0, -1.0]
+    s[40] = np.nan
+    x[1, 99] = np.inf
+    out = vpm.vpm_validate_inputs(dev_(x, kind), dev_(g, kind), dev_(s, kind)).cpu().numpy()
+    assert out[0] == 3 and out[1] == 1
+    x2, g2, s2 = prepare(_random_set(1000, 3), kind)
+    out = vpm.vpm_validate_inputs(dev_(x2, kind), dev_(g2, kind), dev_(s2, kind)).cpu().numpy()
+    assert out[0] == 0 and out[1] == 0
