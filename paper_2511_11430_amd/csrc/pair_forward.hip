@@ -13,8 +13,8 @@
 //    skipped by a whole wavefront when none of its lanes is in a core, which is the common case
 //    for spatially ordered wakes.
 //  - FP32 (VPM_F32C): each target's 9 partial sums (u, A = sum G Gamma_j, B) are plain FP32
-//    within a tile and folded into (hi, lo) two-sum pairs after every tile, so the error does
-//    not grow with N.  The per-target epilogue runs in FP64.
+//    within chunks of 128 sources and folded into (hi, lo) two-sum pairs after every chunk, so
+//    the error does not grow with N.  The per-target epilogue runs in FP64.
 //  - FP64 (VPM_F64): the same schedule with K = 1 and plain FP64 sums.
 //  - Stretching is assembled per target from A and B:
 //      transposed: dGamma_i/dt = (Gamma_i x A - 3 B)/(4 pi),  B = sum Hn (Gamma_i . (Gamma_j x r)) r
@@ -314,23 +314,11 @@ struct FwdBlock {
             }
             const bool near = d2 < (SYM ? tcut + bcut : tcut);
             if (check) {
-                if (near) tile<true, true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
-                else tile<true, false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
+                if (near) tile<true, true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc, hi, lo);
+                else tile<true, false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc, hi, lo);
             } else {
-                if (near) tile<false, true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
-                else tile<false, false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc);
-            }
-            if constexpr (kComp) {
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-#pragma unroll
-                    for (int c = 0; c < kNacc; ++c) {
-                        T s, e;
-                        two_sum(hi[k][c], acc[k][c], s, e);
-                        hi[k][c] = s;
-                        lo[k][c] += e;
-                        acc[k][c] = T(0);
-                    }
+                if (near) tile<false, true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc, hi, lo);
+                else tile<false, false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc, hi, lo);
             }
         }
 
@@ -352,22 +340,45 @@ struct FwdBlock {
         }
     }
 
+    // FP32 partials are folded into the (hi, lo) pairs every kFold sources: the in-chunk FP32
+    // sum error grows with the chunk length and is amplified in Gamma_i x A when neighbouring
+    // strengths are nearly parallel (vortex filaments).
+    static constexpr int kFold = 128;
+
+    static __device__ __forceinline__ void fold(T (&acc)[K][kNacc], T (&hi)[K][kNacc], T (&lo)[K][kNacc]) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < kNacc; ++c) {
+                T s, e;
+                two_sum(hi[k][c], acc[k][c], s, e);
+                hi[k][c] = s;
+                lo[k][c] += e;
+                acc[k][c] = T(0);
+            }
+    }
+
     template <bool CHECK, bool NEAR>
     static __device__ __forceinline__ void tile(const V4* lp, const V4* lq, int cnt, int64_t j0,
                                                 T (&xi)[K][3], T (&gi)[K][3], T (&cut_i)[K],
-                                                int64_t (&ex)[K], T (&acc)[K][kNacc]) {
+                                                int64_t (&ex)[K], T (&acc)[K][kNacc], T (&hi)[K][kNacc],
+                                                T (&lo)[K][kNacc]) {
+        for (int c0 = 0; c0 < cnt; c0 += kFold) {
+            const int c1 = (cnt - c0) < kFold ? cnt : c0 + kFold;
 #pragma unroll U
-        for (int jj = 0; jj < cnt; ++jj) {
-            const V4 p = lp[jj];
-            const V4 q = lq[jj];
+            for (int jj = c0; jj < c1; ++jj) {
+                const V4 p = lp[jj];
+                const V4 q = lq[jj];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                pair_fwd<T, MODE, SYM, CHECK, NEAR>(p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, xi[k][0],
-                                              xi[k][1], xi[k][2], gi[k][0], gi[k][1], gi[k][2],
-                                              cut_i[k], j0 + jj, ex[k], &acc[k][0],
-                                              &acc[k][kNacc > 3 ? 3 : 0],
-                                              &acc[k][kNacc > 3 ? 6 : 0]);
+                for (int k = 0; k < K; ++k) {
+                    pair_fwd<T, MODE, SYM, CHECK, NEAR>(p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, xi[k][0],
+                                                        xi[k][1], xi[k][2], gi[k][0], gi[k][1], gi[k][2],
+                                                        cut_i[k], j0 + jj, ex[k], &acc[k][0],
+                                                        &acc[k][kNacc > 3 ? 3 : 0],
+                                                        &acc[k][kNacc > 3 ? 6 : 0]);
+                }
             }
+            if constexpr (kComp) fold(acc, hi, lo);
         }
     }
 };
