@@ -91,9 +91,19 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
     pu[1] += G * vy;
     pu[2] += G * vz;
     if (MODE != kModeVelocity) {
-        pA[0] += G * qx;
-        pA[1] += G * qy;
-        pA[2] += G * qz;
+        if (NEAR) {
+            // A enters only as Gamma_i x A, so any multiple of Gamma_i may be added to it.  Close
+            // sources dominate A and their strengths are nearly parallel to Gamma_i along a
+            // filament: subtracting Gamma_i before the FP32 sum keeps that large parallel part
+            // out of the rounding.
+            pA[0] += G * (qx - gi0);
+            pA[1] += G * (qy - gi1);
+            pA[2] += G * (qz - gi2);
+        } else {
+            pA[0] += G * qx;
+            pA[1] += G * qy;
+            pA[2] += G * qz;
+        }
         if (MODE == kModeTransposed) {
             const T tau = gi0 * vx + gi1 * vy + gi2 * vz;
             const T w = Hn * tau;
