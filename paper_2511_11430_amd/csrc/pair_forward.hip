@@ -64,6 +64,7 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
     const T rinv2 = rinv * rinv;
     T G = rinv2 * rinv;
     T Hn = G * rinv2;
+    T Ga = G;  // weight of Gamma_j in A
     const T cut = SYM ? (qw + cut_i) : qw;
     // NEAR is false for source tiles that lie entirely outside every core of this block.
     if (NEAR && s2 < cut) {
@@ -77,11 +78,31 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
             isig2 = isig * isig;
         }
         core_weights<T>(s2, isig, isig2, G, Hn, G, Hn);
-    }
-    if (CHECK) {
+        if (CHECK && jglob == ex) {  // the self pair: r = 0, always in the core
+            G = T(0);
+            Hn = T(0);
+        }
+        if (MODE != kModeVelocity) {
+            // In-core pairs dominate A and along a filament their strengths are nearly
+            // parallel to Gamma_i, where Gamma_i x (sum) would cancel in FP32.  Their term
+            // G Gamma_i x Gamma_j is formed per pair instead and added to the stretching sum
+            // through B (dGamma = (Gamma_i x A - 3B)/4pi; classical: -Gamma_i x A - 3B).
+            const T cx = gi1 * qz - gi2 * qy;
+            const T cy = gi2 * qx - gi0 * qz;
+            const T cz = gi0 * qy - gi1 * qx;
+            const T f = (MODE == kModeTransposed ? T(-1.0 / 3.0) : T(1.0 / 3.0)) * G;
+            pB[0] += f * cx;
+            pB[1] += f * cy;
+            pB[2] += f * cz;
+            Ga = T(0);
+        } else {
+            Ga = G;
+        }
+    } else if (CHECK) {
         if (jglob == ex) {
             G = T(0);
             Hn = T(0);
+            Ga = T(0);
         }
     }
     const T vx = qy * rz - qz * ry;
@@ -91,19 +112,9 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
     pu[1] += G * vy;
     pu[2] += G * vz;
     if (MODE != kModeVelocity) {
-        if (NEAR) {
-            // A enters only as Gamma_i x A, so any multiple of Gamma_i may be added to it.  Close
-            // sources dominate A and their strengths are nearly parallel to Gamma_i along a
-            // filament: subtracting Gamma_i before the FP32 sum keeps that large parallel part
-            // out of the rounding.
-            pA[0] += G * (qx - gi0);
-            pA[1] += G * (qy - gi1);
-            pA[2] += G * (qz - gi2);
-        } else {
-            pA[0] += G * qx;
-            pA[1] += G * qy;
-            pA[2] += G * qz;
-        }
+        pA[0] += Ga * qx;
+        pA[1] += Ga * qy;
+        pA[2] += Ga * qz;
         if (MODE == kModeTransposed) {
             const T tau = gi0 * vx + gi1 * vy + gi2 * vz;
             const T w = Hn * tau;
