@@ -47,15 +47,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(launch_units):
-    """HBM bytes per launch from committed rocprofv3 --pmc counters, if the kernel source
-    has not changed since they were taken; else None."""
+def load_traffic(variant):
+    """HBM bytes per launch from committed rocprofv3 --pmc counters, if they were taken on the
+    same kernel source and kernel shape; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_source_hash():
+    if t.get("kernel_hash") != kernel_source_hash() or t.get("variant") != variant:
         return None
     return t.get("bytes_per_launch")
 
@@ -168,7 +168,7 @@ def main():
                                                    "FP64 diagnostics"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": load_traffic(1), "kernel": pair_kernel, "kernel_ms": round(k_ms, 3),
+                     "traffic": load_traffic(plan), "kernel": pair_kernel, "kernel_ms": round(k_ms, 3),
                      "flop_per_pair": FLOP_PER_PAIR_VS},
         "nonfinite": nonfinite,
     }

@@ -71,9 +71,17 @@ template <> struct Prec<double> {
 };
 
 // Hardware reciprocal square root / square root / reciprocal (about 1 ulp) for FP32; the
-// library's correctly rounded versions for FP64.
+// library's correctly rounded square root and division for FP64.
 __device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_fast(double x) { return rsqrt(x); }
+// FP64 1/sqrt(x) for finite x > 0 (callers never use the result at x = 0): the hardware
+// estimate y (about 23 good bits) times the first terms of the binomial series
+// (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y^2, which leaves a relative error of
+// order e^3 plus a few roundings.
+__device__ __forceinline__ double rsqrt_fast(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
 __device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_fast(double x) { return sqrt(x); }
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
