@@ -43,8 +43,12 @@ def _load():
         lib.orc_rk3_program_jvp.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, i32, dbl, i32, i32, i64, _dp,
                                             _dp, _dp, i32]
         lib.orc_diagnostics.argtypes = [i64, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_gradient.argtypes = [i64, _dp, _dp, _dp, i64, _dp, _dp, _lp, i32, _dp, i32]
+        lib.orc_vreman.argtypes = [i64, _dp, _dp, dbl, _dp]
+        lib.orc_pse.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, dbl, _dp, i32]
         for f in ("orc_weights", "orc_ghk", "orc_eval", "orc_eval_jvp", "orc_segments",
-                  "orc_rk3_program", "orc_rk3_program_jvp", "orc_diagnostics"):
+                  "orc_rk3_program", "orc_rk3_program_jvp", "orc_diagnostics", "orc_gradient",
+                  "orc_vreman", "orc_pse"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -228,3 +232,65 @@ def diagnostics(x, gam, u, dgam):
            "diagnostics")
     return {"sum_gamma": out[0:3], "sum_dgamma": out[3:6], "impulse": out[6:9],
             "impulse_rate": out[9:12], "nonfinite": int(out[12])}
+
+
+def velocity_gradient(x_src, gam_src, sig_src, x_tgt=None, sig_tgt=None, excl=None, sigma_rule=SIGMA_SOURCE,
+                      nthreads=0):
+    """Velocity gradient J[a, b] = du_a/dx_b at the targets (sources fixed), shape (3, 3, n_tgt):
+    J = sum_j [g [Gamma_j]_x + h (Gamma_j x r) r^T] (derivative of Eq. 2's Biot-Savart
+    velocity).  With ``x_tgt`` None the targets are the sources and the self pair is skipped."""
+    lib = _load()
+    xs = _vec(x_src, "x_src")
+    gs = _vec(gam_src, "gam_src")
+    ss = np.ascontiguousarray(sig_src, dtype=np.float64).reshape(-1)
+    ns = xs.shape[1]
+    if x_tgt is None:
+        xt, st = xs, ss
+        if excl is None:
+            excl = np.arange(ns, dtype=np.int64)
+    else:
+        xt = _vec(x_tgt, "x_tgt")
+        st = None if sig_tgt is None else np.ascontiguousarray(sig_tgt, dtype=np.float64).reshape(-1)
+    nt = xt.shape[1]
+    e, ep = _excl(excl, nt)
+    J = np.zeros((9, nt))
+    _, stp = _d(st)
+    _check(lib.orc_gradient(ns, xs.ctypes.data_as(_dp), gs.ctypes.data_as(_dp), ss.ctypes.data_as(_dp), nt,
+                            xt.ctypes.data_as(_dp), stp, ep, int(sigma_rule), J.ctypes.data_as(_dp), int(nthreads)),
+           "gradient")
+    return J.reshape(3, 3, nt)
+
+
+def vreman(J, sigma, c_v=0.07):
+    """Vreman eddy viscosity per particle from J (3, 3, n) with filter width sigma (n,)
+    (Sec. II.B: Vreman's model, C_V = 0.07)."""
+    lib = _load()
+    J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(9, -1))
+    n = J.shape[1]
+    sg = np.ascontiguousarray(sigma, dtype=np.float64).reshape(-1)
+    if sg.shape != (n,):
+        raise ValueError("sigma must have one entry per particle")
+    nut = np.zeros(n)
+    _check(lib.orc_vreman(n, J.ctypes.data_as(_dp), sg.ctypes.data_as(_dp), float(c_v), nut.ctypes.data_as(_dp)),
+           "vreman")
+    return nut
+
+
+def pse(x, gam, sigma, vol, nu, nu_t=None, nthreads=0):
+    """Viscous term nu lap(Gamma_i) of Eq. 5 by particle strength exchange with the Gaussian
+    of Eq. 3, for one particle set: returns dGamma/dt (3, n)."""
+    lib = _load()
+    x = _vec(x, "x")
+    g = _vec(gam, "gam")
+    n = x.shape[1]
+    sg = np.ascontiguousarray(sigma, dtype=np.float64).reshape(-1)
+    vo = np.ascontiguousarray(vol, dtype=np.float64).reshape(-1)
+    if sg.shape != (n,) or vo.shape != (n,):
+        raise ValueError("sigma and vol must have one entry per particle")
+    nt_, ntp = _d(None if nu_t is None else np.asarray(nu_t, dtype=np.float64).reshape(-1))
+    if nt_ is not None and nt_.shape != (n,):
+        raise ValueError("nu_t must have one entry per particle")
+    dg = np.zeros((3, n))
+    _check(lib.orc_pse(n, x.ctypes.data_as(_dp), g.ctypes.data_as(_dp), sg.ctypes.data_as(_dp),
+                       vo.ctypes.data_as(_dp), ntp, float(nu), dg.ctypes.data_as(_dp), int(nthreads)), "pse")
+    return dg

@@ -35,17 +35,18 @@ def kernel_weights(s, sigma, dps=40):
         return float(g(s)), float(h(s)), float(k(s))
 
 
-def particle_sums(x, gam, sig, scheme=0, sigma_rule=0, dps=30):
+def particle_sums(x, gam, sig, scheme=0, sigma_rule=0, dps=30, want_grad=False):
     """Self evaluation (self pair excluded) of u_i and dGamma_i/dt for a tiny set.
 
     x, gam: sequences of 3-vectors (n of them); sig: n core sizes.  Returns lists of
-    3-tuples of floats (u, dgamma)."""
+    3-tuples of floats (u, dgamma), and with want_grad also the velocity gradients
+    J[k][l] = du_k/dx_l (3x3 nested tuples) as a third list."""
     n = len(x)
     with mp.workdps(dps):
         X = [[mp.mpf(float(c)) for c in p] for p in x]
         Gm = [[mp.mpf(float(c)) for c in p] for p in gam]
         S = [mp.mpf(float(c)) for c in sig]
-        us, ds = [], []
+        us, ds, js = [], [], []
         for i in range(n):
             grad_sum = [[mp.mpf(0)] * 3 for _ in range(n)]
             u = [mp.mpf(0)] * 3
@@ -90,7 +91,8 @@ def particle_sums(x, gam, sig, scheme=0, sigma_rule=0, dps=30):
                 d = [sum(J[l][k] * Gi[k] for k in range(3)) for l in range(3)]
             us.append(tuple(float(c) for c in u))
             ds.append(tuple(float(c) for c in d))
-        return us, ds
+            js.append(tuple(tuple(float(c) for c in row) for row in J))
+        return (us, ds, js) if want_grad else (us, ds)
 
 
 def segment_velocity_singular(a, b, gam, p, dps=30):

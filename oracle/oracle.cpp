@@ -19,7 +19,19 @@
 //         dGamma_i/dt = sum_{j != i} [ g Gamma_i x Gamma_j + h (Gamma_i . (Gamma_j x r)) r ]
 //     h(s) = g'(s)/s.  Classical option (Gamma_i . grad) u:
 //         sum_{j != i} [ g Gamma_j x Gamma_i + h (r . Gamma_i) (Gamma_j x r) ]
-//     The viscous term of Eq. 5 is not part of this path (nu = 0).
+//   * velocity gradient J_i[a][b] = d u_a / d x_b at the targets (sources held fixed):
+//         J = sum_{j != i} [ g [Gamma_j]_x + h (Gamma_j x r) r^T ]
+//     where [w]_x is the cross-product matrix ([w]_x y = w x y).  The stretching of Eq. 5
+//     is J^T Gamma_i (transposed) or J Gamma_i (classical).
+//   * viscous term of Eq. 5, nu lap(Gamma_i), by particle strength exchange (PSE) with the
+//     Gaussian of Eq. 3 as the exchange kernel (Sec. II.B names PSE):
+//         dGamma_i/dt = sum_{j != i} (2 nu_ij / sigma_ij^2) (V_i Gamma_j - V_j Gamma_i) zeta_{sigma_ij}(|r|)
+//     V = particle volume (an input), sigma_ij^2 = (sigma_i^2 + sigma_j^2)/2 and
+//     nu_ij = nu + (nu_t,i + nu_t,j)/2 (symmetric in i, j, so sum_i dGamma_i/dt = 0).
+//   * Vreman's sub-grid eddy viscosity (Sec. II.B, C_V = 0.07) from J, filter width sigma_i:
+//         nu_t = C_V sqrt(B_beta / (alpha_ab alpha_ab)),  alpha_ab = d u_b / d x_a = J[b][a],
+//         beta_ab = sigma^2 sum_m alpha_ma alpha_mb,
+//         B_beta = b11 b22 - b12^2 + b11 b33 - b13^2 + b22 b33 - b23^2  (0 where alpha = 0).
 //   * straight-segment velocity with a Vatistas core (Sec. II.A): finite-segment
 //     Biot-Savart multiplied by d^2 / (d^(2n) + rc^(2n))^(1/n), d = distance to the line.
 //   * low-storage third-order Runge-Kutta (Williamson 2N-storage, Sec. II.B) for
@@ -302,6 +314,102 @@ void rk3_program(int64_t n, T* x, T* G, const double* sig, int nsteps, double dt
     }
 }
 
+// ---------------------------------------------------------------- velocity gradient
+// Levi-Civita symbol eps_{abc}.
+inline double levi(int a, int b, int c) {
+    if (a == b || b == c || a == c) return 0.0;
+    return ((a == 0 && b == 1 && c == 2) || (a == 1 && b == 2 && c == 0) || (a == 2 && b == 0 && c == 1)) ? 1.0
+                                                                                                        : -1.0;
+}
+
+// J[(3a+b) nt + t] = d u_a / d x_b at target t.  Differentiating g(s) eps_{acd} Gamma_c r_d
+// with respect to x_b (r = x - x_j, ds/dx_b = r_b / s) gives
+//     g eps_{acb} Gamma_c + (g'(s)/s) r_b eps_{acd} Gamma_c r_d.
+void eval_gradient(int64_t ns, const double* xs, const double* gs, const double* sgs, int64_t nt,
+                   const double* xt, const double* sgt, const int64_t* excl, int sigma_rule, double* J) {
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < nt; ++t) {
+        V3<double> xi = load3(xt, nt, t);
+        Neumaier acc[9];
+        for (int64_t j = 0; j < ns; ++j) {
+            if (excl && excl[t] == j) continue;
+            V3<double> xj = load3(xs, ns, j);
+            V3<double> Gj = load3(gs, ns, j);
+            V3<double> r = sub(xi, xj);
+            double s = std::sqrt(dot(r, r));
+            double sig = sgs[j];
+            if (sigma_rule == 1) sig = std::sqrt(0.5 * (sgt[t] * sgt[t] + sgs[j] * sgs[j]));
+            double g, h;
+            ghk<double>(s, sig, &g, &h, nullptr);
+            const double G[3] = {Gj.x, Gj.y, Gj.z};
+            const double R[3] = {r.x, r.y, r.z};
+            V3<double> v = cross(Gj, r);
+            const double Vv[3] = {v.x, v.y, v.z};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double rot = 0.0;
+                    for (int c = 0; c < 3; ++c) rot += levi(a, c, b) * G[c];
+                    acc[3 * a + b].add(g * rot + h * Vv[a] * R[b]);
+                }
+        }
+        for (int k = 0; k < 9; ++k) J[k * nt + t] = acc[k].get();
+    }
+}
+
+// ---------------------------------------------------------------- Vreman eddy viscosity
+double vreman(const double* Jt, double delta, double cv) {
+    // alpha_ab = d u_b / d x_a
+    double al[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) al[a][b] = Jt[3 * b + a];
+    double aa = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) aa += al[a][b] * al[a][b];
+    if (aa == 0.0) return 0.0;
+    double be[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double sum = 0.0;
+            for (int m = 0; m < 3; ++m) sum += al[m][a] * al[m][b];
+            be[a][b] = delta * delta * sum;
+        }
+    double B = be[0][0] * be[1][1] - be[0][1] * be[0][1] + be[0][0] * be[2][2] - be[0][2] * be[0][2] +
+               be[1][1] * be[2][2] - be[1][2] * be[1][2];
+    if (B < 0.0) B = 0.0;  // B_beta >= 0 in exact arithmetic (principal minors of a Gram matrix)
+    return cv * std::sqrt(B / aa);
+}
+
+// ---------------------------------------------------------------- PSE diffusion
+// zeta_sigma(s) = (2 pi sigma^2)^(-3/2) exp(-s^2 / (2 sigma^2))  (Eq. 3)
+double zeta(double s, double sigma) {
+    const double s2 = sigma * sigma;
+    return std::exp(-0.5 * s * s / s2) / std::pow(2.0 * kPi * s2, 1.5);
+}
+
+void eval_pse(int64_t n, const double* x, const double* G, const double* sg, const double* vol,
+              const double* nut, double nu, double* dg) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        V3<double> xi = load3(x, n, i);
+        V3<double> Gi = load3(G, n, i);
+        Neumaier acc[3];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            V3<double> xj = load3(x, n, j);
+            V3<double> Gj = load3(G, n, j);
+            V3<double> r = sub(xi, xj);
+            const double s = std::sqrt(dot(r, r));
+            const double sig2 = 0.5 * (sg[i] * sg[i] + sg[j] * sg[j]);
+            const double nij = nu + (nut ? 0.5 * (nut[i] + nut[j]) : 0.0);
+            const double w = 2.0 * nij / sig2 * zeta(s, std::sqrt(sig2));
+            acc[0].add(w * (vol[i] * Gj.x - vol[j] * Gi.x));
+            acc[1].add(w * (vol[i] * Gj.y - vol[j] * Gi.y));
+            acc[2].add(w * (vol[i] * Gj.z - vol[j] * Gi.z));
+        }
+        for (int c = 0; c < 3; ++c) dg[c * n + i] = acc[c].get();
+    }
+}
+
 template <class T> void set_threads(int nth) {
     if (nth > 0) omp_set_num_threads(nth);
 }
@@ -409,6 +517,37 @@ int orc_rk3_program_jvp(int64_t n, const double* x, const double* G, const doubl
 // out[0..2] = sum Gamma_i, out[3..5] = sum dGamma_i/dt, out[6..8] = impulse 1/2 sum x_i x Gamma_i,
 // out[9..11] = its rate 1/2 sum (u_i x Gamma_i + x_i x dGamma_i/dt), out[12] = number of
 // non-finite entries among x, Gamma, u, dGamma/dt.
+// Velocity gradient J [9][nt] (row-major 3x3 per target: J[(3a+b) nt + t] = du_a/dx_b).
+int orc_gradient(int64_t ns, const double* xs, const double* gs, const double* sgs, int64_t nt,
+                 const double* xt, const double* sgt, const int64_t* excl, int sigma_rule, double* J,
+                 int nthreads) {
+    if (ns < 0 || nt < 0 || !xs || !gs || !sgs || !xt || !J) return 1;
+    if (sigma_rule < 0 || sigma_rule > 1 || (sigma_rule == 1 && !sgt)) return 1;
+    set_threads<double>(nthreads);
+    eval_gradient(ns, xs, gs, sgs, nt, xt, sgt, excl, sigma_rule, J);
+    return 0;
+}
+
+// Vreman eddy viscosity nu_t[n] from J [9][n] with filter width sigma[n].
+int orc_vreman(int64_t n, const double* J, const double* sigma, double cv, double* nut) {
+    if (n < 0 || !J || !sigma || !nut || !(cv >= 0.0)) return 1;
+    for (int64_t i = 0; i < n; ++i) {
+        double Jt[9];
+        for (int k = 0; k < 9; ++k) Jt[k] = J[k * n + i];
+        nut[i] = vreman(Jt, sigma[i], cv);
+    }
+    return 0;
+}
+
+// PSE diffusion dGamma/dt [3][n] of one particle set; nut may be NULL (no eddy viscosity).
+int orc_pse(int64_t n, const double* x, const double* G, const double* sigma, const double* vol,
+            const double* nut, double nu, double* dg, int nthreads) {
+    if (n < 0 || !x || !G || !sigma || !vol || !dg || !(nu >= 0.0)) return 1;
+    set_threads<double>(nthreads);
+    eval_pse(n, x, G, sigma, vol, nut, nu, dg);
+    return 0;
+}
+
 int orc_diagnostics(int64_t n, const double* x, const double* G, const double* u, const double* dg,
                     double* out) {
     if (n < 0 || !x || !G || !u || !dg || !out) return 1;
