@@ -7,7 +7,7 @@
  *   particle field   w(x) = sum_j Gamma_j zeta_sigma(x - x_j)              Sec. II.B, Eq. 2
  *   Gaussian blob    zeta_sigma(rho) = (2 pi sigma^2)^(-3/2) exp(-rho^2/2)  Eq. 3
  *   convection       dx_i/dt = u_i                                          Eq. 4
- *   stretching       dGamma_i/dt = (Gamma_i . grad^T) u_i  (inviscid part)  Eq. 5
+ *   stretching       dGamma_i/dt = (Gamma_i . grad^T) u_i + nu lap(Gamma_i)  Eq. 5
  *
  * with u_i = sum_{j != i} g(|r|) Gamma_j x r, r = x_i - x_j, g(s) = q(s/sigma)/(4 pi s^3),
  * q(rho) = erf(rho/sqrt 2) - sqrt(2/pi) rho exp(-rho^2/2) (the Biot-Savart law of the field
@@ -17,7 +17,9 @@
  * h(s) = g'(s)/s.  It also evaluates the velocity that straight vortex segments (vortex-ring
  * edges of the lattice, Sec. II.A) induce with a Vatistas core, a hand-written adjoint of
  * the particle sums, one stage of the low-storage third-order Runge-Kutta scheme used to
- * advance (x_i, Gamma_i) (Sec. II.B) and its adjoint, and FP64 invariant diagnostics.
+ * advance (x_i, Gamma_i) (Sec. II.B) and its adjoint, FP64 invariant diagnostics, and the
+ * viscous term of Eq. 5: the velocity gradient, Vreman's eddy viscosity and particle strength
+ * exchange (Sec. II.B).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -79,12 +81,14 @@ typedef struct vpm_options {
     int32_t accumulate;  /* 1: outputs += result; 0: outputs = result */
     int32_t variant;     /* 0: tuned/default kernel shape; k > 0: variant k of
                             vpm_variant_count() (used by the tuner and the tests) */
-    int32_t reserved[3]; /* must be 0 */
+    int32_t gradient;    /* 1: the layout is for vpm_eval_velocity_gradient (read by
+                            vpm_workspace_size; vpm_eval_velocity_stretching requires 0) */
+    int32_t reserved[2]; /* must be 0 */
 } vpm_options;
 
 /* ---------------------------------------------------------------------------------------
  * vpm_eval_velocity_stretching — u_t and dGamma_t/dt at every target from every source of
- * its batch (Eqs. 2-5 as above; the viscous term of Eq. 5 is not included).
+ * its batch (Eqs. 2-5 as above; the viscous term of Eq. 5 is vpm_eval_diffusion).
  *
  *  dtype            VPM_F64 or VPM_F32C.
  *  n_batch          number of independent particle sets (wakes), >= 1.
@@ -118,12 +122,75 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
                                         int64_t ld_out, const vpm_options* opt, void* workspace,
                                         size_t ws_bytes, void* stream);
 
-/* Bytes of workspace vpm_eval_velocity_stretching uses for this layout and kernel shape
+/* ---------------------------------------------------------------------------------------
+ * vpm_eval_velocity_gradient — as vpm_eval_velocity_stretching, and also the velocity
+ * gradient at every target, the input of the sub-grid model of Sec. II.B:
+ *   J_t[a][b] = d u_a / d x_b = sum_j [ g [Gamma_j]_x + h (Gamma_j x r) r^T ]   ([w]_x y = w x y)
+ * (the derivative of the Biot-Savart velocity of Eq. 2 at the target, sources fixed).  The
+ * stretching output is J^T Gamma_t (transposed) or J Gamma_t (classical), the same quantity
+ * vpm_eval_velocity_stretching returns.
+ *
+ *  Arguments as for vpm_eval_velocity_stretching, except:
+ *  gamma_tgt        required (the targets are particles); dgamma_out is required.
+ *  grad_out [9][ld_out]: J, row-major per target: element (a, b) of target t at
+ *                   grad_out[(3a + b) ld_out + t]; must not overlap any other argument.
+ *  opt->variant     ignored: the gradient kernel has one shape per dtype.
+ *  workspace        vpm_workspace_size with opt->gradient = 1.
+ * Returns VPM_OK or the first violated condition. */
+vpm_status vpm_eval_velocity_gradient(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                                      const int64_t* tgt_off, const void* x_src, const void* gamma_src,
+                                      const void* sigma_src, int64_t ld_src, const void* x_tgt,
+                                      const void* gamma_tgt, const void* sigma_tgt, int64_t ld_tgt,
+                                      const int32_t* tgt_exclude, void* u_out, void* dgamma_out,
+                                      void* grad_out, int64_t ld_out, const vpm_options* opt,
+                                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace vpm_eval_velocity_stretching (opt->gradient = 0) or
+ * vpm_eval_velocity_gradient (opt->gradient = 1) uses for this layout and kernel shape
  * (opt->variant): the work queue for n_batch > 1, the source-split partials for a small single
  * target set, else 0.  Depends on sizes only (no HIP call).  Returns 0 also for invalid
  * arguments; the evaluation then reports them. */
 size_t vpm_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                           const int64_t* tgt_off, const vpm_options* opt);
+
+/* ---------------------------------------------------------------------------------------
+ * vpm_sgs_vreman — Vreman's sub-grid eddy viscosity per particle (Sec. II.B uses Vreman's
+ * model with C_V = 0.07), with the particle's core size as the filter width:
+ *   nu_t = c_v sqrt(B_beta / (alpha_ab alpha_ab)),  alpha_ab = d u_b / d x_a,
+ *   beta = sigma^2 alpha^T alpha,  B_beta = b11 b22 - b12^2 + b11 b33 - b13^2 + b22 b33 - b23^2,
+ * and nu_t = 0 where alpha = 0.
+ *
+ *  grad [9][ld]     velocity gradients as written by vpm_eval_velocity_gradient.
+ *  sigma [ld]       filter width per particle (its core size), > 0.
+ *  c_v              model constant (0.07 in the paper), >= 0.
+ *  nu_t_out [ld]    result, m^2/s; must not overlap grad or sigma.
+ * Arithmetic is FP64 for both dtypes. */
+vpm_status vpm_sgs_vreman(int32_t dtype, int64_t n, const void* grad, const void* sigma, int64_t ld, double c_v,
+                          void* nu_t_out, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * vpm_eval_diffusion — the viscous term nu lap(Gamma_i) of Eq. 5 by particle strength
+ * exchange (PSE, Sec. II.B) with the Gaussian of Eq. 3 as the exchange kernel, within each
+ * particle set of the batch:
+ *   dGamma_i/dt = sum_{j != i} (2 nu_ij / sigma_ij^2) (V_i Gamma_j - V_j Gamma_i) zeta_{sigma_ij}(|x_i - x_j|)
+ *   sigma_ij^2 = (sigma_i^2 + sigma_j^2)/2,  nu_ij = nu + (nu_t,i + nu_t,j)/2,
+ * which conserves sum_i Gamma_i.  Pairs beyond rho_ij = 7 (FP32C) or 9.5 (FP64) are skipped:
+ * the Gaussian there is below the working precision.
+ *
+ *  off              host int64[n_batch+1] set offsets (as src_off above).
+ *  x [3][ld], gamma [3][ld], sigma [ld]: particles (sigma > 0).
+ *  vol [ld]         particle volumes V_i (> 0), m^3.
+ *  nu_t [ld]        eddy viscosity per particle (vpm_sgs_vreman), or NULL for none.
+ *  nu               kinematic viscosity, >= 0.
+ *  dgamma_out [3][ld_out]: result (accumulate = 1: added to it, e.g. to the stretching of
+ *                   vpm_eval_velocity_stretching); must not overlap any input.
+ *  workspace        vpm_diffusion_workspace_size(...) bytes (tile bounding boxes); required.
+ * Returns VPM_OK or the first violated condition. */
+vpm_status vpm_eval_diffusion(int32_t dtype, int32_t n_batch, const int64_t* off, const void* x,
+                              const void* gamma, const void* sigma, const void* vol, const void* nu_t,
+                              int64_t ld, double nu, void* dgamma_out, int64_t ld_out, int32_t accumulate,
+                              void* workspace, size_t ws_bytes, void* stream);
+size_t vpm_diffusion_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* off);
 
 /* ---------------------------------------------------------------------------------------
  * vpm_eval_segments — velocity at n_tgt points induced by n_seg straight vortex segments

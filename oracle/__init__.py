@@ -46,9 +46,10 @@ def _load():
         lib.orc_gradient.argtypes = [i64, _dp, _dp, _dp, i64, _dp, _dp, _lp, i32, _dp, i32]
         lib.orc_vreman.argtypes = [i64, _dp, _dp, dbl, _dp]
         lib.orc_pse.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, dbl, _dp, i32]
+        lib.orc_pse_at.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, dbl, i64, _lp, _dp, i32]
         for f in ("orc_weights", "orc_ghk", "orc_eval", "orc_eval_jvp", "orc_segments",
                   "orc_rk3_program", "orc_rk3_program_jvp", "orc_diagnostics", "orc_gradient",
-                  "orc_vreman", "orc_pse"):
+                  "orc_vreman", "orc_pse", "orc_pse_at"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -276,9 +277,10 @@ def vreman(J, sigma, c_v=0.07):
     return nut
 
 
-def pse(x, gam, sigma, vol, nu, nu_t=None, nthreads=0):
+def pse(x, gam, sigma, vol, nu, nu_t=None, targets=None, nthreads=0):
     """Viscous term nu lap(Gamma_i) of Eq. 5 by particle strength exchange with the Gaussian
-    of Eq. 3, for one particle set: returns dGamma/dt (3, n)."""
+    of Eq. 3, for one particle set: returns dGamma/dt (3, n), or (3, len(targets)) at the
+    listed particle indices only."""
     lib = _load()
     x = _vec(x, "x")
     g = _vec(gam, "gam")
@@ -290,6 +292,13 @@ def pse(x, gam, sigma, vol, nu, nu_t=None, nthreads=0):
     nt_, ntp = _d(None if nu_t is None else np.asarray(nu_t, dtype=np.float64).reshape(-1))
     if nt_ is not None and nt_.shape != (n,):
         raise ValueError("nu_t must have one entry per particle")
+    if targets is not None:
+        tg = np.ascontiguousarray(targets, dtype=np.int64).reshape(-1)
+        dg = np.zeros((3, tg.shape[0]))
+        _check(lib.orc_pse_at(n, x.ctypes.data_as(_dp), g.ctypes.data_as(_dp), sg.ctypes.data_as(_dp),
+                              vo.ctypes.data_as(_dp), ntp, float(nu), tg.shape[0], tg.ctypes.data_as(_lp),
+                              dg.ctypes.data_as(_dp), int(nthreads)), "pse_at")
+        return dg
     dg = np.zeros((3, n))
     _check(lib.orc_pse(n, x.ctypes.data_as(_dp), g.ctypes.data_as(_dp), sg.ctypes.data_as(_dp),
                        vo.ctypes.data_as(_dp), ntp, float(nu), dg.ctypes.data_as(_dp), int(nthreads)), "pse")

@@ -386,10 +386,12 @@ double zeta(double s, double sigma) {
     return std::exp(-0.5 * s * s / s2) / std::pow(2.0 * kPi * s2, 1.5);
 }
 
+// Targets: tgt[k] for k < nt (tgt == nullptr: every particle, nt == n); result row k of dg [3][nt].
 void eval_pse(int64_t n, const double* x, const double* G, const double* sg, const double* vol,
-              const double* nut, double nu, double* dg) {
+              const double* nut, double nu, int64_t nt, const int64_t* tgt, double* dg) {
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = 0; k < nt; ++k) {
+        const int64_t i = tgt ? tgt[k] : k;
         V3<double> xi = load3(x, n, i);
         V3<double> Gi = load3(G, n, i);
         Neumaier acc[3];
@@ -406,7 +408,7 @@ void eval_pse(int64_t n, const double* x, const double* G, const double* sg, con
             acc[1].add(w * (vol[i] * Gj.y - vol[j] * Gi.y));
             acc[2].add(w * (vol[i] * Gj.z - vol[j] * Gi.z));
         }
-        for (int c = 0; c < 3; ++c) dg[c * n + i] = acc[c].get();
+        for (int c = 0; c < 3; ++c) dg[c * nt + k] = acc[c].get();
     }
 }
 
@@ -544,7 +546,18 @@ int orc_pse(int64_t n, const double* x, const double* G, const double* sigma, co
             const double* nut, double nu, double* dg, int nthreads) {
     if (n < 0 || !x || !G || !sigma || !vol || !dg || !(nu >= 0.0)) return 1;
     set_threads<double>(nthreads);
-    eval_pse(n, x, G, sigma, vol, nut, nu, dg);
+    eval_pse(n, x, G, sigma, vol, nut, nu, n, nullptr, dg);
+    return 0;
+}
+
+// The same at the particles tgt[0..nt) only (each summed over all n particles); dg [3][nt].
+int orc_pse_at(int64_t n, const double* x, const double* G, const double* sigma, const double* vol,
+               const double* nut, double nu, int64_t nt, const int64_t* tgt, double* dg, int nthreads) {
+    if (n < 0 || nt < 0 || !x || !G || !sigma || !vol || !dg || !tgt || !(nu >= 0.0)) return 1;
+    for (int64_t k = 0; k < nt; ++k)
+        if (tgt[k] < 0 || tgt[k] >= n) return 1;
+    set_threads<double>(nthreads);
+    eval_pse(n, x, G, sigma, vol, nut, nu, nt, tgt, dg);
     return 0;
 }
 

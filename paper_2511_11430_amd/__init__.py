@@ -96,19 +96,20 @@ def _offsets(off):
     return arr
 
 
-def _opts(scheme=TRANSPOSED, sigma_rule=SIGMA_SOURCE, self_eval=0, accumulate=0, variant=0):
+def _opts(scheme=TRANSPOSED, sigma_rule=SIGMA_SOURCE, self_eval=0, accumulate=0, variant=0, gradient=0):
     o = _lib.VpmOptions()
     o.scheme, o.sigma_rule, o.self_, o.accumulate, o.variant = int(scheme), int(sigma_rule), int(self_eval), \
         int(accumulate), int(variant)
+    o.gradient = int(gradient)
     return o
 
 
-def vpm_workspace_size(dtype, src_off, tgt_off=None, self_eval=True, variant=0):
+def vpm_workspace_size(dtype, src_off, tgt_off=None, self_eval=True, variant=0, gradient=False):
     """Workspace bytes of a (batched) evaluation; see include/vpm.h."""
     lib = _lib.load()
     so = _offsets(src_off)
     to = None if tgt_off is None else _offsets(tgt_off)
-    o = _opts(self_eval=int(self_eval), variant=variant)
+    o = _opts(self_eval=int(self_eval), variant=variant, gradient=int(gradient))
     return int(lib.vpm_workspace_size(int(dtype), len(src_off) - 1, so, to, ctypes.byref(o)))
 
 
@@ -173,6 +174,128 @@ def vpm_eval_velocity_stretching(x_src, gamma_src, sigma_src, x_tgt=None, gamma_
         _ld(u_out), ctypes.byref(o), _p(workspace), ws_bytes, _stream(stream))
     _check("vpm_eval_velocity_stretching", st)
     return u_out, dgamma_out
+
+
+def vpm_eval_velocity_gradient(x_src, gamma_src, sigma_src, x_tgt=None, gamma_tgt=None, sigma_tgt=None, *,
+                               tgt_exclude=None, u_out=None, dgamma_out=None, grad_out=None, scheme=TRANSPOSED,
+                               sigma_rule=SIGMA_SOURCE, accumulate=False, src_off=None, tgt_off=None,
+                               workspace=None, stream=None):
+    """u, dGamma/dt and the velocity gradient J (shape (9, n): J[3a+b] = du_a/dx_b) at the
+    targets; arguments as vpm_eval_velocity_stretching (targets must carry Gamma).
+    Returns (u, dgamma, grad)."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x_src)
+    tdt = x_src.dtype
+    _vec(x_src, "x_src", dtype=tdt)
+    n_src = x_src.shape[1]
+    _vec(gamma_src, "gamma_src", n_src, tdt)
+    _scal(sigma_src, "sigma_src", n_src, tdt)
+    self_eval = x_tgt is None
+    if self_eval:
+        n_tgt = n_src
+    else:
+        _vec(x_tgt, "x_tgt", dtype=tdt)
+        n_tgt = x_tgt.shape[1]
+        if gamma_tgt is None:
+            raise ValueError("vpm_eval_velocity_gradient: the targets must carry gamma_tgt")
+        _vec(gamma_tgt, "gamma_tgt", n_tgt, tdt)
+        _scal(sigma_tgt, "sigma_tgt", n_tgt, tdt)
+    dev = x_src.device
+    if u_out is None:
+        u_out = torch.empty((3, n_tgt), dtype=tdt, device=dev)
+    if dgamma_out is None:
+        dgamma_out = torch.empty((3, n_tgt), dtype=tdt, device=dev)
+    if grad_out is None:
+        grad_out = torch.empty((9, n_tgt), dtype=tdt, device=dev)
+    _vec(u_out, "u_out", n_tgt, tdt)
+    _vec(dgamma_out, "dgamma_out", n_tgt, tdt)
+    if (not grad_out.is_cuda or grad_out.dim() != 2 or grad_out.shape[0] != 9 or grad_out.shape[1] != n_tgt
+            or grad_out.dtype != tdt or (n_tgt > 1 and grad_out.stride(1) != 1)):
+        raise ValueError("grad_out must be a (9, n_tgt) CUDA tensor of the particle dtype, unit stride along n")
+    if _ld(grad_out) != _ld(u_out) or _ld(dgamma_out) != _ld(u_out):
+        raise ValueError("u_out, dgamma_out and grad_out must share one leading dimension")
+    if tgt_exclude is not None:
+        _scal(tgt_exclude, "tgt_exclude", n_tgt, torch.int32)
+    if src_off is None:
+        src_off = [0, n_src]
+    if tgt_off is None and not self_eval:
+        tgt_off = [0, n_tgt]
+    n_batch = len(src_off) - 1
+    so = _offsets(src_off)
+    to = None if tgt_off is None else _offsets(tgt_off)
+    o = _opts(scheme, sigma_rule, self_eval, accumulate, 0, gradient=1)
+    ws_need = int(lib.vpm_workspace_size(dt, n_batch, so, to, ctypes.byref(o)))
+    if ws_need and workspace is None:
+        workspace = torch.empty(ws_need, dtype=torch.uint8, device=dev)
+    if workspace is not None and workspace.numel() == 0:
+        workspace = None
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    ld_src = _ld(x_src)
+    ld_tgt = 0 if self_eval else _ld(x_tgt)
+    st = lib.vpm_eval_velocity_gradient(
+        dt, n_batch, so, to, _p(x_src), _p(gamma_src), _p(sigma_src), ld_src,
+        None if self_eval else _p(x_tgt), None if self_eval else _p(gamma_tgt),
+        None if self_eval else _p(sigma_tgt), ld_tgt, _p(tgt_exclude), _p(u_out), _p(dgamma_out), _p(grad_out),
+        _ld(u_out), ctypes.byref(o), _p(workspace), ws_bytes, _stream(stream))
+    _check("vpm_eval_velocity_gradient", st)
+    return u_out, dgamma_out, grad_out
+
+
+def vpm_sgs_vreman(grad, sigma, c_v=0.07, *, nu_t_out=None, stream=None):
+    """Vreman eddy viscosity per particle from J (9, n) with filter width sigma (n,)."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(grad)
+    if not grad.is_cuda or grad.dim() != 2 or grad.shape[0] != 9:
+        raise ValueError("grad must be a CUDA tensor of shape (9, n)")
+    n = grad.shape[1]
+    _scal(sigma, "sigma", n, grad.dtype)
+    if nu_t_out is None:
+        nu_t_out = torch.empty(n, dtype=grad.dtype, device=grad.device)
+    _scal(nu_t_out, "nu_t_out", n, grad.dtype)
+    if n > 0 and not grad.is_contiguous():
+        raise ValueError("grad must be contiguous (9, n)")
+    st = lib.vpm_sgs_vreman(dt, n, _p(grad), _p(sigma), n, float(c_v), _p(nu_t_out), _stream(stream))
+    _check("vpm_sgs_vreman", st)
+    return nu_t_out
+
+
+def vpm_eval_diffusion(x, gamma, sigma, vol, nu, nu_t=None, *, dgamma_out=None, accumulate=False, off=None,
+                       workspace=None, stream=None):
+    """Viscous term of Eq. 5 by PSE within each set of ``off`` (default: one set).
+    Returns dgamma_out (3, n)."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x)
+    tdt = x.dtype
+    _vec(x, "x", dtype=tdt)
+    n = x.shape[1]
+    _vec(gamma, "gamma", n, tdt)
+    _scal(sigma, "sigma", n, tdt)
+    _scal(vol, "vol", n, tdt)
+    if nu_t is not None:
+        _scal(nu_t, "nu_t", n, tdt)
+    if dgamma_out is None:
+        if accumulate:
+            raise ValueError("accumulate needs dgamma_out")
+        dgamma_out = torch.empty((3, n), dtype=tdt, device=x.device)
+    _vec(dgamma_out, "dgamma_out", n, tdt)
+    if _ld(gamma) != _ld(x):
+        raise ValueError("x and gamma must share one leading dimension")
+    if off is None:
+        off = [0, n]
+    oo = _offsets(off)
+    nb = len(off) - 1
+    need = int(lib.vpm_diffusion_workspace_size(dt, nb, oo))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    st = lib.vpm_eval_diffusion(dt, nb, oo, _p(x), _p(gamma), _p(sigma), _p(vol), _p(nu_t), _ld(x), float(nu),
+                                _p(dgamma_out), _ld(dgamma_out), int(bool(accumulate)), _p(workspace), ws_bytes,
+                                _stream(stream))
+    _check("vpm_eval_diffusion", st)
+    return dgamma_out
 
 
 def vpm_eval_segments(a, b, gamma_seg, x_tgt, core_radius, vatistas_n=2, *, u_out=None, accumulate=False,

@@ -16,7 +16,7 @@ c_i64p = ctypes.POINTER(ctypes.c_int64)
 
 class VpmOptions(ctypes.Structure):
     _fields_ = [("scheme", c_i32), ("sigma_rule", c_i32), ("self_", c_i32), ("accumulate", c_i32),
-                ("variant", c_i32), ("reserved", c_i32 * 3)]
+                ("variant", c_i32), ("gradient", c_i32), ("reserved", c_i32 * 2)]
 
 
 # name -> (restype, argtypes), matching include/vpm.h
@@ -25,6 +25,13 @@ SIGNATURES = {
                                              c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(VpmOptions),
                                              c_vp, c_sz, c_vp]),
     "vpm_workspace_size": (c_sz, [c_i32, c_i32, c_i64p, c_i64p, ctypes.POINTER(VpmOptions)]),
+    "vpm_eval_velocity_gradient": (c_i32, [c_i32, c_i32, c_i64p, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp,
+                                           c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(VpmOptions),
+                                           c_vp, c_sz, c_vp]),
+    "vpm_sgs_vreman": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_i64, c_dbl, c_vp, c_vp]),
+    "vpm_eval_diffusion": (c_i32, [c_i32, c_i32, c_i64p, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_dbl, c_vp, c_i64,
+                                   c_i32, c_vp, c_sz, c_vp]),
+    "vpm_diffusion_workspace_size": (c_sz, [c_i32, c_i32, c_i64p]),
     "vpm_eval_segments": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_dbl, c_i32, c_i64, c_vp, c_i64,
                                   c_vp, c_i64, c_i32, c_vp]),
     "vpm_backward": (c_i32, [c_i32, c_i32, c_i64p, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64,

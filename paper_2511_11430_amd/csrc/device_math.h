@@ -141,6 +141,43 @@ __device__ __forceinline__ void core_weights3(T s2, T isig, T isig2, T Gf, T Hf,
     }
 }
 
+// Workgroup-wide bounding box (lo, hi per component) and maximum cut: a shuffle reduction in
+// each wavefront, then the wavefront results through LDS (scratch: 7 values per wavefront).
+// Ends with a barrier; every thread receives the result.
+template <typename T>
+__device__ __forceinline__ void block_box(const T (&lo)[3], const T (&hi)[3], T cut, T (&olo)[3], T (&ohi)[3],
+                                          T& ocut, T* scratch) {
+    T v[7] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], cut};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            const T o = __shfl_xor(v[c], off, 64);
+            v[c] = c < 3 ? fmin(v[c], o) : fmax(v[c], o);
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+    const int nwave = (blockDim.x + 63) >> 6;
+    __syncthreads();  // previous readers of scratch are done
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) scratch[wave * 7 + c] = v[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] = scratch[c];
+    for (int w = 1; w < nwave; ++w) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] = c < 3 ? fmin(v[c], scratch[w * 7 + c]) : fmax(v[c], scratch[w * 7 + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        olo[c] = v[c];
+        ohi[c] = v[3 + c];
+    }
+    ocut = v[6];
+}
+
 // Knuth's TwoSum: s + e == a + b exactly.
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
     s = a + b;

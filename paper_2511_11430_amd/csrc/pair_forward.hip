@@ -16,6 +16,8 @@
 //    within chunks of 128 sources and folded into (hi, lo) two-sum pairs after every chunk, so
 //    the error does not grow with N.  The per-target epilogue runs in FP64.
 //  - FP64 (VPM_F64): the same schedule with K = 1 and plain FP64 sums.
+//  - Gradient mode adds the velocity gradient du/dx (nine more FP32 sums per target) for the
+//    sub-grid model; the stretching then comes from the same sums.
 //  - Stretching is assembled per target from A and B:
 //      transposed: dGamma_i/dt = (Gamma_i x A - 3 B)/(4 pi),  B = sum Hn (Gamma_i . (Gamma_j x r)) r
 //      classical:  dGamma_i/dt = (-Gamma_i x A - 3 B)/(4 pi), B = sum Hn (r . Gamma_i) (Gamma_j x r)
@@ -50,12 +52,18 @@ __device__ __forceinline__ double opaque(double v) {
     return v;
 }
 
+// One pair: accumulate into the partial sums p[] of one target.  Layout of p:
+//   velocity:               u = p[0..2]
+//   transposed / classical: u = p[0..2], A = p[3..5], B = p[6..8]
+//   gradient:               u = p[0..2], A = p[3..5] (pairs outside the cores),
+//                           H = p[6..14] = sum Hn v r^T (row-major, v = Gamma_j x r),
+//                           A_core = p[15..17], C = p[18..20] = sum over in-core pairs of G Gamma_i x Gamma_j
 template <typename T, int MODE, bool SYM, bool CHECK, bool NEAR>
 __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, const T pw, const T qx,
                                          const T qy, const T qz, const T qw, const T xi0,
                                          const T xi1, const T xi2, const T gi0, const T gi1,
                                          const T gi2, const T cut_i, const int64_t jglob,
-                                         const int64_t ex, T* pu, T* pA, T* pB) {
+                                         const int64_t ex, T* p) {
     const T rx = xi0 - px;
     const T ry = xi1 - py;
     const T rz = xi2 - pz;
@@ -85,15 +93,25 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
         if (MODE != kModeVelocity) {
             // In-core pairs dominate A and along a filament their strengths are nearly
             // parallel to Gamma_i, where Gamma_i x (sum) would cancel in FP32.  Their term
-            // G Gamma_i x Gamma_j is formed per pair instead and added to the stretching sum
-            // through B (dGamma = (Gamma_i x A - 3B)/4pi; classical: -Gamma_i x A - 3B).
+            // G Gamma_i x Gamma_j is formed per pair instead: added to the stretching sum
+            // through B (dGamma = (Gamma_i x A - 3B)/4pi; classical: -Gamma_i x A - 3B), or
+            // kept in C (gradient mode, which also needs their A for the gradient).
             const T cx = gi1 * qz - gi2 * qy;
             const T cy = gi2 * qx - gi0 * qz;
             const T cz = gi0 * qy - gi1 * qx;
-            const T f = (MODE == kModeTransposed ? T(-1.0 / 3.0) : T(1.0 / 3.0)) * G;
-            pB[0] += f * cx;
-            pB[1] += f * cy;
-            pB[2] += f * cz;
+            if (MODE == kModeGradient) {
+                p[15] += G * qx;
+                p[16] += G * qy;
+                p[17] += G * qz;
+                p[18] += G * cx;
+                p[19] += G * cy;
+                p[20] += G * cz;
+            } else {
+                const T f = (MODE == kModeTransposed ? T(-1.0 / 3.0) : T(1.0 / 3.0)) * G;
+                p[6] += f * cx;
+                p[7] += f * cy;
+                p[8] += f * cz;
+            }
             Ga = T(0);
         } else {
             Ga = G;
@@ -108,67 +126,45 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
     const T vx = qy * rz - qz * ry;
     const T vy = qz * rx - qx * rz;
     const T vz = qx * ry - qy * rx;
-    pu[0] += G * vx;
-    pu[1] += G * vy;
-    pu[2] += G * vz;
+    p[0] += G * vx;
+    p[1] += G * vy;
+    p[2] += G * vz;
     if (MODE != kModeVelocity) {
-        pA[0] += Ga * qx;
-        pA[1] += Ga * qy;
-        pA[2] += Ga * qz;
+        p[3] += Ga * qx;
+        p[4] += Ga * qy;
+        p[5] += Ga * qz;
         if (MODE == kModeTransposed) {
             const T tau = gi0 * vx + gi1 * vy + gi2 * vz;
             const T w = Hn * tau;
-            pB[0] += w * rx;
-            pB[1] += w * ry;
-            pB[2] += w * rz;
-        } else {
+            p[6] += w * rx;
+            p[7] += w * ry;
+            p[8] += w * rz;
+        } else if (MODE == kModeClassical) {
             const T rg = rx * gi0 + ry * gi1 + rz * gi2;
             const T w = Hn * rg;
-            pB[0] += w * vx;
-            pB[1] += w * vy;
-            pB[2] += w * vz;
+            p[6] += w * vx;
+            p[7] += w * vy;
+            p[8] += w * vz;
+        } else {
+            const T hx = Hn * vx, hy = Hn * vy, hz = Hn * vz;
+            p[6] += hx * rx;
+            p[7] += hx * ry;
+            p[8] += hx * rz;
+            p[9] += hy * rx;
+            p[10] += hy * ry;
+            p[11] += hy * rz;
+            p[12] += hz * rx;
+            p[13] += hz * ry;
+            p[14] += hz * rz;
         }
     }
-}
-
-// Workgroup-wide bounding box (lo, hi per component) and maximum cut: a shuffle reduction in
-// each wavefront, then the wavefront results through LDS (scratch: 7 values per wavefront).
-// Ends with a barrier; every thread receives the result.
-template <typename T>
-__device__ __forceinline__ void block_box(const T (&lo)[3], const T (&hi)[3], T cut, T (&olo)[3], T (&ohi)[3],
-                                          T& ocut, T* scratch) {
-    T v[7] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], cut};
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-        for (int c = 0; c < 7; ++c) {
-            const T o = __shfl_xor(v[c], off, 64);
-            v[c] = c < 3 ? fmin(v[c], o) : fmax(v[c], o);
-        }
-    }
-    const int wave = threadIdx.x >> 6;
-    const int nwave = (blockDim.x + 63) >> 6;
-    __syncthreads();  // previous readers of scratch are done
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int c = 0; c < 7; ++c) scratch[wave * 7 + c] = v[c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 7; ++c) v[c] = scratch[c];
-    for (int w = 1; w < nwave; ++w) {
-#pragma unroll
-        for (int c = 0; c < 7; ++c) v[c] = c < 3 ? fmin(v[c], scratch[w * 7 + c]) : fmax(v[c], scratch[w * 7 + c]);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        olo[c] = v[c];
-        ohi[c] = v[3 + c];
-    }
-    ocut = v[6];
 }
 
 // Per-target epilogue in FP64: u = U/(4 pi) and the stretching from A and B (tot holds U, A, B).
+// Gradient mode (tot holds U, A, H, A_core, C):
+//   J = du/dx = ([A + A_core]_x - 3 H) / (4 pi)          ([w]_x y = w x y)
+//   transposed stretching J^T Gamma_i = (Gamma_i x A + C - 3 H^T Gamma_i) / (4 pi)
+//   classical stretching  J Gamma_i   = (A x Gamma_i - C - 3 H Gamma_i) / (4 pi)
 template <typename T, int MODE>
 __device__ __forceinline__ void store_target(const FwdArgs& a, int64_t t, double g0, double g1, double g2,
                                              const double* tot) {
@@ -177,7 +173,7 @@ __device__ __forceinline__ void store_target(const FwdArgs& a, int64_t t, double
     double res[6];
 #pragma unroll
     for (int c = 0; c < 3; ++c) res[c] = kInv4PiD * tot[c];
-    if (MODE != kModeVelocity) {
+    if (MODE == kModeTransposed || MODE == kModeClassical) {
         const double A0 = tot[3], A1 = tot[4], A2 = tot[5];
         double c0 = g1 * A2 - g2 * A1;
         double c1 = g2 * A0 - g0 * A2;
@@ -190,6 +186,33 @@ __device__ __forceinline__ void store_target(const FwdArgs& a, int64_t t, double
         res[3] = kInv4PiD * (c0 - 3.0 * tot[6]);
         res[4] = kInv4PiD * (c1 - 3.0 * tot[7]);
         res[5] = kInv4PiD * (c2 - 3.0 * tot[8]);
+    }
+    if (MODE == kModeGradient) {
+        const double* H = tot + 6;
+        const double gi[3] = {g0, g1, g2};
+        const double A0 = tot[3], A1 = tot[4], A2 = tot[5];
+        double c0 = g1 * A2 - g2 * A1;  // Gamma_i x A
+        double c1 = g2 * A0 - g0 * A2;
+        double c2 = g0 * A1 - g1 * A0;
+        const double sgn = a.classical ? -1.0 : 1.0;
+        double hg[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            hg[r] = a.classical ? H[3 * r] * gi[0] + H[3 * r + 1] * gi[1] + H[3 * r + 2] * gi[2]
+                                : H[r] * gi[0] + H[3 + r] * gi[1] + H[6 + r] * gi[2];
+        }
+        res[3] = kInv4PiD * (sgn * (c0 + tot[18]) - 3.0 * hg[0]);
+        res[4] = kInv4PiD * (sgn * (c1 + tot[19]) - 3.0 * hg[1]);
+        res[5] = kInv4PiD * (sgn * (c2 + tot[20]) - 3.0 * hg[2]);
+        const double At0 = tot[3] + tot[15], At1 = tot[4] + tot[16], At2 = tot[5] + tot[17];
+        const double X[9] = {0.0, -At2, At1, At2, 0.0, -At0, -At1, At0, 0.0};
+        T* __restrict__ jo = static_cast<T*>(a.grad);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const double v = kInv4PiD * (X[c] - 3.0 * H[c]);
+            T* dst = jo + c * a.ldo + t;
+            *dst = a.accumulate ? T(double(*dst) + v) : T(v);
+        }
     }
     T* __restrict__ uo = static_cast<T*>(a.u);
 #pragma unroll
@@ -210,7 +233,7 @@ __device__ __forceinline__ void store_target(const FwdArgs& a, int64_t t, double
 template <typename T, int K, int WG, int MODE, bool SYM, int U>
 struct FwdBlock {
     static constexpr bool kComp = std::is_same<T, float>::value;
-    static constexpr int kNacc = (MODE == kModeVelocity) ? 3 : 9;
+    static constexpr int kNacc = nacc_of(MODE);
     using V4 = typename SrcTile<T>::V4;
 
     // Process targets [t0, t1) (at most WG*K of them) against sources [s0, s1) of one set.
@@ -394,9 +417,7 @@ struct FwdBlock {
                 for (int k = 0; k < K; ++k) {
                     pair_fwd<T, MODE, SYM, CHECK, NEAR>(p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, xi[k][0],
                                                         xi[k][1], xi[k][2], gi[k][0], gi[k][1], gi[k][2],
-                                                        cut_i[k], j0 + jj, ex[k], &acc[k][0],
-                                                        &acc[k][kNacc > 3 ? 3 : 0],
-                                                        &acc[k][kNacc > 3 ? 6 : 0]);
+                                                        cut_i[k], j0 + jj, ex[k], &acc[k][0]);
                 }
             }
             if constexpr (kComp) fold(acc, hi, lo);
@@ -427,7 +448,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd(FwdArgs a) {
 // Adds the per-chunk FP64 partials of every target in chunk order and stores the result.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_pair_fwd_finish(FwdArgs a) {
-    constexpr int kNacc = (MODE == kModeVelocity) ? 3 : 9;
+    constexpr int kNacc = nacc_of(MODE);
     const int64_t t = a.tgt_begin + int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (t >= a.tgt_end) return;
     double tot[kNacc];
@@ -538,6 +559,14 @@ const FwdVariant kF32Variants[kNumF32Variants] = {
 
 hipError_t launch_pair_fwd(int dtype, int variant, int mode, bool sym, const FwdArgs& a,
                            const BatchQueue* bq, int grid, hipStream_t st) {
+    if (mode == kModeGradient) {
+        if (dtype == kDtypeF64)
+            return sym ? launch_one<double, 1, 256, kModeGradient, true, 2>(a, bq, grid, st)
+                       : launch_one<double, 1, 256, kModeGradient, false, 2>(a, bq, grid, st);
+        if (variant != kGradientVariant) return hipErrorInvalidValue;
+        return sym ? launch_one<float, 1, 256, kModeGradient, true, 2>(a, bq, grid, st)
+                   : launch_one<float, 1, 256, kModeGradient, false, 2>(a, bq, grid, st);
+    }
     if (dtype == kDtypeF64) return dispatch_mode<double, 1, 256, 2>(mode, sym, a, bq, grid, st);
     switch (variant) {
 #define X(i, k, wg, u) case i: return dispatch_mode<float, k, wg, u>(mode, sym, a, bq, grid, st);
@@ -548,6 +577,14 @@ hipError_t launch_pair_fwd(int dtype, int variant, int mode, bool sym, const Fwd
 }
 
 int pair_fwd_occupancy(int dtype, int variant, int mode, bool sym, bool batched) {
+    if (mode == kModeGradient) {
+        if (dtype == kDtypeF64)
+            return sym ? occupancy_one<double, 1, 256, kModeGradient, true, 2>(batched)
+                       : occupancy_one<double, 1, 256, kModeGradient, false, 2>(batched);
+        if (variant != kGradientVariant) return 0;
+        return sym ? occupancy_one<float, 1, 256, kModeGradient, true, 2>(batched)
+                   : occupancy_one<float, 1, 256, kModeGradient, false, 2>(batched);
+    }
     if (dtype == kDtypeF64) return occupancy_mode<double, 1, 256, 2>(mode, sym, batched);
     switch (variant) {
 #define X(i, k, wg, u) case i: return occupancy_mode<float, k, wg, u>(mode, sym, batched);

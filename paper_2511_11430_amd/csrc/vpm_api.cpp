@@ -56,7 +56,8 @@ vpm_status check_options(const vpm_options& o) {
     if (o.self != 0 && o.self != 1) return VPM_ERR_ENUM;
     if (o.accumulate != 0 && o.accumulate != 1) return VPM_ERR_ENUM;
     if (o.variant < 0 || o.variant > vpm::kNumF32Variants) return VPM_ERR_ENUM;
-    for (int i = 0; i < 3; ++i)
+    if (o.gradient != 0 && o.gradient != 1) return VPM_ERR_ENUM;
+    for (int i = 0; i < 2; ++i)
         if (o.reserved[i] != 0) return VPM_ERR_ENUM;
     return VPM_OK;
 }
@@ -167,8 +168,10 @@ int plan_bucket(int64_t n) {
     return b;
 }
 
-// 0-based variant for an FP32C launch when the caller leaves opt->variant at 0.
+// 0-based variant for an FP32C launch when the caller leaves opt->variant at 0.  The gradient
+// mode has a single shape.
 int choose_variant(const vpm_options& o, bool batched, int64_t n_tgt) {
+    if (o.gradient) return vpm::kGradientVariant;
     if (o.variant > 0) return o.variant - 1;
     std::lock_guard<std::mutex> lock(g_mutex);
     const int v = g_plan[batched ? 1 : 0][plan_bucket(n_tgt)];
@@ -176,6 +179,7 @@ int choose_variant(const vpm_options& o, bool batched, int64_t n_tgt) {
 }
 
 int fwd_mode(const vpm_options& o, bool stretch) {
+    if (o.gradient) return vpm::kModeGradient;
     if (!stretch) return vpm::kModeVelocity;
     return o.scheme == VPM_STRETCH_CLASSICAL ? vpm::kModeClassical : vpm::kModeTransposed;
 }
@@ -191,13 +195,12 @@ int64_t targets_per_block(int32_t dtype, int variant) {
 constexpr int64_t kSplitBelow = 1024;
 constexpr int64_t kSplitGoal = 2048;
 constexpr int64_t kMinChunk = 2048;
-constexpr int kMaxAcc = 9;
 
 struct SplitPlan {
     int64_t nchunk = 1, chunk = 0;
     size_t bytes = 0;
 };
-SplitPlan split_plan(int32_t dtype, int variant, int64_t n_src, int64_t n_tgt) {
+SplitPlan split_plan(int32_t dtype, int variant, int nacc, int64_t n_src, int64_t n_tgt) {
     SplitPlan p;
     p.chunk = n_src;
     const int64_t per_block = targets_per_block(dtype, variant);
@@ -216,7 +219,7 @@ SplitPlan split_plan(int32_t dtype, int variant, int64_t n_src, int64_t n_tgt) {
         p.chunk = n_src;
         return p;
     }
-    p.bytes = align_up(size_t(p.nchunk) * kMaxAcc * size_t(n_tgt) * sizeof(double));
+    p.bytes = align_up(size_t(p.nchunk) * size_t(nacc) * size_t(n_tgt) * sizeof(double));
     return p;
 }
 
@@ -279,22 +282,25 @@ size_t vpm_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off
     if (check_options(o) != VPM_OK) return 0;
     if (n_batch == 1) {
         const int variant = choose_variant(o, false, tgt_off[1]);
-        return split_plan(dtype, variant, src_off[1], tgt_off[1]).bytes;
+        const int nacc = o.gradient ? vpm::nacc_of(vpm::kModeGradient) : vpm::nacc_of(vpm::kModeTransposed);
+        return split_plan(dtype, variant, nacc, src_off[1], tgt_off[1]).bytes;
     }
     return queue_layout(n_batch, tgt_off, kMinTargetsPerBlock).total;
 }
 
-vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const int64_t* src_off,
-                                        const int64_t* tgt_off, const void* x_src,
-                                        const void* gamma_src, const void* sigma_src,
-                                        int64_t ld_src, const void* x_tgt, const void* gamma_tgt,
-                                        const void* sigma_tgt, int64_t ld_tgt,
-                                        const int32_t* tgt_exclude, void* u_out, void* dgamma_out,
-                                        int64_t ld_out, const vpm_options* opt, void* workspace,
-                                        size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Shared body of vpm_eval_velocity_stretching (grad_out == nullptr, o.gradient == 0) and
+// vpm_eval_velocity_gradient (o.gradient == 1).
+vpm_status eval_impl(int32_t dtype, int32_t n_batch, const int64_t* src_off, const int64_t* tgt_off,
+                     const void* x_src, const void* gamma_src, const void* sigma_src, int64_t ld_src,
+                     const void* x_tgt, const void* gamma_tgt, const void* sigma_tgt, int64_t ld_tgt,
+                     const int32_t* tgt_exclude, void* u_out, void* dgamma_out, void* grad_out, int64_t ld_out,
+                     vpm_options o, void* workspace, size_t ws_bytes, void* stream) {
     if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
     if (n_batch < 1) return VPM_ERR_SIZE;
-    vpm_options o = opt ? *opt : default_options();
     vpm_status s = check_options(o);
     if (s != VPM_OK) return s;
     if (!src_off) return VPM_ERR_NULL;
@@ -328,24 +334,26 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
     if (n_tgt > 0 && (!x_tgt || !u_out)) return VPM_ERR_NULL;
     const bool stretch = dgamma_out != nullptr;
     if (stretch && !gamma_tgt) return VPM_ERR_NULL;
+    if (o.gradient && n_tgt > 0 && (!stretch || !grad_out)) return VPM_ERR_NULL;
     const bool sym = o.sigma_rule == VPM_SIGMA_SYMMETRIC;
     if (sym && n_tgt > 0 && !sigma_tgt) return VPM_ERR_NULL;
 
     const size_t es = elem_size(dtype);
     const Range ru = span(u_out, 3, ld_out, n_tgt, es);
     const Range rd = span(dgamma_out, 3, ld_out, n_tgt, es);
+    const Range rj = span(o.gradient ? grad_out : nullptr, 9, ld_out, n_tgt, es);
     const Range ins[7] = {span(x_src, 3, ld_src, n_src, es),   span(gamma_src, 3, ld_src, n_src, es),
                           span(sigma_src, 1, ld_src, n_src, es), span(x_tgt, 3, ld_tgt, n_tgt, es),
                           span(gamma_tgt, 3, ld_tgt, n_tgt, es), span(sigma_tgt, 1, ld_tgt, n_tgt, es),
                           span(tgt_exclude, 1, n_tgt, n_tgt, sizeof(int32_t))};
     for (const Range& r : ins)
-        if (overlap(ru, r) || overlap(rd, r)) return VPM_ERR_ALIAS;
-    if (overlap(ru, rd)) return VPM_ERR_ALIAS;
+        if (overlap(ru, r) || overlap(rd, r) || overlap(rj, r)) return VPM_ERR_ALIAS;
+    if (overlap(ru, rd) || overlap(ru, rj) || overlap(rd, rj)) return VPM_ERR_ALIAS;
 
     const int variant = choose_variant(o, n_batch > 1, n_tgt);
     if (workspace && ws_bytes > 0) {
         const Range rw = span(workspace, 1, int64_t(ws_bytes), int64_t(ws_bytes), 1);
-        if (overlap(rw, ru) || overlap(rw, rd)) return VPM_ERR_ALIAS;
+        if (overlap(rw, ru) || overlap(rw, rd) || overlap(rw, rj)) return VPM_ERR_ALIAS;
         for (const Range& r : ins)
             if (overlap(rw, r)) return VPM_ERR_ALIAS;
     }
@@ -371,6 +379,7 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
     a.excl = tgt_exclude;
     a.u = u_out;
     a.dg = dgamma_out;
+    a.grad = o.gradient ? grad_out : nullptr;
     a.ldo = ld_out;
     a.src_begin = 0;
     a.src_end = n_src;
@@ -378,6 +387,7 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
     a.tgt_end = n_tgt;
     a.self = o.self;
     a.accumulate = o.accumulate;
+    a.classical = o.scheme == VPM_STRETCH_CLASSICAL;
     a.part = nullptr;
     a.chunk = n_src;
     a.nchunk = 1;
@@ -385,7 +395,7 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
     const int64_t per_block = targets_per_block(dtype, variant);
 
     if (n_batch == 1) {
-        const SplitPlan sp = split_plan(dtype, variant, n_src, n_tgt);
+        const SplitPlan sp = split_plan(dtype, variant, vpm::nacc_of(mode), n_src, n_tgt);
         if (sp.nchunk > 1 && workspace && ws_bytes >= sp.bytes) {
             a.part = static_cast<double*>(workspace);
             a.chunk = sp.chunk;
@@ -437,6 +447,99 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
     q.tgt_off = reinterpret_cast<const int64_t*>(ws + L.off_tgt);
     q.n_items = int(items.size());
     return hip_status(vpm::launch_pair_fwd(dtype, variant, mode, sym, a, &q, int(grid), st));
+}
+
+}  // namespace
+
+extern "C" {
+
+vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                                        const int64_t* tgt_off, const void* x_src,
+                                        const void* gamma_src, const void* sigma_src,
+                                        int64_t ld_src, const void* x_tgt, const void* gamma_tgt,
+                                        const void* sigma_tgt, int64_t ld_tgt,
+                                        const int32_t* tgt_exclude, void* u_out, void* dgamma_out,
+                                        int64_t ld_out, const vpm_options* opt, void* workspace,
+                                        size_t ws_bytes, void* stream) {
+    vpm_options o = opt ? *opt : default_options();
+    if (o.gradient != 0) return VPM_ERR_ENUM;
+    return eval_impl(dtype, n_batch, src_off, tgt_off, x_src, gamma_src, sigma_src, ld_src, x_tgt, gamma_tgt,
+                     sigma_tgt, ld_tgt, tgt_exclude, u_out, dgamma_out, nullptr, ld_out, o, workspace, ws_bytes,
+                     stream);
+}
+
+vpm_status vpm_eval_velocity_gradient(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                                      const int64_t* tgt_off, const void* x_src, const void* gamma_src,
+                                      const void* sigma_src, int64_t ld_src, const void* x_tgt,
+                                      const void* gamma_tgt, const void* sigma_tgt, int64_t ld_tgt,
+                                      const int32_t* tgt_exclude, void* u_out, void* dgamma_out,
+                                      void* grad_out, int64_t ld_out, const vpm_options* opt,
+                                      void* workspace, size_t ws_bytes, void* stream) {
+    vpm_options o = opt ? *opt : default_options();
+    if (o.gradient != 0 && o.gradient != 1) return VPM_ERR_ENUM;
+    o.gradient = 1;
+    const vpm_status s = check_options(o);  // the caller's fields, before the shape is fixed
+    if (s != VPM_OK) return s;
+    o.variant = 0;
+    return eval_impl(dtype, n_batch, src_off, tgt_off, x_src, gamma_src, sigma_src, ld_src, x_tgt, gamma_tgt,
+                     sigma_tgt, ld_tgt, tgt_exclude, u_out, dgamma_out, grad_out, ld_out, o, workspace, ws_bytes,
+                     stream);
+}
+
+vpm_status vpm_sgs_vreman(int32_t dtype, int64_t n, const void* grad, const void* sigma, int64_t ld, double c_v,
+                          void* nu_t_out, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n < 0 || ld < n || n > INT32_MAX) return VPM_ERR_SIZE;
+    if (!(c_v >= 0.0) || c_v > 1e30) return VPM_ERR_SIZE;
+    if (n == 0) return VPM_OK;
+    if (!grad || !sigma || !nu_t_out) return VPM_ERR_NULL;
+    const size_t es = elem_size(dtype);
+    const Range ro = span(nu_t_out, 1, ld, n, es);
+    if (overlap(ro, span(grad, 9, ld, n, es)) || overlap(ro, span(sigma, 1, ld, n, es))) return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_vreman(dtype, n, grad, ld, sigma, c_v, nu_t_out, static_cast<hipStream_t>(stream)));
+}
+
+size_t vpm_diffusion_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* off) {
+    if (!dtype_ok(dtype) || n_batch < 1 || check_offsets(n_batch, off) != VPM_OK) return 0;
+    int64_t tiles = 0;
+    for (int32_t b = 0; b < n_batch; ++b) tiles += vpm::pse_tiles(off[b + 1] - off[b]);
+    return align_up(size_t(tiles > 0 ? tiles : 1) * 8 * elem_size(dtype));
+}
+
+vpm_status vpm_eval_diffusion(int32_t dtype, int32_t n_batch, const int64_t* off, const void* x,
+                              const void* gamma, const void* sigma, const void* vol, const void* nu_t,
+                              int64_t ld, double nu, void* dgamma_out, int64_t ld_out, int32_t accumulate,
+                              void* workspace, size_t ws_bytes, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n_batch < 1) return VPM_ERR_SIZE;
+    vpm_status s = check_offsets(n_batch, off);
+    if (s != VPM_OK) return s;
+    const int64_t n = off[n_batch];
+    if (n > INT32_MAX || ld < n || ld_out < n) return VPM_ERR_SIZE;
+    if (!(nu >= 0.0) || nu > 1e30) return VPM_ERR_SIZE;
+    if (accumulate != 0 && accumulate != 1) return VPM_ERR_ENUM;
+    if (n == 0) return VPM_OK;
+    if (!x || !gamma || !sigma || !vol || !dgamma_out) return VPM_ERR_NULL;
+    const size_t need = vpm_diffusion_workspace_size(dtype, n_batch, off);
+    if (!workspace || ws_bytes < need) return VPM_ERR_WORKSPACE;
+    const size_t es = elem_size(dtype);
+    const Range rd = span(dgamma_out, 3, ld_out, n, es);
+    const Range rw = span(workspace, 1, int64_t(ws_bytes), int64_t(ws_bytes), 1);
+    const Range ins[5] = {span(x, 3, ld, n, es), span(gamma, 3, ld, n, es), span(sigma, 1, ld, n, es),
+                          span(vol, 1, ld, n, es), span(nu_t, 1, ld, n, es)};
+    for (const Range& r : ins)
+        if (overlap(rd, r) || overlap(rw, r)) return VPM_ERR_ALIAS;
+    if (overlap(rd, rw)) return VPM_ERR_ALIAS;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned char* boxes = static_cast<unsigned char*>(workspace);
+    for (int32_t b = 0; b < n_batch; ++b) {
+        if (off[b + 1] == off[b]) continue;
+        hipError_t e = vpm::launch_pse(dtype, off[b], off[b + 1], x, gamma, sigma, vol, nu_t, ld, nu, dgamma_out,
+                                       ld_out, accumulate, boxes, st);
+        if (e != hipSuccess) return VPM_ERR_HIP;
+        boxes += size_t(vpm::pse_tiles(off[b + 1] - off[b])) * 8 * es;
+    }
+    return VPM_OK;
 }
 
 vpm_status vpm_eval_segments(int32_t dtype, int64_t n_seg, const void* a, const void* b,

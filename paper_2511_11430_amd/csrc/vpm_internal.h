@@ -9,7 +9,11 @@
 namespace vpm {
 
 enum { kDtypeF64 = 0, kDtypeF32C = 1 };
-enum { kModeTransposed = 0, kModeClassical = 1, kModeVelocity = 2 };
+enum { kModeTransposed = 0, kModeClassical = 1, kModeVelocity = 2, kModeGradient = 3 };
+
+// Per-target accumulator count of each mode (see pair_forward.hip for the layouts).
+constexpr int nacc_of(int mode) { return mode == kModeVelocity ? 3 : (mode == kModeGradient ? 21 : 9); }
+constexpr int kMaxAcc = 21;
 
 // Arguments of the particle-pair forward kernels.  Pointers are device pointers of the
 // kernel's element type; 3-vectors are [3][ld].
@@ -25,11 +29,13 @@ struct FwdArgs {
     const int32_t* excl;  // per-target source index to skip (or nullptr)
     void* u;
     void* dg;
+    void* grad;         // gradient mode: du_a/dx_b at [3a + b][ldo]
     int64_t ldo;
     int64_t src_begin, src_end;  // single-set launch
     int64_t tgt_begin, tgt_end;
     int32_t self;
     int32_t accumulate;
+    int32_t classical;  // gradient mode: stretching output in the classical scheme
     // Source split (one set only): nchunk > 1 launches a 2-D grid whose y index picks a chunk of
     // `chunk` sources; each workgroup writes FP64 partial sums part[(ch * nacc + c) * n_tgt + t]
     // and launch_pair_fwd then runs the finishing kernel that adds the chunks in order.
@@ -54,10 +60,13 @@ struct FwdVariant {
 };
 constexpr int kNumF32Variants = 8;
 extern const FwdVariant kF32Variants[kNumF32Variants];
+// The gradient mode has one FP32C shape: kF32Variants[kGradientVariant] = (1, 256, 2).
+constexpr int kGradientVariant = 1;
 constexpr int kF64TargetsPerBlock = 256;
 
-// variant: 0-based index into kF32Variants (ignored for FP64).  bq == nullptr: one set,
-// grid = number of target blocks; otherwise persistent grid over bq.
+// variant: 0-based index into kF32Variants (ignored for FP64; must be kGradientVariant in the
+// gradient mode).  bq == nullptr: one set, grid = number of target blocks; otherwise
+// persistent grid over bq.
 hipError_t launch_pair_fwd(int dtype, int variant, int mode, bool sym, const FwdArgs& a,
                            const BatchQueue* bq, int grid, hipStream_t st);
 int pair_fwd_occupancy(int dtype, int variant, int mode, bool sym, bool batched);
@@ -106,6 +115,16 @@ struct BwdArgs {
 };
 hipError_t launch_backward(int dtype, bool role_a, bool role_b, bool stretch, bool sym,
                            const BwdArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------- viscous terms
+// PSE diffusion of the particles [begin, end) of one set; boxes = workspace for pse_tiles(n)
+// tile boxes of 8 values each (element type of dtype).
+hipError_t launch_pse(int dtype, int64_t begin, int64_t end, const void* x, const void* g, const void* sg,
+                      const void* vol, const void* nut, int64_t ld, double nu, void* dg, int64_t ldo,
+                      int accumulate, void* boxes, hipStream_t st);
+int64_t pse_tiles(int64_t n);
+hipError_t launch_vreman(int dtype, int64_t n, const void* J, int64_t ld, const void* sg, double cv, void* nut,
+                         hipStream_t st);
 
 // ---------------------------------------------------------------- RK3 and diagnostics
 hipError_t launch_rk3_stage(int dtype, int state_dtype, int stage, int64_t n, double dt, void* x, void* g,

@@ -30,6 +30,24 @@ DPSI_DEG = 5.0                               # azimuth step (Sec. III.D recommen
 DT = math.radians(DPSI_DEG) / OMEGA          # s
 
 
+# Viscous term (Sec. II.B): kinematic viscosity of air at sea level (the standard atmosphere
+# behind a = 340.3 m/s), Vreman constant C_V = 0.07 as in the paper.
+NU_AIR = 1.46e-5                              # m^2/s
+C_V = 0.07
+
+
+def particle_volume(sigma):
+    """Particle volumes for the diffusion term: the paper takes sigma as the largest distance
+    to the neighbouring particles, so each particle stands for about a cube of side sigma."""
+    return np.asarray(sigma, dtype=np.float64) ** 3
+
+
+def eddy_viscosity_field(n, seed, scale=1e-4):
+    """Seeded synthetic per-particle eddy viscosity nu_t ~ U(0, scale) (m^2/s) for diffusion
+    checks that must not depend on a computed gradient."""
+    return _rng(90, seed).uniform(0.0, scale, n)
+
+
 def to_f32(a):
     """Round float64 values once to float32 and return them promoted back to float64."""
     return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)

@@ -185,3 +185,72 @@ def test_validate_inputs_validation():
     assert v(F32C, 10, P(0), P(1), None, 10, P(3), P(4), need, None) == NULL
     assert v(F32C, 10, P(0), P(1), P(2), 10, P(3), P(4), 8, None) == WORKSPACE
     assert v(F32C, 10, P(0), P(1), P(2), 10, P(0), P(4), need, None) == ALIAS
+
+
+def gvs(dtype=F32C, n_batch=1, so=None, to=None, xs=P(0), gs=P(1), ss=P(2), lds=100, xt=P(3), gt=P(4), st=P(5),
+        ldt=50, ex=None, u=P(6), dg=P(7), J=P(8), ldo=50, o=None, ws=None, wsb=0):
+    lib = _lib.load()
+    so = off(0, 100) if so is None else so
+    to = off(0, 50) if to is None else to
+    o = opts() if o is None else o
+    return lib.vpm_eval_velocity_gradient(dtype, n_batch, so, to, xs, gs, ss, lds, xt, gt, st, ldt, ex, u, dg, J,
+                                          ldo, ctypes.byref(o), ws, wsb, None)
+
+
+def test_gradient_validation_paths():
+    assert evs(o=opts(gradient=1)) == ENUM         # the stretching entry point has no gradient output
+    assert gvs(dtype=5) == DTYPE
+    assert gvs(J=None) == NULL
+    assert gvs(dg=None) == NULL                     # the gradient call returns the stretching too
+    assert gvs(gt=None) == NULL
+    assert gvs(J=P(0)) == ALIAS                     # gradient on an input
+    assert gvs(J=P(6)) == ALIAS                     # gradient on the velocity output
+    assert gvs(o=opts(gradient=2)) == ENUM
+    assert gvs(o=opts(variant=9)) == ENUM
+    assert gvs(ldo=10) == SIZE
+    assert gvs(to=off(0, 0), ldt=0) == OK
+    lib = _lib.load()
+    # small single sets split their sources: the gradient's partials need 21 sums per target
+    o0, o1 = opts(), opts(gradient=1)
+    a = lib.vpm_workspace_size(F32C, 1, off(0, 1 << 20), off(0, 64), ctypes.byref(o0))
+    b = lib.vpm_workspace_size(F32C, 1, off(0, 1 << 20), off(0, 64), ctypes.byref(o1))
+    assert a > 0 and b > a
+
+
+def test_vreman_validation():
+    lib = _lib.load()
+    f = lib.vpm_sgs_vreman
+    assert f(3, 10, P(0), P(1), 10, 0.07, P(2), None) == DTYPE
+    assert f(F32C, -1, P(0), P(1), 10, 0.07, P(2), None) == SIZE
+    assert f(F32C, 10, P(0), P(1), 9, 0.07, P(2), None) == SIZE
+    assert f(F32C, 10, P(0), P(1), 10, -0.1, P(2), None) == SIZE
+    assert f(F32C, 10, None, P(1), 10, 0.07, P(2), None) == NULL
+    assert f(F32C, 10, P(0), P(1), 10, 0.07, P(0), None) == ALIAS
+    assert f(F32C, 0, None, None, 0, 0.07, None, None) == OK
+
+
+def test_diffusion_validation():
+    lib = _lib.load()
+    f = lib.vpm_eval_diffusion
+    ws = lib.vpm_diffusion_workspace_size(F32C, 1, off(0, 1000))
+    assert ws >= 4 * 8 * 4
+    assert lib.vpm_diffusion_workspace_size(F64, 2, off(0, 1000, 1300)) >= (4 + 2) * 8 * 8
+    assert lib.vpm_diffusion_workspace_size(F32C, 1, off(3, 10)) == 0
+
+    def call(dtype=F32C, nb=1, o=None, x=P(0), g=P(1), s=P(2), v=P(3), nut=None, ld=1000, nu=1.5e-5, dg=P(5),
+             ldo=1000, acc=0, w=P(6), wsb=ws):
+        o = off(0, 1000) if o is None else o
+        return f(dtype, nb, o, x, g, s, v, nut, ld, nu, dg, ldo, acc, w, wsb, None)
+
+    assert call(dtype=4) == DTYPE
+    assert call(nb=0) == SIZE
+    assert call(o=off(1, 1000)) == OFFSETS
+    assert call(ld=999) == SIZE
+    assert call(nu=-1.0) == SIZE
+    assert call(acc=2) == ENUM
+    assert call(v=None) == NULL
+    assert call(w=None) == WORKSPACE
+    assert call(wsb=ws - 1) == WORKSPACE
+    assert call(dg=P(0)) == ALIAS
+    assert call(w=P(1)) == ALIAS
+    assert call(o=off(0, 0), ld=0, ldo=0) == OK

@@ -196,3 +196,12 @@ def test_pse_uniform_field_is_still():
     g = np.outer([0.3, -0.2, 0.5], vol)
     dg = O.pse(x, g, s, vol, 1e-3)
     assert np.abs(dg).max() <= 1e-15 * np.abs(g).max() * 1e-3 / s.min() ** 2
+
+
+def test_pse_at_listed_targets_matches_full():
+    x, g, s = _cloud(120, 12, spread=0.05)
+    vol = s ** 3
+    idx = np.array([0, 7, 119, 7])
+    full = O.pse(x, g, s, vol, 1e-5)
+    part = O.pse(x, g, s, vol, 1e-5, targets=idx)
+    assert np.array_equal(part, full[:, idx])
