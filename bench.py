@@ -31,7 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
-FLOP_PER_PAIR_VS = 45               # velocity + transposed stretching, point-vortex branch (DESIGN.md)
+FLOP_PER_PAIR_VS = 45               # velocity + transposed stretching, point-vortex branch
+# gradient mode, point-vortex branch: r 3, s^2 5, rsqrt 1, s^-3 and s^-5 3, v = Gamma_j x r 9,
+# u += G v 6, A += G Gamma_j 6, Hn v 3, H += (Hn v) r^T 18
+FLOP_PER_PAIR_GRAD = 54
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pair_fwd_f32c_forward_flight_1M.json")
 
 
@@ -66,7 +69,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="skip the FP64, adjoint and batching legs")
+    ap.add_argument("--quick", action="store_true", help="skip the FP64, viscous, adjoint and batching legs")
     ap.add_argument("--n", type=int, default=1 << 20, help="particles (default: the full 1,048,576)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates rocprofv3 FETCH/WRITE_SIZE)")
@@ -228,6 +231,43 @@ def main():
                           "rel_l2_u": rel(U64[:, idx], uo), "rel_l2_dgamma": rel(D64[:, idx], do),
                           "gate": 1e-12}
         del x64, g64, s64, u64, d64
+
+        # ------------------------------------------------------------------ viscous term (Eq. 5)
+        # gradient-mode pair kernel (u, stretching and du/dx in one pass), Vreman eddy
+        # viscosity, PSE diffusion with it, on the same 1M wake (FP32C)
+        x.copy_(x0)
+        g.copy_(g0)
+        Jv = torch.empty((9, N), dtype=torch.float32, device=dev)
+        nut = torch.empty(N, dtype=torch.float32, device=dev)
+        vol = f32(W.particle_volume(c["sigma"]))
+        dv = torch.empty_like(x)
+        pse_ws = torch.empty(vpm._lib.load().vpm_diffusion_workspace_size(vpm.F32C, 1, vpm._offsets([0, N])),
+                             dtype=torch.uint8, device=dev)
+
+        def timed_once(fn, reps=1):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps
+
+        grad_ms = timed_once(lambda: vpm.vpm_eval_velocity_gradient(x, g, s, u_out=u, dgamma_out=dg, grad_out=Jv))
+        vre_ms = timed_once(lambda: vpm.vpm_sgs_vreman(Jv, s, W.C_V, nu_t_out=nut), reps=5)
+        pse_ms = timed_once(lambda: vpm.vpm_eval_diffusion(x, g, s, vol, W.NU_AIR, nut, dgamma_out=dv,
+                                                          workspace=pse_ws), reps=3)
+        result["viscous"] = {
+            "workload": c["name"], "nu": W.NU_AIR, "c_v": W.C_V, "volume": "sigma^3",
+            "gradient_kernel_ms": round(grad_ms, 3), "stretching_kernel_ms": round(k_ms, 3),
+            "gradient_over_stretching": round(grad_ms / k_ms, 3),
+            "gradient_tflops": round(FLOP_PER_PAIR_GRAD * pairs / (grad_ms * 1e-3) / 1e12, 2),
+            "flop_per_pair_gradient": FLOP_PER_PAIR_GRAD,
+            "vreman_ms": round(vre_ms, 4), "pse_ms": round(pse_ms, 3),
+            "rhs_with_viscous_ms": round(grad_ms + vre_ms + pse_ms, 3)}
+        del Jv, nut, vol, dv, pse_ws
 
         # ------------------------------------------------------------------ adjoint / forward
         c4 = W.config4()

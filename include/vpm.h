@@ -184,13 +184,17 @@ vpm_status vpm_sgs_vreman(int32_t dtype, int64_t n, const void* grad, const void
  *  nu               kinematic viscosity, >= 0.
  *  dgamma_out [3][ld_out]: result (accumulate = 1: added to it, e.g. to the stretching of
  *                   vpm_eval_velocity_stretching); must not overlap any input.
- *  workspace        vpm_diffusion_workspace_size(...) bytes (tile bounding boxes); required.
+ *  workspace        vpm_diffusion_workspace_size(...) bytes, required: each set is put in
+ *                   Morton order there (sort keys, packed particle records and bounding boxes,
+ *                   about 56 B per particle of the largest set in FP32C, 104 B in FP64), so the
+ *                   cost follows the number of near pairs whatever order the particles come in.
+ *                   Results are written to the particles' own indices.
  * Returns VPM_OK or the first violated condition. */
 vpm_status vpm_eval_diffusion(int32_t dtype, int32_t n_batch, const int64_t* off, const void* x,
                               const void* gamma, const void* sigma, const void* vol, const void* nu_t,
                               int64_t ld, double nu, void* dgamma_out, int64_t ld_out, int32_t accumulate,
                               void* workspace, size_t ws_bytes, void* stream);
-size_t vpm_diffusion_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* off);
+size_t vpm_diffusion_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* off);  /* 0 if invalid */
 
 /* ---------------------------------------------------------------------------------------
  * vpm_eval_segments — velocity at n_tgt points induced by n_seg straight vortex segments

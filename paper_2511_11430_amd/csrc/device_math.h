@@ -141,6 +141,39 @@ __device__ __forceinline__ void core_weights3(T s2, T isig, T isig2, T Gf, T Hf,
     }
 }
 
+// Wavefront-wide bounding box and maximum cut (shuffle reduction only; every lane receives
+// the result).
+template <typename T>
+__device__ __forceinline__ void wave_box(const T (&lo)[3], const T (&hi)[3], T cut, T (&olo)[3], T (&ohi)[3],
+                                         T& ocut) {
+    T v[7] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], cut};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            const T o = __shfl_xor(v[c], off, 64);
+            v[c] = c < 3 ? fmin(v[c], o) : fmax(v[c], o);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        olo[c] = v[c];
+        ohi[c] = v[3 + c];
+    }
+    ocut = v[6];
+}
+
+// A value known to be equal in every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+    const unsigned long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffull));
+    const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+    return __longlong_as_double((static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo));
+}
+
 // Workgroup-wide bounding box (lo, hi per component) and maximum cut: a shuffle reduction in
 // each wavefront, then the wavefront results through LDS (scratch: 7 values per wavefront).
 // Ends with a barrier; every thread receives the result.

@@ -501,9 +501,10 @@ vpm_status vpm_sgs_vreman(int32_t dtype, int64_t n, const void* grad, const void
 
 size_t vpm_diffusion_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* off) {
     if (!dtype_ok(dtype) || n_batch < 1 || check_offsets(n_batch, off) != VPM_OK) return 0;
-    int64_t tiles = 0;
-    for (int32_t b = 0; b < n_batch; ++b) tiles += vpm::pse_tiles(off[b + 1] - off[b]);
-    return align_up(size_t(tiles > 0 ? tiles : 1) * 8 * elem_size(dtype));
+    size_t most = 0;
+    for (int32_t b = 0; b < n_batch; ++b)
+        if (off[b + 1] > off[b]) most = std::max(most, vpm::pse_workspace(off[b + 1] - off[b], dtype));
+    return most;
 }
 
 vpm_status vpm_eval_diffusion(int32_t dtype, int32_t n_batch, const int64_t* off, const void* x,
@@ -521,6 +522,7 @@ vpm_status vpm_eval_diffusion(int32_t dtype, int32_t n_batch, const int64_t* off
     if (n == 0) return VPM_OK;
     if (!x || !gamma || !sigma || !vol || !dgamma_out) return VPM_ERR_NULL;
     const size_t need = vpm_diffusion_workspace_size(dtype, n_batch, off);
+    if (need == 0) return VPM_ERR_SIZE;
     if (!workspace || ws_bytes < need) return VPM_ERR_WORKSPACE;
     const size_t es = elem_size(dtype);
     const Range rd = span(dgamma_out, 3, ld_out, n, es);
@@ -531,13 +533,12 @@ vpm_status vpm_eval_diffusion(int32_t dtype, int32_t n_batch, const int64_t* off
         if (overlap(rd, r) || overlap(rw, r)) return VPM_ERR_ALIAS;
     if (overlap(rd, rw)) return VPM_ERR_ALIAS;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    unsigned char* boxes = static_cast<unsigned char*>(workspace);
+    // the sets run one after the other on the stream and reuse the workspace
     for (int32_t b = 0; b < n_batch; ++b) {
         if (off[b + 1] == off[b]) continue;
         hipError_t e = vpm::launch_pse(dtype, off[b], off[b + 1], x, gamma, sigma, vol, nu_t, ld, nu, dgamma_out,
-                                       ld_out, accumulate, boxes, st);
+                                       ld_out, accumulate, workspace, st);
         if (e != hipSuccess) return VPM_ERR_HIP;
-        boxes += size_t(vpm::pse_tiles(off[b + 1] - off[b])) * 8 * es;
     }
     return VPM_OK;
 }

@@ -117,12 +117,12 @@ hipError_t launch_backward(int dtype, bool role_a, bool role_b, bool stretch, bo
                            const BwdArgs& a, hipStream_t st);
 
 // ---------------------------------------------------------------- viscous terms
-// PSE diffusion of the particles [begin, end) of one set; boxes = workspace for pse_tiles(n)
-// tile boxes of 8 values each (element type of dtype).
+// PSE diffusion of the particles [begin, end) of one set; ws = device scratch of
+// pse_workspace(end - begin, dtype) bytes (reused by the next set once this one is done).
 hipError_t launch_pse(int dtype, int64_t begin, int64_t end, const void* x, const void* g, const void* sg,
                       const void* vol, const void* nut, int64_t ld, double nu, void* dg, int64_t ldo,
-                      int accumulate, void* boxes, hipStream_t st);
-int64_t pse_tiles(int64_t n);
+                      int accumulate, void* ws, hipStream_t st);
+size_t pse_workspace(int64_t n, int dtype);
 hipError_t launch_vreman(int dtype, int64_t n, const void* J, int64_t ld, const void* sg, double cv, void* nut,
                          hipStream_t st);
 
