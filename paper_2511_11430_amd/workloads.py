@@ -164,6 +164,39 @@ def lattice(n_blades=2, n_chord=8, n_span=32, chord=R / 6, r_root=0.2 * R, colle
     return {"a": a, "b": b, "gamma": np.array(G, dtype=np.float64)}
 
 
+def blade_rings(n_blades=2, n_chord=8, n_span=32, chord=R / 6, r_root=0.2 * R, collective_deg=8.0):
+    """Blade vortex-ring lattice for the Neumann solve (Sec. II.A): rings a quarter panel
+    chord aft of the panels, collocation points at the centre of each panel's 3/4-chord line,
+    unit normals e_r x e_chord.  Panel p = (blade * n_chord + i) * n_span + k (i chordwise,
+    k spanwise).  Returns dict(c00, c01, c11, c10, colloc, normal) of shape (3, n_panels),
+    te (the panels of the last chordwise row, blade-major) and the geometry parameters."""
+    cp = chord / n_chord
+    rs = np.linspace(r_root, R, n_span + 1)
+    corners = {k: [] for k in ("c00", "c01", "c11", "c10")}
+    colloc, normal, te = [], [], []
+    for b, (psi, er, cdir) in enumerate(_blade_frames(n_blades, collective_deg)):
+        nrm = np.cross(er, cdir)
+        nrm = nrm / np.linalg.norm(nrm)
+        for i in range(n_chord):
+            xi0 = i * cp + cp / 4
+            xi1 = (i + 1) * cp + cp / 4
+            for k in range(n_span):
+                p = lambda xi, r: r * er + xi * cdir
+                corners["c00"].append(p(xi0, rs[k]))
+                corners["c01"].append(p(xi0, rs[k + 1]))
+                corners["c11"].append(p(xi1, rs[k + 1]))
+                corners["c10"].append(p(xi1, rs[k]))
+                colloc.append(p(i * cp + 0.75 * cp, 0.5 * (rs[k] + rs[k + 1])))
+                normal.append(nrm)
+                if i == n_chord - 1:
+                    te.append((b * n_chord + i) * n_span + k)
+    out = {k: np.ascontiguousarray(np.array(v).T) for k, v in corners.items()}
+    out.update({"colloc": np.ascontiguousarray(np.array(colloc).T),
+                "normal": np.ascontiguousarray(np.array(normal).T), "te": np.array(te, dtype=np.int64),
+                "n_blades": n_blades, "n_chord": n_chord, "n_span": n_span})
+    return out
+
+
 def control_points(n_blades=2, n_chord=8, n_span=32, chord=R / 6, r_root=0.2 * R, collective_deg=8.0,
                    panels=(4,)):
     """Collocation points at the 3/4-chord of the given chordwise panels, strip centres
