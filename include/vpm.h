@@ -232,6 +232,64 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                         const vpm_options* opt, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Blade solve and wake management of one NL-UVLM-VPM step (Sec. II.A; Sec. II.C, Eqs. 6-8).
+ *
+ * vpm_aic_assemble — FP64 influence matrix of a vortex-ring lattice (the Neumann condition
+ * at the collocation points, Sec. II.A):
+ *   aic[i * ld_aic + j] = n_i . u_j(c_i),
+ * u_j = velocity of ring j with unit circulation on the closed path c00 -> c01 -> c11 -> c10,
+ * each edge by the finite-segment law with the Vatistas core (core_radius, vatistas_n), as in
+ * vpm_eval_segments.
+ *  c00, c01, c11, c10 [3][ld_ring]: ring corners (double); colloc, normal [3][ld_col]:
+ *  collocation points (centre of each panel's 3/4-chord line) and unit normals (double).
+ *  aic [n][ld_aic] (double, row-major): output; must not overlap any input.  1 <= n <= 32768. */
+vpm_status vpm_aic_assemble(int64_t n, const double* c00, const double* c01, const double* c11, const double* c10,
+                            int64_t ld_ring, const double* colloc, const double* normal, int64_t ld_col,
+                            double core_radius, int32_t vatistas_n, double* aic, int64_t ld_aic, void* stream);
+
+/* vpm_lu_factor — in-place LU factorisation with partial pivoting of the FP64 matrix
+ * a [n][lda] (row-major): P a = L U, L unit lower (below the diagonal), U upper.  ipiv
+ * (device int32[n]): row swapped with row k at step k.  info (device int32): 0, or k + 1 for
+ * the first column k without a nonzero pivot (the factorisation continues past it).  One
+ * workgroup; meant for the blade systems (a few hundred to a few thousand panels). */
+vpm_status vpm_lu_factor(int64_t n, double* a, int64_t lda, int32_t* ipiv, int32_t* info, void* stream);
+
+/* vpm_lu_solve — solves a x = b with the factors of vpm_lu_factor; b (device double[n]) is
+ * overwritten by x.  Used once per time step with a matrix factored once (the lattice is
+ * rigid in the rotating frame). */
+vpm_status vpm_lu_solve(int64_t n, const double* lu, int64_t lda, const int32_t* ipiv, double* b, void* stream);
+
+/* vpm_wake_shed — Kutta condition and the newest wake row (Sec. II.A; Eq. 7).  The new wake
+ * row takes the trailing-edge panels' circulations gamma_blade[te_index[b * n_span + c]];
+ * the wake is kept as straight lines of frozen strength:
+ *   trailed_out[b * (n_span + 1) + c] = G(b, c - 1) - G(b, c)   (0 outside the blade),
+ *   shed_out[b * n_span + c]          = gamma_te_prev[b * n_span + c] - G(b, c),
+ * then gamma_te_prev is replaced by G (zeros before the first step: the starting vortex).
+ * Trailed lines run downstream, shed lines outward along the span.  Arrays are of dtype
+ * (double or float); te_index is device int32 [n_blades * n_span]. */
+vpm_status vpm_wake_shed(int32_t dtype, int32_t n_blades, int32_t n_span, const void* gamma_blade,
+                         const int32_t* te_index, void* gamma_te_prev, void* trailed_out, void* shed_out,
+                         void* stream);
+
+/* vpm_wake_convert — wake lines to particles, the adaptive conversion of Sec. II.C.
+ * Line i runs a -> b with strength dgamma[i].  Its particle count is
+ *   n_i = ceil(ds_i / ds_t * n_tip)   (Eq. 8)  when tip_index[i] >= 0,
+ * with ds_i = |b_i - a_i| and ds_t the length of line tip_index[i] (the tip trailed line of
+ * its row), capped at n_max; n_i = 1 when tip_index[i] < 0 (shed lines), and when ds_t = 0.
+ * Counts are decided in FP64 as written.  Particles (Eq. 6) go to the midpoints of n_i equal
+ * sub-segments with strength dgamma (b - a) / n_i and core size sigma, line after line, in
+ * line order, into x_out, gamma_out [3][ld_out] and sigma_out [ld_out] from index 0.
+ *  count_out (device int64): total particle count.  Lines that would pass capacity are left
+ *  out whole (the count still reports the total, so the caller can tell).
+ *  workspace        vpm_wake_convert_workspace_size(n_lines) bytes.
+ * dtype applies to every float array. */
+vpm_status vpm_wake_convert(int32_t dtype, int64_t n_lines, const void* a, const void* b, int64_t ld_line,
+                            const void* dgamma, const int32_t* tip_index, int32_t n_tip, int32_t n_max,
+                            double sigma, int64_t capacity, void* x_out, void* gamma_out, void* sigma_out,
+                            int64_t ld_out, int64_t* count_out, void* workspace, size_t ws_bytes, void* stream);
+size_t vpm_wake_convert_workspace_size(int64_t n_lines);
+
+/* ---------------------------------------------------------------------------------------
  * vpm_rk3_stage — stage k (0, 1, 2) of Williamson's low-storage third-order Runge-Kutta
  * scheme (Sec. II.B) on Y = (x, Gamma) with register Q = (qx, qg) and F = (u, dgamma):
  *     Q <- A_k Q + dt F;   Y <- Y + B_k Q,

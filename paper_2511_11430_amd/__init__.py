@@ -298,6 +298,108 @@ def vpm_eval_diffusion(x, gamma, sigma, vol, nu, nu_t=None, *, dgamma_out=None, 
     return dgamma_out
 
 
+def vpm_aic_assemble(c00, c01, c11, c10, colloc, normal, core_radius, vatistas_n=2, *, aic_out=None, stream=None):
+    """FP64 influence matrix (n, n) of a vortex-ring lattice at its collocation points
+    (Sec. II.A); all inputs float64 CUDA tensors of shape (3, n)."""
+    torch = _torch()
+    lib = _lib.load()
+    n = colloc.shape[1]
+    for name, t in (("c00", c00), ("c01", c01), ("c11", c11), ("c10", c10), ("colloc", colloc), ("normal", normal)):
+        _vec(t, name, n, torch.float64)
+    if len({_ld(t) for t in (c00, c01, c11, c10)}) != 1 or _ld(colloc) != _ld(normal):
+        raise ValueError("ring corners must share one leading dimension, and so must colloc and normal")
+    if aic_out is None:
+        aic_out = torch.empty((n, n), dtype=torch.float64, device=colloc.device)
+    if aic_out.dim() != 2 or aic_out.shape != (n, n) or aic_out.stride(1) != 1 or aic_out.dtype != torch.float64:
+        raise ValueError("aic_out must be a row-major (n, n) float64 tensor")
+    st = lib.vpm_aic_assemble(n, _p(c00), _p(c01), _p(c11), _p(c10), _ld(c00), _p(colloc), _p(normal), _ld(colloc),
+                              float(core_radius), int(vatistas_n), _p(aic_out), int(aic_out.stride(0)), _stream(stream))
+    _check("vpm_aic_assemble", st)
+    return aic_out
+
+
+def vpm_lu_factor(a, *, ipiv=None, info=None, stream=None):
+    """In-place LU with partial pivoting of a row-major (n, n) float64 CUDA tensor.
+    Returns (ipiv int32 (n,), info int32 (1,)) as device tensors."""
+    torch = _torch()
+    lib = _lib.load()
+    n = a.shape[0]
+    if a.dim() != 2 or a.shape[1] != n or a.stride(1) != 1 or a.dtype != torch.float64 or not a.is_cuda:
+        raise ValueError("a must be a row-major (n, n) float64 CUDA tensor")
+    if ipiv is None:
+        ipiv = torch.empty(n, dtype=torch.int32, device=a.device)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=a.device)
+    st = lib.vpm_lu_factor(n, _p(a), int(a.stride(0)), _p(ipiv), _p(info), _stream(stream))
+    _check("vpm_lu_factor", st)
+    return ipiv, info
+
+
+def vpm_lu_solve(lu, ipiv, b, *, stream=None):
+    """Solves with the factors of vpm_lu_factor; b (n,) float64 is overwritten by x."""
+    lib = _lib.load()
+    n = lu.shape[0]
+    _scal(b, "b", n)
+    st = lib.vpm_lu_solve(n, _p(lu), int(lu.stride(0)), _p(ipiv), _p(b), _stream(stream))
+    _check("vpm_lu_solve", st)
+    return b
+
+
+def vpm_wake_shed(gamma_blade, te_index, gamma_te_prev, n_blades, n_span, *, trailed_out=None, shed_out=None,
+                  stream=None):
+    """Kutta condition and the newest wake row's line strengths (Eq. 7); updates
+    gamma_te_prev.  Returns (trailed (n_blades * (n_span + 1),), shed (n_blades * n_span,))."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(gamma_blade)
+    _scal(gamma_te_prev, "gamma_te_prev", n_blades * n_span, gamma_blade.dtype)
+    _scal(te_index, "te_index", n_blades * n_span, torch.int32)
+    if trailed_out is None:
+        trailed_out = torch.empty(n_blades * (n_span + 1), dtype=gamma_blade.dtype, device=gamma_blade.device)
+    if shed_out is None:
+        shed_out = torch.empty(n_blades * n_span, dtype=gamma_blade.dtype, device=gamma_blade.device)
+    st = lib.vpm_wake_shed(dt, int(n_blades), int(n_span), _p(gamma_blade), _p(te_index), _p(gamma_te_prev),
+                           _p(trailed_out), _p(shed_out), _stream(stream))
+    _check("vpm_wake_shed", st)
+    return trailed_out, shed_out
+
+
+def vpm_wake_convert(a, b, dgamma, tip_index, n_tip, sigma, capacity, *, n_max=64, x_out=None, gamma_out=None,
+                     sigma_out=None, count_out=None, workspace=None, stream=None):
+    """Wake lines a -> b (3, n) with strengths dgamma (n,) to particles (Eqs. 6-8).
+    Returns (x (3, capacity), gamma (3, capacity), sigma (capacity,), count (device int64))."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(a)
+    n = a.shape[1]
+    _vec(a, "a", dtype=a.dtype)
+    _vec(b, "b", n, a.dtype)
+    _scal(dgamma, "dgamma", n, a.dtype)
+    _scal(tip_index, "tip_index", n, torch.int32)
+    if _ld(a) != _ld(b):
+        raise ValueError("a and b must share one leading dimension")
+    dev = a.device
+    if x_out is None:
+        x_out = torch.empty((3, capacity), dtype=a.dtype, device=dev)
+    if gamma_out is None:
+        gamma_out = torch.empty((3, capacity), dtype=a.dtype, device=dev)
+    if sigma_out is None:
+        sigma_out = torch.empty(capacity, dtype=a.dtype, device=dev)
+    if count_out is None:
+        count_out = torch.empty(1, dtype=torch.int64, device=dev)
+    if _ld(gamma_out) != _ld(x_out):
+        raise ValueError("x_out and gamma_out must share one leading dimension")
+    need = int(lib.vpm_wake_convert_workspace_size(n))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    ld_out = _ld(x_out) if capacity > 0 else 0
+    st = lib.vpm_wake_convert(dt, n, _p(a), _p(b), _ld(a) if n > 0 else 0, _p(dgamma), _p(tip_index), int(n_tip),
+                              int(n_max), float(sigma), int(capacity), _p(x_out), _p(gamma_out), _p(sigma_out),
+                              ld_out, _p(count_out), _p(workspace), workspace.numel(), _stream(stream))
+    _check("vpm_wake_convert", st)
+    return x_out, gamma_out, sigma_out, count_out
+
+
 def vpm_eval_segments(a, b, gamma_seg, x_tgt, core_radius, vatistas_n=2, *, u_out=None, accumulate=False,
                       stream=None):
     """Velocity at x_tgt induced by straight vortex segments a->b (Vatistas core, Sec. II.A)."""

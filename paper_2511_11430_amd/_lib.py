@@ -32,6 +32,14 @@ SIGNATURES = {
     "vpm_eval_diffusion": (c_i32, [c_i32, c_i32, c_i64p, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_dbl, c_vp, c_i64,
                                    c_i32, c_vp, c_sz, c_vp]),
     "vpm_diffusion_workspace_size": (c_sz, [c_i32, c_i32, c_i64p]),
+    "vpm_aic_assemble": (c_i32, [c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_dbl, c_i32, c_vp, c_i64,
+                                 c_vp]),
+    "vpm_lu_factor": (c_i32, [c_i64, c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "vpm_lu_solve": (c_i32, [c_i64, c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "vpm_wake_shed": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "vpm_wake_convert": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_i32, c_i32, c_dbl, c_i64, c_vp, c_vp,
+                                 c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "vpm_wake_convert_workspace_size": (c_sz, [c_i64]),
     "vpm_eval_segments": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_dbl, c_i32, c_i64, c_vp, c_i64,
                                   c_vp, c_i64, c_i32, c_vp]),
     "vpm_backward": (c_i32, [c_i32, c_i32, c_i64p, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64,

@@ -1,0 +1,388 @@
+// Blade solve and wake management of one NL-UVLM-VPM step (Fu & Laurendeau, Sec. II.A and the
+// adaptive wake conversion of Sec. II.C, Eqs. 6-8), for one MI355X (gfx950).
+//
+//  - k_aic: influence matrix of the blade vortex-ring lattice, FP64, one lane per (collocation
+//    point, ring) entry (a row of the matrix is contiguous, so stores coalesce).  A ring is the
+//    closed path c00 -> c01 -> c11 -> c10 with unit circulation; each edge is the finite
+//    straight segment law (r1 x r2) r0 . (r1/|r1| - r2/|r2|) / (4 pi |r0|^2 (d^2n + rc^2n)^(1/n))
+//    with the Vatistas core, d^2 = |r1 x r2|^2 / |r0|^2.  Entry = n_i . u_ring_j(c_i).
+//  - k_lu_factor / k_lu_solve: dense LU with partial pivoting and the two triangular solves in
+//    one workgroup of 1024 lanes (the systems are a few hundred to a few thousand panels;
+//    the matrix of 512 panels is 2 MB and stays in L2).  Pivot = largest |entry| of the
+//    column, the first such row on ties.
+//  - k_wake_shed: Kutta condition and the strengths of the newest wake row's lines (Eq. 7):
+//    trailed line at span station c: Gamma_te(c-1) - Gamma_te(c) (0 outside the blade), shed
+//    line of strip c: Gamma_te,prev(c) - Gamma_te(c); the previous values are then replaced.
+//  - k_conv_count / k_conv_scan / k_conv_emit: panel-line to particle conversion.  Counts
+//    n = ceil(ds / ds_t * n_t) (Eq. 8; FP64, evaluated as written, no contraction) for trailed
+//    lines, 1 for shed lines; an exclusive scan in one workgroup gives each line its first
+//    particle; each line then writes its n particles (midpoints of n equal sub-segments,
+//    strength dGamma (b - a) / n, Eq. 6).
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "vpm_internal.h"
+
+namespace vpm {
+
+namespace {
+
+// Velocity of a straight segment a -> b of unit circulation at p (FP64), Vatistas core.
+// Zero for a vanishing arm or length (below 1e-12 max(|r0|, 1)) or a vanishing denominator.
+__device__ __forceinline__ void segment_unit(const double p[3], const double a[3], const double b[3], double rc2n,
+                                             double inv_n, int vn, double u[3]) {
+    const double r1[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+    const double r2[3] = {p[0] - b[0], p[1] - b[1], p[2] - b[2]};
+    const double r0[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double c[3] = {r1[1] * r2[2] - r1[2] * r2[1], r1[2] * r2[0] - r1[0] * r2[2], r1[0] * r2[1] - r1[1] * r2[0]};
+    const double l1 = sqrt(r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
+    const double l2 = sqrt(r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2]);
+    const double l02 = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
+    const double l0 = sqrt(l02);
+    const double eps = 1e-12 * fmax(l0, 1.0);
+    u[0] = u[1] = u[2] = 0.0;
+    if (l1 < eps || l2 < eps || l0 < eps) return;
+    const double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+    const double d2 = c2 / l02;
+    double den;
+    if (vn == 1) den = d2 + rc2n;
+    else if (vn == 2) den = sqrt(d2 * d2 + rc2n);
+    else den = pow(pow(d2, 1.0 / inv_n) + rc2n, inv_n);
+    den *= l02;
+    if (!(den > 0.0)) return;
+    const double D = (r0[0] * r1[0] + r0[1] * r1[1] + r0[2] * r1[2]) / l1 -
+                     (r0[0] * r2[0] + r0[1] * r2[1] + r0[2] * r2[2]) / l2;
+    const double f = kInv4PiD * D / den;
+    u[0] = f * c[0];
+    u[1] = f * c[1];
+    u[2] = f * c[2];
+}
+
+struct AicArgs {
+    int64_t n;
+    const double* c00;
+    const double* c01;
+    const double* c11;
+    const double* c10;
+    int64_t ldr;
+    const double* col;
+    const double* nrm;
+    int64_t ldc;
+    double rc2n, inv_n;
+    int vn;
+    double* A;
+    int64_t lda;
+};
+
+__global__ __launch_bounds__(256) void k_aic(AicArgs a) {
+    const int64_t i = blockIdx.y;
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= a.n || j >= a.n) return;
+    const double p[3] = {a.col[i], a.col[a.ldc + i], a.col[2 * a.ldc + i]};
+    const double nn[3] = {a.nrm[i], a.nrm[a.ldc + i], a.nrm[2 * a.ldc + i]};
+    const double* cs[4] = {a.c00, a.c01, a.c11, a.c10};
+    double q[4][3];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) q[e][c] = cs[e][c * a.ldr + j];
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        double u[3];
+        segment_unit(p, q[e], q[(e + 1) & 3], a.rc2n, a.inv_n, a.vn, u);
+        s += nn[0] * u[0] + nn[1] * u[1] + nn[2] * u[2];
+    }
+    a.A[i * a.lda + j] = s;
+}
+
+constexpr int kLuThreads = 1024;
+
+// Largest |x| with its index over the workgroup (first index on ties).
+__device__ __forceinline__ void block_argmax(double& v, int64_t& idx, double* sv, int64_t* si) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int64_t oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+        }
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sv[w] = v;
+        si[w] = idx;
+    }
+    __syncthreads();
+    v = sv[0];
+    idx = si[0];
+    for (int k = 1; k < kLuThreads / 64; ++k) {
+        if (sv[k] > v || (sv[k] == v && si[k] < idx)) {
+            v = sv[k];
+            idx = si[k];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kLuThreads) void k_lu_factor(int64_t n, double* A, int64_t lda, int32_t* ipiv,
+                                                          int32_t* info) {
+    __shared__ double sv[kLuThreads / 64];
+    __shared__ int64_t si[kLuThreads / 64];
+    const int t = threadIdx.x;
+    int32_t first_zero = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        double v = -1.0;
+        int64_t idx = k;
+        for (int64_t r = k + t; r < n; r += kLuThreads) {
+            const double x = fabs(A[r * lda + k]);
+            if (x > v) {
+                v = x;
+                idx = r;
+            }
+        }
+        block_argmax(v, idx, sv, si);
+        if (t == 0) ipiv[k] = int32_t(idx);
+        if (v == 0.0) {  // singular column: record the first one, leave the column as is
+            if (first_zero == 0) first_zero = int32_t(k + 1);
+            __syncthreads();
+            continue;
+        }
+        if (idx != k) {
+            for (int64_t c = t; c < n; c += kLuThreads) {
+                const double x = A[k * lda + c];
+                A[k * lda + c] = A[idx * lda + c];
+                A[idx * lda + c] = x;
+            }
+        }
+        __syncthreads();
+        const double piv = A[k * lda + k];
+        for (int64_t r = k + 1 + t; r < n; r += kLuThreads) A[r * lda + k] /= piv;
+        __syncthreads();
+        const int64_t m = n - k - 1;
+        for (int64_t e = t; e < m * m; e += kLuThreads) {
+            const int64_t r = k + 1 + e / m;
+            const int64_t c = k + 1 + e % m;
+            A[r * lda + c] -= A[r * lda + k] * A[k * lda + c];
+        }
+        __syncthreads();
+    }
+    if (t == 0) *info = first_zero;
+}
+
+__global__ __launch_bounds__(kLuThreads) void k_lu_solve(int64_t n, const double* LU, int64_t lda,
+                                                         const int32_t* ipiv, double* b) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t p = ipiv[k];
+            if (p != k && p >= 0 && p < n) {
+                const double x = b[k];
+                b[k] = b[p];
+                b[p] = x;
+            }
+        }
+    }
+    __syncthreads();
+    for (int64_t k = 0; k < n; ++k) {  // L y = P b, unit diagonal
+        const double bk = b[k];
+        for (int64_t r = k + 1 + t; r < n; r += kLuThreads) b[r] -= LU[r * lda + k] * bk;
+        __syncthreads();
+    }
+    for (int64_t k = n - 1; k >= 0; --k) {  // U x = y
+        if (t == 0) b[k] /= LU[k * lda + k];
+        __syncthreads();
+        const double xk = b[k];
+        for (int64_t r = t; r < k; r += kLuThreads) b[r] -= LU[r * lda + k] * xk;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_wake_shed(int n_blades, int n_span, const T* gb, const int32_t* te,
+                                                   T* prev, T* trailed, T* shed) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = 2 * n_span + 1;
+    if (id >= n_blades * per) return;
+    const int b = id / per;
+    const int k = id % per;
+    if (k <= n_span) {  // trailed line at station k
+        const double left = k > 0 ? double(gb[te[b * n_span + k - 1]]) : 0.0;
+        const double right = k < n_span ? double(gb[te[b * n_span + k]]) : 0.0;
+        trailed[b * (n_span + 1) + k] = T(left - right);
+    } else {  // shed line of strip c
+        const int c = k - n_span - 1;
+        shed[b * n_span + c] = T(double(prev[b * n_span + c]) - double(gb[te[b * n_span + c]]));
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_wake_keep(int n, const T* gb, const int32_t* te, T* prev) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < n) prev[id] = gb[te[id]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_conv_count(int64_t n, const T* a, const T* b, int64_t ld,
+                                                    const int32_t* tip, int n_tip, int n_max, int32_t* cnt) {
+#pragma clang fp contract(off)
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t t = tip[i];
+    int32_t c = 1;
+    if (t >= 0 && t < n) {
+        const double dx = double(b[i]) - double(a[i]), dy = double(b[ld + i]) - double(a[ld + i]),
+                     dz = double(b[2 * ld + i]) - double(a[2 * ld + i]);
+        const double tx = double(b[t]) - double(a[t]), ty = double(b[ld + t]) - double(a[ld + t]),
+                     tz = double(b[2 * ld + t]) - double(a[2 * ld + t]);
+        const double ds = sqrt(dx * dx + dy * dy + dz * dz);
+        const double dt = sqrt(tx * tx + ty * ty + tz * tz);
+        if (dt > 0.0) {
+            const double q = ceil(ds / dt * double(n_tip));
+            c = q > double(n_max) ? n_max : int32_t(q);
+        }
+    }
+    cnt[i] = c;
+}
+
+// Exclusive scan of n counts in one workgroup of 1024 lanes: lane l owns a contiguous chunk.
+__global__ __launch_bounds__(1024) void k_conv_scan(int64_t n, const int32_t* cnt, int64_t* first, int64_t* total) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t lo = t * chunk < n ? t * chunk : n;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += cnt[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t > 0 ? part[t - 1] : 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        first[i] = run;
+        run += cnt[i];
+    }
+    if (t == 1023) *total = part[1023];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_conv_emit(int64_t n, const T* a, const T* b, int64_t ld, const T* dg,
+                                                   const int32_t* cnt, const int64_t* first, double sigma,
+                                                   int64_t capacity, T* xo, T* go, T* so, int64_t ldo) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t m = cnt[i];
+    const int64_t f = first[i];
+    if (m <= 0 || f + m > capacity) return;  // a line that does not fit is left out whole
+    const double A[3] = {double(a[i]), double(a[ld + i]), double(a[2 * ld + i])};
+    const double dl[3] = {double(b[i]) - A[0], double(b[ld + i]) - A[1], double(b[2 * ld + i]) - A[2]};
+    const double w = double(dg[i]) / double(m);
+    for (int32_t k = 0; k < m; ++k) {
+        const double s = (double(k) + 0.5) / double(m);
+        const int64_t o = f + k;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xo[c * ldo + o] = T(A[c] + s * dl[c]);
+            go[c * ldo + o] = T(w * dl[c]);
+        }
+        so[o] = T(sigma);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_aic(int64_t n, const double* c00, const double* c01, const double* c11, const double* c10,
+                      int64_t ldr, const double* col, const double* nrm, int64_t ldc, double rc, int vn, double* A,
+                      int64_t lda, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    AicArgs a;
+    a.n = n;
+    a.c00 = c00;
+    a.c01 = c01;
+    a.c11 = c11;
+    a.c10 = c10;
+    a.ldr = ldr;
+    a.col = col;
+    a.nrm = nrm;
+    a.ldc = ldc;
+    a.vn = vn;
+    a.inv_n = 1.0 / double(vn);
+    a.rc2n = rc > 0.0 ? pow(rc * rc, double(vn)) : 0.0;
+    a.A = A;
+    a.lda = lda;
+    hipLaunchKernelGGL(k_aic, dim3(unsigned((n + 255) / 256), unsigned(n)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_factor(int64_t n, double* A, int64_t lda, int32_t* ipiv, int32_t* info, hipStream_t st) {
+    hipLaunchKernelGGL(k_lu_factor, dim3(1), dim3(kLuThreads), 0, st, n, A, lda, ipiv, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_solve(int64_t n, const double* LU, int64_t lda, const int32_t* ipiv, double* b,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(kLuThreads), 0, st, n, LU, lda, ipiv, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_wake_shed(int dtype, int n_blades, int n_span, const void* gb, const int32_t* te, void* prev,
+                            void* trailed, void* shed, hipStream_t st) {
+    const int total = n_blades * (2 * n_span + 1);
+    const int nb = (total + 255) / 256;
+    const int nk = (n_blades * n_span + 255) / 256;
+    if (dtype == kDtypeF64) {
+        hipLaunchKernelGGL(k_wake_shed<double>, dim3(nb), dim3(256), 0, st, n_blades, n_span, (const double*)gb, te,
+                           (double*)prev, (double*)trailed, (double*)shed);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_wake_keep<double>, dim3(nk), dim3(256), 0, st, n_blades * n_span, (const double*)gb, te,
+                           (double*)prev);
+    } else {
+        hipLaunchKernelGGL(k_wake_shed<float>, dim3(nb), dim3(256), 0, st, n_blades, n_span, (const float*)gb, te,
+                           (float*)prev, (float*)trailed, (float*)shed);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_wake_keep<float>, dim3(nk), dim3(256), 0, st, n_blades * n_span, (const float*)gb, te,
+                           (float*)prev);
+    }
+    return hipGetLastError();
+}
+
+size_t conv_workspace(int64_t n) { return ((size_t(n) * 4 + 255) / 256) * 256 + size_t(n + 1) * 8; }
+
+hipError_t launch_wake_convert(int dtype, int64_t n, const void* a, const void* b, int64_t ld, const void* dg,
+                               const int32_t* tip, int n_tip, int n_max, double sigma, int64_t capacity, void* xo,
+                               void* go, void* so, int64_t ldo, int64_t* count, void* ws, hipStream_t st) {
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    int32_t* cnt = reinterpret_cast<int32_t*>(w);
+    int64_t* first = reinterpret_cast<int64_t*>(w + ((size_t(n) * 4 + 255) / 256) * 256);
+    const unsigned nb = unsigned((n + 255) / 256);
+    hipError_t e;
+    if (n == 0) {  // no lines: only the zero total is written
+        hipLaunchKernelGGL(k_conv_scan, dim3(1), dim3(1024), 0, st, n, cnt, first, count);
+        return hipGetLastError();
+    }
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_conv_count<double>, dim3(nb), dim3(256), 0, st, n, (const double*)a, (const double*)b, ld,
+                           tip, n_tip, n_max, cnt);
+    else
+        hipLaunchKernelGGL(k_conv_count<float>, dim3(nb), dim3(256), 0, st, n, (const float*)a, (const float*)b, ld,
+                           tip, n_tip, n_max, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_conv_scan, dim3(1), dim3(1024), 0, st, n, cnt, first, count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_conv_emit<double>, dim3(nb), dim3(256), 0, st, n, (const double*)a, (const double*)b, ld,
+                           (const double*)dg, cnt, first, sigma, capacity, (double*)xo, (double*)go, (double*)so, ldo);
+    else
+        hipLaunchKernelGGL(k_conv_emit<float>, dim3(nb), dim3(256), 0, st, n, (const float*)a, (const float*)b, ld,
+                           (const float*)dg, cnt, first, sigma, capacity, (float*)xo, (float*)go, (float*)so, ldo);
+    return hipGetLastError();
+}
+
+}  // namespace vpm

@@ -796,3 +796,100 @@ vpm_status vpm_diagnostics(int32_t dtype, int64_t n, const void* x, const void* 
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ blade solve and wake management
+extern "C" {
+
+vpm_status vpm_aic_assemble(int64_t n, const double* c00, const double* c01, const double* c11, const double* c10,
+                            int64_t ld_ring, const double* colloc, const double* normal, int64_t ld_col,
+                            double core_radius, int32_t vatistas_n, double* aic, int64_t ld_aic, void* stream) {
+    if (n < 1 || n > 32768 || ld_ring < n || ld_col < n || ld_aic < n) return VPM_ERR_SIZE;
+    if (!c00 || !c01 || !c11 || !c10 || !colloc || !normal || !aic) return VPM_ERR_NULL;
+    if (!(core_radius >= 0.0) || core_radius > 1e30) return VPM_ERR_SIZE;
+    if (vatistas_n < 1 || vatistas_n > 16) return VPM_ERR_ENUM;
+    const Range ra = span(aic, 1, n * ld_aic, n * ld_aic, sizeof(double));
+    const Range ins[6] = {span(c00, 3, ld_ring, n, 8), span(c01, 3, ld_ring, n, 8), span(c11, 3, ld_ring, n, 8),
+                          span(c10, 3, ld_ring, n, 8), span(colloc, 3, ld_col, n, 8), span(normal, 3, ld_col, n, 8)};
+    for (const Range& r : ins)
+        if (overlap(ra, r)) return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_aic(n, c00, c01, c11, c10, ld_ring, colloc, normal, ld_col, core_radius, vatistas_n,
+                                      aic, ld_aic, static_cast<hipStream_t>(stream)));
+}
+
+vpm_status vpm_lu_factor(int64_t n, double* a, int64_t lda, int32_t* ipiv, int32_t* info, void* stream) {
+    if (n < 1 || n > 32768 || lda < n) return VPM_ERR_SIZE;
+    if (!a || !ipiv || !info) return VPM_ERR_NULL;
+    const Range ra = span(a, 1, n * lda, n * lda, sizeof(double));
+    if (overlap(ra, span(ipiv, 1, n, n, 4)) || overlap(ra, span(info, 1, 1, 1, 4)) ||
+        overlap(span(ipiv, 1, n, n, 4), span(info, 1, 1, 1, 4)))
+        return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_lu_factor(n, a, lda, ipiv, info, static_cast<hipStream_t>(stream)));
+}
+
+vpm_status vpm_lu_solve(int64_t n, const double* lu, int64_t lda, const int32_t* ipiv, double* b, void* stream) {
+    if (n < 1 || n > 32768 || lda < n) return VPM_ERR_SIZE;
+    if (!lu || !ipiv || !b) return VPM_ERR_NULL;
+    const Range rb = span(b, 1, n, n, sizeof(double));
+    if (overlap(rb, span(lu, 1, n * lda, n * lda, sizeof(double))) || overlap(rb, span(ipiv, 1, n, n, 4)))
+        return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_lu_solve(n, lu, lda, ipiv, b, static_cast<hipStream_t>(stream)));
+}
+
+vpm_status vpm_wake_shed(int32_t dtype, int32_t n_blades, int32_t n_span, const void* gamma_blade,
+                         const int32_t* te_index, void* gamma_te_prev, void* trailed_out, void* shed_out,
+                         void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n_blades < 1 || n_span < 1 || int64_t(n_blades) * (2 * int64_t(n_span) + 1) > INT32_MAX) return VPM_ERR_SIZE;
+    if (!gamma_blade || !te_index || !gamma_te_prev || !trailed_out || !shed_out) return VPM_ERR_NULL;
+    const size_t es = elem_size(dtype);
+    const int64_t ns = int64_t(n_blades) * n_span, nt = int64_t(n_blades) * (n_span + 1);
+    const Range rt = span(trailed_out, 1, nt, nt, es), rs = span(shed_out, 1, ns, ns, es),
+                rp = span(gamma_te_prev, 1, ns, ns, es), ri = span(te_index, 1, ns, ns, 4);
+    if (overlap(rt, rs) || overlap(rt, rp) || overlap(rs, rp) || overlap(rt, ri) || overlap(rs, ri) ||
+        overlap(rp, ri))
+        return VPM_ERR_ALIAS;
+    if (overlap(rt, span(gamma_blade, 1, 1, 1, es)) || overlap(rs, span(gamma_blade, 1, 1, 1, es)))
+        return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_wake_shed(dtype, n_blades, n_span, gamma_blade, te_index, gamma_te_prev,
+                                            trailed_out, shed_out, static_cast<hipStream_t>(stream)));
+}
+
+size_t vpm_wake_convert_workspace_size(int64_t n_lines) {
+    if (n_lines < 0 || n_lines > INT32_MAX) return 0;
+    return vpm::conv_workspace(n_lines);
+}
+
+vpm_status vpm_wake_convert(int32_t dtype, int64_t n_lines, const void* a, const void* b, int64_t ld_line,
+                            const void* dgamma, const int32_t* tip_index, int32_t n_tip, int32_t n_max,
+                            double sigma, int64_t capacity, void* x_out, void* gamma_out, void* sigma_out,
+                            int64_t ld_out, int64_t* count_out, void* workspace, size_t ws_bytes, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n_lines < 0 || n_lines > INT32_MAX || ld_line < n_lines || capacity < 0 || ld_out < capacity)
+        return VPM_ERR_SIZE;
+    if (n_tip < 1 || n_max < 1 || n_max > 1 << 20) return VPM_ERR_SIZE;
+    if (!(sigma > 0.0) || sigma > 1e30) return VPM_ERR_SIZE;
+    if (!count_out) return VPM_ERR_NULL;
+    if (n_lines > 0 && (!a || !b || !dgamma || !tip_index)) return VPM_ERR_NULL;
+    if (capacity > 0 && (!x_out || !gamma_out || !sigma_out)) return VPM_ERR_NULL;
+    const size_t need = vpm::conv_workspace(n_lines);
+    if (!workspace || ws_bytes < need) return VPM_ERR_WORKSPACE;
+    const size_t es = elem_size(dtype);
+    const Range outs[4] = {span(x_out, 3, ld_out, capacity, es), span(gamma_out, 3, ld_out, capacity, es),
+                           span(sigma_out, 1, ld_out, capacity, es), span(count_out, 1, 1, 1, 8)};
+    const Range ins[5] = {span(a, 3, ld_line, n_lines, es), span(b, 3, ld_line, n_lines, es),
+                          span(dgamma, 1, ld_line, n_lines, es), span(tip_index, 1, n_lines, n_lines, 4),
+                          span(workspace, 1, int64_t(ws_bytes), int64_t(ws_bytes), 1)};
+    for (int i = 0; i < 4; ++i) {
+        for (const Range& r : ins)
+            if (overlap(outs[i], r)) return VPM_ERR_ALIAS;
+        for (int j = i + 1; j < 4; ++j)
+            if (overlap(outs[i], outs[j])) return VPM_ERR_ALIAS;
+    }
+    for (int i = 0; i < 4; ++i)
+        if (overlap(ins[4], ins[i])) return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_wake_convert(dtype, n_lines, a, b, ld_line, dgamma, tip_index, n_tip, n_max, sigma,
+                                               capacity, x_out, gamma_out, sigma_out, ld_out, count_out, workspace,
+                                               static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -126,6 +126,20 @@ size_t pse_workspace(int64_t n, int dtype);
 hipError_t launch_vreman(int dtype, int64_t n, const void* J, int64_t ld, const void* sg, double cv, void* nut,
                          hipStream_t st);
 
+// ---------------------------------------------------------------- blade solve and wake management
+hipError_t launch_aic(int64_t n, const double* c00, const double* c01, const double* c11, const double* c10,
+                      int64_t ldr, const double* col, const double* nrm, int64_t ldc, double rc, int vn, double* A,
+                      int64_t lda, hipStream_t st);
+hipError_t launch_lu_factor(int64_t n, double* A, int64_t lda, int32_t* ipiv, int32_t* info, hipStream_t st);
+hipError_t launch_lu_solve(int64_t n, const double* LU, int64_t lda, const int32_t* ipiv, double* b,
+                           hipStream_t st);
+hipError_t launch_wake_shed(int dtype, int n_blades, int n_span, const void* gb, const int32_t* te, void* prev,
+                            void* trailed, void* shed, hipStream_t st);
+size_t conv_workspace(int64_t n);
+hipError_t launch_wake_convert(int dtype, int64_t n, const void* a, const void* b, int64_t ld, const void* dg,
+                               const int32_t* tip, int n_tip, int n_max, double sigma, int64_t capacity, void* xo,
+                               void* go, void* so, int64_t ldo, int64_t* count, void* ws, hipStream_t st);
+
 // ---------------------------------------------------------------- RK3 and diagnostics
 hipError_t launch_rk3_stage(int dtype, int state_dtype, int stage, int64_t n, double dt, void* x, void* g,
                             void* qx, void* qg, const void* u, const void* dg, int64_t ld, void* xe, void* ge,

@@ -255,3 +255,44 @@ def test_diffusion_validation():
     assert call(dg=P(0)) == ALIAS
     assert call(w=P(1)) == ALIAS
     assert call(o=off(0, 0), ld=0, ldo=0) == OK
+
+
+def test_uvlm_validation():
+    lib = _lib.load()
+    f = lib.vpm_aic_assemble
+    assert f(0, P(0), P(1), P(2), P(3), 10, P(4), P(5), 10, 0.0, 2, P(6), 10, None) == SIZE
+    assert f(10, P(0), P(1), P(2), P(3), 9, P(4), P(5), 10, 0.0, 2, P(6), 10, None) == SIZE
+    assert f(10, P(0), P(1), P(2), P(3), 10, P(4), P(5), 10, -1.0, 2, P(6), 10, None) == SIZE
+    assert f(10, P(0), P(1), P(2), P(3), 10, P(4), P(5), 10, 0.0, 0, P(6), 10, None) == ENUM
+    assert f(10, None, P(1), P(2), P(3), 10, P(4), P(5), 10, 0.0, 2, P(6), 10, None) == NULL
+    assert f(10, P(0), P(1), P(2), P(3), 10, P(4), P(5), 10, 0.0, 2, P(4), 10, None) == ALIAS
+    assert lib.vpm_lu_factor(0, P(0), 1, P(1), P(2), None) == SIZE
+    assert lib.vpm_lu_factor(5, P(0), 4, P(1), P(2), None) == SIZE
+    assert lib.vpm_lu_factor(5, P(0), 5, None, P(2), None) == NULL
+    assert lib.vpm_lu_factor(5, P(0), 5, P(0), P(2), None) == ALIAS
+    assert lib.vpm_lu_solve(5, P(0), 5, P(1), None, None) == NULL
+    assert lib.vpm_lu_solve(5, P(0), 5, P(1), P(0), None) == ALIAS
+    sh = lib.vpm_wake_shed
+    assert sh(9, 2, 8, P(0), P(1), P(2), P(3), P(4), None) == DTYPE
+    assert sh(F64, 0, 8, P(0), P(1), P(2), P(3), P(4), None) == SIZE
+    assert sh(F64, 2, 8, P(0), None, P(2), P(3), P(4), None) == NULL
+    assert sh(F64, 2, 8, P(0), P(1), P(2), P(2), P(4), None) == ALIAS
+    cw = lib.vpm_wake_convert
+    need = lib.vpm_wake_convert_workspace_size(100)
+    assert need >= 100 * 4 + 101 * 8
+
+    def conv(dtype=F64, n=100, a=P(0), b=P(1), ld=100, dg=P(2), tip=P(3), nt=2, nmax=64, sig=0.01, cap=500,
+             x=P(4), g=P(5), s=P(6), ldo=500, cnt=P(7), w=P(8), wsb=need):
+        return cw(dtype, n, a, b, ld, dg, tip, nt, nmax, sig, cap, x, g, s, ldo, cnt, w, wsb, None)
+
+    assert conv(dtype=3) == DTYPE
+    assert conv(ld=99) == SIZE
+    assert conv(ldo=499) == SIZE
+    assert conv(nt=0) == SIZE
+    assert conv(sig=0.0) == SIZE
+    assert conv(cnt=None) == NULL
+    assert conv(tip=None) == NULL
+    assert conv(w=None) == WORKSPACE
+    assert conv(wsb=need - 1) == WORKSPACE
+    assert conv(x=P(0)) == ALIAS
+    assert conv(g=P(4)) == ALIAS
