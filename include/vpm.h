@@ -289,6 +289,32 @@ vpm_status vpm_wake_convert(int32_t dtype, int64_t n_lines, const void* a, const
                             int64_t ld_out, int64_t* count_out, void* workspace, size_t ws_bytes, void* stream);
 size_t vpm_wake_convert_workspace_size(int64_t n_lines);
 
+/* vpm_aic_update — the influence matrix of one time step: out = base plus, in every column j
+ * with ring_of_col[j] = q >= 0, the influence n_i . u_q(c_i) of extra ring q (corners r00,
+ * r01, r11, r10 [3][ld_ring], m rings).  Used for the wake row at the trailing edge, whose
+ * rings carry the (unknown) circulation of the trailing-edge panel they hang from (the Kutta
+ * condition, Sec. II.A).  base and out [n][ld] (double, row-major) may be the same array (same
+ * ld); ring_of_col is device int32 [n] (-1: none).  Other arguments as vpm_aic_assemble. */
+vpm_status vpm_aic_update(int64_t n, const double* base, int64_t ld_base, double* out, int64_t ld_out,
+                          const double* colloc, const double* normal, int64_t ld_col, int64_t m, const double* r00,
+                          const double* r01, const double* r11, const double* r10, int64_t ld_ring,
+                          const int32_t* ring_of_col, double core_radius, int32_t vatistas_n, void* stream);
+
+/* vpm_neumann_rhs — right-hand side of the Neumann system (Sec. II.A) for a lattice turning at
+ * omega (host double[3], rad/s) in a free stream v_inf (host double[3], m/s):
+ *   rhs[i] = -((v_inf - omega x c_i + u[i]) . n_i),
+ * u [3][ld_u] (dtype) the velocity the wake and the particles induce at the collocation
+ * points c (colloc, normal [3][ld_col], double).  rhs: device double[n]. */
+vpm_status vpm_neumann_rhs(int32_t dtype, int64_t n, const double* colloc, const double* normal, int64_t ld_col,
+                           const void* u, int64_t ld_u, const double* v_inf, const double* omega, double* rhs,
+                           void* stream);
+
+/* vpm_advect — one explicit Euler move of n points (wake-line points, particles):
+ *   x += dt (u + v_inf);  gamma += dt dgamma  when gamma is not NULL,
+ * all [3][ld] of dtype; v_inf host double[3]. */
+vpm_status vpm_advect(int32_t dtype, int64_t n, double dt, void* x, const void* u, void* gamma, const void* dgamma,
+                      int64_t ld, const double* v_inf, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * vpm_rk3_stage — stage k (0, 1, 2) of Williamson's low-storage third-order Runge-Kutta
  * scheme (Sec. II.B) on Y = (x, Gamma) with register Q = (qx, qg) and F = (u, dgamma):

@@ -105,3 +105,190 @@ def convert(a, b, dgamma, tip_index, n_tip, sigma):
     x = np.array(xs).T if m else np.zeros((3, 0))
     g = np.array(gs).T if m else np.zeros((3, 0))
     return x, g, np.full(m, float(sigma)), counts
+
+
+def te_points(c10, c11, n_blades, n_chord, n_span):
+    """Trailing-edge stations of every blade, (3, n_blades * (n_span + 1)): the downstream
+    corners of the last chordwise row of rings, station k of blade b at b * (n_span + 1) + k."""
+    out = np.empty((3, n_blades * (n_span + 1)))
+    for b in range(n_blades):
+        p0 = (b * n_chord + n_chord - 1) * n_span
+        out[:, b * (n_span + 1):b * (n_span + 1) + n_span] = c10[:, p0:p0 + n_span]
+        out[:, b * (n_span + 1) + n_span] = c11[:, p0 + n_span - 1]
+    return out
+
+
+def rot_z(psi):
+    c, s = math.cos(psi), math.sin(psi)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+class StepOracle:
+    """One explicit time step of the closed blade/wake/particle loop, FP64 on the CPU.
+
+    Blade: the ring lattice `geom` (body frame at azimuth 0) turning at omega about z in the
+    free stream v_inf.  Wake: boundaries B_1 (youngest free row of points) ... B_m; trailed
+    lines of the row between B_r and B_r+1; shed lines along B_r; particles.
+
+    step():
+     1. blade geometry at the current azimuth (rotation about z);
+     2. influence matrix: the blade's (rotation invariant) plus, once a wake exists, the ring
+        (T_k, T_k+1, B_1,k+1, B_1,k) in the column of trailing-edge panel k (Kutta: the wake
+        row at the trailing edge carries that panel's circulation);
+     3. velocity at the collocation points from the particles, the wake lines and the line
+        along B_1 holding the circulation of the last shed row (still open), Neumann
+        right-hand side, dense solve for the ring circulations;
+     4. the trailing-edge points become the youngest boundary; when a wake existed, the row
+        between them and B_1 becomes lines (Eq. 7), the line along B_1 closes with
+        Gamma_prev - Gamma_now, and Gamma_prev <- Gamma_now (before the first shed row
+        Gamma_prev = 0: the starting vortex);
+     5. velocity at every boundary point and at the particles from the blade rings, every line
+        and the particles (particle stretching from the particles only);
+     6. explicit Euler move: x += dt (u + v_inf), Gamma_p += dt dGamma_p/dt;
+     7. when more than n_rows line rows exist, the oldest row's trailed lines and the shed line
+        along the oldest boundary become particles (Eqs. 6-8, tip line = station n_span of the
+        same blade and row; shed lines one particle each);
+     8. azimuth += omega dt.
+    """
+
+    def __init__(self, geom, omega, v_inf, dt, core_radius, vatistas_n, sigma_p, n_tip, n_rows, n_max=64):
+        self.g = {k: np.asarray(geom[k], dtype=np.float64) for k in ("c00", "c01", "c11", "c10", "colloc", "normal")}
+        self.nb, self.nc, self.ns = geom["n_blades"], geom["n_chord"], geom["n_span"]
+        self.te = np.asarray(geom["te"])
+        self.omega, self.v_inf, self.dt = float(omega), np.asarray(v_inf, dtype=np.float64), float(dt)
+        self.rc, self.vn, self.sig, self.n_tip, self.n_rows, self.n_max = (float(core_radius), int(vatistas_n),
+                                                                           float(sigma_p), int(n_tip),
+                                                                           int(n_rows), int(n_max))
+        self.A0 = aic(self.g["c00"], self.g["c01"], self.g["c11"], self.g["c10"], self.g["colloc"],
+                      self.g["normal"], self.rc, self.vn)
+        self.psi = 0.0
+        self.bounds, self.rows, self.sheds = [], [], []  # sheds[r] along bounds[r] (None: not yet)
+        self.gprev = np.zeros(self.nb * self.ns)
+        self.xp, self.gp = np.zeros((3, 0)), np.zeros((3, 0))
+        self.sp = np.zeros(0)
+        self.gamma = None
+
+    def _geom(self):
+        Rm = rot_z(self.psi)
+        rg = {k: Rm @ v for k, v in self.g.items()}
+        T = te_points(rg["c10"], rg["c11"], self.nb, self.nc, self.ns)
+        return rg, T
+
+    def lines(self, pending=None):
+        """All wake lines as (a, b, strength); `pending` adds the line along B_1."""
+        A, B, G = [], [], []
+        ns1 = self.ns + 1
+        for r, tr in enumerate(self.rows):
+            A.append(self.bounds[r])
+            B.append(self.bounds[r + 1])
+            G.append(tr)
+        for r, sh in enumerate(self.sheds):
+            if sh is None:
+                continue
+            p = self.bounds[r]
+            for bl in range(self.nb):
+                A.append(p[:, bl * ns1:bl * ns1 + self.ns])
+                B.append(p[:, bl * ns1 + 1:bl * ns1 + ns1])
+            G.append(sh)
+        if pending is not None and self.bounds:
+            p = self.bounds[0]
+            for bl in range(self.nb):
+                A.append(p[:, bl * ns1:bl * ns1 + self.ns])
+                B.append(p[:, bl * ns1 + 1:bl * ns1 + ns1])
+            G.append(pending)
+        if not A:
+            return np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0)
+        return np.concatenate(A, 1), np.concatenate(B, 1), np.concatenate(G)
+
+    def _induced(self, y, with_pending):
+        u = np.zeros_like(y)
+        if self.xp.shape[1]:
+            u += _eval_pairs(self.xp, self.gp, self.sp, x_tgt=y)[0]
+        a, b, g = self.lines(self.gprev if with_pending else None)
+        if a.shape[1]:
+            u += _segments(a, b, g, y, self.rc, self.vn)
+        return u
+
+    def step(self):
+        rg, T = self._geom()
+        ns1 = self.ns + 1
+        A = self.A0.copy()
+        if self.bounds:
+            B1 = self.bounds[0]
+            for bl in range(self.nb):
+                for k in range(self.ns):
+                    i0, i1 = bl * ns1 + k, bl * ns1 + k + 1
+                    cs = [T[:, i0:i0 + 1], T[:, i1:i1 + 1], B1[:, i1:i1 + 1], B1[:, i0:i0 + 1]]
+                    a, b, _ = ring_edges(*cs)
+                    u = _segments(a, b, np.ones(4), rg["colloc"], self.rc, self.vn)
+                    A[:, self.te[bl * self.ns + k]] += (u * rg["normal"]).sum(0)
+        u = self._induced(rg["colloc"], with_pending=True)
+        w = np.array([0.0, 0.0, self.omega])
+        vrel = self.v_inf[:, None] - np.cross(w, rg["colloc"].T).T + u
+        gam = solve(A, -(vrel * rg["normal"]).sum(0))
+        self.gamma = gam
+        # the trailing-edge points join the wake as its youngest boundary
+        had_wake = bool(self.bounds)
+        self.bounds.insert(0, T.copy())
+        self.sheds.insert(0, None)
+        if had_wake:
+            trs, shs = [], []
+            for bl in range(self.nb):
+                gte = gam[self.te[bl * self.ns:(bl + 1) * self.ns]]
+                tr, sh = shed(gte, self.gprev[bl * self.ns:(bl + 1) * self.ns])
+                trs.append(tr)
+                shs.append(sh)
+            self.rows.insert(0, np.concatenate(trs))  # between the trailing edge and B_1
+            self.sheds[1] = np.concatenate(shs)      # along B_1
+            self.gprev = gam[self.te].copy()
+        # velocity at every boundary point (the trailing edge included) and at the particles
+        pts = np.concatenate(self.bounds, 1)
+        a, b, gl = self.lines()
+        ra, rb, rgm = ring_edges(rg["c00"], rg["c01"], rg["c11"], rg["c10"], gam)
+        allA = np.concatenate([ra, a], 1)
+        allB = np.concatenate([rb, b], 1)
+        allG = np.concatenate([rgm, gl])
+        up = _segments(allA, allB, allG, pts, self.rc, self.vn)
+        if self.xp.shape[1]:
+            up += _eval_pairs(self.xp, self.gp, self.sp, x_tgt=pts)[0]
+            uq, dq = _eval_pairs(self.xp, self.gp, self.sp)
+            uq += _segments(allA, allB, allG, self.xp, self.rc, self.vn)
+            self.xp = self.xp + self.dt * (uq + self.v_inf[:, None])
+            self.gp = self.gp + self.dt * dq
+        pts = pts + self.dt * (up + self.v_inf[:, None])
+        nb_pts = T.shape[1]
+        self.bounds = [pts[:, i * nb_pts:(i + 1) * nb_pts] for i in range(len(self.bounds))]
+        # conversion of the oldest row
+        if len(self.rows) > self.n_rows:
+            r = len(self.rows) - 1
+            a = [self.bounds[r]]
+            b = [self.bounds[r + 1]]
+            tip = [np.repeat(np.arange(self.nb) * ns1 + self.ns, ns1)]
+            dg = [self.rows[r]]
+            p = self.bounds[r + 1]
+            for bl in range(self.nb):
+                a.append(p[:, bl * ns1:bl * ns1 + self.ns])
+                b.append(p[:, bl * ns1 + 1:bl * ns1 + ns1])
+            dg.append(self.sheds[r + 1])
+            tip.append(-np.ones(self.nb * self.ns, dtype=np.int64))
+            x, g, s, _ = convert(np.concatenate(a, 1), np.concatenate(b, 1), np.concatenate(dg), np.concatenate(tip),
+                                 self.n_tip, self.sig)
+            self.xp = np.concatenate([self.xp, x], 1)
+            self.gp = np.concatenate([self.gp, g], 1)
+            self.sp = np.concatenate([self.sp, s])
+            del self.rows[r]
+            del self.bounds[r + 1]
+            del self.sheds[r + 1]
+        self.psi += self.omega * self.dt
+        return gam
+
+    def total_vorticity(self):
+        """sum over lines of strength x (b - a), plus the particles, plus the line along B_1 that
+        the next shed row closes (Gamma_prev): zero for a closed system of rings."""
+        a, b, g = self.lines(self.gprev)
+        return (g * (b - a)).sum(1) + self.gp.sum(1)
+
+
+def _eval_pairs(*args, **kw):
+    from . import eval_pairs
+    return eval_pairs(*args, **kw)

@@ -400,6 +400,57 @@ def vpm_wake_convert(a, b, dgamma, tip_index, n_tip, sigma, capacity, *, n_max=6
     return x_out, gamma_out, sigma_out, count_out
 
 
+def _host3(v):
+    return (ctypes.c_double * 3)(*[float(c) for c in v])
+
+
+def vpm_aic_update(base, colloc, normal, r00, r01, r11, r10, ring_of_col, core_radius, vatistas_n=2, *, out=None,
+                   stream=None):
+    """out = base + the influence of extra rings in the columns ring_of_col maps them to."""
+    torch = _torch()
+    lib = _lib.load()
+    n = colloc.shape[1]
+    m = r00.shape[1]
+    for name, t in (("r00", r00), ("r01", r01), ("r11", r11), ("r10", r10)):
+        _vec(t, name, m, torch.float64)
+    _scal(ring_of_col, "ring_of_col", n, torch.int32)
+    if out is None:
+        out = torch.empty_like(base)
+    ldr = _ld(r00) if m > 0 else 0
+    st = lib.vpm_aic_update(n, _p(base), int(base.stride(0)), _p(out), int(out.stride(0)), _p(colloc), _p(normal),
+                            _ld(colloc), m, _p(r00), _p(r01), _p(r11), _p(r10), ldr, _p(ring_of_col),
+                            float(core_radius), int(vatistas_n), _stream(stream))
+    _check("vpm_aic_update", st)
+    return out
+
+
+def vpm_neumann_rhs(colloc, normal, u, v_inf, omega, *, rhs_out=None, stream=None):
+    """rhs_i = -((v_inf - omega x c_i + u_i) . n_i) (Neumann condition, Sec. II.A)."""
+    torch = _torch()
+    lib = _lib.load()
+    n = colloc.shape[1]
+    _vec(u, "u", n)
+    if rhs_out is None:
+        rhs_out = torch.empty(n, dtype=torch.float64, device=colloc.device)
+    st = lib.vpm_neumann_rhs(_code(u), n, _p(colloc), _p(normal), _ld(colloc), _p(u), _ld(u), _host3(v_inf),
+                             _host3(omega), _p(rhs_out), _stream(stream))
+    _check("vpm_neumann_rhs", st)
+    return rhs_out
+
+
+def vpm_advect(x, u, dt, v_inf=(0.0, 0.0, 0.0), *, gamma=None, dgamma=None, stream=None):
+    """x += dt (u + v_inf) (and gamma += dt dgamma) in place."""
+    lib = _lib.load()
+    n = x.shape[1]
+    _vec(u, "u", n, x.dtype)
+    if _ld(u) != _ld(x) or (gamma is not None and (_ld(gamma) != _ld(x) or _ld(dgamma) != _ld(x))):
+        raise ValueError("x, u, gamma and dgamma must share one leading dimension")
+    st = lib.vpm_advect(_code(x), n, float(dt), _p(x), _p(u), _p(gamma), _p(dgamma), _ld(x), _host3(v_inf),
+                        _stream(stream))
+    _check("vpm_advect", st)
+    return x
+
+
 def vpm_eval_segments(a, b, gamma_seg, x_tgt, core_radius, vatistas_n=2, *, u_out=None, accumulate=False,
                       stream=None):
     """Velocity at x_tgt induced by straight vortex segments a->b (Vatistas core, Sec. II.A)."""

@@ -40,6 +40,10 @@ SIGNATURES = {
     "vpm_wake_convert": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_i32, c_i32, c_dbl, c_i64, c_vp, c_vp,
                                  c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "vpm_wake_convert_workspace_size": (c_sz, [c_i64]),
+    "vpm_aic_update": (c_i32, [c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64,
+                               c_vp, c_dbl, c_i32, c_vp]),
+    "vpm_neumann_rhs": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
+    "vpm_advect": (c_i32, [c_i32, c_i64, c_dbl, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]),
     "vpm_eval_segments": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_dbl, c_i32, c_i64, c_vp, c_i64,
                                   c_vp, c_i64, c_i32, c_vp]),
     "vpm_backward": (c_i32, [c_i32, c_i32, c_i64p, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64,

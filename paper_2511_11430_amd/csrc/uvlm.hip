@@ -294,6 +294,81 @@ __global__ __launch_bounds__(256) void k_conv_emit(int64_t n, const T* a, const 
     }
 }
 
+// AIC of one time step: out = base plus, in the columns that ring_of_col maps to an extra ring q,
+// the influence of ring q (the wake row at the trailing edge carries the unknown circulation
+// of the trailing-edge panel it hangs from).
+struct AicUpdArgs {
+    int64_t n;
+    const double* base;
+    double* out;
+    int64_t ldb, ldo;
+    const double* col;
+    const double* nrm;
+    int64_t ldc;
+    const double* r00;
+    const double* r01;
+    const double* r11;
+    const double* r10;
+    int64_t ldr;
+    const int32_t* ring_of_col;
+    int64_t m;
+    double rc2n, inv_n;
+    int vn;
+};
+
+__global__ __launch_bounds__(256) void k_aic_update(AicUpdArgs a) {
+    const int64_t i = blockIdx.y;
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= a.n || j >= a.n) return;
+    double v = a.base[i * a.ldb + j];
+    const int64_t q = a.ring_of_col[j];
+    if (q >= 0 && q < a.m) {
+        const double p[3] = {a.col[i], a.col[a.ldc + i], a.col[2 * a.ldc + i]};
+        const double nn[3] = {a.nrm[i], a.nrm[a.ldc + i], a.nrm[2 * a.ldc + i]};
+        const double* cs[4] = {a.r00, a.r01, a.r11, a.r10};
+        double c[4][3];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) c[e][d] = cs[e][d * a.ldr + q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            double u[3];
+            segment_unit(p, c[e], c[(e + 1) & 3], a.rc2n, a.inv_n, a.vn, u);
+            v += nn[0] * u[0] + nn[1] * u[1] + nn[2] * u[2];
+        }
+    }
+    a.out[i * a.ldo + j] = v;
+}
+
+// Neumann right-hand side: rhs_i = -((v_inf - omega x c_i + u_i) . n_i).
+template <typename T>
+__global__ __launch_bounds__(256) void k_neumann_rhs(int64_t n, const double* col, const double* nrm, int64_t ldc,
+                                                     const T* u, int64_t ldu, double v0, double v1, double v2,
+                                                     double w0, double w1, double w2, double* rhs) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double c0 = col[i], c1 = col[ldc + i], c2 = col[2 * ldc + i];
+    const double r0 = v0 - (w1 * c2 - w2 * c1) + double(u[i]);
+    const double r1 = v1 - (w2 * c0 - w0 * c2) + double(u[ldu + i]);
+    const double r2 = v2 - (w0 * c1 - w1 * c0) + double(u[2 * ldu + i]);
+    rhs[i] = -(r0 * nrm[i] + r1 * nrm[ldc + i] + r2 * nrm[2 * ldc + i]);
+}
+
+// Explicit Euler move of points: x += dt (u + v_inf); optionally g += dt dg.
+template <typename T>
+__global__ __launch_bounds__(256) void k_advect(int64_t n, double dt, T* x, const T* u, T* g, const T* dg, int64_t ld,
+                                                double v0, double v1, double v2) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v[3] = {v0, v1, v2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c * ld + i] = T(double(x[c * ld + i]) + dt * (double(u[c * ld + i]) + v[c]));
+        if (g) g[c * ld + i] = T(double(g[c * ld + i]) + dt * double(dg[c * ld + i]));
+    }
+}
+
 }  // namespace
 
 hipError_t launch_aic(int64_t n, const double* c00, const double* c01, const double* c11, const double* c10,
@@ -382,6 +457,61 @@ hipError_t launch_wake_convert(int dtype, int64_t n, const void* a, const void* 
     else
         hipLaunchKernelGGL(k_conv_emit<float>, dim3(nb), dim3(256), 0, st, n, (const float*)a, (const float*)b, ld,
                            (const float*)dg, cnt, first, sigma, capacity, (float*)xo, (float*)go, (float*)so, ldo);
+    return hipGetLastError();
+}
+
+}  // namespace vpm
+
+namespace vpm {
+
+hipError_t launch_aic_update(int64_t n, const double* base, int64_t ldb, double* out, int64_t ldo, const double* col,
+                             const double* nrm, int64_t ldc, int64_t m, const double* r00, const double* r01,
+                             const double* r11, const double* r10, int64_t ldr, const int32_t* ring_of_col,
+                             double rc, int vn, hipStream_t st) {
+    AicUpdArgs a;
+    a.n = n;
+    a.base = base;
+    a.out = out;
+    a.ldb = ldb;
+    a.ldo = ldo;
+    a.col = col;
+    a.nrm = nrm;
+    a.ldc = ldc;
+    a.r00 = r00;
+    a.r01 = r01;
+    a.r11 = r11;
+    a.r10 = r10;
+    a.ldr = ldr;
+    a.ring_of_col = ring_of_col;
+    a.m = m;
+    a.vn = vn;
+    a.inv_n = 1.0 / double(vn);
+    a.rc2n = rc > 0.0 ? pow(rc * rc, double(vn)) : 0.0;
+    hipLaunchKernelGGL(k_aic_update, dim3(unsigned((n + 255) / 256), unsigned(n)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_neumann_rhs(int dtype, int64_t n, const double* col, const double* nrm, int64_t ldc, const void* u,
+                              int64_t ldu, const double* vinf, const double* omega, double* rhs, hipStream_t st) {
+    const unsigned nb = unsigned((n + 255) / 256);
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_neumann_rhs<double>, dim3(nb), dim3(256), 0, st, n, col, nrm, ldc, (const double*)u, ldu,
+                           vinf[0], vinf[1], vinf[2], omega[0], omega[1], omega[2], rhs);
+    else
+        hipLaunchKernelGGL(k_neumann_rhs<float>, dim3(nb), dim3(256), 0, st, n, col, nrm, ldc, (const float*)u, ldu,
+                           vinf[0], vinf[1], vinf[2], omega[0], omega[1], omega[2], rhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_advect(int dtype, int64_t n, double dt, void* x, const void* u, void* g, const void* dg, int64_t ld,
+                         const double* vinf, hipStream_t st) {
+    const unsigned nb = unsigned((n + 255) / 256);
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_advect<double>, dim3(nb), dim3(256), 0, st, n, dt, (double*)x, (const double*)u,
+                           (double*)g, (const double*)dg, ld, vinf[0], vinf[1], vinf[2]);
+    else
+        hipLaunchKernelGGL(k_advect<float>, dim3(nb), dim3(256), 0, st, n, dt, (float*)x, (const float*)u, (float*)g,
+                           (const float*)dg, ld, vinf[0], vinf[1], vinf[2]);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -890,6 +891,60 @@ vpm_status vpm_wake_convert(int32_t dtype, int64_t n_lines, const void* a, const
     return hip_status(vpm::launch_wake_convert(dtype, n_lines, a, b, ld_line, dgamma, tip_index, n_tip, n_max, sigma,
                                                capacity, x_out, gamma_out, sigma_out, ld_out, count_out, workspace,
                                                static_cast<hipStream_t>(stream)));
+}
+
+
+vpm_status vpm_aic_update(int64_t n, const double* base, int64_t ld_base, double* out, int64_t ld_out,
+                          const double* colloc, const double* normal, int64_t ld_col, int64_t m, const double* r00,
+                          const double* r01, const double* r11, const double* r10, int64_t ld_ring,
+                          const int32_t* ring_of_col, double core_radius, int32_t vatistas_n, void* stream) {
+    if (n < 1 || n > 32768 || ld_base < n || ld_out < n || ld_col < n || m < 0 || ld_ring < m) return VPM_ERR_SIZE;
+    if (!base || !out || !colloc || !normal || !ring_of_col) return VPM_ERR_NULL;
+    if (m > 0 && (!r00 || !r01 || !r11 || !r10)) return VPM_ERR_NULL;
+    if (!(core_radius >= 0.0) || core_radius > 1e30) return VPM_ERR_SIZE;
+    if (vatistas_n < 1 || vatistas_n > 16) return VPM_ERR_ENUM;
+    const Range ro = span(out, 1, n * ld_out, n * ld_out, 8), rb = span(base, 1, n * ld_base, n * ld_base, 8);
+    if (overlap(ro, rb) && !(base == out && ld_base == ld_out)) return VPM_ERR_ALIAS;
+    const Range ins[7] = {span(colloc, 3, ld_col, n, 8), span(normal, 3, ld_col, n, 8), span(r00, 3, ld_ring, m, 8),
+                          span(r01, 3, ld_ring, m, 8),   span(r11, 3, ld_ring, m, 8),  span(r10, 3, ld_ring, m, 8),
+                          span(ring_of_col, 1, n, n, 4)};
+    for (const Range& r : ins)
+        if (overlap(ro, r)) return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_aic_update(n, base, ld_base, out, ld_out, colloc, normal, ld_col, m, r00, r01, r11,
+                                             r10, ld_ring, ring_of_col, core_radius, vatistas_n,
+                                             static_cast<hipStream_t>(stream)));
+}
+
+vpm_status vpm_neumann_rhs(int32_t dtype, int64_t n, const double* colloc, const double* normal, int64_t ld_col,
+                           const void* u, int64_t ld_u, const double* v_inf, const double* omega, double* rhs,
+                           void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n < 0 || ld_col < n || ld_u < n || n > INT32_MAX) return VPM_ERR_SIZE;
+    if (!v_inf || !omega) return VPM_ERR_NULL;
+    if (n == 0) return VPM_OK;
+    if (!colloc || !normal || !u || !rhs) return VPM_ERR_NULL;
+    const Range rr = span(rhs, 1, n, n, 8);
+    if (overlap(rr, span(colloc, 3, ld_col, n, 8)) || overlap(rr, span(normal, 3, ld_col, n, 8)) ||
+        overlap(rr, span(u, 3, ld_u, n, elem_size(dtype))))
+        return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_neumann_rhs(dtype, n, colloc, normal, ld_col, u, ld_u, v_inf, omega, rhs,
+                                              static_cast<hipStream_t>(stream)));
+}
+
+vpm_status vpm_advect(int32_t dtype, int64_t n, double dt, void* x, const void* u, void* gamma, const void* dgamma,
+                      int64_t ld, const double* v_inf, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n < 0 || ld < n || n > INT32_MAX || !(dt == dt) || fabs(dt) > 1e30) return VPM_ERR_SIZE;
+    if (!v_inf) return VPM_ERR_NULL;
+    if (n == 0) return VPM_OK;
+    if (!x || !u || (gamma && !dgamma)) return VPM_ERR_NULL;
+    const size_t es = elem_size(dtype);
+    const Range rx = span(x, 3, ld, n, es), rg = span(gamma, 3, ld, n, es);
+    const Range ins[2] = {span(u, 3, ld, n, es), span(dgamma, 3, ld, n, es)};
+    for (const Range& r : ins)
+        if (overlap(rx, r) || overlap(rg, r)) return VPM_ERR_ALIAS;
+    if (overlap(rx, rg)) return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_advect(dtype, n, dt, x, u, gamma, dgamma, ld, v_inf, static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

@@ -135,6 +135,14 @@ hipError_t launch_lu_solve(int64_t n, const double* LU, int64_t lda, const int32
                            hipStream_t st);
 hipError_t launch_wake_shed(int dtype, int n_blades, int n_span, const void* gb, const int32_t* te, void* prev,
                             void* trailed, void* shed, hipStream_t st);
+hipError_t launch_aic_update(int64_t n, const double* base, int64_t ldb, double* out, int64_t ldo, const double* col,
+                             const double* nrm, int64_t ldc, int64_t m, const double* r00, const double* r01,
+                             const double* r11, const double* r10, int64_t ldr, const int32_t* ring_of_col,
+                             double rc, int vn, hipStream_t st);
+hipError_t launch_neumann_rhs(int dtype, int64_t n, const double* col, const double* nrm, int64_t ldc, const void* u,
+                              int64_t ldu, const double* vinf, const double* omega, double* rhs, hipStream_t st);
+hipError_t launch_advect(int dtype, int64_t n, double dt, void* x, const void* u, void* g, const void* dg, int64_t ld,
+                         const double* vinf, hipStream_t st);
 size_t conv_workspace(int64_t n);
 hipError_t launch_wake_convert(int dtype, int64_t n, const void* a, const void* b, int64_t ld, const void* dg,
                                const int32_t* tip, int n_tip, int n_max, double sigma, int64_t capacity, void* xo,

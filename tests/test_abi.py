@@ -296,3 +296,26 @@ def test_uvlm_validation():
     assert conv(wsb=need - 1) == WORKSPACE
     assert conv(x=P(0)) == ALIAS
     assert conv(g=P(4)) == ALIAS
+
+
+def test_step_kernels_validation():
+    lib = _lib.load()
+    v3 = (ctypes.c_double * 3)(0.0, 0.0, -1.0)
+    u = lib.vpm_aic_update
+    assert u(0, P(0), 1, P(1), 1, P(2), P(3), 1, 0, None, None, None, None, 0, P(4), 0.0, 2, None) == SIZE
+    assert u(8, None, 8, P(1), 8, P(2), P(3), 8, 0, None, None, None, None, 0, P(4), 0.0, 2, None) == NULL
+    assert u(8, P(0), 8, P(1), 8, P(2), P(3), 8, 4, None, P(6), P(7), P(8), 4, P(4), 0.0, 2, None) == NULL
+    assert u(8, P(0), 8, P(0) , 7, P(2), P(3), 8, 0, None, None, None, None, 0, P(4), 0.0, 2, None) == SIZE
+    assert u(8, P(0), 8, P(2), 8, P(2), P(3), 8, 0, None, None, None, None, 0, P(4), 0.0, 2, None) == ALIAS
+    r = lib.vpm_neumann_rhs
+    assert r(7, 8, P(0), P(1), 8, P(2), 8, v3, v3, P(3), None) == DTYPE
+    assert r(F64, 8, P(0), P(1), 7, P(2), 8, v3, v3, P(3), None) == SIZE
+    assert r(F64, 8, P(0), P(1), 8, P(2), 8, None, v3, P(3), None) == NULL
+    assert r(F64, 8, P(0), P(1), 8, P(2), 8, v3, v3, P(0), None) == ALIAS
+    assert r(F64, 0, None, None, 0, None, 0, v3, v3, None, None) == OK
+    a = lib.vpm_advect
+    assert a(F64, 8, 0.1, P(0), P(1), None, None, 7, v3, None) == SIZE
+    assert a(F64, 8, 0.1, P(0), None, None, None, 8, v3, None) == NULL
+    assert a(F64, 8, 0.1, P(0), P(1), P(2), None, 8, v3, None) == NULL
+    assert a(F64, 8, 0.1, P(0), P(0), None, None, 8, v3, None) == ALIAS
+    assert a(F64, 0, 0.1, None, None, None, None, 0, v3, None) == OK
