@@ -44,7 +44,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("pair_forward.hip", "device_math.h", "vpm_internal.h"):
+    for f in ("pair_forward.hip", "device_math.h"):
         with open(os.path.join(ROOT, "paper_2511_11430_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -268,6 +268,30 @@ def main():
             "vreman_ms": round(vre_ms, 4), "pse_ms": round(pse_ms, 3),
             "rhs_with_viscous_ms": round(grad_ms + vre_ms + pse_ms, 3)}
         del Jv, nut, vol, dv, pse_ws
+
+        # ------------------------------------------------------------------ closed solver step
+        # hover lattice (2 x 8 x 32 rings) turning in its own 65,536-particle wake (FP32C wake,
+        # FP64 blade solve): influence update + LU + solve, shedding, velocities, Euler move,
+        # conversion of the oldest row (Eqs. 6-8)
+        from paper_2511_11430_amd.solver import Step
+        c2 = W.config2()
+        geom = W.blade_rings()
+        st = Step(geom, omega=W.OMEGA, v_inf=(0.0, 0.0, 0.0), dt=W.DT, core_radius=c2["core_radius"], vatistas_n=2,
+                  sigma_p=0.02 * W.R, n_tip=2, n_rows=8, dtype=torch.float32, capacity=1 << 18, device=dev)
+        st.add_particles(f32(c2["x"]), f32(c2["gamma"]), f32(c2["sigma"]))
+        for _ in range(10):  # build up the line rows so that every timed step converts one
+            st.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_steps = 3
+        for _ in range(n_steps):
+            st.step()
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / n_steps
+        result["solver_step"] = {"workload": "hover lattice 2x8x32 rings in a 65,536-particle wake, 8 line rows",
+                                 "ms_per_step": round(step_ms, 3), "particles_after": int(st.np),
+                                 "panels": int(geom["colloc"].shape[1])}
+        del st
 
         # ------------------------------------------------------------------ adjoint / forward
         c4 = W.config4()

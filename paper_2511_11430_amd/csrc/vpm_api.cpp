@@ -159,7 +159,7 @@ hipError_t stage_and_copy(const std::vector<unsigned char>& blob, void* dst, hip
 
 // ------------------------------------------------------------------ kernel-shape plans
 // Tuned FP32C kernel shape per (single set / batched, ceil(log2(targets))) bucket, written by
-// vpm_set_plan (the tuner); 0 = not set, then variant 1.  Guarded by g_mutex.
+// vpm_set_plan (the tuner); 0 = not set, then the built-in choice.  Guarded by g_mutex.
 constexpr int kPlanBuckets = 40;
 int g_plan[2][kPlanBuckets] = {};
 
@@ -171,12 +171,19 @@ int plan_bucket(int64_t n) {
 
 // 0-based variant for an FP32C launch when the caller leaves opt->variant at 0.  The gradient
 // mode has a single shape.
+// Built-in choice without a tuned plan (what the tuner picks on MI355X): (1, 256, 4) below 16K
+// targets and (1, 512, 2) above for one set; (1, 128, 2) for batches.
+int default_variant(bool batched, int64_t n_tgt) {
+    if (batched) return 5;
+    return n_tgt <= 16384 ? 2 : 7;
+}
+
 int choose_variant(const vpm_options& o, bool batched, int64_t n_tgt) {
     if (o.gradient) return vpm::kGradientVariant;
     if (o.variant > 0) return o.variant - 1;
     std::lock_guard<std::mutex> lock(g_mutex);
     const int v = g_plan[batched ? 1 : 0][plan_bucket(n_tgt)];
-    return v > 0 ? v - 1 : 0;
+    return v > 0 ? v - 1 : default_variant(batched, n_tgt);
 }
 
 int fwd_mode(const vpm_options& o, bool stretch) {

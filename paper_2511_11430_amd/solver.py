@@ -201,3 +201,13 @@ class Step:
 
     def particles(self):
         return self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np]
+
+    def add_particles(self, x, g, s):
+        """Append particles (x, gamma of shape (3, m), sigma (m,)), e.g. an existing wake."""
+        m = x.shape[1]
+        if self.np + m > self.cap:
+            raise RuntimeError(f"particle capacity {self.cap} exceeded")
+        self.xp[:, self.np:self.np + m].copy_(x)
+        self.gp[:, self.np:self.np + m].copy_(g)
+        self.sp[self.np:self.np + m].copy_(s)
+        self.np += m
