@@ -47,9 +47,10 @@ def _load():
         lib.orc_vreman.argtypes = [i64, _dp, _dp, dbl, _dp]
         lib.orc_pse.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, dbl, _dp, i32]
         lib.orc_pse_at.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, dbl, i64, _lp, _dp, i32]
+        lib.orc_segments_gradient.argtypes = [i64, _dp, _dp, _dp, dbl, i32, i64, _dp, _dp, i32]
         for f in ("orc_weights", "orc_ghk", "orc_eval", "orc_eval_jvp", "orc_segments",
                   "orc_rk3_program", "orc_rk3_program_jvp", "orc_diagnostics", "orc_gradient",
-                  "orc_vreman", "orc_pse", "orc_pse_at"):
+                  "orc_vreman", "orc_pse", "orc_pse_at", "orc_segments_gradient"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -184,6 +185,21 @@ def segments(a, b, gam_seg, x_tgt, core_radius, vatistas_n=2, nthreads=0):
                           u.ctypes.data_as(_dp), int(nthreads))
     _check(rc, "segments")
     return u
+
+
+def segments_gradient(a, b, gam_seg, x_tgt, core_radius, vatistas_n=2, nthreads=0):
+    """Velocity gradient J[a, b] = du_a/dx_b (3, 3, n_tgt) of straight segments with the
+    Vatistas core (Sec. II.A) at the targets, by forward-mode differentiation of the segment law."""
+    lib = _load()
+    A, B = _vec(a, "a"), _vec(b, "b")
+    g = np.ascontiguousarray(gam_seg, dtype=np.float64).reshape(-1)
+    xt = _vec(x_tgt, "x_tgt")
+    J = np.zeros((9, xt.shape[1]))
+    rc = lib.orc_segments_gradient(A.shape[1], A.ctypes.data_as(_dp), B.ctypes.data_as(_dp), g.ctypes.data_as(_dp),
+                                   float(core_radius), int(vatistas_n), xt.shape[1], xt.ctypes.data_as(_dp),
+                                   J.ctypes.data_as(_dp), int(nthreads))
+    _check(rc, "segments_gradient")
+    return J.reshape(3, 3, -1)
 
 
 def rk3_program(x, gam, sig, n_steps, dt, y_ctrl=None, scheme=TRANSPOSED, sigma_rule=SIGMA_SOURCE,

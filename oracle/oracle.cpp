@@ -484,6 +484,24 @@ int orc_segments(int64_t nseg, const double* A, const double* B, const double* g
     return 0;
 }
 
+// Velocity gradient of the segments at the targets, J [9][nt] (J[(3a+b) nt + t] = du_a/dx_b),
+// by forward-mode differentiation of the segment law along each coordinate of the targets.
+int orc_segments_gradient(int64_t nseg, const double* A, const double* B, const double* gam, double rc, int vn,
+                          int64_t nt, const double* xt, double* J, int nthreads) {
+    if (nseg < 0 || nt < 0 || !xt || !J || (nseg > 0 && (!A || !B || !gam))) return 1;
+    if (!(rc >= 0.0) || vn < 1) return 1;
+    set_threads<double>(nthreads);
+    std::vector<Dual> X(3 * size_t(nt)), U(3 * size_t(nt));
+    for (int b = 0; b < 3; ++b) {
+        for (int c = 0; c < 3; ++c)
+            for (int64_t t = 0; t < nt; ++t) X[c * nt + t] = Dual(xt[c * nt + t], c == b ? 1.0 : 0.0);
+        eval_segments<Dual>(nseg, A, B, gam, rc, vn, nt, X.data(), U.data());
+        for (int a = 0; a < 3; ++a)
+            for (int64_t t = 0; t < nt; ++t) J[(3 * a + b) * nt + t] = U[a * nt + t].d;
+    }
+    return 0;
+}
+
 // Runs nsteps RK3 steps from (x, G) in place, then the control-point velocity uc [3][m]
 // and the loss sum_c uc_z^2.
 int orc_rk3_program(int64_t n, double* x, double* G, const double* sig, int nsteps, double dt,

@@ -97,3 +97,44 @@ def test_degenerate_segments_contribute_nothing():
     P = np.array([[0.0, 0.5, 1.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
     u = oracle.segments(A, B, [1.0, 1.0, 1.0], P, core_radius=0.02)
     assert np.all(u == 0)
+
+
+# ------------------------------------------------------------------ velocity gradient (lattice on particles)
+
+@pytest.mark.parametrize("rc,vn", [(0.0, 2), (0.05, 2), (0.05, 1), (0.08, 3)])
+def test_segment_gradient_matches_central_differences(rc, vn):
+    rng = np.random.default_rng(11)
+    a = rng.normal(size=(3, 20))
+    b = a + rng.normal(size=(3, 20)) * 0.3
+    g = rng.normal(size=20)
+    y = rng.normal(size=(3, 6))
+    J = oracle.segments_gradient(a, b, g, y, rc, vn)
+    h = 1e-6
+    Jf = np.zeros_like(J)
+    for c in range(3):
+        yp, ym = y.copy(), y.copy()
+        yp[c] += h
+        ym[c] -= h
+        Jf[:, c, :] = (oracle.segments(a, b, g, yp, rc, vn) - oracle.segments(a, b, g, ym, rc, vn)) / (2 * h)
+    assert np.abs(J - Jf).max() <= 1e-8 * np.abs(J).max()
+
+
+def test_segment_gradient_is_divergence_free():
+    """The core factor depends only on the distance to the line, across which the velocity is
+    azimuthal, so the cored field stays divergence free: tr J = 0."""
+    rng = np.random.default_rng(12)
+    a = rng.normal(size=(3, 50))
+    b = a + rng.normal(size=(3, 50)) * 0.2
+    J = oracle.segments_gradient(a, b, rng.normal(size=50), rng.normal(size=(3, 40)), 0.05, 2)
+    assert np.abs(np.einsum("aat->t", J)).max() <= 1e-13 * np.abs(J).max()
+
+
+def test_segment_gradient_infinite_line_profile():
+    """A long line along z (Vatistas n = 2): u_y(x) = G x / (2 pi sqrt(rc^4 + x^4)), so
+    du_y/dx = G (rc^4 - x^4) / (2 pi (rc^4 + x^4)^(3/2)) on the x axis."""
+    G, rc, L = 1.7, 0.05, 1e4
+    a, b = np.array([[0.0], [0.0], [-L]]), np.array([[0.0], [0.0], [L]])
+    for d in (0.01, 0.05, 0.2):
+        J = oracle.segments_gradient(a, b, [G], np.array([[d], [0.0], [0.0]]), rc, 2)
+        ref = G * (rc ** 4 - d ** 4) / (2 * math.pi * (rc ** 4 + d ** 4) ** 1.5)
+        assert J[1, 0, 0] == pytest.approx(ref, rel=1e-7, abs=1e-8 * G / rc ** 2)
