@@ -212,6 +212,25 @@ vpm_status vpm_eval_segments(int32_t dtype, int64_t n_seg, const void* a, const 
                              int32_t vatistas_n, int64_t n_tgt, const void* x_tgt, int64_t ld_tgt,
                              void* u_out, int64_t ld_out, int32_t accumulate, void* stream);
 
+/* vpm_eval_segments_gradient — the segments' velocity, its gradient and the stretching they
+ * impose on particles at the targets (Sec. II.A segment law; the stretching term of the
+ * particle equations, Sec. II.B, with the segments' share of the velocity):
+ *   J[a][b](P) = du_a/dP_b of the vpm_eval_segments law, differentiated exactly (the core
+ *   factor included); pairs that law drops contribute nothing.
+ *   dgamma = J^T gamma_tgt (VPM_STRETCH_TRANSPOSED) or J gamma_tgt (VPM_STRETCH_CLASSICAL).
+ *  Segment arguments, core_radius, vatistas_n as vpm_eval_segments; x_tgt, gamma_tgt [3][ld_tgt]
+ *  (gamma_tgt only read when dgamma_out is given).
+ *  u_out [3][ld_out], grad_out [9][ld_out] (row 3a + b holds du_a/dx_b), dgamma_out
+ *  [3][ld_out]: each may be NULL, not all three (unless n_tgt == 0); outputs must not overlap
+ *  inputs or each other.
+ *  accumulate: 1 = outputs += result, 0 = outputs = result.
+ * Returns VPM_OK or the first violated condition. */
+vpm_status vpm_eval_segments_gradient(int32_t dtype, int64_t n_seg, const void* a, const void* b,
+                                      const void* gamma_seg, int64_t ld_seg, double core_radius,
+                                      int32_t vatistas_n, int64_t n_tgt, const void* x_tgt, const void* gamma_tgt,
+                                      int64_t ld_tgt, int32_t scheme, void* u_out, void* grad_out,
+                                      void* dgamma_out, int64_t ld_out, int32_t accumulate, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * vpm_backward — vector-Jacobian product of vpm_eval_velocity_stretching (transposed
  * scheme, n_batch == 1): given seeds u_bar [3][ld_tgt] and dgamma_bar [3][ld_tgt] on the

@@ -27,6 +27,7 @@ import math
 import numpy as np
 
 from . import segments as _segments
+from . import segments_gradient as _segments_gradient
 
 
 def ring_edges(c00, c01, c11, c10, gamma=None):
@@ -143,7 +144,8 @@ class StepOracle:
         Gamma_prev - Gamma_now, and Gamma_prev <- Gamma_now (before the first shed row
         Gamma_prev = 0: the starting vortex);
      5. velocity at every boundary point and at the particles from the blade rings, every line
-        and the particles (particle stretching from the particles only);
+        and the particles; particle stretching by the whole field (transposed scheme: the
+        particles' share plus J^T Gamma_p with J the rings' and lines' velocity gradient);
      6. explicit Euler move: x += dt (u + v_inf), Gamma_p += dt dGamma_p/dt;
      7. when more than n_rows line rows exist, the oldest row's trailed lines and the shed line
         along the oldest boundary become particles (Eqs. 6-8, tip line = station n_span of the
@@ -253,6 +255,9 @@ class StepOracle:
             up += _eval_pairs(self.xp, self.gp, self.sp, x_tgt=pts)[0]
             uq, dq = _eval_pairs(self.xp, self.gp, self.sp)
             uq += _segments(allA, allB, allG, self.xp, self.rc, self.vn)
+            # stretching by the rings' and lines' share of the velocity gradient (transposed)
+            J = _segments_gradient(allA, allB, allG, self.xp, self.rc, self.vn)
+            dq += np.einsum("abn,an->bn", J, self.gp)
             self.xp = self.xp + self.dt * (uq + self.v_inf[:, None])
             self.gp = self.gp + self.dt * dq
         pts = pts + self.dt * (up + self.v_inf[:, None])

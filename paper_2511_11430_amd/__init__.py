@@ -17,7 +17,7 @@ F64, F32C = 0, 1
 TRANSPOSED, CLASSICAL = 0, 1
 SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
 
-__all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_backward", "vpm_rk3_stage",
+__all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_eval_segments_gradient", "vpm_backward", "vpm_rk3_stage",
            "vpm_rk3_stage_backward", "vpm_diagnostics", "vpm_workspace_size", "vpm_variant_count",
            "vpm_variant_info", "vpm_axial_loss", "vpm_convert", "vpm_validate_inputs", "vpm_set_plan", "vpm_get_plan", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
            "SIGMA_SYMMETRIC"]
@@ -474,6 +474,61 @@ def vpm_eval_segments(a, b, gamma_seg, x_tgt, core_radius, vatistas_n=2, *, u_ou
                                _ld(u_out), int(accumulate), _stream(stream))
     _check("vpm_eval_segments", st)
     return u_out
+
+
+def vpm_eval_segments_gradient(a, b, gamma_seg, x_tgt, core_radius, vatistas_n=2, *, gamma_tgt=None,
+                               scheme=TRANSPOSED, want_u=True, want_grad=True, u_out=None, grad_out=None,
+                               dgamma_out=None, accumulate=False, stream=None):
+    """Velocity (3, n), gradient J (9, n; row 3a + b = du_a/dx_b) and, with gamma_tgt, the
+    stretching J^T gamma (transposed) or J gamma (classical) that straight vortex segments
+    impose at x_tgt (Vatistas core, Sec. II.A).  Outputs share one leading dimension; those
+    not given are allocated with the leading dimension of a given one.  Returns
+    (u, J, dgamma), None where not requested."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x_tgt)
+    tdt = x_tgt.dtype
+    _vec(x_tgt, "x_tgt", dtype=tdt)
+    n_tgt = x_tgt.shape[1]
+    _vec(a, "a", dtype=tdt)
+    n_seg = a.shape[1]
+    _vec(b, "b", n_seg, tdt)
+    _scal(gamma_seg, "gamma_seg", n_seg, tdt)
+    if a.shape[1] > 0 and (b.stride(0) != a.stride(0)):
+        raise ValueError("a and b must share one leading dimension")
+    if gamma_tgt is not None:
+        _vec(gamma_tgt, "gamma_tgt", n_tgt, tdt)
+        if gamma_tgt.stride(0) != x_tgt.stride(0):
+            raise ValueError("x_tgt and gamma_tgt must share one leading dimension")
+    given = [t for t in (u_out, grad_out, dgamma_out) if t is not None]
+    ld = _ld(given[0]) if given else n_tgt
+    if any(_ld(t) != ld for t in given):
+        raise ValueError("u_out, grad_out and dgamma_out must share one leading dimension")
+    ld = max(ld, 1)
+
+    def alloc(rows):
+        return torch.zeros((rows, ld), dtype=tdt, device=x_tgt.device)[:, :n_tgt]
+    if want_u and u_out is None:
+        u_out = alloc(3)
+    if want_grad and grad_out is None:
+        grad_out = alloc(9)
+    if gamma_tgt is not None and dgamma_out is None:
+        dgamma_out = alloc(3)
+    for t, nm, rows in ((u_out, "u_out", 3), (grad_out, "grad_out", 9), (dgamma_out, "dgamma_out", 3)):
+        if t is not None:
+            if t.dim() != 2 or t.shape[0] != rows or t.shape[1] != n_tgt or t.dtype != tdt or t.stride(1) != 1:
+                raise ValueError(f"{nm} must be ({rows}, {n_tgt}) {tdt} with unit stride along points")
+    if dgamma_out is not None and gamma_tgt is None:
+        raise ValueError("dgamma_out needs gamma_tgt")
+    st = lib.vpm_eval_segments_gradient(dt, n_seg, _p(a), _p(b), _p(gamma_seg), _ld(a) if n_seg else 0,
+                                        float(core_radius), int(vatistas_n), n_tgt, _p(x_tgt),
+                                        _p(gamma_tgt) if gamma_tgt is not None else None, _ld(x_tgt), int(scheme),
+                                        _p(u_out) if u_out is not None else None,
+                                        _p(grad_out) if grad_out is not None else None,
+                                        _p(dgamma_out) if dgamma_out is not None else None, ld, int(accumulate),
+                                        _stream(stream))
+    _check("vpm_eval_segments_gradient", st)
+    return u_out, grad_out, dgamma_out
 
 
 def vpm_backward(x_src, gamma_src, sigma_src, u_bar, dgamma_bar=None, x_tgt=None, gamma_tgt=None,

@@ -570,7 +570,7 @@ vpm_status vpm_eval_segments(int32_t dtype, int64_t n_seg, const void* a, const 
     for (const Range& r : ins)
         if (overlap(ru, r)) return VPM_ERR_ALIAS;
     if (n_tgt == 0) return VPM_OK;
-    vpm::SegArgs s;
+    vpm::SegArgs s{};
     s.a = a;
     s.b = b;
     s.gam = gamma_seg;
@@ -585,6 +585,56 @@ vpm_status vpm_eval_segments(int32_t dtype, int64_t n_seg, const void* a, const 
     s.ldo = ld_out;
     s.accumulate = accumulate;
     return hip_status(vpm::launch_segments(dtype, s, static_cast<hipStream_t>(stream)));
+}
+
+vpm_status vpm_eval_segments_gradient(int32_t dtype, int64_t n_seg, const void* a, const void* b,
+                                      const void* gamma_seg, int64_t ld_seg, double core_radius,
+                                      int32_t vatistas_n, int64_t n_tgt, const void* x_tgt, const void* gamma_tgt,
+                                      int64_t ld_tgt, int32_t scheme, void* u_out, void* grad_out,
+                                      void* dgamma_out, int64_t ld_out, int32_t accumulate, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n_seg < 0 || n_tgt < 0 || ld_seg < n_seg || ld_tgt < n_tgt || ld_out < n_tgt) return VPM_ERR_SIZE;
+    if (n_seg > INT32_MAX || n_tgt > INT32_MAX) return VPM_ERR_SIZE;
+    if (n_seg > 0 && (!a || !b || !gamma_seg)) return VPM_ERR_NULL;
+    if (n_tgt > 0 && ((!u_out && !grad_out && !dgamma_out) || !x_tgt)) return VPM_ERR_NULL;
+    if (dgamma_out && n_tgt > 0 && !gamma_tgt) return VPM_ERR_NULL;
+    if (!(core_radius >= 0.0) || core_radius > 1e30) return VPM_ERR_SIZE;
+    if (vatistas_n < 1 || vatistas_n > 16) return VPM_ERR_ENUM;
+    if (scheme != VPM_STRETCH_TRANSPOSED && scheme != VPM_STRETCH_CLASSICAL) return VPM_ERR_ENUM;
+    if (accumulate != 0 && accumulate != 1) return VPM_ERR_ENUM;
+    const size_t es = elem_size(dtype);
+    const Range outs[3] = {u_out ? span(u_out, 3, ld_out, n_tgt, es) : Range{},
+                           grad_out ? span(grad_out, 9, ld_out, n_tgt, es) : Range{},
+                           dgamma_out ? span(dgamma_out, 3, ld_out, n_tgt, es) : Range{}};
+    const Range ins[5] = {span(a, 3, ld_seg, n_seg, es), span(b, 3, ld_seg, n_seg, es),
+                          span(gamma_seg, 1, ld_seg, n_seg, es), span(x_tgt, 3, ld_tgt, n_tgt, es),
+                          dgamma_out ? span(gamma_tgt, 3, ld_tgt, n_tgt, es) : Range{}};
+    for (int i = 0; i < 3; ++i) {
+        for (const Range& r : ins)
+            if (overlap(outs[i], r)) return VPM_ERR_ALIAS;
+        for (int j = i + 1; j < 3; ++j)
+            if (overlap(outs[i], outs[j])) return VPM_ERR_ALIAS;
+    }
+    if (n_tgt == 0) return VPM_OK;
+    vpm::SegArgs s{};
+    s.a = a;
+    s.b = b;
+    s.gam = gamma_seg;
+    s.ld_seg = ld_seg;
+    s.n_seg = n_seg;
+    s.rc = core_radius;
+    s.vn = vatistas_n;
+    s.xt = x_tgt;
+    s.ldt = ld_tgt;
+    s.n_tgt = n_tgt;
+    s.u = u_out;
+    s.ldo = ld_out;
+    s.accumulate = accumulate;
+    s.gt = dgamma_out ? gamma_tgt : nullptr;
+    s.grad = grad_out;
+    s.dg = dgamma_out;
+    s.classical = scheme == VPM_STRETCH_CLASSICAL;
+    return hip_status(vpm::launch_segments_gradient(dtype, s, static_cast<hipStream_t>(stream)));
 }
 
 vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,

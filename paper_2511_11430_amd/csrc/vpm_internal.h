@@ -86,8 +86,14 @@ struct SegArgs {
     void* u;
     int64_t ldo;
     int32_t accumulate;
+    // gradient form only (launch_segments_gradient): outputs may be null
+    const void* gt;  // target strengths [3][ldt] (needed for dg)
+    void* grad;      // J[(3a+b)][ldo] = du_a/dx_b
+    void* dg;        // stretching [3][ldo]: J^T gamma (transposed) or J gamma (classical)
+    int32_t classical;
 };
 hipError_t launch_segments(int dtype, const SegArgs& a, hipStream_t st);
+hipError_t launch_segments_gradient(int dtype, const SegArgs& a, hipStream_t st);
 
 // ---------------------------------------------------------------- adjoint
 // Gather form: each lane owns one particle of the "lane set" and loops over the "loop set".

@@ -16,8 +16,9 @@ turns at omega about z in the free stream v_inf:
     (vpm_eval_velocity_stretching, vpm_eval_segments, vpm_neumann_rhs, vpm_lu_solve);
  4. the trailing-edge points become the youngest boundary; when a wake existed, the row
     between them and B_1 becomes lines (vpm_wake_shed, Eq. 7);
- 5. velocity at every boundary point and at the particles (blade rings, lines, particles;
-    particle stretching from the particles);
+ 5. velocity at every boundary point and at the particles (blade rings, lines, particles);
+    particle stretching by the whole field: the particles' share and J^T Gamma with J the
+    gradient of the rings' and lines' velocity (vpm_eval_segments_gradient);
  6. explicit Euler move (vpm_advect);
  7. beyond n_rows line rows, the oldest row and the shed line along the oldest boundary
     become particles (vpm_wake_convert, Eqs. 6-8);
@@ -32,7 +33,7 @@ import math
 import numpy as np
 import torch
 
-from . import (vpm_advect, vpm_aic_assemble, vpm_aic_update, vpm_eval_segments,
+from . import (vpm_advect, vpm_aic_assemble, vpm_aic_update, vpm_eval_segments, vpm_eval_segments_gradient,
                vpm_eval_velocity_stretching, vpm_lu_factor, vpm_lu_solve, vpm_neumann_rhs, vpm_wake_convert,
                vpm_wake_shed)
 
@@ -173,7 +174,8 @@ class Step:
             xq, gq, sq = self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np]
             uq, dq = self.uq[:, :self.np], self.dq[:, :self.np]
             vpm_eval_velocity_stretching(xq, gq, sq, u_out=uq, dgamma_out=dq)
-            vpm_eval_segments(segs[0], segs[1], segs[2], xq, self.rc, self.vn, u_out=uq, accumulate=True)
+            vpm_eval_segments_gradient(segs[0], segs[1], segs[2], xq, self.rc, self.vn, gamma_tgt=gq,
+                                       want_grad=False, u_out=uq, dgamma_out=dq, accumulate=True)
             vpm_advect(xq, uq, self.dt, self.v_inf, gamma=gq, dgamma=dq)
         vpm_advect(pts, up, self.dt, self.v_inf)
         nbp = T.shape[1]

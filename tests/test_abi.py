@@ -319,3 +319,30 @@ def test_step_kernels_validation():
     assert a(F64, 8, 0.1, P(0), P(1), P(2), None, 8, v3, None) == NULL
     assert a(F64, 8, 0.1, P(0), P(0), None, None, 8, v3, None) == ALIAS
     assert a(F64, 0, 0.1, None, None, None, None, 0, v3, None) == OK
+
+
+def test_segments_gradient_validation():
+    lib = _lib.load()
+    f = lib.vpm_eval_segments_gradient
+
+    def args(**k):
+        return [k.get("dt", F32C), k.get("ns", 10), P(0), P(1), P(2), 10, k.get("rc", 0.02), k.get("vn", 2), 5, P(3),
+                k.get("gt", P(4)), 5, k.get("sch", 0), k.get("u", P(5)), k.get("j", P(6)), k.get("dg", P(7)),
+                k.get("ldo", 5), k.get("acc", 0), None]
+    assert f(*args(dt=7)) == DTYPE
+    assert f(*args(ns=-1)) == SIZE
+    assert f(*args(ldo=4)) == SIZE
+    assert f(*args(rc=-0.1)) == SIZE
+    assert f(*args(vn=0)) == ENUM
+    assert f(*args(sch=2)) == ENUM
+    assert f(*args(acc=3)) == ENUM
+    assert f(*args(u=None, j=None, dg=None)) == NULL
+    assert f(*args(gt=None)) == NULL          # stretching needs the target strengths
+    assert f(*args(j=P(3))) == ALIAS          # gradient over the targets
+    assert f(*args(dg=P(4))) == ALIAS         # stretching over the target strengths
+    assert f(*args(u=P(6))) == ALIAS          # two outputs on one array
+    args0 = args(gt=None, dg=None)
+    args0[8] = 0
+    args0[11] = 0
+    args0[16] = 0
+    assert f(*args0) == OK                    # no targets: nothing to launch

@@ -43,7 +43,8 @@ def test_closed_step_matches_oracle(gpu):
             if first_conversion is None:
                 first_conversion = k
         # closure of the vorticity holds exactly until the converted particles start moving on
-        # their own (their strengths are stretched only by the particles here)
+        # their own: their strengths are then stretched by the rings' and lines' field as well,
+        # which the line ends do not balance exactly
         if first_conversion is None or k == first_conversion:
             wl = gs.lines(gs.gprev)
             tot = np.zeros(3) if wl is None else (host(wl[2]) * (host(wl[1]) - host(wl[0]))).sum(1)
