@@ -39,9 +39,11 @@ def _load():
         lib.orc_eval_jvp.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, i64, _dp, _dp, _dp, _dp, _dp, _lp,
                                      i32, i32, _dp, _dp, _dp, _dp, i32]
         lib.orc_segments.argtypes = [i64, _dp, _dp, _dp, dbl, i32, i64, _dp, _dp, i32]
-        lib.orc_rk3_program.argtypes = [i64, _dp, _dp, _dp, i32, dbl, i32, i32, i64, _dp, _dp, _dp, i32]
+        lat = [i64, _dp, _dp, _dp, dbl, i32]
+        lib.orc_rk3_program.argtypes = [i64, _dp, _dp, _dp, i32, dbl, i32, i32, i64, _dp, _dp, _dp, i32] + lat
         lib.orc_rk3_program_jvp.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, i32, dbl, i32, i32, i64, _dp,
-                                            _dp, _dp, i32]
+                                            _dp, _dp, i32] + lat
+        lib.orc_segments_vjp.argtypes = [i64, _dp, _dp, _dp, dbl, i32, i64, _dp, _dp, _dp, _dp, i32, _dp, _dp, i32]
         lib.orc_diagnostics.argtypes = [i64, _dp, _dp, _dp, _dp, _dp]
         lib.orc_gradient.argtypes = [i64, _dp, _dp, _dp, i64, _dp, _dp, _lp, i32, _dp, i32]
         lib.orc_vreman.argtypes = [i64, _dp, _dp, dbl, _dp]
@@ -50,7 +52,7 @@ def _load():
         lib.orc_segments_gradient.argtypes = [i64, _dp, _dp, _dp, dbl, i32, i64, _dp, _dp, i32]
         for f in ("orc_weights", "orc_ghk", "orc_eval", "orc_eval_jvp", "orc_segments",
                   "orc_rk3_program", "orc_rk3_program_jvp", "orc_diagnostics", "orc_gradient",
-                  "orc_vreman", "orc_pse", "orc_pse_at", "orc_segments_gradient"):
+                  "orc_vreman", "orc_pse", "orc_pse_at", "orc_segments_gradient", "orc_segments_vjp"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -202,11 +204,50 @@ def segments_gradient(a, b, gam_seg, x_tgt, core_radius, vatistas_n=2, nthreads=
     return J.reshape(3, 3, -1)
 
 
-def rk3_program(x, gam, sig, n_steps, dt, y_ctrl=None, scheme=TRANSPOSED, sigma_rule=SIGMA_SOURCE,
-                nthreads=0):
-    """n_steps of low-storage RK3 (Williamson) on (x, Gamma), then the velocity at the
-    control points y_ctrl and L = sum_c (u_c . z)^2.  Returns (x, gam, u_ctrl, L)."""
+def _lattice(segments):
+    """(a, b, gamma_seg, core_radius, vatistas_n) or None -> the trailing C arguments and the
+    arrays they point into (kept alive by the caller)."""
+    if segments is None:
+        return [0, None, None, None, 0.0, 2], ()
+    a, b, g, rc, vn = segments
+    A, B = _vec(a, "seg_a"), _vec(b, "seg_b")
+    G = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+    if B.shape != A.shape or G.shape[0] != A.shape[1]:
+        raise ValueError("segments: a, b must be (3, n) and gamma (n,)")
+    return [A.shape[1], A.ctypes.data_as(_dp), B.ctypes.data_as(_dp), G.ctypes.data_as(_dp), float(rc),
+            int(vn)], (A, B, G)
+
+
+def segments_vjp(a, b, gam_seg, x_tgt, core_radius, vatistas_n, u_bar, dgamma_bar=None, gam_tgt=None,
+                 scheme=TRANSPOSED, nthreads=0):
+    """Vector-Jacobian product of the segments' velocity u(x) and stretching s (J^T Gamma,
+    transposed; J Gamma, classical) at particles (x_tgt, gam_tgt) with seeds u_bar and
+    dgamma_bar: returns (x_bar, gam_bar) of L = sum u_bar . u + dgamma_bar . s (gam_bar None
+    without dgamma_bar).  Second derivatives by hyper-dual numbers."""
     lib = _load()
+    A, B = _vec(a, "a"), _vec(b, "b")
+    g = np.ascontiguousarray(gam_seg, dtype=np.float64).reshape(-1)
+    xt = _vec(x_tgt, "x_tgt")
+    ub = _vec(u_bar, "u_bar")
+    db = None if dgamma_bar is None else _vec(dgamma_bar, "dgamma_bar")
+    gt = None if dgamma_bar is None else _vec(gam_tgt, "gam_tgt")
+    xb = np.zeros_like(xt)
+    gb = None if db is None else np.zeros_like(xt)
+    p = lambda v: None if v is None else v.ctypes.data_as(_dp)
+    rc = lib.orc_segments_vjp(A.shape[1], p(A), p(B), p(g), float(core_radius), int(vatistas_n), xt.shape[1], p(xt),
+                              p(gt), p(ub), p(db), int(scheme), p(xb), p(gb), int(nthreads))
+    _check(rc, "segments_vjp")
+    return xb, gb
+
+
+def rk3_program(x, gam, sig, n_steps, dt, y_ctrl=None, scheme=TRANSPOSED, sigma_rule=SIGMA_SOURCE,
+                nthreads=0, segments=None):
+    """n_steps of low-storage RK3 (Williamson) on (x, Gamma), then the velocity at the
+    control points y_ctrl and L = sum_c (u_c . z)^2.  Returns (x, gam, u_ctrl, L).
+    ``segments`` = (a, b, gamma_seg, core_radius, vatistas_n): a fixed lattice whose velocity
+    and stretching act on the particles and whose velocity adds at the control points."""
+    lib = _load()
+    lat, keep = _lattice(segments)
     X, G = _vec(x, "x").copy(), _vec(gam, "gam").copy()
     s = np.ascontiguousarray(sig, dtype=np.float64).reshape(-1)
     m = 0 if y_ctrl is None else _vec(y_ctrl, "y_ctrl").shape[1]
@@ -216,15 +257,17 @@ def rk3_program(x, gam, sig, n_steps, dt, y_ctrl=None, scheme=TRANSPOSED, sigma_
     rc = lib.orc_rk3_program(X.shape[1], X.ctypes.data_as(_dp), G.ctypes.data_as(_dp), s.ctypes.data_as(_dp),
                              int(n_steps), float(dt), int(scheme), int(sigma_rule), m,
                              None if Y is None else Y.ctypes.data_as(_dp), uc.ctypes.data_as(_dp),
-                             ctypes.byref(L), int(nthreads))
+                             ctypes.byref(L), int(nthreads), *lat)
     _check(rc, "rk3_program")
+    del keep
     return X, G, uc[:, :m], L.value
 
 
 def rk3_program_jvp(x, gam, sig, x_dot, gam_dot, n_steps, dt, y_ctrl, scheme=TRANSPOSED,
-                    sigma_rule=SIGMA_SOURCE, nthreads=0):
+                    sigma_rule=SIGMA_SOURCE, nthreads=0, segments=None):
     """Loss of :func:`rk3_program` and its directional derivative along (x_dot, gam_dot)."""
     lib = _load()
+    lat, keep = _lattice(segments)
     X, G = _vec(x, "x"), _vec(gam, "gam")
     Xd, Gd = _vec(x_dot, "x_dot"), _vec(gam_dot, "gam_dot")
     s = np.ascontiguousarray(sig, dtype=np.float64).reshape(-1)
@@ -233,8 +276,9 @@ def rk3_program_jvp(x, gam, sig, x_dot, gam_dot, n_steps, dt, y_ctrl, scheme=TRA
     rc = lib.orc_rk3_program_jvp(X.shape[1], X.ctypes.data_as(_dp), G.ctypes.data_as(_dp),
                                  s.ctypes.data_as(_dp), Xd.ctypes.data_as(_dp), Gd.ctypes.data_as(_dp),
                                  int(n_steps), float(dt), int(scheme), int(sigma_rule), Y.shape[1],
-                                 Y.ctypes.data_as(_dp), ctypes.byref(L), ctypes.byref(dL), int(nthreads))
+                                 Y.ctypes.data_as(_dp), ctypes.byref(L), ctypes.byref(dL), int(nthreads), *lat)
     _check(rc, "rk3_program_jvp")
+    del keep
     return L.value, dL.value
 
 

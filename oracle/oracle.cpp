@@ -93,6 +93,41 @@ inline Dual dpow(Dual a, double p) {  // a > 0
 }
 inline double dpow(double a, double p) { return std::pow(a, p); }
 
+// Hyper-dual scalar: value v, derivatives a and b along two directions, and the mixed second
+// derivative ab.  A function f of one argument maps x to
+//   (f, f' x.a, f' x.b, f' x.ab + f'' x.a x.b).
+struct HDual {
+    double v, a, b, ab;
+    HDual() : v(0), a(0), b(0), ab(0) {}
+    HDual(double x) : v(x), a(0), b(0), ab(0) {}
+    HDual(double x, double da, double db, double dab) : v(x), a(da), b(db), ab(dab) {}
+};
+inline HDual chain(const HDual& x, double f, double f1, double f2) {
+    return HDual(f, f1 * x.a, f1 * x.b, f1 * x.ab + f2 * x.a * x.b);
+}
+inline HDual operator+(HDual x, HDual y) { return HDual(x.v + y.v, x.a + y.a, x.b + y.b, x.ab + y.ab); }
+inline HDual operator-(HDual x, HDual y) { return HDual(x.v - y.v, x.a - y.a, x.b - y.b, x.ab - y.ab); }
+inline HDual operator-(HDual x) { return HDual(-x.v, -x.a, -x.b, -x.ab); }
+inline HDual operator*(HDual x, HDual y) {
+    return HDual(x.v * y.v, x.a * y.v + x.v * y.a, x.b * y.v + x.v * y.b,
+                 x.ab * y.v + x.a * y.b + x.b * y.a + x.v * y.ab);
+}
+inline HDual operator/(HDual x, HDual y) {
+    const double r = 1.0 / y.v;
+    return x * chain(y, r, -r * r, 2.0 * r * r * r);
+}
+inline HDual& operator+=(HDual& x, HDual y) { x = x + y; return x; }
+inline bool operator<(HDual x, double y) { return x.v < y; }
+inline double val(HDual x) { return x.v; }
+inline HDual dsqrt(HDual x) {
+    const double s = std::sqrt(x.v);
+    if (!(s > 0)) return HDual(s, 0, 0, 0);
+    return chain(x, s, 0.5 / s, -0.25 / (s * x.v));
+}
+inline HDual dpow(HDual x, double p) {  // x > 0
+    return chain(x, std::pow(x.v, p), p * std::pow(x.v, p - 1.0), p * (p - 1.0) * std::pow(x.v, p - 2.0));
+}
+
 // ---------------------------------------------------------------- compensated sum
 // Neumaier's variant of Kahan summation, applied separately to value and tangent.
 struct Neumaier {
@@ -115,6 +150,11 @@ template <> struct Acc<Dual> {
     Neumaier a, b;
     void add(Dual x) { a.add(x.v); b.add(x.d); }
     Dual get() const { return Dual(a.get(), b.get()); }
+};
+template <> struct Acc<HDual> {
+    Neumaier v, a, b, ab;
+    void add(HDual x) { v.add(x.v); a.add(x.a); b.add(x.b); ab.add(x.ab); }
+    HDual get() const { return HDual(v.get(), a.get(), b.get(), ab.get()); }
 };
 
 template <class T> struct V3 { T x, y, z; };
@@ -276,6 +316,85 @@ void eval_segments(int64_t nseg, const double* A, const double* B, const double*
     }
 }
 
+// ---------------------------------------------------------------- segments acting on particles
+// A fixed lattice of straight segments (blade rings or frozen wake lines) adds its velocity
+// and its share of the stretching to the particles' right-hand side (Sec. II.B: the
+// particles move with, and are stretched by, the total velocity).
+struct Lattice {
+    int64_t nseg = 0;
+    const double* A = nullptr;
+    const double* B = nullptr;
+    const double* gam = nullptr;
+    double rc = 0.0;
+    int vn = 2;
+};
+
+// J[(3a+b) nt + t] = d u_a / d x_b of the segments at nt points, by forward mode.
+void segment_jacobian(const Lattice& L, int64_t nt, const double* xt, double* J) {
+    std::vector<Dual> X(3 * size_t(nt)), U(3 * size_t(nt));
+    for (int b = 0; b < 3; ++b) {
+        for (int c = 0; c < 3; ++c)
+            for (int64_t t = 0; t < nt; ++t) X[c * nt + t] = Dual(xt[c * nt + t], c == b ? 1.0 : 0.0);
+        eval_segments<Dual>(L.nseg, L.A, L.B, L.gam, L.rc, L.vn, nt, X.data(), U.data());
+        for (int a = 0; a < 3; ++a)
+            for (int64_t t = 0; t < nt; ++t) J[(3 * a + b) * nt + t] = U[a * nt + t].d;
+    }
+}
+
+// J as above and M[(3a+b) nt + t] = d/dx_b (w_t . grad) u_a, the derivative of J's column
+// sum along w_t (hyper-dual: direction a = e_b, direction b = w_t).
+void segment_jacobian_and_hessian(const Lattice& L, int64_t nt, const double* xt, const double* w, double* J,
+                                  double* M) {
+    std::vector<HDual> X(3 * size_t(nt)), U(3 * size_t(nt));
+    for (int b = 0; b < 3; ++b) {
+        for (int c = 0; c < 3; ++c)
+            for (int64_t t = 0; t < nt; ++t)
+                X[c * nt + t] = HDual(xt[c * nt + t], c == b ? 1.0 : 0.0, w[c * nt + t], 0.0);
+        eval_segments<HDual>(L.nseg, L.A, L.B, L.gam, L.rc, L.vn, nt, X.data(), U.data());
+        for (int a = 0; a < 3; ++a)
+            for (int64_t t = 0; t < nt; ++t) {
+                J[(3 * a + b) * nt + t] = U[a * nt + t].a;
+                M[(3 * a + b) * nt + t] = U[a * nt + t].ab;
+            }
+    }
+}
+
+// fx += u_seg(x), fg += J^T G (scheme 0, transposed) or J G (scheme 1, classical).
+void add_segment_rhs(const Lattice& L, int64_t n, const double* x, const double* G, int scheme, double* fx,
+                     double* fg) {
+    std::vector<double> u(3 * n), J(9 * n);
+    eval_segments<double>(L.nseg, L.A, L.B, L.gam, L.rc, L.vn, n, x, u.data());
+    segment_jacobian(L, n, x, J.data());
+    for (int64_t t = 0; t < n; ++t)
+        for (int c = 0; c < 3; ++c) {
+            fx[c * n + t] += u[c * n + t];
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a)
+                s += (scheme == 0 ? J[(3 * a + c) * n + t] : J[(3 * c + a) * n + t]) * G[a * n + t];
+            fg[c * n + t] += s;
+        }
+}
+
+// Tangent form: x and G carry tangents; the tangent of J along x's tangent comes from the
+// hyper-dual pass (M with w = x.d).
+void add_segment_rhs(const Lattice& L, int64_t n, const Dual* x, const Dual* G, int scheme, Dual* fx, Dual* fg) {
+    std::vector<Dual> u(3 * n);
+    eval_segments<Dual>(L.nseg, L.A, L.B, L.gam, L.rc, L.vn, n, x, u.data());
+    std::vector<double> xv(3 * n), xd(3 * n), J(9 * n), Jd(9 * n);
+    for (int64_t i = 0; i < 3 * n; ++i) { xv[i] = x[i].v; xd[i] = x[i].d; }
+    segment_jacobian_and_hessian(L, n, xv.data(), xd.data(), J.data(), Jd.data());
+    for (int64_t t = 0; t < n; ++t)
+        for (int c = 0; c < 3; ++c) {
+            fx[c * n + t] += u[c * n + t];
+            Dual s;
+            for (int a = 0; a < 3; ++a) {
+                const int64_t k = (scheme == 0 ? (3 * a + c) : (3 * c + a)) * n + t;
+                s += Dual(J[k], Jd[k]) * G[a * n + t];
+            }
+            fg[c * n + t] += s;
+        }
+}
+
 // ---------------------------------------------------------------- RK3 program
 // Williamson's low-storage third-order scheme, 2N-storage form:
 //   Q <- a_k Q + dt F(Y);  Y <- Y + b_k Q,   k = 1..3,
@@ -285,7 +404,7 @@ const double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 
 template <class T>
 void rk3_program(int64_t n, T* x, T* G, const double* sig, int nsteps, double dt, int scheme,
-                 int sigma_rule, int64_t m, const double* y, T* uc, T* loss) {
+                 int sigma_rule, int64_t m, const double* y, T* uc, T* loss, const Lattice& lat) {
     std::vector<T> qx(3 * n), qg(3 * n), fx(3 * n), fg(3 * n);
     std::vector<int64_t> excl(n);
     for (int64_t i = 0; i < n; ++i) excl[i] = i;
@@ -294,6 +413,7 @@ void rk3_program(int64_t n, T* x, T* G, const double* sig, int nsteps, double dt
         for (int k = 0; k < 3; ++k) {
             eval_pairs<T>(n, x, G, sig, n, x, G, sig, excl.data(), scheme, sigma_rule,
                           fx.data(), fg.data());
+            if (lat.nseg > 0) add_segment_rhs(lat, n, x, G, scheme, fx.data(), fg.data());
             for (int64_t i = 0; i < 3 * n; ++i) {
                 qx[i] = T(kRkA[k]) * qx[i] + T(dt) * fx[i];
                 qg[i] = T(kRkA[k]) * qg[i] + T(dt) * fg[i];
@@ -306,6 +426,11 @@ void rk3_program(int64_t n, T* x, T* G, const double* sig, int nsteps, double dt
         std::vector<T> yt(3 * m);
         for (int64_t i = 0; i < 3 * m; ++i) yt[i] = T(y[i]);
         eval_pairs<T>(n, x, G, sig, m, yt.data(), nullptr, nullptr, nullptr, 0, 0, uc, nullptr);
+        if (lat.nseg > 0) {
+            std::vector<T> us(3 * m);
+            eval_segments<T>(lat.nseg, lat.A, lat.B, lat.gam, lat.rc, lat.vn, m, yt.data(), us.data());
+            for (int64_t i = 0; i < 3 * m; ++i) uc[i] = uc[i] + us[i];
+        }
         Acc<T> l;
         for (int64_t c = 0; c < m; ++c) l.add(uc[2 * m + c] * uc[2 * m + c]);
         *loss = l.get();
@@ -502,15 +627,56 @@ int orc_segments_gradient(int64_t nseg, const double* A, const double* B, const 
     return 0;
 }
 
+// Vector-Jacobian product of the segments' velocity and stretching at particles (x, G)
+// [3][nt] with seeds ubar, dbar [3][nt] (dbar may be null):
+//   L = sum_t ubar_t . u(x_t) + dbar_t . s_t,  s = J^T G (scheme 0) or J G (scheme 1),
+//   xbar = J^T ubar + sum_a w2_a M[a][.],  M = d/dx (w1 . grad) u,
+//   (w1, w2) = (dbar, G) for scheme 0 and (G, dbar) for scheme 1,
+//   Gbar = J dbar (scheme 0) or J^T dbar (scheme 1).
+int orc_segments_vjp(int64_t nseg, const double* A, const double* B, const double* gam, double rc, int vn,
+                     int64_t nt, const double* xt, const double* gt, const double* ubar, const double* dbar,
+                     int scheme, double* xbar, double* gbar, int nthreads) {
+    if (nseg < 0 || nt < 0 || !xt || !ubar || !xbar || (nseg > 0 && (!A || !B || !gam))) return 1;
+    if (!(rc >= 0.0) || vn < 1 || scheme < 0 || scheme > 1) return 1;
+    if (dbar && (!gt || !gbar)) return 1;
+    set_threads<double>(nthreads);
+    Lattice lat;
+    lat.nseg = nseg; lat.A = A; lat.B = B; lat.gam = gam; lat.rc = rc; lat.vn = vn;
+    std::vector<double> J(9 * nt), M(9 * nt, 0.0), zero(3 * nt, 0.0);
+    const double* w1 = !dbar ? zero.data() : (scheme == 0 ? dbar : gt);
+    const double* w2 = !dbar ? zero.data() : (scheme == 0 ? gt : dbar);
+    segment_jacobian_and_hessian(lat, nt, xt, w1, J.data(), M.data());
+    for (int64_t t = 0; t < nt; ++t)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a)
+                s += J[(3 * a + b) * nt + t] * ubar[a * nt + t] + w2[a * nt + t] * M[(3 * a + b) * nt + t];
+            xbar[b * nt + t] = s;
+            if (dbar) {
+                double g = 0.0;
+                for (int c = 0; c < 3; ++c)
+                    g += (scheme == 0 ? J[(3 * b + c) * nt + t] : J[(3 * c + b) * nt + t]) * dbar[c * nt + t];
+                gbar[b * nt + t] = g;
+            }
+        }
+    return 0;
+}
+
 // Runs nsteps RK3 steps from (x, G) in place, then the control-point velocity uc [3][m]
 // and the loss sum_c uc_z^2.
+// Optional fixed lattice: nseg segments A -> B [3][nseg] of strength gs, core rc, exponent vn
+// (nseg = 0: particles only).
 int orc_rk3_program(int64_t n, double* x, double* G, const double* sig, int nsteps, double dt,
                     int scheme, int sigma_rule, int64_t m, const double* y, double* uc,
-                    double* loss, int nthreads) {
+                    double* loss, int nthreads, int64_t nseg, const double* A, const double* B,
+                    const double* gs, double rc, int vn) {
     if (n < 0 || m < 0 || nsteps < 0 || !x || !G || !sig || !loss || (m > 0 && (!y || !uc)))
         return 1;
+    if (nseg < 0 || (nseg > 0 && (!A || !B || !gs || !(rc >= 0.0) || vn < 1))) return 1;
     set_threads<double>(nthreads);
-    rk3_program<double>(n, x, G, sig, nsteps, dt, scheme, sigma_rule, m, y, uc, loss);
+    Lattice lat;
+    lat.nseg = nseg; lat.A = A; lat.B = B; lat.gam = gs; lat.rc = rc; lat.vn = vn;
+    rk3_program<double>(n, x, G, sig, nsteps, dt, scheme, sigma_rule, m, y, uc, loss, lat);
     return 0;
 }
 
@@ -519,15 +685,19 @@ int orc_rk3_program(int64_t n, double* x, double* G, const double* sig, int nste
 int orc_rk3_program_jvp(int64_t n, const double* x, const double* G, const double* sig,
                         const double* xd, const double* Gd, int nsteps, double dt, int scheme,
                         int sigma_rule, int64_t m, const double* y, double* loss,
-                        double* dloss, int nthreads) {
+                        double* dloss, int nthreads, int64_t nseg, const double* A, const double* B,
+                        const double* gs, double rc, int vn) {
     if (n < 0 || m < 0 || nsteps < 0 || !x || !G || !sig || !xd || !Gd || !loss || !dloss)
         return 1;
     if (m > 0 && !y) return 1;
+    if (nseg < 0 || (nseg > 0 && (!A || !B || !gs || !(rc >= 0.0) || vn < 1))) return 1;
     set_threads<double>(nthreads);
+    Lattice lat;
+    lat.nseg = nseg; lat.A = A; lat.B = B; lat.gam = gs; lat.rc = rc; lat.vn = vn;
     std::vector<Dual> X(3 * n), Gm(3 * n), UC(3 * (m > 0 ? m : 1));
     for (int64_t i = 0; i < 3 * n; ++i) { X[i] = Dual(x[i], xd[i]); Gm[i] = Dual(G[i], Gd[i]); }
     Dual L;
-    rk3_program<Dual>(n, X.data(), Gm.data(), sig, nsteps, dt, scheme, sigma_rule, m, y, UC.data(), &L);
+    rk3_program<Dual>(n, X.data(), Gm.data(), sig, nsteps, dt, scheme, sigma_rule, m, y, UC.data(), &L, lat);
     *loss = L.v;
     *dloss = L.d;
     return 0;

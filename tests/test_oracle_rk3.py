@@ -90,3 +90,65 @@ def test_program_tangent_matches_central_differences():
     _, _, _, L0 = oracle.rk3_program(x, g, s, nsteps, dt, y)
     assert L == pytest.approx(L0, rel=1e-15)
     assert dL == pytest.approx((Lp - Lm) / (2 * h), rel=1e-6)
+
+
+def _lattice(rng):
+    a = rng.uniform(-0.12, 0.12, (3, 8))
+    b = a + rng.normal(size=(3, 8)) * 0.05
+    return a, b, rng.normal(size=8) * 1e-3
+
+
+@pytest.mark.parametrize("scheme", [oracle.TRANSPOSED, oracle.CLASSICAL])
+def test_single_step_with_lattice_is_williamson_rk3(scheme):
+    """With a fixed lattice the right-hand side gains the segments' velocity and stretching
+    (J^T Gamma or J Gamma); one program step equals the Butcher form built from the
+    oracle's separate particle, segment and segment-gradient routines."""
+    rng = np.random.default_rng(12)
+    x = rng.uniform(-0.05, 0.05, (3, 5))
+    g = rng.normal(0, 1e-3, (3, 5))
+    s = np.full(5, 0.03)
+    sa, sb, sg = _lattice(rng)
+    dt = 0.7
+
+    def F(x, g):
+        u, d = oracle.eval_pairs(x, g, s, scheme=scheme)
+        u = u + oracle.segments(sa, sb, sg, x, 0.02, 2)
+        J = oracle.segments_gradient(sa, sb, sg, x, 0.02, 2)
+        d = d + (np.einsum("abn,an->bn", J, g) if scheme == oracle.TRANSPOSED else np.einsum("abn,bn->an", J, g))
+        return u, d
+
+    A, b = BUTCHER_A, BUTCHER_B
+    k1 = F(x, g)
+    k2 = F(x + dt * A[1][0] * k1[0], g + dt * A[1][0] * k1[1])
+    k3 = F(x + dt * (A[2][0] * k1[0] + A[2][1] * k2[0]), g + dt * (A[2][0] * k1[1] + A[2][1] * k2[1]))
+    xe = x + dt * (b[0] * k1[0] + b[1] * k2[0] + b[2] * k3[0])
+    ge = g + dt * (b[0] * k1[1] + b[1] * k2[1] + b[2] * k3[1])
+    y = rng.uniform(-0.1, 0.1, (3, 3))
+    x1, g1, uc, _ = oracle.rk3_program(x, g, s, 1, dt, y, scheme=scheme, segments=(sa, sb, sg, 0.02, 2))
+    assert np.allclose(x1, xe, rtol=1e-13, atol=1e-16)
+    assert np.allclose(g1, ge, rtol=1e-12, atol=1e-18)
+    uc_e = oracle.eval_pairs(x1, g1, s, x_tgt=y)[0] + oracle.segments(sa, sb, sg, y, 0.02, 2)
+    assert np.allclose(uc, uc_e, rtol=1e-13, atol=1e-18)
+
+
+@pytest.mark.parametrize("scheme", [oracle.TRANSPOSED, oracle.CLASSICAL])
+def test_program_with_lattice_tangent_matches_central_differences(scheme):
+    rng = np.random.default_rng(13)
+    n = 16
+    x = rng.uniform(-0.1, 0.1, (3, n))
+    g = rng.normal(0, 1e-3, (3, n))
+    s = np.full(n, 0.04)
+    y = rng.uniform(-0.1, 0.1, (3, 5))
+    lat = (*_lattice(rng), 0.02, 2)
+    xd = rng.normal(size=x.shape)
+    gd = rng.normal(size=g.shape) * 1e-3
+    dt, nsteps = 0.5, 3
+    L, dL = oracle.rk3_program_jvp(x, g, s, xd, gd, nsteps, dt, y, scheme=scheme, segments=lat)
+    h = 1e-6
+    Lp = oracle.rk3_program(x + h * xd, g + h * gd, s, nsteps, dt, y, scheme=scheme, segments=lat)[3]
+    Lm = oracle.rk3_program(x - h * xd, g - h * gd, s, nsteps, dt, y, scheme=scheme, segments=lat)[3]
+    L0 = oracle.rk3_program(x, g, s, nsteps, dt, y, scheme=scheme, segments=lat)[3]
+    assert L == pytest.approx(L0, rel=1e-15)
+    assert dL == pytest.approx((Lp - Lm) / (2 * h), rel=1e-6)
+    # without the lattice the loss differs (the lattice is felt)
+    assert abs(oracle.rk3_program(x, g, s, nsteps, dt, y, scheme=scheme)[3] - L0) > 1e-3 * abs(L0)

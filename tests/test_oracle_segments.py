@@ -138,3 +138,67 @@ def test_segment_gradient_infinite_line_profile():
         J = oracle.segments_gradient(a, b, [G], np.array([[d], [0.0], [0.0]]), rc, 2)
         ref = G * (rc ** 4 - d ** 4) / (2 * math.pi * (rc ** 4 + d ** 4) ** 1.5)
         assert J[1, 0, 0] == pytest.approx(ref, rel=1e-7, abs=1e-8 * G / rc ** 2)
+
+
+def _vjp_case(seed=7, n=12):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-0.2, 0.2, (3, 6))
+    b = a + rng.normal(size=(3, 6)) * 0.1
+    gs = rng.normal(size=6)
+    x = rng.uniform(-0.25, 0.25, (3, n))
+    g = rng.normal(size=(3, n))
+    ub = rng.normal(size=(3, n))
+    db = rng.normal(size=(3, n))
+    return a, b, gs, x, g, ub, db
+
+
+def _seg_loss(a, b, gs, x, g, ub, db, rc, scheme):
+    """L = sum ub . u + db . s from the oracle's velocity and first-derivative routines."""
+    u = oracle.segments(a, b, gs, x, rc, 2)
+    J = oracle.segments_gradient(a, b, gs, x, rc, 2)
+    s = np.einsum("abn,an->bn", J, g) if scheme == oracle.TRANSPOSED else np.einsum("abn,bn->an", J, g)
+    return float((ub * u).sum() + (db * s).sum())
+
+
+@pytest.mark.parametrize("scheme", [oracle.TRANSPOSED, oracle.CLASSICAL])
+@pytest.mark.parametrize("rc", [0.0, 0.03])
+def test_segment_vjp_matches_central_differences(scheme, rc):
+    """x_bar (which needs the segment law's second derivatives) against central differences
+    of L built from the velocity and its first derivative."""
+    a, b, gs, x, g, ub, db = _vjp_case()
+    xb, _ = oracle.segments_vjp(a, b, gs, x, rc, 2, ub, db, g, scheme)
+    h = 1e-6
+    for t in (0, 5, 11):
+        for c in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[c, t] += h
+            xm[c, t] -= h
+            fd = (_seg_loss(a, b, gs, xp, g, ub, db, rc, scheme) - _seg_loss(a, b, gs, xm, g, ub, db, rc, scheme))
+            fd /= 2 * h
+            assert xb[c, t] == pytest.approx(fd, rel=2e-6, abs=1e-6 * np.abs(xb).max())
+
+
+@pytest.mark.parametrize("scheme", [oracle.TRANSPOSED, oracle.CLASSICAL])
+def test_segment_vjp_strength_gradient_is_exact_by_linearity(scheme):
+    """L is linear in the particle strengths, so L(G + D) - L(G) = D . G_bar to rounding."""
+    a, b, gs, x, g, ub, db = _vjp_case(8)
+    _, gb = oracle.segments_vjp(a, b, gs, x, 0.02, 2, ub, db, g, scheme)
+    D = np.random.default_rng(9).normal(size=g.shape)
+    dL = _seg_loss(a, b, gs, x, g + D, ub, db, 0.02, scheme) - _seg_loss(a, b, gs, x, g, ub, db, 0.02, scheme)
+    assert dL == pytest.approx(float((D * gb).sum()), rel=1e-12)
+
+
+def test_segment_hessian_is_symmetric():
+    """The second-derivative term is H w with H the Hessian of Gamma . u at each particle, so
+    v . (H w) = w . (H v) point by point (a swapped index would break it)."""
+    a, b, gs, x, g, _, _ = _vjp_case(10)
+    rng = np.random.default_rng(11)
+    v, w = rng.normal(size=x.shape), rng.normal(size=x.shape)
+    z = np.zeros_like(x)
+    Hw, _ = oracle.segments_vjp(a, b, gs, x, 0.02, 2, z, w, g, oracle.TRANSPOSED)
+    Hv, _ = oracle.segments_vjp(a, b, gs, x, 0.02, 2, z, v, g, oracle.TRANSPOSED)
+    lhs, rhs = (v * Hw).sum(0), (w * Hv).sum(0)
+    assert np.allclose(lhs, rhs, rtol=1e-10, atol=1e-12 * np.abs(lhs).max())
+    # the two schemes swap the roles of the particle strength and the stretching seed
+    Hc, _ = oracle.segments_vjp(a, b, gs, x, 0.02, 2, z, g, w, oracle.CLASSICAL)
+    assert np.allclose(Hc, Hw, rtol=1e-12, atol=1e-14 * np.abs(Hw).max())
