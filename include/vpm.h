@@ -231,6 +231,25 @@ vpm_status vpm_eval_segments_gradient(int32_t dtype, int64_t n_seg, const void* 
                                       int64_t ld_tgt, int32_t scheme, void* u_out, void* grad_out,
                                       void* dgamma_out, int64_t ld_out, int32_t accumulate, void* stream);
 
+/* vpm_segments_backward — vector-Jacobian product of vpm_eval_segments_gradient's velocity
+ * and stretching with respect to the target particles (segments held fixed): given seeds
+ * u_bar and dgamma_bar on u and on s = J^T gamma_tgt (transposed) or J gamma_tgt (classical),
+ * ADD to the particle gradients
+ *   x_bar     += J^T u_bar + d/dx [dgamma_bar . s]   (second derivatives of the segment law),
+ *   gamma_bar += J dgamma_bar (transposed) or J^T dgamma_bar (classical).
+ * Used where segments (blade rings, frozen wake lines) act on particles inside a
+ * differentiated time integration.
+ *  Segment arguments, core_radius, vatistas_n as vpm_eval_segments; x_tgt, gamma_tgt
+ *  [3][ld_tgt]; u_bar, dgamma_bar [3][ld_bar] (either may be NULL, not both); x_bar,
+ *  gamma_bar [3][ld_grad].  Without dgamma_bar, gamma_tgt and gamma_bar are not used.
+ *  Gradient arrays must not overlap the inputs or each other.
+ * Returns VPM_OK or the first violated condition. */
+vpm_status vpm_segments_backward(int32_t dtype, int64_t n_seg, const void* a, const void* b,
+                                 const void* gamma_seg, int64_t ld_seg, double core_radius, int32_t vatistas_n,
+                                 int64_t n_tgt, const void* x_tgt, const void* gamma_tgt, int64_t ld_tgt,
+                                 int32_t scheme, const void* u_bar, const void* dgamma_bar, int64_t ld_bar,
+                                 void* x_bar, void* gamma_bar, int64_t ld_grad, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * vpm_backward — vector-Jacobian product of vpm_eval_velocity_stretching (transposed
  * scheme, n_batch == 1): given seeds u_bar [3][ld_tgt] and dgamma_bar [3][ld_tgt] on the

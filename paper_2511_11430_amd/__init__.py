@@ -17,7 +17,7 @@ F64, F32C = 0, 1
 TRANSPOSED, CLASSICAL = 0, 1
 SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
 
-__all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_eval_segments_gradient", "vpm_backward", "vpm_rk3_stage",
+__all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_eval_segments_gradient", "vpm_segments_backward", "vpm_backward", "vpm_rk3_stage",
            "vpm_rk3_stage_backward", "vpm_diagnostics", "vpm_workspace_size", "vpm_variant_count",
            "vpm_variant_info", "vpm_axial_loss", "vpm_convert", "vpm_validate_inputs", "vpm_set_plan", "vpm_get_plan", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
            "SIGMA_SYMMETRIC"]
@@ -529,6 +529,57 @@ def vpm_eval_segments_gradient(a, b, gamma_seg, x_tgt, core_radius, vatistas_n=2
                                         _stream(stream))
     _check("vpm_eval_segments_gradient", st)
     return u_out, grad_out, dgamma_out
+
+
+def vpm_segments_backward(a, b, gamma_seg, x_tgt, core_radius, vatistas_n=2, u_bar=None, dgamma_bar=None, *,
+                          gamma_tgt=None, scheme=TRANSPOSED, x_bar=None, gamma_bar=None, stream=None):
+    """Vector-Jacobian product of :func:`vpm_eval_segments_gradient`'s velocity and stretching
+    with respect to the target particles.  Gradients are ADDED to x_bar and gamma_bar
+    (zero-initialised when allocated here).  Returns (x_bar, gamma_bar); gamma_bar is None
+    without dgamma_bar."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x_tgt)
+    tdt = x_tgt.dtype
+    _vec(x_tgt, "x_tgt", dtype=tdt)
+    n_tgt = x_tgt.shape[1]
+    _vec(a, "a", dtype=tdt)
+    n_seg = a.shape[1]
+    _vec(b, "b", n_seg, tdt)
+    _scal(gamma_seg, "gamma_seg", n_seg, tdt)
+    if a.shape[1] > 0 and (b.stride(0) != a.stride(0)):
+        raise ValueError("a and b must share one leading dimension")
+    if u_bar is None and dgamma_bar is None:
+        raise ValueError("give u_bar, dgamma_bar or both")
+    for t, nm in ((u_bar, "u_bar"), (dgamma_bar, "dgamma_bar")):
+        if t is not None:
+            _vec(t, nm, n_tgt, tdt)
+    if u_bar is not None and dgamma_bar is not None and _ld(u_bar) != _ld(dgamma_bar):
+        raise ValueError("u_bar and dgamma_bar must share one leading dimension")
+    ld_bar = _ld(u_bar if u_bar is not None else dgamma_bar)
+    if dgamma_bar is not None:
+        if gamma_tgt is None:
+            raise ValueError("dgamma_bar needs gamma_tgt")
+        _vec(gamma_tgt, "gamma_tgt", n_tgt, tdt)
+        if gamma_tgt.stride(0) != x_tgt.stride(0):
+            raise ValueError("x_tgt and gamma_tgt must share one leading dimension")
+    if x_bar is None:
+        x_bar = torch.zeros((3, n_tgt), dtype=tdt, device=x_tgt.device)
+    _vec(x_bar, "x_bar", n_tgt, tdt)
+    if dgamma_bar is not None:
+        if gamma_bar is None:
+            gamma_bar = torch.zeros((3, max(_ld(x_bar), 1)), dtype=tdt, device=x_tgt.device)[:, :n_tgt]
+        _vec(gamma_bar, "gamma_bar", n_tgt, tdt)
+        if _ld(gamma_bar) != _ld(x_bar):
+            raise ValueError("x_bar and gamma_bar must share one leading dimension")
+    else:
+        gamma_bar = None
+    st = lib.vpm_segments_backward(dt, n_seg, _p(a), _p(b), _p(gamma_seg), _ld(a) if n_seg else 0,
+                                   float(core_radius), int(vatistas_n), n_tgt, _p(x_tgt), _p(gamma_tgt),
+                                   _ld(x_tgt), int(scheme), _p(u_bar), _p(dgamma_bar), ld_bar, _p(x_bar),
+                                   _p(gamma_bar), _ld(x_bar), _stream(stream))
+    _check("vpm_segments_backward", st)
+    return x_bar, gamma_bar
 
 
 def vpm_backward(x_src, gamma_src, sigma_src, u_bar, dgamma_bar=None, x_tgt=None, gamma_tgt=None,

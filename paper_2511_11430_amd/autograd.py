@@ -13,13 +13,20 @@ reverse without recomputing the trajectory: at each stage it applies the RK3 reg
 adjoint (``vpm_rk3_stage_backward``) and adds J_F^T seed with ``vpm_backward`` at the
 stage's checkpointed input.
 
+An optional fixed lattice of straight segments (blade rings, frozen wake lines: a, b, strength,
+core radius, Vatistas exponent) acts on the particles in every stage: its velocity and its
+share of the stretching join F (``vpm_eval_segments_gradient``), its velocity adds at the
+control points, and the backward pass adds the segments' vector-Jacobian product
+(``vpm_segments_backward``).  The lattice itself is not differentiated.
+
 All arithmetic runs in libvpm kernels; this module only orders the calls and allocates
 tensors.
 """
 import torch
 
-from . import (SIGMA_SOURCE, vpm_axial_loss, vpm_backward, vpm_convert, vpm_eval_velocity_stretching,
-               vpm_rk3_stage, vpm_rk3_stage_backward)
+from . import (SIGMA_SOURCE, vpm_axial_loss, vpm_backward, vpm_convert, vpm_eval_segments,
+               vpm_eval_segments_gradient, vpm_eval_velocity_stretching, vpm_rk3_stage, vpm_rk3_stage_backward,
+               vpm_segments_backward)
 
 
 class VPMFunction(torch.autograd.Function):
@@ -62,7 +69,7 @@ class ControlPointVelocity(torch.autograd.Function):
         return xb, gb, None, None
 
 
-def rk3_forward(x0, gamma0, sigma, n_steps, dt, y_ctrl, checkpoints=None):
+def rk3_forward(x0, gamma0, sigma, n_steps, dt, y_ctrl, checkpoints=None, segments=None):
     """Run the program.  The state (x0, gamma0) may be float64 while sigma and y_ctrl are
     float32: then the RK3 registers stay in FP64 and each evaluation reads an FP32 copy of the
     state (mixed program).  Optionally appends each stage's evaluation input to
@@ -84,16 +91,23 @@ def rk3_forward(x0, gamma0, sigma, n_steps, dt, y_ctrl, checkpoints=None):
             if checkpoints is not None:
                 checkpoints.append((xe.clone(), ge.clone()))
             vpm_eval_velocity_stretching(xe, ge, sigma, u_out=u, dgamma_out=dg)
+            if segments is not None:
+                sa, sb, sg, rc, vn = segments
+                vpm_eval_segments_gradient(sa, sb, sg, xe, rc, vn, gamma_tgt=ge, want_grad=False, u_out=u,
+                                           dgamma_out=dg, accumulate=True)
             if mixed:
                 vpm_rk3_stage(k, dt, x, g, qx, qg, u, dg, x_eval=xe, gamma_eval=ge)
             else:
                 vpm_rk3_stage(k, dt, x, g, qx, qg, u, dg)
     uc, _ = vpm_eval_velocity_stretching(xe, ge, sigma, y_ctrl)
+    if segments is not None:
+        sa, sb, sg, rc, vn = segments
+        vpm_eval_segments(sa, sb, sg, y_ctrl, rc, vn, u_out=uc, accumulate=True)
     loss, _ = vpm_axial_loss(uc, want_seed=False)
     return x, g, uc, loss, (xe, ge)
 
 
-def rk3_backward(checkpoints, final_eval, sigma, uc, y_ctrl, dt, state_dtype, loss_bar=None):
+def rk3_backward(checkpoints, final_eval, sigma, uc, y_ctrl, dt, state_dtype, loss_bar=None, segments=None):
     """Gradient of the loss with respect to the program's initial (x, gamma), in state_dtype.
     loss_bar: float64 CUDA scalar (None = 1)."""
     xe, ge = final_eval
@@ -122,6 +136,9 @@ def rk3_backward(checkpoints, final_eval, sigma, uc, y_ctrl, dt, state_dtype, lo
         fold()
         vpm_rk3_stage_backward(k, dt, xb, gb, qxb, qgb, us, ds)
         vpm_backward(xk, gk, sigma, us, ds, x_src_bar=ix, gamma_src_bar=ig)
+        if segments is not None:
+            sa, sb, sg, rc, vn = segments
+            vpm_segments_backward(sa, sb, sg, xk, rc, vn, us, ds, gamma_tgt=gk, x_bar=ix, gamma_bar=ig)
     fold()
     return xb, gb
 
@@ -130,10 +147,11 @@ class RK3Program(torch.autograd.Function):
     """loss = program(x0, gamma0) with stage checkpoints kept in device memory."""
 
     @staticmethod
-    def forward(ctx, x0, gamma0, sigma, n_steps, dt, y_ctrl):
+    def forward(ctx, x0, gamma0, sigma, n_steps, dt, y_ctrl, segments=None):
         ckpt = []
         _, _, uc, loss, final_eval = rk3_forward(x0.contiguous(), gamma0.contiguous(), sigma.contiguous(),
-                                                 int(n_steps), float(dt), y_ctrl.contiguous(), ckpt)
+                                                 int(n_steps), float(dt), y_ctrl.contiguous(), ckpt, segments)
+        ctx.segments = segments
         ctx.ckpt = ckpt
         ctx.final_eval = final_eval
         ctx.dt = float(dt)
@@ -146,13 +164,19 @@ class RK3Program(torch.autograd.Function):
         sigma, uc, y_ctrl = ctx.saved_tensors
         lb = loss_bar.detach().to(torch.float64).reshape(()).contiguous()
         xb, gb = rk3_backward(ctx.ckpt, ctx.final_eval, sigma, uc, y_ctrl.contiguous(), ctx.dt, ctx.state_dtype,
-                              lb)
+                              lb, ctx.segments)
         ctx.ckpt = None
         ctx.final_eval = None
-        return xb, gb, None, None, None, None
+        ctx.segments = None
+        return xb, gb, None, None, None, None, None
 
 
-def rk3_program_loss(x0, gamma0, sigma, n_steps, dt, y_ctrl):
+def rk3_program_loss(x0, gamma0, sigma, n_steps, dt, y_ctrl, segments=None):
     """Differentiable loss of the RK3 wake program (see RK3Program).  float64 (x0, gamma0)
-    with float32 (sigma, y_ctrl) runs the mixed program."""
-    return RK3Program.apply(x0, gamma0, sigma, n_steps, dt, y_ctrl)
+    with float32 (sigma, y_ctrl) runs the mixed program.  ``segments`` = (a, b, strength,
+    core_radius, vatistas_n), device arrays in sigma's dtype: a fixed lattice acting on the
+    particles."""
+    if segments is not None:
+        sa, sb, sg, rc, vn = segments
+        segments = (sa.contiguous(), sb.contiguous(), sg.contiguous(), float(rc), int(vn))
+    return RK3Program.apply(x0, gamma0, sigma, n_steps, dt, y_ctrl, segments)

@@ -637,6 +637,57 @@ vpm_status vpm_eval_segments_gradient(int32_t dtype, int64_t n_seg, const void* 
     return hip_status(vpm::launch_segments_gradient(dtype, s, static_cast<hipStream_t>(stream)));
 }
 
+vpm_status vpm_segments_backward(int32_t dtype, int64_t n_seg, const void* a, const void* b,
+                                 const void* gamma_seg, int64_t ld_seg, double core_radius, int32_t vatistas_n,
+                                 int64_t n_tgt, const void* x_tgt, const void* gamma_tgt, int64_t ld_tgt,
+                                 int32_t scheme, const void* u_bar, const void* dgamma_bar, int64_t ld_bar,
+                                 void* x_bar, void* gamma_bar, int64_t ld_grad, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n_seg < 0 || n_tgt < 0 || ld_seg < n_seg || ld_tgt < n_tgt || ld_bar < n_tgt || ld_grad < n_tgt)
+        return VPM_ERR_SIZE;
+    if (n_seg > INT32_MAX || n_tgt > INT32_MAX) return VPM_ERR_SIZE;
+    if (n_seg > 0 && (!a || !b || !gamma_seg)) return VPM_ERR_NULL;
+    if (n_tgt > 0) {
+        if (!x_tgt || !x_bar || (!u_bar && !dgamma_bar)) return VPM_ERR_NULL;
+        if (dgamma_bar && (!gamma_tgt || !gamma_bar)) return VPM_ERR_NULL;
+    }
+    if (!(core_radius >= 0.0) || core_radius > 1e30) return VPM_ERR_SIZE;
+    if (vatistas_n < 1 || vatistas_n > 16) return VPM_ERR_ENUM;
+    if (scheme != VPM_STRETCH_TRANSPOSED && scheme != VPM_STRETCH_CLASSICAL) return VPM_ERR_ENUM;
+    const size_t es = elem_size(dtype);
+    const Range outs[2] = {span(x_bar, 3, ld_grad, n_tgt, es),
+                           dgamma_bar ? span(gamma_bar, 3, ld_grad, n_tgt, es) : Range{}};
+    const Range ins[7] = {span(a, 3, ld_seg, n_seg, es), span(b, 3, ld_seg, n_seg, es),
+                          span(gamma_seg, 1, ld_seg, n_seg, es), span(x_tgt, 3, ld_tgt, n_tgt, es),
+                          dgamma_bar ? span(gamma_tgt, 3, ld_tgt, n_tgt, es) : Range{},
+                          span(u_bar, 3, ld_bar, n_tgt, es), span(dgamma_bar, 3, ld_bar, n_tgt, es)};
+    for (const Range& o : outs)
+        for (const Range& r : ins)
+            if (overlap(o, r)) return VPM_ERR_ALIAS;
+    if (overlap(outs[0], outs[1])) return VPM_ERR_ALIAS;
+    if (n_tgt == 0) return VPM_OK;
+    vpm::SegArgs s{};
+    s.a = a;
+    s.b = b;
+    s.gam = gamma_seg;
+    s.ld_seg = ld_seg;
+    s.n_seg = n_seg;
+    s.rc = core_radius;
+    s.vn = vatistas_n;
+    s.xt = x_tgt;
+    s.ldt = ld_tgt;
+    s.n_tgt = n_tgt;
+    s.ldo = ld_grad;
+    s.gt = dgamma_bar ? gamma_tgt : nullptr;
+    s.classical = scheme == VPM_STRETCH_CLASSICAL;
+    s.ub = u_bar;
+    s.db = dgamma_bar;
+    s.ldb = ld_bar;
+    s.xb = x_bar;
+    s.gb = dgamma_bar ? gamma_bar : nullptr;
+    return hip_status(vpm::launch_segments_vjp(dtype, s, static_cast<hipStream_t>(stream)));
+}
+
 vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                         const int64_t* tgt_off, const void* x_src, const void* gamma_src,
                         const void* sigma_src, int64_t ld_src, const void* x_tgt,

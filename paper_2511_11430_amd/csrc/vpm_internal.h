@@ -91,9 +91,16 @@ struct SegArgs {
     void* grad;      // J[(3a+b)][ldo] = du_a/dx_b
     void* dg;        // stretching [3][ldo]: J^T gamma (transposed) or J gamma (classical)
     int32_t classical;
+    // adjoint form only (launch_segments_vjp): seeds [3][ldb], gradients [3][ldo] (added to)
+    const void* ub;  // may be null
+    const void* db;  // may be null (then gt, gb unused)
+    int64_t ldb;
+    void* xb;
+    void* gb;
 };
 hipError_t launch_segments(int dtype, const SegArgs& a, hipStream_t st);
 hipError_t launch_segments_gradient(int dtype, const SegArgs& a, hipStream_t st);
+hipError_t launch_segments_vjp(int dtype, const SegArgs& a, hipStream_t st);
 
 // ---------------------------------------------------------------- adjoint
 // Gather form: each lane owns one particle of the "lane set" and loops over the "loop set".

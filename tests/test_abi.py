@@ -346,3 +346,24 @@ def test_segments_gradient_validation():
     args0[11] = 0
     args0[16] = 0
     assert f(*args0) == OK                    # no targets: nothing to launch
+
+
+def test_segments_backward_validation():
+    lib = _lib.load()
+    f = lib.vpm_segments_backward
+
+    def args(**k):
+        return [k.get("dt", F32C), 10, P(0), P(1), P(2), 10, k.get("rc", 0.02), k.get("vn", 2), 5, P(3),
+                k.get("gt", P(4)), 5, k.get("sch", 0), k.get("ub", P(5)), k.get("db", P(6)), k.get("ldb", 5),
+                k.get("xb", P(7)), k.get("gb", P(8)), 5, None]
+    assert f(*args(dt=3)) == DTYPE
+    assert f(*args(ldb=4)) == SIZE
+    assert f(*args(vn=17)) == ENUM
+    assert f(*args(sch=-1)) == ENUM
+    assert f(*args(ub=None, db=None)) == NULL    # no seed
+    assert f(*args(xb=None)) == NULL
+    assert f(*args(gb=None)) == NULL             # dgamma_bar needs gamma_bar
+    assert f(*args(gt=None)) == NULL             # and gamma_tgt
+    assert f(*args(xb=P(3))) == ALIAS            # gradient over the positions
+    assert f(*args(gb=P(6))) == ALIAS            # gradient over a seed
+    assert f(*args(gb=P(7))) == ALIAS            # the two gradients on one array
