@@ -44,6 +44,8 @@ def _load():
         lib.orc_rk3_program_jvp.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, i32, dbl, i32, i32, i64, _dp,
                                             _dp, _dp, i32] + lat
         lib.orc_segments_vjp.argtypes = [i64, _dp, _dp, _dp, dbl, i32, i64, _dp, _dp, _dp, _dp, i32, _dp, _dp, i32]
+        lib.orc_fmm.argtypes = [i64, _dp, _dp, _dp, i32, i32, i32, _dp, _dp, i32]
+        lib.orc_inv_r_taylor.argtypes = [_dp, i32, _dp, ctypes.POINTER(ctypes.c_int)]
         lib.orc_diagnostics.argtypes = [i64, _dp, _dp, _dp, _dp, _dp]
         lib.orc_gradient.argtypes = [i64, _dp, _dp, _dp, i64, _dp, _dp, _lp, i32, _dp, i32]
         lib.orc_vreman.argtypes = [i64, _dp, _dp, dbl, _dp]
@@ -52,7 +54,7 @@ def _load():
         lib.orc_segments_gradient.argtypes = [i64, _dp, _dp, _dp, dbl, i32, i64, _dp, _dp, i32]
         for f in ("orc_weights", "orc_ghk", "orc_eval", "orc_eval_jvp", "orc_segments",
                   "orc_rk3_program", "orc_rk3_program_jvp", "orc_diagnostics", "orc_gradient",
-                  "orc_vreman", "orc_pse", "orc_pse_at", "orc_segments_gradient", "orc_segments_vjp"):
+                  "orc_vreman", "orc_pse", "orc_pse_at", "orc_segments_gradient", "orc_segments_vjp", "orc_fmm", "orc_inv_r_taylor"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -216,6 +218,33 @@ def _lattice(segments):
         raise ValueError("segments: a, b must be (3, n) and gamma (n,)")
     return [A.shape[1], A.ctypes.data_as(_dp), B.ctypes.data_as(_dp), G.ctypes.data_as(_dp), float(rc),
             int(vn)], (A, B, G)
+
+
+def fmm(x, gam, sig, level, order, scheme=TRANSPOSED, nthreads=0):
+    """Cartesian FMM (Sec. II.B) of the self-interaction: uniform octree of depth ``level``
+    over the bounding cube, Taylor expansions of the vector potential of order ``order``,
+    exact Gaussian kernel over each leaf's 27 neighbours.  Returns (u, dgamma)."""
+    lib = _load()
+    X, G = _vec(x, "x"), _vec(gam, "gam")
+    s = np.ascontiguousarray(sig, dtype=np.float64).reshape(-1)
+    u, d = np.zeros_like(X), np.zeros_like(X)
+    rc = lib.orc_fmm(X.shape[1], X.ctypes.data_as(_dp), G.ctypes.data_as(_dp), s.ctypes.data_as(_dp), int(level),
+                     int(order), int(scheme), u.ctypes.data_as(_dp), d.ctypes.data_as(_dp), int(nthreads))
+    _check(rc, "fmm")
+    return u, d
+
+
+def inv_r_taylor(R, Q):
+    """Taylor coefficients of 1/|R + h| in h up to total degree Q: (coef, multi-indices (T, 3))."""
+    lib = _load()
+    from math import comb
+    nt = comb(Q + 3, 3)
+    c = np.zeros(nt)
+    idx = np.zeros((nt, 3), dtype=np.int32)
+    Rv = np.ascontiguousarray(R, dtype=np.float64)
+    _check(lib.orc_inv_r_taylor(Rv.ctypes.data_as(_dp), int(Q), c.ctypes.data_as(_dp),
+                                idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), "inv_r_taylor")
+    return c, idx
 
 
 def segments_vjp(a, b, gam_seg, x_tgt, core_radius, vatistas_n, u_bar, dgamma_bar=None, gam_tgt=None,

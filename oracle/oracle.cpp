@@ -49,7 +49,10 @@
 // excluded by index; Vatistas exponent n given by the caller (2 by default); segments
 // with a vanishing arm or length contribute nothing.
 
+#include <array>
 #include <cmath>
+#include <cstdlib>
+#include <map>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -541,6 +544,364 @@ template <class T> void set_threads(int nth) {
     if (nth > 0) omp_set_num_threads(nth);
 }
 
+// ---------------------------------------------------------------- Cartesian FMM
+// The far field of the particle sum with the singular kernel (the Gaussian differs from it
+// by less than 2e-9 beyond 7 core radii), as the Laplace vector potential
+//   psi(y) = sum_j Gamma_j G(y - x_j),  G(r) = 1/(4 pi |r|),  u = curl psi,
+//   J_ae = d u_a / d y_e = eps_abc d_e d_b psi_c,
+// expanded in Cartesian Taylor series of total order p (Sec. II.B names a Cartesian FMM):
+//   multipole  M_k = sum_j Gamma_j (x_j - c)^k / k!                          (P2M)
+//   shift      M_k(c') = sum_{m <= k} M_m(c) (c - c')^(k-m) / (k-m)!           (M2M)
+//   local      L_n = sum_{|k| <= p-|n|} (-1)^|k| D_{n+k}(c_t - c_s) M_k        (M2L)
+//              with D_m = d^m G, so psi(y) ~ sum_n L_n (y - c_t)^n / n!
+//   shift      L_n(c') = sum_{m >= n, |m| <= p} L_m(c) (c' - c)^(m-n) / (m-n)! (L2L)
+//   evaluate   d_b psi = sum_n L_{n+e_b} a^n / n!, d_e d_b psi likewise        (L2P)
+// on a uniform octree of depth `level` over the particles' bounding cube: the leaves'
+// 27-neighbourhoods are summed directly with the exact Gaussian kernel (P2P, self pair
+// excluded), and at each level from 2 down every cell takes M2L from the children of its
+// parent's neighbours that are not its own neighbours.  Derivatives of 1/|R| come from the
+// Taylor expansion of 1/|R + h| in h, built by composing polynomials:
+//   1/|R + h| = |R|^-1 (1 + w)^(-1/2),  w = (2 R.h + |h|^2)/|R|^2,
+//   (1 + w)^(-1/2) = sum_m binom(-1/2, m) w^m,
+// whose coefficient of h^n is D_n / n! of 1/|R|.
+
+// Multi-indices with |n| <= P: by total degree, then decreasing n_x, then decreasing n_y.
+struct Terms {
+    int P = 0;
+    std::vector<std::array<int, 3>> idx;
+    std::vector<int> pos;  // (a (P+1) + b)(P+1) + c -> position, -1 beyond P
+    explicit Terms(int P_) : P(P_), pos(size_t(P_ + 1) * (P_ + 1) * (P_ + 1), -1) {
+        for (int d = 0; d <= P; ++d)
+            for (int a = d; a >= 0; --a)
+                for (int b = d - a; b >= 0; --b) {
+                    const int c = d - a - b;
+                    pos[(size_t(a) * (P + 1) + b) * (P + 1) + c] = int(idx.size());
+                    idx.push_back({a, b, c});
+                }
+    }
+    int at(int a, int b, int c) const {
+        if (a < 0 || b < 0 || c < 0 || a + b + c > P) return -1;
+        return pos[(size_t(a) * (P + 1) + b) * (P + 1) + c];
+    }
+    int size() const { return int(idx.size()); }
+};
+
+inline double factorial(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+// Product of two polynomials in h (coefficients by Terms), truncated at total degree P.
+std::vector<double> poly_mul(const std::vector<double>& a, const std::vector<double>& b, const Terms& T) {
+    std::vector<double> out(T.size(), 0.0);
+    std::vector<int> nzb;
+    for (int j = 0; j < T.size(); ++j)
+        if (b[j] != 0.0) nzb.push_back(j);
+    for (int i = 0; i < T.size(); ++i) {
+        if (a[i] == 0.0) continue;
+        const auto& ni = T.idx[i];
+        for (int j : nzb) {
+            const auto& nj = T.idx[j];
+            const int k = T.at(ni[0] + nj[0], ni[1] + nj[1], ni[2] + nj[2]);
+            if (k >= 0) out[k] += a[i] * b[j];
+        }
+    }
+    return out;
+}
+
+// Taylor coefficients of 1/|R + h| up to total degree Q (T.P == Q): D_n(R)/n! of 1/|R|.
+std::vector<double> inv_r_taylor(const double R[3], const Terms& T) {
+    const int Q = T.P;
+    const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+    std::vector<double> w(T.size(), 0.0), acc(T.size(), 0.0), wp(T.size(), 0.0);
+    for (int a = 0; a < 3; ++a) {
+        int e[3] = {0, 0, 0};
+        e[a] = 1;
+        if (Q >= 1) w[T.at(e[0], e[1], e[2])] = 2.0 * R[a] / r2;
+        e[a] = 2;
+        if (Q >= 2) w[T.at(e[0], e[1], e[2])] = 1.0 / r2;
+    }
+    acc[0] = 1.0;
+    wp[0] = 1.0;
+    double binom = 1.0;
+    for (int m = 1; m <= Q; ++m) {
+        wp = poly_mul(wp, w, T);
+        binom *= (-0.5 - (m - 1)) / m;
+        for (int i = 0; i < T.size(); ++i) acc[i] += binom * wp[i];
+    }
+    const double ir = 1.0 / std::sqrt(r2);
+    for (double& v : acc) v *= ir;
+    return acc;
+}
+
+struct FmmCell {
+    int64_t key;            // (ix << 40) | (iy << 20) | iz at its level
+    double c[3];            // centre
+    std::vector<double> M;  // 3 x terms (component-major)
+    std::vector<double> L;
+};
+
+inline int64_t cell_key(int64_t ix, int64_t iy, int64_t iz) { return (ix << 40) | (iy << 20) | iz; }
+inline void key_coords(int64_t k, int64_t* i) { i[0] = k >> 40; i[1] = (k >> 20) & 0xFFFFF; i[2] = k & 0xFFFFF; }
+
+void fmm_eval(int64_t n, const double* x, const double* G, const double* sig, int level, int p, int scheme,
+              double* u, double* dg) {
+    const Terms T(p);
+    const int nt = T.size();
+    // root cube: bounding box centre, half of the largest extent
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = hi[d] = n > 0 ? x[d * n] : 0.0;
+        for (int64_t i = 1; i < n; ++i) {
+            lo[d] = std::fmin(lo[d], x[d * n + i]);
+            hi[d] = std::fmax(hi[d], x[d * n + i]);
+        }
+    }
+    double H = 0.0, c0[3];
+    for (int d = 0; d < 3; ++d) {
+        c0[d] = 0.5 * (lo[d] + hi[d]);
+        H = std::fmax(H, 0.5 * (hi[d] - lo[d]));
+    }
+    if (!(H > 0.0)) H = 1.0;
+    double corner[3];
+    for (int d = 0; d < 3; ++d) corner[d] = c0[d] - H;
+    auto width = [&](int l) { return std::ldexp(2.0 * H, -l); };
+    const int64_t side = int64_t(1) << level;
+    // leaves
+    std::vector<int64_t> leaf_of(n);
+    std::map<int64_t, std::vector<int64_t>> leaves;
+    const double wL = width(level);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t ic[3];
+        for (int d = 0; d < 3; ++d) {
+            int64_t v = int64_t(std::floor((x[d * n + i] - corner[d]) / wL));
+            ic[d] = v < 0 ? 0 : (v >= side ? side - 1 : v);
+        }
+        leaf_of[i] = cell_key(ic[0], ic[1], ic[2]);
+        leaves[leaf_of[i]].push_back(i);
+    }
+    // cells of every level
+    std::vector<std::map<int64_t, FmmCell>> lev(level + 1);
+    for (const auto& kv : leaves) {
+        int64_t ic[3];
+        key_coords(kv.first, ic);
+        for (int l = level; l >= 0; --l) {
+            const int sh = level - l;
+            const int64_t k = cell_key(ic[0] >> sh, ic[1] >> sh, ic[2] >> sh);
+            if (lev[l].count(k)) continue;
+            FmmCell C;
+            C.key = k;
+            for (int d = 0; d < 3; ++d) C.c[d] = corner[d] + (double((&ic[0])[d] >> sh) + 0.5) * width(l);
+            C.M.assign(3 * nt, 0.0);
+            C.L.assign(3 * nt, 0.0);
+            lev[l][k] = C;
+        }
+    }
+    // P2M
+    for (auto& kv : lev[level]) {
+        FmmCell& C = kv.second;
+        for (int64_t i : leaves[kv.first]) {
+            const double a[3] = {x[i] - C.c[0], x[n + i] - C.c[1], x[2 * n + i] - C.c[2]};
+            for (int t = 0; t < nt; ++t) {
+                const auto& k = T.idx[t];
+                const double mono = std::pow(a[0], k[0]) * std::pow(a[1], k[1]) * std::pow(a[2], k[2]) /
+                                    (factorial(k[0]) * factorial(k[1]) * factorial(k[2]));
+                for (int d = 0; d < 3; ++d) C.M[d * nt + t] += G[d * n + i] * mono;
+            }
+        }
+    }
+    // M2M
+    for (int l = level - 1; l >= 0; --l) {
+        for (auto& kv : lev[l + 1]) {
+            const FmmCell& Ch = kv.second;
+            int64_t ic[3];
+            key_coords(Ch.key, ic);
+            FmmCell& Pa = lev[l][cell_key(ic[0] >> 1, ic[1] >> 1, ic[2] >> 1)];
+            const double dlt[3] = {Ch.c[0] - Pa.c[0], Ch.c[1] - Pa.c[1], Ch.c[2] - Pa.c[2]};
+            for (int t = 0; t < nt; ++t) {
+                const auto& k = T.idx[t];
+                for (int s = 0; s < nt; ++s) {
+                    const auto& m = T.idx[s];
+                    if (m[0] > k[0] || m[1] > k[1] || m[2] > k[2]) continue;
+                    const int q[3] = {k[0] - m[0], k[1] - m[1], k[2] - m[2]};
+                    const double f = std::pow(dlt[0], q[0]) * std::pow(dlt[1], q[1]) * std::pow(dlt[2], q[2]) /
+                                     (factorial(q[0]) * factorial(q[1]) * factorial(q[2]));
+                    for (int d = 0; d < 3; ++d) Pa.M[d * nt + t] += Ch.M[d * nt + s] * f;
+                }
+            }
+        }
+    }
+    // M2L (levels 2 .. level)
+    const Terms T2(2 * p);
+    for (int l = 2; l <= level; ++l) {
+        std::map<int64_t, std::vector<double>> dcache;  // offset -> D_m / 4 pi, |m| <= 2p
+        std::vector<int64_t> keys;
+        for (const auto& kv : lev[l]) keys.push_back(kv.first);
+#pragma omp parallel for schedule(dynamic)
+        for (size_t ci = 0; ci < keys.size(); ++ci) {
+            FmmCell& C = lev[l].at(keys[ci]);
+            int64_t ic[3];
+            key_coords(C.key, ic);
+            for (int64_t dx = -1; dx <= 1; ++dx)
+                for (int64_t dy = -1; dy <= 1; ++dy)
+                    for (int64_t dz = -1; dz <= 1; ++dz) {
+                        const int64_t px = (ic[0] >> 1) + dx, py = (ic[1] >> 1) + dy, pz = (ic[2] >> 1) + dz;
+                        const int64_t ps = int64_t(1) << (l - 1);
+                        if (px < 0 || py < 0 || pz < 0 || px >= ps || py >= ps || pz >= ps) continue;
+                        for (int ch = 0; ch < 8; ++ch) {
+                            const int64_t sx = 2 * px + (ch >> 2), sy = 2 * py + ((ch >> 1) & 1),
+                                          sz = 2 * pz + (ch & 1);
+                            if (std::llabs(sx - ic[0]) <= 1 && std::llabs(sy - ic[1]) <= 1 &&
+                                std::llabs(sz - ic[2]) <= 1)
+                                continue;
+                            auto it = lev[l].find(cell_key(sx, sy, sz));
+                            if (it == lev[l].end()) continue;
+                            const FmmCell& S = it->second;
+                            const int64_t off = cell_key(sx - ic[0] + 8, sy - ic[1] + 8, sz - ic[2] + 8);
+                            std::vector<double> D;
+#pragma omp critical(fmm_dcache)
+                            {
+                                auto dit = dcache.find(off);
+                                if (dit != dcache.end()) D = dit->second;
+                            }
+                            if (D.empty()) {
+                                // offset of the centres, canonically (integer offset) x (cell width)
+                                const double R[3] = {double(ic[0] - sx) * width(l), double(ic[1] - sy) * width(l),
+                                                     double(ic[2] - sz) * width(l)};
+                                D = inv_r_taylor(R, T2);
+                                for (int t = 0; t < T2.size(); ++t) {
+                                    const auto& m = T2.idx[t];
+                                    D[t] *= factorial(m[0]) * factorial(m[1]) * factorial(m[2]) / (4.0 * kPi);
+                                }
+#pragma omp critical(fmm_dcache)
+                                dcache[off] = D;
+                            }
+                            for (int tn = 0; tn < nt; ++tn) {
+                                const auto& nn = T.idx[tn];
+                                const int dn = nn[0] + nn[1] + nn[2];
+                                for (int tk = 0; tk < nt; ++tk) {
+                                    const auto& k = T.idx[tk];
+                                    const int dk = k[0] + k[1] + k[2];
+                                    if (dn + dk > p) continue;
+                                    const double Dv = D[T2.at(nn[0] + k[0], nn[1] + k[1], nn[2] + k[2])];
+                                    const double sgn = (dk & 1) ? -1.0 : 1.0;
+                                    for (int d = 0; d < 3; ++d) C.L[d * nt + tn] += sgn * Dv * S.M[d * nt + tk];
+                                }
+                            }
+                        }
+                    }
+        }
+    }
+    // L2L (parents at levels 2 .. level-1)
+    for (int l = 2; l < level; ++l) {
+        for (auto& kv : lev[l + 1]) {
+            FmmCell& Ch = kv.second;
+            int64_t ic[3];
+            key_coords(Ch.key, ic);
+            const FmmCell& Pa = lev[l].at(cell_key(ic[0] >> 1, ic[1] >> 1, ic[2] >> 1));
+            const double dlt[3] = {Ch.c[0] - Pa.c[0], Ch.c[1] - Pa.c[1], Ch.c[2] - Pa.c[2]};
+            for (int tn = 0; tn < nt; ++tn) {
+                const auto& nn = T.idx[tn];
+                for (int tm = 0; tm < nt; ++tm) {
+                    const auto& m = T.idx[tm];
+                    if (m[0] < nn[0] || m[1] < nn[1] || m[2] < nn[2]) continue;
+                    const int q[3] = {m[0] - nn[0], m[1] - nn[1], m[2] - nn[2]};
+                    const double f = std::pow(dlt[0], q[0]) * std::pow(dlt[1], q[1]) * std::pow(dlt[2], q[2]) /
+                                     (factorial(q[0]) * factorial(q[1]) * factorial(q[2]));
+                    for (int d = 0; d < 3; ++d) Ch.L[d * nt + tn] += Pa.L[d * nt + tm] * f;
+                }
+            }
+        }
+    }
+    // L2P and P2P
+    std::vector<int64_t> leaf_keys;
+    for (const auto& kv : leaves) leaf_keys.push_back(kv.first);
+    for (int64_t i = 0; i < 3 * n; ++i) u[i] = dg[i] = 0.0;
+#pragma omp parallel for schedule(dynamic)
+    for (size_t li = 0; li < leaf_keys.size(); ++li) {
+        const std::vector<int64_t>& tg = leaves.at(leaf_keys[li]);
+        const FmmCell& C = lev[level].at(leaf_keys[li]);
+        int64_t ic[3];
+        key_coords(leaf_keys[li], ic);
+        // near field: the 27 neighbouring leaves, exact kernel
+        std::vector<int64_t> src;
+        for (int64_t dx = -1; dx <= 1; ++dx)
+            for (int64_t dy = -1; dy <= 1; ++dy)
+                for (int64_t dz = -1; dz <= 1; ++dz) {
+                    auto it = leaves.find(cell_key(ic[0] + dx, ic[1] + dy, ic[2] + dz));
+                    if (ic[0] + dx < 0 || ic[1] + dy < 0 || ic[2] + dz < 0 || it == leaves.end()) continue;
+                    src.insert(src.end(), it->second.begin(), it->second.end());
+                }
+        for (int64_t i : tg) {
+            const double xi[3] = {x[i], x[n + i], x[2 * n + i]};
+            const double Gi[3] = {G[i], G[n + i], G[2 * n + i]};
+            Neumaier au[3], ad[3];
+            for (int64_t j : src) {
+                if (j == i) continue;
+                const double r[3] = {xi[0] - x[j], xi[1] - x[n + j], xi[2] - x[2 * n + j]};
+                const double Gj[3] = {G[j], G[n + j], G[2 * n + j]};
+                const double s = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                double g, h;
+                ghk<double>(s, sig[j], &g, &h, nullptr);
+                const double v[3] = {Gj[1] * r[2] - Gj[2] * r[1], Gj[2] * r[0] - Gj[0] * r[2],
+                                     Gj[0] * r[1] - Gj[1] * r[0]};
+                for (int a = 0; a < 3; ++a) au[a].add(g * v[a]);
+                if (scheme == 0) {
+                    const double cgg[3] = {Gi[1] * Gj[2] - Gi[2] * Gj[1], Gi[2] * Gj[0] - Gi[0] * Gj[2],
+                                           Gi[0] * Gj[1] - Gi[1] * Gj[0]};
+                    const double tau = Gi[0] * v[0] + Gi[1] * v[1] + Gi[2] * v[2];
+                    for (int a = 0; a < 3; ++a) ad[a].add(g * cgg[a] + h * tau * r[a]);
+                } else {
+                    const double cgg[3] = {Gj[1] * Gi[2] - Gj[2] * Gi[1], Gj[2] * Gi[0] - Gj[0] * Gi[2],
+                                           Gj[0] * Gi[1] - Gj[1] * Gi[0]};
+                    const double rg = r[0] * Gi[0] + r[1] * Gi[1] + r[2] * Gi[2];
+                    for (int a = 0; a < 3; ++a) ad[a].add(g * cgg[a] + h * rg * v[a]);
+                }
+            }
+            // far field from the local expansion (levels >= 2 only)
+            double gp[3][3] = {{0}}, hp[3][3][3] = {{{0}}};  // d_b psi_c, d_e d_b psi_c
+            if (level >= 2) {
+                const double a[3] = {xi[0] - C.c[0], xi[1] - C.c[1], xi[2] - C.c[2]};
+                for (int tn = 0; tn < nt; ++tn) {
+                    const auto& nn = T.idx[tn];
+                    const double mono = std::pow(a[0], nn[0]) * std::pow(a[1], nn[1]) * std::pow(a[2], nn[2]) /
+                                        (factorial(nn[0]) * factorial(nn[1]) * factorial(nn[2]));
+                    for (int b = 0; b < 3; ++b) {
+                        int e1[3] = {nn[0], nn[1], nn[2]};
+                        e1[b] += 1;
+                        const int t1 = T.at(e1[0], e1[1], e1[2]);
+                        if (t1 < 0) continue;
+                        for (int c = 0; c < 3; ++c) gp[b][c] += C.L[c * nt + t1] * mono;
+                        for (int e = 0; e < 3; ++e) {
+                            int e2[3] = {e1[0], e1[1], e1[2]};
+                            e2[e] += 1;
+                            const int t2 = T.at(e2[0], e2[1], e2[2]);
+                            if (t2 < 0) continue;
+                            for (int c = 0; c < 3; ++c) hp[e][b][c] += C.L[c * nt + t2] * mono;
+                        }
+                    }
+                }
+            }
+            double uf[3] = {0, 0, 0}, J[3][3] = {{0}};
+            for (int aa = 0; aa < 3; ++aa)
+                for (int b = 0; b < 3; ++b)
+                    for (int c = 0; c < 3; ++c) {
+                        const double e = levi(aa, b, c);
+                        if (e == 0.0) continue;
+                        uf[aa] += e * gp[b][c];
+                        for (int ee = 0; ee < 3; ++ee) J[aa][ee] += e * hp[ee][b][c];
+                    }
+            for (int a = 0; a < 3; ++a) {
+                double sf = 0.0;
+                for (int b = 0; b < 3; ++b) sf += (scheme == 0 ? J[b][a] : J[a][b]) * Gi[b];
+                u[a * n + i] = au[a].get() + uf[a];
+                dg[a * n + i] = ad[a].get() + sf;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // ================================================================ C entry points
@@ -772,4 +1133,29 @@ int orc_diagnostics(int64_t n, const double* x, const double* G, const double* u
     return 0;
 }
 
+
+// Cartesian FMM evaluation of the self-interaction of n particles (velocity and stretching,
+// scheme 0 transposed / 1 classical) on a uniform octree of depth `level` (0..10) with
+// expansions of order `order` (1..16).
+int orc_fmm(int64_t n, const double* x, const double* G, const double* sig, int level, int order, int scheme,
+            double* u, double* dg, int nthreads) {
+    if (n < 0 || (n > 0 && (!x || !G || !sig || !u || !dg))) return 1;
+    if (level < 0 || level > 10 || order < 1 || order > 16 || scheme < 0 || scheme > 1) return 1;
+    set_threads<double>(nthreads);
+    fmm_eval(n, x, G, sig, level, order, scheme, u, dg);
+    return 0;
+}
+
+// Taylor coefficients of 1/|R + h| in h up to total degree Q, in the oracle's multi-index
+// order (by degree, then decreasing n_x, then decreasing n_y); idx receives the multi-indices.
+int orc_inv_r_taylor(const double* R, int Q, double* coef, int* idx) {
+    if (!R || !coef || !idx || Q < 0 || Q > 40) return 1;
+    const Terms T(Q);
+    const std::vector<double> c = inv_r_taylor(R, T);
+    for (int t = 0; t < T.size(); ++t) {
+        coef[t] = c[t];
+        for (int d = 0; d < 3; ++d) idx[3 * t + d] = T.idx[t][d];
+    }
+    return 0;
+}
 }  // extern "C"
