@@ -212,7 +212,39 @@ def main():
                                   "sample": f"{m} seeded targets x {N} sources of the same wake, FP64 direct sums "
                                             f"({t_or:.1f} s)", "cpu": cpu_model}
 
+    def timed_once(fn, reps=1):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
     if not args.quick:
+        # ------------------------------------------------------------------ Cartesian FMM (Sec. II.B)
+        # the same 1M wake and sums through the FMM: depth 6 (leaf width 6.5 sigma_max), two
+        # orders; error against the direct FP32C sums above and the oracle's sample
+        fmm_legs = []
+        for lev, order in ((6, 8), (6, 12)):
+            fws = torch.empty(vpm.vpm_fmm_workspace_size(N, lev, order, torch.float32), dtype=torch.uint8,
+                              device=dev)
+            uf, df = torch.empty_like(x), torch.empty_like(x)
+            fmm_ms = timed_once(lambda: vpm.vpm_fmm_eval(x0, g0, s, lev, order, u_out=uf, dgamma_out=df,
+                                                         workspace=fws), reps=3)
+            UF, DF = uf.cpu().double().numpy(), df.cpu().double().numpy()
+            fmm_legs.append({"level": lev, "order": order, "ms": round(fmm_ms, 3),
+                             "speedup_over_direct": round(k_ms / fmm_ms, 2),
+                             "direct_equivalent_gpair_s": round(pairs / (fmm_ms * 1e-3) / 1e9, 1),
+                             "rel_l2_u_vs_direct": rel(UF, U), "rel_l2_dgamma_vs_direct": rel(DF, D),
+                             "rel_l2_u_vs_oracle": rel(UF[:, idx], uo), "rel_l2_dgamma_vs_oracle": rel(DF[:, idx], do)})
+            log(f"fmm level {lev} order {order}: {fmm_ms:.1f} ms")
+            del fws, uf, df
+        result["fmm"] = {"workload": f"forward-flight skewed wake N_p={N} (self evaluation, FP32C near field, "
+                                     f"FP64 expansions)", "legs": fmm_legs}
+
         # ------------------------------------------------------------------ FP64 GPU path
         x64, g64, s64 = (torch.tensor(np.ascontiguousarray(W.to_f32(c[k])), dtype=torch.float64, device=dev)
                          for k in ("x", "gamma", "sigma"))
@@ -243,17 +275,6 @@ def main():
         dv = torch.empty_like(x)
         pse_ws = torch.empty(vpm._lib.load().vpm_diffusion_workspace_size(vpm.F32C, 1, vpm._offsets([0, N])),
                              dtype=torch.uint8, device=dev)
-
-        def timed_once(fn, reps=1):
-            fn()
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(reps):
-                fn()
-            b.record(stream)
-            torch.cuda.synchronize()
-            return a.elapsed_time(b) / reps
 
         grad_ms = timed_once(lambda: vpm.vpm_eval_velocity_gradient(x, g, s, u_out=u, dgamma_out=dg, grad_out=Jv))
         vre_ms = timed_once(lambda: vpm.vpm_sgs_vreman(Jv, s, W.C_V, nu_t_out=nut), reps=5)

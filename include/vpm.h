@@ -251,6 +251,30 @@ vpm_status vpm_segments_backward(int32_t dtype, int64_t n_seg, const void* a, co
                                  void* x_bar, void* gamma_bar, int64_t ld_grad, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * vpm_fmm_eval — the self-interaction of n particles (velocity u and stretching dGamma/dt, as
+ * vpm_eval_velocity_stretching with self = 1 and the source core rule) by a Cartesian fast
+ * multipole method (Sec. II.B: the paper accelerates the velocity and its gradient with one):
+ *  - a uniform octree of depth `level` over the particles' bounding cube (centre of the box,
+ *    half of its largest extent); each particle belongs to the leaf floor((x - corner)/w);
+ *  - each leaf's 27 neighbouring leaves are summed directly with the exact Gaussian kernel;
+ *  - all other pairs through Taylor expansions of total order `order` of the vector
+ *    potential of the point-vortex kernel (P2M, M2M, M2L from level 2 on, L2L, L2P), which
+ *    the Gaussian equals to 2e-9 beyond seven core radii: choose the level so that the leaf
+ *    width is at least seven times the largest sigma.
+ * The error of the far field falls geometrically with the order (about x0.6 per order on
+ * rotor wakes).  Expansions are FP64 for both dtypes; VPM_F32C sums the near field in FP32
+ * with compensation.
+ *  x, gamma [3][ld], sigma [ld]; u_out, dgamma_out [3][ld_out] (written, in the input order).
+ *  0 <= level <= 10, 1 <= order <= 16, n < 2^30.
+ *  workspace        vpm_fmm_workspace_size(dtype, n, level, order) bytes (0 if invalid);
+ *                   holds the sorted particles, the tree and the expansions.
+ * Returns VPM_OK or the first violated condition. */
+vpm_status vpm_fmm_eval(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* sigma, int64_t ld,
+                        int32_t level, int32_t order, int32_t scheme, void* u_out, void* dgamma_out, int64_t ld_out,
+                        void* workspace, size_t ws_bytes, void* stream);
+size_t vpm_fmm_workspace_size(int32_t dtype, int64_t n, int32_t level, int32_t order);
+
+/* ---------------------------------------------------------------------------------------
  * vpm_backward — vector-Jacobian product of vpm_eval_velocity_stretching (transposed
  * scheme, n_batch == 1): given seeds u_bar [3][ld_tgt] and dgamma_bar [3][ld_tgt] on the
  * outputs, ADD dL/dx and dL/dGamma to the gradient arrays.  sigma is not differentiated.

@@ -17,7 +17,7 @@ F64, F32C = 0, 1
 TRANSPOSED, CLASSICAL = 0, 1
 SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
 
-__all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_eval_segments_gradient", "vpm_segments_backward", "vpm_backward", "vpm_rk3_stage",
+__all__ = ["vpm_eval_velocity_stretching", "vpm_eval_segments", "vpm_eval_segments_gradient", "vpm_segments_backward", "vpm_fmm_eval", "vpm_fmm_workspace_size", "vpm_backward", "vpm_rk3_stage",
            "vpm_rk3_stage_backward", "vpm_diagnostics", "vpm_workspace_size", "vpm_variant_count",
            "vpm_variant_info", "vpm_axial_loss", "vpm_convert", "vpm_validate_inputs", "vpm_set_plan", "vpm_get_plan", "VpmError", "F64", "F32C", "TRANSPOSED", "CLASSICAL", "SIGMA_SOURCE",
            "SIGMA_SYMMETRIC"]
@@ -580,6 +580,47 @@ def vpm_segments_backward(a, b, gamma_seg, x_tgt, core_radius, vatistas_n=2, u_b
                                    _p(gamma_bar), _ld(x_bar), _stream(stream))
     _check("vpm_segments_backward", st)
     return x_bar, gamma_bar
+
+
+def vpm_fmm_workspace_size(n, level, order, dtype=None):
+    """Workspace bytes of :func:`vpm_fmm_eval` (dtype: torch.float64 or torch.float32)."""
+    torch = _torch()
+    lib = _lib.load()
+    code = F64 if (dtype or torch.float64) == torch.float64 else F32C
+    return int(lib.vpm_fmm_workspace_size(code, int(n), int(level), int(order)))
+
+
+def vpm_fmm_eval(x, gamma, sigma, level, order, *, scheme=TRANSPOSED, u_out=None, dgamma_out=None, workspace=None,
+                 stream=None):
+    """Self-interaction (u, dgamma) of the particles by the Cartesian FMM (Sec. II.B): uniform
+    octree of depth ``level``, expansions of order ``order``, exact Gaussian kernel over each
+    leaf's 27 neighbours.  Returns (u, dgamma)."""
+    torch = _torch()
+    lib = _lib.load()
+    dt = _code(x)
+    tdt = x.dtype
+    _vec(x, "x", dtype=tdt)
+    n = x.shape[1]
+    _vec(gamma, "gamma", n, tdt)
+    _scal(sigma, "sigma", n, tdt)
+    if n > 0 and gamma.stride(0) != x.stride(0):
+        raise ValueError("x and gamma must share one leading dimension")
+    if u_out is None:
+        u_out = torch.empty((3, n), dtype=tdt, device=x.device)
+    if dgamma_out is None:
+        dgamma_out = torch.empty((3, max(_ld(u_out), 1)), dtype=tdt, device=x.device)[:, :n]
+    _vec(u_out, "u_out", n, tdt)
+    _vec(dgamma_out, "dgamma_out", n, tdt)
+    if n > 0 and _ld(u_out) != _ld(dgamma_out):
+        raise ValueError("u_out and dgamma_out must share one leading dimension")
+    need = int(lib.vpm_fmm_workspace_size(dt, n, int(level), int(order)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    st = lib.vpm_fmm_eval(dt, n, _p(x), _p(gamma), _p(sigma), _ld(x), int(level), int(order), int(scheme), _p(u_out),
+                          _p(dgamma_out), _ld(u_out), _p(workspace), ws_bytes, _stream(stream))
+    _check("vpm_fmm_eval", st)
+    return u_out, dgamma_out
 
 
 def vpm_backward(x_src, gamma_src, sigma_src, u_bar, dgamma_bar=None, x_tgt=None, gamma_tgt=None,

@@ -1,0 +1,960 @@
+// Cartesian fast multipole evaluation of the particle right-hand side (Fu & Laurendeau,
+// Sec. II.B: a Cartesian FMM accelerates the velocity and its gradient for the particles).
+//
+// Far field.  Beyond about seven core radii the Gaussian blob acts as a point vortex (the
+// weights differ by less than 2e-9), so well-separated cells interact through the vector
+// potential of the singular kernel,
+//   psi(y) = sum_j Gamma_j G(y - x_j),  G(r) = 1/(4 pi |r|),
+//   u = curl psi,   J_ae = du_a/dy_e = eps_abc d_e d_b psi_c,
+// stretching J^T Gamma_i (transposed) or J Gamma_i (classical).  Each cell carries Taylor
+// moments of total order p about its centre c,
+//   M_k = sum_j Gamma_j (x_j - c)^k / k!,
+// shifted to the parent by M_k(c') = sum_{m<=k} M_m(c) (c - c')^(k-m)/(k-m)!, converted to
+// local coefficients of a well-separated target cell t,
+//   L_n = sum_{|k| <= p - |n|} (-1)^|k| d^(n+k) G (c_t - c_s) M_k,
+// shifted down by L_n(c') = sum_{m >= n} L_m(c) (c' - c)^(m-n)/(m-n)!, and evaluated at a
+// particle as d_b psi = sum_n L_(n+e_b) a^n/n!, d_e d_b psi = sum_n L_(n+e_b+e_e) a^n/n!.
+//
+// Tree.  A uniform octree of depth `level` over the particles' bounding cube (centre of the
+// box, half of its largest extent): every particle goes to the leaf floor((x - corner)/w),
+// clamped to the grid.  Leaves interact directly with their 27 neighbours through the exact
+// Gaussian kernel (the pair arithmetic of the direct kernel, self pair excluded); from level
+// 2 down every cell receives the moments of the children of its parent's neighbours that
+// are not its own neighbours.  Only occupied cells exist: particles are sorted by the Morton
+// code of their leaf, and each level's cells are the distinct code prefixes, found by
+// segmented scans on the device; neighbours are found by binary search in the sorted codes.
+//
+// Derivatives of 1/r.  With phi = 1/|R|, r^2 d_i phi + R_i phi = 0; applying d^(n - e_i)
+// and Leibniz's rule gives, for any i with n_i >= 1,
+//   r^2 D_n = -[(2 n_i - 1) R_i D_(n-e_i) + sum_(j != i) 2 n_j R_j D_(n-e_j)
+//               + (n_i - 1)^2 D_(n-2e_i) + sum_(j != i) n_j (n_j - 1) D_(n-2e_j)],
+// computed degree by degree.  D of the offset Delta w equals w^(-1-|n|) D of Delta, so one
+// table for unit spacing (offsets in [-3, 3]^3) serves every level; M2L scales the source
+// moments by (-1/w)^|k| and the result by w^(-1-|n|)/(4 pi).
+//
+// Precision: expansions and the far field in FP64; the near field in the caller's type
+// (FP32 with per-tile two-sum folding, or FP64), summed in FP64 at the end.
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "vpm_internal.h"
+
+namespace vpm {
+
+namespace {
+
+constexpr int kMaxOrder = 16;
+constexpr int kMaxTerms = (kMaxOrder + 1) * (kMaxOrder + 2) * (kMaxOrder + 3) / 6;  // 969
+constexpr int kMaxLevel = 10;
+constexpr int kNearTile = 256;
+constexpr int kOffsets = 343;  // [-3, 3]^3
+constexpr double kInv4Pi = 0.0795774715459476678844418816862571810;
+
+__host__ __device__ constexpr int nterms(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// Position of the multi-index (a, b, c): by total degree d, then decreasing a, then
+// decreasing b.  Terms of degree < d: d(d+1)(d+2)/6; with e = d - a, the terms of degree d
+// before a: e(e+1)/2; within a: e - b.
+__device__ __forceinline__ int mpos(int a, int b, int c) {
+    const int d = a + b + c;
+    const int e = d - a;
+    return d * (d + 1) * (d + 2) / 6 + e * (e + 1) / 2 + (e - b);
+}
+
+__device__ __forceinline__ uint32_t spread_bits(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__device__ __forceinline__ uint32_t gather_bits(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x3ffu;
+    return v;
+}
+// x in the highest of each bit triple, z in the lowest: the parent's code is code >> 3.
+__device__ __forceinline__ uint32_t cell_code(int ix, int iy, int iz) {
+    return (spread_bits(uint32_t(ix)) << 2) | (spread_bits(uint32_t(iy)) << 1) | spread_bits(uint32_t(iz));
+}
+__device__ __forceinline__ void cell_coords(uint32_t code, int* i) {
+    i[0] = int(gather_bits(code >> 2));
+    i[1] = int(gather_bits(code >> 1));
+    i[2] = int(gather_bits(code));
+}
+
+// box: corner[3], H, leaf width.  Centre of cell i at level l: corner + (i + 1/2) w_l, each
+// operation rounded on its own.
+__device__ __forceinline__ double cell_centre(const double* box, int d, int i, int l) {
+    const double w = ldexp(2.0 * box[3], -l);
+    return __dadd_rn(box[d], __dmul_rn(double(i) + 0.5, w));
+}
+
+// Index of `key` in the ascending codes[0, n), or -1.
+__device__ __forceinline__ int find_code(const uint32_t* codes, int n, uint32_t key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (codes[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < n && codes[lo] == key) ? lo : -1;
+}
+
+struct FmmLevel {
+    uint32_t* code;    // [cap]
+    int32_t* first;    // [cap + 1]: first particle (leaves) or first child (inner levels)
+    int32_t* pstart;   // [cap + 1]: first particle of the cell
+    int32_t* parent;   // [cap]: parent index (levels >= 1)
+    double* M;         // [cap][3][nt]
+    double* L;         // [cap][3][nt]
+    int64_t cap;
+};
+
+// ---------------------------------------------------------------- tree
+template <typename T>
+__global__ __launch_bounds__(1024) void k_fmm_box(const T* __restrict__ x, int64_t ld, int64_t n, int level,
+                                                  double* __restrict__ box) {
+    __shared__ double red[6][16];
+    double v[6];
+    for (int d = 0; d < 3; ++d) {
+        v[d] = INFINITY;
+        v[3 + d] = -INFINITY;
+    }
+    for (int64_t i = threadIdx.x; i < n; i += 1024)
+        for (int d = 0; d < 3; ++d) {
+            const double xv = double(x[d * ld + i]);
+            v[d] = fmin(v[d], xv);
+            v[3 + d] = fmax(v[3 + d], xv);
+        }
+    for (int off = 32; off > 0; off >>= 1)
+        for (int d = 0; d < 3; ++d) {
+            v[d] = fmin(v[d], __shfl_xor(v[d], off));
+            v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], off));
+        }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < 6; ++c) red[c][wv] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = red[d][0];
+            hi[d] = red[3 + d][0];
+            for (int w = 1; w < 16; ++w) {
+                lo[d] = fmin(lo[d], red[d][w]);
+                hi[d] = fmax(hi[d], red[3 + d][w]);
+            }
+        }
+        double H = 0.0, c[3];
+        for (int d = 0; d < 3; ++d) {
+            c[d] = 0.5 * (lo[d] + hi[d]);
+            H = fmax(H, 0.5 * (hi[d] - lo[d]));
+        }
+        if (!(H > 0.0)) H = 1.0;
+        for (int d = 0; d < 3; ++d) box[d] = c[d] - H;
+        box[3] = H;
+        box[4] = ldexp(2.0 * H, -level);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fmm_keys(const T* __restrict__ x, int64_t ld, int64_t n, int level,
+                                                  const double* __restrict__ box, uint64_t* __restrict__ keys,
+                                                  int64_t P) {
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= P) return;
+    if (p >= n) {
+        keys[p] = ~0ull;
+        return;
+    }
+    const double w = box[4];
+    const int side = 1 << level;
+    int ic[3];
+    for (int d = 0; d < 3; ++d) {
+        const double q = floor((double(x[d * ld + p]) - box[d]) / w);
+        ic[d] = q < 0.0 ? 0 : (q >= double(side) ? side - 1 : int(q));
+    }
+    keys[p] = (uint64_t(cell_code(ic[0], ic[1], ic[2])) << 32) | uint64_t(p);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fmm_gather(const T* __restrict__ x, const T* __restrict__ g,
+                                                    const T* __restrict__ sg, int64_t ld, int64_t n,
+                                                    const uint64_t* __restrict__ keys, T* __restrict__ xs,
+                                                    T* __restrict__ gs, T* __restrict__ ss, int32_t* __restrict__ perm,
+                                                    uint32_t* __restrict__ lcode) {
+    const int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (q >= n) return;
+    const uint64_t k = keys[q];
+    const int64_t i = int64_t(k & 0xffffffffull);
+    for (int d = 0; d < 3; ++d) {
+        xs[d * n + q] = x[d * ld + i];
+        gs[d * n + q] = g[d * ld + i];
+    }
+    ss[q] = sg[i];
+    perm[q] = int32_t(i);
+    lcode[q] = uint32_t(k >> 32);
+}
+
+// Distinct values of in[i] >> shift over a sorted input (one workgroup): code_out, the first
+// input index of each (first_out, with first_out[count] = n_in), each input's segment
+// (seg_of, optional), the count, and the first particle of each (pstart_out, optional:
+// pstart_child of the first member, pstart_out[count] = n_particles).
+__global__ __launch_bounds__(1024) void k_fmm_unique(const uint32_t* __restrict__ in, const int32_t* __restrict__ n_dev,
+                                                     int64_t n_host, int shift, uint32_t* __restrict__ code_out,
+                                                     int32_t* __restrict__ first_out, int32_t* __restrict__ seg_of,
+                                                     int32_t* __restrict__ count_out,
+                                                     const int32_t* __restrict__ pstart_child,
+                                                     int32_t* __restrict__ pstart_out, int32_t n_particles) {
+    __shared__ int32_t part[1024];
+    const int64_t n_in = n_dev ? int64_t(*n_dev) : n_host;
+    const int tid = threadIdx.x;
+    const int64_t chunk = (n_in + 1023) / 1024;
+    const int64_t b = int64_t(tid) * chunk;
+    const int64_t e = b + chunk < n_in ? b + chunk : n_in;
+    int32_t cnt = 0;
+    for (int64_t i = b; i < e; ++i)
+        if (i == 0 || (in[i] >> shift) != (in[i - 1] >> shift)) ++cnt;
+    part[tid] = cnt;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t seg = part[tid] - cnt - 1;
+    for (int64_t i = b; i < e; ++i) {
+        if (i == 0 || (in[i] >> shift) != (in[i - 1] >> shift)) {
+            ++seg;
+            code_out[seg] = in[i] >> shift;
+            first_out[seg] = int32_t(i);
+            if (pstart_out) pstart_out[seg] = pstart_child ? pstart_child[i] : int32_t(i);
+        }
+        if (seg_of) seg_of[i] = seg;
+    }
+    if (tid == 1023) {
+        const int32_t total = part[1023];
+        *count_out = total;
+        first_out[total] = int32_t(n_in);
+        if (pstart_out) pstart_out[total] = n_particles;
+    }
+}
+
+// Multi-index table: terms[t] = a | b << 8 | c << 16 for |n| <= p.
+__global__ __launch_bounds__(64) void k_fmm_terms(int p, uint32_t* __restrict__ terms) {
+    const int d = threadIdx.x;
+    if (d > p) return;
+    for (int a = d; a >= 0; --a)
+        for (int b = d - a; b >= 0; --b) {
+            const int c = d - a - b;
+            terms[mpos(a, b, c)] = uint32_t(a) | (uint32_t(b) << 8) | (uint32_t(c) << 16);
+        }
+}
+
+// D_n(Delta) of 1/|R| for unit spacing, |n| <= p, for the offsets in [-3, 3]^3 that are not
+// neighbours (one workgroup per offset, one degree at a time).
+__global__ __launch_bounds__(256) void k_fmm_dtab(int p, const uint32_t* __restrict__ terms, double* __restrict__ dtab) {
+    const int o = blockIdx.x;
+    const int R[3] = {o / 49 - 3, (o / 7) % 7 - 3, o % 7 - 3};
+    if (abs(R[0]) <= 1 && abs(R[1]) <= 1 && abs(R[2]) <= 1) return;
+    const int nt = nterms(p);
+    double* D = dtab + int64_t(o) * nt;
+    const double r2 = double(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    const double ir2 = 1.0 / r2;
+    if (threadIdx.x == 0) D[0] = 1.0 / sqrt(r2);
+    for (int d = 1; d <= p; ++d) {
+        __syncthreads();
+        const int t0 = d * (d + 1) * (d + 2) / 6;
+        const int nd = (d + 1) * (d + 2) / 2;
+        for (int t = t0 + int(threadIdx.x); t < t0 + nd; t += 256) {
+            const uint32_t m = terms[t];
+            const int n[3] = {int(m & 0xff), int((m >> 8) & 0xff), int(m >> 16)};
+            const int i = n[0] > 0 ? 0 : (n[1] > 0 ? 1 : 2);
+            double s = 0.0;
+            for (int j = 0; j < 3; ++j) {
+                if (n[j] == 0) continue;
+                int q1[3] = {n[0], n[1], n[2]};
+                q1[j] -= 1;
+                const double c1 = (j == i) ? double(2 * n[i] - 1) : double(2 * n[j]);
+                s += c1 * double(R[j]) * D[mpos(q1[0], q1[1], q1[2])];
+                if (n[j] >= 2) {
+                    int q2[3] = {n[0], n[1], n[2]};
+                    q2[j] -= 2;
+                    const double c2 = (j == i) ? double((n[i] - 1) * (n[i] - 1)) : double(n[j] * (n[j] - 1));
+                    s += c2 * D[mpos(q2[0], q2[1], q2[2])];
+                }
+            }
+            D[t] = -s * ir2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- upward pass
+template <typename T>
+__global__ __launch_bounds__(256) void k_fmm_p2m(const T* __restrict__ xs, const T* __restrict__ gs, int64_t n,
+                                                 FmmLevel lv, const int32_t* __restrict__ count,
+                                                 const double* __restrict__ box, int level, int p,
+                                                 const uint32_t* __restrict__ terms) {
+    const int cell = blockIdx.x;
+    if (cell >= *count) return;
+    const int nt = nterms(p);
+    __shared__ double pw[64][3][kMaxOrder + 1];
+    __shared__ double gg[64][3];
+    int ic[3];
+    cell_coords(lv.code[cell], ic);
+    double c[3];
+    for (int d = 0; d < 3; ++d) c[d] = cell_centre(box, d, ic[d], level);
+    double acc[4][3];
+    for (int j = 0; j < 4; ++j)
+        for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
+    const int b0 = lv.pstart[cell], b1 = lv.pstart[cell + 1];
+    for (int base = b0; base < b1; base += 64) {
+        const int m = b1 - base < 64 ? b1 - base : 64;
+        __syncthreads();
+        if (int(threadIdx.x) < 3 * m) {
+            const int q = threadIdx.x / 3, d = threadIdx.x % 3;
+            const double a = double(xs[d * n + base + q]) - c[d];
+            double v = 1.0;
+            pw[q][d][0] = 1.0;
+            for (int i = 1; i <= p; ++i) {
+                v = v * a / double(i);
+                pw[q][d][i] = v;
+            }
+            gg[q][d] = double(gs[d * n + base + q]);
+        }
+        __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+            const int t = threadIdx.x + 256 * j;
+            if (t >= nt) break;
+            const uint32_t k = terms[t];
+            const int k0 = int(k & 0xff), k1 = int((k >> 8) & 0xff), k2 = int(k >> 16);
+            for (int q = 0; q < m; ++q) {
+                const double mono = pw[q][0][k0] * pw[q][1][k1] * pw[q][2][k2];
+                for (int d = 0; d < 3; ++d) acc[j][d] += gg[q][d] * mono;
+            }
+        }
+    }
+    for (int j = 0; j < 4; ++j) {
+        const int t = threadIdx.x + 256 * j;
+        if (t >= nt) break;
+        for (int d = 0; d < 3; ++d) lv.M[(int64_t(cell) * 3 + d) * nt + t] = acc[j][d];
+    }
+}
+
+// Parents at level l from their children at level l + 1.
+__global__ __launch_bounds__(256) void k_fmm_m2m(FmmLevel par, FmmLevel chi, const int32_t* __restrict__ count, int l,
+                                                 const double* __restrict__ box, int p,
+                                                 const uint32_t* __restrict__ terms) {
+    const int cell = blockIdx.x;
+    if (cell >= *count) return;
+    const int nt = nterms(p);
+    __shared__ double pw[8][3][kMaxOrder + 1];
+    const int c0 = par.first[cell], c1 = par.first[cell + 1];
+    const int nch = c1 - c0;
+    if (int(threadIdx.x) < 3 * nch) {
+        const int q = threadIdx.x / 3, d = threadIdx.x % 3;
+        int ip[3], ic[3];
+        cell_coords(par.code[cell], ip);
+        cell_coords(chi.code[c0 + q], ic);
+        const double dl = cell_centre(box, d, ic[d], l + 1) - cell_centre(box, d, ip[d], l);
+        double v = 1.0;
+        pw[q][d][0] = 1.0;
+        for (int i = 1; i <= p; ++i) {
+            v = v * dl / double(i);
+            pw[q][d][i] = v;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nt; t += 256) {
+        const uint32_t k = terms[t];
+        const int k0 = int(k & 0xff), k1 = int((k >> 8) & 0xff), k2 = int(k >> 16);
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < nch; ++q) {
+            const double* Mc = chi.M + int64_t(c0 + q) * 3 * nt;
+            for (int m0 = 0; m0 <= k0; ++m0)
+                for (int m1 = 0; m1 <= k1; ++m1)
+                    for (int m2 = 0; m2 <= k2; ++m2) {
+                        const double f = pw[q][0][k0 - m0] * pw[q][1][k1 - m1] * pw[q][2][k2 - m2];
+                        const int s = mpos(m0, m1, m2);
+                        for (int d = 0; d < 3; ++d) acc[d] += Mc[d * nt + s] * f;
+                    }
+        }
+        for (int d = 0; d < 3; ++d) par.M[(int64_t(cell) * 3 + d) * nt + t] = acc[d];
+    }
+}
+
+// ---------------------------------------------------------------- M2L and L2L
+// One workgroup per target cell of level l: L = M2L over the interaction list (written, not
+// added: the parent's shifted expansion is added afterwards by k_fmm_l2l).
+__global__ __launch_bounds__(256) void k_fmm_m2l(FmmLevel lv, const int32_t* __restrict__ count, int l,
+                                                 const double* __restrict__ box, int p,
+                                                 const uint32_t* __restrict__ terms, const double* __restrict__ dtab) {
+    const int cell = blockIdx.x;
+    const int ncell = *count;
+    if (cell >= ncell) return;
+    const int nt = nterms(p);
+    __shared__ int32_t cand[216];
+    __shared__ int32_t list_src[216];
+    __shared__ int32_t list_off[216];
+    __shared__ int32_t nlist;
+    __shared__ double sD[kMaxTerms];
+    __shared__ double sM[3][kMaxTerms];
+    __shared__ double sc[kMaxOrder + 1];
+    int ic[3];
+    cell_coords(lv.code[cell], ic);
+    const int side = 1 << l;
+    const double w = ldexp(2.0 * box[3], -l);
+    if (threadIdx.x < 216) {
+        const int pn = threadIdx.x / 8, ch = threadIdx.x % 8;
+        const int pc[3] = {(ic[0] >> 1) + pn / 9 - 1, (ic[1] >> 1) + (pn / 3) % 3 - 1, (ic[2] >> 1) + pn % 3 - 1};
+        const int s[3] = {2 * pc[0] + (ch >> 2), 2 * pc[1] + ((ch >> 1) & 1), 2 * pc[2] + (ch & 1)};
+        int idx = -1;
+        const bool inside = pc[0] >= 0 && pc[1] >= 0 && pc[2] >= 0 && 2 * pc[0] < side && 2 * pc[1] < side &&
+                            2 * pc[2] < side;
+        const bool adjacent = abs(s[0] - ic[0]) <= 1 && abs(s[1] - ic[1]) <= 1 && abs(s[2] - ic[2]) <= 1;
+        if (inside && !adjacent) idx = find_code(lv.code, ncell, cell_code(s[0], s[1], s[2]));
+        cand[threadIdx.x] = idx;
+        if (idx >= 0)
+            list_off[threadIdx.x] = (ic[0] - s[0] + 3) * 49 + (ic[1] - s[1] + 3) * 7 + (ic[2] - s[2] + 3);
+    }
+    if (threadIdx.x <= p) {
+        // (-1/w)^k
+        double v = 1.0;
+        for (int k = 0; k < int(threadIdx.x); ++k) v *= -1.0 / w;
+        sc[threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int t = 0; t < 216; ++t)
+            if (cand[t] >= 0) {
+                list_src[m] = cand[t];
+                list_off[m] = list_off[t];
+                ++m;
+            }
+        nlist = m;
+    }
+    __syncthreads();
+    int nn[4][4];  // n0, n1, n2, |n| of this lane's terms
+    double acc[4][3];
+    for (int j = 0; j < 4; ++j) {
+        const int t = threadIdx.x + 256 * j;
+        const uint32_t k = t < nt ? terms[t] : 0u;
+        nn[j][0] = int(k & 0xff);
+        nn[j][1] = int((k >> 8) & 0xff);
+        nn[j][2] = int(k >> 16);
+        nn[j][3] = nn[j][0] + nn[j][1] + nn[j][2];
+        for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
+    }
+    for (int e = 0; e < nlist; ++e) {
+        __syncthreads();
+        const double* D = dtab + int64_t(list_off[e]) * nt;
+        const double* M = lv.M + int64_t(list_src[e]) * 3 * nt;
+        for (int t = threadIdx.x; t < nt; t += 256) {
+            const uint32_t k = terms[t];
+            const double f = sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
+            sD[t] = D[t];
+            for (int d = 0; d < 3; ++d) sM[d][t] = M[d * nt + t] * f;
+        }
+        __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+            if (int(threadIdx.x) + 256 * j >= nt) break;
+            const int P = p - nn[j][3];
+            for (int k0 = 0; k0 <= P; ++k0)
+                for (int k1 = 0; k1 <= P - k0; ++k1)
+                    for (int k2 = 0; k2 <= P - k0 - k1; ++k2) {
+                        const double Dv = sD[mpos(nn[j][0] + k0, nn[j][1] + k1, nn[j][2] + k2)];
+                        const int s = mpos(k0, k1, k2);
+                        for (int d = 0; d < 3; ++d) acc[j][d] += Dv * sM[d][s];
+                    }
+        }
+    }
+    for (int j = 0; j < 4; ++j) {
+        const int t = threadIdx.x + 256 * j;
+        if (t >= nt) break;
+        // w^(-1-|n|) / (4 pi)
+        double f = kInv4Pi / w;
+        for (int k = 0; k < nn[j][3]; ++k) f /= w;
+        for (int d = 0; d < 3; ++d) lv.L[(int64_t(cell) * 3 + d) * nt + t] = acc[j][d] * f;
+    }
+}
+
+// Children at level l += shifted expansion of their parents at level l - 1.
+__global__ __launch_bounds__(256) void k_fmm_l2l(FmmLevel chi, FmmLevel par, const int32_t* __restrict__ count, int l,
+                                                 const double* __restrict__ box, int p,
+                                                 const uint32_t* __restrict__ terms) {
+    const int cell = blockIdx.x;
+    if (cell >= *count) return;
+    const int nt = nterms(p);
+    __shared__ double pw[3][kMaxOrder + 1];
+    const int pa = chi.parent[cell];
+    if (threadIdx.x < 3) {
+        const int d = threadIdx.x;
+        int ic[3], ip[3];
+        cell_coords(chi.code[cell], ic);
+        cell_coords(par.code[pa], ip);
+        const double dl = cell_centre(box, d, ic[d], l) - cell_centre(box, d, ip[d], l - 1);
+        double v = 1.0;
+        pw[d][0] = 1.0;
+        for (int i = 1; i <= p; ++i) {
+            v = v * dl / double(i);
+            pw[d][i] = v;
+        }
+    }
+    __syncthreads();
+    const double* Lp = par.L + int64_t(pa) * 3 * nt;
+    for (int t = threadIdx.x; t < nt; t += 256) {
+        const uint32_t k = terms[t];
+        const int n0 = int(k & 0xff), n1 = int((k >> 8) & 0xff), n2 = int(k >> 16);
+        const int P = p - (n0 + n1 + n2);
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 <= P; ++q0)
+            for (int q1 = 0; q1 <= P - q0; ++q1)
+                for (int q2 = 0; q2 <= P - q0 - q1; ++q2) {
+                    const double f = pw[0][q0] * pw[1][q1] * pw[2][q2];
+                    const int s = mpos(n0 + q0, n1 + q1, n2 + q2);
+                    for (int d = 0; d < 3; ++d) acc[d] += Lp[d * nt + s] * f;
+                }
+        for (int d = 0; d < 3; ++d) chi.L[(int64_t(cell) * 3 + d) * nt + t] += acc[d];
+    }
+}
+
+// ---------------------------------------------------------------- near field + evaluation
+// Work items: chunks of kNearTile consecutive targets of one leaf (one workgroup).
+__global__ __launch_bounds__(1024) void k_fmm_items(const int32_t* __restrict__ count, const int32_t* __restrict__ pstart,
+                                                    int32_t* __restrict__ item_leaf, int32_t* __restrict__ item_t0,
+                                                    int32_t* __restrict__ nitems) {
+    __shared__ int32_t part[1024];
+    const int64_t nl = *count;
+    const int tid = threadIdx.x;
+    const int64_t chunk = (nl + 1023) / 1024;
+    const int64_t b = int64_t(tid) * chunk;
+    const int64_t e = b + chunk < nl ? b + chunk : nl;
+    int32_t cnt = 0;
+    for (int64_t i = b; i < e; ++i) cnt += (pstart[i + 1] - pstart[i] + kNearTile - 1) / kNearTile;
+    part[tid] = cnt;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t pos = part[tid] - cnt;
+    for (int64_t i = b; i < e; ++i)
+        for (int32_t t0 = pstart[i]; t0 < pstart[i + 1]; t0 += kNearTile) {
+            item_leaf[pos] = int32_t(i);
+            item_t0[pos] = t0;
+            ++pos;
+        }
+    if (tid == 1023) *nitems = part[1023];
+}
+
+struct NearArgs {
+    const void* xs;
+    const void* gs;
+    const void* ss;
+    const int32_t* perm;
+    int64_t n;
+    FmmLevel leaf;
+    const int32_t* count;
+    const int32_t* item_leaf;
+    const int32_t* item_t0;
+    const int32_t* nitems;
+    const double* box;
+    const uint32_t* terms;
+    int level;
+    int p;
+    void* u;
+    void* dg;
+    int64_t ldo;
+};
+
+template <typename T, bool CLASSICAL>
+__global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
+    constexpr bool kComp = std::is_same<T, float>::value;
+    const int item = blockIdx.x;
+    if (item >= *a.nitems) return;
+    const T* __restrict__ xs = static_cast<const T*>(a.xs);
+    const T* __restrict__ gs = static_cast<const T*>(a.gs);
+    const T* __restrict__ ss = static_cast<const T*>(a.ss);
+    const int64_t n = a.n;
+    const int leaf = a.item_leaf[item];
+    const int t0 = a.item_t0[item];
+    const int tend = a.leaf.pstart[leaf + 1];
+    const int q = t0 + int(threadIdx.x);
+    const bool valid = q < tend;
+    const int qq = valid ? q : t0;
+    const int nleaf = *a.count;
+    const int nt = nterms(a.p);
+
+    __shared__ T sx[3][kNearTile], sg[3][kNearTile], sis[kNearTile], sis2[kNearTile], scut[kNearTile];
+    __shared__ int32_t nb_lo[27], nb_hi[27];
+    __shared__ double sL[3][kMaxTerms];
+    int ic[3];
+    cell_coords(a.leaf.code[leaf], ic);
+    const int side = 1 << a.level;
+    if (threadIdx.x < 27) {
+        const int t = threadIdx.x;
+        const int s[3] = {ic[0] + t / 9 - 1, ic[1] + (t / 3) % 3 - 1, ic[2] + t % 3 - 1};
+        int idx = -1;
+        if (s[0] >= 0 && s[1] >= 0 && s[2] >= 0 && s[0] < side && s[1] < side && s[2] < side)
+            idx = find_code(a.leaf.code, nleaf, cell_code(s[0], s[1], s[2]));
+        nb_lo[t] = idx >= 0 ? a.leaf.pstart[idx] : 0;
+        nb_hi[t] = idx >= 0 ? a.leaf.pstart[idx + 1] : 0;
+    }
+    const bool far = a.level >= 2;
+    if (far)
+        for (int t = threadIdx.x; t < nt; t += 256)
+            for (int d = 0; d < 3; ++d) sL[d][t] = a.leaf.L[(int64_t(leaf) * 3 + d) * nt + t];
+    __syncthreads();
+
+    const T xi = xs[qq], yi = xs[n + qq], zi = xs[2 * n + qq];
+    const T gxi = gs[qq], gyi = gs[n + qq], gzi = gs[2 * n + qq];
+    // U = sum G v, A = sum G Gamma_j, B = sum Hn tau r (transposed) or sum Hn (r . Gamma_i) v
+    // (classical); in-core pairs put their cross term into B directly (scaled by -1/3).
+    T acc[9], hi[9], lo[9];
+    for (int c = 0; c < 9; ++c) acc[c] = hi[c] = lo[c] = T(0);
+    for (int nb = 0; nb < 27; ++nb) {
+        const int lo_j = nb_lo[nb], hi_j = nb_hi[nb];
+        for (int j0 = lo_j; j0 < hi_j; j0 += kNearTile) {
+            const int cnt = hi_j - j0 < kNearTile ? hi_j - j0 : kNearTile;
+            __syncthreads();
+            if (int(threadIdx.x) < cnt) {
+                const int j = j0 + threadIdx.x;
+                for (int d = 0; d < 3; ++d) {
+                    sx[d][threadIdx.x] = xs[d * n + j];
+                    sg[d][threadIdx.x] = gs[d * n + j];
+                }
+                const T sj = ss[j];
+                const T is = T(1) / sj;
+                sis[threadIdx.x] = is;
+                sis2[threadIdx.x] = is * is;
+                scut[threadIdx.x] = Prec<T>::kFarRho2 * sj * sj;
+            }
+            __syncthreads();
+            for (int jj = 0; jj < cnt; ++jj) {
+                if (j0 + jj == qq) continue;  // self pair
+                const T rx = xi - sx[0][jj], ry = yi - sx[1][jj], rz = zi - sx[2][jj];
+                const T s2 = rx * rx + ry * ry + rz * rz;
+                const T gxj = sg[0][jj], gyj = sg[1][jj], gzj = sg[2][jj];
+                const T vx = gyj * rz - gzj * ry, vy = gzj * rx - gxj * rz, vz = gxj * ry - gyj * rx;
+                const T inv = rsqrt_fast(s2);
+                const T inv2 = inv * inv;
+                T G = inv * inv2, Hn = G * inv2;
+                const bool core = s2 < scut[jj];
+                if (core) core_weights<T>(s2, sis[jj], sis2[jj], G, Hn, G, Hn);
+                acc[0] += G * vx;
+                acc[1] += G * vy;
+                acc[2] += G * vz;
+                if constexpr (!CLASSICAL) {
+                    const T tau = gxi * vx + gyi * vy + gzi * vz;
+                    const T w = Hn * tau;
+                    acc[6] += w * rx;
+                    acc[7] += w * ry;
+                    acc[8] += w * rz;
+                    if (core) {
+                        const T f = G * T(-1.0 / 3.0);
+                        acc[6] += f * (gyi * gzj - gzi * gyj);
+                        acc[7] += f * (gzi * gxj - gxi * gzj);
+                        acc[8] += f * (gxi * gyj - gyi * gxj);
+                    } else {
+                        acc[3] += G * gxj;
+                        acc[4] += G * gyj;
+                        acc[5] += G * gzj;
+                    }
+                } else {
+                    const T rg = rx * gxi + ry * gyi + rz * gzi;
+                    const T w = Hn * rg;
+                    acc[6] += w * vx;
+                    acc[7] += w * vy;
+                    acc[8] += w * vz;
+                    if (core) {
+                        // G Gamma_j x Gamma_i into B, scaled by -1/3
+                        const T f = G * T(-1.0 / 3.0);
+                        acc[6] += f * (gyj * gzi - gzj * gyi);
+                        acc[7] += f * (gzj * gxi - gxj * gzi);
+                        acc[8] += f * (gxj * gyi - gyj * gxi);
+                    } else {
+                        acc[3] += G * gxj;
+                        acc[4] += G * gyj;
+                        acc[5] += G * gzj;
+                    }
+                }
+            }
+            if constexpr (kComp) {
+                for (int c = 0; c < 9; ++c) {
+                    T s, e;
+                    two_sum(hi[c], acc[c], s, e);
+                    hi[c] = s;
+                    lo[c] += e;
+                    acc[c] = T(0);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!valid) return;
+    double S[9];
+    for (int c = 0; c < 9; ++c) S[c] = kComp ? double(hi[c]) + double(lo[c]) : double(acc[c]);
+    const double Gi[3] = {double(gxi), double(gyi), double(gzi)};
+    double u[3], dgv[3];
+    // near part: u = U/4pi; transposed (Gamma_i x A - 3B)/4pi; classical (A x Gamma_i - 3B)/4pi
+    const double Ax = S[3], Ay = S[4], Az = S[5];
+    double cx, cy, cz;
+    if constexpr (!CLASSICAL) {
+        cx = Gi[1] * Az - Gi[2] * Ay;
+        cy = Gi[2] * Ax - Gi[0] * Az;
+        cz = Gi[0] * Ay - Gi[1] * Ax;
+    } else {
+        cx = Ay * Gi[2] - Az * Gi[1];
+        cy = Az * Gi[0] - Ax * Gi[2];
+        cz = Ax * Gi[1] - Ay * Gi[0];
+    }
+    u[0] = S[0] * kInv4Pi;
+    u[1] = S[1] * kInv4Pi;
+    u[2] = S[2] * kInv4Pi;
+    dgv[0] = (cx - 3.0 * S[6]) * kInv4Pi;
+    dgv[1] = (cy - 3.0 * S[7]) * kInv4Pi;
+    dgv[2] = (cz - 3.0 * S[8]) * kInv4Pi;
+    if (far) {
+        double cc[3];
+        for (int d = 0; d < 3; ++d) cc[d] = cell_centre(a.box, d, ic[d], a.level);
+        const double av[3] = {double(xi) - cc[0], double(yi) - cc[1], double(zi) - cc[2]};
+        double gp[3][3], hp[6][3];  // d_b psi_c; d_e d_b psi_c for (e, b) in xx yy zz xy xz yz
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) gp[b][c] = 0.0;
+        for (int m = 0; m < 6; ++m)
+            for (int c = 0; c < 3; ++c) hp[m][c] = 0.0;
+        const int p = a.p;
+        double px = 1.0;
+        for (int n0 = 0; n0 <= p - 1; ++n0) {
+            double pxy = px;
+            for (int n1 = 0; n1 <= p - 1 - n0; ++n1) {
+                double mono = pxy;
+                for (int n2 = 0; n2 <= p - 1 - n0 - n1; ++n2) {
+                    const int i0 = mpos(n0 + 1, n1, n2), i1 = mpos(n0, n1 + 1, n2), i2 = mpos(n0, n1, n2 + 1);
+                    for (int c = 0; c < 3; ++c) {
+                        gp[0][c] += sL[c][i0] * mono;
+                        gp[1][c] += sL[c][i1] * mono;
+                        gp[2][c] += sL[c][i2] * mono;
+                    }
+                    if (n0 + n1 + n2 <= p - 2) {
+                        const int h[6] = {mpos(n0 + 2, n1, n2), mpos(n0, n1 + 2, n2), mpos(n0, n1, n2 + 2),
+                                          mpos(n0 + 1, n1 + 1, n2), mpos(n0 + 1, n1, n2 + 1),
+                                          mpos(n0, n1 + 1, n2 + 1)};
+                        for (int m = 0; m < 6; ++m)
+                            for (int c = 0; c < 3; ++c) hp[m][c] += sL[c][h[m]] * mono;
+                    }
+                    mono = mono * av[2] / double(n2 + 1);
+                }
+                pxy = pxy * av[1] / double(n1 + 1);
+            }
+            px = px * av[0] / double(n0 + 1);
+        }
+        // Hessian H[e][b][c] from the six symmetric slots
+        auto H = [&](int e, int b, int c) -> double {
+            if (e == b) return hp[e][c];
+            const int lo2 = e < b ? e : b, hi2 = e < b ? b : e;
+            const int m = (lo2 == 0 && hi2 == 1) ? 3 : ((lo2 == 0 && hi2 == 2) ? 4 : 5);
+            return hp[m][c];
+        };
+        // u_a = eps_abc d_b psi_c;  J_ae = eps_abc d_e d_b psi_c
+        u[0] += gp[1][2] - gp[2][1];
+        u[1] += gp[2][0] - gp[0][2];
+        u[2] += gp[0][1] - gp[1][0];
+        double J[3][3];
+        for (int e = 0; e < 3; ++e) {
+            J[0][e] = H(e, 1, 2) - H(e, 2, 1);
+            J[1][e] = H(e, 2, 0) - H(e, 0, 2);
+            J[2][e] = H(e, 0, 1) - H(e, 1, 0);
+        }
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int b = 0; b < 3; ++b) s += (CLASSICAL ? J[c][b] : J[b][c]) * Gi[b];
+            dgv[c] += s;
+        }
+    }
+    T* __restrict__ U = static_cast<T*>(a.u);
+    T* __restrict__ DG = static_cast<T*>(a.dg);
+    const int64_t o = a.perm[q];
+    for (int c = 0; c < 3; ++c) {
+        U[c * a.ldo + o] = T(u[c]);
+        DG[c * a.ldo + o] = T(dgv[c]);
+    }
+}
+
+// ---------------------------------------------------------------- workspace
+size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+
+struct Layout {
+    size_t keys, box, xs, gs, ss, perm, lcode, terms, dtab, item_leaf, item_t0, counts;
+    size_t code[kMaxLevel + 1], first[kMaxLevel + 1], pstart[kMaxLevel + 1], parent[kMaxLevel + 1];
+    size_t M[kMaxLevel + 1], L[kMaxLevel + 1];
+    int64_t cap[kMaxLevel + 1];
+    int64_t items_cap;
+    size_t total;
+};
+
+Layout layout(int64_t n, int level, int order, size_t es) {
+    Layout y{};
+    const int nt = nterms(order);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += al256(bytes);
+        return at;
+    };
+    y.keys = take(size_t(sort_len(n)) * 8);
+    y.box = take(8 * sizeof(double));
+    y.xs = take(3 * size_t(n) * es);
+    y.gs = take(3 * size_t(n) * es);
+    y.ss = take(size_t(n) * es);
+    y.perm = take(size_t(n) * 4);
+    y.lcode = take(size_t(n) * 4);
+    y.terms = take(size_t(kMaxTerms) * 4);
+    y.dtab = take(size_t(kOffsets) * nt * sizeof(double));
+    y.items_cap = n / kNearTile + n + 1;
+    y.item_leaf = take(size_t(y.items_cap) * 4);
+    y.item_t0 = take(size_t(y.items_cap) * 4);
+    y.counts = take(size_t(kMaxLevel + 2) * 4);
+    for (int l = 0; l <= level; ++l) {
+        const int64_t full = int64_t(1) << (3 * l);
+        const int64_t cap = full < n ? full : n;
+        y.cap[l] = cap < 1 ? 1 : cap;
+        y.code[l] = take(size_t(y.cap[l]) * 4);
+        y.first[l] = take(size_t(y.cap[l] + 1) * 4);
+        y.pstart[l] = take(size_t(y.cap[l] + 1) * 4);
+        y.parent[l] = take(size_t(y.cap[l]) * 4);
+        y.M[l] = take(size_t(y.cap[l]) * 3 * nt * sizeof(double));
+        y.L[l] = take(size_t(y.cap[l]) * 3 * nt * sizeof(double));
+    }
+    y.total = o;
+    return y;
+}
+
+template <typename T>
+hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, int level, int p, int classical,
+                   T* u, T* dg, int64_t ldo, unsigned char* ws, hipStream_t st) {
+    const Layout y = layout(n, level, p, sizeof(T));
+    uint64_t* keys = reinterpret_cast<uint64_t*>(ws + y.keys);
+    double* box = reinterpret_cast<double*>(ws + y.box);
+    T* xs = reinterpret_cast<T*>(ws + y.xs);
+    T* gs = reinterpret_cast<T*>(ws + y.gs);
+    T* ss = reinterpret_cast<T*>(ws + y.ss);
+    int32_t* perm = reinterpret_cast<int32_t*>(ws + y.perm);
+    uint32_t* lcode = reinterpret_cast<uint32_t*>(ws + y.lcode);
+    uint32_t* terms = reinterpret_cast<uint32_t*>(ws + y.terms);
+    double* dtab = reinterpret_cast<double*>(ws + y.dtab);
+    int32_t* item_leaf = reinterpret_cast<int32_t*>(ws + y.item_leaf);
+    int32_t* item_t0 = reinterpret_cast<int32_t*>(ws + y.item_t0);
+    int32_t* counts = reinterpret_cast<int32_t*>(ws + y.counts);  // [level + 1] cells, then items
+    FmmLevel lv[kMaxLevel + 1];
+    for (int l = 0; l <= level; ++l) {
+        lv[l].code = reinterpret_cast<uint32_t*>(ws + y.code[l]);
+        lv[l].first = reinterpret_cast<int32_t*>(ws + y.first[l]);
+        lv[l].pstart = reinterpret_cast<int32_t*>(ws + y.pstart[l]);
+        lv[l].parent = reinterpret_cast<int32_t*>(ws + y.parent[l]);
+        lv[l].M = reinterpret_cast<double*>(ws + y.M[l]);
+        lv[l].L = reinterpret_cast<double*>(ws + y.L[l]);
+        lv[l].cap = y.cap[l];
+    }
+    hipError_t e;
+    const int64_t P = sort_len(n);
+    hipLaunchKernelGGL(k_fmm_box<T>, dim3(1), dim3(1024), 0, st, x, ld, n, level, box);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fmm_keys<T>, dim3(unsigned(P / 256)), dim3(256), 0, st, x, ld, n, level, box, keys, P);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = sort_keys(keys, P, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fmm_gather<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, x, g, sg, ld, n, keys, xs,
+                       gs, ss, perm, lcode);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // leaves: distinct leaf codes of the sorted particles
+    hipLaunchKernelGGL(k_fmm_unique, dim3(1), dim3(1024), 0, st, lcode, nullptr, n, 0, lv[level].code,
+                       lv[level].pstart, nullptr, counts + level, nullptr, nullptr, int32_t(n));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // coarser levels: distinct parent codes of the level below
+    for (int l = level - 1; l >= 0; --l) {
+        hipLaunchKernelGGL(k_fmm_unique, dim3(1), dim3(1024), 0, st, lv[l + 1].code, counts + l + 1, int64_t(0), 3,
+                           lv[l].code, lv[l].first, lv[l + 1].parent, counts + l, lv[l + 1].pstart, lv[l].pstart,
+                           int32_t(n));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_fmm_terms, dim3(1), dim3(64), 0, st, p, terms);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (level >= 2) {
+        hipLaunchKernelGGL(k_fmm_dtab, dim3(kOffsets), dim3(256), 0, st, p, terms, dtab);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fmm_p2m<T>, dim3(unsigned(y.cap[level])), dim3(256), 0, st, xs, gs, n, lv[level],
+                           counts + level, box, level, p, terms);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int l = level - 1; l >= 2; --l) {
+            hipLaunchKernelGGL(k_fmm_m2m, dim3(unsigned(y.cap[l])), dim3(256), 0, st, lv[l], lv[l + 1], counts + l, l,
+                               box, p, terms);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        for (int l = 2; l <= level; ++l) {
+            hipLaunchKernelGGL(k_fmm_m2l, dim3(unsigned(y.cap[l])), dim3(256), 0, st, lv[l], counts + l, l, box, p,
+                               terms, dtab);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if (l >= 3) {
+                hipLaunchKernelGGL(k_fmm_l2l, dim3(unsigned(y.cap[l])), dim3(256), 0, st, lv[l], lv[l - 1],
+                                   counts + l, l, box, p, terms);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_fmm_items, dim3(1), dim3(1024), 0, st, counts + level, lv[level].pstart, item_leaf, item_t0,
+                       counts + level + 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    NearArgs na;
+    na.xs = xs;
+    na.gs = gs;
+    na.ss = ss;
+    na.perm = perm;
+    na.n = n;
+    na.leaf = lv[level];
+    na.count = counts + level;
+    na.item_leaf = item_leaf;
+    na.item_t0 = item_t0;
+    na.nitems = counts + level + 1;
+    na.box = box;
+    na.terms = terms;
+    na.level = level;
+    na.p = p;
+    na.u = u;
+    na.dg = dg;
+    na.ldo = ldo;
+    const unsigned grid = unsigned((n + kNearTile - 1) / kNearTile + y.cap[level]);
+    if (classical)
+        hipLaunchKernelGGL((k_fmm_near<T, true>), dim3(grid), dim3(256), 0, st, na);
+    else
+        hipLaunchKernelGGL((k_fmm_near<T, false>), dim3(grid), dim3(256), 0, st, na);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t fmm_workspace(int64_t n, int level, int order, int dtype) {
+    return layout(n, level, order, dtype == kDtypeF64 ? sizeof(double) : sizeof(float)).total;
+}
+
+hipError_t launch_fmm(int dtype, int64_t n, const void* x, const void* g, const void* sg, int64_t ld, int level,
+                      int order, int classical, void* u, void* dg, int64_t ldo, void* ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    if (dtype == kDtypeF64)
+        return run_fmm<double>(n, static_cast<const double*>(x), static_cast<const double*>(g),
+                               static_cast<const double*>(sg), ld, level, order, classical, static_cast<double*>(u),
+                               static_cast<double*>(dg), ldo, w, st);
+    return run_fmm<float>(n, static_cast<const float*>(x), static_cast<const float*>(g), static_cast<const float*>(sg),
+                          ld, level, order, classical, static_cast<float*>(u), static_cast<float*>(dg), ldo, w, st);
+}
+
+}  // namespace vpm

@@ -415,11 +415,7 @@ __global__ __launch_bounds__(256) void k_vreman(int64_t n, const T* __restrict__
 // Workspace of one set of n particles (sets reuse it one after the other):
 // [keys: P x 8 B][records: n x 12 T][subtile boxes: ceil(n/64) x 8 T][tile boxes: ceil(n/256) x 8 T][bbox: 8 T]
 namespace {
-int64_t sort_len(int64_t n) {
-    int64_t P = 1024;
-    while (P < n) P <<= 1;
-    return P;
-}
+
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 struct PseLayout {
     size_t keys, rec, sub, tile, bb, total;
@@ -454,17 +450,7 @@ hipError_t pse_set(int64_t begin, int64_t end, const T* x, const T* g, const T* 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_morton<T>, dim3(unsigned(P / 256)), dim3(256), 0, st, x, ld, begin, n, bb, keys, P);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bitonic_local, dim3(unsigned(P / 1024)), dim3(512), 0, st, keys, int64_t(2), int64_t(1024),
-                       int64_t(1));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    for (int64_t k = 2048; k <= P; k <<= 1) {
-        for (int64_t j = k >> 1; j >= 1024; j >>= 1) {
-            hipLaunchKernelGGL(k_bitonic_global, dim3(unsigned(P / 2 / 256)), dim3(256), 0, st, keys, P, j, k);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL(k_bitonic_local, dim3(unsigned(P / 1024)), dim3(512), 0, st, keys, k, k, int64_t(512));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    if ((e = sort_keys(keys, P, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pack<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, x, g, sg, vol, nut, ld, begin, n,
                        nu, keys, rec);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -484,6 +470,28 @@ hipError_t pse_set(int64_t begin, int64_t end, const T* x, const T* g, const T* 
     return hipGetLastError();
 }
 }  // namespace
+
+int64_t sort_len(int64_t n) {
+    int64_t P = 1024;
+    while (P < n) P <<= 1;
+    return P;
+}
+
+hipError_t sort_keys(uint64_t* keys, int64_t P, hipStream_t st) {
+    hipLaunchKernelGGL(k_bitonic_local, dim3(unsigned(P / 1024)), dim3(512), 0, st, keys, int64_t(2), int64_t(1024),
+                       int64_t(1));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int64_t k = 2048; k <= P; k <<= 1) {
+        for (int64_t j = k >> 1; j >= 1024; j >>= 1) {
+            hipLaunchKernelGGL(k_bitonic_global, dim3(unsigned(P / 2 / 256)), dim3(256), 0, st, keys, P, j, k);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_bitonic_local, dim3(unsigned(P / 1024)), dim3(512), 0, st, keys, k, k, int64_t(512));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 size_t pse_workspace(int64_t n, int dtype) {
     return pse_layout(n, dtype == kDtypeF64 ? sizeof(double) : sizeof(float)).total;

@@ -367,3 +367,27 @@ def test_segments_backward_validation():
     assert f(*args(xb=P(3))) == ALIAS            # gradient over the positions
     assert f(*args(gb=P(6))) == ALIAS            # gradient over a seed
     assert f(*args(gb=P(7))) == ALIAS            # the two gradients on one array
+
+
+def test_fmm_validation():
+    lib = _lib.load()
+    f = lib.vpm_fmm_eval
+    ws = lib.vpm_fmm_workspace_size
+    assert ws(F32C, 1000, 4, 8) > 0 and ws(F32C, 1000, 11, 8) == 0 and ws(F32C, 1000, 4, 17) == 0
+    assert ws(7, 1000, 4, 8) == 0 and ws(F64, 1000, 4, 8) > ws(F32C, 1000, 4, 8)
+
+    def args(**k):
+        return [k.get("dt", F32C), k.get("n", 100), P(0), P(1), P(2), k.get("ld", 100), k.get("lev", 3),
+                k.get("ord", 8), k.get("sch", 0), k.get("u", P(3)), k.get("d", P(4)), k.get("ldo", 100),
+                k.get("w", P(5)), k.get("wb", 1 << 40), None]
+    assert f(*args(dt=2)) == DTYPE
+    assert f(*args(ld=99)) == SIZE
+    assert f(*args(lev=11)) == ENUM
+    assert f(*args(ord=0)) == ENUM
+    assert f(*args(sch=3)) == ENUM
+    assert f(*args(u=None)) == NULL
+    assert f(*args(u=P(0))) == ALIAS
+    assert f(*args(d=P(3))) == ALIAS
+    assert f(*args(wb=16)) == WORKSPACE
+    assert f(*args(w=None)) == WORKSPACE
+    assert f(*args(n=0, ld=0, ldo=0, w=None, wb=0)) == OK
