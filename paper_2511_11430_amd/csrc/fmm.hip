@@ -172,12 +172,14 @@ __global__ __launch_bounds__(256) void k_fmm_keys(const T* __restrict__ x, int64
         keys[p] = ~0ull;
         return;
     }
-    const double w = box[4];
-    const int side = 1 << level;
+    // cells of the finest grid (1024 per axis): w_10 = w_level 2^-(10 - level) exactly, so
+    // the quotient is the level's quotient times a power of two and its floor, shifted, is the
+    // level's cell; sorting by the full code keeps the particles of a leaf in space order too
+    const double w = ldexp(box[4], level - kMaxLevel);
     int ic[3];
     for (int d = 0; d < 3; ++d) {
         const double q = floor((double(x[d * ld + p]) - box[d]) / w);
-        ic[d] = q < 0.0 ? 0 : (q >= double(side) ? side - 1 : int(q));
+        ic[d] = q < 0.0 ? 0 : (q >= 1024.0 ? 1023 : int(q));
     }
     keys[p] = (uint64_t(cell_code(ic[0], ic[1], ic[2])) << 32) | uint64_t(p);
 }
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(256) void k_fmm_gather(const T* __restrict__ x, con
                                                     const T* __restrict__ sg, int64_t ld, int64_t n,
                                                     const uint64_t* __restrict__ keys, T* __restrict__ xs,
                                                     T* __restrict__ gs, T* __restrict__ ss, int32_t* __restrict__ perm,
-                                                    uint32_t* __restrict__ lcode) {
+                                                    uint32_t* __restrict__ lcode, int level) {
     const int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (q >= n) return;
     const uint64_t k = keys[q];
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(256) void k_fmm_gather(const T* __restrict__ x, con
     }
     ss[q] = sg[i];
     perm[q] = int32_t(i);
-    lcode[q] = uint32_t(k >> 32);
+    lcode[q] = uint32_t(k >> 32) >> (3 * (kMaxLevel - level));
 }
 
 // Distinct values of in[i] >> shift over a sorted input (one workgroup): code_out, the first
@@ -568,14 +570,93 @@ struct NearArgs {
     const int32_t* item_t0;
     const int32_t* nitems;
     const double* box;
-    const uint32_t* terms;
     int level;
     int p;
+    const double* far;  // [6][n] far field (u, dgamma) in sorted order, or null
     void* u;
     void* dg;
     int64_t ldo;
 };
 
+// Far field at the targets of one work item from their leaf's local expansion (FP64):
+// far[0..2] = curl psi, far[3..5] = J^T Gamma_i (transposed) or J Gamma_i (classical).
+template <typename T, bool CLASSICAL>
+__global__ __launch_bounds__(256) void k_fmm_l2p(NearArgs a, double* __restrict__ far) {
+    const int item = blockIdx.x;
+    if (item >= *a.nitems) return;
+    const T* __restrict__ xs = static_cast<const T*>(a.xs);
+    const T* __restrict__ gs = static_cast<const T*>(a.gs);
+    const int64_t n = a.n;
+    const int leaf = a.item_leaf[item];
+    const int q = a.item_t0[item] + int(threadIdx.x);
+    const int nt = nterms(a.p);
+    __shared__ double sL[3][kMaxTerms];
+    for (int t = threadIdx.x; t < nt; t += 256)
+        for (int d = 0; d < 3; ++d) sL[d][t] = a.leaf.L[(int64_t(leaf) * 3 + d) * nt + t];
+    __syncthreads();
+    if (q >= a.leaf.pstart[leaf + 1]) return;
+    int ic[3];
+    cell_coords(a.leaf.code[leaf], ic);
+    double av[3];
+    for (int d = 0; d < 3; ++d) av[d] = double(xs[d * n + q]) - cell_centre(a.box, d, ic[d], a.level);
+    double gp[3][3], hp[6][3];  // d_b psi_c; d_e d_b psi_c for (e, b) in xx yy zz xy xz yz
+    for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c) gp[b][c] = 0.0;
+    for (int m = 0; m < 6; ++m)
+        for (int c = 0; c < 3; ++c) hp[m][c] = 0.0;
+    const int p = a.p;
+    double px = 1.0;
+    for (int n0 = 0; n0 <= p - 1; ++n0) {
+        double pxy = px;
+        for (int n1 = 0; n1 <= p - 1 - n0; ++n1) {
+            double mono = pxy;
+            for (int n2 = 0; n2 <= p - 1 - n0 - n1; ++n2) {
+                const int i0 = mpos(n0 + 1, n1, n2), i1 = mpos(n0, n1 + 1, n2), i2 = mpos(n0, n1, n2 + 1);
+                for (int c = 0; c < 3; ++c) {
+                    gp[0][c] += sL[c][i0] * mono;
+                    gp[1][c] += sL[c][i1] * mono;
+                    gp[2][c] += sL[c][i2] * mono;
+                }
+                if (n0 + n1 + n2 <= p - 2) {
+                    const int h[6] = {mpos(n0 + 2, n1, n2), mpos(n0, n1 + 2, n2), mpos(n0, n1, n2 + 2),
+                                      mpos(n0 + 1, n1 + 1, n2), mpos(n0 + 1, n1, n2 + 1), mpos(n0, n1 + 1, n2 + 1)};
+                    for (int m = 0; m < 6; ++m)
+                        for (int c = 0; c < 3; ++c) hp[m][c] += sL[c][h[m]] * mono;
+                }
+                mono = mono * av[2] / double(n2 + 1);
+            }
+            pxy = pxy * av[1] / double(n1 + 1);
+        }
+        px = px * av[0] / double(n0 + 1);
+    }
+    auto H = [&](int e, int b, int c) -> double {
+        if (e == b) return hp[e][c];
+        const int lo2 = e < b ? e : b, hi2 = e < b ? b : e;
+        const int m = (lo2 == 0 && hi2 == 1) ? 3 : ((lo2 == 0 && hi2 == 2) ? 4 : 5);
+        return hp[m][c];
+    };
+    // u_a = eps_abc d_b psi_c;  J_ae = eps_abc d_e d_b psi_c
+    far[q] = gp[1][2] - gp[2][1];
+    far[n + q] = gp[2][0] - gp[0][2];
+    far[2 * n + q] = gp[0][1] - gp[1][0];
+    double J[3][3];
+    for (int e = 0; e < 3; ++e) {
+        J[0][e] = H(e, 1, 2) - H(e, 2, 1);
+        J[1][e] = H(e, 2, 0) - H(e, 0, 2);
+        J[2][e] = H(e, 0, 1) - H(e, 1, 0);
+    }
+    const double Gi[3] = {double(gs[q]), double(gs[n + q]), double(gs[2 * n + q])};
+    for (int c = 0; c < 3; ++c) {
+        double sum = 0.0;
+        for (int b = 0; b < 3; ++b) sum += (CLASSICAL ? J[c][b] : J[b][c]) * Gi[b];
+        far[(3 + c) * n + q] = sum;
+    }
+}
+
+// Near field of one work item: the exact Gaussian pair sum over the 27 neighbouring leaves.
+// Sources stream through LDS in tiles of 256; each wavefront tests every 64-source subtile
+// against its own 64 targets and runs the loop without the core test where the boxes are
+// farther apart than the subtile's largest core cut (rho_far sigma).
 template <typename T, bool CLASSICAL>
 __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
     constexpr bool kComp = std::is_same<T, float>::value;
@@ -592,11 +673,11 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
     const bool valid = q < tend;
     const int qq = valid ? q : t0;
     const int nleaf = *a.count;
-    const int nt = nterms(a.p);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
     __shared__ T sx[3][kNearTile], sg[3][kNearTile], sis[kNearTile], sis2[kNearTile], scut[kNearTile];
+    __shared__ T sbox[4][7];
     __shared__ int32_t nb_lo[27], nb_hi[27];
-    __shared__ double sL[3][kMaxTerms];
     int ic[3];
     cell_coords(a.leaf.code[leaf], ic);
     const int side = 1 << a.level;
@@ -609,14 +690,16 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
         nb_lo[t] = idx >= 0 ? a.leaf.pstart[idx] : 0;
         nb_hi[t] = idx >= 0 ? a.leaf.pstart[idx + 1] : 0;
     }
-    const bool far = a.level >= 2;
-    if (far)
-        for (int t = threadIdx.x; t < nt; t += 256)
-            for (int d = 0; d < 3; ++d) sL[d][t] = a.leaf.L[(int64_t(leaf) * 3 + d) * nt + t];
     __syncthreads();
 
     const T xi = xs[qq], yi = xs[n + qq], zi = xs[2 * n + qq];
     const T gxi = gs[qq], gyi = gs[n + qq], gzi = gs[2 * n + qq];
+    // box of this wavefront's targets (lanes past the end repeat the item's first target)
+    T tlo[3], thi[3], tcut;
+    {
+        const T pl[3] = {xi, yi, zi};
+        wave_box(pl, pl, T(0), tlo, thi, tcut);
+    }
     // U = sum G v, A = sum G Gamma_j, B = sum Hn tau r (transposed) or sum Hn (r . Gamma_i) v
     // (classical); in-core pairs put their cross term into B directly (scaled by -1/3).
     T acc[9], hi[9], lo[9];
@@ -626,65 +709,117 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
         for (int j0 = lo_j; j0 < hi_j; j0 += kNearTile) {
             const int cnt = hi_j - j0 < kNearTile ? hi_j - j0 : kNearTile;
             __syncthreads();
-            if (int(threadIdx.x) < cnt) {
-                const int j = j0 + threadIdx.x;
+            {
+                const bool has = int(threadIdx.x) < cnt;
+                const int j = has ? j0 + threadIdx.x : j0;
+                T pl[3], cut = T(0);
                 for (int d = 0; d < 3; ++d) {
-                    sx[d][threadIdx.x] = xs[d * n + j];
+                    pl[d] = xs[d * n + j];
+                    sx[d][threadIdx.x] = pl[d];
                     sg[d][threadIdx.x] = gs[d * n + j];
                 }
                 const T sj = ss[j];
                 const T is = T(1) / sj;
                 sis[threadIdx.x] = is;
                 sis2[threadIdx.x] = is * is;
-                scut[threadIdx.x] = Prec<T>::kFarRho2 * sj * sj;
+                cut = Prec<T>::kFarRho2 * sj * sj;
+                scut[threadIdx.x] = cut;
+                // subtile box of this wavefront's 64 staged sources (past the end: the tile's
+                // first source again, which leaves the box unchanged)
+                T blo[3], bhi[3], bcut;
+                wave_box(pl, pl, cut, blo, bhi, bcut);
+                if (lane == 0) {
+                    for (int d = 0; d < 3; ++d) {
+                        sbox[wv][d] = blo[d];
+                        sbox[wv][3 + d] = bhi[d];
+                    }
+                    sbox[wv][6] = bcut;
+                }
             }
             __syncthreads();
-            for (int jj = 0; jj < cnt; ++jj) {
-                if (j0 + jj == qq) continue;  // self pair
-                const T rx = xi - sx[0][jj], ry = yi - sx[1][jj], rz = zi - sx[2][jj];
-                const T s2 = rx * rx + ry * ry + rz * rz;
-                const T gxj = sg[0][jj], gyj = sg[1][jj], gzj = sg[2][jj];
-                const T vx = gyj * rz - gzj * ry, vy = gzj * rx - gxj * rz, vz = gxj * ry - gyj * rx;
-                const T inv = rsqrt_fast(s2);
-                const T inv2 = inv * inv;
-                T G = inv * inv2, Hn = G * inv2;
-                const bool core = s2 < scut[jj];
-                if (core) core_weights<T>(s2, sis[jj], sis2[jj], G, Hn, G, Hn);
-                acc[0] += G * vx;
-                acc[1] += G * vy;
-                acc[2] += G * vz;
-                if constexpr (!CLASSICAL) {
-                    const T tau = gxi * vx + gyi * vy + gzi * vz;
-                    const T w = Hn * tau;
-                    acc[6] += w * rx;
-                    acc[7] += w * ry;
-                    acc[8] += w * rz;
-                    if (core) {
-                        const T f = G * T(-1.0 / 3.0);
-                        acc[6] += f * (gyi * gzj - gzi * gyj);
-                        acc[7] += f * (gzi * gxj - gxi * gzj);
-                        acc[8] += f * (gxi * gyj - gyi * gxj);
-                    } else {
+            for (int sub = 0; sub * 64 < cnt; ++sub) {
+                const int jb = sub * 64;
+                const int je = cnt - jb < 64 ? cnt : jb + 64;
+                T d2 = T(0);
+                for (int d = 0; d < 3; ++d) {
+                    const T g1 = sbox[sub][d] - thi[d], g2 = tlo[d] - sbox[sub][3 + d];
+                    const T gap = g1 > g2 ? g1 : g2;
+                    d2 += gap > T(0) ? gap * gap : T(0);
+                }
+                if (d2 >= sbox[sub][6]) {
+                    // every pair of this wavefront and subtile is outside the cores
+                    for (int jj = jb; jj < je; ++jj) {
+                        const T rx = xi - sx[0][jj], ry = yi - sx[1][jj], rz = zi - sx[2][jj];
+                        const T s2 = rx * rx + ry * ry + rz * rz;
+                        const T gxj = sg[0][jj], gyj = sg[1][jj], gzj = sg[2][jj];
+                        const T vx = gyj * rz - gzj * ry, vy = gzj * rx - gxj * rz, vz = gxj * ry - gyj * rx;
+                        const T inv = rsqrt_fast(s2);
+                        const T inv2 = inv * inv;
+                        const T G = inv * inv2, Hn = G * inv2;
+                        acc[0] += G * vx;
+                        acc[1] += G * vy;
+                        acc[2] += G * vz;
                         acc[3] += G * gxj;
                         acc[4] += G * gyj;
                         acc[5] += G * gzj;
+                        const T w = CLASSICAL ? Hn * (rx * gxi + ry * gyi + rz * gzi) : Hn * (gxi * vx + gyi * vy + gzi * vz);
+                        if constexpr (!CLASSICAL) {
+                            acc[6] += w * rx;
+                            acc[7] += w * ry;
+                            acc[8] += w * rz;
+                        } else {
+                            acc[6] += w * vx;
+                            acc[7] += w * vy;
+                            acc[8] += w * vz;
+                        }
                     }
-                } else {
-                    const T rg = rx * gxi + ry * gyi + rz * gzi;
-                    const T w = Hn * rg;
-                    acc[6] += w * vx;
-                    acc[7] += w * vy;
-                    acc[8] += w * vz;
-                    if (core) {
-                        // G Gamma_j x Gamma_i into B, scaled by -1/3
-                        const T f = G * T(-1.0 / 3.0);
-                        acc[6] += f * (gyj * gzi - gzj * gyi);
-                        acc[7] += f * (gzj * gxi - gxj * gzi);
-                        acc[8] += f * (gxj * gyi - gyj * gxi);
+                    continue;
+                }
+                for (int jj = jb; jj < je; ++jj) {
+                    if (j0 + jj == qq) continue;  // self pair
+                    const T rx = xi - sx[0][jj], ry = yi - sx[1][jj], rz = zi - sx[2][jj];
+                    const T s2 = rx * rx + ry * ry + rz * rz;
+                    const T gxj = sg[0][jj], gyj = sg[1][jj], gzj = sg[2][jj];
+                    const T vx = gyj * rz - gzj * ry, vy = gzj * rx - gxj * rz, vz = gxj * ry - gyj * rx;
+                    const T inv = rsqrt_fast(s2);
+                    const T inv2 = inv * inv;
+                    T G = inv * inv2, Hn = G * inv2;
+                    const bool core = s2 < scut[jj];
+                    if (core) core_weights<T>(s2, sis[jj], sis2[jj], G, Hn, G, Hn);
+                    acc[0] += G * vx;
+                    acc[1] += G * vy;
+                    acc[2] += G * vz;
+                    if constexpr (!CLASSICAL) {
+                        const T w = Hn * (gxi * vx + gyi * vy + gzi * vz);
+                        acc[6] += w * rx;
+                        acc[7] += w * ry;
+                        acc[8] += w * rz;
+                        if (core) {
+                            const T f = G * T(-1.0 / 3.0);
+                            acc[6] += f * (gyi * gzj - gzi * gyj);
+                            acc[7] += f * (gzi * gxj - gxi * gzj);
+                            acc[8] += f * (gxi * gyj - gyi * gxj);
+                        } else {
+                            acc[3] += G * gxj;
+                            acc[4] += G * gyj;
+                            acc[5] += G * gzj;
+                        }
                     } else {
-                        acc[3] += G * gxj;
-                        acc[4] += G * gyj;
-                        acc[5] += G * gzj;
+                        const T w = Hn * (rx * gxi + ry * gyi + rz * gzi);
+                        acc[6] += w * vx;
+                        acc[7] += w * vy;
+                        acc[8] += w * vz;
+                        if (core) {
+                            // G Gamma_j x Gamma_i into B, scaled by -1/3
+                            const T f = G * T(-1.0 / 3.0);
+                            acc[6] += f * (gyj * gzi - gzj * gyi);
+                            acc[7] += f * (gzj * gxi - gxj * gzi);
+                            acc[8] += f * (gxj * gyi - gyj * gxi);
+                        } else {
+                            acc[3] += G * gxj;
+                            acc[4] += G * gyj;
+                            acc[5] += G * gzj;
+                        }
                     }
                 }
             }
@@ -699,12 +834,10 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
             }
         }
     }
-    __syncthreads();
     if (!valid) return;
     double S[9];
     for (int c = 0; c < 9; ++c) S[c] = kComp ? double(hi[c]) + double(lo[c]) : double(acc[c]);
     const double Gi[3] = {double(gxi), double(gyi), double(gzi)};
-    double u[3], dgv[3];
     // near part: u = U/4pi; transposed (Gamma_i x A - 3B)/4pi; classical (A x Gamma_i - 3B)/4pi
     const double Ax = S[3], Ay = S[4], Az = S[5];
     double cx, cy, cz;
@@ -717,70 +850,13 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
         cy = Az * Gi[0] - Ax * Gi[2];
         cz = Ax * Gi[1] - Ay * Gi[0];
     }
-    u[0] = S[0] * kInv4Pi;
-    u[1] = S[1] * kInv4Pi;
-    u[2] = S[2] * kInv4Pi;
-    dgv[0] = (cx - 3.0 * S[6]) * kInv4Pi;
-    dgv[1] = (cy - 3.0 * S[7]) * kInv4Pi;
-    dgv[2] = (cz - 3.0 * S[8]) * kInv4Pi;
-    if (far) {
-        double cc[3];
-        for (int d = 0; d < 3; ++d) cc[d] = cell_centre(a.box, d, ic[d], a.level);
-        const double av[3] = {double(xi) - cc[0], double(yi) - cc[1], double(zi) - cc[2]};
-        double gp[3][3], hp[6][3];  // d_b psi_c; d_e d_b psi_c for (e, b) in xx yy zz xy xz yz
-        for (int b = 0; b < 3; ++b)
-            for (int c = 0; c < 3; ++c) gp[b][c] = 0.0;
-        for (int m = 0; m < 6; ++m)
-            for (int c = 0; c < 3; ++c) hp[m][c] = 0.0;
-        const int p = a.p;
-        double px = 1.0;
-        for (int n0 = 0; n0 <= p - 1; ++n0) {
-            double pxy = px;
-            for (int n1 = 0; n1 <= p - 1 - n0; ++n1) {
-                double mono = pxy;
-                for (int n2 = 0; n2 <= p - 1 - n0 - n1; ++n2) {
-                    const int i0 = mpos(n0 + 1, n1, n2), i1 = mpos(n0, n1 + 1, n2), i2 = mpos(n0, n1, n2 + 1);
-                    for (int c = 0; c < 3; ++c) {
-                        gp[0][c] += sL[c][i0] * mono;
-                        gp[1][c] += sL[c][i1] * mono;
-                        gp[2][c] += sL[c][i2] * mono;
-                    }
-                    if (n0 + n1 + n2 <= p - 2) {
-                        const int h[6] = {mpos(n0 + 2, n1, n2), mpos(n0, n1 + 2, n2), mpos(n0, n1, n2 + 2),
-                                          mpos(n0 + 1, n1 + 1, n2), mpos(n0 + 1, n1, n2 + 1),
-                                          mpos(n0, n1 + 1, n2 + 1)};
-                        for (int m = 0; m < 6; ++m)
-                            for (int c = 0; c < 3; ++c) hp[m][c] += sL[c][h[m]] * mono;
-                    }
-                    mono = mono * av[2] / double(n2 + 1);
-                }
-                pxy = pxy * av[1] / double(n1 + 1);
-            }
-            px = px * av[0] / double(n0 + 1);
-        }
-        // Hessian H[e][b][c] from the six symmetric slots
-        auto H = [&](int e, int b, int c) -> double {
-            if (e == b) return hp[e][c];
-            const int lo2 = e < b ? e : b, hi2 = e < b ? b : e;
-            const int m = (lo2 == 0 && hi2 == 1) ? 3 : ((lo2 == 0 && hi2 == 2) ? 4 : 5);
-            return hp[m][c];
-        };
-        // u_a = eps_abc d_b psi_c;  J_ae = eps_abc d_e d_b psi_c
-        u[0] += gp[1][2] - gp[2][1];
-        u[1] += gp[2][0] - gp[0][2];
-        u[2] += gp[0][1] - gp[1][0];
-        double J[3][3];
-        for (int e = 0; e < 3; ++e) {
-            J[0][e] = H(e, 1, 2) - H(e, 2, 1);
-            J[1][e] = H(e, 2, 0) - H(e, 0, 2);
-            J[2][e] = H(e, 0, 1) - H(e, 1, 0);
-        }
+    double u[3] = {S[0] * kInv4Pi, S[1] * kInv4Pi, S[2] * kInv4Pi};
+    double dgv[3] = {(cx - 3.0 * S[6]) * kInv4Pi, (cy - 3.0 * S[7]) * kInv4Pi, (cz - 3.0 * S[8]) * kInv4Pi};
+    if (a.far)
         for (int c = 0; c < 3; ++c) {
-            double s = 0.0;
-            for (int b = 0; b < 3; ++b) s += (CLASSICAL ? J[c][b] : J[b][c]) * Gi[b];
-            dgv[c] += s;
+            u[c] += a.far[c * n + q];
+            dgv[c] += a.far[(3 + c) * n + q];
         }
-    }
     T* __restrict__ U = static_cast<T*>(a.u);
     T* __restrict__ DG = static_cast<T*>(a.dg);
     const int64_t o = a.perm[q];
@@ -794,7 +870,7 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-    size_t keys, box, xs, gs, ss, perm, lcode, terms, dtab, item_leaf, item_t0, counts;
+    size_t keys, box, xs, gs, ss, perm, lcode, terms, dtab, item_leaf, item_t0, counts, far;
     size_t code[kMaxLevel + 1], first[kMaxLevel + 1], pstart[kMaxLevel + 1], parent[kMaxLevel + 1];
     size_t M[kMaxLevel + 1], L[kMaxLevel + 1];
     int64_t cap[kMaxLevel + 1];
@@ -824,6 +900,7 @@ Layout layout(int64_t n, int level, int order, size_t es) {
     y.item_leaf = take(size_t(y.items_cap) * 4);
     y.item_t0 = take(size_t(y.items_cap) * 4);
     y.counts = take(size_t(kMaxLevel + 2) * 4);
+    y.far = take(6 * size_t(n) * sizeof(double));
     for (int l = 0; l <= level; ++l) {
         const int64_t full = int64_t(1) << (3 * l);
         const int64_t cap = full < n ? full : n;
@@ -873,7 +950,7 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = sort_keys(keys, P, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_fmm_gather<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, x, g, sg, ld, n, keys, xs,
-                       gs, ss, perm, lcode);
+                       gs, ss, perm, lcode, level);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // leaves: distinct leaf codes of the sorted particles
     hipLaunchKernelGGL(k_fmm_unique, dim3(1), dim3(1024), 0, st, lcode, nullptr, n, 0, lv[level].code,
@@ -925,13 +1002,22 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     na.item_t0 = item_t0;
     na.nitems = counts + level + 1;
     na.box = box;
-    na.terms = terms;
     na.level = level;
     na.p = p;
+    na.far = nullptr;
     na.u = u;
     na.dg = dg;
     na.ldo = ldo;
     const unsigned grid = unsigned((n + kNearTile - 1) / kNearTile + y.cap[level]);
+    if (level >= 2) {
+        double* far = reinterpret_cast<double*>(ws + y.far);
+        if (classical)
+            hipLaunchKernelGGL((k_fmm_l2p<T, true>), dim3(grid), dim3(256), 0, st, na, far);
+        else
+            hipLaunchKernelGGL((k_fmm_l2p<T, false>), dim3(grid), dim3(256), 0, st, na, far);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        na.far = far;
+    }
     if (classical)
         hipLaunchKernelGGL((k_fmm_near<T, true>), dim3(grid), dim3(256), 0, st, na);
     else
