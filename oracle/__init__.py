@@ -44,7 +44,7 @@ def _load():
         lib.orc_rk3_program_jvp.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, i32, dbl, i32, i32, i64, _dp,
                                             _dp, _dp, i32] + lat
         lib.orc_segments_vjp.argtypes = [i64, _dp, _dp, _dp, dbl, i32, i64, _dp, _dp, _dp, _dp, i32, _dp, _dp, i32]
-        lib.orc_fmm.argtypes = [i64, _dp, _dp, _dp, i32, i32, i32, _dp, _dp, i32]
+        lib.orc_fmm.argtypes = [i64, _dp, _dp, _dp, i32, i32, i32, _dp, _dp, _dp, i32]
         lib.orc_inv_r_taylor.argtypes = [_dp, i32, _dp, ctypes.POINTER(ctypes.c_int)]
         lib.orc_diagnostics.argtypes = [i64, _dp, _dp, _dp, _dp, _dp]
         lib.orc_gradient.argtypes = [i64, _dp, _dp, _dp, i64, _dp, _dp, _lp, i32, _dp, i32]
@@ -220,18 +220,21 @@ def _lattice(segments):
             int(vn)], (A, B, G)
 
 
-def fmm(x, gam, sig, level, order, scheme=TRANSPOSED, nthreads=0):
+def fmm(x, gam, sig, level, order, scheme=TRANSPOSED, nthreads=0, want_grad=False):
     """Cartesian FMM (Sec. II.B) of the self-interaction: uniform octree of depth ``level``
     over the bounding cube, Taylor expansions of the vector potential of order ``order``,
-    exact Gaussian kernel over each leaf's 27 neighbours.  Returns (u, dgamma)."""
+    exact Gaussian kernel over each leaf's 27 neighbours.  Returns (u, dgamma), plus the
+    velocity gradient J (3, 3, n) with ``want_grad``."""
     lib = _load()
     X, G = _vec(x, "x"), _vec(gam, "gam")
     s = np.ascontiguousarray(sig, dtype=np.float64).reshape(-1)
     u, d = np.zeros_like(X), np.zeros_like(X)
+    J = np.zeros((9, X.shape[1])) if want_grad else None
     rc = lib.orc_fmm(X.shape[1], X.ctypes.data_as(_dp), G.ctypes.data_as(_dp), s.ctypes.data_as(_dp), int(level),
-                     int(order), int(scheme), u.ctypes.data_as(_dp), d.ctypes.data_as(_dp), int(nthreads))
+                     int(order), int(scheme), u.ctypes.data_as(_dp), d.ctypes.data_as(_dp),
+                     None if J is None else J.ctypes.data_as(_dp), int(nthreads))
     _check(rc, "fmm")
-    return u, d
+    return (u, d, J.reshape(3, 3, -1)) if want_grad else (u, d)
 
 
 def inv_r_taylor(R, Q):

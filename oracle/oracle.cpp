@@ -646,7 +646,7 @@ inline int64_t cell_key(int64_t ix, int64_t iy, int64_t iz) { return (ix << 40) 
 inline void key_coords(int64_t k, int64_t* i) { i[0] = k >> 40; i[1] = (k >> 20) & 0xFFFFF; i[2] = k & 0xFFFFF; }
 
 void fmm_eval(int64_t n, const double* x, const double* G, const double* sig, int level, int p, int scheme,
-              double* u, double* dg) {
+              double* u, double* dg, double* Jout) {
     const Terms T(p);
     const int nt = T.size();
     // root cube: bounding box centre, half of the largest extent
@@ -818,6 +818,8 @@ void fmm_eval(int64_t n, const double* x, const double* G, const double* sig, in
     std::vector<int64_t> leaf_keys;
     for (const auto& kv : leaves) leaf_keys.push_back(kv.first);
     for (int64_t i = 0; i < 3 * n; ++i) u[i] = dg[i] = 0.0;
+    if (Jout)
+        for (int64_t i = 0; i < 9 * n; ++i) Jout[i] = 0.0;
 #pragma omp parallel for schedule(dynamic)
     for (size_t li = 0; li < leaf_keys.size(); ++li) {
         const std::vector<int64_t>& tg = leaves.at(leaf_keys[li]);
@@ -836,7 +838,7 @@ void fmm_eval(int64_t n, const double* x, const double* G, const double* sig, in
         for (int64_t i : tg) {
             const double xi[3] = {x[i], x[n + i], x[2 * n + i]};
             const double Gi[3] = {G[i], G[n + i], G[2 * n + i]};
-            Neumaier au[3], ad[3];
+            Neumaier au[3], ad[3], aj[9];
             for (int64_t j : src) {
                 if (j == i) continue;
                 const double r[3] = {xi[0] - x[j], xi[1] - x[n + j], xi[2] - x[2 * n + j]};
@@ -847,6 +849,13 @@ void fmm_eval(int64_t n, const double* x, const double* G, const double* sig, in
                 const double v[3] = {Gj[1] * r[2] - Gj[2] * r[1], Gj[2] * r[0] - Gj[0] * r[2],
                                      Gj[0] * r[1] - Gj[1] * r[0]};
                 for (int a = 0; a < 3; ++a) au[a].add(g * v[a]);
+                if (Jout)  // J += g [Gamma_j]x + h (Gamma_j x r) r^T
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) {
+                            double gx = 0.0;
+                            for (int c = 0; c < 3; ++c) gx += levi(a, c, b) * Gj[c];
+                            aj[3 * a + b].add(g * gx + h * v[a] * r[b]);
+                        }
                 if (scheme == 0) {
                     const double cgg[3] = {Gi[1] * Gj[2] - Gi[2] * Gj[1], Gi[2] * Gj[0] - Gi[0] * Gj[2],
                                            Gi[0] * Gj[1] - Gi[1] * Gj[0]};
@@ -897,6 +906,8 @@ void fmm_eval(int64_t n, const double* x, const double* G, const double* sig, in
                 for (int b = 0; b < 3; ++b) sf += (scheme == 0 ? J[b][a] : J[a][b]) * Gi[b];
                 u[a * n + i] = au[a].get() + uf[a];
                 dg[a * n + i] = ad[a].get() + sf;
+                if (Jout)
+                    for (int b = 0; b < 3; ++b) Jout[(3 * a + b) * n + i] = aj[3 * a + b].get() + J[a][b];
             }
         }
     }
@@ -1135,14 +1146,15 @@ int orc_diagnostics(int64_t n, const double* x, const double* G, const double* u
 
 
 // Cartesian FMM evaluation of the self-interaction of n particles (velocity and stretching,
-// scheme 0 transposed / 1 classical) on a uniform octree of depth `level` (0..10) with
-// expansions of order `order` (1..16).
+// scheme 0 transposed / 1 classical; optionally the velocity gradient J [9][n], row 3a + b =
+// du_a/dx_b) on a uniform octree of depth `level` (0..10) with expansions of order `order`
+// (1..16).
 int orc_fmm(int64_t n, const double* x, const double* G, const double* sig, int level, int order, int scheme,
-            double* u, double* dg, int nthreads) {
+            double* u, double* dg, double* J, int nthreads) {
     if (n < 0 || (n > 0 && (!x || !G || !sig || !u || !dg))) return 1;
     if (level < 0 || level > 10 || order < 1 || order > 16 || scheme < 0 || scheme > 1) return 1;
     set_threads<double>(nthreads);
-    fmm_eval(n, x, G, sig, level, order, scheme, u, dg);
+    fmm_eval(n, x, G, sig, level, order, scheme, u, dg, J);
     return 0;
 }
 

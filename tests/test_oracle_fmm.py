@@ -98,3 +98,19 @@ def test_fmm_far_field_of_separated_clusters():
     u, d = oracle.fmm(x, g, s, 3, 16)
     uo, do = oracle.eval_pairs(x, g, s)
     assert _rel(u, uo) <= 1e-9 and _rel(d, do) <= 1e-9
+
+
+@pytest.mark.parametrize("level", [1, 4])
+def test_fmm_velocity_gradient(level):
+    """J from the FMM: the direct sums' gradient at depth 1 (no far field), and at depth 4
+    within the truncation error of the velocity; its trace vanishes (div u = 0) up to that
+    error, and J^T Gamma_i equals the transposed stretching the FMM returns."""
+    c = W.config3(n=3000)
+    x, g, s = c["x"], c["gamma"], c["sigma"]
+    u, d, J = oracle.fmm(x, g, s, level, 10, want_grad=True)
+    Jo = oracle.velocity_gradient(x, g, s)
+    e = _rel(J.reshape(9, -1), Jo.reshape(9, -1))
+    assert e <= (1e-14 if level == 1 else 1e-3)
+    assert np.allclose(np.einsum("abn,an->bn", J, g), d, rtol=0, atol=1e-10 * np.abs(d).max())
+    tr = J[0, 0] + J[1, 1] + J[2, 2]
+    assert np.abs(tr).max() <= (1e-12 if level == 1 else 1e-3) * np.abs(J).max()
