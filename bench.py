@@ -288,6 +288,23 @@ def main():
             "flop_per_pair_gradient": FLOP_PER_PAIR_GRAD,
             "vreman_ms": round(vre_ms, 4), "pse_ms": round(pse_ms, 3),
             "rhs_with_viscous_ms": round(grad_ms + vre_ms + pse_ms, 3)}
+        # the same right-hand side with the FMM's velocity, stretching and gradient (depth 6,
+        # order 12), against the direct gradient
+        fws = torch.empty(vpm.vpm_fmm_workspace_size(N, 6, 12, torch.float32), dtype=torch.uint8, device=dev)
+        uf, df = torch.empty_like(x), torch.empty_like(x)
+        Jf = torch.empty((9, N), dtype=torch.float32, device=dev)
+        fg_ms = timed_once(lambda: vpm.vpm_fmm_eval(x, g, s, 6, 12, u_out=uf, dgamma_out=df, grad_out=Jf,
+                                                    workspace=fws), reps=3)
+        nut_f = torch.empty_like(nut)
+        vpm.vpm_sgs_vreman(Jf, s, W.C_V, nu_t_out=nut_f)
+        Jh, Jfh = Jv.cpu().double().numpy(), Jf.cpu().double().numpy()
+        result["viscous"].update({
+            "fmm_gradient_ms": round(fg_ms, 3), "fmm_level": 6, "fmm_order": 12,
+            "fmm_rel_l2_J_vs_direct": rel(Jfh, Jh),
+            "fmm_rel_l2_nu_t_vs_direct": rel(nut_f.cpu().double().numpy(), nut.cpu().double().numpy()),
+            "rhs_with_viscous_fmm_ms": round(fg_ms + vre_ms + pse_ms, 3)})
+        log(f"viscous RHS: direct gradient {grad_ms:.1f} ms, FMM gradient {fg_ms:.1f} ms")
+        del fws, uf, df, Jf, nut_f
         del Jv, nut, vol, dv, pse_ws
 
         # ------------------------------------------------------------------ closed solver step

@@ -264,14 +264,16 @@ vpm_status vpm_segments_backward(int32_t dtype, int64_t n_seg, const void* a, co
  * The error of the far field falls geometrically with the order (about x0.6 per order on
  * rotor wakes).  Expansions are FP64 for both dtypes; VPM_F32C sums the near field in FP32
  * with compensation.
- *  x, gamma [3][ld], sigma [ld]; u_out, dgamma_out [3][ld_out] (written, in the input order).
+ *  x, gamma [3][ld], sigma [ld]; u_out, dgamma_out [3][ld_out] (written, in the input order);
+ *  grad_out [9][ld_out] (row 3a + b = du_a/dx_b, near pairs exact, far field from the local
+ *  expansions) or NULL: the velocity gradient the paper's FMM also provides (Vreman's model).
  *  0 <= level <= 10, 1 <= order <= 16, n < 2^30.
  *  workspace        vpm_fmm_workspace_size(dtype, n, level, order) bytes (0 if invalid);
  *                   holds the sorted particles, the tree and the expansions.
  * Returns VPM_OK or the first violated condition. */
 vpm_status vpm_fmm_eval(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* sigma, int64_t ld,
-                        int32_t level, int32_t order, int32_t scheme, void* u_out, void* dgamma_out, int64_t ld_out,
-                        void* workspace, size_t ws_bytes, void* stream);
+                        int32_t level, int32_t order, int32_t scheme, void* u_out, void* dgamma_out, void* grad_out,
+                        int64_t ld_out, void* workspace, size_t ws_bytes, void* stream);
 size_t vpm_fmm_workspace_size(int32_t dtype, int64_t n, int32_t level, int32_t order);
 
 /* ---------------------------------------------------------------------------------------

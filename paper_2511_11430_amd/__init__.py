@@ -590,11 +590,12 @@ def vpm_fmm_workspace_size(n, level, order, dtype=None):
     return int(lib.vpm_fmm_workspace_size(code, int(n), int(level), int(order)))
 
 
-def vpm_fmm_eval(x, gamma, sigma, level, order, *, scheme=TRANSPOSED, u_out=None, dgamma_out=None, workspace=None,
-                 stream=None):
+def vpm_fmm_eval(x, gamma, sigma, level, order, *, scheme=TRANSPOSED, u_out=None, dgamma_out=None, want_grad=False,
+                 grad_out=None, workspace=None, stream=None):
     """Self-interaction (u, dgamma) of the particles by the Cartesian FMM (Sec. II.B): uniform
     octree of depth ``level``, expansions of order ``order``, exact Gaussian kernel over each
-    leaf's 27 neighbours.  Returns (u, dgamma)."""
+    leaf's 27 neighbours.  Returns (u, dgamma), or (u, dgamma, J) with ``want_grad`` (J of
+    shape (9, n), row 3a + b = du_a/dx_b)."""
     torch = _torch()
     lib = _lib.load()
     dt = _code(x)
@@ -613,14 +614,21 @@ def vpm_fmm_eval(x, gamma, sigma, level, order, *, scheme=TRANSPOSED, u_out=None
     _vec(dgamma_out, "dgamma_out", n, tdt)
     if n > 0 and _ld(u_out) != _ld(dgamma_out):
         raise ValueError("u_out and dgamma_out must share one leading dimension")
+    if want_grad and grad_out is None:
+        grad_out = torch.empty((9, max(_ld(u_out), 1)), dtype=tdt, device=x.device)[:, :n]
+    if grad_out is not None:
+        if grad_out.dim() != 2 or grad_out.shape != (9, n) or grad_out.dtype != tdt or (n > 1 and grad_out.stride(1) != 1):
+            raise ValueError(f"grad_out must be (9, {n}) {tdt} with unit stride along points")
+        if n > 0 and _ld(grad_out) != _ld(u_out):
+            raise ValueError("grad_out and u_out must share one leading dimension")
     need = int(lib.vpm_fmm_workspace_size(dt, n, int(level), int(order)))
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
     ws_bytes = workspace.numel() * workspace.element_size()
     st = lib.vpm_fmm_eval(dt, n, _p(x), _p(gamma), _p(sigma), _ld(x), int(level), int(order), int(scheme), _p(u_out),
-                          _p(dgamma_out), _ld(u_out), _p(workspace), ws_bytes, _stream(stream))
+                          _p(dgamma_out), _p(grad_out), _ld(u_out), _p(workspace), ws_bytes, _stream(stream))
     _check("vpm_fmm_eval", st)
-    return u_out, dgamma_out
+    return (u_out, dgamma_out, grad_out) if grad_out is not None else (u_out, dgamma_out)
 
 
 def vpm_backward(x_src, gamma_src, sigma_src, u_bar, dgamma_bar=None, x_tgt=None, gamma_tgt=None,

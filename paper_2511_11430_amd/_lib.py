@@ -50,8 +50,8 @@ SIGNATURES = {
                                            c_i64, c_i32, c_vp, c_vp, c_vp, c_i64, c_i32, c_vp]),
     "vpm_segments_backward": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_dbl, c_i32, c_i64, c_vp, c_vp, c_i64,
                                       c_i32, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp]),
-    "vpm_fmm_eval": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_vp, c_i64, c_vp, c_sz,
-                             c_vp]),
+    "vpm_fmm_eval": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_i64, c_vp,
+                             c_sz, c_vp]),
     "vpm_fmm_workspace_size": (c_sz, [c_i32, c_i64, c_i32, c_i32]),
     "vpm_backward": (c_i32, [c_i32, c_i32, c_i64p, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64,
                              c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(VpmOptions), c_vp, c_sz, c_vp]),

@@ -572,14 +572,16 @@ struct NearArgs {
     const double* box;
     int level;
     int p;
-    const double* far;  // [6][n] far field (u, dgamma) in sorted order, or null
+    const double* far;  // [15][n] far field (u, dgamma, J) in sorted order, or null
     void* u;
     void* dg;
+    void* grad;         // [9][ldo] velocity gradient, or null
     int64_t ldo;
 };
 
 // Far field at the targets of one work item from their leaf's local expansion (FP64):
-// far[0..2] = curl psi, far[3..5] = J^T Gamma_i (transposed) or J Gamma_i (classical).
+// far[0..2] = curl psi, far[3..5] = J^T Gamma_i (transposed) or J Gamma_i (classical),
+// far[6..14] = J (row-major) when the gradient is wanted.
 template <typename T, bool CLASSICAL>
 __global__ __launch_bounds__(256) void k_fmm_l2p(NearArgs a, double* __restrict__ far) {
     const int item = blockIdx.x;
@@ -651,15 +653,92 @@ __global__ __launch_bounds__(256) void k_fmm_l2p(NearArgs a, double* __restrict_
         for (int b = 0; b < 3; ++b) sum += (CLASSICAL ? J[c][b] : J[b][c]) * Gi[b];
         far[(3 + c) * n + q] = sum;
     }
+    if (a.grad)
+        for (int c = 0; c < 3; ++c)
+            for (int e = 0; e < 3; ++e) far[(6 + 3 * c + e) * n + q] = J[c][e];
+}
+
+// One near-field pair.  Sums (as the direct kernel's):
+//   plain:    U = sum G v (v = Gamma_j x r), A = sum G Gamma_j outside the cores,
+//             B = sum Hn tau r (transposed, tau = Gamma_i . v) or sum Hn (r . Gamma_i) v
+//             (classical), in-core cross terms G Gamma_i x Gamma_j put into B (x -1/3; the
+//             classical sign is folded in);
+//   gradient: U, A outside the cores, H = sum Hn v r^T (row-major), A of the in-core pairs,
+//             C = sum over in-core pairs of G Gamma_i x Gamma_j.
+template <typename T, bool CLASSICAL, bool GRAD, bool MAYCORE>
+__device__ __forceinline__ void near_pair(T xi, T yi, T zi, T gxi, T gyi, T gzi, T sxj, T syj, T szj, T gxj, T gyj,
+                                          T gzj, T isj, T isj2, T cutj, T* acc) {
+    const T rx = xi - sxj, ry = yi - syj, rz = zi - szj;
+    const T s2 = rx * rx + ry * ry + rz * rz;
+    const T vx = gyj * rz - gzj * ry, vy = gzj * rx - gxj * rz, vz = gxj * ry - gyj * rx;
+    const T inv = rsqrt_fast(s2);
+    const T inv2 = inv * inv;
+    T G = inv * inv2, Hn = G * inv2;
+    bool core = false;
+    if constexpr (MAYCORE) {
+        core = s2 < cutj;
+        if (core) core_weights<T>(s2, isj, isj2, G, Hn, G, Hn);
+    }
+    acc[0] += G * vx;
+    acc[1] += G * vy;
+    acc[2] += G * vz;
+    if constexpr (GRAD) {
+        const T hx = Hn * vx, hy = Hn * vy, hz = Hn * vz;
+        acc[6] += hx * rx;
+        acc[7] += hx * ry;
+        acc[8] += hx * rz;
+        acc[9] += hy * rx;
+        acc[10] += hy * ry;
+        acc[11] += hy * rz;
+        acc[12] += hz * rx;
+        acc[13] += hz * ry;
+        acc[14] += hz * rz;
+        if (MAYCORE && core) {
+            acc[15] += G * gxj;
+            acc[16] += G * gyj;
+            acc[17] += G * gzj;
+            acc[18] += G * (gyi * gzj - gzi * gyj);
+            acc[19] += G * (gzi * gxj - gxi * gzj);
+            acc[20] += G * (gxi * gyj - gyi * gxj);
+        } else {
+            acc[3] += G * gxj;
+            acc[4] += G * gyj;
+            acc[5] += G * gzj;
+        }
+    } else {
+        const T w = CLASSICAL ? Hn * (rx * gxi + ry * gyi + rz * gzi) : Hn * (gxi * vx + gyi * vy + gzi * vz);
+        if constexpr (!CLASSICAL) {
+            acc[6] += w * rx;
+            acc[7] += w * ry;
+            acc[8] += w * rz;
+        } else {
+            acc[6] += w * vx;
+            acc[7] += w * vy;
+            acc[8] += w * vz;
+        }
+        if (MAYCORE && core) {
+            // transposed: G Gamma_i x Gamma_j, classical: G Gamma_j x Gamma_i, into B x -1/3
+            const T f = G * T(CLASSICAL ? 1.0 / 3.0 : -1.0 / 3.0);
+            acc[6] += f * (gyi * gzj - gzi * gyj);
+            acc[7] += f * (gzi * gxj - gxi * gzj);
+            acc[8] += f * (gxi * gyj - gyi * gxj);
+        } else {
+            acc[3] += G * gxj;
+            acc[4] += G * gyj;
+            acc[5] += G * gzj;
+        }
+    }
 }
 
 // Near field of one work item: the exact Gaussian pair sum over the 27 neighbouring leaves.
 // Sources stream through LDS in tiles of 256; each wavefront tests every 64-source subtile
 // against its own 64 targets and runs the loop without the core test where the boxes are
-// farther apart than the subtile's largest core cut (rho_far sigma).
-template <typename T, bool CLASSICAL>
+// farther apart than the subtile's largest core cut (rho_far sigma).  The epilogue adds the
+// far field (if any) and writes in the caller's order.
+template <typename T, bool CLASSICAL, bool GRAD>
 __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
     constexpr bool kComp = std::is_same<T, float>::value;
+    constexpr int NA = GRAD ? 21 : 9;
     const int item = blockIdx.x;
     if (item >= *a.nitems) return;
     const T* __restrict__ xs = static_cast<const T*>(a.xs);
@@ -700,10 +779,8 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
         const T pl[3] = {xi, yi, zi};
         wave_box(pl, pl, T(0), tlo, thi, tcut);
     }
-    // U = sum G v, A = sum G Gamma_j, B = sum Hn tau r (transposed) or sum Hn (r . Gamma_i) v
-    // (classical); in-core pairs put their cross term into B directly (scaled by -1/3).
-    T acc[9], hi[9], lo[9];
-    for (int c = 0; c < 9; ++c) acc[c] = hi[c] = lo[c] = T(0);
+    T acc[NA], hi[NA], lo[NA];
+    for (int c = 0; c < NA; ++c) acc[c] = hi[c] = lo[c] = T(0);
     for (int nb = 0; nb < 27; ++nb) {
         const int lo_j = nb_lo[nb], hi_j = nb_hi[nb];
         for (int j0 = lo_j; j0 < hi_j; j0 += kNearTile) {
@@ -712,7 +789,7 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
             {
                 const bool has = int(threadIdx.x) < cnt;
                 const int j = has ? j0 + threadIdx.x : j0;
-                T pl[3], cut = T(0);
+                T pl[3];
                 for (int d = 0; d < 3; ++d) {
                     pl[d] = xs[d * n + j];
                     sx[d][threadIdx.x] = pl[d];
@@ -722,10 +799,10 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
                 const T is = T(1) / sj;
                 sis[threadIdx.x] = is;
                 sis2[threadIdx.x] = is * is;
-                cut = Prec<T>::kFarRho2 * sj * sj;
+                const T cut = Prec<T>::kFarRho2 * sj * sj;
                 scut[threadIdx.x] = cut;
                 // subtile box of this wavefront's 64 staged sources (past the end: the tile's
-                // first source again, which leaves the box unchanged)
+                // first source again, which only makes the box larger)
                 T blo[3], bhi[3], bcut;
                 wave_box(pl, pl, cut, blo, bhi, bcut);
                 if (lane == 0) {
@@ -748,83 +825,21 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
                 }
                 if (d2 >= sbox[sub][6]) {
                     // every pair of this wavefront and subtile is outside the cores
+                    for (int jj = jb; jj < je; ++jj)
+                        near_pair<T, CLASSICAL, GRAD, false>(xi, yi, zi, gxi, gyi, gzi, sx[0][jj], sx[1][jj],
+                                                             sx[2][jj], sg[0][jj], sg[1][jj], sg[2][jj], T(0), T(0),
+                                                             T(0), acc);
+                } else {
                     for (int jj = jb; jj < je; ++jj) {
-                        const T rx = xi - sx[0][jj], ry = yi - sx[1][jj], rz = zi - sx[2][jj];
-                        const T s2 = rx * rx + ry * ry + rz * rz;
-                        const T gxj = sg[0][jj], gyj = sg[1][jj], gzj = sg[2][jj];
-                        const T vx = gyj * rz - gzj * ry, vy = gzj * rx - gxj * rz, vz = gxj * ry - gyj * rx;
-                        const T inv = rsqrt_fast(s2);
-                        const T inv2 = inv * inv;
-                        const T G = inv * inv2, Hn = G * inv2;
-                        acc[0] += G * vx;
-                        acc[1] += G * vy;
-                        acc[2] += G * vz;
-                        acc[3] += G * gxj;
-                        acc[4] += G * gyj;
-                        acc[5] += G * gzj;
-                        const T w = CLASSICAL ? Hn * (rx * gxi + ry * gyi + rz * gzi) : Hn * (gxi * vx + gyi * vy + gzi * vz);
-                        if constexpr (!CLASSICAL) {
-                            acc[6] += w * rx;
-                            acc[7] += w * ry;
-                            acc[8] += w * rz;
-                        } else {
-                            acc[6] += w * vx;
-                            acc[7] += w * vy;
-                            acc[8] += w * vz;
-                        }
-                    }
-                    continue;
-                }
-                for (int jj = jb; jj < je; ++jj) {
-                    if (j0 + jj == qq) continue;  // self pair
-                    const T rx = xi - sx[0][jj], ry = yi - sx[1][jj], rz = zi - sx[2][jj];
-                    const T s2 = rx * rx + ry * ry + rz * rz;
-                    const T gxj = sg[0][jj], gyj = sg[1][jj], gzj = sg[2][jj];
-                    const T vx = gyj * rz - gzj * ry, vy = gzj * rx - gxj * rz, vz = gxj * ry - gyj * rx;
-                    const T inv = rsqrt_fast(s2);
-                    const T inv2 = inv * inv;
-                    T G = inv * inv2, Hn = G * inv2;
-                    const bool core = s2 < scut[jj];
-                    if (core) core_weights<T>(s2, sis[jj], sis2[jj], G, Hn, G, Hn);
-                    acc[0] += G * vx;
-                    acc[1] += G * vy;
-                    acc[2] += G * vz;
-                    if constexpr (!CLASSICAL) {
-                        const T w = Hn * (gxi * vx + gyi * vy + gzi * vz);
-                        acc[6] += w * rx;
-                        acc[7] += w * ry;
-                        acc[8] += w * rz;
-                        if (core) {
-                            const T f = G * T(-1.0 / 3.0);
-                            acc[6] += f * (gyi * gzj - gzi * gyj);
-                            acc[7] += f * (gzi * gxj - gxi * gzj);
-                            acc[8] += f * (gxi * gyj - gyi * gxj);
-                        } else {
-                            acc[3] += G * gxj;
-                            acc[4] += G * gyj;
-                            acc[5] += G * gzj;
-                        }
-                    } else {
-                        const T w = Hn * (rx * gxi + ry * gyi + rz * gzi);
-                        acc[6] += w * vx;
-                        acc[7] += w * vy;
-                        acc[8] += w * vz;
-                        if (core) {
-                            // G Gamma_j x Gamma_i into B, scaled by -1/3
-                            const T f = G * T(-1.0 / 3.0);
-                            acc[6] += f * (gyj * gzi - gzj * gyi);
-                            acc[7] += f * (gzj * gxi - gxj * gzi);
-                            acc[8] += f * (gxj * gyi - gyj * gxi);
-                        } else {
-                            acc[3] += G * gxj;
-                            acc[4] += G * gyj;
-                            acc[5] += G * gzj;
-                        }
+                        if (j0 + jj == qq) continue;  // self pair
+                        near_pair<T, CLASSICAL, GRAD, true>(xi, yi, zi, gxi, gyi, gzi, sx[0][jj], sx[1][jj],
+                                                            sx[2][jj], sg[0][jj], sg[1][jj], sg[2][jj], sis[jj],
+                                                            sis2[jj], scut[jj], acc);
                     }
                 }
             }
             if constexpr (kComp) {
-                for (int c = 0; c < 9; ++c) {
+                for (int c = 0; c < NA; ++c) {
                     T s, e;
                     two_sum(hi[c], acc[c], s, e);
                     hi[c] = s;
@@ -835,34 +850,56 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
         }
     }
     if (!valid) return;
-    double S[9];
-    for (int c = 0; c < 9; ++c) S[c] = kComp ? double(hi[c]) + double(lo[c]) : double(acc[c]);
+    double S[NA];
+    for (int c = 0; c < NA; ++c) S[c] = kComp ? double(hi[c]) + double(lo[c]) : double(acc[c]);
     const double Gi[3] = {double(gxi), double(gyi), double(gzi)};
-    // near part: u = U/4pi; transposed (Gamma_i x A - 3B)/4pi; classical (A x Gamma_i - 3B)/4pi
-    const double Ax = S[3], Ay = S[4], Az = S[5];
-    double cx, cy, cz;
-    if constexpr (!CLASSICAL) {
-        cx = Gi[1] * Az - Gi[2] * Ay;
-        cy = Gi[2] * Ax - Gi[0] * Az;
-        cz = Gi[0] * Ay - Gi[1] * Ax;
-    } else {
-        cx = Ay * Gi[2] - Az * Gi[1];
-        cy = Az * Gi[0] - Ax * Gi[2];
-        cz = Ax * Gi[1] - Ay * Gi[0];
-    }
     double u[3] = {S[0] * kInv4Pi, S[1] * kInv4Pi, S[2] * kInv4Pi};
-    double dgv[3] = {(cx - 3.0 * S[6]) * kInv4Pi, (cy - 3.0 * S[7]) * kInv4Pi, (cz - 3.0 * S[8]) * kInv4Pi};
-    if (a.far)
+    double dgv[3];
+    // Gamma_i x A
+    const double cx = Gi[1] * S[5] - Gi[2] * S[4];
+    const double cy = Gi[2] * S[3] - Gi[0] * S[5];
+    const double cz = Gi[0] * S[4] - Gi[1] * S[3];
+    double Jn[9];
+    if constexpr (GRAD) {
+        // stretching from the same sums: transposed (Gamma_i x A + C - 3 H^T Gamma_i)/4pi,
+        // classical (A x Gamma_i - C - 3 H Gamma_i)/4pi; J = ([A + A_core]x - 3H)/4pi
+        const double* H = S + 6;
+        const double sgn = CLASSICAL ? -1.0 : 1.0;
+        double hg[3];
+        for (int r = 0; r < 3; ++r)
+            hg[r] = CLASSICAL ? H[3 * r] * Gi[0] + H[3 * r + 1] * Gi[1] + H[3 * r + 2] * Gi[2]
+                              : H[r] * Gi[0] + H[3 + r] * Gi[1] + H[6 + r] * Gi[2];
+        dgv[0] = (sgn * (cx + S[18]) - 3.0 * hg[0]) * kInv4Pi;
+        dgv[1] = (sgn * (cy + S[19]) - 3.0 * hg[1]) * kInv4Pi;
+        dgv[2] = (sgn * (cz + S[20]) - 3.0 * hg[2]) * kInv4Pi;
+        const double At0 = S[3] + S[15], At1 = S[4] + S[16], At2 = S[5] + S[17];
+        const double X[9] = {0.0, -At2, At1, At2, 0.0, -At0, -At1, At0, 0.0};
+        for (int c = 0; c < 9; ++c) Jn[c] = (X[c] - 3.0 * H[c]) * kInv4Pi;
+    } else {
+        // transposed (Gamma_i x A - 3B)/4pi; classical (A x Gamma_i - 3B)/4pi
+        const double sgn = CLASSICAL ? -1.0 : 1.0;
+        dgv[0] = (sgn * cx - 3.0 * S[6]) * kInv4Pi;
+        dgv[1] = (sgn * cy - 3.0 * S[7]) * kInv4Pi;
+        dgv[2] = (sgn * cz - 3.0 * S[8]) * kInv4Pi;
+    }
+    if (a.far) {
         for (int c = 0; c < 3; ++c) {
             u[c] += a.far[c * n + q];
             dgv[c] += a.far[(3 + c) * n + q];
         }
+        if constexpr (GRAD)
+            for (int c = 0; c < 9; ++c) Jn[c] += a.far[(6 + c) * n + q];
+    }
     T* __restrict__ U = static_cast<T*>(a.u);
     T* __restrict__ DG = static_cast<T*>(a.dg);
     const int64_t o = a.perm[q];
     for (int c = 0; c < 3; ++c) {
         U[c * a.ldo + o] = T(u[c]);
         DG[c * a.ldo + o] = T(dgv[c]);
+    }
+    if constexpr (GRAD) {
+        T* __restrict__ JO = static_cast<T*>(a.grad);
+        for (int c = 0; c < 9; ++c) JO[c * a.ldo + o] = T(Jn[c]);
     }
 }
 
@@ -900,7 +937,7 @@ Layout layout(int64_t n, int level, int order, size_t es) {
     y.item_leaf = take(size_t(y.items_cap) * 4);
     y.item_t0 = take(size_t(y.items_cap) * 4);
     y.counts = take(size_t(kMaxLevel + 2) * 4);
-    y.far = take(6 * size_t(n) * sizeof(double));
+    y.far = take(15 * size_t(n) * sizeof(double));
     for (int l = 0; l <= level; ++l) {
         const int64_t full = int64_t(1) << (3 * l);
         const int64_t cap = full < n ? full : n;
@@ -918,7 +955,7 @@ Layout layout(int64_t n, int level, int order, size_t es) {
 
 template <typename T>
 hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, int level, int p, int classical,
-                   T* u, T* dg, int64_t ldo, unsigned char* ws, hipStream_t st) {
+                   T* u, T* dg, T* grad, int64_t ldo, unsigned char* ws, hipStream_t st) {
     const Layout y = layout(n, level, p, sizeof(T));
     uint64_t* keys = reinterpret_cast<uint64_t*>(ws + y.keys);
     double* box = reinterpret_cast<double*>(ws + y.box);
@@ -1007,6 +1044,7 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     na.far = nullptr;
     na.u = u;
     na.dg = dg;
+    na.grad = grad;
     na.ldo = ldo;
     const unsigned grid = unsigned((n + kNearTile - 1) / kNearTile + y.cap[level]);
     if (level >= 2) {
@@ -1018,10 +1056,17 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
         if ((e = hipGetLastError()) != hipSuccess) return e;
         na.far = far;
     }
-    if (classical)
-        hipLaunchKernelGGL((k_fmm_near<T, true>), dim3(grid), dim3(256), 0, st, na);
-    else
-        hipLaunchKernelGGL((k_fmm_near<T, false>), dim3(grid), dim3(256), 0, st, na);
+    if (grad) {
+        if (classical)
+            hipLaunchKernelGGL((k_fmm_near<T, true, true>), dim3(grid), dim3(256), 0, st, na);
+        else
+            hipLaunchKernelGGL((k_fmm_near<T, false, true>), dim3(grid), dim3(256), 0, st, na);
+    } else {
+        if (classical)
+            hipLaunchKernelGGL((k_fmm_near<T, true, false>), dim3(grid), dim3(256), 0, st, na);
+        else
+            hipLaunchKernelGGL((k_fmm_near<T, false, false>), dim3(grid), dim3(256), 0, st, na);
+    }
     return hipGetLastError();
 }
 
@@ -1032,15 +1077,17 @@ size_t fmm_workspace(int64_t n, int level, int order, int dtype) {
 }
 
 hipError_t launch_fmm(int dtype, int64_t n, const void* x, const void* g, const void* sg, int64_t ld, int level,
-                      int order, int classical, void* u, void* dg, int64_t ldo, void* ws, hipStream_t st) {
+                      int order, int classical, void* u, void* dg, void* grad, int64_t ldo, void* ws,
+                      hipStream_t st) {
     if (n == 0) return hipSuccess;
     unsigned char* w = static_cast<unsigned char*>(ws);
     if (dtype == kDtypeF64)
         return run_fmm<double>(n, static_cast<const double*>(x), static_cast<const double*>(g),
                                static_cast<const double*>(sg), ld, level, order, classical, static_cast<double*>(u),
-                               static_cast<double*>(dg), ldo, w, st);
+                               static_cast<double*>(dg), static_cast<double*>(grad), ldo, w, st);
     return run_fmm<float>(n, static_cast<const float*>(x), static_cast<const float*>(g), static_cast<const float*>(sg),
-                          ld, level, order, classical, static_cast<float*>(u), static_cast<float*>(dg), ldo, w, st);
+                          ld, level, order, classical, static_cast<float*>(u), static_cast<float*>(dg),
+                          static_cast<float*>(grad), ldo, w, st);
 }
 
 }  // namespace vpm

@@ -695,8 +695,8 @@ size_t vpm_fmm_workspace_size(int32_t dtype, int64_t n, int32_t level, int32_t o
 }
 
 vpm_status vpm_fmm_eval(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* sigma, int64_t ld,
-                        int32_t level, int32_t order, int32_t scheme, void* u_out, void* dgamma_out, int64_t ld_out,
-                        void* workspace, size_t ws_bytes, void* stream) {
+                        int32_t level, int32_t order, int32_t scheme, void* u_out, void* dgamma_out, void* grad_out,
+                        int64_t ld_out, void* workspace, size_t ws_bytes, void* stream) {
     if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
     if (n < 0 || n > INT32_MAX / 2 || ld < n || ld_out < n) return VPM_ERR_SIZE;
     if (level < 0 || level > 10 || order < 1 || order > 16) return VPM_ERR_ENUM;
@@ -704,19 +704,21 @@ vpm_status vpm_fmm_eval(int32_t dtype, int64_t n, const void* x, const void* gam
     if (n > 0 && (!x || !gamma || !sigma || !u_out || !dgamma_out)) return VPM_ERR_NULL;
     const size_t es = elem_size(dtype);
     const Range ru = span(u_out, 3, ld_out, n, es), rd = span(dgamma_out, 3, ld_out, n, es);
+    const Range rg = span(grad_out, 9, ld_out, n, es);
     const Range ins[3] = {span(x, 3, ld, n, es), span(gamma, 3, ld, n, es), span(sigma, 1, ld, n, es)};
     for (const Range& r : ins)
-        if (overlap(ru, r) || overlap(rd, r)) return VPM_ERR_ALIAS;
-    if (overlap(ru, rd)) return VPM_ERR_ALIAS;
+        if (overlap(ru, r) || overlap(rd, r) || overlap(rg, r)) return VPM_ERR_ALIAS;
+    if (overlap(ru, rd) || overlap(ru, rg) || overlap(rd, rg)) return VPM_ERR_ALIAS;
     if (n == 0) return VPM_OK;
     const size_t need = vpm::fmm_workspace(n, level, order, dtype);
     if (!workspace || ws_bytes < need) return VPM_ERR_WORKSPACE;
     const Range rw = span(workspace, 1, int64_t(need), int64_t(need), 1);
     for (const Range& r : ins)
         if (overlap(rw, r)) return VPM_ERR_ALIAS;
-    if (overlap(rw, ru) || overlap(rw, rd)) return VPM_ERR_ALIAS;
+    if (overlap(rw, ru) || overlap(rw, rd) || overlap(rw, rg)) return VPM_ERR_ALIAS;
     return hip_status(vpm::launch_fmm(dtype, n, x, gamma, sigma, ld, level, order, scheme == VPM_STRETCH_CLASSICAL,
-                                      u_out, dgamma_out, ld_out, workspace, static_cast<hipStream_t>(stream)));
+                                      u_out, dgamma_out, grad_out, ld_out, workspace,
+                                      static_cast<hipStream_t>(stream)));
 }
 
 vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,

@@ -108,7 +108,8 @@ hipError_t sort_keys(uint64_t* keys, int64_t P, hipStream_t st);
 // ---------------------------------------------------------------- Cartesian FMM (fmm.hip)
 size_t fmm_workspace(int64_t n, int level, int order, int dtype);
 hipError_t launch_fmm(int dtype, int64_t n, const void* x, const void* g, const void* sg, int64_t ld, int level,
-                      int order, int classical, void* u, void* dg, int64_t ldo, void* ws, hipStream_t st);
+                      int order, int classical, void* u, void* dg, void* grad, int64_t ldo, void* ws,
+                      hipStream_t st);
 hipError_t launch_segments_gradient(int dtype, const SegArgs& a, hipStream_t st);
 hipError_t launch_segments_vjp(int dtype, const SegArgs& a, hipStream_t st);
 

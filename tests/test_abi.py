@@ -378,8 +378,8 @@ def test_fmm_validation():
 
     def args(**k):
         return [k.get("dt", F32C), k.get("n", 100), P(0), P(1), P(2), k.get("ld", 100), k.get("lev", 3),
-                k.get("ord", 8), k.get("sch", 0), k.get("u", P(3)), k.get("d", P(4)), k.get("ldo", 100),
-                k.get("w", P(5)), k.get("wb", 1 << 40), None]
+                k.get("ord", 8), k.get("sch", 0), k.get("u", P(3)), k.get("d", P(4)), k.get("j", None),
+                k.get("ldo", 100), k.get("w", P(5)), k.get("wb", 1 << 40), None]
     assert f(*args(dt=2)) == DTYPE
     assert f(*args(ld=99)) == SIZE
     assert f(*args(lev=11)) == ENUM
@@ -388,6 +388,8 @@ def test_fmm_validation():
     assert f(*args(u=None)) == NULL
     assert f(*args(u=P(0))) == ALIAS
     assert f(*args(d=P(3))) == ALIAS
+    assert f(*args(j=P(4))) == ALIAS   # gradient over the stretching
+    assert f(*args(j=P(1))) == ALIAS   # gradient over the strengths
     assert f(*args(wb=16)) == WORKSPACE
     assert f(*args(w=None)) == WORKSPACE
     assert f(*args(n=0, ld=0, ldo=0, w=None, wb=0)) == OK

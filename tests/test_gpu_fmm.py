@@ -109,3 +109,37 @@ def test_fmm_full_size_against_direct(gpu):
     e8 = max(rel_l2(host(u8), host(ud)), rel_l2(host(d8), host(dd)))
     say(f"  order 8: {e8:.2e}")
     assert e8 > 3 * max(eu, ed)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("scheme", [vpm.TRANSPOSED, vpm.CLASSICAL])
+@pytest.mark.parametrize("level,order", [(1, 4), (3, 8), (4, 10)])
+def test_fmm_velocity_gradient_matches_oracle(kind, scheme, level, order, gpu):
+    x, g, s = _wake(3333, kind)
+    u, d, J = vpm.vpm_fmm_eval(dev(x, kind), dev(g, kind), dev(s, kind), level, order, scheme=scheme, want_grad=True)
+    uo, do, Jo = oracle.fmm(x, g, s, level, order, scheme, want_grad=True)
+    eu, ed, ej = rel_l2(host(u), uo), rel_l2(host(d), do), rel_l2(host(J), Jo.reshape(9, -1))
+    say(f"fmm grad {kind} scheme={scheme} level={level} order={order}: u {eu:.1e} dgamma {ed:.1e} J {ej:.1e}")
+    assert max(eu, ed, ej) <= TOL[kind]
+
+
+def test_fmm_velocity_gradient_full_size(gpu):
+    """1M wake, depth 6, order 12: J against the direct gradient kernel, and the viscous
+    right-hand side built on it (Vreman, PSE) against the one built on the direct gradient."""
+    import torch
+    c = W.config3()
+    x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], "f32c")
+    X, G, S = dev(x, "f32c"), dev(g, "f32c"), dev(s, "f32c")
+    u, d, J = vpm.vpm_fmm_eval(X, G, S, 6, 12, want_grad=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    vpm.vpm_fmm_eval(X, G, S, 6, 12, u_out=u, dgamma_out=d, grad_out=J)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3
+    ud, dd, Jd = vpm.vpm_eval_velocity_gradient(X, G, S)
+    ej = rel_l2(host(J), host(Jd))
+    nut_f = vpm.vpm_sgs_vreman(J, S, W.C_V)
+    nut_d = vpm.vpm_sgs_vreman(Jd, S, W.C_V)
+    en = rel_l2(host(nut_f), host(nut_d))
+    say(f"fmm 1M with gradient: {ms:.1f} ms; J vs direct {ej:.2e}; Vreman nu_t {en:.2e}")
+    assert ej <= 3e-4 and en <= 3e-4
