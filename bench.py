@@ -174,7 +174,24 @@ def main():
                      "traffic": load_traffic(plan), "kernel": pair_kernel, "kernel_ms": round(k_ms, 3),
                      "flop_per_pair": FLOP_PER_PAIR_VS},
         "nonfinite": nonfinite,
+        "env": {"gpu": torch.cuda.get_device_name(0),
+                "arch": getattr(torch.cuda.get_device_properties(0), "gcnArchName", None),
+                "compute_units": torch.cuda.get_device_properties(0).multi_processor_count,
+                "rocm": torch.version.hip, "torch": torch.__version__,
+                "kernel_ms_min": round(float(np.min(kernel_ms)), 3),
+                "kernel_ms_median": round(float(np.median(kernel_ms)), 3)},
     }
+
+    def timed_once(fn, reps=1):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
 
     # ------------------------------------------------------------------ accuracy + CPU baseline
     import oracle
@@ -200,7 +217,25 @@ def main():
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     result["accuracy"] = {"rel_l2_u": rel(U[:, idx], uo), "rel_l2_dgamma": rel(D[:, idx], do),
                           "sample_targets": m, "gate": 1e-5, "against": "FP64 oracle"}
+    # the symmetric core rule on the same wake: time and accuracy on the first 64 sample targets
+    if not args.quick:
+        us, ds_ = torch.empty_like(u), torch.empty_like(dg)
+        sym_ms = timed_once(lambda: vpm.vpm_eval_velocity_stretching(x, g, s, u_out=us, dgamma_out=ds_,
+                                                                     sigma_rule=vpm.SIGMA_SYMMETRIC))
+        i64 = sample[:64]
+        uso, dso = oracle.eval_pairs(xs_h, gs_h, ss_h, x_tgt=xs_h[:, i64], gam_tgt=gs_h[:, i64], excl=i64,
+                                     sig_tgt=ss_h[i64], sigma_rule=oracle.SIGMA_SYMMETRIC, nthreads=threads)
+        US, DS = us.cpu().double().numpy(), ds_.cpu().double().numpy()
+        result["symmetric_rule"] = {"kernel_ms": round(sym_ms, 3), "gpair_s": round(pairs / (sym_ms * 1e-3) / 1e9, 2),
+                                    "rel_l2_u": rel(US[:, i64], uso), "rel_l2_dgamma": rel(DS[:, i64], dso),
+                                    "sample_targets": 64}
+        del us, ds_
     if not args.no_cpu_baseline:
+        # one core, 4 sample targets
+        t = time.perf_counter()
+        oracle.eval_pairs(xs_h, gs_h, ss_h, x_tgt=xs_h[:, sample[:4]], gam_tgt=gs_h[:, sample[:4]], excl=sample[:4],
+                          nthreads=1)
+        t1 = time.perf_counter() - t
         cpu_model = ""
         try:
             with open("/proc/cpuinfo") as f:
@@ -210,18 +245,8 @@ def main():
         result["cpu_baseline"] = {"value": round(m * N / t_or / 1e9, 4), "unit": "Gpair/s", "cores": threads,
                                   "kind": "oracle",
                                   "sample": f"{m} seeded targets x {N} sources of the same wake, FP64 direct sums "
-                                            f"({t_or:.1f} s)", "cpu": cpu_model}
-
-    def timed_once(fn, reps=1):
-        fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
-            fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
+                                            f"({t_or:.1f} s)", "cpu": cpu_model,
+                                  "single_core_gpair_s": round(4 * N / t1 / 1e9, 4)}
 
     if not args.quick:
         # ------------------------------------------------------------------ Cartesian FMM (Sec. II.B)
@@ -390,10 +415,39 @@ def main():
                                                                     src_off=off, workspace=ws), reps=2)
         t_sep = timed(separate, reps=2)
         sq = float(sum((b - a) ** 2 for a, b in zip(off[:-1], off[1:])))
+        # per-wake error of the persistent launch on 256 seeded targets per wake
+        UW, DW = uw.cpu().double().numpy(), dw.cpu().double().numpy()
+        worst_u = worst_d = 0.0
+        for wi, w in enumerate(wakes):
+            a0, b0 = off[wi], off[wi + 1]
+            xw_h, gw_h, sw_h = (W.to_f32(w[k]) for k in ("x", "gamma", "sigma"))
+            it = np.sort(np.random.default_rng([5, wi]).choice(b0 - a0, min(256, b0 - a0), replace=False))
+            uo_w, do_w = oracle.eval_pairs(xw_h, gw_h, sw_h, x_tgt=xw_h[:, it], gam_tgt=gw_h[:, it], excl=it,
+                                           nthreads=threads)
+            worst_u = max(worst_u, rel(UW[:, a0:b0][:, it], uo_w))
+            worst_d = max(worst_d, rel(DW[:, a0:b0][:, it], do_w))
         result["batched"] = {"n_wakes": len(wakes), "n_particles": off[-1], "sum_n_sq": sq,
                              "persistent_ms": round(t_batched, 3), "separate_ms": round(t_sep, 3),
                              "gpair_s": round(sq / (t_batched * 1e-3) / 1e9, 2),
-                             "speedup": round(t_sep / t_batched, 3)}
+                             "speedup": round(t_sep / t_batched, 3),
+                             "max_wake_rel_l2_u": worst_u, "max_wake_rel_l2_dgamma": worst_d,
+                             "targets_per_wake": 256}
+        del xw, gw, sw, uw, dw, ws, views
+
+        # ------------------------------------------------------------------ C1: FP64, 4096 particles
+        c1 = W.config1()
+        x1, g1, s1 = (torch.tensor(c1[k], dtype=torch.float64, device=dev) for k in ("x", "gamma", "sigma"))
+        u1, d1 = torch.empty_like(x1), torch.empty_like(x1)
+        c1_ms = timed_once(lambda: vpm.vpm_eval_velocity_stretching(x1, g1, s1, u_out=u1, dgamma_out=d1), reps=10)
+        t = time.perf_counter()
+        uo1, do1 = oracle.eval_pairs(c1["x"], c1["gamma"], c1["sigma"], nthreads=threads)
+        or1 = time.perf_counter() - t
+        n1 = c1["x"].shape[1]
+        result["c1_fp64"] = {"workload": c1["name"], "gpu_ms": round(c1_ms, 4), "oracle_s": round(or1, 3),
+                             "gpu_gpair_s": round(n1 * n1 / (c1_ms * 1e-3) / 1e9, 2),
+                             "oracle_gpair_s": round(n1 * n1 / or1 / 1e9, 4), "oracle_cores": threads,
+                             "rel_l2_u": rel(u1.cpu().numpy(), uo1), "rel_l2_dgamma": rel(d1.cpu().numpy(), do1),
+                             "gate": 1e-12}
 
     print(json.dumps(result), flush=True)
 
