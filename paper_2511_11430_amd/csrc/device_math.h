@@ -15,7 +15,9 @@
 //               q/rho^3              = c0 sum_{n>=0} a_n t^n,          a_n = (-1)^n/((2n+3) 2^n n!)
 //               (rho q'-3q)/rho^5    = c0 sum_{n>=1} 2n a_n t^(n-1)
 //               (rho^2 q''-7 rho q'+15 q)/rho^7 = c0 sum_{n>=2} 4n(n-1) a_n t^(n-2)
-//   rho >= 1: closed form with erf and exp (cancellation at most ~10x there).
+//   rho >= 1: closed form (cancellation at most ~10x there): erf and exp in FP64; in FP32
+//             q = 1 - E (F + c0 rho) with E = exp(-rho^2/2) and F = erfcx(rho/sqrt2) fitted
+//             (closed_q below).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -93,6 +95,33 @@ __device__ __forceinline__ double dexp(double x) { return exp(x); }
 __device__ __forceinline__ float derf(float x) { return erff(x); }
 __device__ __forceinline__ double derf(double x) { return erf(x); }
 
+// Closed form for 1 <= t < rho_far^2: rho = sqrt(t), e = exp(-t/2) and q(rho).
+__device__ __forceinline__ void closed_q(double t, double& rho, double& q, double& e) {
+    rho = sqrt_fast(t);
+    e = dexp(-0.5 * t);
+    q = derf(rho * kInvSqrt2D) - kC0D * rho * e;
+}
+// FP32: erf(x) = 1 - exp(-x^2) erfcx(x) turns q into 1 - E (F + c0 rho), E = exp(-t/2),
+// F = erfcx(rho/sqrt2), so that one exponential serves q and the gradient weight.  F is a
+// degree-7 polynomial in w = 1/(1 + p rho) (the variable of Hastings' rational approximations
+// of erfc), fitted for minimax relative error on 1 <= rho <= 7: below 1e-8 with the FP32
+// coefficients (gen_core_fit.py prints them).  E comes from the hardware base-2 exponential
+// (t <= 49 keeps it a normal number).  Against erf and exp of the math library this saves an
+// exponential and erf's two-branch split at rho = sqrt2, with the same FP32 cancellation at
+// rho ~ 1 (1 - E (F + c0 rho) ~ 0.2 there).
+constexpr float kErfcxP = 0.26f;
+constexpr float kErfcxC[8] = {0.00024324792f, 0.20333688f, 0.23765302f, 0.06786008f,
+                              0.487162f,      -0.38822648f, 0.565143f,  -0.17319544f};
+__device__ __forceinline__ void closed_q(float t, float& rho, float& q, float& e) {
+    rho = sqrt_fast(t);
+    e = __builtin_amdgcn_exp2f(t * -0.72134752044448170368f);  // exp(-t/2) = 2^(-t log2(e)/2)
+    const float w = rcp_fast(fmaf(kErfcxP, rho, 1.0f));
+    float f = kErfcxC[7];
+#pragma unroll
+    for (int k = 6; k >= 0; --k) f = fmaf(f, w, kErfcxC[k]);
+    q = fmaf(-e, fmaf(float(kC0D), rho, f), 1.0f);
+}
+
 // In-core weights.  Inputs: s2 = |r|^2, isig = 1/sigma, isig2 = 1/sigma^2, Gf = s^-3 and
 // Hf = s^-5 (valid when s > 0).  Outputs G = 4 pi g and Hn = -(4 pi/3) h.
 template <typename T>
@@ -106,9 +135,8 @@ __device__ __forceinline__ void core_weights(T s2, T isig, T isig2, T Gf, T Hf, 
         G = T(kC0D) * gw * isig3;
         Hn = T(-kC0D / 3.0) * hw * isig5;
     } else {
-        const T rho = sqrt_fast(t);
-        const T e = dexp(T(-0.5) * t);
-        const T q = derf(rho * T(kInvSqrt2D)) - T(kC0D) * rho * e;
+        T rho, q, e;
+        closed_q(t, rho, q, e);
         G = q * Gf;
         Hn = (q - T(kC0D / 3.0) * rho * t * e) * Hf;
     }
@@ -130,9 +158,8 @@ __device__ __forceinline__ void core_weights3(T s2, T isig, T isig2, T Gf, T Hf,
         Hn = T(-kC0D / 3.0) * hw * isig5;
         Kn = T(kC0D / 15.0) * kw * isig7;
     } else {
-        const T rho = sqrt_fast(t);
-        const T e = dexp(T(-0.5) * t);
-        const T q = derf(rho * T(kInvSqrt2D)) - T(kC0D) * rho * e;
+        T rho, q, e;
+        closed_q(t, rho, q, e);
         const T r3e = rho * t * e;  // rho^3 e
         G = q * Gf;
         Hn = (q - T(kC0D / 3.0) * r3e) * Hf;
