@@ -116,21 +116,11 @@ struct FmmLevel {
 };
 
 // ---------------------------------------------------------------- tree
-template <typename T>
-__global__ __launch_bounds__(1024) void k_fmm_box(const T* __restrict__ x, int64_t ld, int64_t n, int level,
-                                                  double* __restrict__ box) {
-    __shared__ double red[6][16];
-    double v[6];
-    for (int d = 0; d < 3; ++d) {
-        v[d] = INFINITY;
-        v[3 + d] = -INFINITY;
-    }
-    for (int64_t i = threadIdx.x; i < n; i += 1024)
-        for (int d = 0; d < 3; ++d) {
-            const double xv = double(x[d * ld + i]);
-            v[d] = fmin(v[d], xv);
-            v[3 + d] = fmax(v[3 + d], xv);
-        }
+constexpr int kBoxParts = 1024;   // most workgroups of the bounding-box reduction
+constexpr int kScanChunk = 4096;  // leaf codes per workgroup of the leaf enumeration
+
+// min and max of one value per lane over a workgroup of 256 (result valid in thread 0)
+__device__ __forceinline__ void block_minmax6(double (&v)[6], double (*red)[4]) {
     for (int off = 32; off > 0; off >>= 1)
         for (int d = 0; d < 3; ++d) {
             v[d] = fmin(v[d], __shfl_xor(v[d], off));
@@ -140,20 +130,57 @@ __global__ __launch_bounds__(1024) void k_fmm_box(const T* __restrict__ x, int64
     if ((threadIdx.x & 63) == 0)
         for (int c = 0; c < 6; ++c) red[c][wv] = v[c];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double lo[3], hi[3];
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = red[d][0];
-            hi[d] = red[3 + d][0];
-            for (int w = 1; w < 16; ++w) {
-                lo[d] = fmin(lo[d], red[d][w]);
-                hi[d] = fmax(hi[d], red[3 + d][w]);
+    if (threadIdx.x == 0)
+        for (int w = 1; w < 4; ++w)
+            for (int d = 0; d < 3; ++d) {
+                v[d] = fmin(v[d], red[d][w]);
+                v[3 + d] = fmax(v[3 + d], red[3 + d][w]);
             }
+}
+
+// Bounding box, first pass: each workgroup reduces a grid-strided share of the particles to
+// part[c][blockIdx.x] (c = min x, y, z, max x, y, z).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fmm_box_part(const T* __restrict__ x, int64_t ld, int64_t n,
+                                                      double* __restrict__ part) {
+    __shared__ double red[6][4];
+    double v[6];
+    for (int d = 0; d < 3; ++d) {
+        v[d] = INFINITY;
+        v[3 + d] = -INFINITY;
+    }
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride)
+        for (int d = 0; d < 3; ++d) {
+            const double xv = double(x[d * ld + i]);
+            v[d] = fmin(v[d], xv);
+            v[3 + d] = fmax(v[3 + d], xv);
         }
+    block_minmax6(v, red);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 6; ++c) part[c * gridDim.x + blockIdx.x] = v[c];
+}
+
+// Second pass (one workgroup): the cube around the box, box = (corner[3], H, leaf width).
+__global__ __launch_bounds__(256) void k_fmm_box(const double* __restrict__ part, int nparts, int level,
+                                                 double* __restrict__ box) {
+    __shared__ double red[6][4];
+    double v[6];
+    for (int d = 0; d < 3; ++d) {
+        v[d] = INFINITY;
+        v[3 + d] = -INFINITY;
+    }
+    for (int b = threadIdx.x; b < nparts; b += 256)
+        for (int d = 0; d < 3; ++d) {
+            v[d] = fmin(v[d], part[d * nparts + b]);
+            v[3 + d] = fmax(v[3 + d], part[(3 + d) * nparts + b]);
+        }
+    block_minmax6(v, red);
+    if (threadIdx.x == 0) {
         double H = 0.0, c[3];
         for (int d = 0; d < 3; ++d) {
-            c[d] = 0.5 * (lo[d] + hi[d]);
-            H = fmax(H, 0.5 * (hi[d] - lo[d]));
+            c[d] = 0.5 * (v[d] + v[3 + d]);
+            H = fmax(H, 0.5 * (v[3 + d] - v[d]));
         }
         if (!(H > 0.0)) H = 1.0;
         for (int d = 0; d < 3; ++d) box[d] = c[d] - H;
@@ -201,6 +228,96 @@ __global__ __launch_bounds__(256) void k_fmm_gather(const T* __restrict__ x, con
     ss[q] = sg[i];
     perm[q] = int32_t(i);
     lcode[q] = uint32_t(k >> 32) >> (3 * (kMaxLevel - level));
+}
+
+// Distinct leaf codes of the sorted particles in three passes over workgroups of kScanChunk
+// codes (the single-workgroup k_fmm_unique below serves the short inner levels).
+// Pass 1: the number of segment starts (i = 0 or in[i] != in[i - 1]) in each chunk.
+__global__ __launch_bounds__(256) void k_fmm_leaf_count(const uint32_t* __restrict__ in, int64_t n,
+                                                        int32_t* __restrict__ bsum) {
+    __shared__ int32_t red[4];
+    const int64_t b0 = int64_t(blockIdx.x) * kScanChunk;
+    int32_t cnt = 0;
+    for (int k = 0; k < kScanChunk / 256; ++k) {
+        const int64_t i = b0 + k * 256 + threadIdx.x;
+        if (i < n && (i == 0 || in[i] != in[i - 1])) ++cnt;
+    }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Pass 2 (one workgroup): exclusive scan of the chunk counts in place; the leaf count and
+// first_out[count] = n.
+__global__ __launch_bounds__(1024) void k_fmm_leaf_scan(int32_t* __restrict__ bsum, int64_t nb, int64_t n,
+                                                        int32_t* __restrict__ first_out,
+                                                        int32_t* __restrict__ count_out) {
+    __shared__ int32_t part[1024];
+    const int tid = threadIdx.x;
+    int32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int32_t v = base + tid < nb ? bsum[base + tid] : 0;
+        part[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int32_t w = tid >= off ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += w;
+            __syncthreads();
+        }
+        if (base + tid < nb) bsum[base + tid] = carry + part[tid] - v;
+        carry += part[1023];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        *count_out = carry;
+        first_out[carry] = int32_t(n);
+    }
+}
+
+// Pass 3: each chunk writes its segment starts at its scanned offset: code_out[seg] = code,
+// first_out[seg] = first particle.  Thread t takes 16 consecutive codes of the chunk (staged
+// in LDS with the code before the chunk).
+__global__ __launch_bounds__(256) void k_fmm_leaf_scatter(const uint32_t* __restrict__ in, int64_t n,
+                                                          const int32_t* __restrict__ boff,
+                                                          uint32_t* __restrict__ code_out,
+                                                          int32_t* __restrict__ first_out) {
+    constexpr int kPer = kScanChunk / 256;
+    __shared__ uint32_t sc[kScanChunk + 1];
+    __shared__ int32_t wsum[4];
+    const int64_t b0 = int64_t(blockIdx.x) * kScanChunk;
+    const int tid = threadIdx.x;
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = b0 + k * 256 + tid;
+        sc[1 + k * 256 + tid] = i < n ? in[i] : 0u;
+    }
+    if (tid == 0) sc[0] = b0 > 0 ? in[b0 - 1] : ~in[0];  // code 0 always starts a segment
+    __syncthreads();
+    int32_t cnt = 0;
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid * kPer + k;
+        if (b0 + j < n && sc[1 + j] != sc[j]) ++cnt;
+    }
+    // exclusive prefix of cnt over the workgroup
+    int32_t incl = cnt;
+    const int lane = tid & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t w = __shfl_up(incl, off);
+        if (lane >= off) incl += w;
+    }
+    if (lane == 63) wsum[tid >> 6] = incl;
+    __syncthreads();
+    int32_t seg = boff[blockIdx.x] + incl - cnt;
+    for (int w = 0; w < (tid >> 6); ++w) seg += wsum[w];
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid * kPer + k;
+        if (b0 + j < n && sc[1 + j] != sc[j]) {
+            code_out[seg] = sc[1 + j];
+            first_out[seg] = int32_t(b0 + j);
+            ++seg;
+        }
+    }
 }
 
 // Distinct values of in[i] >> shift over a sorted input (one workgroup): code_out, the first
@@ -907,7 +1024,7 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-    size_t keys, box, xs, gs, ss, perm, lcode, terms, dtab, item_leaf, item_t0, counts, far;
+    size_t keys, box, scan, xs, gs, ss, perm, lcode, terms, dtab, item_leaf, item_t0, counts, far;
     size_t code[kMaxLevel + 1], first[kMaxLevel + 1], pstart[kMaxLevel + 1], parent[kMaxLevel + 1];
     size_t M[kMaxLevel + 1], L[kMaxLevel + 1];
     int64_t cap[kMaxLevel + 1];
@@ -926,6 +1043,8 @@ Layout layout(int64_t n, int level, int order, size_t es) {
     };
     y.keys = take(size_t(sort_len(n)) * 8);
     y.box = take(8 * sizeof(double));
+    const size_t nb = size_t((n + kScanChunk - 1) / kScanChunk);
+    y.scan = take(nb * 4 > 6 * kBoxParts * sizeof(double) ? nb * 4 : 6 * kBoxParts * sizeof(double));
     y.xs = take(3 * size_t(n) * es);
     y.gs = take(3 * size_t(n) * es);
     y.ss = take(size_t(n) * es);
@@ -981,8 +1100,15 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     }
     hipError_t e;
     const int64_t P = sort_len(n);
-    hipLaunchKernelGGL(k_fmm_box<T>, dim3(1), dim3(1024), 0, st, x, ld, n, level, box);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        const int64_t want = (n + 2047) / 2048;
+        const int nparts = int(want < kBoxParts ? want : kBoxParts);
+        double* part = reinterpret_cast<double*>(ws + y.scan);
+        hipLaunchKernelGGL(k_fmm_box_part<T>, dim3(unsigned(nparts)), dim3(256), 0, st, x, ld, n, part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fmm_box, dim3(1), dim3(256), 0, st, part, nparts, level, box);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_fmm_keys<T>, dim3(unsigned(P / 256)), dim3(256), 0, st, x, ld, n, level, box, keys, P);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = sort_keys(keys, P, st)) != hipSuccess) return e;
@@ -990,9 +1116,18 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
                        gs, ss, perm, lcode, level);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // leaves: distinct leaf codes of the sorted particles
-    hipLaunchKernelGGL(k_fmm_unique, dim3(1), dim3(1024), 0, st, lcode, nullptr, n, 0, lv[level].code,
-                       lv[level].pstart, nullptr, counts + level, nullptr, nullptr, int32_t(n));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+        int32_t* bsum = reinterpret_cast<int32_t*>(ws + y.scan);
+        hipLaunchKernelGGL(k_fmm_leaf_count, dim3(unsigned(nb)), dim3(256), 0, st, lcode, n, bsum);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fmm_leaf_scan, dim3(1), dim3(1024), 0, st, bsum, nb, n, lv[level].pstart,
+                           counts + level);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fmm_leaf_scatter, dim3(unsigned(nb)), dim3(256), 0, st, lcode, n, bsum,
+                           lv[level].code, lv[level].pstart);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // coarser levels: distinct parent codes of the level below
     for (int l = level - 1; l >= 0; --l) {
         hipLaunchKernelGGL(k_fmm_unique, dim3(1), dim3(1024), 0, st, lv[l + 1].code, counts + l + 1, int64_t(0), 3,
