@@ -365,14 +365,18 @@ __global__ __launch_bounds__(1024) void k_fmm_unique(const uint32_t* __restrict_
     }
 }
 
-// Multi-index table: terms[t] = a | b << 8 | c << 16 for |n| <= p.
+// Multi-index table: terms[t] = a | b << 8 | c << 16 for |n| <= p, and at terms[kMaxTerms + t]
+// the index of term t on the (p + 1)^3 grid, (a Q + b) Q + c with Q = p + 1 (the grid index
+// of n + k is the sum of those of n and k).
 __global__ __launch_bounds__(64) void k_fmm_terms(int p, uint32_t* __restrict__ terms) {
     const int d = threadIdx.x;
     if (d > p) return;
+    const int Q = p + 1;
     for (int a = d; a >= 0; --a)
         for (int b = d - a; b >= 0; --b) {
             const int c = d - a - b;
             terms[mpos(a, b, c)] = uint32_t(a) | (uint32_t(b) << 8) | (uint32_t(c) << 16);
+            terms[kMaxTerms + mpos(a, b, c)] = uint32_t((a * Q + b) * Q + c);
         }
 }
 
@@ -509,8 +513,19 @@ __global__ __launch_bounds__(256) void k_fmm_m2m(FmmLevel par, FmmLevel chi, con
 }
 
 // ---------------------------------------------------------------- M2L and L2L
+typedef __attribute__((address_space(4))) const double* CDouble;
+typedef __attribute__((address_space(4))) const uint32_t* CUint;
+
 // One workgroup per target cell of level l: L = M2L over the interaction list (written, not
-// added: the parent's shifted expansion is added afterwards by k_fmm_l2l).
+// added: the parent's shifted expansion is added afterwards by k_fmm_l2l).  With the
+// unit-spacing table D of the offset and the cell width w,
+//   L_n = w^(-1-|n|)/(4 pi) sum_k D_{n+k} (-1/w)^|k| M_k = (-1)^|n|/(4 pi w) sum_k D'_{n+k} M_k,
+//   D'_m = (-1/w)^|m| D_m.
+// Each interaction's D' is staged in LDS on the (p + 1)^3 grid (dynamic LDS), where the index
+// of n + k is the sum of the indices of n and k.  Lanes own terms n (t = lane + 256 j); the
+// terms k with |k| <= p - |n| are a prefix of the degree order, so all lanes of a wavefront
+// walk the same k, whose M_k and grid index are uniform (scalar loads), and a lane drops out
+// when its prefix ends.  Per lane and k: one LDS read and three FMAs.
 __global__ __launch_bounds__(256) void k_fmm_m2l(FmmLevel lv, const int32_t* __restrict__ count, int l,
                                                  const double* __restrict__ box, int p,
                                                  const uint32_t* __restrict__ terms, const double* __restrict__ dtab) {
@@ -518,12 +533,11 @@ __global__ __launch_bounds__(256) void k_fmm_m2l(FmmLevel lv, const int32_t* __r
     const int ncell = *count;
     if (cell >= ncell) return;
     const int nt = nterms(p);
+    extern __shared__ double sDg[];  // (p + 1)^3 + 1
     __shared__ int32_t cand[216];
     __shared__ int32_t list_src[216];
     __shared__ int32_t list_off[216];
     __shared__ int32_t nlist;
-    __shared__ double sD[kMaxTerms];
-    __shared__ double sM[3][kMaxTerms];
     __shared__ double sc[kMaxOrder + 1];
     int ic[3];
     cell_coords(lv.code[cell], ic);
@@ -560,46 +574,68 @@ __global__ __launch_bounds__(256) void k_fmm_m2l(FmmLevel lv, const int32_t* __r
         nlist = m;
     }
     __syncthreads();
-    int nn[4][4];  // n0, n1, n2, |n| of this lane's terms
+    const CUint gidx = (CUint)(terms + kMaxTerms);
+    const int zero_at = (p + 1) * (p + 1) * (p + 1);  // the staging never writes there
+    if (threadIdx.x == 0) sDg[zero_at] = 0.0;
+    int nb[4], cnt[4], smax[4], deg[4];
     double acc[4][3];
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int t = threadIdx.x + 256 * j;
-        const uint32_t k = t < nt ? terms[t] : 0u;
-        nn[j][0] = int(k & 0xff);
-        nn[j][1] = int((k >> 8) & 0xff);
-        nn[j][2] = int(k >> 16);
-        nn[j][3] = nn[j][0] + nn[j][1] + nn[j][2];
+        nb[j] = 0;
+        cnt[j] = 0;
+        deg[j] = 0;
+        if (t < nt) {
+            const uint32_t k = terms[t];
+            deg[j] = int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16);
+            nb[j] = int(terms[kMaxTerms + t]);
+            cnt[j] = nterms(p - deg[j]);
+        }
+        // lane 0 of the wavefront owns its lowest degree, hence the longest prefix
+        smax[j] = __builtin_amdgcn_readfirstlane(cnt[j]);
         for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
     }
     for (int e = 0; e < nlist; ++e) {
         __syncthreads();
         const double* D = dtab + int64_t(list_off[e]) * nt;
-        const double* M = lv.M + int64_t(list_src[e]) * 3 * nt;
         for (int t = threadIdx.x; t < nt; t += 256) {
             const uint32_t k = terms[t];
-            const double f = sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
-            sD[t] = D[t];
-            for (int d = 0; d < 3; ++d) sM[d][t] = M[d * nt + t] * f;
+            sDg[terms[kMaxTerms + t]] = D[t] * sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
         }
         __syncthreads();
+        const CDouble M0 = (CDouble)(lv.M + int64_t(list_src[e]) * 3 * nt);
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (int(threadIdx.x) + 256 * j >= nt) break;
-            const int P = p - nn[j][3];
-            for (int k0 = 0; k0 <= P; ++k0)
-                for (int k1 = 0; k1 <= P - k0; ++k1)
-                    for (int k2 = 0; k2 <= P - k0 - k1; ++k2) {
-                        const double Dv = sD[mpos(nn[j][0] + k0, nn[j][1] + k1, nn[j][2] + k2)];
-                        const int s = mpos(k0, k1, k2);
-                        for (int d = 0; d < 3; ++d) acc[j][d] += Dv * sM[d][s];
-                    }
+            // 8 steps per batch of scalar loads (reads up to 7 entries past the prefix, inside
+            // the workspace; they are not used)
+            for (int s0 = 0; s0 < smax[j]; s0 += 8) {
+                int ks[8];
+                double m[3][8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    ks[i] = int(gidx[s0 + i]);
+                    m[0][i] = M0[s0 + i];
+                    m[1][i] = M0[nt + s0 + i];
+                    m[2][i] = M0[2 * nt + s0 + i];
+                }
+                // lanes past their prefix read the zero after the grid (no branch, so that the
+                // eight reads are in flight together)
+                double Dv[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) Dv[i] = sDg[s0 + i < cnt[j] ? nb[j] + ks[i] : zero_at];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    acc[j][0] += Dv[i] * m[0][i];
+                    acc[j][1] += Dv[i] * m[1][i];
+                    acc[j][2] += Dv[i] * m[2][i];
+                }
+            }
         }
     }
     for (int j = 0; j < 4; ++j) {
         const int t = threadIdx.x + 256 * j;
         if (t >= nt) break;
-        // w^(-1-|n|) / (4 pi)
-        double f = kInv4Pi / w;
-        for (int k = 0; k < nn[j][3]; ++k) f /= w;
+        const double f = ((deg[j] & 1) ? -kInv4Pi : kInv4Pi) / w;
         for (int d = 0; d < 3; ++d) lv.L[(int64_t(cell) * 3 + d) * nt + t] = acc[j][d] * f;
     }
 }
@@ -1050,7 +1086,7 @@ Layout layout(int64_t n, int level, int order, size_t es) {
     y.ss = take(size_t(n) * es);
     y.perm = take(size_t(n) * 4);
     y.lcode = take(size_t(n) * 4);
-    y.terms = take(size_t(kMaxTerms) * 4);
+    y.terms = take(size_t(2 * kMaxTerms + 8) * 4);  // + 8: M2L's batched reads past a prefix
     y.dtab = take(size_t(kOffsets) * nt * sizeof(double));
     y.items_cap = n / kNearTile + n + 1;
     y.item_leaf = take(size_t(y.items_cap) * 4);
@@ -1149,8 +1185,9 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         for (int l = 2; l <= level; ++l) {
-            hipLaunchKernelGGL(k_fmm_m2l, dim3(unsigned(y.cap[l])), dim3(256), 0, st, lv[l], counts + l, l, box, p,
-                               terms, dtab);
+            const size_t grid_lds = (size_t(p + 1) * (p + 1) * (p + 1) + 1) * sizeof(double);
+            hipLaunchKernelGGL(k_fmm_m2l, dim3(unsigned(y.cap[l])), dim3(256), grid_lds, st, lv[l], counts + l, l,
+                               box, p, terms, dtab);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if (l >= 3) {
                 hipLaunchKernelGGL(k_fmm_l2l, dim3(unsigned(y.cap[l])), dim3(256), 0, st, lv[l], lv[l - 1],
