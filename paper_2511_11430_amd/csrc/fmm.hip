@@ -906,6 +906,7 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
     const int qq = valid ? q : t0;
     const int nleaf = *a.count;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wq0 = t0 + 64 * wv;  // first target of this wavefront
 
     __shared__ T sx[3][kNearTile], sg[3][kNearTile], sis[kNearTile], sis2[kNearTile], scut[kNearTile];
     __shared__ T sbox[4][7];
@@ -976,19 +977,27 @@ __global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
                     const T gap = g1 > g2 ? g1 : g2;
                     d2 += gap > T(0) ? gap * gap : T(0);
                 }
+                // the self pairs of this wavefront's targets can only lie in a subtile whose
+                // sources overlap their index range
+                const bool self_sub = j0 + jb < wq0 + 64 && j0 + je > wq0;
                 if (d2 >= sbox[sub][6]) {
                     // every pair of this wavefront and subtile is outside the cores
                     for (int jj = jb; jj < je; ++jj)
                         near_pair<T, CLASSICAL, GRAD, false>(xi, yi, zi, gxi, gyi, gzi, sx[0][jj], sx[1][jj],
                                                              sx[2][jj], sg[0][jj], sg[1][jj], sg[2][jj], T(0), T(0),
                                                              T(0), acc);
-                } else {
+                } else if (self_sub) {
                     for (int jj = jb; jj < je; ++jj) {
                         if (j0 + jj == qq) continue;  // self pair
                         near_pair<T, CLASSICAL, GRAD, true>(xi, yi, zi, gxi, gyi, gzi, sx[0][jj], sx[1][jj],
                                                             sx[2][jj], sg[0][jj], sg[1][jj], sg[2][jj], sis[jj],
                                                             sis2[jj], scut[jj], acc);
                     }
+                } else {
+                    for (int jj = jb; jj < je; ++jj)
+                        near_pair<T, CLASSICAL, GRAD, true>(xi, yi, zi, gxi, gyi, gzi, sx[0][jj], sx[1][jj],
+                                                            sx[2][jj], sg[0][jj], sg[1][jj], sg[2][jj], sis[jj],
+                                                            sis2[jj], scut[jj], acc);
                 }
             }
             if constexpr (kComp) {
