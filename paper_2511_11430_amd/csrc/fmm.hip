@@ -521,19 +521,27 @@ typedef __attribute__((address_space(4))) const uint32_t* CUint;
 // unit-spacing table D of the offset and the cell width w,
 //   L_n = w^(-1-|n|)/(4 pi) sum_k D_{n+k} (-1/w)^|k| M_k = (-1)^|n|/(4 pi w) sum_k D'_{n+k} M_k,
 //   D'_m = (-1/w)^|m| D_m.
-// Each interaction's D' is staged in LDS on the (p + 1)^3 grid (dynamic LDS), where the index
-// of n + k is the sum of the indices of n and k.  Lanes own terms n (t = lane + 256 j); the
-// terms k with |k| <= p - |n| are a prefix of the degree order, so all lanes of a wavefront
-// walk the same k, whose M_k and grid index are uniform (scalar loads), and a lane drops out
-// when its prefix ends.  Per lane and k: one LDS read and three FMAs.
-__global__ __launch_bounds__(256) void k_fmm_m2l(FmmLevel lv, const int32_t* __restrict__ count, int l,
-                                                 const double* __restrict__ box, int p,
-                                                 const uint32_t* __restrict__ terms, const double* __restrict__ dtab) {
+// The workgroup is G groups of 256 lanes; group g takes interactions g, g + G, ...  Each
+// interaction's D' is staged in the group's LDS grid of (p + 1)^3 entries (plus one zero),
+// where the index of n + k is the sum of the indices of n and k.  Lanes own terms n
+// (t = lane + 256 j); the terms k with |k| <= p - |n| are a prefix of the degree order, so the
+// lanes of a wavefront walk the same k, whose M_k and grid index are uniform (scalar loads), and
+// a lane past its prefix reads the zero.  Per lane and k: one LDS read and three FMAs.  The
+// groups' sums are added in group order at the end (deterministic).
+__global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __restrict__ count, int l,
+                                                  const double* __restrict__ box, int p,
+                                                  const uint32_t* __restrict__ terms, const double* __restrict__ dtab) {
     const int cell = blockIdx.x;
     const int ncell = *count;
     if (cell >= ncell) return;
     const int nt = nterms(p);
-    extern __shared__ double sDg[];  // (p + 1)^3 + 1
+    const int ngroup = int(blockDim.x) >> 8;
+    // the group is uniform over each wavefront (256-lane groups)
+    const int grp = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 8), gt = int(threadIdx.x) & 255;
+    const int gsize = (p + 1) * (p + 1) * (p + 1) + 1;  // grid + the zero
+    const int gstride = gsize > 3 * nt ? gsize : 3 * nt;
+    extern __shared__ double sDyn[];                    // ngroup grids; reused for the final sum
+    double* sDg = sDyn + grp * gstride;
     __shared__ int32_t cand[216];
     __shared__ int32_t list_src[216];
     __shared__ int32_t list_off[216];
@@ -573,15 +581,14 @@ __global__ __launch_bounds__(256) void k_fmm_m2l(FmmLevel lv, const int32_t* __r
             }
         nlist = m;
     }
-    __syncthreads();
     const CUint gidx = (CUint)(terms + kMaxTerms);
-    const int zero_at = (p + 1) * (p + 1) * (p + 1);  // the staging never writes there
-    if (threadIdx.x == 0) sDg[zero_at] = 0.0;
+    const int zero_at = gsize - 1;  // the staging never writes there
+    if (gt == 0) sDg[zero_at] = 0.0;
     int nb[4], cnt[4], smax[4], deg[4];
     double acc[4][3];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int t = threadIdx.x + 256 * j;
+        const int t = gt + 256 * j;
         nb[j] = 0;
         cnt[j] = 0;
         deg[j] = 0;
@@ -595,15 +602,23 @@ __global__ __launch_bounds__(256) void k_fmm_m2l(FmmLevel lv, const int32_t* __r
         smax[j] = __builtin_amdgcn_readfirstlane(cnt[j]);
         for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
     }
-    for (int e = 0; e < nlist; ++e) {
+    __syncthreads();
+    const int rounds = (nlist + ngroup - 1) / ngroup;
+    for (int r = 0; r < rounds; ++r) {
+        const int e = r * ngroup + grp;
+        const bool has = e < nlist;
         __syncthreads();
-        const double* D = dtab + int64_t(list_off[e]) * nt;
-        for (int t = threadIdx.x; t < nt; t += 256) {
-            const uint32_t k = terms[t];
-            sDg[terms[kMaxTerms + t]] = D[t] * sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
+        if (has) {
+            const double* D = dtab + int64_t(list_off[e]) * nt;
+            for (int t = gt; t < nt; t += 256) {
+                const uint32_t k = terms[t];
+                sDg[terms[kMaxTerms + t]] = D[t] * sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
+            }
         }
         __syncthreads();
-        const CDouble M0 = (CDouble)(lv.M + int64_t(list_src[e]) * 3 * nt);
+        if (!has) continue;
+        const int src = __builtin_amdgcn_readfirstlane(list_src[e]);
+        const CDouble M0 = (CDouble)(lv.M + int64_t(src) * 3 * nt);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             // 8 steps per batch of scalar loads (reads up to 7 entries past the prefix, inside
@@ -632,11 +647,22 @@ __global__ __launch_bounds__(256) void k_fmm_m2l(FmmLevel lv, const int32_t* __r
             }
         }
     }
+    // add the groups' sums in group order through LDS (3 nt doubles per group)
+    __syncthreads();
     for (int j = 0; j < 4; ++j) {
-        const int t = threadIdx.x + 256 * j;
+        const int t = gt + 256 * j;
         if (t >= nt) break;
-        const double f = ((deg[j] & 1) ? -kInv4Pi : kInv4Pi) / w;
-        for (int d = 0; d < 3; ++d) lv.L[(int64_t(cell) * 3 + d) * nt + t] = acc[j][d] * f;
+        for (int d = 0; d < 3; ++d) sDyn[(grp * 3 + d) * nt + t] = acc[j][d];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 3 * nt; idx += blockDim.x) {
+        const int d = idx / nt, t = idx - d * nt;
+        double v = 0.0;
+        for (int g2 = 0; g2 < ngroup; ++g2) v += sDyn[(g2 * 3 + d) * nt + t];
+        const uint32_t k = terms[t];
+        const int dg = int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16);
+        const double f = ((dg & 1) ? -kInv4Pi : kInv4Pi) / w;
+        lv.L[(int64_t(cell) * 3 + d) * nt + t] = v * f;
     }
 }
 
@@ -1182,6 +1208,13 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     }
     hipLaunchKernelGGL(k_fmm_terms, dim3(1), dim3(64), 0, st, p, terms);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // M2L: as many groups of 256 lanes as 60 KiB of LDS allow (at least one, at most 4); each
+    // group holds its grid, or its 3 nt sums at the end if those are larger
+    const size_t m2l_cells = size_t(p + 1) * (p + 1) * (p + 1) + 1;
+    const size_t m2l_grid = (m2l_cells > size_t(3 * nterms(p)) ? m2l_cells : size_t(3 * nterms(p))) * sizeof(double);
+    int m2l_groups = int((60 * 1024) / m2l_grid);
+    m2l_groups = m2l_groups < 1 ? 1 : (m2l_groups > 4 ? 4 : m2l_groups);
+    const size_t m2l_lds = size_t(m2l_groups) * m2l_grid;
     if (level >= 2) {
         hipLaunchKernelGGL(k_fmm_dtab, dim3(kOffsets), dim3(256), 0, st, p, terms, dtab);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1194,9 +1227,8 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         for (int l = 2; l <= level; ++l) {
-            const size_t grid_lds = (size_t(p + 1) * (p + 1) * (p + 1) + 1) * sizeof(double);
-            hipLaunchKernelGGL(k_fmm_m2l, dim3(unsigned(y.cap[l])), dim3(256), grid_lds, st, lv[l], counts + l, l,
-                               box, p, terms, dtab);
+            hipLaunchKernelGGL(k_fmm_m2l, dim3(unsigned(y.cap[l])), dim3(256 * m2l_groups), m2l_lds, st, lv[l],
+                               counts + l, l, box, p, terms, dtab);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if (l >= 3) {
                 hipLaunchKernelGGL(k_fmm_l2l, dim3(unsigned(y.cap[l])), dim3(256), 0, st, lv[l], lv[l - 1],
