@@ -470,45 +470,93 @@ __global__ __launch_bounds__(256) void k_fmm_p2m(const T* __restrict__ xs, const
     }
 }
 
-// Parents at level l from their children at level l + 1.
+// One axis of a separable Taylor shift of 3 x nt coefficients (mpos order, [3][nt]) held in
+// LDS, with pw[i] = dl^i / i! along axis ax.  Moments (UP = false):
+//   out(k) = sum_{i <= k_ax} in(k - i e_ax) pw[i];
+// local expansions (UP = true):
+//   out(n) = sum_{i <= p - |n|} in(n + i e_ax) pw[i].
+// The three-dimensional shift is the product of the three axes' (the shift factor dl^q/q! is
+// a product over the axes), and each axis keeps the set |n| <= p.  The term t's result is
+// returned in o[3] (t < nt).
+template <bool UP>
+__device__ __forceinline__ void shift_axis_term(const double* in, const double* pw, int ax, int p, int nt,
+                                                uint32_t k, double (&o)[3]) {
+    const int n[3] = {int(k & 0xff), int((k >> 8) & 0xff), int(k >> 16)};
+    const int cnt = UP ? p - (n[0] + n[1] + n[2]) : n[ax];
+    o[0] = o[1] = o[2] = 0.0;
+    for (int i = 0; i <= cnt; ++i) {
+        int m[3] = {n[0], n[1], n[2]};
+        m[ax] += UP ? i : -i;
+        const int s = mpos(m[0], m[1], m[2]);
+        const double f = pw[i];
+        o[0] += in[s] * f;
+        o[1] += in[nt + s] * f;
+        o[2] += in[2 * nt + s] * f;
+    }
+}
+template <bool UP>
+__device__ __forceinline__ void shift_axis(const double* in, double* out, const double* pw, int ax, int p, int nt,
+                                           const uint32_t* __restrict__ terms) {
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+        double o[3];
+        shift_axis_term<UP>(in, pw, ax, p, nt, terms[t], o);
+        out[t] = o[0];
+        out[nt + t] = o[1];
+        out[2 * nt + t] = o[2];
+    }
+}
+
+// Parents at level l from their children at level l + 1: each child's moments are shifted by
+// dl = c_child - c_parent one axis at a time in LDS (dynamic: 2 x 3 nt doubles) and added.
 __global__ __launch_bounds__(256) void k_fmm_m2m(FmmLevel par, FmmLevel chi, const int32_t* __restrict__ count, int l,
                                                  const double* __restrict__ box, int p,
                                                  const uint32_t* __restrict__ terms) {
     const int cell = blockIdx.x;
     if (cell >= *count) return;
     const int nt = nterms(p);
-    __shared__ double pw[8][3][kMaxOrder + 1];
+    extern __shared__ double sShift[];
+    double* bufA = sShift;
+    double* bufB = sShift + 3 * nt;
+    __shared__ double pw[3][kMaxOrder + 1];
     const int c0 = par.first[cell], c1 = par.first[cell + 1];
-    const int nch = c1 - c0;
-    if (int(threadIdx.x) < 3 * nch) {
-        const int q = threadIdx.x / 3, d = threadIdx.x % 3;
-        int ip[3], ic[3];
-        cell_coords(par.code[cell], ip);
-        cell_coords(chi.code[c0 + q], ic);
-        const double dl = cell_centre(box, d, ic[d], l + 1) - cell_centre(box, d, ip[d], l);
-        double v = 1.0;
-        pw[q][d][0] = 1.0;
-        for (int i = 1; i <= p; ++i) {
-            v = v * dl / double(i);
-            pw[q][d][i] = v;
+    int ip[3];
+    cell_coords(par.code[cell], ip);
+    double acc[4][3];
+    for (int j = 0; j < 4; ++j)
+        for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
+    for (int q = c0; q < c1; ++q) {
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            const int d = threadIdx.x;
+            int ic[3];
+            cell_coords(chi.code[q], ic);
+            const double dl = cell_centre(box, d, ic[d], l + 1) - cell_centre(box, d, ip[d], l);
+            double v = 1.0;
+            pw[d][0] = 1.0;
+            for (int i = 1; i <= p; ++i) {
+                v = v * dl / double(i);
+                pw[d][i] = v;
+            }
+        }
+        const double* Mc = chi.M + int64_t(q) * 3 * nt;
+        for (int i = threadIdx.x; i < 3 * nt; i += 256) bufA[i] = Mc[i];
+        __syncthreads();
+        shift_axis<false>(bufA, bufB, pw[0], 0, p, nt, terms);
+        __syncthreads();
+        shift_axis<false>(bufB, bufA, pw[1], 1, p, nt, terms);
+        __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+            const int t = threadIdx.x + 256 * j;
+            if (t >= nt) break;
+            double o[3];
+            shift_axis_term<false>(bufA, pw[2], 2, p, nt, terms[t], o);
+            for (int d = 0; d < 3; ++d) acc[j][d] += o[d];
         }
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nt; t += 256) {
-        const uint32_t k = terms[t];
-        const int k0 = int(k & 0xff), k1 = int((k >> 8) & 0xff), k2 = int(k >> 16);
-        double acc[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < nch; ++q) {
-            const double* Mc = chi.M + int64_t(c0 + q) * 3 * nt;
-            for (int m0 = 0; m0 <= k0; ++m0)
-                for (int m1 = 0; m1 <= k1; ++m1)
-                    for (int m2 = 0; m2 <= k2; ++m2) {
-                        const double f = pw[q][0][k0 - m0] * pw[q][1][k1 - m1] * pw[q][2][k2 - m2];
-                        const int s = mpos(m0, m1, m2);
-                        for (int d = 0; d < 3; ++d) acc[d] += Mc[d * nt + s] * f;
-                    }
-        }
-        for (int d = 0; d < 3; ++d) par.M[(int64_t(cell) * 3 + d) * nt + t] = acc[d];
+    for (int j = 0; j < 4; ++j) {
+        const int t = threadIdx.x + 256 * j;
+        if (t >= nt) break;
+        for (int d = 0; d < 3; ++d) par.M[(int64_t(cell) * 3 + d) * nt + t] = acc[j][d];
     }
 }
 
@@ -666,13 +714,17 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
     }
 }
 
-// Children at level l += shifted expansion of their parents at level l - 1.
+// Children at level l += shifted expansion of their parents at level l - 1 (one axis at a time
+// in LDS, as k_fmm_m2m).
 __global__ __launch_bounds__(256) void k_fmm_l2l(FmmLevel chi, FmmLevel par, const int32_t* __restrict__ count, int l,
                                                  const double* __restrict__ box, int p,
                                                  const uint32_t* __restrict__ terms) {
     const int cell = blockIdx.x;
     if (cell >= *count) return;
     const int nt = nterms(p);
+    extern __shared__ double sShift[];
+    double* bufA = sShift;
+    double* bufB = sShift + 3 * nt;
     __shared__ double pw[3][kMaxOrder + 1];
     const int pa = chi.parent[cell];
     if (threadIdx.x < 3) {
@@ -688,21 +740,17 @@ __global__ __launch_bounds__(256) void k_fmm_l2l(FmmLevel chi, FmmLevel par, con
             pw[d][i] = v;
         }
     }
-    __syncthreads();
     const double* Lp = par.L + int64_t(pa) * 3 * nt;
+    for (int i = threadIdx.x; i < 3 * nt; i += 256) bufA[i] = Lp[i];
+    __syncthreads();
+    shift_axis<true>(bufA, bufB, pw[0], 0, p, nt, terms);
+    __syncthreads();
+    shift_axis<true>(bufB, bufA, pw[1], 1, p, nt, terms);
+    __syncthreads();
     for (int t = threadIdx.x; t < nt; t += 256) {
-        const uint32_t k = terms[t];
-        const int n0 = int(k & 0xff), n1 = int((k >> 8) & 0xff), n2 = int(k >> 16);
-        const int P = p - (n0 + n1 + n2);
-        double acc[3] = {0.0, 0.0, 0.0};
-        for (int q0 = 0; q0 <= P; ++q0)
-            for (int q1 = 0; q1 <= P - q0; ++q1)
-                for (int q2 = 0; q2 <= P - q0 - q1; ++q2) {
-                    const double f = pw[0][q0] * pw[1][q1] * pw[2][q2];
-                    const int s = mpos(n0 + q0, n1 + q1, n2 + q2);
-                    for (int d = 0; d < 3; ++d) acc[d] += Lp[d * nt + s] * f;
-                }
-        for (int d = 0; d < 3; ++d) chi.L[(int64_t(cell) * 3 + d) * nt + t] += acc[d];
+        double o[3];
+        shift_axis_term<true>(bufA, pw[2], 2, p, nt, terms[t], o);
+        for (int d = 0; d < 3; ++d) chi.L[(int64_t(cell) * 3 + d) * nt + t] += o[d];
     }
 }
 
@@ -1215,6 +1263,7 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     int m2l_groups = int((60 * 1024) / m2l_grid);
     m2l_groups = m2l_groups < 1 ? 1 : (m2l_groups > 4 ? 4 : m2l_groups);
     const size_t m2l_lds = size_t(m2l_groups) * m2l_grid;
+    const size_t shift_lds = size_t(6 * nterms(p)) * sizeof(double);  // M2M and L2L: two 3 nt buffers
     if (level >= 2) {
         hipLaunchKernelGGL(k_fmm_dtab, dim3(kOffsets), dim3(256), 0, st, p, terms, dtab);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1222,8 +1271,8 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
                            counts + level, box, level, p, terms);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         for (int l = level - 1; l >= 2; --l) {
-            hipLaunchKernelGGL(k_fmm_m2m, dim3(unsigned(y.cap[l])), dim3(256), 0, st, lv[l], lv[l + 1], counts + l, l,
-                               box, p, terms);
+            hipLaunchKernelGGL(k_fmm_m2m, dim3(unsigned(y.cap[l])), dim3(256), shift_lds, st, lv[l], lv[l + 1],
+                               counts + l, l, box, p, terms);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         for (int l = 2; l <= level; ++l) {
@@ -1231,7 +1280,7 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
                                counts + l, l, box, p, terms, dtab);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if (l >= 3) {
-                hipLaunchKernelGGL(k_fmm_l2l, dim3(unsigned(y.cap[l])), dim3(256), 0, st, lv[l], lv[l - 1],
+                hipLaunchKernelGGL(k_fmm_l2l, dim3(unsigned(y.cap[l])), dim3(256), shift_lds, st, lv[l], lv[l - 1],
                                    counts + l, l, box, p, terms);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
             }
