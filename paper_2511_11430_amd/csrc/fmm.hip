@@ -963,7 +963,7 @@ __device__ __forceinline__ void near_pair(T xi, T yi, T zi, T gxi, T gyi, T gzi,
 // farther apart than the subtile's largest core cut (rho_far sigma).  The epilogue adds the
 // far field (if any) and writes in the caller's order.
 template <typename T, bool CLASSICAL, bool GRAD>
-__global__ __launch_bounds__(256) void k_fmm_near(NearArgs a) {
+__global__ __launch_bounds__(256, GRAD ? 4 : 1) void k_fmm_near(NearArgs a) {
     constexpr bool kComp = std::is_same<T, float>::value;
     constexpr int NA = GRAD ? 21 : 9;
     const int item = blockIdx.x;
