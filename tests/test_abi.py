@@ -393,3 +393,14 @@ def test_fmm_validation():
     assert f(*args(wb=16)) == WORKSPACE
     assert f(*args(w=None)) == WORKSPACE
     assert f(*args(n=0, ld=0, ldo=0, w=None, wb=0)) == OK
+
+
+def test_tuning_cache_matches_the_kernel_sources():
+    """The shipped tuning cache is applied only when its hash matches the pair-kernel sources;
+    a stale cache would silently fall back to the default shapes."""
+    import json
+    from paper_2511_11430_amd import tune
+    with open(tune.DEFAULT_CACHE) as f:
+        cache = json.load(f)
+    assert cache["source_hash"] == tune.source_hash()
+    assert {p["batched"] for p in cache["plans"]} == {0, 1}
