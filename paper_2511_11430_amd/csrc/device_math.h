@@ -245,4 +245,25 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
     e = (a - (s - bb)) + (b - bb);
 }
 
+// The kernels call these.  The FP64 versions are calls, not inlined: their series and erf hold
+// many FP64 constants (no FP64 literal operands), which inlined would raise the register count
+// of the whole pair loop that contains this rarely taken branch (FP64 transposed pair kernel:
+// 249 -> 124 VGPRs, two -> four wavefronts per SIMD).
+__device__ __forceinline__ void core_weights_call(float s2, float isig, float isig2, float& G, float& Hn) {
+    core_weights<float>(s2, isig, isig2, G, Hn, G, Hn);
+}
+static __device__ __attribute__((noinline, unused)) void core_weights_call(double s2, double isig, double isig2, double& G,
+                                                                   double& Hn) {
+    core_weights<double>(s2, isig, isig2, G, Hn, G, Hn);
+}
+__device__ __forceinline__ void core_weights3_call(float s2, float is, float is2, float Gf, float Hf, float Kf,
+                                                   float& G, float& Hn, float& Kn) {
+    core_weights3<float>(s2, is, is2, Gf, Hf, Kf, G, Hn, Kn);
+}
+static __device__ __attribute__((noinline, unused)) void core_weights3_call(double s2, double is, double is2, double Gf,
+                                                                    double Hf, double Kf, double& G, double& Hn,
+                                                                    double& Kn) {
+    core_weights3<double>(s2, is, is2, Gf, Hf, Kf, G, Hn, Kn);
+}
+
 }  // namespace vpm
