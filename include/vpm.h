@@ -314,8 +314,9 @@ vpm_status vpm_aic_assemble(int64_t n, const double* c00, const double* c01, con
 /* vpm_lu_factor — in-place LU factorisation with partial pivoting of the FP64 matrix
  * a [n][lda] (row-major): P a = L U, L unit lower (below the diagonal), U upper.  ipiv
  * (device int32[n]): row swapped with row k at step k.  info (device int32): 0, or k + 1 for
- * the first column k without a nonzero pivot (the factorisation continues past it).  One
- * workgroup; meant for the blade systems (a few hundred to a few thousand panels). */
+ * the first column k without a nonzero pivot (the factorisation continues past it).  Meant
+ * for the blade systems (a few hundred to a few thousand panels): blocked in panels of 16
+ * columns up to n = 1024 (several launches on the stream), one workgroup beyond. */
 vpm_status vpm_lu_factor(int64_t n, double* a, int64_t lda, int32_t* ipiv, int32_t* info, void* stream);
 
 /* vpm_lu_solve — solves a x = b with the factors of vpm_lu_factor; b (device double[n]) is

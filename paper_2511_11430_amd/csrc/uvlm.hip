@@ -6,10 +6,11 @@
 //    closed path c00 -> c01 -> c11 -> c10 with unit circulation; each edge is the finite
 //    straight segment law (r1 x r2) r0 . (r1/|r1| - r2/|r2|) / (4 pi |r0|^2 (d^2n + rc^2n)^(1/n))
 //    with the Vatistas core, d^2 = |r1 x r2|^2 / |r0|^2.  Entry = n_i . u_ring_j(c_i).
-//  - k_lu_factor / k_lu_solve: dense LU with partial pivoting and the two triangular solves in
-//    one workgroup of 1024 lanes (the systems are a few hundred to a few thousand panels;
-//    the matrix of 512 panels is 2 MB and stays in L2).  Pivot = largest |entry| of the
-//    column, the first such row on ties.
+//  - k_lu_panel / k_lu_swap / k_lu_trsm / k_lu_gemm: dense LU with partial pivoting, blocked
+//    in panels of 16 columns for n <= 1024 (a panel in one workgroup with a row per lane, the
+//    rest on many workgroups); k_lu_factor: the same column by column in one workgroup for
+//    larger n; k_lu_solve: the two triangular solves in one workgroup.  Pivot = largest |entry|
+//    of the column, the first such row on ties.
 //  - k_wake_shed: Kutta condition and the strengths of the newest wake row's lines (Eq. 7):
 //    trailed line at span station c: Gamma_te(c-1) - Gamma_te(c) (0 outside the blade), shed
 //    line of strip c: Gamma_te,prev(c) - Gamma_te(c); the previous values are then replaced.
@@ -168,6 +169,148 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_factor(int64_t n, double* A, 
         __syncthreads();
     }
     if (t == 0) *info = first_zero;
+}
+
+// ---- blocked LU for n <= kLuThreads: panels of kPanel columns.  Each panel is factored in one
+// workgroup with its rows in registers (one row per lane); the row exchanges are then applied
+// to the other columns, the panel's block row of U is solved, and the trailing matrix takes the
+// panel's rank-kPanel update on many workgroups.  Every entry receives the same operations in
+// the same order as in the unblocked factorisation above (a_rc -= l_rk u_kc for k = 0, 1, ...,
+// a_rk /= u_kk), and the pivots are chosen the same way, so the factors are the same.
+constexpr int kPanel = 16;
+
+// Panel [j0, j0 + nb): rows [j0, n), row j0 + t in lane t.
+__global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, int64_t lda, int64_t j0, int nb,
+                                                         int32_t* ipiv, int32_t* info) {
+    __shared__ double sv[kLuThreads / 64];
+    __shared__ int64_t si[kLuThreads / 64];
+    __shared__ double srow[2][kPanel];
+    const int t = threadIdx.x;
+    const int64_t r = j0 + t;
+    const bool has = r < n;
+    if (j0 == 0 && t == 0) *info = 0;
+    double p[kPanel];
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) p[j] = (has && j < nb) ? A[r * lda + j0 + j] : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < kPanel; ++cc) {
+        if (cc < nb) {  // uniform
+            double v = (has && t >= cc) ? fabs(p[cc]) : -1.0;
+            int64_t idx = t;
+            block_argmax(v, idx, sv, si);
+            if (t == 0) ipiv[j0 + cc] = int32_t(j0 + idx);
+            if (v == 0.0) {  // singular column: record the first one, leave the column as is
+                if (t == 0 && *info == 0) *info = int32_t(j0 + cc + 1);
+            } else {
+                if (idx != cc) {  // exchange the panel parts of rows cc and idx
+                    if (t == cc || t == idx) {
+#pragma unroll
+                        for (int j = 0; j < kPanel; ++j) srow[t == cc ? 0 : 1][j] = p[j];
+                    }
+                    __syncthreads();
+                    if (t == cc || t == idx) {
+#pragma unroll
+                        for (int j = 0; j < kPanel; ++j) p[j] = srow[t == cc ? 1 : 0][j];
+                    }
+                    __syncthreads();
+                }
+                if (t == cc) {
+#pragma unroll
+                    for (int j = 0; j < kPanel; ++j) srow[0][j] = p[j];
+                }
+                __syncthreads();
+                if (has && t > cc) {
+                    p[cc] /= srow[0][cc];
+#pragma unroll
+                    for (int j = cc + 1; j < kPanel; ++j)
+                        if (j < nb) p[j] -= p[cc] * srow[0][j];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (has) {
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j)
+            if (j < nb) A[r * lda + j0 + j] = p[j];
+    }
+}
+
+// The panel's row exchanges, in order, on the columns outside the panel (one lane per column).
+__global__ __launch_bounds__(256) void k_lu_swap(int64_t n, double* A, int64_t lda, int64_t j0, int nb,
+                                                 const int32_t* ipiv) {
+    const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= n || (c >= j0 && c < j0 + nb)) return;
+    for (int cc = 0; cc < nb; ++cc) {
+        const int64_t k = j0 + cc, q = ipiv[k];
+        if (q != k) {
+            const double x = A[k * lda + c];
+            A[k * lda + c] = A[q * lda + c];
+            A[q * lda + c] = x;
+        }
+    }
+}
+
+// Block row of U right of the panel: forward substitution with the panel's unit lower block
+// (one lane per column).
+__global__ __launch_bounds__(256) void k_lu_trsm(int64_t n, double* A, int64_t lda, int64_t j0, int nb) {
+    __shared__ double sl[kPanel][kPanel];
+    for (int e = threadIdx.x; e < nb * nb; e += 256) sl[e / nb][e % nb] = A[(j0 + e / nb) * lda + j0 + e % nb];
+    __syncthreads();
+    const int64_t c = j0 + nb + int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= n) return;
+    double x[kPanel];
+#pragma unroll
+    for (int i = 0; i < kPanel; ++i) x[i] = i < nb ? A[(j0 + i) * lda + c] : 0.0;
+#pragma unroll
+    for (int i = 1; i < kPanel; ++i) {
+        if (i < nb) {
+#pragma unroll
+            for (int k = 0; k < i; ++k) x[i] -= sl[i][k] * x[k];
+        }
+    }
+#pragma unroll
+    for (int i = 1; i < kPanel; ++i)
+        if (i < nb) A[(j0 + i) * lda + c] = x[i];
+}
+
+// Trailing update a_rc -= sum_k l_rk u_kc (k over the panel, in order), r, c >= j0 + nb:
+// 64 x 64 tiles, 4 x 4 entries per lane, the panel's L and U parts staged in LDS.
+__global__ __launch_bounds__(256) void k_lu_gemm(int64_t n, double* A, int64_t lda, int64_t j0, int nb) {
+    __shared__ double sL[64][kPanel + 1];
+    __shared__ double sU[kPanel][64];
+    const int64_t b0 = j0 + nb;
+    const int64_t r0 = b0 + int64_t(blockIdx.y) * 64, c0 = b0 + int64_t(blockIdx.x) * 64;
+    for (int e = threadIdx.x; e < 64 * kPanel; e += 256) {
+        const int i = e / kPanel, k = e % kPanel;
+        const int64_t r = r0 + i;
+        sL[i][k] = (r < n && k < nb) ? A[r * lda + j0 + k] : 0.0;
+        const int kk = e / 64, j = e % 64;
+        const int64_t c = c0 + j;
+        sU[kk][j] = (c < n && kk < nb) ? A[(j0 + kk) * lda + c] : 0.0;
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+    double acc[4][4];
+    bool ok[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t r = r0 + ty + 16 * a, c = c0 + tx + 16 * b;
+            ok[a][b] = r < n && c < n;
+            acc[a][b] = ok[a][b] ? A[r * lda + c] : 0.0;
+        }
+    for (int k = 0; k < nb; ++k)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] -= sL[ty + 16 * a][k] * sU[k][tx + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (ok[a][b]) A[(r0 + ty + 16 * a) * lda + c0 + tx + 16 * b] = acc[a][b];
 }
 
 __global__ __launch_bounds__(kLuThreads) void k_lu_solve(int64_t n, const double* LU, int64_t lda,
@@ -395,8 +538,29 @@ hipError_t launch_aic(int64_t n, const double* c00, const double* c01, const dou
 }
 
 hipError_t launch_lu_factor(int64_t n, double* A, int64_t lda, int32_t* ipiv, int32_t* info, hipStream_t st) {
-    hipLaunchKernelGGL(k_lu_factor, dim3(1), dim3(kLuThreads), 0, st, n, A, lda, ipiv, info);
-    return hipGetLastError();
+    if (n > kLuThreads) {  // one workgroup, column by column
+        hipLaunchKernelGGL(k_lu_factor, dim3(1), dim3(kLuThreads), 0, st, n, A, lda, ipiv, info);
+        return hipGetLastError();
+    }
+    hipError_t e;
+    for (int64_t j0 = 0; j0 < n; j0 += kPanel) {
+        const int nb = int(n - j0 < kPanel ? n - j0 : kPanel);
+        hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(kLuThreads), 0, st, n, A, lda, j0, nb, ipiv, info);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (n > nb) {
+            hipLaunchKernelGGL(k_lu_swap, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n, A, lda, j0, nb, ipiv);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        const int64_t m = n - j0 - nb;
+        if (m > 0) {
+            hipLaunchKernelGGL(k_lu_trsm, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, n, A, lda, j0, nb);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            const unsigned tiles = unsigned((m + 63) / 64);
+            hipLaunchKernelGGL(k_lu_gemm, dim3(tiles, tiles), dim3(256), 0, st, n, A, lda, j0, nb);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_lu_solve(int64_t n, const double* LU, int64_t lda, const int32_t* ipiv, double* b,

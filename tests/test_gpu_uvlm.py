@@ -46,7 +46,7 @@ def test_aic_full_blade_lattice(gpu):
     assert rel_l2(A, Ao) <= 1e-13
 
 
-@pytest.mark.parametrize("n", [1, 7, 300, 1100])
+@pytest.mark.parametrize("n", [1, 7, 16, 17, 33, 300, 512, 1024, 1025, 1100])
 def test_lu_solve_matches_library_solve(n, gpu):
     rng = np.random.default_rng(n)
     M = rng.normal(size=(n, n)) + n ** 0.5 * np.eye(n) * rng.choice([-1, 1], size=n)
