@@ -9,7 +9,8 @@
 //  - k_lu_panel / k_lu_swap / k_lu_trsm / k_lu_gemm: dense LU with partial pivoting, blocked
 //    in panels of 16 columns for n <= 1024 (a panel in one workgroup with a row per lane, the
 //    rest on many workgroups); k_lu_factor: the same column by column in one workgroup for
-//    larger n; k_lu_solve: the two triangular solves in one workgroup.  Pivot = largest |entry|
+//    larger n; k_lu_solve_blocked / k_lu_solve: the two triangular solves in one workgroup (in
+//    blocks of 64 rows for n <= 1024).  Pivot = largest |entry|
 //    of the column, the first such row on ties.
 //  - k_wake_shed: Kutta condition and the strengths of the newest wake row's lines (Eq. 7):
 //    trailed line at span station c: Gamma_te(c-1) - Gamma_te(c) (0 outside the blade), shed
@@ -118,7 +119,8 @@ __device__ __forceinline__ void block_argmax(double& v, int64_t& idx, double* sv
     __syncthreads();
     v = sv[0];
     idx = si[0];
-    for (int k = 1; k < kLuThreads / 64; ++k) {
+    const int nw = int(blockDim.x) >> 6;
+    for (int k = 1; k < nw; ++k) {
         if (sv[k] > v || (sv[k] == v && si[k] < idx)) {
             v = sv[k];
             idx = si[k];
@@ -179,7 +181,8 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_factor(int64_t n, double* A, 
 // a_rk /= u_kk), and the pivots are chosen the same way, so the factors are the same.
 constexpr int kPanel = 16;
 
-// Panel [j0, j0 + nb): rows [j0, n), row j0 + t in lane t.
+// Panel [j0, j0 + nb): rows [j0, n), row j0 + t in lane t (the workgroup has as many
+// wavefronts as the rows need).
 __global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, int64_t lda, int64_t j0, int nb,
                                                          int32_t* ipiv, int32_t* info) {
     __shared__ double sv[kLuThreads / 64];
@@ -339,6 +342,76 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_solve(int64_t n, const double
         for (int64_t r = t; r < k; r += kLuThreads) b[r] -= LU[r * lda + k] * xk;
         __syncthreads();
     }
+}
+
+// The two triangular solves for n <= kLuThreads, b in LDS, in blocks of 64 rows: one
+// wavefront solves a diagonal block (staged in LDS) with shuffles, then the lanes update the
+// remaining rows with that block's columns.  Every entry receives the same operations in the
+// same order as in k_lu_solve (forward: k ascending; backward: k descending, then the division).
+__global__ __launch_bounds__(kLuThreads) void k_lu_solve_blocked(int64_t n, const double* LU, int64_t lda,
+                                                                 const int32_t* ipiv, double* b) {
+    __shared__ double sb[kLuThreads];
+    __shared__ double sd[64][65];
+    const int t = threadIdx.x, lane = t & 63;
+    if (t < n) sb[t] = b[t];
+    __syncthreads();
+    if (t == 0)
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t p = ipiv[k];
+            if (p != k && p >= 0 && p < n) {
+                const double x = sb[k];
+                sb[k] = sb[p];
+                sb[p] = x;
+            }
+        }
+    __syncthreads();
+    // L y = P b, unit diagonal
+    for (int64_t kb = 0; kb < n; kb += 64) {
+        const int nbk = int(n - kb < 64 ? n - kb : 64);
+        for (int e = t; e < nbk * nbk; e += kLuThreads) sd[e / nbk][e % nbk] = LU[(kb + e / nbk) * lda + kb + e % nbk];
+        __syncthreads();
+        if (t < 64) {
+            double y = lane < nbk ? sb[kb + lane] : 0.0;
+            for (int k = 0; k < nbk; ++k) {
+                const double yk = __shfl(y, k, 64);
+                if (lane > k && lane < nbk) y -= sd[lane][k] * yk;
+            }
+            if (lane < nbk) sb[kb + lane] = y;
+        }
+        __syncthreads();
+        const int64_t r = kb + nbk + t;
+        if (r < n) {
+            double v = sb[r];
+            for (int k = 0; k < nbk; ++k) v -= LU[r * lda + kb + k] * sb[kb + k];
+            sb[r] = v;
+        }
+        __syncthreads();
+    }
+    // U x = y
+    const int64_t nblk = (n + 63) / 64;
+    for (int64_t bi = nblk - 1; bi >= 0; --bi) {
+        const int64_t kb = bi * 64;
+        const int nbk = int(n - kb < 64 ? n - kb : 64);
+        for (int e = t; e < nbk * nbk; e += kLuThreads) sd[e / nbk][e % nbk] = LU[(kb + e / nbk) * lda + kb + e % nbk];
+        __syncthreads();
+        if (t < 64) {
+            double y = lane < nbk ? sb[kb + lane] : 0.0;
+            for (int k = nbk - 1; k >= 0; --k) {
+                if (lane == k) y /= sd[k][k];
+                const double xk = __shfl(y, k, 64);
+                if (lane < k) y -= sd[lane][k] * xk;
+            }
+            if (lane < nbk) sb[kb + lane] = y;
+        }
+        __syncthreads();
+        if (t < kb) {
+            double v = sb[t];
+            for (int k = nbk - 1; k >= 0; --k) v -= LU[int64_t(t) * lda + kb + k] * sb[kb + k];
+            sb[t] = v;
+        }
+        __syncthreads();
+    }
+    if (t < n) b[t] = sb[t];
 }
 
 template <typename T>
@@ -545,7 +618,8 @@ hipError_t launch_lu_factor(int64_t n, double* A, int64_t lda, int32_t* ipiv, in
     hipError_t e;
     for (int64_t j0 = 0; j0 < n; j0 += kPanel) {
         const int nb = int(n - j0 < kPanel ? n - j0 : kPanel);
-        hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(kLuThreads), 0, st, n, A, lda, j0, nb, ipiv, info);
+        const unsigned lanes = unsigned((n - j0 + 63) / 64 * 64);
+        hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(lanes), 0, st, n, A, lda, j0, nb, ipiv, info);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (n > nb) {
             hipLaunchKernelGGL(k_lu_swap, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n, A, lda, j0, nb, ipiv);
@@ -565,7 +639,10 @@ hipError_t launch_lu_factor(int64_t n, double* A, int64_t lda, int32_t* ipiv, in
 
 hipError_t launch_lu_solve(int64_t n, const double* LU, int64_t lda, const int32_t* ipiv, double* b,
                            hipStream_t st) {
-    hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(kLuThreads), 0, st, n, LU, lda, ipiv, b);
+    if (n <= kLuThreads)
+        hipLaunchKernelGGL(k_lu_solve_blocked, dim3(1), dim3(kLuThreads), 0, st, n, LU, lda, ipiv, b);
+    else
+        hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(kLuThreads), 0, st, n, LU, lda, ipiv, b);
     return hipGetLastError();
 }
 
