@@ -156,6 +156,80 @@ __global__ __launch_bounds__(WG) void k_segments(SegArgs a) {
     }
 }
 
+// Few targets (collocation and lattice points): one wavefront per target, its lanes take the
+// segments in turn (segment j in lane j mod 64, read straight from memory), each lane sums in
+// FP64, and the lanes' sums are added by a fixed butterfly.  The per-pair arithmetic is that of
+// k_segments; the segment set-up is repeated per target, which costs nothing at these sizes but
+// fills the GPU where k_segments would run a handful of workgroups.
+constexpr int64_t kSegSmallTargets = 8192;
+
+template <typename T, int VN>
+__global__ __launch_bounds__(256) void k_segments_few(SegArgs a) {
+    const T* __restrict__ A = static_cast<const T*>(a.a);
+    const T* __restrict__ B = static_cast<const T*>(a.b);
+    const T* __restrict__ Gs = static_cast<const T*>(a.gam);
+    const T* __restrict__ X = static_cast<const T*>(a.xt);
+    const int lane = threadIdx.x & 63;
+    const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t >= a.n_tgt) return;  // whole wavefronts
+    const T rc2 = T(a.rc * a.rc);
+    const T n_f = T(a.vn);
+    const T inv_n = T(1.0 / a.vn);
+    T rc2n;
+    if constexpr (VN == 0) rc2n = T(0);
+    else if constexpr (VN == 1) rc2n = rc2;
+    else if constexpr (VN == 2) rc2n = rc2 * rc2;
+    else rc2n = T(pow(double(rc2), double(a.vn)));
+    const T P0 = X[t], P1 = X[a.ldt + t], P2 = X[2 * a.ldt + t];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = lane; j < a.n_seg; j += 64) {
+        const T ax = A[j], ay = A[a.ld_seg + j], az = A[2 * a.ld_seg + j];
+        const T r0x = B[j] - ax, r0y = B[a.ld_seg + j] - ay, r0z = B[2 * a.ld_seg + j] - az;
+        const T L02 = r0x * r0x + r0y * r0y + r0z * r0z;
+        const T L0 = dsqrt(L02);
+        const T eps = T(1e-12) * (L0 > T(1) ? L0 : T(1));
+        const bool dead = L0 < eps;
+        T coef = T(kInv4PiD) * Gs[j];
+        if (VN != 0) coef = coef / L02;
+        if (dead) coef = T(0);
+        const T qw = dead ? T(1) : L02;
+        const T eps2 = eps * eps;
+        const T inv_l02 = T(1) / qw;
+        const T r1x = P0 - ax, r1y = P1 - ay, r1z = P2 - az;
+        const T r2x = r1x - r0x, r2y = r1y - r0y, r2z = r1z - r0z;
+        const T cx = r0y * r1z - r0z * r1y;
+        const T cy = r0z * r1x - r0x * r1z;
+        const T cz = r0x * r1y - r0y * r1x;
+        const T c2 = cx * cx + cy * cy + cz * cz;
+        const T l1s = r1x * r1x + r1y * r1y + r1z * r1z;
+        const T l2s = r2x * r2x + r2y * r2y + r2z * r2z;
+        const T d1 = r0x * r1x + r0y * r1y + r0z * r1z;
+        const T d2 = d1 - qw;
+        const T D = d1 * rsqrt_fast(l1s) - d2 * rsqrt_fast(l2s);
+        T f;
+        if constexpr (VN == 0) {
+            f = (c2 > T(0)) ? coef * D / c2 : T(0);
+        } else {
+            f = coef * D * core_factor<T, VN>(c2 * inv_l02, rc2n, inv_n, n_f);
+        }
+        f = (l1s < eps2 || l2s < eps2) ? T(0) : f;
+        acc[0] += double(f * cx);
+        acc[1] += double(f * cy);
+        acc[2] += double(f * cz);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    if (lane == 0) {
+        T* __restrict__ U = static_cast<T*>(a.u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T* dst = U + c * a.ldo + t;
+            *dst = a.accumulate ? T(double(*dst) + acc[c]) : T(acc[c]);
+        }
+    }
+}
+
 // Gradient form: velocity and its gradient J = du/dP at the targets, and from J the
 // stretching of target particles of strength gamma_t.  With u = f c, c = r0 x r1,
 // f = coef D K(d^2), D = r0 . (r1/|r1| - r2/|r2|), d^2 = |c|^2 / |r0|^2:
@@ -591,8 +665,24 @@ hipError_t launch_segments_vjp(int dtype, const SegArgs& a, hipStream_t st) {
     return launch_vjp_t<float, 256>(a, st);
 }
 
+template <typename T>
+hipError_t launch_few_t(const SegArgs& a, hipStream_t st) {
+    const int grid = int((a.n_tgt + 3) / 4);
+    if (a.rc == 0.0)
+        hipLaunchKernelGGL((k_segments_few<T, 0>), dim3(grid), dim3(256), 0, st, a);
+    else if (a.vn == 1)
+        hipLaunchKernelGGL((k_segments_few<T, 1>), dim3(grid), dim3(256), 0, st, a);
+    else if (a.vn == 2)
+        hipLaunchKernelGGL((k_segments_few<T, 2>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_segments_few<T, 3>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_segments(int dtype, const SegArgs& a, hipStream_t st) {
     if (a.n_tgt == 0) return hipSuccess;
+    if (a.n_tgt <= kSegSmallTargets)
+        return dtype == kDtypeF64 ? launch_few_t<double>(a, st) : launch_few_t<float>(a, st);
     if (dtype == kDtypeF64) return launch_t<double, 1, 256>(a, st);
     return launch_t<float, 2, 256>(a, st);
 }
