@@ -205,23 +205,27 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, i
             if (v == 0.0) {  // singular column: record the first one, leave the column as is
                 if (t == 0 && *info == 0) *info = int32_t(j0 + cc + 1);
             } else {
-                if (idx != cc) {  // exchange the panel parts of rows cc and idx
-                    if (t == cc || t == idx) {
-#pragma unroll
-                        for (int j = 0; j < kPanel; ++j) srow[t == cc ? 0 : 1][j] = p[j];
-                    }
-                    __syncthreads();
-                    if (t == cc || t == idx) {
-#pragma unroll
-                        for (int j = 0; j < kPanel; ++j) p[j] = srow[t == cc ? 1 : 0][j];
-                    }
-                    __syncthreads();
-                }
-                if (t == cc) {
+                // rows cc and idx trade places: row idx becomes the pivot row (srow[0]), row cc
+                // moves down (srow[1]); one barrier.  srow is next written after the two
+                // barriers of the next column's arg-max, when every lane is done reading it.
+                if (t == idx) {
 #pragma unroll
                     for (int j = 0; j < kPanel; ++j) srow[0][j] = p[j];
                 }
+                if (t == cc && idx != cc) {
+#pragma unroll
+                    for (int j = 0; j < kPanel; ++j) srow[1][j] = p[j];
+                }
                 __syncthreads();
+                if (idx != cc) {
+                    if (t == cc) {
+#pragma unroll
+                        for (int j = 0; j < kPanel; ++j) p[j] = srow[0][j];
+                    } else if (t == idx) {
+#pragma unroll
+                        for (int j = 0; j < kPanel; ++j) p[j] = srow[1][j];
+                    }
+                }
                 if (has && t > cc) {
                     p[cc] /= srow[0][cc];
 #pragma unroll
@@ -229,7 +233,6 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, i
                         if (j < nb) p[j] -= p[cc] * srow[0][j];
                 }
             }
-            __syncthreads();
         }
     }
     if (has) {
