@@ -924,13 +924,22 @@ __device__ __forceinline__ void near_pair(T xi, T yi, T zi, T gxi, T gyi, T gzi,
         acc[12] += hz * rx;
         acc[13] += hz * ry;
         acc[14] += hz * rz;
-        if (MAYCORE && core) {
-            acc[15] += G * gxj;
-            acc[16] += G * gyj;
-            acc[17] += G * gzj;
-            acc[18] += G * (gyi * gzj - gzi * gyj);
-            acc[19] += G * (gzi * gxj - gxi * gzj);
-            acc[20] += G * (gxi * gyj - gyi * gxj);
+        if constexpr (MAYCORE) {
+            // A of the in-core pairs and A outside the cores go to different sums; the weights
+            // are selected rather than the destinations (a selected destination becomes an
+            // indexed array in scratch memory)
+            const T Gc = core ? G : T(0), Go = core ? T(0) : G;
+            acc[3] += Go * gxj;
+            acc[4] += Go * gyj;
+            acc[5] += Go * gzj;
+            acc[15] += Gc * gxj;
+            acc[16] += Gc * gyj;
+            acc[17] += Gc * gzj;
+            if (core) {
+                acc[18] += G * (gyi * gzj - gzi * gyj);
+                acc[19] += G * (gzi * gxj - gxi * gzj);
+                acc[20] += G * (gxi * gyj - gyi * gxj);
+            }
         } else {
             acc[3] += G * gxj;
             acc[4] += G * gyj;
@@ -1012,6 +1021,7 @@ __global__ __launch_bounds__(256, GRAD ? 4 : 1) void k_fmm_near(NearArgs a) {
         wave_box(pl, pl, T(0), tlo, thi, tcut);
     }
     T acc[NA], hi[NA], lo[NA];
+#pragma unroll
     for (int c = 0; c < NA; ++c) acc[c] = hi[c] = lo[c] = T(0);
     for (int nb = 0; nb < 27; ++nb) {
         const int lo_j = nb_lo[nb], hi_j = nb_hi[nb];
@@ -1079,6 +1089,7 @@ __global__ __launch_bounds__(256, GRAD ? 4 : 1) void k_fmm_near(NearArgs a) {
                 }
             }
             if constexpr (kComp) {
+#pragma unroll
                 for (int c = 0; c < NA; ++c) {
                     T s, e;
                     two_sum(hi[c], acc[c], s, e);
@@ -1091,6 +1102,7 @@ __global__ __launch_bounds__(256, GRAD ? 4 : 1) void k_fmm_near(NearArgs a) {
     }
     if (!valid) return;
     double S[NA];
+#pragma unroll
     for (int c = 0; c < NA; ++c) S[c] = kComp ? double(hi[c]) + double(lo[c]) : double(acc[c]);
     const double Gi[3] = {double(gxi), double(gyi), double(gzi)};
     double u[3] = {S[0] * kInv4Pi, S[1] * kInv4Pi, S[2] * kInv4Pi};
