@@ -75,8 +75,8 @@ def main():
                     help="also run one plain 256 MiB device copy (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding over GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

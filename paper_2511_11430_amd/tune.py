@@ -102,7 +102,7 @@ def tune(out=DEFAULT_CACHE, quick=False, log=print):
 
 
 def apply_cache(path=None):
-    """Apply a tuning cache to the loaded library if it matches this build; returns the
+    """Apply a tuning cache to the loaded library if it matches the kernel sources; returns the
     number of plans applied (0 if none or stale)."""
     from . import F32C, _lib
     path = path or os.environ.get("VPM_TUNE_CACHE", DEFAULT_CACHE)
