@@ -178,7 +178,8 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_factor(int64_t n, double* A, 
 // to the other columns, the panel's block row of U is solved, and the trailing matrix takes the
 // panel's rank-kPanel update on many workgroups.  Every entry receives the same operations in
 // the same order as in the unblocked factorisation above (a_rc -= l_rk u_kc for k = 0, 1, ...,
-// a_rk /= u_kk), and the pivots are chosen the same way, so the factors are the same.
+// a_rk /= u_kk), and the pivots are chosen the same way, so the factors agree with the
+// unblocked ones up to how each update is contracted into an FMA.
 constexpr int kPanel = 16;
 
 // Panel [j0, j0 + nb): rows [j0, n), row j0 + t in lane t (the workgroup has as many
