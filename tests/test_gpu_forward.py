@@ -156,6 +156,24 @@ def test_segments(kind, rc, vn, gpu):
 
 
 @pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n_tgt", [1, 65, 8192, 8193])
+def test_segments_on_either_side_of_the_few_target_kernel(kind, n_tgt, gpu):
+    """Up to 8192 targets take a wavefront per target, beyond one lane per target: both
+    against the oracle, accumulating onto a given field."""
+    c = W.config2(n=8193)
+    a, b, gs, x = prepare([c["seg_a"], c["seg_b"], c["seg_gamma"], c["x"]], kind)
+    x = np.ascontiguousarray(x[:, :n_tgt])
+    uo = oracle.segments(a, b, gs, x, 0.02, 2)
+    # a field of the same size to accumulate onto
+    base = (np.random.default_rng(n_tgt).normal(size=(3, n_tgt)) * uo.std()).astype(x.dtype)
+    say(f"segments {kind} n_tgt={n_tgt}")
+    u = dev_(base, kind)
+    vpm.vpm_eval_segments(dev_(a, kind), dev_(b, kind), dev_(gs, kind), dev_(x, kind), 0.02, 2, u_out=u,
+                          accumulate=True)
+    assert rel_l2(host(u), base.astype(np.float64) + uo) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
 def test_segments_full_size_on_particles_and_control_points(kind, gpu):
     c = W.config2()
     a, b, gs, x, y = prepare([c["seg_a"], c["seg_b"], c["seg_gamma"], c["x"], c["ctrl"]], kind)
