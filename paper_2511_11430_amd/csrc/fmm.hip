@@ -53,6 +53,11 @@ constexpr int kMaxLevel = 10;
 constexpr int kNearTile = 256;
 constexpr int kOffsets = 343;  // [-3, 3]^3
 constexpr double kInv4Pi = 0.0795774715459476678844418816862571810;
+// 1/k for the monomial recurrences a^k/k! = (a^(k-1)/(k-1)!) a (1/k) (a multiply, not an FP64
+// division, in the per-particle loops)
+__constant__ double kInvInt[kMaxOrder + 2] = {0.0,      1.0,       1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,
+                                              1.0 / 6,  1.0 / 7,   1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
+                                              1.0 / 12, 1.0 / 13,  1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17};
 
 __host__ __device__ constexpr int nterms(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
@@ -856,11 +861,11 @@ __global__ __launch_bounds__(256) void k_fmm_l2p(NearArgs a, double* __restrict_
                     for (int m = 0; m < 6; ++m)
                         for (int c = 0; c < 3; ++c) hp[m][c] += sL[c][h[m]] * mono;
                 }
-                mono = mono * av[2] / double(n2 + 1);
+                mono = mono * av[2] * kInvInt[n2 + 1];
             }
-            pxy = pxy * av[1] / double(n1 + 1);
+            pxy = pxy * av[1] * kInvInt[n1 + 1];
         }
-        px = px * av[0] / double(n0 + 1);
+        px = px * av[0] * kInvInt[n0 + 1];
     }
     auto H = [&](int e, int b, int c) -> double {
         if (e == b) return hp[e][c];
