@@ -6,7 +6,7 @@
 //    closed path c00 -> c01 -> c11 -> c10 with unit circulation; each edge is the finite
 //    straight segment law (r1 x r2) r0 . (r1/|r1| - r2/|r2|) / (4 pi |r0|^2 (d^2n + rc^2n)^(1/n))
 //    with the Vatistas core, d^2 = |r1 x r2|^2 / |r0|^2.  Entry = n_i . u_ring_j(c_i).
-//  - k_lu_panel / k_lu_swap / k_lu_trsm / k_lu_gemm: dense LU with partial pivoting, blocked
+//  - k_lu_panel / k_lu_swap_trsm / k_lu_gemm: dense LU with partial pivoting, blocked
 //    in panels of 16 columns for n <= 1024 (a panel in one workgroup with a row per lane, the
 //    rest on many workgroups); k_lu_factor: the same column by column in one workgroup for
 //    larger n; k_lu_solve_blocked / k_lu_solve: the two triangular solves in one workgroup (in
@@ -243,9 +243,14 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, i
     }
 }
 
-// The panel's row exchanges, in order, on the columns outside the panel (one lane per column).
-__global__ __launch_bounds__(256) void k_lu_swap(int64_t n, double* A, int64_t lda, int64_t j0, int nb,
-                                                 const int32_t* ipiv) {
+// One lane per column outside the panel: the panel's row exchanges, in order, and for the
+// columns right of the panel the block row of U by forward substitution with the panel's unit
+// lower block (staged in LDS).
+__global__ __launch_bounds__(256) void k_lu_swap_trsm(int64_t n, double* A, int64_t lda, int64_t j0, int nb,
+                                                      const int32_t* ipiv) {
+    __shared__ double sl[kPanel][kPanel];
+    for (int e = threadIdx.x; e < nb * nb; e += 256) sl[e / nb][e % nb] = A[(j0 + e / nb) * lda + j0 + e % nb];
+    __syncthreads();
     const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (c >= n || (c >= j0 && c < j0 + nb)) return;
     for (int cc = 0; cc < nb; ++cc) {
@@ -256,16 +261,7 @@ __global__ __launch_bounds__(256) void k_lu_swap(int64_t n, double* A, int64_t l
             A[q * lda + c] = x;
         }
     }
-}
-
-// Block row of U right of the panel: forward substitution with the panel's unit lower block
-// (one lane per column).
-__global__ __launch_bounds__(256) void k_lu_trsm(int64_t n, double* A, int64_t lda, int64_t j0, int nb) {
-    __shared__ double sl[kPanel][kPanel];
-    for (int e = threadIdx.x; e < nb * nb; e += 256) sl[e / nb][e % nb] = A[(j0 + e / nb) * lda + j0 + e % nb];
-    __syncthreads();
-    const int64_t c = j0 + nb + int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (c >= n) return;
+    if (c < j0) return;
     double x[kPanel];
 #pragma unroll
     for (int i = 0; i < kPanel; ++i) x[i] = i < nb ? A[(j0 + i) * lda + c] : 0.0;
@@ -626,13 +622,12 @@ hipError_t launch_lu_factor(int64_t n, double* A, int64_t lda, int32_t* ipiv, in
         hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(lanes), 0, st, n, A, lda, j0, nb, ipiv, info);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (n > nb) {
-            hipLaunchKernelGGL(k_lu_swap, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n, A, lda, j0, nb, ipiv);
+            hipLaunchKernelGGL(k_lu_swap_trsm, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n, A, lda, j0, nb,
+                               ipiv);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         const int64_t m = n - j0 - nb;
         if (m > 0) {
-            hipLaunchKernelGGL(k_lu_trsm, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, n, A, lda, j0, nb);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
             const unsigned tiles = unsigned((m + 63) / 64);
             hipLaunchKernelGGL(k_lu_gemm, dim3(tiles, tiles), dim3(256), 0, st, n, A, lda, j0, nb);
             if ((e = hipGetLastError()) != hipSuccess) return e;
