@@ -184,12 +184,47 @@ constexpr int kPanel = 16;
 
 // Panel [j0, j0 + nb): rows [j0, n), row j0 + t in lane t (the workgroup has as many
 // wavefronts as the rows need).
+// Unsigned 64-bit maximum over a full wavefront, returned in every lane: row shifts by 1, 2, 4
+// and 8 leave each 16-lane row's maximum in its last lane, the two row broadcasts carry row 0
+// into row 1, row 2 into row 3 and then lane 31 into rows 2 and 3, so lane 63 holds the
+// wavefront's maximum.  Lanes a DPP move does not write keep 0, the identity.  Every lane of the
+// wavefront must be active.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp_umax_step(uint64_t k) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(k)), kCtrl, kRowMask, 0xf, false));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(k >> 32)), kCtrl, kRowMask, 0xf, false));
+    const uint64_t o = (uint64_t(hi) << 32) | lo;
+    return o > k ? o : k;
+}
+
+__device__ __forceinline__ uint64_t wave_umax(uint64_t k) {
+    k = dpp_umax_step<0x111, 0xf>(k);  // row_shr:1
+    k = dpp_umax_step<0x112, 0xf>(k);  // row_shr:2
+    k = dpp_umax_step<0x114, 0xf>(k);  // row_shr:4
+    k = dpp_umax_step<0x118, 0xf>(k);  // row_shr:8
+    k = dpp_umax_step<0x142, 0xa>(k);  // row_bcast:15
+    k = dpp_umax_step<0x143, 0xc>(k);  // row_bcast:31
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(k)), 63));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(k >> 32)), 63));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// One panel of kPanel columns in one workgroup, a row per lane held in registers (rows j0 ..
+// n-1; the launch has whole wavefronts).  Pivot search on the key bits(|a|) + 1 (0 for rows
+// above the diagonal or past n): for non-negative doubles the bit patterns order as the
+// values, so the largest key is the largest magnitude, and the first lane holding it, found by
+// a ballot, is the first row on ties.  Each wavefront posts its candidate row (key, row index
+// and the row's kPanel entries) and lane cc posts row cc, in buffers alternating by column;
+// one barrier, then every wavefront reduces the posted keys the same way (the first wavefront
+// on ties) and reads the pivot row.  A buffer written at column cc is next written at column
+// cc + 2, after the barrier of column cc + 1 that every lane reaches only when done reading it.
 __global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, int64_t lda, int64_t j0, int nb,
                                                          int32_t* ipiv, int32_t* info) {
-    __shared__ double sv[kLuThreads / 64];
-    __shared__ int64_t si[kLuThreads / 64];
-    __shared__ double srow[2][kPanel];
-    const int t = threadIdx.x;
+    constexpr int kWaves = kLuThreads / 64;
+    __shared__ double srow[2][kWaves + 1][kPanel];  // [buffer][wavefront candidates, then row cc]
+    __shared__ uint64_t skey[2][kWaves];
+    __shared__ int sidx[2][kWaves];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = int(blockDim.x) >> 6;
     const int64_t r = j0 + t;
     const bool has = r < n;
     if (j0 == 0 && t == 0) *info = 0;
@@ -199,39 +234,44 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, i
 #pragma unroll
     for (int cc = 0; cc < kPanel; ++cc) {
         if (cc < nb) {  // uniform
-            double v = (has && t >= cc) ? fabs(p[cc]) : -1.0;
-            int64_t idx = t;
-            block_argmax(v, idx, sv, si);
+            const int b = cc & 1;
+            const uint64_t key = (has && t >= cc) ? uint64_t(__double_as_longlong(fabs(p[cc]))) + 1 : 0;
+            const uint64_t wmax = wave_umax(key);
+            const int lead = __ffsll((unsigned long long)__ballot(key == wmax)) - 1;
+            if (lane == lead) {
+                skey[b][w] = wmax;
+                sidx[b][w] = t;
+#pragma unroll
+                for (int j = 0; j < kPanel; ++j) srow[b][w][j] = p[j];
+            }
+            if (t == cc) {
+#pragma unroll
+                for (int j = 0; j < kPanel; ++j) srow[b][kWaves][j] = p[j];
+            }
+            __syncthreads();
+            const uint64_t ck = lane < nw ? skey[b][lane] : 0;
+            const uint64_t gmax = wave_umax(ck);
+            const int ww = __ffsll((unsigned long long)__ballot(lane < nw && ck == gmax)) - 1;
+            const int idx = sidx[b][ww];
             if (t == 0) ipiv[j0 + cc] = int32_t(j0 + idx);
-            if (v == 0.0) {  // singular column: record the first one, leave the column as is
+            if (gmax == 1) {  // singular column: record the first one, leave the column as is
                 if (t == 0 && *info == 0) *info = int32_t(j0 + cc + 1);
             } else {
-                // rows cc and idx trade places: row idx becomes the pivot row (srow[0]), row cc
-                // moves down (srow[1]); one barrier.  srow is next written after the two
-                // barriers of the next column's arg-max, when every lane is done reading it.
-                if (t == idx) {
-#pragma unroll
-                    for (int j = 0; j < kPanel; ++j) srow[0][j] = p[j];
-                }
-                if (t == cc && idx != cc) {
-#pragma unroll
-                    for (int j = 0; j < kPanel; ++j) srow[1][j] = p[j];
-                }
-                __syncthreads();
+                // rows cc and idx trade places
                 if (idx != cc) {
                     if (t == cc) {
 #pragma unroll
-                        for (int j = 0; j < kPanel; ++j) p[j] = srow[0][j];
+                        for (int j = 0; j < kPanel; ++j) p[j] = srow[b][ww][j];
                     } else if (t == idx) {
 #pragma unroll
-                        for (int j = 0; j < kPanel; ++j) p[j] = srow[1][j];
+                        for (int j = 0; j < kPanel; ++j) p[j] = srow[b][kWaves][j];
                     }
                 }
                 if (has && t > cc) {
-                    p[cc] /= srow[0][cc];
+                    p[cc] /= srow[b][ww][cc];
 #pragma unroll
                     for (int j = cc + 1; j < kPanel; ++j)
-                        if (j < nb) p[j] -= p[cc] * srow[0][j];
+                        if (j < nb) p[j] -= p[cc] * srow[b][ww][j];
                 }
             }
         }

@@ -68,6 +68,53 @@ def test_lu_reports_a_singular_column(gpu):
     assert int(info.item()) == 18
 
 
+def _exact_lu_case(n, seed, ties):
+    """A with rows of L U in the order perm, L unit lower with entries in {0, +-1/2, +-1}, U with
+    small integers and a diagonal in {+-1, +-2}: every value elimination forms is a multiple of
+    1/2 far below 2^52, so LU with partial pivoting is exact in FP64 and its factors are L and U
+    themselves.  ties: perm = identity and |l_ik| = 1 for about half the rows below the diagonal,
+    whose magnitude then equals the pivot's (the diagonal row, the first of them, must win);
+    otherwise |l_ik| <= 1/2 and perm is random, so each pivot is unique and sits anywhere."""
+    rng = np.random.default_rng(seed)
+    if ties:
+        Lv = rng.choice([-1.0, -0.5, 0.0, 0.5, 1.0], p=[0.25, 0.15, 0.2, 0.15, 0.25], size=(n, n))
+    else:
+        Lv = rng.choice([-0.5, 0.0, 0.5], size=(n, n))
+    L = np.tril(Lv, -1) + np.eye(n)
+    U = np.triu(rng.integers(-2, 3, size=(n, n)).astype(np.float64), 1) + np.diag(
+        rng.choice([-2.0, -1.0, 1.0, 2.0], size=n))
+    perm = np.arange(n) if ties else rng.permutation(n)
+    A = np.empty((n, n))
+    A[perm] = L @ U
+    # pivot rows by the textbook exchange sequence: row k of L U sits at position perm[k]
+    cur = np.argsort(perm)            # cur[p] = row of L U now at position p
+    ipiv = np.empty(n, dtype=np.int64)
+    for k in range(n):
+        q = int(np.nonzero(cur == k)[0][0])
+        ipiv[k] = q
+        cur[[k, q]] = cur[[q, k]]
+    return A, np.tril(L, -1) + U, ipiv
+
+
+@pytest.mark.parametrize("ties", [True, False])
+@pytest.mark.parametrize("n", [40, 600, 1024, 1100])
+def test_lu_exact_on_dyadic_systems(n, ties, gpu):
+    """Bit-exact factors, pivot sequence and solution where elimination is exact: the first row
+    wins a tie (within a wavefront and across wavefronts of the panel), pivots found at any
+    position, both the blocked path (n <= 1024) and the column-by-column one."""
+    A, F, ipiv_ref = _exact_lu_case(n, 1000 + n, ties)
+    x_ref = np.random.default_rng(n).integers(-3, 4, size=n).astype(np.float64)
+    b = A @ x_ref
+    say(f"lu exact n={n} ties={ties}")
+    Ad = _d64(A)
+    ipiv, info = vpm.vpm_lu_factor(Ad)
+    x = host(vpm.vpm_lu_solve(Ad, ipiv, _d64(b)))
+    assert int(info.item()) == 0
+    assert np.array_equal(host(ipiv).astype(np.int64), ipiv_ref)
+    assert np.array_equal(host(Ad), F)
+    assert np.array_equal(x, x_ref)
+
+
 def test_blade_system_solve(gpu):
     """The hover lattice's Neumann system with a rotor-like right-hand side."""
     g = W.blade_rings()
