@@ -184,50 +184,59 @@ constexpr int kPanel = 16;
 
 // Panel [j0, j0 + nb): rows [j0, n), row j0 + t in lane t (the workgroup has as many
 // wavefronts as the rows need).
-// Unsigned 64-bit maximum over a full wavefront, returned in every lane: row shifts by 1, 2, 4
-// and 8 leave each 16-lane row's maximum in its last lane, the two row broadcasts carry row 0
-// into row 1, row 2 into row 3 and then lane 31 into rows 2 and 3, so lane 63 holds the
-// wavefront's maximum.  Lanes a DPP move does not write keep 0, the identity.  Every lane of the
-// wavefront must be active.
-template <int kCtrl, int kRowMask>
-__device__ __forceinline__ uint64_t dpp_umax_step(uint64_t k) {
-    const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(k)), kCtrl, kRowMask, 0xf, false));
-    const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(k >> 32)), kCtrl, kRowMask, 0xf, false));
-    const uint64_t o = (uint64_t(hi) << 32) | lo;
-    return o > k ? o : k;
+// Unsigned maximum over lanes 0 .. 16 * kRows - 1 of a full wavefront, returned in every lane:
+// row shifts by 1, 2, 4 and 8 leave each 16-lane row's maximum in its last lane; for a whole
+// wavefront the two row broadcasts then carry row 0 into row 1, row 2 into row 3 and lane 31
+// into rows 2 and 3, so lane 63 holds the maximum.  Lanes a DPP move does not write read 0, the
+// identity.  Every lane of the wavefront must be active.
+template <int kRows>
+__device__ __forceinline__ uint32_t lanes_umax(uint32_t k) {
+    static_assert(kRows == 1 || kRows == 4, "one row or the whole wavefront");
+    k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0x111, 0xf, 0xf, false)));  // row_shr:1
+    k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0x112, 0xf, 0xf, false)));  // row_shr:2
+    k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0x114, 0xf, 0xf, false)));  // row_shr:4
+    k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0x118, 0xf, 0xf, false)));  // row_shr:8
+    if constexpr (kRows == 4) {
+        k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0x142, 0xa, 0xf, false)));  // row_bcast:15
+        k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0x143, 0xc, 0xf, false)));  // row_bcast:31
+    }
+    return uint32_t(__builtin_amdgcn_readlane(int(k), kRows * 16 - 1));
 }
 
-__device__ __forceinline__ uint64_t wave_umax(uint64_t k) {
-    k = dpp_umax_step<0x111, 0xf>(k);  // row_shr:1
-    k = dpp_umax_step<0x112, 0xf>(k);  // row_shr:2
-    k = dpp_umax_step<0x114, 0xf>(k);  // row_shr:4
-    k = dpp_umax_step<0x118, 0xf>(k);  // row_shr:8
-    k = dpp_umax_step<0x142, 0xa>(k);  // row_bcast:15
-    k = dpp_umax_step<0x143, 0xc>(k);  // row_bcast:31
-    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(k)), 63));
-    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(k >> 32)), 63));
-    return (uint64_t(hi) << 32) | lo;
+// The first lane (lowest lane index) holding the largest 64-bit key among lanes 0 .. 16 * kRows
+// - 1 (lanes beyond hold 0): maximum of the high words, then of the low words among the lanes
+// that hold the high maximum, then a ballot.  Returns the lane and the maximum.
+template <int kRows>
+__device__ __forceinline__ int first_umax(uint64_t key, uint64_t& kmax) {
+    const uint32_t hi = uint32_t(key >> 32), lo = uint32_t(key);
+    const uint32_t hmax = lanes_umax<kRows>(hi);
+    const uint32_t lmax = lanes_umax<kRows>(hi == hmax ? lo : 0u);
+    kmax = (uint64_t(hmax) << 32) | lmax;
+    return __ffsll((unsigned long long)__ballot(hi == hmax && lo == lmax)) - 1;
 }
 
 // One panel of kPanel columns in one workgroup, a row per lane held in registers (rows j0 ..
 // n-1; the launch has whole wavefronts).  Pivot search on the key bits(|a|) + 1 (0 for rows
 // above the diagonal or past n): for non-negative doubles the bit patterns order as the
-// values, so the largest key is the largest magnitude, and the first lane holding it, found by
-// a ballot, is the first row on ties.  Each wavefront posts its candidate row (key, row index
-// and the row's kPanel entries) and lane cc posts row cc, in buffers alternating by column;
-// one barrier, then every wavefront reduces the posted keys the same way (the first wavefront
-// on ties) and reads the pivot row.  A buffer written at column cc is next written at column
-// cc + 2, after the barrier of column cc + 1 that every lane reaches only when done reading it.
+// values, so the largest key is the largest magnitude, and the first lane holding it is the
+// first row on ties.  Each wavefront posts its candidate row (key, row index and the row's
+// kPanel entries) and lane cc posts row cc, in buffers alternating by column; one barrier, then
+// every wavefront reduces the posted keys the same way (the first wavefront on ties) and reads
+// the pivot row.  A buffer written at column cc is next written at column cc + 2, after the
+// barrier of column cc + 1 that every lane reaches only when done reading it.  A column without
+// a nonzero pivot has every candidate at key 1, so its pivot is row cc itself and nothing moves.
 __global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, int64_t lda, int64_t j0, int nb,
                                                          int32_t* ipiv, int32_t* info) {
     constexpr int kWaves = kLuThreads / 64;
-    __shared__ double srow[2][kWaves + 1][kPanel];  // [buffer][wavefront candidates, then row cc]
+    static_assert(kWaves <= 16, "the posted keys are reduced within one 16-lane row");
+    __shared__ double srow[2][kPanel][kWaves + 1];  // [buffer][column][wavefront candidates, then row cc]
     __shared__ uint64_t skey[2][kWaves];
     __shared__ int sidx[2][kWaves];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = int(blockDim.x) >> 6;
     const int64_t r = j0 + t;
     const bool has = r < n;
-    if (j0 == 0 && t == 0) *info = 0;
+    int32_t piv = 0;          // lane cc: the pivot row of column j0 + cc
+    int first_singular = -1;  // uniform
     double p[kPanel];
 #pragma unroll
     for (int j = 0; j < kPanel; ++j) p[j] = (has && j < nb) ? A[r * lda + j0 + j] : 0.0;
@@ -236,43 +245,36 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, i
         if (cc < nb) {  // uniform
             const int b = cc & 1;
             const uint64_t key = (has && t >= cc) ? uint64_t(__double_as_longlong(fabs(p[cc]))) + 1 : 0;
-            const uint64_t wmax = wave_umax(key);
-            const int lead = __ffsll((unsigned long long)__ballot(key == wmax)) - 1;
+            uint64_t wmax;
+            const int lead = first_umax<4>(key, wmax);
             if (lane == lead) {
                 skey[b][w] = wmax;
                 sidx[b][w] = t;
 #pragma unroll
-                for (int j = 0; j < kPanel; ++j) srow[b][w][j] = p[j];
+                for (int j = 0; j < kPanel; ++j) srow[b][j][w] = p[j];
             }
             if (t == cc) {
 #pragma unroll
-                for (int j = 0; j < kPanel; ++j) srow[b][kWaves][j] = p[j];
+                for (int j = 0; j < kPanel; ++j) srow[b][j][kWaves] = p[j];
             }
             __syncthreads();
-            const uint64_t ck = lane < nw ? skey[b][lane] : 0;
-            const uint64_t gmax = wave_umax(ck);
-            const int ww = __ffsll((unsigned long long)__ballot(lane < nw && ck == gmax)) - 1;
+            uint64_t gmax;
+            const int ww = first_umax<1>(lane < nw ? skey[b][lane] : 0, gmax);
             const int idx = sidx[b][ww];
-            if (t == 0) ipiv[j0 + cc] = int32_t(j0 + idx);
-            if (gmax == 1) {  // singular column: record the first one, leave the column as is
-                if (t == 0 && *info == 0) *info = int32_t(j0 + cc + 1);
-            } else {
-                // rows cc and idx trade places
-                if (idx != cc) {
-                    if (t == cc) {
+            const bool singular = gmax == 1;
+            if (t == cc) piv = int32_t(j0 + idx);
+            if (singular && first_singular < 0) first_singular = cc;
+            // rows cc and idx trade places
+            if (idx != cc && (t == cc || t == idx)) {
+                const int from = t == cc ? ww : kWaves;
 #pragma unroll
-                        for (int j = 0; j < kPanel; ++j) p[j] = srow[b][ww][j];
-                    } else if (t == idx) {
+                for (int j = 0; j < kPanel; ++j) p[j] = srow[b][j][from];
+            }
+            if (has && t > cc && !singular) {
+                p[cc] /= srow[b][cc][ww];
 #pragma unroll
-                        for (int j = 0; j < kPanel; ++j) p[j] = srow[b][kWaves][j];
-                    }
-                }
-                if (has && t > cc) {
-                    p[cc] /= srow[b][ww][cc];
-#pragma unroll
-                    for (int j = cc + 1; j < kPanel; ++j)
-                        if (j < nb) p[j] -= p[cc] * srow[b][ww][j];
-                }
+                for (int j = cc + 1; j < kPanel; ++j)
+                    if (j < nb) p[j] -= p[cc] * srow[b][j][ww];
             }
         }
     }
@@ -280,6 +282,13 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_panel(int64_t n, double* A, i
 #pragma unroll
         for (int j = 0; j < kPanel; ++j)
             if (j < nb) A[r * lda + j0 + j] = p[j];
+    }
+    // The pivots and the status are written once at the end: a global store pending at a
+    // barrier holds every wavefront there until the store completes.
+    if (t < nb) ipiv[j0 + t] = piv;
+    if (t == 0) {
+        if (j0 == 0) *info = 0;
+        if (first_singular >= 0 && *info == 0) *info = int32_t(j0 + first_singular + 1);  // the first such column
     }
 }
 
@@ -388,6 +397,38 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_solve(int64_t n, const double
 // wavefront solves a diagonal block (staged in LDS) with shuffles, then the lanes update the
 // remaining rows with that block's columns.  Every entry receives the same operations in the
 // same order as in k_lu_solve (forward: k ascending; backward: k descending, then the division).
+// A uniform lane's double, read into scalar registers.
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const int64_t b = __double_as_longlong(v);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b)), k));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(uint64_t(b) >> 32)), k));
+    return __longlong_as_double(int64_t((uint64_t(hi) << 32) | lo));
+}
+
+// sb[r] -= sum_k LU[r][kb + k] sb[kb + k] (k < nbk <= 64) for rows r0 <= r < r1: eight lanes
+// per row, lane s taking the columns s, s + 8, ..., so that one load instruction of a wavefront
+// reads eight rows' consecutive 64-byte runs; the eight partial sums are added by a butterfly.
+__device__ __forceinline__ void lu_solve_rows(const double* LU, int64_t lda, double* sb, int64_t kb, int nbk,
+                                              int64_t r0, int64_t r1) {
+    const int g = threadIdx.x >> 3, sub = threadIdx.x & 7;
+    for (int64_t rb = r0; rb < r1; rb += kLuThreads / 8) {
+        const int64_t r = rb + g;  // uniform per eight lanes; the shuffles below run on all lanes
+        double v = 0.0;
+        if (r < r1) {
+            const double* row = LU + r * lda + kb;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = sub + 8 * i;
+                if (k < nbk) v += row[k] * sb[kb + k];
+            }
+        }
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        if (r < r1 && sub == 0) sb[r] -= v;
+    }
+}
+
 __global__ __launch_bounds__(kLuThreads) void k_lu_solve_blocked(int64_t n, const double* LU, int64_t lda,
                                                                  const int32_t* ipiv, double* b) {
     __shared__ double sb[kLuThreads];
@@ -405,7 +446,8 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_solve_blocked(int64_t n, cons
             }
         }
     __syncthreads();
-    // L y = P b, unit diagonal
+    // L y = P b, unit diagonal, in blocks of 64 rows: one wavefront solves the diagonal block
+    // (the solved entry broadcast from its lane), then all lanes update the rows below.
     for (int64_t kb = 0; kb < n; kb += 64) {
         const int nbk = int(n - kb < 64 ? n - kb : 64);
         for (int e = t; e < nbk * nbk; e += kLuThreads) sd[e / nbk][e % nbk] = LU[(kb + e / nbk) * lda + kb + e % nbk];
@@ -413,21 +455,16 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_solve_blocked(int64_t n, cons
         if (t < 64) {
             double y = lane < nbk ? sb[kb + lane] : 0.0;
             for (int k = 0; k < nbk; ++k) {
-                const double yk = __shfl(y, k, 64);
+                const double yk = lane_value(y, k);
                 if (lane > k && lane < nbk) y -= sd[lane][k] * yk;
             }
             if (lane < nbk) sb[kb + lane] = y;
         }
         __syncthreads();
-        const int64_t r = kb + nbk + t;
-        if (r < n) {
-            double v = sb[r];
-            for (int k = 0; k < nbk; ++k) v -= LU[r * lda + kb + k] * sb[kb + k];
-            sb[r] = v;
-        }
+        lu_solve_rows(LU, lda, sb, kb, nbk, kb + nbk, n);
         __syncthreads();
     }
-    // U x = y
+    // U x = y, the blocks from the last: the diagonal block, then the rows above
     const int64_t nblk = (n + 63) / 64;
     for (int64_t bi = nblk - 1; bi >= 0; --bi) {
         const int64_t kb = bi * 64;
@@ -438,17 +475,13 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_solve_blocked(int64_t n, cons
             double y = lane < nbk ? sb[kb + lane] : 0.0;
             for (int k = nbk - 1; k >= 0; --k) {
                 if (lane == k) y /= sd[k][k];
-                const double xk = __shfl(y, k, 64);
+                const double xk = lane_value(y, k);
                 if (lane < k) y -= sd[lane][k] * xk;
             }
             if (lane < nbk) sb[kb + lane] = y;
         }
         __syncthreads();
-        if (t < kb) {
-            double v = sb[t];
-            for (int k = nbk - 1; k >= 0; --k) v -= LU[int64_t(t) * lda + kb + k] * sb[kb + k];
-            sb[t] = v;
-        }
+        lu_solve_rows(LU, lda, sb, kb, nbk, 0, kb);
         __syncthreads();
     }
     if (t < n) b[t] = sb[t];
