@@ -74,6 +74,10 @@ class Step:
         self.sp = torch.zeros(self.cap, dtype=dtype, device=self.dev)
         self.uq = torch.zeros_like(self.xp)
         self.dq = torch.zeros_like(self.xp)
+        # The particles' self-interaction depends only on the particles at the start of the step,
+        # so it runs on a second stream (default priority) beside the blade solve, whose LU keeps
+        # a few compute units busy at a time; the step joins it before adding the segments.
+        self.side = torch.cuda.Stream(device=self.dev)
         self.np = 0
         self.gamma = None
         ns1 = self.ns + 1
@@ -136,6 +140,12 @@ class Step:
 
     # ------------------------------------------------------------------ the step
     def step(self):
+        main = torch.cuda.current_stream(self.dev)
+        if self.np:
+            self.side.wait_stream(main)
+            with torch.cuda.stream(self.side):
+                vpm_eval_velocity_stretching(self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np],
+                                             u_out=self.uq[:, :self.np], dgamma_out=self.dq[:, :self.np])
         g, T = self._geometry()
         T_t = T.to(self.dt_t)
         if self.bounds:
@@ -173,7 +183,7 @@ class Step:
         if self.np:
             xq, gq, sq = self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np]
             uq, dq = self.uq[:, :self.np], self.dq[:, :self.np]
-            vpm_eval_velocity_stretching(xq, gq, sq, u_out=uq, dgamma_out=dq)
+            main.wait_stream(self.side)
             vpm_eval_segments_gradient(segs[0], segs[1], segs[2], xq, self.rc, self.vn, gamma_tgt=gq,
                                        want_grad=False, u_out=uq, dgamma_out=dq, accumulate=True)
             vpm_advect(xq, uq, self.dt, self.v_inf, gamma=gq, dgamma=dq)
