@@ -74,9 +74,8 @@ class Step:
         self.sp = torch.zeros(self.cap, dtype=dtype, device=self.dev)
         self.uq = torch.zeros_like(self.xp)
         self.dq = torch.zeros_like(self.xp)
-        # The particles' self-interaction depends only on the particles at the start of the step,
-        # so it runs on a second stream (default priority) beside the blade solve, whose LU keeps
-        # a few compute units busy at a time; the step joins it before adding the segments.
+        # a second stream (default priority) for the particle sums, which run beside the blade
+        # solve (its LU keeps a few compute units busy at a time)
         self.side = torch.cuda.Stream(device=self.dev)
         self.np = 0
         self.gamma = None
@@ -128,26 +127,27 @@ class Step:
             return None
         return torch.cat(A, 1).contiguous(), torch.cat(B, 1).contiguous(), torch.cat(G).contiguous()
 
-    def _velocity(self, y, segs):
-        """Velocity at points y (3, n) from the particles and the segments (a, b, g) or None."""
-        u = torch.zeros((3, y.shape[1]), dtype=self.dt_t, device=self.dev)
-        if self.np:
-            vpm_eval_velocity_stretching(self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np], y,
-                                         u_out=u)
-        if segs is not None:
-            vpm_eval_segments(segs[0], segs[1], segs[2], y, self.rc, self.vn, u_out=u, accumulate=True)
-        return u
-
     # ------------------------------------------------------------------ the step
     def step(self):
         main = torch.cuda.current_stream(self.dev)
-        if self.np:
-            self.side.wait_stream(main)
-            with torch.cuda.stream(self.side):
-                vpm_eval_velocity_stretching(self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np],
-                                             u_out=self.uq[:, :self.np], dgamma_out=self.dq[:, :self.np])
         g, T = self._geometry()
         T_t = T.to(self.dt_t)
+        col_t = g["colloc"].to(self.dt_t)
+        pts = torch.cat([T_t] + self.bounds, 1).contiguous()  # boundary points: the new line first
+        u = torch.zeros((3, col_t.shape[1]), dtype=self.dt_t, device=self.dev)
+        up = torch.zeros((3, pts.shape[1]), dtype=self.dt_t, device=self.dev)
+        if self.np:
+            # The particles' contributions (at the collocation points, the boundary points and
+            # the particles) depend only on the particles at the start of the step: they run on
+            # the second stream beside the blade solve, the segments' shares are added after.
+            P = (self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np])
+            self.side.wait_stream(main)
+            with torch.cuda.stream(self.side):
+                vpm_eval_velocity_stretching(*P, col_t, u_out=u)
+                ev_col = self.side.record_event()
+                vpm_eval_velocity_stretching(*P, pts, u_out=up)
+                ev_pts = self.side.record_event()
+                vpm_eval_velocity_stretching(*P, u_out=self.uq[:, :self.np], dgamma_out=self.dq[:, :self.np])
         if self.bounds:
             B1 = self.bounds[0].to(torch.float64)
             lo, hi = self.span_lo, self.span_hi
@@ -158,8 +158,11 @@ class Step:
         else:
             self.A.copy_(self.A0)
         ipiv, _ = vpm_lu_factor(self.A)
-        col_t = g["colloc"].to(self.dt_t)
-        u = self._velocity(col_t, self.lines(self.gprev))
+        wl = self.lines(self.gprev)
+        if self.np:
+            main.wait_event(ev_col)
+        if wl is not None:
+            vpm_eval_segments(wl[0], wl[1], wl[2], col_t, self.rc, self.vn, u_out=u, accumulate=True)
         rhs = vpm_neumann_rhs(g["colloc"], g["normal"], u, self.v_inf, (0.0, 0.0, self.omega))
         gam = vpm_lu_solve(self.A, ipiv, rhs)
         self.gamma = gam
@@ -171,7 +174,6 @@ class Step:
             self.rows.insert(0, tr)
             self.sheds[1] = sh
         # velocity at the boundary points and the particles
-        pts = torch.cat(self.bounds, 1).contiguous()
         ca = torch.stack([g["c00"], g["c01"], g["c11"], g["c10"]], 2).reshape(3, -1)
         cb = torch.stack([g["c01"], g["c11"], g["c10"], g["c00"]], 2).reshape(3, -1)
         cg = gam.repeat_interleave(4)
@@ -179,7 +181,9 @@ class Step:
         wl = self.lines()
         if wl is not None:
             segs = [torch.cat([segs[i], wl[i]], -1).contiguous() for i in range(3)]
-        up = self._velocity(pts, segs)
+        if self.np:
+            main.wait_event(ev_pts)
+        vpm_eval_segments(segs[0], segs[1], segs[2], pts, self.rc, self.vn, u_out=up, accumulate=True)
         if self.np:
             xq, gq, sq = self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np]
             uq, dq = self.uq[:, :self.np], self.dq[:, :self.np]
