@@ -393,16 +393,22 @@ __device__ __forceinline__ void fold_tile(T (&acc)[NA], T (&hi)[NA], T (&lo)[NA]
     }
 }
 
-template <typename T, int K, int WG, int VN>
+// LPT lanes per target (neighbouring lanes of one wavefront) split each staged tile of segments
+// between them, lane q taking the segments q, q + LPT, ...; their sums are added in FP64 by a
+// butterfly before the write, so a launch with few targets still has several wavefronts per SIMD.
+template <typename T, int K, int WG, int VN, int LPT>
 __global__ __launch_bounds__(WG) void k_segments_grad(SegArgs a) {
+    static_assert(LPT == 1 || K == 1, "lanes per target only with one target per lane group");
+    static_assert((LPT & (LPT - 1)) == 0 && LPT <= 64, "a power of two within a wavefront");
     constexpr bool kComp = std::is_same<T, float>::value;
     constexpr int NA = 12;  // u (3), J row-major (9)
+    constexpr int kSlots = WG / LPT;  // targets per workgroup and K
     __shared__ V4<T> l0[WG];
     __shared__ V4<T> l1[WG];
     __shared__ T l2[WG];
     const T* __restrict__ X = static_cast<const T*>(a.xt);
-    const int tid = threadIdx.x;
-    const int64_t t0 = int64_t(blockIdx.x) * (WG * K);
+    const int tid = threadIdx.x / LPT, q = threadIdx.x % LPT;
+    const int64_t t0 = int64_t(blockIdx.x) * (kSlots * K);
     const T n_f = T(a.vn);
     const T inv_n = T(1.0 / a.vn);
     const T rc2n = core_power<T>(a, VN);
@@ -411,7 +417,7 @@ __global__ __launch_bounds__(WG) void k_segments_grad(SegArgs a) {
     bool valid[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int64_t t = t0 + tid + int64_t(k) * WG;
+        const int64_t t = t0 + tid + int64_t(k) * kSlots;
         valid[k] = t < a.n_tgt;
         const int64_t tt = valid[k] ? t : 0;
         P[k][0] = X[tt];
@@ -429,7 +435,7 @@ __global__ __launch_bounds__(WG) void k_segments_grad(SegArgs a) {
         __syncthreads();
         stage_segments<T, WG, VN>(a, j0, cnt, l0, l1, l2);
         __syncthreads();
-        for (int jj = 0; jj < cnt; ++jj) {
+        for (int jj = q; jj < cnt; jj += LPT) {
             const V4<T> p = l0[jj];
             const V4<T> q = l1[jj];
             const T eps2 = l2[jj];
@@ -465,11 +471,17 @@ __global__ __launch_bounds__(WG) void k_segments_grad(SegArgs a) {
     const T* __restrict__ Gt = static_cast<const T*>(a.gt);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        if (!valid[k]) continue;
-        const int64_t t = t0 + tid + int64_t(k) * WG;
         double v[NA];
 #pragma unroll
         for (int c = 0; c < NA; ++c) v[c] = kComp ? double(hi[k][c]) + double(lo[k][c]) : double(acc[k][c]);
+        if constexpr (LPT > 1) {  // every lane takes part; each ends with the same sums
+#pragma unroll
+            for (int m = 1; m < LPT; m <<= 1)
+#pragma unroll
+                for (int c = 0; c < NA; ++c) v[c] += __shfl_xor(v[c], m, 64);
+        }
+        if (!valid[k] || q != 0) continue;
+        const int64_t t = t0 + tid + int64_t(k) * kSlots;
         if (U) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -623,18 +635,31 @@ hipError_t launch_t(const SegArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <typename T, int K, int WG>
+template <typename T, int K, int WG, int LPT>
 hipError_t launch_grad_t(const SegArgs& a, hipStream_t st) {
-    const int grid = int((a.n_tgt + WG * K - 1) / (WG * K));
+    const int64_t per = int64_t(WG / LPT) * K;
+    const int grid = int((a.n_tgt + per - 1) / per);
     if (a.rc == 0.0)
-        hipLaunchKernelGGL((k_segments_grad<T, K, WG, 0>), dim3(grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((k_segments_grad<T, K, WG, 0, LPT>), dim3(grid), dim3(WG), 0, st, a);
     else if (a.vn == 1)
-        hipLaunchKernelGGL((k_segments_grad<T, K, WG, 1>), dim3(grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((k_segments_grad<T, K, WG, 1, LPT>), dim3(grid), dim3(WG), 0, st, a);
     else if (a.vn == 2)
-        hipLaunchKernelGGL((k_segments_grad<T, K, WG, 2>), dim3(grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((k_segments_grad<T, K, WG, 2, LPT>), dim3(grid), dim3(WG), 0, st, a);
     else
-        hipLaunchKernelGGL((k_segments_grad<T, K, WG, 3>), dim3(grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((k_segments_grad<T, K, WG, 3, LPT>), dim3(grid), dim3(WG), 0, st, a);
     return hipGetLastError();
+}
+
+// Lanes per target for the gradient kernel: one above kSegGradSplit1 targets (four or more
+// wavefronts per SIMD on 256 compute units), four above kSegGradSplit4, sixteen below.
+constexpr int64_t kSegGradSplit1 = 196608;
+constexpr int64_t kSegGradSplit4 = 16384;
+
+template <typename T>
+hipError_t launch_grad_split(const SegArgs& a, hipStream_t st) {
+    if (a.n_tgt > kSegGradSplit1) return launch_grad_t<T, 1, 256, 1>(a, st);
+    if (a.n_tgt > kSegGradSplit4) return launch_grad_t<T, 1, 256, 4>(a, st);
+    return launch_grad_t<T, 1, 256, 16>(a, st);
 }
 
 template <typename T, int WG>
@@ -655,8 +680,8 @@ hipError_t launch_vjp_t(const SegArgs& a, hipStream_t st) {
 
 hipError_t launch_segments_gradient(int dtype, const SegArgs& a, hipStream_t st) {
     if (a.n_tgt == 0) return hipSuccess;
-    if (dtype == kDtypeF64) return launch_grad_t<double, 1, 256>(a, st);
-    return launch_grad_t<float, 1, 256>(a, st);
+    if (dtype == kDtypeF64) return launch_grad_split<double>(a, st);
+    return launch_grad_split<float>(a, st);
 }
 
 hipError_t launch_segments_vjp(int dtype, const SegArgs& a, hipStream_t st) {

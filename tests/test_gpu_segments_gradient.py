@@ -78,6 +78,25 @@ def test_segments_gradient_full_size_sampled(kind, gpu):
 
 
 @pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n", [16384, 16385, 196608, 196609])
+def test_segments_gradient_on_either_side_of_the_lane_splits(n, kind, gpu):
+    """Target counts on either side of those where the kernel changes the number of lanes that
+    share a target's segments (16 below 16,385 targets, 4 below 196,609, then 1); the oracle
+    checks 512 sampled targets, the first and the last among them."""
+    c = W.config2(n=n)
+    a, b, gs, x, g = prepare([c["seg_a"], c["seg_b"], c["seg_gamma"], c["x"], c["gamma"]], kind)
+    say(f"segments gradient {kind} n_tgt={n}")
+    u, J, d = vpm.vpm_eval_segments_gradient(dev(a, kind), dev(b, kind), dev(gs, kind), dev(x, kind), 0.02, 2,
+                                             gamma_tgt=dev(g, kind))
+    rng = np.random.default_rng(n)
+    idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 510, replace=False)]))
+    Jo = oracle.segments_gradient(a, b, gs, x[:, idx], 0.02, 2)
+    assert rel_l2(host(u)[:, idx], oracle.segments(a, b, gs, x[:, idx], 0.02, 2)) <= TOL[kind]
+    assert rel_l2(host(J)[:, idx], Jo.reshape(9, -1)) <= TOL[kind]
+    assert rel_l2(host(d)[:, idx], _stretch(Jo, g[:, idx], False)) <= TOL[kind]
+
+
+@pytest.mark.parametrize("kind", KINDS)
 def test_segments_gradient_degenerate_cases(kind, gpu):
     """A zero-length segment, a target on a segment's end point and on its line without a
     core contribute nothing; no segments give zeros; no targets launch nothing."""
