@@ -74,9 +74,10 @@ class Step:
         self.sp = torch.zeros(self.cap, dtype=dtype, device=self.dev)
         self.uq = torch.zeros_like(self.xp)
         self.dq = torch.zeros_like(self.xp)
-        # a second stream (default priority) for the particle sums, which run beside the blade
+        # two more streams (default priority) for the particle sums, which run beside the blade
         # solve (its LU keeps a few compute units busy at a time)
         self.side = torch.cuda.Stream(device=self.dev)
+        self.side2 = torch.cuda.Stream(device=self.dev)
         self.np = 0
         self.gamma = None
         ns1 = self.ns + 1
@@ -130,6 +131,16 @@ class Step:
     # ------------------------------------------------------------------ the step
     def step(self):
         main = torch.cuda.current_stream(self.dev)
+        if self.np:
+            # The particles' contributions depend only on the particles at the start of the
+            # step: their self-interaction (the largest part of the step) starts first, on the
+            # second stream; their velocities at the collocation and boundary points follow on
+            # the third once the points are known.  The blade solve runs beside them on the
+            # main stream, which joins each result before adding the segments' shares.
+            P = (self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np])
+            self.side.wait_stream(main)
+            with torch.cuda.stream(self.side):
+                vpm_eval_velocity_stretching(*P, u_out=self.uq[:, :self.np], dgamma_out=self.dq[:, :self.np])
         g, T = self._geometry()
         T_t = T.to(self.dt_t)
         col_t = g["colloc"].to(self.dt_t)
@@ -137,17 +148,12 @@ class Step:
         u = torch.zeros((3, col_t.shape[1]), dtype=self.dt_t, device=self.dev)
         up = torch.zeros((3, pts.shape[1]), dtype=self.dt_t, device=self.dev)
         if self.np:
-            # The particles' contributions (at the collocation points, the boundary points and
-            # the particles) depend only on the particles at the start of the step: they run on
-            # the second stream beside the blade solve, the segments' shares are added after.
-            P = (self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np])
-            self.side.wait_stream(main)
-            with torch.cuda.stream(self.side):
+            self.side2.wait_stream(main)
+            with torch.cuda.stream(self.side2):
                 vpm_eval_velocity_stretching(*P, col_t, u_out=u)
-                ev_col = self.side.record_event()
+                ev_col = self.side2.record_event()
                 vpm_eval_velocity_stretching(*P, pts, u_out=up)
-                ev_pts = self.side.record_event()
-                vpm_eval_velocity_stretching(*P, u_out=self.uq[:, :self.np], dgamma_out=self.dq[:, :self.np])
+                ev_pts = self.side2.record_event()
         if self.bounds:
             B1 = self.bounds[0].to(torch.float64)
             lo, hi = self.span_lo, self.span_hi
