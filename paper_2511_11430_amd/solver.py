@@ -45,7 +45,7 @@ def _rot_z(psi):
 
 class Step:
     def __init__(self, geom, omega, v_inf, dt, core_radius, vatistas_n, sigma_p, n_tip, n_rows, n_max=64,
-                 dtype=torch.float64, capacity=1 << 20, device="cuda"):
+                 dtype=torch.float64, capacity=1 << 20, device="cuda", overlap=True):
         self.dev = torch.device(device)
         self.dt_t = dtype
         self.g0 = {k: np.asarray(geom[k], dtype=np.float64) for k in ("c00", "c01", "c11", "c10", "colloc",
@@ -76,8 +76,9 @@ class Step:
         self.dq = torch.zeros_like(self.xp)
         # two more streams (default priority) for the particle sums, which run beside the blade
         # solve (its LU keeps a few compute units busy at a time)
-        self.side = torch.cuda.Stream(device=self.dev)
-        self.side2 = torch.cuda.Stream(device=self.dev)
+        # (overlap=False: everything on the caller's stream, in the same order)
+        self.side = torch.cuda.Stream(device=self.dev) if overlap else None
+        self.side2 = torch.cuda.Stream(device=self.dev) if overlap else None
         self.np = 0
         self.gamma = None
         ns1 = self.ns + 1
@@ -131,6 +132,8 @@ class Step:
     # ------------------------------------------------------------------ the step
     def step(self):
         main = torch.cuda.current_stream(self.dev)
+        side = self.side or main
+        side2 = self.side2 or main
         if self.np:
             # The particles' contributions depend only on the particles at the start of the
             # step: their self-interaction (the largest part of the step) starts first, on the
@@ -138,8 +141,8 @@ class Step:
             # the third once the points are known.  The blade solve runs beside them on the
             # main stream, which joins each result before adding the segments' shares.
             P = (self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np])
-            self.side.wait_stream(main)
-            with torch.cuda.stream(self.side):
+            side.wait_stream(main)
+            with torch.cuda.stream(side):
                 vpm_eval_velocity_stretching(*P, u_out=self.uq[:, :self.np], dgamma_out=self.dq[:, :self.np])
         g, T = self._geometry()
         T_t = T.to(self.dt_t)
@@ -148,12 +151,12 @@ class Step:
         u = torch.zeros((3, col_t.shape[1]), dtype=self.dt_t, device=self.dev)
         up = torch.zeros((3, pts.shape[1]), dtype=self.dt_t, device=self.dev)
         if self.np:
-            self.side2.wait_stream(main)
-            with torch.cuda.stream(self.side2):
+            side2.wait_stream(main)
+            with torch.cuda.stream(side2):
                 vpm_eval_velocity_stretching(*P, col_t, u_out=u)
-                ev_col = self.side2.record_event()
+                ev_col = side2.record_event()
                 vpm_eval_velocity_stretching(*P, pts, u_out=up)
-                ev_pts = self.side2.record_event()
+                ev_pts = side2.record_event()
         if self.bounds:
             B1 = self.bounds[0].to(torch.float64)
             lo, hi = self.span_lo, self.span_hi
@@ -193,7 +196,7 @@ class Step:
         if self.np:
             xq, gq, sq = self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np]
             uq, dq = self.uq[:, :self.np], self.dq[:, :self.np]
-            main.wait_stream(self.side)
+            main.wait_stream(side)
             vpm_eval_segments_gradient(segs[0], segs[1], segs[2], xq, self.rc, self.vn, gamma_tgt=gq,
                                        want_grad=False, u_out=uq, dgamma_out=dq, accumulate=True)
             vpm_advect(xq, uq, self.dt, self.v_inf, gamma=gq, dgamma=dq)

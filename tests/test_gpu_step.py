@@ -52,3 +52,28 @@ def test_closed_step_matches_oracle(gpu):
             scale = np.abs(gam_g).max() * 0.1
             assert np.abs(tot).max() <= 1e-12 * scale
     assert first_conversion is not None
+
+
+def test_streams_give_the_bits_of_one_stream(gpu):
+    """The hover lattice in its 65,536-particle FP32C wake: the particle sums on streams of
+    their own beside the blade solve give the same bits, step after step (conversions
+    included), as the same calls in order on one stream."""
+    import torch
+    from paper_2511_11430_amd.solver import Step
+    c2 = W.config2()
+    geom = W.blade_rings()
+    f32 = lambda a: torch.tensor(np.ascontiguousarray(W.to_f32(a)), dtype=torch.float32, device="cuda")
+    kw = dict(omega=W.OMEGA, v_inf=(0.0, 0.0, 0.0), dt=W.DT, core_radius=c2["core_radius"], vatistas_n=2,
+              sigma_p=0.02 * W.R, n_tip=2, n_rows=2, dtype=torch.float32, capacity=1 << 17)
+    steps = [Step(geom, overlap=ov, **kw) for ov in (True, False)]
+    for st in steps:
+        st.add_particles(f32(c2["x"]), f32(c2["gamma"]), f32(c2["sigma"]))
+    for k in range(5):
+        gam = [st.step() for st in steps]
+        say(f"step {k}: particles {steps[0].np} / {steps[1].np}")
+        assert steps[0].np == steps[1].np
+        assert torch.equal(gam[0], gam[1])
+        for p, q in zip(steps[0].particles(), steps[1].particles()):
+            assert torch.equal(p, q)
+        assert all(torch.equal(a, b) for a, b in zip(steps[0].bounds, steps[1].bounds))
+    assert steps[0].np > 65536  # rows were converted
