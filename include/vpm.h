@@ -320,8 +320,9 @@ vpm_status vpm_aic_assemble(int64_t n, const double* c00, const double* c01, con
 vpm_status vpm_lu_factor(int64_t n, double* a, int64_t lda, int32_t* ipiv, int32_t* info, void* stream);
 
 /* vpm_lu_solve — solves a x = b with the factors of vpm_lu_factor; b (device double[n]) is
- * overwritten by x.  Used once per time step with a matrix factored once (the lattice is
- * rigid in the rotating frame). */
+ * overwritten by x.  The closed step factors and solves once per time step: the wake row at
+ * the trailing edge (the Kutta rings) moves with the wake, so the matrix changes every step.
+ * One workgroup; up to n = 1024 in blocks of 64 rows with b in LDS. */
 vpm_status vpm_lu_solve(int64_t n, const double* lu, int64_t lda, const int32_t* ipiv, double* b, void* stream);
 
 /* vpm_wake_shed — Kutta condition and the newest wake row (Sec. II.A; Eq. 7).  The new wake

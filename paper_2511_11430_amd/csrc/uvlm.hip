@@ -394,9 +394,11 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_solve(int64_t n, const double
 }
 
 // The two triangular solves for n <= kLuThreads, b in LDS, in blocks of 64 rows: one
-// wavefront solves a diagonal block (staged in LDS) with shuffles, then the lanes update the
-// remaining rows with that block's columns.  Every entry receives the same operations in the
-// same order as in k_lu_solve (forward: k ascending; backward: k descending, then the division).
+// wavefront solves a diagonal block (staged in LDS) in the order of k_lu_solve, then the lanes
+// update the remaining rows with that block's columns (lu_solve_rows: the block's 64 products
+// of a row summed as eight partial sums and a butterfly, so the rounding differs from
+// k_lu_solve's sequential sums).
+
 // A uniform lane's double, read into scalar registers.
 __device__ __forceinline__ double lane_value(double v, int k) {
     const int64_t b = __double_as_longlong(v);
