@@ -202,7 +202,7 @@ int64_t targets_per_block(int32_t dtype, int variant) {
 // about kSplitGoal workgroups run; partial sums go to the workspace.  Depends only on sizes.
 constexpr int64_t kSplitBelow = 1024;
 constexpr int64_t kSplitGoal = 2048;
-constexpr int64_t kMinChunk = 2048;
+constexpr int64_t kMinChunk = 256;
 
 struct SplitPlan {
     int64_t nchunk = 1, chunk = 0;
