@@ -375,11 +375,20 @@ vpm_status vpm_neumann_rhs(int32_t dtype, int64_t n, const double* colloc, const
                            const void* u, int64_t ld_u, const double* v_inf, const double* omega, double* rhs,
                            void* stream);
 
-/* vpm_advect — one explicit Euler move of n points (wake-line points, particles):
- *   x += dt (u + v_inf);  gamma += dt dgamma  when gamma is not NULL,
- * all [3][ld] of dtype; v_inf host double[3]. */
-vpm_status vpm_advect(int32_t dtype, int64_t n, double dt, void* x, const void* u, void* gamma, const void* dgamma,
-                      int64_t ld, const double* v_inf, void* stream);
+/* vpm_rk3_advect — stage k (0, 1, 2) of Williamson's low-storage third-order Runge-Kutta
+ * scheme (Sec. II.B) for n points carried by the flow in a free stream (the wake-line points
+ * and the particles of the closed step):
+ *   Qx <- A_k Qx + dt (u + v_inf);   x <- x + B_k Qx,
+ * and, when gamma is not NULL, Qg <- A_k Qg + dt dgamma;  gamma <- gamma + B_k Qg, with
+ * A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15).  u and dgamma are the right-hand side at
+ * the stage's state (evaluated at time t + (0, 1/3, 3/4)[k] dt).  x, qx, u, gamma, qg, dgamma:
+ * [3][ld] device arrays of dtype, caller-owned; the registers qx, qg are read at stages 1 and 2
+ * and only written at stage 0.  v_inf: host double[3] (m/s).  The update is computed in FP64
+ * and stored in dtype.  Errors: VPM_ERR_DTYPE, VPM_ERR_ENUM (stage), VPM_ERR_SIZE (n < 0,
+ * ld < n, non-finite dt), VPM_ERR_NULL (missing array, gamma without qg or dgamma),
+ * VPM_ERR_ALIAS (overlapping arrays), VPM_ERR_HIP. */
+vpm_status vpm_rk3_advect(int32_t dtype, int32_t stage, int64_t n, double dt, void* x, void* qx, const void* u,
+                          void* gamma, void* qg, const void* dgamma, int64_t ld, const double* v_inf, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * vpm_rk3_stage — stage k (0, 1, 2) of Williamson's low-storage third-order Runge-Kutta

@@ -124,8 +124,16 @@ def rot_z(psi):
     return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
 
 
+# Williamson's low-storage third-order Runge-Kutta scheme (Sec. II.B), in its 2N-storage
+# form: per stage k, register Q <- A_k Q + dt F(Y, t + C_k dt) and state Y <- Y + B_k Q.
+# C holds the nodes of the same scheme's Butcher form (the times at which stage k evaluates).
+RK3_A = (0.0, -5.0 / 9.0, -153.0 / 128.0)
+RK3_B = (1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0)
+RK3_C = (0.0, 1.0 / 3.0, 3.0 / 4.0)
+
+
 class StepOracle:
-    """One explicit time step of the closed blade/wake/particle loop, FP64 on the CPU.
+    """One time step of the closed blade/wake/particle loop, FP64 on the CPU.
 
     Blade: the ring lattice `geom` (body frame at azimuth 0) turning at omega about z in the
     free stream v_inf.  Wake: boundaries B_1 (youngest free row of points) ... B_m; trailed
@@ -138,22 +146,24 @@ class StepOracle:
         row at the trailing edge carries that panel's circulation);
      3. velocity at the collocation points from the particles, the wake lines and the line
         along B_1 holding the circulation of the last shed row (still open), Neumann
-        right-hand side, dense solve for the ring circulations;
+        right-hand side, dense solve for the ring circulations (or the prescribed ones);
      4. the trailing-edge points become the youngest boundary; when a wake existed, the row
         between them and B_1 becomes lines (Eq. 7), the line along B_1 closes with
         Gamma_prev - Gamma_now, and Gamma_prev <- Gamma_now (before the first shed row
         Gamma_prev = 0: the starting vortex);
-     5. velocity at every boundary point and at the particles from the blade rings, every line
-        and the particles; particle stretching by the whole field (transposed scheme: the
-        particles' share plus J^T Gamma_p with J the rings' and lines' velocity gradient);
-     6. explicit Euler move: x += dt (u + v_inf), Gamma_p += dt dGamma_p/dt;
-     7. when more than n_rows line rows exist, the oldest row's trailed lines and the shed line
+     5. advance(dt): the boundary points and the particles (x, Gamma) move through the three
+        stages of the low-storage RK3 (Sec. II.B); the circulations of step 3 and the line
+        strengths stay fixed over the step, the blade follows its prescribed rotation;
+     6. when more than n_rows line rows exist, the oldest row's trailed lines and the shed line
         along the oldest boundary become particles (Eqs. 6-8, tip line = station n_span of the
-        same blade and row; shed lines one particle each);
-     8. azimuth += omega dt.
+        same blade and row; shed lines one particle each).
+
+    prescribed_gamma: ring circulations used instead of the solve (steps 2-3 skipped);
+    shed=False: the blade leaves no wake (steps 4 and 6 skipped), it only acts on particles.
     """
 
-    def __init__(self, geom, omega, v_inf, dt, core_radius, vatistas_n, sigma_p, n_tip, n_rows, n_max=64):
+    def __init__(self, geom, omega, v_inf, dt, core_radius, vatistas_n, sigma_p, n_tip, n_rows, n_max=64,
+                 prescribed_gamma=None, shed=True):
         self.g = {k: np.asarray(geom[k], dtype=np.float64) for k in ("c00", "c01", "c11", "c10", "colloc", "normal")}
         self.nb, self.nc, self.ns = geom["n_blades"], geom["n_chord"], geom["n_span"]
         self.te = np.asarray(geom["te"])
@@ -161,8 +171,12 @@ class StepOracle:
         self.rc, self.vn, self.sig, self.n_tip, self.n_rows, self.n_max = (float(core_radius), int(vatistas_n),
                                                                            float(sigma_p), int(n_tip),
                                                                            int(n_rows), int(n_max))
-        self.A0 = aic(self.g["c00"], self.g["c01"], self.g["c11"], self.g["c10"], self.g["colloc"],
-                      self.g["normal"], self.rc, self.vn)
+        self.fixed = None if prescribed_gamma is None else np.asarray(prescribed_gamma, dtype=np.float64).copy()
+        self.shed = bool(shed)
+        self.A0 = None
+        if self.fixed is None:
+            self.A0 = aic(self.g["c00"], self.g["c01"], self.g["c11"], self.g["c10"], self.g["colloc"],
+                          self.g["normal"], self.rc, self.vn)
         self.psi = 0.0
         self.bounds, self.rows, self.sheds = [], [], []  # sheds[r] along bounds[r] (None: not yet)
         self.gprev = np.zeros(self.nb * self.ns)
@@ -170,11 +184,16 @@ class StepOracle:
         self.sp = np.zeros(0)
         self.gamma = None
 
-    def _geom(self):
-        Rm = rot_z(self.psi)
+    def _geom(self, psi=None):
+        Rm = rot_z(self.psi if psi is None else psi)
         rg = {k: Rm @ v for k, v in self.g.items()}
         T = te_points(rg["c10"], rg["c11"], self.nb, self.nc, self.ns)
         return rg, T
+
+    def add_particles(self, x, g, s):
+        self.xp = np.concatenate([self.xp, np.asarray(x, dtype=np.float64)], 1)
+        self.gp = np.concatenate([self.gp, np.asarray(g, dtype=np.float64)], 1)
+        self.sp = np.concatenate([self.sp, np.asarray(s, dtype=np.float64)])
 
     def lines(self, pending=None):
         """All wake lines as (a, b, strength); `pending` adds the line along B_1."""
@@ -211,60 +230,109 @@ class StepOracle:
             u += _segments(a, b, g, y, self.rc, self.vn)
         return u
 
+    def _kutta_rings(self, T, gam):
+        """The wake row between the trailing edge T and the youngest boundary B_1, one ring per
+        trailing-edge panel carrying that panel's circulation: (T_k, T_k+1, B_1,k+1, B_1,k)."""
+        ns1 = self.ns + 1
+        B1 = self.bounds[0]
+        cs = [[], [], [], []]
+        for bl in range(self.nb):
+            lo = np.arange(bl * ns1, bl * ns1 + self.ns)
+            cs[0].append(T[:, lo])
+            cs[1].append(T[:, lo + 1])
+            cs[2].append(B1[:, lo + 1])
+            cs[3].append(B1[:, lo])
+        return ring_edges(*(np.concatenate(c, 1) for c in cs), gam[self.te])
+
+    def vortex_system(self, psi):
+        """Every straight vortex element at azimuth psi during a step, as (a, b, strength): the
+        blade rings with the circulations of the step, the Kutta row from the trailing edge to
+        B_1, the wake lines and the line along B_1 with Gamma_prev.  The Kutta row's front edges
+        cancel the blade's trailing-edge edges and its back edges cancel the line along B_1
+        (once a row has been shed), so the trailing edge carries no vorticity and the lines
+        stay attached to it while the blade turns."""
+        rg, T = self._geom(psi)
+        parts = [ring_edges(rg["c00"], rg["c01"], rg["c11"], rg["c10"], self.gamma)]
+        if self.bounds:
+            parts.append(self._kutta_rings(T, self.gamma))
+            parts.append(self.lines(self.gprev))
+        return tuple(np.concatenate([p[i] for p in parts], -1) for i in range(3))
+
+    def _rhs(self, psi):
+        """Velocity at every boundary point, velocity and stretching rate of every particle."""
+        a, b, g = self.vortex_system(psi)
+        pts = np.concatenate(self.bounds, 1) if self.bounds else np.zeros((3, 0))
+        up = _segments(a, b, g, pts, self.rc, self.vn) if pts.shape[1] else np.zeros((3, 0))
+        uq, dq = np.zeros((3, 0)), np.zeros((3, 0))
+        if self.xp.shape[1]:
+            if pts.shape[1]:
+                up += _eval_pairs(self.xp, self.gp, self.sp, x_tgt=pts)[0]
+            uq, dq = _eval_pairs(self.xp, self.gp, self.sp)
+            uq += _segments(a, b, g, self.xp, self.rc, self.vn)
+            # stretching by the rings' and lines' share of the velocity gradient (transposed)
+            J = _segments_gradient(a, b, g, self.xp, self.rc, self.vn)
+            dq += np.einsum("abn,an->bn", J, self.gp)
+        return up, uq, dq
+
+    def advance(self, h):
+        """Move the boundary points and the particles over the interval h (three RK3 stages,
+        the blade at its azimuth at each stage's time) and turn the blade by omega h."""
+        nbp = self.nb * (self.ns + 1)
+        qp = np.zeros((3, nbp * len(self.bounds)))
+        qx, qg = np.zeros_like(self.xp), np.zeros_like(self.gp)
+        vinf = self.v_inf[:, None]
+        for k in range(3):
+            up, uq, dq = self._rhs(self.psi + RK3_C[k] * self.omega * h)
+            if self.bounds:
+                qp = RK3_A[k] * qp + h * (up + vinf)
+                pts = np.concatenate(self.bounds, 1) + RK3_B[k] * qp
+                self.bounds = [pts[:, i * nbp:(i + 1) * nbp] for i in range(len(self.bounds))]
+            if self.xp.shape[1]:
+                qx = RK3_A[k] * qx + h * (uq + vinf)
+                qg = RK3_A[k] * qg + h * dq
+                self.xp = self.xp + RK3_B[k] * qx
+                self.gp = self.gp + RK3_B[k] * qg
+        self.psi += self.omega * h
+
     def step(self):
         rg, T = self._geom()
         ns1 = self.ns + 1
-        A = self.A0.copy()
-        if self.bounds:
-            B1 = self.bounds[0]
-            for bl in range(self.nb):
-                for k in range(self.ns):
-                    i0, i1 = bl * ns1 + k, bl * ns1 + k + 1
-                    cs = [T[:, i0:i0 + 1], T[:, i1:i1 + 1], B1[:, i1:i1 + 1], B1[:, i0:i0 + 1]]
-                    a, b, _ = ring_edges(*cs)
-                    u = _segments(a, b, np.ones(4), rg["colloc"], self.rc, self.vn)
-                    A[:, self.te[bl * self.ns + k]] += (u * rg["normal"]).sum(0)
-        u = self._induced(rg["colloc"], with_pending=True)
-        w = np.array([0.0, 0.0, self.omega])
-        vrel = self.v_inf[:, None] - np.cross(w, rg["colloc"].T).T + u
-        gam = solve(A, -(vrel * rg["normal"]).sum(0))
+        if self.fixed is None:
+            A = self.A0.copy()
+            if self.bounds:
+                B1 = self.bounds[0]
+                for bl in range(self.nb):
+                    for k in range(self.ns):
+                        i0, i1 = bl * ns1 + k, bl * ns1 + k + 1
+                        cs = [T[:, i0:i0 + 1], T[:, i1:i1 + 1], B1[:, i1:i1 + 1], B1[:, i0:i0 + 1]]
+                        a, b, _ = ring_edges(*cs)
+                        u = _segments(a, b, np.ones(4), rg["colloc"], self.rc, self.vn)
+                        A[:, self.te[bl * self.ns + k]] += (u * rg["normal"]).sum(0)
+            u = self._induced(rg["colloc"], with_pending=True)
+            w = np.array([0.0, 0.0, self.omega])
+            vrel = self.v_inf[:, None] - np.cross(w, rg["colloc"].T).T + u
+            gam = solve(A, -(vrel * rg["normal"]).sum(0))
+        else:
+            gam = self.fixed.copy()
         self.gamma = gam
-        # the trailing-edge points join the wake as its youngest boundary
-        had_wake = bool(self.bounds)
-        self.bounds.insert(0, T.copy())
-        self.sheds.insert(0, None)
-        if had_wake:
-            trs, shs = [], []
-            for bl in range(self.nb):
-                gte = gam[self.te[bl * self.ns:(bl + 1) * self.ns]]
-                tr, sh = shed(gte, self.gprev[bl * self.ns:(bl + 1) * self.ns])
-                trs.append(tr)
-                shs.append(sh)
-            self.rows.insert(0, np.concatenate(trs))  # between the trailing edge and B_1
-            self.sheds[1] = np.concatenate(shs)      # along B_1
-            self.gprev = gam[self.te].copy()
-        # velocity at every boundary point (the trailing edge included) and at the particles
-        pts = np.concatenate(self.bounds, 1)
-        a, b, gl = self.lines()
-        ra, rb, rgm = ring_edges(rg["c00"], rg["c01"], rg["c11"], rg["c10"], gam)
-        allA = np.concatenate([ra, a], 1)
-        allB = np.concatenate([rb, b], 1)
-        allG = np.concatenate([rgm, gl])
-        up = _segments(allA, allB, allG, pts, self.rc, self.vn)
-        if self.xp.shape[1]:
-            up += _eval_pairs(self.xp, self.gp, self.sp, x_tgt=pts)[0]
-            uq, dq = _eval_pairs(self.xp, self.gp, self.sp)
-            uq += _segments(allA, allB, allG, self.xp, self.rc, self.vn)
-            # stretching by the rings' and lines' share of the velocity gradient (transposed)
-            J = _segments_gradient(allA, allB, allG, self.xp, self.rc, self.vn)
-            dq += np.einsum("abn,an->bn", J, self.gp)
-            self.xp = self.xp + self.dt * (uq + self.v_inf[:, None])
-            self.gp = self.gp + self.dt * dq
-        pts = pts + self.dt * (up + self.v_inf[:, None])
-        nb_pts = T.shape[1]
-        self.bounds = [pts[:, i * nb_pts:(i + 1) * nb_pts] for i in range(len(self.bounds))]
+        if self.shed:
+            # the trailing-edge points join the wake as its youngest boundary
+            had_wake = bool(self.bounds)
+            self.bounds.insert(0, T.copy())
+            self.sheds.insert(0, None)
+            if had_wake:
+                trs, shs = [], []
+                for bl in range(self.nb):
+                    gte = gam[self.te[bl * self.ns:(bl + 1) * self.ns]]
+                    tr, sh = shed(gte, self.gprev[bl * self.ns:(bl + 1) * self.ns])
+                    trs.append(tr)
+                    shs.append(sh)
+                self.rows.insert(0, np.concatenate(trs))  # between the trailing edge and B_1
+                self.sheds[1] = np.concatenate(shs)      # along B_1
+                self.gprev = gam[self.te].copy()
+        self.advance(self.dt)
         # conversion of the oldest row
-        if len(self.rows) > self.n_rows:
+        if self.shed and len(self.rows) > self.n_rows:
             r = len(self.rows) - 1
             a = [self.bounds[r]]
             b = [self.bounds[r + 1]]
@@ -278,13 +346,10 @@ class StepOracle:
             tip.append(-np.ones(self.nb * self.ns, dtype=np.int64))
             x, g, s, _ = convert(np.concatenate(a, 1), np.concatenate(b, 1), np.concatenate(dg), np.concatenate(tip),
                                  self.n_tip, self.sig)
-            self.xp = np.concatenate([self.xp, x], 1)
-            self.gp = np.concatenate([self.gp, g], 1)
-            self.sp = np.concatenate([self.sp, s])
+            self.add_particles(x, g, s)
             del self.rows[r]
             del self.bounds[r + 1]
             del self.sheds[r + 1]
-        self.psi += self.omega * self.dt
         return gam
 
     def total_vorticity(self):

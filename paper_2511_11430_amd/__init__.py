@@ -438,16 +438,21 @@ def vpm_neumann_rhs(colloc, normal, u, v_inf, omega, *, rhs_out=None, stream=Non
     return rhs_out
 
 
-def vpm_advect(x, u, dt, v_inf=(0.0, 0.0, 0.0), *, gamma=None, dgamma=None, stream=None):
-    """x += dt (u + v_inf) (and gamma += dt dgamma) in place."""
+def vpm_rk3_advect(stage, x, qx, u, dt, v_inf=(0.0, 0.0, 0.0), *, gamma=None, qg=None, dgamma=None,
+                   stream=None):
+    """RK3 stage `stage` in place: qx = A_k qx + dt (u + v_inf), x += B_k qx (and the same for
+    gamma with qg, dgamma)."""
     lib = _lib.load()
     n = x.shape[1]
-    _vec(u, "u", n, x.dtype)
-    if _ld(u) != _ld(x) or (gamma is not None and (_ld(gamma) != _ld(x) or _ld(dgamma) != _ld(x))):
-        raise ValueError("x, u, gamma and dgamma must share one leading dimension")
-    st = lib.vpm_advect(_code(x), n, float(dt), _p(x), _p(u), _p(gamma), _p(dgamma), _ld(x), _host3(v_inf),
-                        _stream(stream))
-    _check("vpm_advect", st)
+    for t, name in ((qx, "qx"), (u, "u")) + (((qg, "qg"), (dgamma, "dgamma")) if gamma is not None else ()):
+        _vec(t, name, n, x.dtype)
+        if _ld(t) != _ld(x):
+            raise ValueError("x, qx, u (and gamma, qg, dgamma) must share one leading dimension")
+    if gamma is not None and _ld(gamma) != _ld(x):
+        raise ValueError("x, qx, u (and gamma, qg, dgamma) must share one leading dimension")
+    st = lib.vpm_rk3_advect(_code(x), int(stage), n, float(dt), _p(x), _p(qx), _p(u), _p(gamma), _p(qg),
+                            _p(dgamma), _ld(x), _host3(v_inf), _stream(stream))
+    _check("vpm_rk3_advect", st)
     return x
 
 

@@ -43,7 +43,7 @@ SIGNATURES = {
     "vpm_aic_update": (c_i32, [c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64,
                                c_vp, c_dbl, c_i32, c_vp]),
     "vpm_neumann_rhs": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
-    "vpm_advect": (c_i32, [c_i32, c_i64, c_dbl, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "vpm_rk3_advect": (c_i32, [c_i32, c_i32, c_i64, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]),
     "vpm_eval_segments": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_dbl, c_i32, c_i64, c_vp, c_i64,
                                   c_vp, c_i64, c_i32, c_vp]),
     "vpm_eval_segments_gradient": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_dbl, c_i32, c_i64, c_vp, c_vp,

@@ -39,6 +39,32 @@ __global__ __launch_bounds__(256) void k_rk3_stage(int stage, int64_t n, S dt, S
     }
 }
 
+// Stage k for points carried by the flow in a free stream (wake-line points, particles of the
+// closed step): Qx <- A_k Qx + dt (u + v_inf), x <- x + B_k Qx and, when g is given,
+// Qg <- A_k Qg + dt dg, g <- g + B_k Qg.  State and register are stored in T, the arithmetic
+// is FP64; stage 0 does not read the registers.  One thread per point, all three components.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rk3_advect(int stage, int64_t n, double dt, T* x, T* qx, const T* u,
+                                                    T* g, T* qg, const T* dg, int64_t ld, double v0, double v1,
+                                                    double v2) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double A = kRkA[stage], B = kRkB[stage];
+    const double v[3] = {v0, v1, v2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int64_t o = c * ld + i;
+        const double q = (stage ? A * double(qx[o]) : 0.0) + dt * (double(u[o]) + v[c]);
+        qx[o] = T(q);
+        x[o] = T(double(x[o]) + B * double(T(q)));
+        if (g) {
+            const double p = (stage ? A * double(qg[o]) : 0.0) + dt * double(dg[o]);
+            qg[o] = T(p);
+            g[o] = T(double(g[o]) + B * double(T(p)));
+        }
+    }
+}
+
 // Adjoint: qtot = Qbar + B_k Ybar;  seed = dt qtot;  Qbar <- A_k qtot.
 template <typename S, typename T>
 __global__ __launch_bounds__(256) void k_rk3_stage_bwd(int stage, int64_t n, S dt, const S* xb,
@@ -222,6 +248,21 @@ hipError_t launch_rk3_stage(int dtype, int state_dtype, int stage, int64_t n, do
         hipLaunchKernelGGL((k_rk3_stage<float, float>), dim3(grid), dim3(256), 0, st, stage, n, float(dt),
                            (float*)x, (float*)g, (float*)qx, (float*)qg, (const float*)u,
                            (const float*)dg, ld, (float*)xe, (float*)ge);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk3_advect(int dtype, int stage, int64_t n, double dt, void* x, void* qx, const void* u, void* g,
+                            void* qg, const void* dg, int64_t ld, const double* vinf, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const unsigned nb = unsigned((n + 255) / 256);
+    if (dtype == kDtypeF64)
+        hipLaunchKernelGGL(k_rk3_advect<double>, dim3(nb), dim3(256), 0, st, stage, n, dt, (double*)x, (double*)qx,
+                           (const double*)u, (double*)g, (double*)qg, (const double*)dg, ld, vinf[0], vinf[1],
+                           vinf[2]);
+    else
+        hipLaunchKernelGGL(k_rk3_advect<float>, dim3(nb), dim3(256), 0, st, stage, n, dt, (float*)x, (float*)qx,
+                           (const float*)u, (float*)g, (float*)qg, (const float*)dg, ld, vinf[0], vinf[1],
+                           vinf[2]);
     return hipGetLastError();
 }
 

@@ -647,19 +647,6 @@ __global__ __launch_bounds__(256) void k_neumann_rhs(int64_t n, const double* co
 }
 
 // Explicit Euler move of points: x += dt (u + v_inf); optionally g += dt dg.
-template <typename T>
-__global__ __launch_bounds__(256) void k_advect(int64_t n, double dt, T* x, const T* u, T* g, const T* dg, int64_t ld,
-                                                double v0, double v1, double v2) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double v[3] = {v0, v1, v2};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        x[c * ld + i] = T(double(x[c * ld + i]) + dt * (double(u[c * ld + i]) + v[c]));
-        if (g) g[c * ld + i] = T(double(g[c * ld + i]) + dt * double(dg[c * ld + i]));
-    }
-}
-
 }  // namespace
 
 hipError_t launch_aic(int64_t n, const double* c00, const double* c01, const double* c11, const double* c10,
@@ -815,18 +802,6 @@ hipError_t launch_neumann_rhs(int dtype, int64_t n, const double* col, const dou
     else
         hipLaunchKernelGGL(k_neumann_rhs<float>, dim3(nb), dim3(256), 0, st, n, col, nrm, ldc, (const float*)u, ldu,
                            vinf[0], vinf[1], vinf[2], omega[0], omega[1], omega[2], rhs);
-    return hipGetLastError();
-}
-
-hipError_t launch_advect(int dtype, int64_t n, double dt, void* x, const void* u, void* g, const void* dg, int64_t ld,
-                         const double* vinf, hipStream_t st) {
-    const unsigned nb = unsigned((n + 255) / 256);
-    if (dtype == kDtypeF64)
-        hipLaunchKernelGGL(k_advect<double>, dim3(nb), dim3(256), 0, st, n, dt, (double*)x, (const double*)u,
-                           (double*)g, (const double*)dg, ld, vinf[0], vinf[1], vinf[2]);
-    else
-        hipLaunchKernelGGL(k_advect<float>, dim3(nb), dim3(256), 0, st, n, dt, (float*)x, (const float*)u, (float*)g,
-                           (const float*)dg, ld, vinf[0], vinf[1], vinf[2]);
     return hipGetLastError();
 }
 

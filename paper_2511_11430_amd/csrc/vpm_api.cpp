@@ -1072,20 +1072,23 @@ vpm_status vpm_neumann_rhs(int32_t dtype, int64_t n, const double* colloc, const
                                               static_cast<hipStream_t>(stream)));
 }
 
-vpm_status vpm_advect(int32_t dtype, int64_t n, double dt, void* x, const void* u, void* gamma, const void* dgamma,
-                      int64_t ld, const double* v_inf, void* stream) {
+vpm_status vpm_rk3_advect(int32_t dtype, int32_t stage, int64_t n, double dt, void* x, void* qx, const void* u,
+                          void* gamma, void* qg, const void* dgamma, int64_t ld, const double* v_inf, void* stream) {
     if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (stage < 0 || stage > 2) return VPM_ERR_ENUM;
     if (n < 0 || ld < n || n > INT32_MAX || !(dt == dt) || fabs(dt) > 1e30) return VPM_ERR_SIZE;
     if (!v_inf) return VPM_ERR_NULL;
     if (n == 0) return VPM_OK;
-    if (!x || !u || (gamma && !dgamma)) return VPM_ERR_NULL;
+    if (!x || !qx || !u) return VPM_ERR_NULL;
+    if ((gamma == nullptr) != (qg == nullptr) || (gamma && !dgamma)) return VPM_ERR_NULL;
     const size_t es = elem_size(dtype);
-    const Range rx = span(x, 3, ld, n, es), rg = span(gamma, 3, ld, n, es);
-    const Range ins[2] = {span(u, 3, ld, n, es), span(dgamma, 3, ld, n, es)};
-    for (const Range& r : ins)
-        if (overlap(rx, r) || overlap(rg, r)) return VPM_ERR_ALIAS;
-    if (overlap(rx, rg)) return VPM_ERR_ALIAS;
-    return hip_status(vpm::launch_advect(dtype, n, dt, x, u, gamma, dgamma, ld, v_inf, static_cast<hipStream_t>(stream)));
+    const Range rs[6] = {span(x, 3, ld, n, es),     span(qx, 3, ld, n, es), span(gamma, 3, ld, n, es),
+                         span(qg, 3, ld, n, es),    span(u, 3, ld, n, es),  span(gamma ? dgamma : nullptr, 3, ld, n, es)};
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j)
+            if (overlap(rs[i], rs[j])) return VPM_ERR_ALIAS;
+    return hip_status(vpm::launch_rk3_advect(dtype, stage, n, dt, x, qx, u, gamma, qg, dgamma, ld, v_inf,
+                                             static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

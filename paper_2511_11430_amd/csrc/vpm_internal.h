@@ -165,8 +165,6 @@ hipError_t launch_aic_update(int64_t n, const double* base, int64_t ldb, double*
                              double rc, int vn, hipStream_t st);
 hipError_t launch_neumann_rhs(int dtype, int64_t n, const double* col, const double* nrm, int64_t ldc, const void* u,
                               int64_t ldu, const double* vinf, const double* omega, double* rhs, hipStream_t st);
-hipError_t launch_advect(int dtype, int64_t n, double dt, void* x, const void* u, void* g, const void* dg, int64_t ld,
-                         const double* vinf, hipStream_t st);
 size_t conv_workspace(int64_t n);
 hipError_t launch_wake_convert(int dtype, int64_t n, const void* a, const void* b, int64_t ld, const void* dg,
                                const int32_t* tip, int n_tip, int n_max, double sigma, int64_t capacity, void* xo,
@@ -176,6 +174,8 @@ hipError_t launch_wake_convert(int dtype, int64_t n, const void* a, const void* 
 hipError_t launch_rk3_stage(int dtype, int state_dtype, int stage, int64_t n, double dt, void* x, void* g,
                             void* qx, void* qg, const void* u, const void* dg, int64_t ld, void* xe, void* ge,
                             hipStream_t st);
+hipError_t launch_rk3_advect(int dtype, int stage, int64_t n, double dt, void* x, void* qx, const void* u, void* g,
+                            void* qg, const void* dg, int64_t ld, const double* vinf, hipStream_t st);
 hipError_t launch_rk3_stage_bwd(int dtype, int state_dtype, int stage, int64_t n, double dt, const void* xb,
                                 const void* gb, void* qxb, void* qgb, void* us, void* ds, int64_t ld,
                                 hipStream_t st);

@@ -1,5 +1,6 @@
-"""One explicit time step of the closed blade / wake / particle loop on the GPU (Sec. II.A,
-the adaptive conversion of Sec. II.C, the particle right-hand side of Sec. II.B).
+"""One time step of the closed blade / wake / particle loop on the GPU (Sec. II.A, the
+adaptive conversion of Sec. II.C, the particle right-hand side and the low-storage RK3 time
+integration of Sec. II.B).
 
 ``Step`` keeps the state in device memory and sequences libvpm calls; it does no arithmetic
 of its own beyond gathering and concatenating arrays (the blade's prescribed rotation is
@@ -16,13 +17,16 @@ turns at omega about z in the free stream v_inf:
     (vpm_eval_velocity_stretching, vpm_eval_segments, vpm_neumann_rhs, vpm_lu_solve);
  4. the trailing-edge points become the youngest boundary; when a wake existed, the row
     between them and B_1 becomes lines (vpm_wake_shed, Eq. 7);
- 5. velocity at every boundary point and at the particles (blade rings, lines, particles);
-    particle stretching by the whole field: the particles' share and J^T Gamma with J the
-    gradient of the rings' and lines' velocity (vpm_eval_segments_gradient);
- 6. explicit Euler move (vpm_advect);
- 7. beyond n_rows line rows, the oldest row and the shed line along the oldest boundary
+ 5. three stages of Williamson's low-storage RK3 move the boundary points and the particles
+    (x, Gamma) with vpm_rk3_advect.  Stage k evaluates at t + (0, 1/3, 3/4)[k] dt: the blade
+    at that azimuth with the circulations of step 3, the Kutta row from its trailing edge to
+    B_1 carrying the trailing-edge circulations, the wake lines with the line along B_1, and
+    the particles; velocity at every boundary point and particle, particle stretching by the
+    whole field (the particles' share and J^T Gamma with J the gradient of the segments'
+    velocity, vpm_eval_segments_gradient);
+ 6. beyond n_rows line rows, the oldest row and the shed line along the oldest boundary
     become particles (vpm_wake_convert, Eqs. 6-8);
- 8. azimuth += omega dt.
+ 7. azimuth += omega dt.
 
 Boundaries B_r are (3, n_blades * (n_span + 1)) point sets, station k of blade b at
 b * (n_span + 1) + k; trailed lines of the row between B_r and B_r+1 run downstream at every
@@ -33,9 +37,12 @@ import math
 import numpy as np
 import torch
 
-from . import (vpm_advect, vpm_aic_assemble, vpm_aic_update, vpm_eval_segments, vpm_eval_segments_gradient,
-               vpm_eval_velocity_stretching, vpm_lu_factor, vpm_lu_solve, vpm_neumann_rhs, vpm_wake_convert,
-               vpm_wake_shed)
+from . import (vpm_aic_assemble, vpm_aic_update, vpm_eval_segments, vpm_eval_segments_gradient,
+               vpm_eval_velocity_stretching, vpm_lu_factor, vpm_lu_solve, vpm_neumann_rhs, vpm_rk3_advect,
+               vpm_wake_convert, vpm_wake_shed)
+
+# Butcher nodes of the three-stage low-storage RK3: the times t + C_k dt of its stages.
+RK3_C = (0.0, 1.0 / 3.0, 3.0 / 4.0)
 
 
 def _rot_z(psi):
@@ -74,6 +81,8 @@ class Step:
         self.sp = torch.zeros(self.cap, dtype=dtype, device=self.dev)
         self.uq = torch.zeros_like(self.xp)
         self.dq = torch.zeros_like(self.xp)
+        self.qx = torch.zeros_like(self.xp)  # RK3 registers of the particles
+        self.qg = torch.zeros_like(self.xp)
         # two more streams (default priority) for the particle sums, which run beside the blade
         # solve (its LU keeps a few compute units busy at a time)
         # (overlap=False: everything on the caller's stream, in the same order)
@@ -90,8 +99,8 @@ class Step:
         self.span_hi = self.span_lo + 1
 
     # ------------------------------------------------------------------ helpers
-    def _geometry(self):
-        Rm = _rot_z(self.psi)
+    def _geometry(self, psi):
+        Rm = _rot_z(psi)
         g = {k: Rm @ v for k, v in self.g0.items()}
         ns1 = self.ns + 1
         T = np.empty((3, self.nb * ns1))
@@ -130,21 +139,39 @@ class Step:
         return torch.cat(A, 1).contiguous(), torch.cat(B, 1).contiguous(), torch.cat(G).contiguous()
 
     # ------------------------------------------------------------------ the step
+    def vortex_system(self, g, T):
+        """Segments (a, b, strength) of every vortex element during the step, with the blade at
+        the geometry g (trailing edge T): its rings carrying the step's circulations, the Kutta
+        row from T to B_1 carrying the trailing-edge circulations, the wake lines and the line
+        along B_1 with Gamma_prev."""
+        cat = lambda *c: torch.stack(c, 2).reshape(3, -1).to(self.dt_t)
+        segs = [(cat(g["c00"], g["c01"], g["c11"], g["c10"]), cat(g["c01"], g["c11"], g["c10"], g["c00"]),
+                 self.gamma.repeat_interleave(4).to(self.dt_t))]
+        if self.bounds:
+            lo, hi = self.span_lo, self.span_hi
+            B1, Tt = self.bounds[0], T.to(self.dt_t)
+            k00, k01, k11, k10 = Tt[:, lo], Tt[:, hi], B1[:, hi], B1[:, lo]
+            segs.append((cat(k00, k01, k11, k10), cat(k01, k11, k10, k00),
+                         self.gamma[self.te_d.long()].repeat_interleave(4).to(self.dt_t)))
+            segs.append(self.lines(self.gprev))
+        return [torch.cat([sg[i] for sg in segs], -1).contiguous() for i in range(3)]
+
     def step(self):
         main = torch.cuda.current_stream(self.dev)
         side = self.side or main
         side2 = self.side2 or main
         if self.np:
-            # The particles' contributions depend only on the particles at the start of the
-            # step: their self-interaction (the largest part of the step) starts first, on the
-            # second stream; their velocities at the collocation and boundary points follow on
-            # the third once the points are known.  The blade solve runs beside them on the
-            # main stream, which joins each result before adding the segments' shares.
+            # The particles' contributions to the solve and to the first stage depend only on
+            # the particles at the start of the step: their self-interaction (the largest part
+            # of the step) starts first, on the second stream; their velocities at the
+            # collocation and boundary points follow on the third once the points are known.
+            # The blade solve runs beside them on the main stream, which joins each result
+            # before adding the segments' shares.
             P = (self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np])
             side.wait_stream(main)
             with torch.cuda.stream(side):
                 vpm_eval_velocity_stretching(*P, u_out=self.uq[:, :self.np], dgamma_out=self.dq[:, :self.np])
-        g, T = self._geometry()
+        g, T = self._geometry(self.psi)
         T_t = T.to(self.dt_t)
         col_t = g["colloc"].to(self.dt_t)
         pts = torch.cat([T_t] + self.bounds, 1).contiguous()  # boundary points: the new line first
@@ -182,27 +209,37 @@ class Step:
             tr, sh = vpm_wake_shed(gam.to(self.dt_t), self.te_d, self.gprev, self.nb, self.ns)
             self.rows.insert(0, tr)
             self.sheds[1] = sh
-        # velocity at the boundary points and the particles
-        ca = torch.stack([g["c00"], g["c01"], g["c11"], g["c10"]], 2).reshape(3, -1)
-        cb = torch.stack([g["c01"], g["c11"], g["c10"], g["c00"]], 2).reshape(3, -1)
-        cg = gam.repeat_interleave(4)
-        segs = [ca.to(self.dt_t).contiguous(), cb.to(self.dt_t).contiguous(), cg.to(self.dt_t).contiguous()]
-        wl = self.lines()
-        if wl is not None:
-            segs = [torch.cat([segs[i], wl[i]], -1).contiguous() for i in range(3)]
-        if self.np:
-            main.wait_event(ev_pts)
-        vpm_eval_segments(segs[0], segs[1], segs[2], pts, self.rc, self.vn, u_out=up, accumulate=True)
-        if self.np:
-            xq, gq, sq = self.xp[:, :self.np], self.gp[:, :self.np], self.sp[:self.np]
-            uq, dq = self.uq[:, :self.np], self.dq[:, :self.np]
-            main.wait_stream(side)
-            vpm_eval_segments_gradient(segs[0], segs[1], segs[2], xq, self.rc, self.vn, gamma_tgt=gq,
-                                       want_grad=False, u_out=uq, dgamma_out=dq, accumulate=True)
-            vpm_advect(xq, uq, self.dt, self.v_inf, gamma=gq, dgamma=dq)
-        vpm_advect(pts, up, self.dt, self.v_inf)
+        # three RK3 stages for the boundary points and the particles
         nbp = T.shape[1]
-        self.bounds = [pts[:, i * nbp:(i + 1) * nbp].contiguous() for i in range(len(self.bounds))]
+        qp = torch.zeros_like(pts)
+        xq, gq = self.xp[:, :self.np], self.gp[:, :self.np]
+        uq, dq = self.uq[:, :self.np], self.dq[:, :self.np]
+        qx, qg = self.qx[:, :self.np], self.qg[:, :self.np]
+        for k in range(3):
+            if k:
+                g, T = self._geometry(self.psi + RK3_C[k] * self.omega * self.dt)
+                up = torch.zeros_like(pts)
+                if self.np:
+                    P = (xq, gq, self.sp[:self.np])
+                    side.wait_stream(main)
+                    with torch.cuda.stream(side):
+                        vpm_eval_velocity_stretching(*P, u_out=uq, dgamma_out=dq)
+                    side2.wait_stream(main)
+                    with torch.cuda.stream(side2):
+                        vpm_eval_velocity_stretching(*P, pts, u_out=up)
+                        ev_pts = side2.record_event()
+            segs = self.vortex_system(g, T)
+            if self.np:
+                main.wait_event(ev_pts)
+            vpm_eval_segments(segs[0], segs[1], segs[2], pts, self.rc, self.vn, u_out=up, accumulate=True)
+            if self.np:
+                main.wait_stream(side)
+                vpm_eval_segments_gradient(segs[0], segs[1], segs[2], xq, self.rc, self.vn, gamma_tgt=gq,
+                                           want_grad=False, u_out=uq, dgamma_out=dq, accumulate=True)
+                vpm_rk3_advect(k, xq, qx, uq, self.dt, self.v_inf, gamma=gq, qg=qg, dgamma=dq)
+            vpm_rk3_advect(k, pts, qp, up, self.dt, self.v_inf)
+            self.bounds = [pts[:, i * nbp:(i + 1) * nbp] for i in range(len(self.bounds))]
+        self.bounds = [b.contiguous() for b in self.bounds]
         if len(self.rows) > self.n_rows:
             r = len(self.rows) - 1
             sa, sb = self._span(self.bounds[r + 1])

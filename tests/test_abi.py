@@ -313,12 +313,18 @@ def test_step_kernels_validation():
     assert r(F64, 8, P(0), P(1), 8, P(2), 8, None, v3, P(3), None) == NULL
     assert r(F64, 8, P(0), P(1), 8, P(2), 8, v3, v3, P(0), None) == ALIAS
     assert r(F64, 0, None, None, 0, None, 0, v3, v3, None, None) == OK
-    a = lib.vpm_advect
-    assert a(F64, 8, 0.1, P(0), P(1), None, None, 7, v3, None) == SIZE
-    assert a(F64, 8, 0.1, P(0), None, None, None, 8, v3, None) == NULL
-    assert a(F64, 8, 0.1, P(0), P(1), P(2), None, 8, v3, None) == NULL
-    assert a(F64, 8, 0.1, P(0), P(0), None, None, 8, v3, None) == ALIAS
-    assert a(F64, 0, 0.1, None, None, None, None, 0, v3, None) == OK
+    a = lib.vpm_rk3_advect
+    assert a(F64, 0, 8, 0.1, P(0), P(5), P(1), None, None, None, 7, v3, None) == SIZE
+    assert a(F64, 3, 8, 0.1, P(0), P(5), P(1), None, None, None, 8, v3, None) == ENUM
+    assert a(7, 0, 8, 0.1, P(0), P(5), P(1), None, None, None, 8, v3, None) == DTYPE
+    assert a(F64, 0, 8, 0.1, P(0), P(5), None, None, None, None, 8, v3, None) == NULL
+    assert a(F64, 0, 8, 0.1, P(0), None, P(1), None, None, None, 8, v3, None) == NULL
+    assert a(F64, 0, 8, 0.1, P(0), P(5), P(1), P(2), None, P(3), 8, v3, None) == NULL
+    assert a(F64, 0, 8, 0.1, P(0), P(5), P(1), P(2), P(4), None, 8, v3, None) == NULL
+    assert a(F64, 0, 8, 0.1, P(0), P(5), P(1), None, None, None, 8, None, None) == NULL
+    assert a(F64, 0, 8, 0.1, P(0), P(5), P(0), None, None, None, 8, v3, None) == ALIAS
+    assert a(F64, 0, 8, 0.1, P(0), P(5), P(1), P(2), P(4), P(2), 8, v3, None) == ALIAS
+    assert a(F64, 1, 0, 0.1, None, None, None, None, None, None, 0, v3, None) == OK
 
 
 def test_segments_gradient_validation():
