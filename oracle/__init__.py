@@ -20,6 +20,7 @@ _lib = None
 
 TRANSPOSED, CLASSICAL = 0, 1
 SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
+STORE_F64, STORE_F32_EVAL, STORE_F32 = 0, 1, 2  # storage models of the RK3 program
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _lp = ctypes.POINTER(ctypes.c_int64)
@@ -40,9 +41,9 @@ def _load():
                                      i32, i32, _dp, _dp, _dp, _dp, i32]
         lib.orc_segments.argtypes = [i64, _dp, _dp, _dp, dbl, i32, i64, _dp, _dp, i32]
         lat = [i64, _dp, _dp, _dp, dbl, i32]
-        lib.orc_rk3_program.argtypes = [i64, _dp, _dp, _dp, i32, dbl, i32, i32, i64, _dp, _dp, _dp, i32] + lat
+        lib.orc_rk3_program.argtypes = [i64, _dp, _dp, _dp, i32, dbl, i32, i32, i64, _dp, _dp, _dp, i32] + lat + [i32]
         lib.orc_rk3_program_jvp.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, i32, dbl, i32, i32, i64, _dp,
-                                            _dp, _dp, i32] + lat
+                                            _dp, _dp, i32] + lat + [i32]
         lib.orc_segments_vjp.argtypes = [i64, _dp, _dp, _dp, dbl, i32, i64, _dp, _dp, _dp, _dp, i32, _dp, _dp, i32]
         lib.orc_fmm.argtypes = [i64, _dp, _dp, _dp, i32, i32, i32, _dp, _dp, _dp, i32]
         lib.orc_inv_r_taylor.argtypes = [_dp, i32, _dp, ctypes.POINTER(ctypes.c_int)]
@@ -273,11 +274,14 @@ def segments_vjp(a, b, gam_seg, x_tgt, core_radius, vatistas_n, u_bar, dgamma_ba
 
 
 def rk3_program(x, gam, sig, n_steps, dt, y_ctrl=None, scheme=TRANSPOSED, sigma_rule=SIGMA_SOURCE,
-                nthreads=0, segments=None):
+                nthreads=0, segments=None, storage=STORE_F64):
     """n_steps of low-storage RK3 (Williamson) on (x, Gamma), then the velocity at the
     control points y_ctrl and L = sum_c (u_c . z)^2.  Returns (x, gam, u_ctrl, L).
     ``segments`` = (a, b, gamma_seg, core_radius, vatistas_n): a fixed lattice whose velocity
-    and stretching act on the particles and whose velocity adds at the control points."""
+    and stretching act on the particles and whose velocity adds at the control points.
+    ``storage``: STORE_F64 (the exact program), STORE_F32_EVAL (every evaluation reads the
+    state rounded to FP32 and returns FP32 results; FP64 state) or STORE_F32 (state and
+    registers also rounded to FP32 after every update)."""
     lib = _load()
     lat, keep = _lattice(segments)
     X, G = _vec(x, "x").copy(), _vec(gam, "gam").copy()
@@ -289,15 +293,16 @@ def rk3_program(x, gam, sig, n_steps, dt, y_ctrl=None, scheme=TRANSPOSED, sigma_
     rc = lib.orc_rk3_program(X.shape[1], X.ctypes.data_as(_dp), G.ctypes.data_as(_dp), s.ctypes.data_as(_dp),
                              int(n_steps), float(dt), int(scheme), int(sigma_rule), m,
                              None if Y is None else Y.ctypes.data_as(_dp), uc.ctypes.data_as(_dp),
-                             ctypes.byref(L), int(nthreads), *lat)
+                             ctypes.byref(L), int(nthreads), *lat, int(storage))
     _check(rc, "rk3_program")
     del keep
     return X, G, uc[:, :m], L.value
 
 
 def rk3_program_jvp(x, gam, sig, x_dot, gam_dot, n_steps, dt, y_ctrl, scheme=TRANSPOSED,
-                    sigma_rule=SIGMA_SOURCE, nthreads=0, segments=None):
-    """Loss of :func:`rk3_program` and its directional derivative along (x_dot, gam_dot)."""
+                    sigma_rule=SIGMA_SOURCE, nthreads=0, segments=None, storage=STORE_F64):
+    """Loss of :func:`rk3_program` and its directional derivative along (x_dot, gam_dot)
+    (rounding, under the FP32 storage models, passes tangents through unchanged)."""
     lib = _load()
     lat, keep = _lattice(segments)
     X, G = _vec(x, "x"), _vec(gam, "gam")
@@ -308,7 +313,8 @@ def rk3_program_jvp(x, gam, sig, x_dot, gam_dot, n_steps, dt, y_ctrl, scheme=TRA
     rc = lib.orc_rk3_program_jvp(X.shape[1], X.ctypes.data_as(_dp), G.ctypes.data_as(_dp),
                                  s.ctypes.data_as(_dp), Xd.ctypes.data_as(_dp), Gd.ctypes.data_as(_dp),
                                  int(n_steps), float(dt), int(scheme), int(sigma_rule), Y.shape[1],
-                                 Y.ctypes.data_as(_dp), ctypes.byref(L), ctypes.byref(dL), int(nthreads), *lat)
+                                 Y.ctypes.data_as(_dp), ctypes.byref(L), ctypes.byref(dL), int(nthreads), *lat,
+                                 int(storage))
     _check(rc, "rk3_program_jvp")
     del keep
     return L.value, dL.value

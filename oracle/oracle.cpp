@@ -405,34 +405,64 @@ void add_segment_rhs(const Lattice& L, int64_t n, const Dual* x, const Dual* G, 
 const double kRkA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 const double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 
+// Storage model of the program (how the GPU programs in FP32 store their numbers):
+//   0  every quantity in FP64 (the exact program);
+//   1  each evaluation reads the state rounded to FP32 and its results are rounded to FP32
+//      (an FP32 result that a second contribution is added to is rounded again), the state
+//      and the registers stay FP64;
+//   2  as 1, and the registers and the state are rounded to FP32 after every update.
+// Rounding acts on values only: a tangent passes through it unchanged (the derivative of the
+// program in which rounding is the identity).
+inline double r32(double v) { return double(float(v)); }
+inline Dual r32(Dual v) { return Dual(double(float(v.v)), v.d); }
+
 template <class T>
 void rk3_program(int64_t n, T* x, T* G, const double* sig, int nsteps, double dt, int scheme,
-                 int sigma_rule, int64_t m, const double* y, T* uc, T* loss, const Lattice& lat) {
-    std::vector<T> qx(3 * n), qg(3 * n), fx(3 * n), fg(3 * n);
+                 int sigma_rule, int64_t m, const double* y, T* uc, T* loss, const Lattice& lat,
+                 int storage) {
+    std::vector<T> qx(3 * n), qg(3 * n), fx(3 * n), fg(3 * n), xe(3 * n), ge(3 * n);
     std::vector<int64_t> excl(n);
     for (int64_t i = 0; i < n; ++i) excl[i] = i;
+    auto round_all = [](std::vector<T>& v) { for (T& e : v) e = r32(e); };
+    // the evaluation input: the state itself, or its FP32 copy
+    auto eval_input = [&]() {
+        for (int64_t i = 0; i < 3 * n; ++i) {
+            xe[i] = storage ? r32(x[i]) : x[i];
+            ge[i] = storage ? r32(G[i]) : G[i];
+        }
+    };
     for (int step = 0; step < nsteps; ++step) {
         for (int64_t i = 0; i < 3 * n; ++i) { qx[i] = T(0.0); qg[i] = T(0.0); }
         for (int k = 0; k < 3; ++k) {
-            eval_pairs<T>(n, x, G, sig, n, x, G, sig, excl.data(), scheme, sigma_rule,
-                          fx.data(), fg.data());
-            if (lat.nseg > 0) add_segment_rhs(lat, n, x, G, scheme, fx.data(), fg.data());
+            eval_input();
+            eval_pairs<T>(n, xe.data(), ge.data(), sig, n, xe.data(), ge.data(), sig, excl.data(), scheme,
+                          sigma_rule, fx.data(), fg.data());
+            if (storage) { round_all(fx); round_all(fg); }
+            if (lat.nseg > 0) {
+                add_segment_rhs(lat, n, xe.data(), ge.data(), scheme, fx.data(), fg.data());
+                if (storage) { round_all(fx); round_all(fg); }
+            }
             for (int64_t i = 0; i < 3 * n; ++i) {
                 qx[i] = T(kRkA[k]) * qx[i] + T(dt) * fx[i];
                 qg[i] = T(kRkA[k]) * qg[i] + T(dt) * fg[i];
+                if (storage == 2) { qx[i] = r32(qx[i]); qg[i] = r32(qg[i]); }
                 x[i] = x[i] + T(kRkB[k]) * qx[i];
                 G[i] = G[i] + T(kRkB[k]) * qg[i];
+                if (storage == 2) { x[i] = r32(x[i]); G[i] = r32(G[i]); }
             }
         }
     }
     if (m > 0) {
+        eval_input();
         std::vector<T> yt(3 * m);
         for (int64_t i = 0; i < 3 * m; ++i) yt[i] = T(y[i]);
-        eval_pairs<T>(n, x, G, sig, m, yt.data(), nullptr, nullptr, nullptr, 0, 0, uc, nullptr);
+        eval_pairs<T>(n, xe.data(), ge.data(), sig, m, yt.data(), nullptr, nullptr, nullptr, 0, 0, uc, nullptr);
+        if (storage)
+            for (int64_t i = 0; i < 3 * m; ++i) uc[i] = r32(uc[i]);
         if (lat.nseg > 0) {
             std::vector<T> us(3 * m);
             eval_segments<T>(lat.nseg, lat.A, lat.B, lat.gam, lat.rc, lat.vn, m, yt.data(), us.data());
-            for (int64_t i = 0; i < 3 * m; ++i) uc[i] = uc[i] + us[i];
+            for (int64_t i = 0; i < 3 * m; ++i) uc[i] = storage ? r32(uc[i] + us[i]) : uc[i] + us[i];
         }
         Acc<T> l;
         for (int64_t c = 0; c < m; ++c) l.add(uc[2 * m + c] * uc[2 * m + c]);
@@ -1041,14 +1071,15 @@ int orc_segments_vjp(int64_t nseg, const double* A, const double* B, const doubl
 int orc_rk3_program(int64_t n, double* x, double* G, const double* sig, int nsteps, double dt,
                     int scheme, int sigma_rule, int64_t m, const double* y, double* uc,
                     double* loss, int nthreads, int64_t nseg, const double* A, const double* B,
-                    const double* gs, double rc, int vn) {
+                    const double* gs, double rc, int vn, int storage) {
     if (n < 0 || m < 0 || nsteps < 0 || !x || !G || !sig || !loss || (m > 0 && (!y || !uc)))
         return 1;
+    if (storage < 0 || storage > 2) return 1;
     if (nseg < 0 || (nseg > 0 && (!A || !B || !gs || !(rc >= 0.0) || vn < 1))) return 1;
     set_threads<double>(nthreads);
     Lattice lat;
     lat.nseg = nseg; lat.A = A; lat.B = B; lat.gam = gs; lat.rc = rc; lat.vn = vn;
-    rk3_program<double>(n, x, G, sig, nsteps, dt, scheme, sigma_rule, m, y, uc, loss, lat);
+    rk3_program<double>(n, x, G, sig, nsteps, dt, scheme, sigma_rule, m, y, uc, loss, lat, storage);
     return 0;
 }
 
@@ -1058,9 +1089,10 @@ int orc_rk3_program_jvp(int64_t n, const double* x, const double* G, const doubl
                         const double* xd, const double* Gd, int nsteps, double dt, int scheme,
                         int sigma_rule, int64_t m, const double* y, double* loss,
                         double* dloss, int nthreads, int64_t nseg, const double* A, const double* B,
-                        const double* gs, double rc, int vn) {
+                        const double* gs, double rc, int vn, int storage) {
     if (n < 0 || m < 0 || nsteps < 0 || !x || !G || !sig || !xd || !Gd || !loss || !dloss)
         return 1;
+    if (storage < 0 || storage > 2) return 1;
     if (m > 0 && !y) return 1;
     if (nseg < 0 || (nseg > 0 && (!A || !B || !gs || !(rc >= 0.0) || vn < 1))) return 1;
     set_threads<double>(nthreads);
@@ -1069,7 +1101,8 @@ int orc_rk3_program_jvp(int64_t n, const double* x, const double* G, const doubl
     std::vector<Dual> X(3 * n), Gm(3 * n), UC(3 * (m > 0 ? m : 1));
     for (int64_t i = 0; i < 3 * n; ++i) { X[i] = Dual(x[i], xd[i]); Gm[i] = Dual(G[i], Gd[i]); }
     Dual L;
-    rk3_program<Dual>(n, X.data(), Gm.data(), sig, nsteps, dt, scheme, sigma_rule, m, y, UC.data(), &L, lat);
+    rk3_program<Dual>(n, X.data(), Gm.data(), sig, nsteps, dt, scheme, sigma_rule, m, y, UC.data(), &L, lat,
+                      storage);
     *loss = L.v;
     *dloss = L.d;
     return 0;

@@ -285,6 +285,13 @@ def config4(n=262144, n_steps=10):
     return w
 
 
+def program_direction(n, k, gamma_scale):
+    """Seeded direction (x_dot, gamma_dot) in the space of a program's initial state:
+    x_dot ~ N(0, 1e-3) m, gamma_dot ~ N(0, gamma_scale) m^3/s per component."""
+    rng = _rng(4, 100 + k)
+    return rng.normal(0.0, 1e-3, (3, n)), rng.normal(0.0, gamma_scale, (3, n))
+
+
 def config5(n_wakes=64, n_min=2048, n_max=200000, scale=1.0):
     """64 independent helical wakes, N_w log-uniform in [n_min, n_max], 2-4 blades,
     sigma_w ~ U(0.01R, 0.05R) per wake.  ``scale`` shrinks every N_w (parity tests)."""

@@ -152,3 +152,39 @@ def test_program_with_lattice_tangent_matches_central_differences(scheme):
     assert dL == pytest.approx((Lp - Lm) / (2 * h), rel=1e-6)
     # without the lattice the loss differs (the lattice is felt)
     assert abs(oracle.rk3_program(x, g, s, nsteps, dt, y, scheme=scheme)[3] - L0) > 1e-3 * abs(L0)
+
+
+def test_fp32_storage_models_do_what_they_state():
+    """The program's FP32 storage models (test instruments that separate the GPU kernels' error
+    from the cost of FP32 storage): with the state and registers stored in FP32 every returned
+    state value is an FP32 number; with FP32 evaluations only the state stays FP64; both stay
+    within FP32 rounding of the exact program on a short program; with no step, the loss is
+    the sum of squares of the FP32-rounded control-point velocities."""
+    rng = np.random.default_rng(11)
+    n = 20
+    x = rng.uniform(-0.1, 0.1, (3, n)).astype(np.float32).astype(np.float64)
+    g = rng.normal(0, 1e-3, (3, n)).astype(np.float32).astype(np.float64)
+    s = np.full(n, 0.03)
+    y = rng.uniform(-0.1, 0.1, (3, 4))
+    dt = 2e-4
+    x0, g0, uc0, L0 = oracle.rk3_program(x, g, s, 3, dt, y)
+    x1, g1, uc1, L1 = oracle.rk3_program(x, g, s, 3, dt, y, storage=oracle.STORE_F32_EVAL)
+    x2, g2, uc2, L2 = oracle.rk3_program(x, g, s, 3, dt, y, storage=oracle.STORE_F32)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    assert np.array_equal(x2, f32(x2)) and np.array_equal(g2, f32(g2))
+    assert not np.array_equal(x1, f32(x1))  # FP64 state under FP32 evaluations
+    assert np.array_equal(uc1, f32(uc1)) and np.array_equal(uc2, f32(uc2))
+    for L in (L1, L2):
+        assert abs(L - L0) <= 1e-5 * abs(L0) and L != L0
+    assert np.abs(x1 - x0).max() <= 1e-6 and np.abs(x2 - x0).max() <= 1e-6
+    # no step: the loss of the rounded velocities
+    _, _, ucz, Lz = oracle.rk3_program(x, g, s, 0, dt, y, storage=oracle.STORE_F32_EVAL)
+    _, _, ucx, _ = oracle.rk3_program(x, g, s, 0, dt, y)
+    assert np.array_equal(ucz, f32(ucx))
+    assert Lz == pytest.approx(float((f32(ucx)[2] ** 2).sum()), rel=1e-15)
+    # a tangent passes the rounding unchanged: the storage models' tangents stay close to the
+    # exact program's
+    xd, gd = rng.normal(size=x.shape), rng.normal(size=x.shape) * 1e-3
+    d0 = oracle.rk3_program_jvp(x, g, s, xd, gd, 3, dt, y)[1]
+    d1 = oracle.rk3_program_jvp(x, g, s, xd, gd, 3, dt, y, storage=oracle.STORE_F32_EVAL)[1]
+    assert abs(d1 - d0) <= 1e-4 * abs(d0)
