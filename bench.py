@@ -12,7 +12,8 @@ wake (N_p = 1,048,576 particles, 4 blades, advance ratio 0.15, 20 revolutions):
 ``value`` is particle-pair interactions per second of the whole step (N_p^2 / step time).
 
 Also measured (same JSON line): the plain FP64 GPU path on the same particles (speedup),
-the adjoint/forward time ratio on the 262,144-particle hover wake, the batched
+the backward/forward time ratio of the 10-step differentiated program on the 262,144-particle
+hover wake (and of one adjoint call), the batched
 persistent launch of 64 uneven wakes vs 64 separate launches, the dominant kernel's
 roofline position, the error against the FP64 oracle on seeded sample targets, and the
 oracle's own throughput on the host cores (cpu_baseline).
@@ -73,6 +74,9 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20, help="particles (default: the full 1,048,576)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates rocprofv3 FETCH/WRITE_SIZE)")
+    ap.add_argument("--calib-fma", action="store_true",
+                    help="also run the library's FMA-chain kernel with a known FP32 FMA instruction count "
+                         "(calibrates rocprofv3's SQ_INSTS_VALU_* counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
@@ -152,6 +156,17 @@ def main():
     plan = vpm.vpm_get_plan(0, N)
     tpl, wg = vpm.vpm_variant_info(plan)
     pair_kernel = f"k_pair_fwd<float, {tpl} target(s)/lane, {wg} lanes, transposed, source rule> (shape {plan})"
+    if args.calib_fma:
+        import ctypes
+        lanes, fmas = 1 << 20, 1024
+        out = torch.empty(lanes, dtype=torch.float32, device=dev)
+        n_fma = ctypes.c_int64()
+        st_ = vpm._lib.load().vpm_fma_chain(lanes, fmas, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n_fma),
+                                            ctypes.c_void_p(stream.cuda_stream))
+        torch.cuda.synchronize()
+        log(f"calibration k_fma_chain: status {st_}, {n_fma.value} FP32 FMA wavefront instructions "
+            f"({lanes} lanes x 8 chains x {fmas})")
+        del out
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -202,12 +217,8 @@ def main():
     U, D = u.cpu().double().numpy(), dg.cpu().double().numpy()
     threads = len(os.sched_getaffinity(0))
     sample = c["sample"]
-    # calibrate the sample so the oracle runs ~15 s on the host cores
-    t = time.perf_counter()
-    oracle.eval_pairs(xs_h, gs_h, ss_h, x_tgt=xs_h[:, sample[:8]], gam_tgt=gs_h[:, sample[:8]], excl=sample[:8],
-                      nthreads=threads)
-    per_tgt = (time.perf_counter() - t) / 8
-    m = 64 if args.no_cpu_baseline else int(min(len(sample), max(64, 15.0 / max(per_tgt, 1e-6))))
+    # all seeded sample targets (4096 at the full size); --no-cpu-baseline keeps 64
+    m = 64 if args.no_cpu_baseline else len(sample)
     idx = sample[:m]
     log(f"oracle on {m} sample targets x {N} sources, {threads} threads")
     t = time.perf_counter()
@@ -215,20 +226,26 @@ def main():
                                nthreads=threads)
     t_or = time.perf_counter() - t
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def worst(a, b):
+        """largest single-target error, relative to the RMS magnitude of the reference"""
+        return float(np.sqrt(((a - b) ** 2).sum(0)).max() / np.sqrt((b * b).sum(0).mean()))
+
     result["accuracy"] = {"rel_l2_u": rel(U[:, idx], uo), "rel_l2_dgamma": rel(D[:, idx], do),
+                          "worst_target_u": worst(U[:, idx], uo), "worst_target_dgamma": worst(D[:, idx], do),
                           "sample_targets": m, "gate": 1e-5, "against": "FP64 oracle"}
-    # the symmetric core rule on the same wake: time and accuracy on the first 64 sample targets
+    # the symmetric core rule on the same wake: time and accuracy on the same sample targets
     if not args.quick:
         us, ds_ = torch.empty_like(u), torch.empty_like(dg)
         sym_ms = timed_once(lambda: vpm.vpm_eval_velocity_stretching(x, g, s, u_out=us, dgamma_out=ds_,
                                                                      sigma_rule=vpm.SIGMA_SYMMETRIC))
-        i64 = sample[:64]
-        uso, dso = oracle.eval_pairs(xs_h, gs_h, ss_h, x_tgt=xs_h[:, i64], gam_tgt=gs_h[:, i64], excl=i64,
-                                     sig_tgt=ss_h[i64], sigma_rule=oracle.SIGMA_SYMMETRIC, nthreads=threads)
+        uso, dso = oracle.eval_pairs(xs_h, gs_h, ss_h, x_tgt=xs_h[:, idx], gam_tgt=gs_h[:, idx], excl=idx,
+                                     sig_tgt=ss_h[idx], sigma_rule=oracle.SIGMA_SYMMETRIC, nthreads=threads)
         US, DS = us.cpu().double().numpy(), ds_.cpu().double().numpy()
         result["symmetric_rule"] = {"kernel_ms": round(sym_ms, 3), "gpair_s": round(pairs / (sym_ms * 1e-3) / 1e9, 2),
-                                    "rel_l2_u": rel(US[:, i64], uso), "rel_l2_dgamma": rel(DS[:, i64], dso),
-                                    "sample_targets": 64}
+                                    "rel_l2_u": rel(US[:, idx], uso), "rel_l2_dgamma": rel(DS[:, idx], dso),
+                                    "worst_target_u": worst(US[:, idx], uso),
+                                    "worst_target_dgamma": worst(DS[:, idx], dso), "sample_targets": m}
         del us, ds_
     if not args.no_cpu_baseline:
         # one core, 4 sample targets
@@ -276,16 +293,21 @@ def main():
         u64, d64 = torch.empty_like(x64), torch.empty_like(x64)
         vpm.vpm_eval_velocity_stretching(x64, g64, s64, u_out=u64, dgamma_out=d64)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        vpm.vpm_eval_velocity_stretching(x64, g64, s64, u_out=u64, dgamma_out=d64)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        f64_ms = e0.elapsed_time(e1)
+        f64_runs = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            vpm.vpm_eval_velocity_stretching(x64, g64, s64, u_out=u64, dgamma_out=d64)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            f64_runs.append(e0.elapsed_time(e1))
+        f64_ms = float(np.median(f64_runs))
         U64, D64 = u64.cpu().numpy(), d64.cpu().numpy()
-        result["fp64"] = {"kernel_ms": round(f64_ms, 2), "gpair_s": round(pairs / (f64_ms * 1e-3) / 1e9, 2),
+        result["fp64"] = {"kernel_ms": round(f64_ms, 2), "kernel_ms_min": round(float(np.min(f64_runs)), 2),
+                          "reps": len(f64_runs), "gpair_s": round(pairs / (f64_ms * 1e-3) / 1e9, 2),
                           "speedup_f32c_over_f64": round(f64_ms / k_ms, 3),
                           "rel_l2_u": rel(U64[:, idx], uo), "rel_l2_dgamma": rel(D64[:, idx], do),
+                          "worst_target_u": worst(U64[:, idx], uo), "worst_target_dgamma": worst(D64[:, idx], do),
                           "gate": 1e-12}
         del x64, g64, s64, u64, d64
 
@@ -334,8 +356,8 @@ def main():
 
         # ------------------------------------------------------------------ closed solver step
         # hover lattice (2 x 8 x 32 rings) turning in its own 65,536-particle wake (FP32C wake,
-        # FP64 blade solve): influence update + LU + solve, shedding, velocities, Euler move,
-        # conversion of the oldest row (Eqs. 6-8)
+        # FP64 blade solve): influence update + LU + solve, shedding, three RK3 stages of the
+        # wake (velocities and stretching at each), conversion of the oldest row (Eqs. 6-8)
         from paper_2511_11430_amd.solver import Step
         c2 = W.config2()
         geom = W.blade_rings()
@@ -387,12 +409,50 @@ def main():
                                                                   u_out=ua, dgamma_out=da, accumulate=True))
         seg_bwd_ms = timed(lambda: vpm.vpm_segments_backward(la, lb, lg, xa, lrc, 2, ub, db, gamma_tgt=ga,
                                                              x_bar=xb, gamma_bar=gb))
-        result["adjoint"] = {"workload": c4["name"], "fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3),
-                             "bwd_over_fwd": round(bwd_ms / fwd_ms, 3), "target": 3.0,
+        # the differentiation workload's whole program: 10 RK3 steps (30 stages) on the
+        # 262,144-particle hover wake and the loss on 128 control points, forward with every
+        # stage's input kept in HBM, then the backward pass over the checkpoints
+        from paper_2511_11430_amd import autograd as AG
+        y4 = torch.tensor(np.ascontiguousarray(W.to_f32(c4["ctrl"])), dtype=torch.float32, device=dev)
+        programs = {}
+        for kind, sdt in (("mixed", torch.float64), ("f32c", torch.float32)):
+            X4, G4 = xa.to(sdt), ga.to(sdt)
+
+            def run_fwd(ck):
+                return AG.rk3_forward(X4, G4, sa4, c4["n_steps"], c4["dt"], y4, checkpoints=ck)
+
+            run_fwd(None)
+            torch.cuda.synchronize()
+            t0p = time.perf_counter()
+            run_fwd(None)
+            torch.cuda.synchronize()
+            plain_ms = (time.perf_counter() - t0p) * 1e3
+            ck = []
+            t0p = time.perf_counter()
+            _, _, ucp, lossp, fin = run_fwd(ck)
+            torch.cuda.synchronize()
+            pf_ms = (time.perf_counter() - t0p) * 1e3
+            t0p = time.perf_counter()
+            AG.rk3_backward(ck, fin, sa4, ucp, y4, c4["dt"], sdt)
+            torch.cuda.synchronize()
+            pb_ms = (time.perf_counter() - t0p) * 1e3
+            ck_mb = sum(a.numel() * a.element_size() + b.numel() * b.element_size() for a, b in ck) / 2 ** 20
+            programs[kind] = {"state": "FP64 state, FP32C sums" if kind == "mixed" else "FP32 state, FP32C sums",
+                              "forward_ms": round(plain_ms, 1), "forward_with_checkpoints_ms": round(pf_ms, 1),
+                              "backward_ms": round(pb_ms, 1), "bwd_over_fwd": round(pb_ms / pf_ms, 3),
+                              "checkpoints_mib": round(ck_mb, 1), "stages": len(ck)}
+            log(f"program {kind}: forward {pf_ms:.0f} ms, backward {pb_ms:.0f} ms")
+            del ck, fin, ucp, X4, G4
+        result["adjoint"] = {"workload": c4["name"] + ", 128 control points",
+                             "program": programs, "program_bwd_over_fwd": programs["mixed"]["bwd_over_fwd"],
+                             "target": 3.0,
+                             "single_call": {"what": "one vpm_backward against one forward evaluation",
+                                             "fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3),
+                                             "bwd_over_fwd": round(bwd_ms / fwd_ms, 3)},
                              "lattice": {"n_segments": int(la.shape[1]), "fwd_ms": round(seg_fwd_ms, 3),
                                          "bwd_ms": round(seg_bwd_ms, 3),
                                          "bwd_over_fwd": round(seg_bwd_ms / seg_fwd_ms, 3)}}
-        del xa, ga, sa4, ua, da, ub, db, xb, gb, la, lb, lg
+        del xa, ga, sa4, ua, da, ub, db, xb, gb, la, lb, lg, y4
 
         # ------------------------------------------------------------------ batched persistent
         wakes = W.config5()
