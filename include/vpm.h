@@ -59,7 +59,7 @@ typedef enum vpm_status {
     VPM_ERR_OFFSETS = 6,     /* batch offsets not starting at 0, decreasing, or mismatched */
     VPM_ERR_WORKSPACE = 7,   /* workspace NULL or smaller than required */
     VPM_ERR_HIP = 8,         /* the HIP runtime reported an error */
-    VPM_ERR_INPUT = 9,       /* reserved: invalid input values found on the device */
+    VPM_ERR_INPUT = 9,       /* invalid input values found on the device (vpm_check_inputs) */
     VPM_ERR_UNSUPPORTED = 10 /* valid combination that this library does not implement */
 } vpm_status;
 
@@ -277,16 +277,26 @@ vpm_status vpm_fmm_eval(int32_t dtype, int64_t n, const void* x, const void* gam
 size_t vpm_fmm_workspace_size(int32_t dtype, int64_t n, int32_t level, int32_t order);
 
 /* ---------------------------------------------------------------------------------------
- * vpm_backward — vector-Jacobian product of vpm_eval_velocity_stretching (transposed
- * scheme, n_batch == 1): given seeds u_bar [3][ld_tgt] and dgamma_bar [3][ld_tgt] on the
- * outputs, ADD dL/dx and dL/dGamma to the gradient arrays.  sigma is not differentiated.
+ * vpm_backward — vector-Jacobian product of vpm_eval_velocity_stretching (Eqs. 2-5, both
+ * stretching schemes of opt->scheme, both core rules, one set or n_batch independent sets):
+ * given seeds u_bar [3][ld_tgt] and dgamma_bar [3][ld_tgt] on the outputs, ADD dL/dx and
+ * dL/dGamma to the gradient arrays.  sigma is not differentiated.
  *  With opt->self: sources are targets; the gradients are x_src_bar and gamma_src_bar, each
  *  particle gathering its contributions both as target and as source.  x_tgt_bar and
  *  gamma_tgt_bar must be NULL.
  *  Without self: x_src_bar/gamma_src_bar receive the source gradients (required);
  *  x_tgt_bar/gamma_tgt_bar receive the target gradients (both NULL to skip).
  *  dgamma_bar NULL: only velocities are seeded (gamma_tgt may then be NULL).
- * Gradient arrays are [3][ld_src] / [3][ld_tgt] and must not overlap inputs. */
+ *  n_batch > 1: sets b = [src_off[b], src_off[b+1]) (targets by tgt_off, or the same sets
+ *  with self) do not interact; one persistent launch per lane role pops (set, block) items in
+ *  decreasing cost from a queue kept in the workspace, which must hold
+ *  vpm_backward_workspace_size() bytes and is overwritten.  The classical scheme with
+ *  stretching seeds runs three launches per set (its pair term is the transposed one with
+ *  the target strength and its seed exchanged) and needs no workspace.
+ * Gradient arrays are [3][ld_src] / [3][ld_tgt] and must not overlap inputs or the workspace.
+ * Errors: VPM_ERR_DTYPE, VPM_ERR_ENUM (options), VPM_ERR_SIZE (n_batch < 1, ld < n, more than
+ * INT32_MAX particles), VPM_ERR_OFFSETS, VPM_ERR_NULL, VPM_ERR_ALIAS, VPM_ERR_WORKSPACE
+ * (n_batch > 1 with a missing or short workspace), VPM_ERR_HIP. */
 vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                         const int64_t* tgt_off, const void* x_src, const void* gamma_src,
                         const void* sigma_src, int64_t ld_src, const void* x_tgt,
@@ -294,6 +304,10 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                         const void* u_bar, const void* dgamma_bar, void* x_src_bar,
                         void* gamma_src_bar, void* x_tgt_bar, void* gamma_tgt_bar,
                         const vpm_options* opt, void* workspace, size_t ws_bytes, void* stream);
+
+/* vpm_backward_workspace_size — bytes of workspace vpm_backward needs for these offsets
+ * (0 for one set; tgt_off NULL: the sets of src_off); 0 also for invalid arguments. */
+size_t vpm_backward_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off, const int64_t* tgt_off);
 
 /* ---------------------------------------------------------------------------------------
  * Blade solve and wake management of one NL-UVLM-VPM step (Sec. II.A; Sec. II.C, Eqs. 6-8).
@@ -441,6 +455,14 @@ size_t vpm_diagnostics_workspace_size(void);
 vpm_status vpm_validate_inputs(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* sigma,
                                int64_t ld, double* out, void* workspace, size_t ws_bytes, void* stream);
 
+/* vpm_check_inputs — synchronous form of vpm_validate_inputs for callers that want a status:
+ * runs the same device check, waits for the stream, and returns VPM_ERR_INPUT when any sigma
+ * is not finite and positive or any entry of x or Gamma is not finite (VPM_OK otherwise).
+ * workspace: device memory of vpm_check_inputs_workspace_size() bytes (overwritten). */
+vpm_status vpm_check_inputs(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* sigma,
+                            int64_t ld, void* workspace, size_t ws_bytes, void* stream);
+size_t vpm_check_inputs_workspace_size(void);
+
 /* ---------------------------------------------------------------------------------------
  * vpm_axial_loss — the blade-point loss used for wake gradients: L = sum_c (u_c . z)^2 over
  * m control-point velocities u [3][ld] (u_c from vpm_eval_velocity_stretching with the
@@ -458,6 +480,22 @@ vpm_status vpm_axial_loss(int32_t dtype, int64_t m, const void* u, int64_t ld, d
 int32_t vpm_variant_count(void);
 vpm_status vpm_variant_info(int32_t k, int32_t* targets_per_lane, int32_t* workgroup);
 
+/* vpm_autotune — the kernel-shape tuner (FP32C only): times every shape of the particle
+ * kernel (vpm_variant_count of them) on the caller's particle set(s) — a self evaluation of
+ * n_batch sets with offsets src_off (host int64[n_batch+1]), x, gamma, sigma [3][ld] — with
+ * HIP events on `stream`, reps timed runs each after one untimed run, keeps the fastest
+ * (minimum over the runs) and records it in the plan for launches of that many targets
+ * (single-set or batched, as vpm_set_plan).  u_scratch, dgamma_scratch [3][ld] receive
+ * results and are overwritten; workspace as for vpm_eval_velocity_stretching (required when
+ * n_batch > 1).  variant_out (host, may be NULL) receives the chosen variant (1-based), ms_out
+ * (host float[vpm_variant_count()], may be NULL) each shape's best time in ms.  A setup call:
+ * it synchronises the stream after each timed run and creates (and destroys) two events; it
+ * allocates no device memory.  Errors: VPM_ERR_DTYPE (not FP32C), VPM_ERR_SIZE (n_batch < 1,
+ * no particle, reps outside 1..1000), those of vpm_eval_velocity_stretching, VPM_ERR_HIP. */
+vpm_status vpm_autotune(int32_t dtype, int32_t n_batch, const int64_t* src_off, const void* x, const void* gamma,
+                        const void* sigma, int64_t ld, void* u_scratch, void* dgamma_scratch, void* workspace,
+                        size_t ws_bytes, int32_t reps, int32_t* variant_out, float* ms_out, void* stream);
+
 /* Kernel-shape plan used when opt->variant is 0 (FP32C only): for target counts in
  * [n_lo, n_hi] (rounded out to powers of two), single-set (batched = 0) or batched
  * (batched = 1, counted over all sets) launches use variant k (0 restores the default, 1).
@@ -465,6 +503,16 @@ vpm_status vpm_variant_info(int32_t k, int32_t* targets_per_lane, int32_t* workg
  * launch of n targets would use. */
 vpm_status vpm_set_plan(int32_t dtype, int32_t batched, int64_t n_lo, int64_t n_hi, int32_t variant);
 int32_t vpm_get_plan(int32_t dtype, int32_t batched, int64_t n);
+
+/* vpm_fma_chain — calibration kernel for hardware counters (not part of the method): n_lanes
+ * lanes each run 8 independent chains of fmas_per_chain dependent FP32 fused multiply-adds
+ * (a multiple of 4) and store one float to out (device float[n_lanes]).  fma_instructions
+ * (host, may be NULL) receives the number of FP32 FMA instructions the launch issues,
+ * ceil(n_lanes / 64) x 8 x fmas_per_chain wavefront instructions, against which counter
+ * readings (e.g. rocprofv3's SQ_INSTS_VALU_FMA_F32) are scaled.  Errors: VPM_ERR_SIZE,
+ * VPM_ERR_NULL, VPM_ERR_HIP. */
+vpm_status vpm_fma_chain(int64_t n_lanes, int32_t fmas_per_chain, float* out, int64_t* fma_instructions,
+                         void* stream);
 
 /* Human-readable name of a status code (static string). */
 const char* vpm_status_string(int32_t status);

@@ -14,6 +14,7 @@ import ctypes
 from . import _lib
 
 F64, F32C = 0, 1
+INPUT_ERROR = 9  # VPM_ERR_INPUT
 TRANSPOSED, CLASSICAL = 0, 1
 SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1
 
@@ -638,9 +639,11 @@ def vpm_fmm_eval(x, gamma, sigma, level, order, *, scheme=TRANSPOSED, u_out=None
 
 def vpm_backward(x_src, gamma_src, sigma_src, u_bar, dgamma_bar=None, x_tgt=None, gamma_tgt=None,
                  sigma_tgt=None, *, x_src_bar=None, gamma_src_bar=None, x_tgt_bar=None, gamma_tgt_bar=None,
-                 want_target_grads=False, sigma_rule=SIGMA_SOURCE, stream=None):
-    """Vector-Jacobian product of :func:`vpm_eval_velocity_stretching` (transposed scheme).
-    Gradients are accumulated into the given arrays (zero-initialised when allocated here).
+                 want_target_grads=False, scheme=TRANSPOSED, sigma_rule=SIGMA_SOURCE, src_off=None, tgt_off=None,
+                 workspace=None, stream=None):
+    """Vector-Jacobian product of :func:`vpm_eval_velocity_stretching` (either stretching
+    scheme; src_off / tgt_off: many independent sets, as in the forward call).  Gradients are
+    accumulated into the given arrays (zero-initialised when allocated here).
     Returns (x_src_bar, gamma_src_bar, x_tgt_bar, gamma_tgt_bar)."""
     torch = _torch()
     lib = _lib.load()
@@ -668,14 +671,24 @@ def vpm_backward(x_src, gamma_src, sigma_src, u_bar, dgamma_bar=None, x_tgt=None
             x_tgt_bar = torch.zeros((3, n_tgt), dtype=tdt, device=dev)
         if gamma_tgt_bar is None and dgamma_bar is not None:
             gamma_tgt_bar = torch.zeros((3, n_tgt), dtype=tdt, device=dev)
-    so = _offsets([0, n_src])
-    to = None if self_eval else _offsets([0, n_tgt])
-    o = _opts(TRANSPOSED, sigma_rule, self_eval, 1, 0)
-    st = lib.vpm_backward(dt, 1, so, to, _p(x_src), _p(gamma_src), _p(sigma_src), _ld(x_src),
+    so = _offsets([0, n_src] if src_off is None else src_off)
+    nb = len(so) - 1
+    if self_eval:
+        to = None
+    else:
+        to = _offsets([0, n_tgt] if tgt_off is None else tgt_off)
+        if len(to) != len(so):
+            raise ValueError("src_off and tgt_off must have the same length")
+    if nb > 1 and workspace is None:
+        need = lib.vpm_backward_workspace_size(dt, nb, so, to)
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    o = _opts(scheme, sigma_rule, self_eval, 1, 0)
+    st = lib.vpm_backward(dt, nb, so, to, _p(x_src), _p(gamma_src), _p(sigma_src), _ld(x_src),
                           None if self_eval else _p(x_tgt), None if self_eval else _p(gamma_tgt),
                           None if self_eval else _p(sigma_tgt), 0 if self_eval else _ld(x_tgt), _p(u_bar),
                           _p(dgamma_bar), _p(x_src_bar), _p(gamma_src_bar), _p(x_tgt_bar), _p(gamma_tgt_bar),
-                          ctypes.byref(o), None, 0, _stream(stream))
+                          ctypes.byref(o), _p(workspace), 0 if workspace is None else workspace.numel(),
+                          _stream(stream))
     _check("vpm_backward", st)
     return x_src_bar, gamma_src_bar, x_tgt_bar, gamma_tgt_bar
 
@@ -801,6 +814,55 @@ def vpm_set_plan(batched, n_lo, n_hi, variant):
 
 def vpm_get_plan(batched, n):
     return int(_lib.load().vpm_get_plan(F32C, int(batched), int(n)))
+
+
+def vpm_check_inputs(x, gamma, sigma, *, workspace=None, stream=None):
+    """Synchronous input check: True when every sigma is finite and positive and every entry of
+    x and Gamma is finite, False when the library reports VPM_ERR_INPUT."""
+    torch = _torch()
+    lib = _lib.load()
+    n = x.shape[1]
+    _vec(x, "x", dtype=x.dtype)
+    _vec(gamma, "gamma", n, x.dtype)
+    _scal(sigma, "sigma", n, x.dtype)
+    if n and gamma.stride(0) != x.stride(0):
+        raise ValueError("x and gamma must share one leading dimension")
+    if workspace is None:
+        workspace = torch.empty(int(lib.vpm_check_inputs_workspace_size()), dtype=torch.uint8, device=x.device)
+    st = lib.vpm_check_inputs(_code(x), n, _p(x), _p(gamma), _p(sigma), _ld(x), _p(workspace),
+                              workspace.numel() * workspace.element_size(), _stream(stream))
+    if st == INPUT_ERROR:
+        return False
+    _check("vpm_check_inputs", st)
+    return True
+
+
+def vpm_autotune(x, gamma, sigma, *, src_off=None, reps=3, u_scratch=None, dgamma_scratch=None, workspace=None,
+                 stream=None):
+    """Times every FP32C kernel shape on these particles (self evaluation; src_off: many sets)
+    inside the library and records the fastest in its plan.  Returns (variant, [ms per shape])."""
+    torch = _torch()
+    lib = _lib.load()
+    n = x.shape[1]
+    _vec(x, "x", dtype=torch.float32)
+    _vec(gamma, "gamma", n, torch.float32)
+    _scal(sigma, "sigma", n, torch.float32)
+    if u_scratch is None:
+        u_scratch = torch.empty_like(x)
+    if dgamma_scratch is None:
+        dgamma_scratch = torch.empty_like(x)
+    off = [0, n] if src_off is None else list(src_off)
+    so = _offsets(off)
+    if workspace is None and len(off) > 2:
+        workspace = torch.empty(max(vpm_workspace_size(F32C, off), 1), dtype=torch.uint8, device=x.device)
+    nv = vpm_variant_count()
+    ms = (ctypes.c_float * nv)()
+    v = ctypes.c_int32()
+    st = lib.vpm_autotune(F32C, len(off) - 1, so, _p(x), _p(gamma), _p(sigma), _ld(x), _p(u_scratch),
+                          _p(dgamma_scratch), _p(workspace), 0 if workspace is None else workspace.numel(),
+                          int(reps), ctypes.byref(v), ms, _stream(stream))
+    _check("vpm_autotune", st)
+    return v.value, [float(t) for t in ms]
 
 
 def vpm_variant_count():

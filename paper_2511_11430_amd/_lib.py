@@ -62,6 +62,12 @@ SIGNATURES = {
     "vpm_convert": (c_i32, [c_i32, c_i32, c_i64, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp]),
     "vpm_diagnostics": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "vpm_diagnostics_workspace_size": (c_sz, []),
+    "vpm_backward_workspace_size": (c_sz, [c_i32, c_i32, c_i64p, c_i64p]),
+    "vpm_check_inputs": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]),
+    "vpm_check_inputs_workspace_size": (c_sz, []),
+    "vpm_fma_chain": (c_i32, [c_i64, c_i32, c_vp, c_i64p, c_vp]),
+    "vpm_autotune": (c_i32, [c_i32, c_i32, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_i32,
+                             ctypes.POINTER(c_i32), ctypes.POINTER(ctypes.c_float), c_vp]),
     "vpm_validate_inputs": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "vpm_axial_loss": (c_i32, [c_i32, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "vpm_variant_count": (c_i32, []),

@@ -1,5 +1,8 @@
 // Adjoint (vector-Jacobian product) of the particle sums of Eqs. 2-5 (Fu & Laurendeau,
-// Sec. II.B), transposed stretching scheme, written out by hand.
+// Sec. II.B), transposed stretching scheme, written out by hand.  (The classical scheme's
+// adjoint is composed from this kernel and the forward kernel on the host side: its pair
+// term S.(J Gamma_i) equals the transposed term Gamma_i.(J^T S) with the target strength and
+// the stretching seed exchanged.)
 //
 // One pair (target i, source j, r = x_i - x_j) contributes, for seeds (ub_i, Sb_i) on
 // (u_i, dGamma_i/dt), with v = Gamma_j x r, w = Gamma_i x Gamma_j, a = ub_i.v, b = Sb_i.w,
@@ -295,8 +298,11 @@ __device__ __forceinline__ void box_reduce(T (&v)[7], T* scratch) {
     }
 }
 
+// One workgroup's lane block blk of a lane set [lb, lb + nl) against the loop set
+// [ob, ob + no) (indices into the arrays of a; with a.self both sets are the same range).
 template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
-__device__ __forceinline__ void backward_body(const BwdArgs& a) {
+__device__ __forceinline__ void backward_body(const BwdArgs& a, int64_t blk, int64_t lb, int64_t nl, int64_t ob,
+                                              int64_t no) {
     using B = Bwd<T, WG, RA, RB, STR, SYM>;
     constexpr int kN = B::kN;
     constexpr bool kComp = B::kComp;
@@ -306,21 +312,23 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a) {
     __shared__ V4<T> l3[(RB && STR) ? WG : 1];  // Sb_q
     __shared__ V4<T> l4[(RB && STR) ? WG : 1];  // Sb_q x Gamma_q
     __shared__ T box[7 * (WG / 64)];
-    const T* __restrict__ xl = static_cast<const T*>(a.xl);
-    const T* __restrict__ gl = static_cast<const T*>(a.gl);
-    const T* __restrict__ sl = static_cast<const T*>(a.sl);
-    const T* __restrict__ ubl = static_cast<const T*>(a.ubl);
-    const T* __restrict__ sbl = static_cast<const T*>(a.sbl);
-    const T* __restrict__ xo = static_cast<const T*>(a.xo);
-    const T* __restrict__ go = static_cast<const T*>(a.go);
-    const T* __restrict__ so = static_cast<const T*>(a.so);
-    const T* __restrict__ ubo = static_cast<const T*>(a.ubo);
-    const T* __restrict__ sbo = static_cast<const T*>(a.sbo);
+    // the set bases are folded into the pointers (null pointers stay null)
+    auto at = [](const void* q, int64_t base) { return q ? static_cast<const T*>(q) + base : nullptr; };
+    const T* __restrict__ xl = at(a.xl, lb);
+    const T* __restrict__ gl = at(a.gl, lb);
+    const T* __restrict__ sl = at(a.sl, lb);
+    const T* __restrict__ ubl = at(a.ubl, lb);
+    const T* __restrict__ sbl = at(a.sbl, lb);
+    const T* __restrict__ xo = at(a.xo, ob);
+    const T* __restrict__ go = at(a.go, ob);
+    const T* __restrict__ so = at(a.so, ob);
+    const T* __restrict__ ubo = at(a.ubo, ob);
+    const T* __restrict__ sbo = at(a.sbo, ob);
     const T far2 = T(Prec<T>::kFarRho2);
     const int tid = threadIdx.x;
-    const int64_t pb0 = int64_t(blockIdx.x) * WG;
+    const int64_t pb0 = blk * WG;
     const int64_t p = pb0 + tid;
-    const bool valid = p < a.nl;
+    const bool valid = p < nl;
     const int64_t pp = valid ? p : pb0;
 
     T xp[3] = {xl[pp], xl[a.ldl + pp], xl[2 * a.ldl + pp]};
@@ -357,8 +365,8 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a) {
 #pragma unroll
     for (int c = 0; c < kN; ++c) acc[c] = hi[c] = lo[c] = T(0);
 
-    for (int64_t j0 = 0; j0 < a.no; j0 += WG) {
-        const int cnt = int((a.no - j0) < WG ? (a.no - j0) : WG);
+    for (int64_t j0 = 0; j0 < no; j0 += WG) {
+        const int cnt = int((no - j0) < WG ? (no - j0) : WG);
         __syncthreads();
         // idle slots (tid >= cnt) read the tile's first particle, which keeps the box exact
         const int64_t jl = j0 + (tid < cnt ? tid : 0);
@@ -422,7 +430,7 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a) {
             }
         }
     }
-    if (!valid) return;
+    if (!valid) return;  // (nothing follows in a caller's loop that this lane must reach)
     double t[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) t[c] = 0.0;
@@ -446,15 +454,16 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a) {
         gb[1] += t[5] * s0 - t[3] * s2;
         gb[2] += t[3] * s1 - t[4] * s0;
     }
-    T* __restrict__ xo_bar = static_cast<T*>(a.xbar);
-    T* __restrict__ go_bar = static_cast<T*>(a.gbar);
+    T* __restrict__ xo_bar = static_cast<T*>(a.xbar) + lb;
+    T* __restrict__ go_bar = a.gbar ? static_cast<T*>(a.gbar) + lb : nullptr;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         T* d = xo_bar + c * a.ldg + p;
         *d = T(double(*d) + kInv4PiD * xb[c]);
     }
-    // velocity-only target gradients touch x only
-    if (RB || STR) {
+    // velocity-only target gradients touch x only; a null gbar drops the strength gradient
+    // (the classical scheme's composition discards the target-role part it recomputes)
+    if ((RB || STR) && go_bar) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             T* d = go_bar + c * a.ldg + p;
@@ -467,11 +476,41 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a) {
 // the compiler's choice: its accumulators need twice the registers.
 template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_backward_f32(BwdArgs a) {
-    backward_body<T, WG, RA, RB, STR, SYM>(a);
+    backward_body<T, WG, RA, RB, STR, SYM>(a, blockIdx.x, 0, a.nl, 0, a.no);
 }
 template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
 __global__ __launch_bounds__(WG) void k_backward_f64(BwdArgs a) {
-    backward_body<T, WG, RA, RB, STR, SYM>(a);
+    backward_body<T, WG, RA, RB, STR, SYM>(a, blockIdx.x, 0, a.nl, 0, a.no);
+}
+
+// Many independent sets in one launch: persistent workgroups pop (set, lane block) items,
+// ordered by decreasing cost, from the queue's counter; the lane set of item set b is
+// [src_off[b], src_off[b+1]) and the loop set [tgt_off[b], tgt_off[b+1]) (exchanged when
+// lane_is_tgt).  Every workgroup leaves once the counter passes the item count.
+template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
+__device__ __forceinline__ void backward_queue(const BwdArgs& a, const BatchQueue& q, int lane_is_tgt) {
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(q.counter, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= q.n_items) break;
+        const int2 it = q.items[item];
+        const int64_t* lo = lane_is_tgt ? q.tgt_off : q.src_off;
+        const int64_t* oo = lane_is_tgt ? q.src_off : q.tgt_off;
+        const int64_t lb = lo[it.x], ob = oo[it.x];
+        backward_body<T, WG, RA, RB, STR, SYM>(a, it.y, lb, lo[it.x + 1] - lb, ob, oo[it.x + 1] - ob);
+    }
+}
+template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_backward_batched_f32(
+    BwdArgs a, BatchQueue q, int lane_is_tgt) {
+    backward_queue<T, WG, RA, RB, STR, SYM>(a, q, lane_is_tgt);
+}
+template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
+__global__ __launch_bounds__(WG) void k_backward_batched_f64(BwdArgs a, BatchQueue q, int lane_is_tgt) {
+    backward_queue<T, WG, RA, RB, STR, SYM>(a, q, lane_is_tgt);
 }
 
 template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
@@ -482,9 +521,39 @@ void launch_k(int grid, const BwdArgs& a, hipStream_t st) {
         hipLaunchKernelGGL((k_backward_f64<T, WG, RA, RB, STR, SYM>), dim3(grid), dim3(WG), 0, st, a);
 }
 
+// Persistent launch over a queue (grid <= 0: only report the kernel's resident workgroups
+// per CU through *occ).
+template <typename T, int WG, bool RA, bool RB, bool STR, bool SYM>
+hipError_t launch_kq(int grid, const BwdArgs& a, const BatchQueue& q, int lane_is_tgt, int* occ, hipStream_t st) {
+    if (grid <= 0) {
+        if constexpr (std::is_same<T, float>::value)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                occ, reinterpret_cast<const void*>(k_backward_batched_f32<T, WG, RA, RB, STR, SYM>), WG, 0);
+        else
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                occ, reinterpret_cast<const void*>(k_backward_batched_f64<T, WG, RA, RB, STR, SYM>), WG, 0);
+    }
+    if constexpr (std::is_same<T, float>::value)
+        hipLaunchKernelGGL((k_backward_batched_f32<T, WG, RA, RB, STR, SYM>), dim3(grid), dim3(WG), 0, st, a, q,
+                           lane_is_tgt);
+    else
+        hipLaunchKernelGGL((k_backward_batched_f64<T, WG, RA, RB, STR, SYM>), dim3(grid), dim3(WG), 0, st, a, q,
+                           lane_is_tgt);
+    return hipGetLastError();
+}
+
 template <typename T, int WG, bool RA, bool RB>
-hipError_t launch_rs(bool stretch, bool sym, const BwdArgs& a, hipStream_t st) {
-    const int grid = int((a.nl + WG - 1) / WG);
+hipError_t launch_rs(bool stretch, bool sym, const BwdArgs& a, const BatchQueue* q, int grid, int lane_is_tgt,
+                     int* occ, hipStream_t st) {
+    if (q) {
+        if (stretch) {
+            if (sym) return launch_kq<T, WG, RA, RB, true, true>(grid, a, *q, lane_is_tgt, occ, st);
+            return launch_kq<T, WG, RA, RB, true, false>(grid, a, *q, lane_is_tgt, occ, st);
+        }
+        if (sym) return launch_kq<T, WG, RA, RB, false, true>(grid, a, *q, lane_is_tgt, occ, st);
+        return launch_kq<T, WG, RA, RB, false, false>(grid, a, *q, lane_is_tgt, occ, st);
+    }
+    grid = int((a.nl + WG - 1) / WG);
     if (stretch) {
         if (sym) launch_k<T, WG, RA, RB, true, true>(grid, a, st);
         else launch_k<T, WG, RA, RB, true, false>(grid, a, st);
@@ -496,10 +565,11 @@ hipError_t launch_rs(bool stretch, bool sym, const BwdArgs& a, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_t(bool ra, bool rb, bool stretch, bool sym, const BwdArgs& a, hipStream_t st) {
-    if (ra && rb) return launch_rs<T, 256, true, true>(stretch, sym, a, st);
-    if (ra) return launch_rs<T, 256, true, false>(stretch, sym, a, st);
-    return launch_rs<T, 256, false, true>(stretch, sym, a, st);
+hipError_t launch_t(bool ra, bool rb, bool stretch, bool sym, const BwdArgs& a, const BatchQueue* q, int grid,
+                    int lane_is_tgt, int* occ, hipStream_t st) {
+    if (ra && rb) return launch_rs<T, kBwdWG, true, true>(stretch, sym, a, q, grid, lane_is_tgt, occ, st);
+    if (ra) return launch_rs<T, kBwdWG, true, false>(stretch, sym, a, q, grid, lane_is_tgt, occ, st);
+    return launch_rs<T, kBwdWG, false, true>(stretch, sym, a, q, grid, lane_is_tgt, occ, st);
 }
 
 }  // namespace
@@ -508,8 +578,24 @@ hipError_t launch_backward(int dtype, bool role_a, bool role_b, bool stretch, bo
                            const BwdArgs& a, hipStream_t st) {
     if (a.nl == 0) return hipSuccess;
     if (!role_a && !role_b) return hipErrorInvalidValue;
-    if (dtype == kDtypeF64) return launch_t<double>(role_a, role_b, stretch, sym, a, st);
-    return launch_t<float>(role_a, role_b, stretch, sym, a, st);
+    if (dtype == kDtypeF64) return launch_t<double>(role_a, role_b, stretch, sym, a, nullptr, 0, 0, nullptr, st);
+    return launch_t<float>(role_a, role_b, stretch, sym, a, nullptr, 0, 0, nullptr, st);
+}
+
+hipError_t launch_backward_batched(int dtype, bool role_a, bool role_b, bool stretch, bool sym, const BwdArgs& a,
+                                   const BatchQueue& q, int grid, int lane_is_tgt, hipStream_t st) {
+    if (!role_a && !role_b) return hipErrorInvalidValue;
+    if (dtype == kDtypeF64) return launch_t<double>(role_a, role_b, stretch, sym, a, &q, grid, lane_is_tgt, nullptr, st);
+    return launch_t<float>(role_a, role_b, stretch, sym, a, &q, grid, lane_is_tgt, nullptr, st);
+}
+
+int backward_occupancy(int dtype, bool role_a, bool role_b, bool stretch, bool sym) {
+    int occ = 0;
+    BwdArgs a{};
+    BatchQueue q{};
+    hipError_t e = dtype == kDtypeF64 ? launch_t<double>(role_a, role_b, stretch, sym, a, &q, 0, 0, &occ, nullptr)
+                                      : launch_t<float>(role_a, role_b, stretch, sym, a, &q, 0, 0, &occ, nullptr);
+    return e == hipSuccess ? occ : 0;
 }
 
 }  // namespace vpm

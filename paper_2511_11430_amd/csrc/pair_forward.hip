@@ -218,11 +218,14 @@ __device__ __forceinline__ void store_target(const FwdArgs& a, int64_t t, double
             *dst = a.accumulate ? T(double(*dst) + v) : T(v);
         }
     }
+    // (the library's own stretching-only use passes no velocity output)
     T* __restrict__ uo = static_cast<T*>(a.u);
+    if (uo) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        T* dst = uo + c * a.ldo + t;
-        *dst = a.accumulate ? T(double(*dst) + res[c]) : T(res[c]);
+        for (int c = 0; c < 3; ++c) {
+            T* dst = uo + c * a.ldo + t;
+            *dst = a.accumulate ? T(double(*dst) + res[c]) : T(res[c]);
+        }
     }
     if (MODE != kModeVelocity) {
         T* __restrict__ dgo = static_cast<T*>(a.dg);

@@ -103,16 +103,63 @@ struct QueueLayout {
     size_t off_src, off_tgt, off_items, total;
     int64_t max_items;
 };
-QueueLayout queue_layout(int32_t n_batch, const int64_t* tgt_off, int64_t per_block) {
-    QueueLayout L;
+int64_t count_blocks(int32_t n_batch, const int64_t* off, int64_t per_block) {
     int64_t items = 0;
-    for (int32_t b = 0; b < n_batch; ++b) items += (tgt_off[b + 1] - tgt_off[b] + per_block - 1) / per_block;
+    for (int32_t b = 0; b < n_batch; ++b) items += (off[b + 1] - off[b] + per_block - 1) / per_block;
+    return items;
+}
+QueueLayout queue_layout_items(int32_t n_batch, int64_t items) {
+    QueueLayout L;
     L.max_items = items;
     L.off_src = kAlign;
     L.off_tgt = L.off_src + align_up(sizeof(int64_t) * (n_batch + 1));
     L.off_items = L.off_tgt + align_up(sizeof(int64_t) * (n_batch + 1));
     L.total = L.off_items + align_up(sizeof(int2) * size_t(items > 0 ? items : 1));
     return L;
+}
+QueueLayout queue_layout(int32_t n_batch, const int64_t* tgt_off, int64_t per_block) {
+    return queue_layout_items(n_batch, count_blocks(n_batch, tgt_off, per_block));
+}
+
+// Adjoint of many sets: the larger of the two queues (source blocks, target blocks).
+QueueLayout backward_queue_layout(int32_t n_batch, const int64_t* src_off, const int64_t* tgt_off) {
+    const int64_t per = vpm::kBwdWG;
+    return queue_layout_items(n_batch, std::max(count_blocks(n_batch, src_off, per),
+                                                count_blocks(n_batch, tgt_off, per)));
+}
+
+hipError_t stage_and_copy(const std::vector<unsigned char>& blob, void* dst, hipStream_t st);
+
+// Stages the LPT-ordered (set, block) items of the lane sets `lane_off` (cost: lane count x
+// loop-set size) with both offset tables into the workspace; returns the item count.
+hipError_t stage_queue(int32_t n_batch, const int64_t* src_off, const int64_t* tgt_off, bool lane_is_tgt,
+                       int64_t per_block, void* workspace, hipStream_t st, int64_t* n_items) {
+    const int64_t* lane = lane_is_tgt ? tgt_off : src_off;
+    const int64_t* loop = lane_is_tgt ? src_off : tgt_off;
+    struct Item {
+        int b, blk;
+        int64_t cost;
+    };
+    std::vector<Item> items;
+    for (int32_t b = 0; b < n_batch; ++b) {
+        const int64_t nl = lane[b + 1] - lane[b], no = loop[b + 1] - loop[b];
+        const int64_t nblk = (nl + per_block - 1) / per_block;
+        for (int64_t k = 0; k < nblk; ++k)
+            items.push_back({b, int(k), (no + 1) * std::min<int64_t>(per_block, nl - k * per_block)});
+    }
+    *n_items = int64_t(items.size());
+    if (items.empty()) return hipSuccess;
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    const QueueLayout L = queue_layout_items(n_batch, int64_t(items.size()));
+    std::vector<unsigned char> blob(L.off_items + sizeof(int2) * items.size(), 0);
+    std::memcpy(blob.data() + L.off_src, src_off, sizeof(int64_t) * (n_batch + 1));
+    std::memcpy(blob.data() + L.off_tgt, tgt_off, sizeof(int64_t) * (n_batch + 1));
+    int2* it = reinterpret_cast<int2*>(blob.data() + L.off_items);
+    for (size_t i = 0; i < items.size(); ++i) {
+        it[i].x = items[i].b;
+        it[i].y = items[i].blk;
+    }
+    return stage_and_copy(blob, workspace, st);
 }
 
 // Pinned host staging for the queue, reused across calls; the event of the previous copy
@@ -229,6 +276,81 @@ SplitPlan split_plan(int32_t dtype, int variant, int nacc, int64_t n_src, int64_
     }
     p.bytes = align_up(size_t(p.nchunk) * size_t(nacc) * size_t(n_tgt) * sizeof(double));
     return p;
+}
+
+// Adjoint of the classical scheme.  Its pair term S_i . (J Gamma_i) equals the transposed
+// term Gamma_i . (J^T S_i) with the target's strength and its stretching seed exchanged, while
+// the velocity term and the source strengths are unchanged.  So: the transposed adjoint kernel
+// with S in the target-strength slot and Gamma in the seed slot gives every position gradient
+// and the source strengths' gradient; the target strengths' gradient is the derivative with
+// respect to that seed slot, J^T S (the transposed stretching of a target of strength S),
+// which the forward kernel adds.  Self evaluations split the two roles of each particle into
+// two launches because its strength differs between them.
+vpm_status classical_backward(int32_t dtype, bool sym, bool self, int64_t n_src, int64_t n_tgt, const void* x_src,
+                              const void* gamma_src, const void* sigma_src, int64_t ld_src, const void* x_tgt,
+                              const void* gamma_tgt, const void* sigma_tgt, int64_t ld_tgt, const void* u_bar,
+                              const void* dgamma_bar, void* x_src_bar, void* gamma_src_bar, void* x_tgt_bar,
+                              void* gamma_tgt_bar, hipStream_t st) {
+    // sources as sources (role B): loop over the targets with S in their strength slot
+    vpm::BwdArgs b;
+    b.xl = x_src; b.gl = gamma_src; b.sl = sigma_src; b.ubl = nullptr; b.sbl = nullptr;
+    b.ldl = ld_src; b.nl = n_src;
+    b.xo = x_tgt; b.go = dgamma_bar; b.so = sigma_tgt; b.ubo = u_bar; b.sbo = gamma_tgt;
+    b.ldo = ld_tgt; b.no = n_tgt;
+    b.xbar = x_src_bar; b.gbar = gamma_src_bar; b.ldg = ld_src; b.self = self ? 1 : 0;
+    if (vpm::launch_backward(dtype, false, true, true, sym, b, st) != hipSuccess) return VPM_ERR_HIP;
+    // targets as targets (role A): their positions; the strength-slot gradient is dropped
+    void* xtb = self ? x_src_bar : x_tgt_bar;
+    void* gtb = self ? gamma_src_bar : gamma_tgt_bar;
+    if (!xtb) return VPM_OK;
+    vpm::BwdArgs a;
+    a.xl = x_tgt; a.gl = dgamma_bar; a.sl = sigma_tgt; a.ubl = u_bar; a.sbl = gamma_tgt;
+    a.ldl = ld_tgt; a.nl = n_tgt;
+    a.xo = x_src; a.go = gamma_src; a.so = sigma_src; a.ubo = nullptr; a.sbo = nullptr;
+    a.ldo = ld_src; a.no = n_src;
+    a.xbar = xtb; a.gbar = nullptr; a.ldg = self ? ld_src : ld_tgt; a.self = self ? 1 : 0;
+    if (vpm::launch_backward(dtype, true, false, true, sym, a, st) != hipSuccess) return VPM_ERR_HIP;
+    // target strengths: += J^T S (transposed stretching with S as the target strength)
+    vpm::FwdArgs f;
+    f.xs = x_src; f.gs = gamma_src; f.ss = sigma_src; f.lds = ld_src;
+    f.xt = x_tgt; f.gt = dgamma_bar; f.st = sym ? sigma_tgt : nullptr; f.ldt = ld_tgt;
+    f.excl = nullptr; f.u = nullptr; f.dg = gtb; f.grad = nullptr; f.ldo = self ? ld_src : ld_tgt;
+    f.src_begin = 0; f.src_end = n_src; f.tgt_begin = 0; f.tgt_end = n_tgt;
+    f.self = self ? 1 : 0; f.accumulate = 1; f.classical = 0;
+    f.part = nullptr; f.chunk = n_src; f.nchunk = 1;
+    vpm_options fo = default_options();
+    fo.self = self ? 1 : 0;
+    const int variant = choose_variant(fo, false, n_tgt);
+    const int mode = fwd_mode(fo, true);
+    const int64_t per_block = targets_per_block(dtype, variant);
+    const int64_t grid = (n_tgt + per_block - 1) / per_block;
+    return hip_status(vpm::launch_pair_fwd(dtype, variant, mode, sym, f, nullptr, int(grid), st));
+}
+
+// Persistent adjoint launch over many sets: stages the queue of the lane sets' blocks into
+// the workspace and fills the GPU with resident workgroups.
+hipError_t backward_batched(int32_t dtype, int32_t n_batch, const int64_t* src_off, const int64_t* tgt_off,
+                            bool role_a, bool role_b, bool stretch, bool sym, const vpm::BwdArgs& a,
+                            bool lane_is_tgt, void* workspace, hipStream_t st) {
+    int64_t n_items = 0;
+    hipError_t e = stage_queue(n_batch, src_off, tgt_off, lane_is_tgt, vpm::kBwdWG, workspace, st, &n_items);
+    if (e != hipSuccess || n_items == 0) return e;
+    DeviceInfo di;
+    e = device_info(di);
+    if (e != hipSuccess) return e;
+    int occ = vpm::backward_occupancy(dtype, role_a, role_b, stretch, sym);
+    if (occ < 1) occ = 1;
+    int64_t grid = std::min<int64_t>(int64_t(di.cus) * occ, n_items);
+    const QueueLayout L = queue_layout_items(n_batch, n_items);
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    vpm::BatchQueue q;
+    q.counter = reinterpret_cast<int*>(ws);
+    q.items = reinterpret_cast<const int2*>(ws + L.off_items);
+    q.src_off = reinterpret_cast<const int64_t*>(ws + L.off_src);
+    q.tgt_off = reinterpret_cast<const int64_t*>(ws + L.off_tgt);
+    q.n_items = int(n_items);
+    return vpm::launch_backward_batched(dtype, role_a, role_b, stretch, sym, a, q, int(grid), lane_is_tgt ? 1 : 0,
+                                        st);
 }
 
 }  // namespace
@@ -728,8 +850,6 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                         const void* u_bar, const void* dgamma_bar, void* x_src_bar,
                         void* gamma_src_bar, void* x_tgt_bar, void* gamma_tgt_bar,
                         const vpm_options* opt, void* workspace, size_t ws_bytes, void* stream) {
-    (void)workspace;
-    (void)ws_bytes;
     if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
     if (n_batch < 1) return VPM_ERR_SIZE;
     vpm_options o = opt ? *opt : default_options();
@@ -738,11 +858,12 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
     if (!src_off) return VPM_ERR_NULL;
     s = check_offsets(n_batch, src_off);
     if (s != VPM_OK) return s;
-    if (n_batch != 1) return VPM_ERR_UNSUPPORTED;
-    if (o.scheme != VPM_STRETCH_TRANSPOSED) return VPM_ERR_UNSUPPORTED;
     // Gradients are always accumulated (+=); opt->accumulate is not consulted.
     if (o.self) {
-        if (tgt_off && tgt_off[1] != src_off[1]) return VPM_ERR_OFFSETS;
+        if (tgt_off && tgt_off != src_off) {
+            for (int32_t b = 0; b <= n_batch; ++b)
+                if (tgt_off[b] != src_off[b]) return VPM_ERR_OFFSETS;
+        }
         if ((x_tgt && x_tgt != x_src) || (gamma_tgt && gamma_tgt != gamma_src) ||
             (sigma_tgt && sigma_tgt != sigma_src))
             return VPM_ERR_ALIAS;
@@ -758,8 +879,8 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
         s = check_offsets(n_batch, tgt_off);
         if (s != VPM_OK) return s;
     }
-    const int64_t n_src = src_off[1];
-    const int64_t n_tgt = tgt_off[1];
+    const int64_t n_src = src_off[n_batch];
+    const int64_t n_tgt = tgt_off[n_batch];
     if (n_src > INT32_MAX || n_tgt > INT32_MAX) return VPM_ERR_SIZE;
     if (ld_src < n_src || ld_tgt < n_tgt) return VPM_ERR_SIZE;
     const bool stretch = dgamma_bar != nullptr;
@@ -784,9 +905,40 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
         for (int j = i + 1; j < 4; ++j)
             if (overlap(outs[i], outs[j])) return VPM_ERR_ALIAS;
     }
+    const bool classical = o.scheme == VPM_STRETCH_CLASSICAL && stretch;
+    if (n_batch > 1 && !classical) {
+        const QueueLayout L = backward_queue_layout(n_batch, src_off, tgt_off);
+        if (!workspace || ws_bytes < L.total) return VPM_ERR_WORKSPACE;
+        const Range rw = span(workspace, 1, int64_t(ws_bytes), int64_t(ws_bytes), 1);
+        for (int i = 0; i < 4; ++i)
+            if (overlap(rw, outs[i])) return VPM_ERR_ALIAS;
+        for (const Range& r : ins)
+            if (overlap(rw, r)) return VPM_ERR_ALIAS;
+    }
     if (n_src == 0 && n_tgt == 0) return VPM_OK;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (classical) {
+        // one set after another (the composition runs three launches per set)
+        auto sh = [es](const void* q, int64_t off) -> const void* {
+            return q ? static_cast<const unsigned char*>(q) + size_t(off) * es : nullptr;
+        };
+        auto shm = [es](void* q, int64_t off) -> void* {
+            return q ? static_cast<unsigned char*>(q) + size_t(off) * es : nullptr;
+        };
+        for (int32_t b = 0; b < n_batch; ++b) {
+            const int64_t s0 = src_off[b], t0 = tgt_off[b];
+            const int64_t ns = src_off[b + 1] - s0, nt = tgt_off[b + 1] - t0;
+            if (ns == 0 && nt == 0) continue;
+            const vpm_status r = classical_backward(
+                dtype, sym, o.self != 0, ns, nt, sh(x_src, s0), sh(gamma_src, s0), sh(sigma_src, s0), ld_src,
+                sh(x_tgt, t0), sh(gamma_tgt, t0), sh(sigma_tgt, t0), ld_tgt, sh(u_bar, t0), sh(dgamma_bar, t0),
+                shm(x_src_bar, s0), shm(gamma_src_bar, s0), want_tgt ? shm(x_tgt_bar, t0) : nullptr,
+                want_tgt ? shm(gamma_tgt_bar, t0) : nullptr, st);
+            if (r != VPM_OK) return r;
+        }
+        return VPM_OK;
+    }
     vpm::BwdArgs a;
     if (o.self) {
         a.xl = x_src; a.gl = gamma_src; a.sl = sigma_src; a.ubl = u_bar; a.sbl = dgamma_bar;
@@ -794,7 +946,9 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
         a.xo = x_src; a.go = gamma_src; a.so = sigma_src; a.ubo = u_bar; a.sbo = dgamma_bar;
         a.ldo = ld_src; a.no = n_src;
         a.xbar = x_src_bar; a.gbar = gamma_src_bar; a.ldg = ld_src; a.self = 1;
-        return hip_status(vpm::launch_backward(dtype, true, true, stretch, sym, a, st));
+        if (n_batch == 1) return hip_status(vpm::launch_backward(dtype, true, true, stretch, sym, a, st));
+        return hip_status(backward_batched(dtype, n_batch, src_off, tgt_off, true, true, stretch, sym, a, false,
+                                           workspace, st));
     }
     // Sources' gradients: lane = source (role B), loop = targets.
     a.xl = x_src; a.gl = gamma_src; a.sl = sigma_src; a.ubl = nullptr; a.sbl = nullptr;
@@ -802,7 +956,9 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
     a.xo = x_tgt; a.go = gamma_tgt; a.so = sigma_tgt; a.ubo = u_bar; a.sbo = dgamma_bar;
     a.ldo = ld_tgt; a.no = n_tgt;
     a.xbar = x_src_bar; a.gbar = gamma_src_bar; a.ldg = ld_src; a.self = 0;
-    hipError_t e = vpm::launch_backward(dtype, false, true, stretch, sym, a, st);
+    hipError_t e = n_batch == 1 ? vpm::launch_backward(dtype, false, true, stretch, sym, a, st)
+                                : backward_batched(dtype, n_batch, src_off, tgt_off, false, true, stretch, sym, a,
+                                                   false, workspace, st);
     if (e != hipSuccess) return VPM_ERR_HIP;
     if (want_tgt) {
         // Targets' gradients: lane = target (role A), loop = sources.
@@ -812,10 +968,20 @@ vpm_status vpm_backward(int32_t dtype, int32_t n_batch, const int64_t* src_off,
         b.xo = x_src; b.go = gamma_src; b.so = sigma_src; b.ubo = nullptr; b.sbo = nullptr;
         b.ldo = ld_src; b.no = n_src;
         b.xbar = x_tgt_bar; b.gbar = gamma_tgt_bar; b.ldg = ld_tgt; b.self = 0;
-        e = vpm::launch_backward(dtype, true, false, stretch, sym, b, st);
+        e = n_batch == 1 ? vpm::launch_backward(dtype, true, false, stretch, sym, b, st)
+                         : backward_batched(dtype, n_batch, src_off, tgt_off, true, false, stretch, sym, b, true,
+                                            workspace, st);
         if (e != hipSuccess) return VPM_ERR_HIP;
     }
     return VPM_OK;
+}
+
+size_t vpm_backward_workspace_size(int32_t dtype, int32_t n_batch, const int64_t* src_off, const int64_t* tgt_off) {
+    if (!dtype_ok(dtype) || n_batch < 1 || check_offsets(n_batch, src_off) != VPM_OK) return 0;
+    if (n_batch == 1) return 0;
+    if (!tgt_off) tgt_off = src_off;
+    if (check_offsets(n_batch, tgt_off) != VPM_OK) return 0;
+    return backward_queue_layout(n_batch, src_off, tgt_off).total;
 }
 
 // State arrays may be FP64 while F and the evaluation copies are FP32 (mixed program);
@@ -914,6 +1080,92 @@ vpm_status vpm_validate_inputs(int32_t dtype, int64_t n, const void* x, const vo
         if (overlap(ro, r) || overlap(rw, r)) return VPM_ERR_ALIAS;
     return hip_status(vpm::launch_validate(dtype, n, x, gamma, sigma, ld, out, static_cast<double*>(workspace),
                                            static_cast<hipStream_t>(stream)));
+}
+
+size_t vpm_check_inputs_workspace_size(void) { return vpm_diagnostics_workspace_size() + kAlign; }
+
+vpm_status vpm_check_inputs(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* sigma,
+                            int64_t ld, void* workspace, size_t ws_bytes, void* stream) {
+    if (!workspace || ws_bytes < vpm_check_inputs_workspace_size()) return VPM_ERR_WORKSPACE;
+    const size_t dws = vpm_diagnostics_workspace_size();
+    double* out = reinterpret_cast<double*>(static_cast<unsigned char*>(workspace) + dws);
+    vpm_status s = vpm_validate_inputs(dtype, n, x, gamma, sigma, ld, out, workspace, dws, stream);
+    if (s != VPM_OK || n == 0) return s;
+    double host[2] = {0.0, 0.0};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, st) != hipSuccess) return VPM_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return VPM_ERR_HIP;
+    return (host[0] != 0.0 || host[1] != 0.0) ? VPM_ERR_INPUT : VPM_OK;
+}
+
+vpm_status vpm_autotune(int32_t dtype, int32_t n_batch, const int64_t* src_off, const void* x, const void* gamma,
+                        const void* sigma, int64_t ld, void* u_scratch, void* dgamma_scratch, void* workspace,
+                        size_t ws_bytes, int32_t reps, int32_t* variant_out, float* ms_out, void* stream) {
+    if (dtype != kDtypeF32C) return VPM_ERR_DTYPE;
+    if (n_batch < 1 || reps < 1 || reps > 1000) return VPM_ERR_SIZE;
+    if (!src_off) return VPM_ERR_NULL;
+    vpm_status s = check_offsets(n_batch, src_off);
+    if (s != VPM_OK) return s;
+    const int64_t n = src_off[n_batch];
+    if (n < 1) return VPM_ERR_SIZE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    vpm_options o = default_options();
+    o.self = 1;
+    // every shape once (validation, first-launch costs), then reps timed runs of each
+    for (int v = 1; v <= vpm::kNumF32Variants; ++v) {
+        o.variant = v;
+        s = eval_impl(dtype, n_batch, src_off, nullptr, x, gamma, sigma, ld, nullptr, nullptr, nullptr, 0, nullptr,
+                      u_scratch, dgamma_scratch, nullptr, ld, o, workspace, ws_bytes, stream);
+        if (s != VPM_OK) return s;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return VPM_ERR_HIP;
+    }
+    float best_ms[vpm::kNumF32Variants];
+    s = VPM_OK;
+    for (int v = 1; v <= vpm::kNumF32Variants && s == VPM_OK; ++v) {
+        o.variant = v;
+        float best = -1.0f;
+        for (int r = 0; r < reps && s == VPM_OK; ++r) {
+            if (hipEventRecord(e0, st) != hipSuccess) { s = VPM_ERR_HIP; break; }
+            s = eval_impl(dtype, n_batch, src_off, nullptr, x, gamma, sigma, ld, nullptr, nullptr, nullptr, 0,
+                          nullptr, u_scratch, dgamma_scratch, nullptr, ld, o, workspace, ws_bytes, stream);
+            if (s != VPM_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                s = VPM_ERR_HIP;
+                break;
+            }
+            if (best < 0.0f || ms < best) best = ms;
+        }
+        best_ms[v - 1] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != VPM_OK) return s;
+    int pick = 1;
+    for (int v = 2; v <= vpm::kNumF32Variants; ++v)
+        if (best_ms[v - 1] < best_ms[pick - 1]) pick = v;
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        g_plan[n_batch > 1 ? 1 : 0][plan_bucket(n)] = pick;
+    }
+    if (variant_out) *variant_out = pick;
+    if (ms_out)
+        for (int v = 0; v < vpm::kNumF32Variants; ++v) ms_out[v] = best_ms[v];
+    return VPM_OK;
+}
+
+vpm_status vpm_fma_chain(int64_t n_lanes, int32_t fmas_per_chain, float* out, int64_t* fma_instructions,
+                         void* stream) {
+    if (n_lanes < 1 || n_lanes > INT32_MAX || fmas_per_chain < 4 || fmas_per_chain % 4 != 0) return VPM_ERR_SIZE;
+    if (!out) return VPM_ERR_NULL;
+    const int64_t waves = (n_lanes + 63) / 64;
+    if (fma_instructions) *fma_instructions = waves * int64_t(vpm::fma_chain_count()) * fmas_per_chain;
+    return hip_status(vpm::launch_fma_chain(n_lanes, fmas_per_chain, out, static_cast<hipStream_t>(stream)));
 }
 
 vpm_status vpm_diagnostics(int32_t dtype, int64_t n, const void* x, const void* gamma, const void* u,

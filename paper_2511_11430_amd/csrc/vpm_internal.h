@@ -137,6 +137,13 @@ struct BwdArgs {
     int64_t ldg;
     int32_t self;  // loop set == lane set, skip j == i
 };
+// Lane set per workgroup of the adjoint kernel.
+constexpr int kBwdWG = 256;
+// Persistent launch over a queue of (set, lane block) items (lane_is_tgt: the lane set of set
+// b is its target range, the loop set its source range); grid = resident workgroups.
+hipError_t launch_backward_batched(int dtype, bool role_a, bool role_b, bool stretch, bool sym, const BwdArgs& a,
+                                   const BatchQueue& q, int grid, int lane_is_tgt, hipStream_t st);
+int backward_occupancy(int dtype, bool role_a, bool role_b, bool stretch, bool sym);
 hipError_t launch_backward(int dtype, bool role_a, bool role_b, bool stretch, bool sym,
                            const BwdArgs& a, hipStream_t st);
 
@@ -191,5 +198,9 @@ hipError_t launch_validate(int dtype, int64_t n, const void* x, const void* g, c
                            double* out, double* partials, hipStream_t st);
 hipError_t launch_axial_loss(int dtype, int64_t m, const void* u, int64_t ld, double* loss, void* ubar,
                              const double* loss_bar, hipStream_t st);
+
+// ---------------------------------------------------------------- counter calibration
+int fma_chain_count();
+hipError_t launch_fma_chain(int64_t n, int fmas, float* out, hipStream_t st);
 
 }  // namespace vpm

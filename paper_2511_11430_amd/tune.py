@@ -1,10 +1,10 @@
 """Kernel-shape tuner for the FP32C particle kernel (targets per lane x workgroup size).
 
 For each size bucket of single-set launches, and for the batched persistent launch of 64
-uneven wakes, every shape variant of libvpm is timed with HIP events on wake-shaped
-inputs; the fastest becomes the plan (``vpm_set_plan``) and all timings are written to a
-JSON cache keyed by the GPU architecture and a hash of the kernel sources.  The binding
-applies a matching cache when it first loads the library.
+uneven wakes, the library's own tuner (``vpm_autotune``) times every shape variant with HIP
+events on wake-shaped inputs and records the fastest in its plan; all timings are written
+to a JSON cache keyed by the GPU architecture and a hash of the kernel sources.  The
+binding applies a matching cache (``vpm_set_plan``) when it first loads the library.
 
 Usage (on the GPU):  python -m paper_2511_11430_amd.tune [--out PATH] [--quick]
 """
@@ -29,49 +29,32 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def _time(fn, reps):
-    import torch
-    fn()
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    best = None
-    for _ in range(reps):
-        a.record()
-        fn()
-        b.record()
-        torch.cuda.synchronize()
-        t = a.elapsed_time(b)
-        best = t if best is None else min(best, t)
-    return best
-
-
 def tune(out=DEFAULT_CACHE, quick=False, log=print):
+    """Runs the library's tuner (vpm_autotune: HIP-event timings of every shape on the
+    caller's stream, the fastest recorded in the plan) on forward-flight wakes of each size
+    bucket and on the 64 uneven wakes of the batched launch, then writes the timings and
+    choices to the JSON cache."""
     import numpy as np
     import torch
 
-    from . import F32C, _lib, vpm_eval_velocity_stretching, vpm_variant_count, vpm_variant_info
+    from . import vpm_autotune
     from . import workloads as W
 
-    lib = _lib.load()
     dev = torch.device("cuda:0")
-    nv = vpm_variant_count()
     f32 = lambda a: torch.tensor(np.ascontiguousarray(W.to_f32(a)), dtype=torch.float32, device=dev)
     plans = []
     sizes = SINGLE_SIZES[:3] if quick else SINGLE_SIZES
     for i, n in enumerate(sizes):
         c = W.config3(n=n)
         x, g, s = f32(c["x"]), f32(c["gamma"]), f32(c["sigma"])
-        u, d = torch.empty_like(x), torch.empty_like(x)
-        reps = 2 if n >= 262144 else 3
-        ms = {}
-        for v in range(1, nv + 1):
-            ms[v] = _time(lambda: vpm_eval_velocity_stretching(x, g, s, u_out=u, dgamma_out=d, variant=v), reps)
-            log(f"single N={n} variant {v} {vpm_variant_info(v)}: {ms[v]:.3f} ms")
-        best = min(ms, key=ms.get)
+        best, ms = vpm_autotune(x, g, s, reps=2 if n >= 262144 else 3)
+        for v, t in enumerate(ms, 1):
+            log(f"single N={n} variant {v}: {t:.3f} ms")
         lo = sizes[i - 1] + 1 if i > 0 else 0
         hi = sizes[i + 1] - 1 if i + 1 < len(sizes) else 1 << 31
-        plans.append({"batched": 0, "n_lo": lo, "n_hi": hi, "variant": best, "ms": ms, "n": n})
-        del x, g, s, u, d
+        plans.append({"batched": 0, "n_lo": lo, "n_hi": hi, "variant": best,
+                      "ms": {str(v): t for v, t in enumerate(ms, 1)}, "n": n})
+        del x, g, s
     # batched persistent launch over the 64 uneven wakes
     wakes = W.config5(scale=0.25 if quick else 1.0)
     off = [0]
@@ -81,16 +64,11 @@ def tune(out=DEFAULT_CACHE, quick=False, log=print):
     xw = torch.tensor(cat("x"), dtype=torch.float32, device=dev)
     gw = torch.tensor(cat("gamma"), dtype=torch.float32, device=dev)
     sw = torch.tensor(cat("sigma"), dtype=torch.float32, device=dev)
-    uw, dw = torch.empty_like(xw), torch.empty_like(xw)
-    from . import vpm_workspace_size
-    ws = torch.empty(vpm_workspace_size(F32C, off), dtype=torch.uint8, device=dev)
-    ms = {}
-    for v in range(1, nv + 1):
-        ms[v] = _time(lambda: vpm_eval_velocity_stretching(xw, gw, sw, u_out=uw, dgamma_out=dw, src_off=off,
-                                                           workspace=ws, variant=v), 2)
-        log(f"batched {len(wakes)} wakes ({off[-1]} particles) variant {v} {vpm_variant_info(v)}: {ms[v]:.3f} ms")
-    best = min(ms, key=ms.get)
-    plans.append({"batched": 1, "n_lo": 0, "n_hi": 1 << 31, "variant": best, "ms": ms, "n": off[-1]})
+    best, ms = vpm_autotune(xw, gw, sw, src_off=off, reps=2)
+    for v, t in enumerate(ms, 1):
+        log(f"batched {len(wakes)} wakes ({off[-1]} particles) variant {v}: {t:.3f} ms")
+    plans.append({"batched": 1, "n_lo": 0, "n_hi": 1 << 31, "variant": best,
+                  "ms": {str(v): t for v, t in enumerate(ms, 1)}, "n": off[-1]})
     props = torch.cuda.get_device_properties(0)
     cache = {"arch": getattr(props, "gcnArchName", "gfx950").split(":")[0], "device": props.name,
              "hip": torch.version.hip, "source_hash": source_hash(), "created": time.strftime("%Y-%m-%d %H:%M:%S"),

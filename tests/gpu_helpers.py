@@ -11,6 +11,16 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
+def per_target(a, b):
+    """Largest error of one target's 3-vector, relative to the RMS magnitude of the reference
+    over all targets: no single target may exceed the gate that rel-L2 applies on average."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    rms = np.sqrt(np.mean(np.sum(b * b, axis=0)))
+    err = np.sqrt(np.sum((a - b) ** 2, axis=0))
+    return float(err.max() / rms) if rms > 0 else float(err.max())
+
+
 def torch_dtype(kind):
     import torch
     return torch.float64 if kind == "f64" else torch.float32

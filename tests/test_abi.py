@@ -131,10 +131,18 @@ def test_backward_validation():
     b = lib.vpm_backward
     args = lambda **k: [k.get("dt", F32C), k.get("nb", 1), k.get("so", off(0, 100)), None, P(0), P(1), P(2), 100,
                         None, None, None, 0, P(3), P(4), k.get("xb", P(5)), P(6), None, None,
-                        ctypes.byref(k.get("o", o)), None, 0, None]
+                        ctypes.byref(k.get("o", o)), k.get("ws", None), k.get("wsb", 0), None]
     assert b(*args(dt=4)) == DTYPE
-    assert b(*args(nb=2, so=off(0, 50, 100))) == UNSUPPORTED
-    assert b(*args(o=opts(self_=1, scheme=1))) == UNSUPPORTED
+    # many sets need the queue workspace, of the size the library reports
+    two = off(0, 50, 100)
+    need = lib.vpm_backward_workspace_size(F32C, 2, two, None)
+    assert need > 0 and lib.vpm_backward_workspace_size(F32C, 1, off(0, 100), None) == 0
+    assert lib.vpm_backward_workspace_size(F32C, 2, off(0, 60, 50), None) == 0
+    assert b(*args(nb=2, so=two)) == WORKSPACE
+    assert b(*args(nb=2, so=two, ws=P(9), wsb=need - 1)) == WORKSPACE
+    assert b(*args(nb=2, so=two, ws=P(5), wsb=need)) == ALIAS
+    assert b(*args(nb=2, so=off(0, 60, 50), ws=P(9), wsb=need)) == OFFSETS
+    assert b(*args(o=opts(self_=1, scheme=2))) == ENUM
     assert b(*args(xb=None)) == NULL
     assert b(*args(xb=P(0))) == ALIAS
 
@@ -185,6 +193,38 @@ def test_validate_inputs_validation():
     assert v(F32C, 10, P(0), P(1), None, 10, P(3), P(4), need, None) == NULL
     assert v(F32C, 10, P(0), P(1), P(2), 10, P(3), P(4), 8, None) == WORKSPACE
     assert v(F32C, 10, P(0), P(1), P(2), 10, P(0), P(4), need, None) == ALIAS
+
+
+def test_check_inputs_validation():
+    lib = _lib.load()
+    c = lib.vpm_check_inputs
+    need = lib.vpm_check_inputs_workspace_size()
+    assert need >= lib.vpm_diagnostics_workspace_size() + 13 * 8
+    assert c(F32C, 10, P(0), P(1), P(2), 10, P(4), need - 1, None) == WORKSPACE
+    assert c(F32C, 10, P(0), P(1), P(2), 10, None, need, None) == WORKSPACE
+    assert c(5, 10, P(0), P(1), P(2), 10, P(4), need, None) == DTYPE
+    assert c(F32C, 10, P(0), P(1), None, 10, P(4), need, None) == NULL
+    assert c(F32C, 10, P(0), P(1), P(2), 9, P(4), need, None) == SIZE
+    assert c(F32C, 10, P(0), P(1), P(2), 10, P(0), need, None) == ALIAS
+
+
+def test_autotune_validation():
+    lib = _lib.load()
+    t = lib.vpm_autotune
+    v = ctypes.c_int32(-1)
+
+    def call(dt=F32C, nb=1, so=None, reps=3, ws=None, wsb=0):
+        so = off(0, 100) if so is None else so
+        return t(dt, nb, so, P(0), P(1), P(2), 100, P(3), P(4), ws, wsb, reps, ctypes.byref(v), None, None)
+
+    assert call(dt=F64) == DTYPE
+    assert call(nb=0) == SIZE
+    assert call(reps=0) == SIZE and call(reps=1001) == SIZE
+    assert t(F32C, 1, None, P(0), P(1), P(2), 100, P(3), P(4), None, 0, 3, None, None, None) == NULL
+    assert call(so=off(0, 0)) == SIZE
+    assert call(nb=2, so=off(0, 60, 50)) == OFFSETS
+    assert call(nb=2, so=off(0, 50, 100)) == WORKSPACE  # the batched evaluation needs its queue
+    assert v.value == -1  # nothing chosen by a rejected call
 
 
 def gvs(dtype=F32C, n_batch=1, so=None, to=None, xs=P(0), gs=P(1), ss=P(2), lds=100, xt=P(3), gt=P(4), st=P(5),

@@ -8,7 +8,7 @@ import oracle
 import paper_2511_11430_amd as vpm
 from paper_2511_11430_amd import workloads as W
 
-from gpu_helpers import TOL, dev, host, prepare, rel_l2, say
+from gpu_helpers import TOL, dev, host, per_target, prepare, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 KINDS = ["f64", "f32c"]
@@ -113,35 +113,36 @@ def test_control_points_and_sampled_targets(kind, gpu):
     assert rel_l2(host(dt_), do) <= TOL[kind]
 
 
-def _sampled_parity(c, kind, n_sample, seed):
+def _sampled_parity(c, kind, idx, rule=0):
+    """Self evaluation of the whole set on the GPU, checked on the targets idx against the
+    oracle: rel-L2 and the worst single target (both within the gate)."""
     x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], kind)
-    n = x.shape[1]
-    say(f"full-size self evaluation {kind} N={n}")
-    u, d = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
-    idx = np.sort(np.random.default_rng(seed).choice(n, n_sample, replace=False))
-    uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
+    say(f"full-size self evaluation {kind} N={x.shape[1]} rule={rule}, {idx.size} sampled targets")
+    u, d = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind), sigma_rule=rule)
+    uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], sig_tgt=s[idx], excl=idx,
+                               sigma_rule=rule)
     U, D = host(u)[:, idx], host(d)[:, idx]
-    return rel_l2(U, uo), rel_l2(D, do)
+    out = rel_l2(U, uo), rel_l2(D, do), per_target(U, uo), per_target(D, do)
+    say(f"  rel-L2 u {out[0]:.3e} dgamma {out[1]:.3e}; worst target u {out[2]:.3e} dgamma {out[3]:.3e}")
+    return out
 
 
 @pytest.mark.parametrize("kind", KINDS)
 def test_config2_full_size_sampled(kind, gpu):
-    eu, ed = _sampled_parity(W.config2(), kind, 512, 21)
-    say(f"config2 {kind}: rel-L2 u {eu:.3e} dgamma {ed:.3e}")
-    assert eu <= TOL[kind] and ed <= TOL[kind]
+    idx = np.sort(np.random.default_rng(21).choice(65536, 512, replace=False))
+    errs = _sampled_parity(W.config2(), kind, idx)
+    assert max(errs) <= TOL[kind]
 
 
 @pytest.mark.parametrize("kind", KINDS)
-def test_config3_full_size_sampled(kind, gpu):
+@pytest.mark.parametrize("rule", [0, 1])
+def test_config3_full_size_sampled(kind, rule, gpu):
+    """The 1M forward-flight wake in the benchmark's launch, on all 4096 seeded sample
+    targets, with the source and the symmetric core rule."""
     c = W.config3()
-    x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], kind)
-    say(f"config3 {kind} N={x.shape[1]}")
-    u, d = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
-    idx = c["sample"][:: 16]  # 256 of the 4096 seeded sample targets
-    uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
-    eu, ed = rel_l2(host(u)[:, idx], uo), rel_l2(host(d)[:, idx], do)
-    say(f"config3 {kind}: rel-L2 u {eu:.3e} dgamma {ed:.3e}")
-    assert eu <= TOL[kind] and ed <= TOL[kind]
+    assert c["sample"].size == 4096
+    errs = _sampled_parity(c, kind, c["sample"], rule)
+    assert max(errs) <= TOL[kind]
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -301,9 +302,10 @@ def test_batched_full_size_sampled(kind, gpu):
         uo, do = oracle.eval_pairs(x, g, s, x_tgt=x[:, idx], gam_tgt=g[:, idx], excl=idx)
         lo = off[w]
         eu, ed = rel_l2(U[:, lo + idx], uo), rel_l2(D[:, lo + idx], do)
-        worst = max(worst, eu, ed)
-        assert eu <= TOL[kind] and ed <= TOL[kind], (w, eu, ed)
-    say(f"  worst per-wake rel-L2 {worst:.2e}")
+        pu, pd = per_target(U[:, lo + idx], uo), per_target(D[:, lo + idx], do)
+        worst = max(worst, eu, ed, pu, pd)
+        assert max(eu, ed, pu, pd) <= TOL[kind], (w, eu, ed, pu, pd)
+    say(f"  worst per-wake rel-L2 or single-target error {worst:.2e}")
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -317,6 +319,34 @@ def test_validate_inputs_flags_bad_particles(kind, gpu):
     x[1, 99] = np.inf
     out = vpm.vpm_validate_inputs(dev_(x, kind), dev_(g, kind), dev_(s, kind)).cpu().numpy()
     assert out[0] == 3 and out[1] == 1
+    assert not vpm.vpm_check_inputs(dev_(x, kind), dev_(g, kind), dev_(s, kind))  # VPM_ERR_INPUT
     x2, g2, s2 = prepare(_random_set(1000, 3), kind)
     out = vpm.vpm_validate_inputs(dev_(x2, kind), dev_(g2, kind), dev_(s2, kind)).cpu().numpy()
     assert out[0] == 0 and out[1] == 0
+    assert vpm.vpm_check_inputs(dev_(x2, kind), dev_(g2, kind), dev_(s2, kind))
+
+
+def test_autotune_times_every_shape_and_sets_the_plan(gpu):
+    """The library's tuner on an 8192-particle forward-flight wake and on six uneven wakes:
+    every shape timed, the fastest recorded in the plan (the tuning cache is re-applied after)."""
+    from paper_2511_11430_amd import tune
+    c = W.config3(n=8192)
+    x, g, s = (dev_(W.to_f32(c[k]), "f32c") for k in ("x", "gamma", "sigma"))
+    try:
+        best, ms = vpm.vpm_autotune(x, g, s, reps=2)
+        say(f"autotune 8192: variant {best}, ms {['%.3f' % t for t in ms]}")
+        assert len(ms) == vpm.vpm_variant_count() and all(t > 0 for t in ms)
+        assert best == 1 + int(np.argmin(ms))
+        assert vpm._lib.load().vpm_get_plan(vpm.F32C, 0, 8192) == best
+        wakes = W.config5(n_wakes=6, scale=0.05)
+        off = [0]
+        for w in wakes:
+            off.append(off[-1] + w["x"].shape[1])
+        cat = lambda k: dev_(np.concatenate([W.to_f32(w[k]) for w in wakes], -1), "f32c")
+        best_b, ms_b = vpm.vpm_autotune(cat("x"), cat("gamma"), cat("sigma"), src_off=off, reps=2)
+        assert best_b == 1 + int(np.argmin(ms_b))
+        assert vpm._lib.load().vpm_get_plan(vpm.F32C, 1, off[-1]) == best_b
+    finally:
+        for b in (0, 1):
+            vpm._lib.load().vpm_set_plan(vpm.F32C, b, 0, 1 << 31, 0)
+        tune.apply_cache()
