@@ -37,6 +37,7 @@ FLOP_PER_PAIR_VS = 45               # velocity + transposed stretching, point-vo
 # u += G v 6, A += G Gamma_j 6, Hn v 3, H += (Hn v) r^T 18
 FLOP_PER_PAIR_GRAD = 54
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pair_fwd_f32c_forward_flight_1M.json")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "counters_pair_fwd_f32c_forward_flight_1M.json")
 
 
 def log(msg):
@@ -62,6 +63,49 @@ def load_traffic(variant):
     if t.get("kernel_hash") != kernel_source_hash() or t.get("variant") != variant:
         return None
     return t.get("bytes_per_launch")
+
+
+def load_counters(variant):
+    """FP32 instruction counters of the pair kernel (rocprofv3 --pmc, calibrated against the
+    FMA-chain kernel) from the committed summary, if taken on the same kernel source and shape."""
+    try:
+        with open(COUNTER_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_source_hash() or t.get("variant") != variant:
+        return None
+    d = t["derived"]
+    keys = ("counter_tflops", "counter_flop_per_pair", "valu_instructions_per_pair", "fp32_fma_per_pair",
+            "fp32_mul_per_pair", "fp32_add_per_pair", "fp32_trans_per_pair", "valu_issue_per_cu_clock",
+            "clock_ghz")
+    out = {k: round(d[k], 4) for k in keys}
+    out["source"] = os.path.relpath(COUNTER_FILE, ROOT)
+    return out
+
+
+def fma_ceiling_tflops(vpm, torch, stream):
+    """FP32 rate of independent FMA chains (the library's calibration kernel) on this GPU with
+    packed FP32 instructions disabled: the practical ceiling of FMA-type VALU code."""
+    import ctypes
+    lanes, fmas = 1 << 22, 2048
+    out = torch.empty(lanes, dtype=torch.float32, device="cuda")
+    n = ctypes.c_int64()
+    lib = vpm._lib.load()
+    call = lambda: lib.vpm_fma_chain(lanes, fmas, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n),
+                                     ctypes.c_void_p(stream.cuda_stream))
+    assert call() == 0
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        call()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    return 2.0 * 64 * n.value / (best * 1e-3) / 1e12
 
 
 def main():
@@ -174,6 +218,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     nonfinite = int(diag[12].item())
+    fma_tf = fma_ceiling_tflops(vpm, torch, stream)
+    log(f"FMA-chain ceiling {fma_tf:.1f} TFLOP/s; pair kernel {achieved:.1f} TFLOP/s algorithmic")
 
     result = {
         "metric": "Gpair-interactions/s FP32-comp vs FP64 GPU at 1e-5 relL2; adjoint/fwd time",
@@ -187,7 +233,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": load_traffic(plan), "kernel": pair_kernel, "kernel_ms": round(k_ms, 3),
-                     "flop_per_pair": FLOP_PER_PAIR_VS},
+                     "flop_per_pair": FLOP_PER_PAIR_VS, "counters": load_counters(plan),
+                     "fma_chain_tflops": round(fma_tf, 2), "frac_of_fma_chain": round(achieved / fma_tf, 4)},
         "nonfinite": nonfinite,
         "env": {"gpu": torch.cuda.get_device_name(0),
                 "arch": getattr(torch.cuda.get_device_properties(0), "gcnArchName", None),

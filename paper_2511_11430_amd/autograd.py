@@ -11,7 +11,9 @@ control points.  The forward pass keeps every stage's input state in device memo
 (checkpoints: 3 n_steps states of 6 N values), so the backward pass replays the stages in
 reverse without recomputing the trajectory: at each stage it applies the RK3 register
 adjoint (``vpm_rk3_stage_backward``) and adds J_F^T seed with ``vpm_backward`` at the
-stage's checkpointed input.
+stage's checkpointed input.  ``rk3_gradient_recompute`` gives the same gradient keeping no
+stage inputs (each is recomputed from the initial state), for programs whose checkpoints
+would not fit.
 
 An optional fixed lattice of straight segments (blade rings, frozen wake lines: a, b, strength,
 core radius, Vatistas exponent) acts on the particles in every stage: its velocity and its
@@ -141,6 +143,72 @@ def rk3_backward(checkpoints, final_eval, sigma, uc, y_ctrl, dt, state_dtype, lo
             vpm_segments_backward(sa, sb, sg, xk, rc, vn, us, ds, gamma_tgt=gk, x_bar=ix, gamma_bar=ig)
     fold()
     return xb, gb
+
+
+def rk3_gradient_recompute(x0, gamma0, sigma, n_steps, dt, y_ctrl, segments=None):
+    """Gradient of the program's loss with respect to (x0, gamma0) keeping no stage inputs:
+    the backward pass re-runs the forward program from the initial state up to each stage it
+    needs (quadratic in the number of stages, memory of one state).  Returns (loss, x_bar,
+    gamma_bar); the same calls in the same order as with checkpoints, so the same bits."""
+    n_stages = 3 * int(n_steps)
+    x, g, uc, loss, final_eval = rk3_forward(x0, gamma0, sigma, n_steps, dt, y_ctrl, None, segments)
+    del x, g
+    xe, ge = final_eval
+    state_dtype = x0.dtype
+    mixed = state_dtype != xe.dtype
+    xb = torch.zeros(xe.shape, dtype=state_dtype, device=xe.device)
+    gb = torch.zeros_like(xb)
+    ix, ig = (torch.zeros_like(xe), torch.zeros_like(xe)) if mixed else (xb, gb)
+    _, ucb = vpm_axial_loss(uc, loss_bar=None)
+    vpm_backward(xe, ge, sigma, ucb, None, y_ctrl, None, None, x_src_bar=ix, gamma_src_bar=ig)
+    qxb, qgb = torch.zeros_like(xb), torch.zeros_like(xb)
+    us, ds = torch.empty_like(xe), torch.empty_like(xe)
+
+    def fold():
+        if mixed:
+            vpm_convert(ix, xb, accumulate=True)
+            vpm_convert(ig, gb, accumulate=True)
+            ix.zero_()
+            ig.zero_()
+
+    for i in reversed(range(n_stages)):
+        # the input of stage i: re-run the program's first i stages
+        xk, gk = _stage_input(x0, gamma0, sigma, dt, i, segments)
+        fold()
+        vpm_rk3_stage_backward(i % 3, dt, xb, gb, qxb, qgb, us, ds)
+        vpm_backward(xk, gk, sigma, us, ds, x_src_bar=ix, gamma_src_bar=ig)
+        if segments is not None:
+            sa, sb, sg, rc, vn = segments
+            vpm_segments_backward(sa, sb, sg, xk, rc, vn, us, ds, gamma_tgt=gk, x_bar=ix, gamma_bar=ig)
+        del xk, gk
+    fold()
+    return loss, xb, gb
+
+
+def _stage_input(x0, gamma0, sigma, dt, i, segments):
+    """The evaluation input of stage i (0-based) of the program, by re-running stages 0..i-1."""
+    edt = sigma.dtype
+    mixed = x0.dtype != edt
+    x, g = x0.clone(), gamma0.clone()
+    qx, qg = torch.zeros_like(x), torch.zeros_like(x)
+    if mixed:
+        xe, ge = torch.empty(x.shape, dtype=edt, device=x.device), torch.empty(x.shape, dtype=edt, device=x.device)
+        vpm_convert(x, xe)
+        vpm_convert(g, ge)
+    else:
+        xe, ge = x, g
+    u, dg = torch.empty_like(xe), torch.empty_like(xe)
+    for k in range(i):  # as in rk3_forward
+        vpm_eval_velocity_stretching(xe, ge, sigma, u_out=u, dgamma_out=dg)
+        if segments is not None:
+            sa, sb, sg, rc, vn = segments
+            vpm_eval_segments_gradient(sa, sb, sg, xe, rc, vn, gamma_tgt=ge, want_grad=False, u_out=u,
+                                       dgamma_out=dg, accumulate=True)
+        if mixed:
+            vpm_rk3_stage(k % 3, dt, x, g, qx, qg, u, dg, x_eval=xe, gamma_eval=ge)
+        else:
+            vpm_rk3_stage(k % 3, dt, x, g, qx, qg, u, dg)
+    return xe.clone(), ge.clone()
 
 
 class RK3Program(torch.autograd.Function):

@@ -427,3 +427,20 @@ def test_vjp_dot_product_varied_cores(kind, rule, gpu):
     lhs = (host(xb) * xd).sum() + (host(gb) * gd).sum()
     rhs = (ub * ud).sum() + (sb * dd).sum()
     assert abs(lhs - rhs) <= (1e-11 if kind == "f64" else 1e-5) * abs(rhs)
+
+
+@pytest.mark.parametrize("kind", ["f64", "mixed"])
+def test_checkpointed_and_recomputed_gradients_are_the_same_bits(kind, gpu):
+    """The program's gradient from its stage checkpoints and from stage inputs recomputed from
+    the initial state (no checkpoints kept) are bitwise equal: the checkpoints hold exactly the
+    states the backward pass needs."""
+    c = W.config4(n=4096, n_steps=3)
+    x, g, s, y = (W.to_f32(c[k]) for k in ("x", "gamma", "sigma", "ctrl"))
+    ek = "f64" if kind == "f64" else "f32c"
+    S, Y = dev(s, ek), dev(y, ek)
+    X, G = dev(x, "f64").requires_grad_(True), dev(g, "f64").requires_grad_(True)
+    L = AG.rk3_program_loss(X, G, S, c["n_steps"], c["dt"], Y)
+    L.backward()
+    L2, xb, gb = AG.rk3_gradient_recompute(dev(x, "f64"), dev(g, "f64"), S, c["n_steps"], c["dt"], Y)
+    assert torch.equal(L.detach(), L2)
+    assert torch.equal(X.grad, xb) and torch.equal(G.grad, gb)

@@ -273,8 +273,9 @@ def test_permutation_invariance(kind, gpu):
     u1, d1 = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
     u2, d2 = vpm.vpm_eval_velocity_stretching(dev_(x[:, perm], kind), dev_(g[:, perm], kind), dev_(s[perm], kind))
     tight = 1e-13 if kind == "f64" else TOL[kind]
-    assert rel_l2(host(u2), host(u1)[:, perm]) <= tight
-    assert rel_l2(host(d2), host(d1)[:, perm]) <= tight
+    eu, ed = rel_l2(host(u2), host(u1)[:, perm]), rel_l2(host(d2), host(d1)[:, perm])
+    say(f"permutation {kind}: rel-L2 u {eu:.2e} dgamma {ed:.2e}")
+    assert eu <= tight and ed <= tight
     # and twice the same launch is bitwise identical (no order-dependent reduction)
     u3, d3 = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
     assert torch.equal(u1, u3) and torch.equal(d1, d3)

@@ -112,12 +112,17 @@ def test_rk3_program_with_lattice_gradient_vs_oracle_tangents(kind, gpu):
     X, G = dev(x, "f64").requires_grad_(True), dev(g, "f64").requires_grad_(True)
     L = AG.rk3_program_loss(X, G, dev(s, ek), steps, dt, dev(y, ek), segments=lat_d)
     L.backward()
-    Lo = oracle.rk3_program(x, g, s, steps, dt, y, segments=lat_o)[3]
-    # mixed: the FP32 evaluation inputs quantise positions of ~1 m to 6e-8 m; 0.017 m from the
-    # nearest segment the stretching's second-derivative term (~1/d^3) moves by ~3 x 6e-8 /
-    # 0.017 = 1e-5 relative per evaluation, over six stages: 1e-4 per direction.
-    tol = 1e-10 if kind == "f64" else 1e-4
-    assert abs(L.item() - Lo) <= (1e-12 if kind == "f64" else 1e-5) * abs(Lo)
+    # mixed: compared with the oracle's program under the same storage model (evaluation
+    # inputs and results rounded to FP32, FP64 state), to the adjoint gate; how far that model
+    # itself is from the exact program (FP32 positions near 1 m, 0.017 m from the nearest
+    # segment) is printed
+    st = oracle.STORE_F64 if kind == "f64" else oracle.STORE_F32_EVAL
+    Lo = oracle.rk3_program(x, g, s, steps, dt, y, segments=lat_o, storage=st)[3]
+    Lx = oracle.rk3_program(x, g, s, steps, dt, y, segments=lat_o)[3]
+    say(f"  loss {abs(L.item() - Lo) / abs(Lo):.2e} against the storage model; model vs exact "
+        f"{abs(Lo - Lx) / abs(Lx):.2e}")
+    tol = 1e-10 if kind == "f64" else 1e-6
+    assert abs(L.item() - Lo) <= (1e-12 if kind == "f64" else 1e-6) * abs(Lo)
     gx, gg = host(X.grad), host(G.grad)
     rng = np.random.default_rng(17)
     dirs = [(rng.normal(size=x.shape), np.zeros_like(g)) for _ in range(3)]
@@ -128,14 +133,18 @@ def test_rk3_program_with_lattice_gradient_vs_oracle_tangents(kind, gpu):
             xd = np.zeros_like(x)
             xd[c, i] = 1.0
             dirs.append((xd, np.zeros_like(g)))
-    worst = 0.0
+    worst = worst_model = 0.0
     for xd, gd in dirs:
-        ref = oracle.rk3_program_jvp(x, g, s, xd, gd, steps, dt, y, segments=lat_o)[1]
+        ref = oracle.rk3_program_jvp(x, g, s, xd, gd, steps, dt, y, segments=lat_o, storage=st)[1]
         got = float((gx * xd).sum() + (gg * gd).sum())
         worst = max(worst, abs(got - ref) / max(abs(ref), 1e-30))
-    say(f"  worst relative error over {len(dirs)} directions {worst:.2e}")
+        if kind != "f64":
+            ex = oracle.rk3_program_jvp(x, g, s, xd, gd, steps, dt, y, segments=lat_o)[1]
+            worst_model = max(worst_model, abs(ref - ex) / max(abs(ex), 1e-30))
+    say(f"  worst relative error over {len(dirs)} directions {worst:.2e} (storage model vs exact "
+        f"{worst_model:.2e})")
     assert worst <= tol
     # the lattice is felt by the gradient, not only by the loss
     X2, G2 = dev(x, "f64").requires_grad_(True), dev(g, "f64").requires_grad_(True)
     AG.rk3_program_loss(X2, G2, dev(s, ek), steps, dt, dev(y, ek)).backward()
-    assert rel_l2(host(X2.grad), gx) > 10 * tol  # 0.46 % here
+    assert rel_l2(host(X2.grad), gx) > 1e-3  # 0.46 % here
