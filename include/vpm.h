@@ -122,6 +122,26 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
                                         int64_t ld_out, const vpm_options* opt, void* workspace,
                                         size_t ws_bytes, void* stream);
 
+/* vpm_eval_velocity_stretching_noalloc — vpm_eval_velocity_stretching for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments without the workspace, one set only (n_batch == 1;
+ * VPM_ERR_UNSUPPORTED otherwise, since the batched queue is staged from host memory).  Source-
+ * split partial sums of small target sets go to a static device array of
+ * vpm_noalloc_scratch_bytes() bytes (32 MiB) that the library holds on each GPU it runs on for
+ * the life of the process; when the split would need more, it uses as many source chunks as
+ * the array holds (results then differ from the workspace form only in summation order).  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library routine; its first call
+ * on a device looks up the array's address).  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (different streams, or different host threads) race
+ * and must be serialised by the caller.  Errors as vpm_eval_velocity_stretching. */
+vpm_status vpm_eval_velocity_stretching_noalloc(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                                                const int64_t* tgt_off, const void* x_src, const void* gamma_src,
+                                                const void* sigma_src, int64_t ld_src, const void* x_tgt,
+                                                const void* gamma_tgt, const void* sigma_tgt, int64_t ld_tgt,
+                                                const int32_t* tgt_exclude, void* u_out, void* dgamma_out,
+                                                int64_t ld_out, const vpm_options* opt, void* stream);
+size_t vpm_noalloc_scratch_bytes(void);
+
 /* ---------------------------------------------------------------------------------------
  * vpm_eval_velocity_gradient — as vpm_eval_velocity_stretching, and also the velocity
  * gradient at every target, the input of the sub-grid model of Sec. II.B:

@@ -66,6 +66,10 @@ SIGNATURES = {
     "vpm_check_inputs": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]),
     "vpm_check_inputs_workspace_size": (c_sz, []),
     "vpm_fma_chain": (c_i32, [c_i64, c_i32, c_vp, c_i64p, c_vp]),
+    "vpm_eval_velocity_stretching_noalloc": (c_i32, [c_i32, c_i32, c_i64p, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp,
+                                                     c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64,
+                                                     ctypes.POINTER(VpmOptions), c_vp]),
+    "vpm_noalloc_scratch_bytes": (c_sz, []),
     "vpm_autotune": (c_i32, [c_i32, c_i32, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_i32,
                              ctypes.POINTER(c_i32), ctypes.POINTER(ctypes.c_float), c_vp]),
     "vpm_validate_inputs": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),

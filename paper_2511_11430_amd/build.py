@@ -16,7 +16,7 @@ BUILD = os.path.join(CSRC, "_build")
 LIB = os.path.join(HERE, "libvpm.so")
 ARCH = "gfx950"
 SOURCES = ["vpm_api.cpp", "pair_forward.hip", "segments.hip", "backward.hip", "rk3_diag.hip", "viscous.hip", "uvlm.hip", "fmm.hip",
-           "calibrate.hip"]
+           "calibrate.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

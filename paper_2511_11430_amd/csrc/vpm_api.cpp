@@ -278,6 +278,27 @@ SplitPlan split_plan(int32_t dtype, int variant, int nacc, int64_t n_src, int64_
     return p;
 }
 
+// The same split with as many chunks as `bytes` of partial sums hold (none below two).
+SplitPlan fit_plan(SplitPlan p, int nacc, int64_t n_src, int64_t n_tgt, size_t bytes) {
+    const size_t per_chunk = size_t(nacc) * size_t(n_tgt) * sizeof(double);
+    for (int64_t most = per_chunk ? int64_t(bytes / per_chunk) : 0; most >= 2; --most) {
+        int64_t chunk = (n_src + most - 1) / most;
+        chunk = (chunk + 255) / 256 * 256;
+        const int64_t nchunk = (n_src + chunk - 1) / chunk;
+        const size_t need = align_up(size_t(nchunk) * per_chunk);
+        if (nchunk >= 2 && need <= bytes) {
+            p.chunk = chunk;
+            p.nchunk = nchunk;
+            p.bytes = need;
+            return p;
+        }
+    }
+    p.chunk = n_src;
+    p.nchunk = 1;
+    p.bytes = 0;
+    return p;
+}
+
 // Adjoint of the classical scheme.  Its pair term S_i . (J Gamma_i) equals the transposed
 // term Gamma_i . (J^T S_i) with the target's strength and its stretching seed exchanged, while
 // the velocity term and the source strengths are unchanged.  So: the transposed adjoint kernel
@@ -428,7 +449,7 @@ vpm_status eval_impl(int32_t dtype, int32_t n_batch, const int64_t* src_off, con
                      const void* x_src, const void* gamma_src, const void* sigma_src, int64_t ld_src,
                      const void* x_tgt, const void* gamma_tgt, const void* sigma_tgt, int64_t ld_tgt,
                      const int32_t* tgt_exclude, void* u_out, void* dgamma_out, void* grad_out, int64_t ld_out,
-                     vpm_options o, void* workspace, size_t ws_bytes, void* stream) {
+                     vpm_options o, void* workspace, size_t ws_bytes, void* stream, bool noalloc = false) {
     if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
     if (n_batch < 1) return VPM_ERR_SIZE;
     vpm_status s = check_options(o);
@@ -497,6 +518,11 @@ vpm_status eval_impl(int32_t dtype, int32_t n_batch, const int64_t* src_off, con
 
     // ---- launch (first HIP call)
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (noalloc) {
+        // the source-split partials go to the library's own scratch array
+        if (vpm::noalloc_scratch(&workspace) != hipSuccess) return VPM_ERR_HIP;
+        ws_bytes = vpm::kNoAllocScratchBytes;
+    }
     vpm::FwdArgs a;
     a.xs = x_src;
     a.gs = gamma_src;
@@ -525,7 +551,9 @@ vpm_status eval_impl(int32_t dtype, int32_t n_batch, const int64_t* src_off, con
     const int64_t per_block = targets_per_block(dtype, variant);
 
     if (n_batch == 1) {
-        const SplitPlan sp = split_plan(dtype, variant, vpm::nacc_of(mode), n_src, n_tgt);
+        SplitPlan sp = split_plan(dtype, variant, vpm::nacc_of(mode), n_src, n_tgt);
+        if (noalloc && sp.nchunk > 1 && sp.bytes > ws_bytes)
+            sp = fit_plan(sp, vpm::nacc_of(mode), n_src, n_tgt, ws_bytes);
         if (sp.nchunk > 1 && workspace && ws_bytes >= sp.bytes) {
             a.part = static_cast<double*>(workspace);
             a.chunk = sp.chunk;
@@ -597,6 +625,23 @@ vpm_status vpm_eval_velocity_stretching(int32_t dtype, int32_t n_batch, const in
                      sigma_tgt, ld_tgt, tgt_exclude, u_out, dgamma_out, nullptr, ld_out, o, workspace, ws_bytes,
                      stream);
 }
+
+vpm_status vpm_eval_velocity_stretching_noalloc(int32_t dtype, int32_t n_batch, const int64_t* src_off,
+                                                const int64_t* tgt_off, const void* x_src, const void* gamma_src,
+                                                const void* sigma_src, int64_t ld_src, const void* x_tgt,
+                                                const void* gamma_tgt, const void* sigma_tgt, int64_t ld_tgt,
+                                                const int32_t* tgt_exclude, void* u_out, void* dgamma_out,
+                                                int64_t ld_out, const vpm_options* opt, void* stream) {
+    if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
+    if (n_batch < 1) return VPM_ERR_SIZE;
+    if (n_batch != 1) return VPM_ERR_UNSUPPORTED;  // the batched queue is staged from host memory
+    vpm_options o = opt ? *opt : default_options();
+    if (o.gradient != 0) return VPM_ERR_ENUM;
+    return eval_impl(dtype, n_batch, src_off, tgt_off, x_src, gamma_src, sigma_src, ld_src, x_tgt, gamma_tgt,
+                     sigma_tgt, ld_tgt, tgt_exclude, u_out, dgamma_out, nullptr, ld_out, o, nullptr, 0, stream, true);
+}
+
+size_t vpm_noalloc_scratch_bytes(void) { return vpm::kNoAllocScratchBytes; }
 
 vpm_status vpm_eval_velocity_gradient(int32_t dtype, int32_t n_batch, const int64_t* src_off,
                                       const int64_t* tgt_off, const void* x_src, const void* gamma_src,

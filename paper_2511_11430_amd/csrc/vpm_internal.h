@@ -69,6 +69,10 @@ constexpr int kF64TargetsPerBlock = 256;
 // persistent grid over bq.
 hipError_t launch_pair_fwd(int dtype, int variant, int mode, bool sym, const FwdArgs& a,
                            const BatchQueue* bq, int grid, hipStream_t st);
+// Scratch of the no-allocation entry point: a file-scope device array of this many bytes
+// (noalloc.hip); noalloc_scratch returns its address on the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+hipError_t noalloc_scratch(void** ptr);
 int pair_fwd_occupancy(int dtype, int variant, int mode, bool sym, bool batched);
 
 // ---------------------------------------------------------------- segments
