@@ -84,15 +84,17 @@ def load_counters(variant):
     return out
 
 
-def fma_ceiling_tflops(vpm, torch, stream):
+def fma_chain_tflops(vpm, torch, stream, form):
     """FP32 rate of independent FMA chains (the library's calibration kernel) on this GPU with
-    packed FP32 instructions disabled: the practical ceiling of FMA-type VALU code."""
+    packed FP32 instructions disabled.  form 0: the accumulating form with register operands,
+    the VALU FMA rate that the pair kernel's arithmetic competes with; form 1: one operand in a
+    scalar register, a slower issue form; form 2: three register operands (VOP3 encoding)."""
     import ctypes
     lanes, fmas = 1 << 22, 2048
     out = torch.empty(lanes, dtype=torch.float32, device="cuda")
     n = ctypes.c_int64()
     lib = vpm._lib.load()
-    call = lambda: lib.vpm_fma_chain(lanes, fmas, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n),
+    call = lambda: lib.vpm_fma_chain(lanes, fmas, form, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n),
                                      ctypes.c_void_p(stream.cuda_stream))
     assert call() == 0
     torch.cuda.synchronize()
@@ -205,7 +207,7 @@ def main():
         lanes, fmas = 1 << 20, 1024
         out = torch.empty(lanes, dtype=torch.float32, device=dev)
         n_fma = ctypes.c_int64()
-        st_ = vpm._lib.load().vpm_fma_chain(lanes, fmas, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n_fma),
+        st_ = vpm._lib.load().vpm_fma_chain(lanes, fmas, 0, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n_fma),
                                             ctypes.c_void_p(stream.cuda_stream))
         torch.cuda.synchronize()
         log(f"calibration k_fma_chain: status {st_}, {n_fma.value} FP32 FMA wavefront instructions "
@@ -218,8 +220,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     nonfinite = int(diag[12].item())
-    fma_tf = fma_ceiling_tflops(vpm, torch, stream)
-    log(f"FMA-chain ceiling {fma_tf:.1f} TFLOP/s; pair kernel {achieved:.1f} TFLOP/s algorithmic")
+    fma_tf = fma_chain_tflops(vpm, torch, stream, 0)
+    fma_tf_s = fma_chain_tflops(vpm, torch, stream, 1)
+    fma_tf_3 = fma_chain_tflops(vpm, torch, stream, 2)
+    log(f"FMA chains: {fma_tf:.1f} TFLOP/s (accumulating, register operands), {fma_tf_3:.1f} (three register "
+        f"operands), {fma_tf_s:.1f} (scalar operand); pair kernel {achieved:.1f} TFLOP/s algorithmic")
 
     result = {
         "metric": "Gpair-interactions/s FP32-comp vs FP64 GPU at 1e-5 relL2; adjoint/fwd time",
@@ -234,7 +239,10 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": load_traffic(plan), "kernel": pair_kernel, "kernel_ms": round(k_ms, 3),
                      "flop_per_pair": FLOP_PER_PAIR_VS, "counters": load_counters(plan),
-                     "fma_chain_tflops": round(fma_tf, 2), "frac_of_fma_chain": round(achieved / fma_tf, 4)},
+                     "fma_chain_tflops": {"accumulating_register_operands": round(fma_tf, 2),
+                                          "three_register_operands": round(fma_tf_3, 2),
+                                          "scalar_operand": round(fma_tf_s, 2)},
+                     "frac_of_fma_chain": round(achieved / fma_tf, 4)},
         "nonfinite": nonfinite,
         "env": {"gpu": torch.cuda.get_device_name(0),
                 "arch": getattr(torch.cuda.get_device_properties(0), "gcnArchName", None),

@@ -54,7 +54,7 @@ typedef enum vpm_status {
     VPM_ERR_NULL = 1,        /* a required pointer is NULL */
     VPM_ERR_SIZE = 2,        /* a count < 0, ld < count, or a size above the supported range */
     VPM_ERR_DTYPE = 3,       /* dtype is not VPM_F64 / VPM_F32C */
-    VPM_ERR_ENUM = 4,        /* scheme, sigma rule, stage or Vatistas exponent out of range */
+    VPM_ERR_ENUM = 4,        /* scheme, sigma rule, stage, Vatistas exponent or form out of range */
     VPM_ERR_ALIAS = 5,       /* an output overlaps an input or another output */
     VPM_ERR_OFFSETS = 6,     /* batch offsets not starting at 0, decreasing, or mismatched */
     VPM_ERR_WORKSPACE = 7,   /* workspace NULL or smaller than required */
@@ -524,15 +524,20 @@ vpm_status vpm_autotune(int32_t dtype, int32_t n_batch, const int64_t* src_off, 
 vpm_status vpm_set_plan(int32_t dtype, int32_t batched, int64_t n_lo, int64_t n_hi, int32_t variant);
 int32_t vpm_get_plan(int32_t dtype, int32_t batched, int64_t n);
 
-/* vpm_fma_chain — calibration kernel for hardware counters (not part of the method): n_lanes
- * lanes each run 8 independent chains of fmas_per_chain dependent FP32 fused multiply-adds
- * (a multiple of 4) and store one float to out (device float[n_lanes]).  fma_instructions
- * (host, may be NULL) receives the number of FP32 FMA instructions the launch issues,
+/* vpm_fma_chain — calibration kernel for hardware counters and for the FP32 FMA rate (not part
+ * of the method): n_lanes lanes each run 8 independent chains of fmas_per_chain dependent FP32
+ * fused multiply-adds (a multiple of 4) and store one float to out (device float[n_lanes]).
+ * form 0: the accumulating form with per-lane register operands (a = b * d + a, v_fmac_f32),
+ * which the particle kernels' sums use; form 1: one operand a kernel argument held in a
+ * scalar register (a = a * s + t), a slower issue form on this GPU; form 2: the three-operand
+ * encoding with register operands (a = a * b + d, v_fma_f32).  fma_instructions (host,
+ * may be NULL) receives the number of FP32 FMA instructions the launch issues,
  * ceil(n_lanes / 64) x 8 x fmas_per_chain wavefront instructions, against which counter
- * readings (e.g. rocprofv3's SQ_INSTS_VALU_FMA_F32) are scaled.  Errors: VPM_ERR_SIZE,
+ * readings (e.g. rocprofv3's SQ_INSTS_VALU_FMA_F32) are scaled, and from which the achieved
+ * FMA rate follows with a timing of the launch.  Errors: VPM_ERR_SIZE, VPM_ERR_ENUM (form),
  * VPM_ERR_NULL, VPM_ERR_HIP. */
-vpm_status vpm_fma_chain(int64_t n_lanes, int32_t fmas_per_chain, float* out, int64_t* fma_instructions,
-                         void* stream);
+vpm_status vpm_fma_chain(int64_t n_lanes, int32_t fmas_per_chain, int32_t form, float* out,
+                         int64_t* fma_instructions, void* stream);
 
 /* Human-readable name of a status code (static string). */
 const char* vpm_status_string(int32_t status);

@@ -14,6 +14,7 @@ import ctypes
 from . import _lib
 
 F64, F32C = 0, 1
+ENUM_ERROR = 4  # VPM_ERR_ENUM
 INPUT_ERROR = 9  # VPM_ERR_INPUT
 TRANSPOSED, CLASSICAL = 0, 1
 SIGMA_SOURCE, SIGMA_SYMMETRIC = 0, 1

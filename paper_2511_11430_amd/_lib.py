@@ -65,7 +65,7 @@ SIGNATURES = {
     "vpm_backward_workspace_size": (c_sz, [c_i32, c_i32, c_i64p, c_i64p]),
     "vpm_check_inputs": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]),
     "vpm_check_inputs_workspace_size": (c_sz, []),
-    "vpm_fma_chain": (c_i32, [c_i64, c_i32, c_vp, c_i64p, c_vp]),
+    "vpm_fma_chain": (c_i32, [c_i64, c_i32, c_i32, c_vp, c_i64p, c_vp]),
     "vpm_eval_velocity_stretching_noalloc": (c_i32, [c_i32, c_i32, c_i64p, c_i64p, c_vp, c_vp, c_vp, c_i64, c_vp,
                                                      c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64,
                                                      ctypes.POINTER(VpmOptions), c_vp]),

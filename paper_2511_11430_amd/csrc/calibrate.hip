@@ -1,11 +1,18 @@
-// Calibration kernel for hardware counters: a known number of FP32 fused multiply-adds, so
-// that the instruction counts rocprofv3 reports for the particle kernels can be scaled to
-// per-wavefront instructions and FLOPs (counters on this GPU are aggregated per shader engine).
+// Calibration kernel for hardware counters and for the FP32 FMA rate of this GPU: a known
+// number of FP32 fused multiply-adds, so that the instruction counts rocprofv3 reports for the
+// particle kernels can be scaled to per-wavefront instructions and FLOPs (counters on this GPU
+// are aggregated per shader engine), and so that the VALU rate the pair kernels compete with
+// is measured rather than assumed.
 //
-// Each lane runs kChains independent chains of `fmas` dependent a = a * b + c steps (runtime
-// b and c, so nothing folds), then adds its chains and stores one float.  Per wavefront that is
-// exactly kChains * fmas FP32 FMA instructions (the compiler emits one v_fma/v_fmac per step;
-// the final sum is kChains - 1 FP32 adds).
+// Each lane runs kChains independent chains of `fmas` dependent steps, then adds its chains and
+// stores one float.  Per wavefront that is exactly kChains * fmas FP32 FMA instructions (the
+// final sum is kChains - 1 FP32 adds).  Two operand forms:
+//  - form 0: a = b * d + a with b, d per-lane registers, the accumulating VOP2 form
+//    (v_fmac_f32 with VGPR operands) that the pair kernels' sums use;
+//  - form 1: a = a * s + t with s, t kernel arguments, one of them read from a scalar
+//    register (v_fma_f32 with an SGPR operand);
+//  - form 2: a = a * b + d, the three-operand VOP3 encoding (v_fma_f32) with register operands.
+// On gfx950 form 1 issues at about half the rate of form 0, form 2 in between.
 #include <hip/hip_runtime.h>
 
 #include "vpm_internal.h"
@@ -16,30 +23,41 @@ namespace {
 
 constexpr int kChains = 8;
 
-__global__ __launch_bounds__(256) void k_fma_chain(int64_t n, int fmas, float b, float c, float* out) {
+template <int FORM>
+__global__ __launch_bounds__(256) void k_fma_chain(int64_t n, int fmas, float s, float t, float* out) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    // per-lane factors (not foldable, not uniform, and formed without an FMA): b is s moved
+    // by a few ulps, d small
+    const float b = __int_as_float(__float_as_int(s) + int(threadIdx.x & 7));
+    const float d = t * float(1 + (threadIdx.x & 3));
     float a[kChains];
 #pragma unroll
     for (int k = 0; k < kChains; ++k) a[k] = float(int(threadIdx.x) + k);
-    for (int s = 0; s < fmas; s += 4) {
+    for (int r = 0; r < fmas; r += 4) {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int k = 0; k < kChains; ++k) a[k] = fmaf(a[k], b, c);
+            for (int k = 0; k < kChains; ++k)
+                a[k] = FORM == 0 ? fmaf(b, d, a[k]) : (FORM == 1 ? fmaf(a[k], s, t) : fmaf(a[k], b, d));
     }
-    float t = a[0];
+    float acc = a[0];
 #pragma unroll
-    for (int k = 1; k < kChains; ++k) t += a[k];
-    if (i < n) out[i] = t;
+    for (int k = 1; k < kChains; ++k) acc += a[k];
+    if (i < n) out[i] = acc;
 }
 
 }  // namespace
 
 int fma_chain_count() { return kChains; }
 
-hipError_t launch_fma_chain(int64_t n, int fmas, float* out, hipStream_t st) {
+hipError_t launch_fma_chain(int64_t n, int fmas, int form, float* out, hipStream_t st) {
     const unsigned nb = unsigned((n + 255) / 256);
-    hipLaunchKernelGGL(k_fma_chain, dim3(nb), dim3(256), 0, st, n, fmas, 0.999f, 1e-3f, out);
+    if (form == 0)
+        hipLaunchKernelGGL(k_fma_chain<0>, dim3(nb), dim3(256), 0, st, n, fmas, 0.999f, 1e-3f, out);
+    else if (form == 1)
+        hipLaunchKernelGGL(k_fma_chain<1>, dim3(nb), dim3(256), 0, st, n, fmas, 0.999f, 1e-3f, out);
+    else
+        hipLaunchKernelGGL(k_fma_chain<2>, dim3(nb), dim3(256), 0, st, n, fmas, 0.999f, 1e-3f, out);
     return hipGetLastError();
 }
 

@@ -205,6 +205,6 @@ hipError_t launch_axial_loss(int dtype, int64_t m, const void* u, int64_t ld, do
 
 // ---------------------------------------------------------------- counter calibration
 int fma_chain_count();
-hipError_t launch_fma_chain(int64_t n, int fmas, float* out, hipStream_t st);
+hipError_t launch_fma_chain(int64_t n, int fmas, int form, float* out, hipStream_t st);
 
 }  // namespace vpm

@@ -272,7 +272,7 @@ def test_permutation_invariance(kind, gpu):
     perm = np.random.default_rng(9).permutation(x.shape[1])
     u1, d1 = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
     u2, d2 = vpm.vpm_eval_velocity_stretching(dev_(x[:, perm], kind), dev_(g[:, perm], kind), dev_(s[perm], kind))
-    tight = 1e-13 if kind == "f64" else TOL[kind]
+    tight = 1e-13 if kind == "f64" else 1e-6  # measured 1.1e-7 (u), 2.3e-7 (dgamma)
     eu, ed = rel_l2(host(u2), host(u1)[:, perm]), rel_l2(host(d2), host(d1)[:, perm])
     say(f"permutation {kind}: rel-L2 u {eu:.2e} dgamma {ed:.2e}")
     assert eu <= tight and ed <= tight
@@ -351,3 +351,39 @@ def test_autotune_times_every_shape_and_sets_the_plan(gpu):
         for b in (0, 1):
             vpm._lib.load().vpm_set_plan(vpm.F32C, b, 0, 1 << 31, 0)
         tune.apply_cache()
+
+
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_fma_chain_calibration_kernel(form, gpu):
+    """The calibration kernel reports the FMA instruction count it issues and computes the
+    chains it claims: each lane's result is the sum of its 8 chains, checked on the host (FP64
+    emulation of the FP32 steps, each rounded to FP32, for a short chain)."""
+    import ctypes
+    import torch
+    lanes, fmas = 256, 8
+    out = torch.empty(lanes, dtype=torch.float32, device="cuda")
+    n = ctypes.c_int64()
+    lib = vpm._lib.load()
+    assert lib.vpm_fma_chain(lanes, fmas, form, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), None) == 0
+    torch.cuda.synchronize()
+    assert n.value == (lanes // 64) * 8 * fmas
+    assert lib.vpm_fma_chain(lanes, fmas, 3, ctypes.c_void_p(out.data_ptr()), None, None) == vpm.ENUM_ERROR
+    s, t = np.float32(0.999), np.float32(1e-3)
+    f32 = np.float32
+    got = host(out)
+    for lane in (0, 5, 63, 200):
+        b = np.frombuffer((np.frombuffer(s.tobytes(), np.int32) + (lane & 7)).tobytes(), np.float32)[0]
+        d = f32(t * f32(1 + (lane & 3)))
+        a = [f32(lane + k) for k in range(8)]
+        for _ in range(fmas):
+            for k in range(8):
+                if form == 0:
+                    a[k] = f32(float(b) * float(d) + float(a[k]))
+                elif form == 1:
+                    a[k] = f32(float(a[k]) * float(s) + float(t))
+                else:
+                    a[k] = f32(float(a[k]) * float(b) + float(d))
+        acc = a[0]
+        for k in range(1, 8):
+            acc = f32(acc + a[k])
+        assert got[lane] == acc, (lane, got[lane], acc)

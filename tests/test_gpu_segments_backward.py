@@ -113,15 +113,18 @@ def test_rk3_program_with_lattice_gradient_vs_oracle_tangents(kind, gpu):
     L = AG.rk3_program_loss(X, G, dev(s, ek), steps, dt, dev(y, ek), segments=lat_d)
     L.backward()
     # mixed: compared with the oracle's program under the same storage model (evaluation
-    # inputs and results rounded to FP32, FP64 state), to the adjoint gate; how far that model
+    # inputs and results rounded to FP32, FP64 state), to the FP32C gate; how far that model
     # itself is from the exact program (FP32 positions near 1 m, 0.017 m from the nearest
-    # segment) is printed
+    # segment; 3.6e-5 at the unit directions) is printed.  What remains against the model
+    # (4.2e-6 at a unit direction next to the lattice, 1e-7 on the loss) is the FP32 evaluation
+    # itself: the rings' shared edges carry opposite circulations, whose large contributions
+    # cancel at a particle that close
     st = oracle.STORE_F64 if kind == "f64" else oracle.STORE_F32_EVAL
     Lo = oracle.rk3_program(x, g, s, steps, dt, y, segments=lat_o, storage=st)[3]
     Lx = oracle.rk3_program(x, g, s, steps, dt, y, segments=lat_o)[3]
     say(f"  loss {abs(L.item() - Lo) / abs(Lo):.2e} against the storage model; model vs exact "
         f"{abs(Lo - Lx) / abs(Lx):.2e}")
-    tol = 1e-10 if kind == "f64" else 1e-6
+    tol = 1e-10 if kind == "f64" else TOL[ek]
     assert abs(L.item() - Lo) <= (1e-12 if kind == "f64" else 1e-6) * abs(Lo)
     gx, gg = host(X.grad), host(G.grad)
     rng = np.random.default_rng(17)
