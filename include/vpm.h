@@ -287,7 +287,7 @@ vpm_status vpm_segments_backward(int32_t dtype, int64_t n_seg, const void* a, co
  *  x, gamma [3][ld], sigma [ld]; u_out, dgamma_out [3][ld_out] (written, in the input order);
  *  grad_out [9][ld_out] (row 3a + b = du_a/dx_b, near pairs exact, far field from the local
  *  expansions) or NULL: the velocity gradient the paper's FMM also provides (Vreman's model).
- *  0 <= level <= 10, 1 <= order <= 16, n < 2^30.
+ *  0 <= level <= 10, 1 <= order <= 20, n < 2^30.
  *  workspace        vpm_fmm_workspace_size(dtype, n, level, order) bytes (0 if invalid);
  *                   holds the sorted particles, the tree and the expansions.
  * Returns VPM_OK or the first violated condition. */

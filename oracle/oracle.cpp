@@ -1181,11 +1181,11 @@ int orc_diagnostics(int64_t n, const double* x, const double* G, const double* u
 // Cartesian FMM evaluation of the self-interaction of n particles (velocity and stretching,
 // scheme 0 transposed / 1 classical; optionally the velocity gradient J [9][n], row 3a + b =
 // du_a/dx_b) on a uniform octree of depth `level` (0..10) with expansions of order `order`
-// (1..16).
+// (1..20).
 int orc_fmm(int64_t n, const double* x, const double* G, const double* sig, int level, int order, int scheme,
             double* u, double* dg, double* J, int nthreads) {
     if (n < 0 || (n > 0 && (!x || !G || !sig || !u || !dg))) return 1;
-    if (level < 0 || level > 10 || order < 1 || order > 16 || scheme < 0 || scheme > 1) return 1;
+    if (level < 0 || level > 10 || order < 1 || order > 20 || scheme < 0 || scheme > 1) return 1;
     set_threads<double>(nthreads);
     fmm_eval(n, x, G, sig, level, order, scheme, u, dg, J);
     return 0;

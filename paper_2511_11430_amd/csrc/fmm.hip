@@ -47,17 +47,20 @@ namespace vpm {
 
 namespace {
 
-constexpr int kMaxOrder = 16;
-constexpr int kMaxTerms = (kMaxOrder + 1) * (kMaxOrder + 2) * (kMaxOrder + 3) / 6;  // 969
+constexpr int kMaxOrder = 20;
+constexpr int kMaxTerms = (kMaxOrder + 1) * (kMaxOrder + 2) * (kMaxOrder + 3) / 6;  // 1771
+// terms per lane in the kernels whose 256 lanes own the terms t = lane + 256 j
+constexpr int kSlots = (kMaxTerms + 255) / 256;  // 7
 constexpr int kMaxLevel = 10;
 constexpr int kNearTile = 256;
 constexpr int kOffsets = 343;  // [-3, 3]^3
 constexpr double kInv4Pi = 0.0795774715459476678844418816862571810;
 // 1/k for the monomial recurrences a^k/k! = (a^(k-1)/(k-1)!) a (1/k) (a multiply, not an FP64
 // division, in the per-particle loops)
-__constant__ double kInvInt[kMaxOrder + 2] = {0.0,      1.0,       1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,
-                                              1.0 / 6,  1.0 / 7,   1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
-                                              1.0 / 12, 1.0 / 13,  1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17};
+__constant__ double kInvInt[kMaxOrder + 2] = {0.0,      1.0,      1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,
+                                              1.0 / 6,  1.0 / 7,  1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
+                                              1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17,
+                                              1.0 / 18, 1.0 / 19, 1.0 / 20, 1.0 / 21};
 
 __host__ __device__ constexpr int nterms(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
@@ -442,8 +445,8 @@ __global__ __launch_bounds__(256) void k_fmm_p2m(const T* __restrict__ xs, const
     cell_coords(lv.code[cell], ic);
     double c[3];
     for (int d = 0; d < 3; ++d) c[d] = cell_centre(box, d, ic[d], level);
-    double acc[4][3];
-    for (int j = 0; j < 4; ++j)
+    double acc[kSlots][3];
+    for (int j = 0; j < kSlots; ++j)
         for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
     const int b0 = lv.pstart[cell], b1 = lv.pstart[cell + 1];
     for (int base = b0; base < b1; base += 64) {
@@ -461,7 +464,7 @@ __global__ __launch_bounds__(256) void k_fmm_p2m(const T* __restrict__ xs, const
             gg[q][d] = double(gs[d * n + base + q]);
         }
         __syncthreads();
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kSlots; ++j) {
             const int t = threadIdx.x + 256 * j;
             if (t >= nt) break;
             const uint32_t k = terms[t];
@@ -472,7 +475,7 @@ __global__ __launch_bounds__(256) void k_fmm_p2m(const T* __restrict__ xs, const
             }
         }
     }
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kSlots; ++j) {
         const int t = threadIdx.x + 256 * j;
         if (t >= nt) break;
         for (int d = 0; d < 3; ++d) lv.M[(int64_t(cell) * 3 + d) * nt + t] = acc[j][d];
@@ -530,8 +533,8 @@ __global__ __launch_bounds__(256) void k_fmm_m2m(FmmLevel par, FmmLevel chi, con
     const int c0 = par.first[cell], c1 = par.first[cell + 1];
     int ip[3];
     cell_coords(par.code[cell], ip);
-    double acc[4][3];
-    for (int j = 0; j < 4; ++j)
+    double acc[kSlots][3];
+    for (int j = 0; j < kSlots; ++j)
         for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
     for (int q = c0; q < c1; ++q) {
         __syncthreads();
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(256) void k_fmm_m2m(FmmLevel par, FmmLevel chi, con
         __syncthreads();
         shift_axis<false>(bufB, bufA, pw[1], 1, p, nt, terms);
         __syncthreads();
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kSlots; ++j) {
             const int t = threadIdx.x + 256 * j;
             if (t >= nt) break;
             double o[3];
@@ -562,7 +565,7 @@ __global__ __launch_bounds__(256) void k_fmm_m2m(FmmLevel par, FmmLevel chi, con
             for (int d = 0; d < 3; ++d) acc[j][d] += o[d];
         }
     }
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kSlots; ++j) {
         const int t = threadIdx.x + 256 * j;
         if (t >= nt) break;
         for (int d = 0; d < 3; ++d) par.M[(int64_t(cell) * 3 + d) * nt + t] = acc[j][d];
@@ -641,10 +644,10 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
     const CUint gidx = (CUint)(terms + kMaxTerms);
     const int zero_at = gsize - 1;  // the staging never writes there
     if (gt == 0) sDg[zero_at] = 0.0;
-    int nb[4], cnt[4], smax[4], deg[4];
-    double acc[4][3];
+    int nb[kSlots], cnt[kSlots], smax[kSlots], deg[kSlots];
+    double acc[kSlots][3];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kSlots; ++j) {
         const int t = gt + 256 * j;
         nb[j] = 0;
         cnt[j] = 0;
@@ -677,7 +680,7 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
         const int src = __builtin_amdgcn_readfirstlane(list_src[e]);
         const CDouble M0 = (CDouble)(lv.M + int64_t(src) * 3 * nt);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kSlots; ++j) {
             // 8 steps per batch of scalar loads (reads up to 7 entries past the prefix, inside
             // the workspace; they are not used)
             for (int s0 = 0; s0 < smax[j]; s0 += 8) {
@@ -706,7 +709,7 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
     }
     // add the groups' sums in group order through LDS (3 nt doubles per group)
     __syncthreads();
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kSlots; ++j) {
         const int t = gt + 256 * j;
         if (t >= nt) break;
         for (int d = 0; d < 3; ++d) sDyn[(grp * 3 + d) * nt + t] = acc[j][d];
@@ -828,9 +831,9 @@ __global__ __launch_bounds__(256) void k_fmm_l2p(NearArgs a, double* __restrict_
     const int leaf = a.item_leaf[item];
     const int q = a.item_t0[item] + int(threadIdx.x);
     const int nt = nterms(a.p);
-    __shared__ double sL[3][kMaxTerms];
+    extern __shared__ double sLx[];  // the leaf's expansion, [3][nt] (dynamic: 3 nt doubles)
     for (int t = threadIdx.x; t < nt; t += 256)
-        for (int d = 0; d < 3; ++d) sL[d][t] = a.leaf.L[(int64_t(leaf) * 3 + d) * nt + t];
+        for (int d = 0; d < 3; ++d) sLx[d * nt + t] = a.leaf.L[(int64_t(leaf) * 3 + d) * nt + t];
     __syncthreads();
     if (q >= a.leaf.pstart[leaf + 1]) return;
     int ic[3];
@@ -851,15 +854,15 @@ __global__ __launch_bounds__(256) void k_fmm_l2p(NearArgs a, double* __restrict_
             for (int n2 = 0; n2 <= p - 1 - n0 - n1; ++n2) {
                 const int i0 = mpos(n0 + 1, n1, n2), i1 = mpos(n0, n1 + 1, n2), i2 = mpos(n0, n1, n2 + 1);
                 for (int c = 0; c < 3; ++c) {
-                    gp[0][c] += sL[c][i0] * mono;
-                    gp[1][c] += sL[c][i1] * mono;
-                    gp[2][c] += sL[c][i2] * mono;
+                    gp[0][c] += sLx[c * nt + i0] * mono;
+                    gp[1][c] += sLx[c * nt + i1] * mono;
+                    gp[2][c] += sLx[c * nt + i2] * mono;
                 }
                 if (n0 + n1 + n2 <= p - 2) {
                     const int h[6] = {mpos(n0 + 2, n1, n2), mpos(n0, n1 + 2, n2), mpos(n0, n1, n2 + 2),
                                       mpos(n0 + 1, n1 + 1, n2), mpos(n0 + 1, n1, n2 + 1), mpos(n0, n1 + 1, n2 + 1)};
                     for (int m = 0; m < 6; ++m)
-                        for (int c = 0; c < 3; ++c) hp[m][c] += sL[c][h[m]] * mono;
+                        for (int c = 0; c < 3; ++c) hp[m][c] += sLx[c * nt + h[m]] * mono;
                 }
                 mono = mono * av[2] * kInvInt[n2 + 1];
             }
@@ -1332,10 +1335,11 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     const unsigned grid = unsigned((n + kNearTile - 1) / kNearTile + y.cap[level]);
     if (level >= 2) {
         double* far = reinterpret_cast<double*>(ws + y.far);
+        const size_t l2p_lds = size_t(3 * nterms(p)) * sizeof(double);
         if (classical)
-            hipLaunchKernelGGL((k_fmm_l2p<T, true>), dim3(grid), dim3(256), 0, st, na, far);
+            hipLaunchKernelGGL((k_fmm_l2p<T, true>), dim3(grid), dim3(256), l2p_lds, st, na, far);
         else
-            hipLaunchKernelGGL((k_fmm_l2p<T, false>), dim3(grid), dim3(256), 0, st, na, far);
+            hipLaunchKernelGGL((k_fmm_l2p<T, false>), dim3(grid), dim3(256), l2p_lds, st, na, far);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         na.far = far;
     }

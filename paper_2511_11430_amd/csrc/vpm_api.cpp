@@ -856,7 +856,7 @@ vpm_status vpm_segments_backward(int32_t dtype, int64_t n_seg, const void* a, co
 }
 
 size_t vpm_fmm_workspace_size(int32_t dtype, int64_t n, int32_t level, int32_t order) {
-    if (!dtype_ok(dtype) || n < 0 || n > INT32_MAX / 2 || level < 0 || level > 10 || order < 1 || order > 16)
+    if (!dtype_ok(dtype) || n < 0 || n > INT32_MAX / 2 || level < 0 || level > 10 || order < 1 || order > 20)
         return 0;
     return vpm::fmm_workspace(n, level, order, dtype);
 }
@@ -866,7 +866,7 @@ vpm_status vpm_fmm_eval(int32_t dtype, int64_t n, const void* x, const void* gam
                         int64_t ld_out, void* workspace, size_t ws_bytes, void* stream) {
     if (!dtype_ok(dtype)) return VPM_ERR_DTYPE;
     if (n < 0 || n > INT32_MAX / 2 || ld < n || ld_out < n) return VPM_ERR_SIZE;
-    if (level < 0 || level > 10 || order < 1 || order > 16) return VPM_ERR_ENUM;
+    if (level < 0 || level > 10 || order < 1 || order > 20) return VPM_ERR_ENUM;
     if (scheme != VPM_STRETCH_TRANSPOSED && scheme != VPM_STRETCH_CLASSICAL) return VPM_ERR_ENUM;
     if (n > 0 && (!x || !gamma || !sigma || !u_out || !dgamma_out)) return VPM_ERR_NULL;
     const size_t es = elem_size(dtype);
