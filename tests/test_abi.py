@@ -419,7 +419,8 @@ def test_fmm_validation():
     lib = _lib.load()
     f = lib.vpm_fmm_eval
     ws = lib.vpm_fmm_workspace_size
-    assert ws(F32C, 1000, 4, 8) > 0 and ws(F32C, 1000, 11, 8) == 0 and ws(F32C, 1000, 4, 17) == 0
+    assert ws(F32C, 1000, 4, 8) > 0 and ws(F32C, 1000, 11, 8) == 0 and ws(F32C, 1000, 4, 21) == 0
+    assert ws(F32C, 1000, 4, 20) > ws(F32C, 1000, 4, 16) > 0
     assert ws(7, 1000, 4, 8) == 0 and ws(F64, 1000, 4, 8) > ws(F32C, 1000, 4, 8)
 
     def args(**k):
@@ -430,6 +431,7 @@ def test_fmm_validation():
     assert f(*args(ld=99)) == SIZE
     assert f(*args(lev=11)) == ENUM
     assert f(*args(ord=0)) == ENUM
+    assert f(*args(ord=21)) == ENUM
     assert f(*args(sch=3)) == ENUM
     assert f(*args(u=None)) == NULL
     assert f(*args(u=P(0))) == ALIAS
