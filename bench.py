@@ -84,11 +84,13 @@ def load_counters(variant):
     return out
 
 
-def fma_chain_tflops(vpm, torch, stream, form):
-    """FP32 rate of independent FMA chains (the library's calibration kernel) on this GPU with
-    packed FP32 instructions disabled.  form 0: the accumulating form with register operands,
-    the VALU FMA rate that the pair kernel's arithmetic competes with; form 1: one operand in a
-    scalar register, a slower issue form; form 2: three register operands (VOP3 encoding)."""
+def fma_chain_run(vpm, torch, stream, form):
+    """Best of five timings (ms) and FP32 rate (TFLOP/s) of the library's calibration kernel on
+    this GPU, packed FP32 instructions disabled.  form 0: independent FMA chains in the
+    accumulating form with register operands, the VALU FMA rate that the pair kernel's
+    arithmetic competes with; 1: one operand in a scalar register; 2: three register operands
+    (VOP3 encoding); 3: FP32 matrix FMAs (16x16x4); 4: forms 0 and 3 interleaved (the same
+    work as 0 and 3 together)."""
     import ctypes
     lanes, fmas = 1 << 22, 2048
     out = torch.empty(lanes, dtype=torch.float32, device="cuda")
@@ -107,7 +109,7 @@ def fma_chain_tflops(vpm, torch, stream, form):
         torch.cuda.synchronize()
         ms = a.elapsed_time(b)
         best = ms if best is None else min(best, ms)
-    return 2.0 * 64 * n.value / (best * 1e-3) / 1e12
+    return best, 2.0 * 64 * n.value / (best * 1e-3) / 1e12
 
 
 def main():
@@ -220,11 +222,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     nonfinite = int(diag[12].item())
-    fma_tf = fma_chain_tflops(vpm, torch, stream, 0)
-    fma_tf_s = fma_chain_tflops(vpm, torch, stream, 1)
-    fma_tf_3 = fma_chain_tflops(vpm, torch, stream, 2)
+    t_acc, fma_tf = fma_chain_run(vpm, torch, stream, 0)
+    _, fma_tf_s = fma_chain_run(vpm, torch, stream, 1)
+    _, fma_tf_3 = fma_chain_run(vpm, torch, stream, 2)
+    t_mfma, mfma_tf = fma_chain_run(vpm, torch, stream, 3)
+    t_both, _ = fma_chain_run(vpm, torch, stream, 4)
     log(f"FMA chains: {fma_tf:.1f} TFLOP/s (accumulating, register operands), {fma_tf_3:.1f} (three register "
-        f"operands), {fma_tf_s:.1f} (scalar operand); pair kernel {achieved:.1f} TFLOP/s algorithmic")
+        f"operands), {fma_tf_s:.1f} (scalar operand), {mfma_tf:.1f} (FP32 MFMA); MFMA and VALU interleaved "
+        f"{t_both:.3f} ms vs {t_acc:.3f} + {t_mfma:.3f} ms apart; pair kernel {achieved:.1f} TFLOP/s algorithmic")
 
     result = {
         "metric": "Gpair-interactions/s FP32-comp vs FP64 GPU at 1e-5 relL2; adjoint/fwd time",
@@ -241,7 +246,10 @@ def main():
                      "flop_per_pair": FLOP_PER_PAIR_VS, "counters": load_counters(plan),
                      "fma_chain_tflops": {"accumulating_register_operands": round(fma_tf, 2),
                                           "three_register_operands": round(fma_tf_3, 2),
-                                          "scalar_operand": round(fma_tf_s, 2)},
+                                          "scalar_operand": round(fma_tf_s, 2),
+                                          "fp32_mfma_16x16x4": round(mfma_tf, 2),
+                                          "mfma_and_valu_interleaved_ms": round(t_both, 3),
+                                          "mfma_and_valu_apart_ms": [round(t_acc, 3), round(t_mfma, 3)]},
                      "frac_of_fma_chain": round(achieved / fma_tf, 4)},
         "nonfinite": nonfinite,
         "env": {"gpu": torch.cuda.get_device_name(0),

@@ -530,9 +530,11 @@ int32_t vpm_get_plan(int32_t dtype, int32_t batched, int64_t n);
  * form 0: the accumulating form with per-lane register operands (a = b * d + a, v_fmac_f32),
  * which the particle kernels' sums use; form 1: one operand a kernel argument held in a
  * scalar register (a = a * s + t), a slower issue form on this GPU; form 2: the three-operand
- * encoding with register operands (a = a * b + d, v_fma_f32).  fma_instructions (host,
- * may be NULL) receives the number of FP32 FMA instructions the launch issues,
- * ceil(n_lanes / 64) x 8 x fmas_per_chain wavefront instructions, against which counter
+ * encoding with register operands (a = a * b + d, v_fma_f32); form 3: fmas_per_chain FP32
+ * matrix steps (v_mfma_f32_16x16x4f32, four independent accumulators) per wavefront instead;
+ * form 4: forms 0 and 3 interleaved.  fma_instructions (host, may be NULL) receives the number
+ * of FP32 FMA instructions the launch issues (a 16x16x4 matrix step counts as 16),
+ * ceil(n_lanes / 64) x (8, 16 or 24) x fmas_per_chain wavefront instructions, against which counter
  * readings (e.g. rocprofv3's SQ_INSTS_VALU_FMA_F32) are scaled, and from which the achieved
  * FMA rate follows with a timing of the launch.  Errors: VPM_ERR_SIZE, VPM_ERR_ENUM (form),
  * VPM_ERR_NULL, VPM_ERR_HIP. */

@@ -11,8 +11,13 @@
 //    (v_fmac_f32 with VGPR operands) that the pair kernels' sums use;
 //  - form 1: a = a * s + t with s, t kernel arguments, one of them read from a scalar
 //    register (v_fma_f32 with an SGPR operand);
-//  - form 2: a = a * b + d, the three-operand VOP3 encoding (v_fma_f32) with register operands.
-// On gfx950 form 1 issues at about half the rate of form 0, form 2 in between.
+//  - form 2: a = a * b + d, the three-operand VOP3 encoding (v_fma_f32) with register operands;
+//  - form 3: FP32 matrix FMAs instead, four independent v_mfma_f32_16x16x4f32 chains per
+//    wavefront (one 16x16x4 step is 1024 FMAs, 16 wavefront FMA instructions' worth);
+//  - form 4: forms 0 and 3 interleaved in every wavefront (independent registers), to see
+//    whether the matrix cores and the VALU run concurrently.
+// On gfx950 form 1 issues at about half the rate of form 0, form 2 in between, and form 4
+// takes as long as forms 0 and 3 one after the other.
 #include <hip/hip_runtime.h>
 
 #include "vpm_internal.h"
@@ -22,6 +27,8 @@ namespace vpm {
 namespace {
 
 constexpr int kChains = 8;
+
+typedef float MfmaAcc __attribute__((ext_vector_type(4)));
 
 template <int FORM>
 __global__ __launch_bounds__(256) void k_fma_chain(int64_t n, int fmas, float s, float t, float* out) {
@@ -46,6 +53,37 @@ __global__ __launch_bounds__(256) void k_fma_chain(int64_t n, int fmas, float s,
     if (i < n) out[i] = acc;
 }
 
+// Forms 3 and 4: per step of four, four 16x16x4 matrix FMAs on independent accumulators
+// (fmas steps in all per wavefront), and for form 4 also the 32 FMAs of form 0's step.
+template <bool VALU_TOO>
+__global__ __launch_bounds__(256) void k_mfma_chain(int64_t n, int fmas, float s, float t, float* out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const float b = __int_as_float(__float_as_int(s) + int(threadIdx.x & 7));
+    const float d = t * float(1 + (threadIdx.x & 3));
+    MfmaAcc c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = MfmaAcc{0.0f, 0.0f, 0.0f, 0.0f};
+    float a[kChains];
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) a[k] = float(int(threadIdx.x) + k);
+    for (int r = 0; r < fmas; r += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(b, d, c[u], 0, 0, 0);
+            if (VALU_TOO) {
+#pragma unroll
+                for (int k = 0; k < kChains; ++k) a[k] = fmaf(b, d, a[k]);
+            }
+        }
+    }
+    float acc = c[0][0] + c[1][1] + c[2][2] + c[3][3];
+    if (VALU_TOO) {
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) acc += a[k];
+    }
+    if (i < n) out[i] = acc;
+}
+
 }  // namespace
 
 int fma_chain_count() { return kChains; }
@@ -56,8 +94,12 @@ hipError_t launch_fma_chain(int64_t n, int fmas, int form, float* out, hipStream
         hipLaunchKernelGGL(k_fma_chain<0>, dim3(nb), dim3(256), 0, st, n, fmas, 0.999f, 1e-3f, out);
     else if (form == 1)
         hipLaunchKernelGGL(k_fma_chain<1>, dim3(nb), dim3(256), 0, st, n, fmas, 0.999f, 1e-3f, out);
-    else
+    else if (form == 2)
         hipLaunchKernelGGL(k_fma_chain<2>, dim3(nb), dim3(256), 0, st, n, fmas, 0.999f, 1e-3f, out);
+    else if (form == 3)
+        hipLaunchKernelGGL(k_mfma_chain<false>, dim3(nb), dim3(256), 0, st, n, fmas, 0.999f, 1e-3f, out);
+    else
+        hipLaunchKernelGGL(k_mfma_chain<true>, dim3(nb), dim3(256), 0, st, n, fmas, 0.999f, 1e-3f, out);
     return hipGetLastError();
 }
 

@@ -1207,10 +1207,12 @@ vpm_status vpm_autotune(int32_t dtype, int32_t n_batch, const int64_t* src_off, 
 vpm_status vpm_fma_chain(int64_t n_lanes, int32_t fmas_per_chain, int32_t form, float* out,
                          int64_t* fma_instructions, void* stream) {
     if (n_lanes < 1 || n_lanes > INT32_MAX || fmas_per_chain < 4 || fmas_per_chain % 4 != 0) return VPM_ERR_SIZE;
-    if (form < 0 || form > 2) return VPM_ERR_ENUM;
+    if (form < 0 || form > 4) return VPM_ERR_ENUM;
     if (!out) return VPM_ERR_NULL;
     const int64_t waves = (n_lanes + 63) / 64;
-    if (fma_instructions) *fma_instructions = waves * int64_t(vpm::fma_chain_count()) * fmas_per_chain;
+    // wavefront FP32 FMA instructions, a 16x16x4 matrix step counting as 16 of them
+    const int64_t per_step = form < 3 ? vpm::fma_chain_count() : (form == 3 ? 16 : 16 + vpm::fma_chain_count());
+    if (fma_instructions) *fma_instructions = waves * per_step * fmas_per_chain;
     return hip_status(vpm::launch_fma_chain(n_lanes, fmas_per_chain, form, out, static_cast<hipStream_t>(stream)));
 }
 

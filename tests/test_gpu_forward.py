@@ -353,7 +353,7 @@ def test_autotune_times_every_shape_and_sets_the_plan(gpu):
         tune.apply_cache()
 
 
-@pytest.mark.parametrize("form", [0, 1, 2])
+@pytest.mark.parametrize("form", [0, 1, 2, 3, 4])
 def test_fma_chain_calibration_kernel(form, gpu):
     """The calibration kernel reports the FMA instruction count it issues and computes the
     chains it claims: each lane's result is the sum of its 8 chains, checked on the host (FP64
@@ -366,8 +366,11 @@ def test_fma_chain_calibration_kernel(form, gpu):
     lib = vpm._lib.load()
     assert lib.vpm_fma_chain(lanes, fmas, form, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), None) == 0
     torch.cuda.synchronize()
-    assert n.value == (lanes // 64) * 8 * fmas
-    assert lib.vpm_fma_chain(lanes, fmas, 3, ctypes.c_void_p(out.data_ptr()), None, None) == vpm.ENUM_ERROR
+    assert n.value == (lanes // 64) * (8, 8, 8, 16, 24)[form] * fmas
+    assert lib.vpm_fma_chain(lanes, fmas, 5, ctypes.c_void_p(out.data_ptr()), None, None) == vpm.ENUM_ERROR
+    if form >= 3:  # matrix forms: the count above and a finite result
+        assert np.all(np.isfinite(host(out)))
+        return
     s, t = np.float32(0.999), np.float32(1e-3)
     f32 = np.float32
     got = host(out)
