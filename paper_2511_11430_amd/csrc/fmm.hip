@@ -581,23 +581,27 @@ typedef __attribute__((address_space(4))) const uint32_t* CUint;
 // unit-spacing table D of the offset and the cell width w,
 //   L_n = w^(-1-|n|)/(4 pi) sum_k D_{n+k} (-1/w)^|k| M_k = (-1)^|n|/(4 pi w) sum_k D'_{n+k} M_k,
 //   D'_m = (-1/w)^|m| D_m.
-// The workgroup is G groups of 256 lanes; group g takes interactions g, g + G, ...  Each
-// interaction's D' is staged in the group's LDS grid of (p + 1)^3 entries (plus one zero),
-// where the index of n + k is the sum of the indices of n and k.  Lanes own terms n
-// (t = lane + 256 j); the terms k with |k| <= p - |n| are a prefix of the degree order, so the
-// lanes of a wavefront walk the same k, whose M_k and grid index are uniform (scalar loads), and
-// a lane past its prefix reads the zero.  Per lane and k: one LDS read and three FMAs.  The
-// groups' sums are added in group order at the end (deterministic).
+// The workgroup is G groups of glanes lanes (a multiple of 64); group g takes interactions
+// g, g + G, ...  Each interaction's D' is staged in the group's LDS grid of (p + 1)^3 entries
+// (plus one zero), where the index of n + k is the sum of the indices of n and k.  Lanes own
+// terms n (t = lane + glanes j, j < SLOTS); the terms k with |k| <= p - |n| are a prefix of the
+// degree order, so the lanes of a wavefront walk the same k, whose M_k and grid index are
+// uniform (scalar loads), and a lane past its prefix reads the zero.  Per lane and k: one LDS
+// read and three FMAs.  The groups' sums are added in group order at the end (deterministic).
+// Low orders take several 256-lane groups (interactions in parallel); high orders, whose grids
+// fill the LDS, one group of up to 1024 lanes (terms in parallel).
+template <int SLOTS>
 __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __restrict__ count, int l,
                                                   const double* __restrict__ box, int p,
-                                                  const uint32_t* __restrict__ terms, const double* __restrict__ dtab) {
+                                                  const uint32_t* __restrict__ terms, const double* __restrict__ dtab,
+                                                  int glanes) {
     const int cell = blockIdx.x;
     const int ncell = *count;
     if (cell >= ncell) return;
     const int nt = nterms(p);
-    const int ngroup = int(blockDim.x) >> 8;
-    // the group is uniform over each wavefront (256-lane groups)
-    const int grp = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 8), gt = int(threadIdx.x) & 255;
+    const int ngroup = int(blockDim.x) / glanes;
+    // the group is uniform over each wavefront (groups of whole wavefronts)
+    const int grp = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / glanes), gt = int(threadIdx.x) % glanes;
     const int gsize = (p + 1) * (p + 1) * (p + 1) + 1;  // grid + the zero
     const int gstride = gsize > 3 * nt ? gsize : 3 * nt;
     extern __shared__ double sDyn[];                    // ngroup grids; reused for the final sum
@@ -644,11 +648,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
     const CUint gidx = (CUint)(terms + kMaxTerms);
     const int zero_at = gsize - 1;  // the staging never writes there
     if (gt == 0) sDg[zero_at] = 0.0;
-    int nb[kSlots], cnt[kSlots], smax[kSlots], deg[kSlots];
-    double acc[kSlots][3];
+    int nb[SLOTS], cnt[SLOTS], smax[SLOTS], deg[SLOTS];
+    double acc[SLOTS][3];
 #pragma unroll
-    for (int j = 0; j < kSlots; ++j) {
-        const int t = gt + 256 * j;
+    for (int j = 0; j < SLOTS; ++j) {
+        const int t = gt + glanes * j;
         nb[j] = 0;
         cnt[j] = 0;
         deg[j] = 0;
@@ -670,7 +674,7 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
         __syncthreads();
         if (has) {
             const double* D = dtab + int64_t(list_off[e]) * nt;
-            for (int t = gt; t < nt; t += 256) {
+            for (int t = gt; t < nt; t += glanes) {
                 const uint32_t k = terms[t];
                 sDg[terms[kMaxTerms + t]] = D[t] * sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
             }
@@ -680,7 +684,7 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
         const int src = __builtin_amdgcn_readfirstlane(list_src[e]);
         const CDouble M0 = (CDouble)(lv.M + int64_t(src) * 3 * nt);
 #pragma unroll
-        for (int j = 0; j < kSlots; ++j) {
+        for (int j = 0; j < SLOTS; ++j) {
             // 8 steps per batch of scalar loads (reads up to 7 entries past the prefix, inside
             // the workspace; they are not used)
             for (int s0 = 0; s0 < smax[j]; s0 += 8) {
@@ -709,8 +713,8 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
     }
     // add the groups' sums in group order through LDS (3 nt doubles per group)
     __syncthreads();
-    for (int j = 0; j < kSlots; ++j) {
-        const int t = gt + 256 * j;
+    for (int j = 0; j < SLOTS; ++j) {
+        const int t = gt + glanes * j;
         if (t >= nt) break;
         for (int d = 0; d < 3; ++d) sDyn[(grp * 3 + d) * nt + t] = acc[j][d];
     }
@@ -1280,12 +1284,23 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     }
     hipLaunchKernelGGL(k_fmm_terms, dim3(1), dim3(64), 0, st, p, terms);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // M2L: as many groups of 256 lanes as 60 KiB of LDS allow (at least one, at most 4); each
-    // group holds its grid, or its 3 nt sums at the end if those are larger
+    // M2L: as many groups of 256 lanes as 60 KiB of LDS allow (at most 4), each holding its grid
+    // (or its 3 nt sums at the end if those are larger); where fewer than two fit, one group of
+    // as many wavefronts as the terms fill (up to 1024 lanes, at most two terms per lane)
     const size_t m2l_cells = size_t(p + 1) * (p + 1) * (p + 1) + 1;
     const size_t m2l_grid = (m2l_cells > size_t(3 * nterms(p)) ? m2l_cells : size_t(3 * nterms(p))) * sizeof(double);
     int m2l_groups = int((60 * 1024) / m2l_grid);
-    m2l_groups = m2l_groups < 1 ? 1 : (m2l_groups > 4 ? 4 : m2l_groups);
+    m2l_groups = m2l_groups > 4 ? 4 : m2l_groups;
+    int m2l_gsize = 256;
+    if (m2l_groups < 2) {
+        m2l_groups = 1;
+        const int half = (nterms(p) + 1) / 2;  // two terms per lane
+        m2l_gsize = ((half + 63) / 64) * 64;
+        m2l_gsize = m2l_gsize < 256 ? 256 : (m2l_gsize > 1024 ? 1024 : m2l_gsize);
+    }
+    // every term has a lane: 5 per lane in 256-lane groups (two or more groups fit only while
+    // 3 nt doubles take at most 30 KiB, nt <= 1280), 2 per lane in the single group
+    if (nterms(p) > (m2l_gsize == 256 ? 5 : 2) * m2l_gsize) return hipErrorInvalidValue;
     const size_t m2l_lds = size_t(m2l_groups) * m2l_grid;
     const size_t shift_lds = size_t(6 * nterms(p)) * sizeof(double);  // M2M and L2L: two 3 nt buffers
     if (level >= 2) {
@@ -1300,8 +1315,12 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         for (int l = 2; l <= level; ++l) {
-            hipLaunchKernelGGL(k_fmm_m2l, dim3(unsigned(y.cap[l])), dim3(256 * m2l_groups), m2l_lds, st, lv[l],
-                               counts + l, l, box, p, terms, dtab);
+            if (m2l_gsize == 256)
+                hipLaunchKernelGGL(k_fmm_m2l<5>, dim3(unsigned(y.cap[l])), dim3(256 * m2l_groups), m2l_lds, st, lv[l],
+                               counts + l, l, box, p, terms, dtab, m2l_gsize);
+            else
+                hipLaunchKernelGGL(k_fmm_m2l<2>, dim3(unsigned(y.cap[l])), dim3(m2l_gsize), m2l_lds, st, lv[l],
+                               counts + l, l, box, p, terms, dtab, m2l_gsize);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if (l >= 3) {
                 hipLaunchKernelGGL(k_fmm_l2l, dim3(unsigned(y.cap[l])), dim3(256), shift_lds, st, lv[l], lv[l - 1],
