@@ -85,8 +85,9 @@ def test_fmm_edge_cases(kind, gpu):
 
 def test_fmm_full_size_against_direct(gpu):
     """The 1,048,576-particle forward-flight wake at depth 6 (leaf width 6.5 sigma_max) and
-    order 12: the FP32C FMM against the FP64 oracle's direct sums at 512 sampled particles,
-    and against the GPU's direct FP32C sums on every particle."""
+    orders 12 and 18: the FP32C FMM against the FP64 oracle's direct sums at 512 sampled
+    particles, and against the GPU's direct FP32C sums on every particle; order 18 within 1e-5
+    for both outputs."""
     import torch
     c = W.config3()
     x, g, s = prepare([c["x"], c["gamma"], c["sigma"]], "f32c")
@@ -113,6 +114,16 @@ def test_fmm_full_size_against_direct(gpu):
     e8 = max(rel_l2(host(u8), host(ud)), rel_l2(host(d8), host(dd)))
     say(f"  order 8: {e8:.2e}")
     assert e8 > 3 * max(eu, ed)
+    del ws
+    # order 18 is the setting within the direct path's 1e-5 for both outputs (measured 1.6e-6
+    # and 8.6e-6 against the direct FP32C sums), here also against the oracle's sample
+    ws18 = torch.empty(vpm.vpm_fmm_workspace_size(X.shape[1], 6, 18, torch.float32), dtype=torch.uint8,
+                       device="cuda")
+    u18, d18 = vpm.vpm_fmm_eval(X, G, S, 6, 18, workspace=ws18)
+    e18u, e18d = rel_l2(host(u18), host(ud)), rel_l2(host(d18), host(dd))
+    s18u, s18d = rel_l2(host(u18)[:, idx], uo), rel_l2(host(d18)[:, idx], do)
+    say(f"  order 18: vs direct GPU u {e18u:.2e} dgamma {e18d:.2e}; vs oracle (512) u {s18u:.2e} dgamma {s18d:.2e}")
+    assert max(e18u, e18d, s18u, s18d) <= 1e-5
 
 
 @pytest.mark.parametrize("kind", KINDS)
