@@ -58,7 +58,9 @@ def off(*v):
 
 def opts(**kw):
     o = _lib.VpmOptions()
+    fields = {f[0] for f in _lib.VpmOptions._fields_}
     for k, v in kw.items():
+        assert k in fields, k  # a misspelt field would be set silently on the ctypes struct
         setattr(o, k, v)
     return o
 
@@ -452,3 +454,33 @@ def test_tuning_cache_matches_the_kernel_sources():
         cache = json.load(f)
     assert cache["source_hash"] == tune.source_hash()
     assert {p["batched"] for p in cache["plans"]} == {0, 1}
+
+
+def test_fma_chain_validation():
+    lib = _lib.load()
+    f = lib.vpm_fma_chain
+    n = ctypes.c_int64(-1)
+    assert f(0, 8, 0, P(0), ctypes.byref(n), None) == SIZE
+    assert f(64, 6, 0, P(0), ctypes.byref(n), None) == SIZE   # not a multiple of 4
+    assert f(64, 8, 5, P(0), ctypes.byref(n), None) == ENUM
+    assert f(64, 8, -1, P(0), ctypes.byref(n), None) == ENUM
+    assert f(64, 8, 0, None, ctypes.byref(n), None) == NULL
+    assert n.value == -1  # nothing counted by a rejected call
+
+
+def test_noalloc_validation():
+    lib = _lib.load()
+    f = lib.vpm_eval_velocity_stretching_noalloc
+    assert lib.vpm_noalloc_scratch_bytes() == 32 << 20
+
+    def call(dtype=F32C, nb=1, so=None, xs=P(0), u=P(6), dg=P(7), o=None):
+        so = off(0, 100) if so is None else so
+        o = opts(self_=1) if o is None else o
+        return f(dtype, nb, so, None, xs, P(1), P(2), 100, None, None, None, 0, None, u, dg, 100, ctypes.byref(o), None)
+
+    assert call(dtype=7) == DTYPE
+    assert call(nb=0) == SIZE
+    assert call(nb=2, so=off(0, 50, 100)) == UNSUPPORTED  # one set per call
+    assert call(xs=None) == NULL
+    assert call(u=P(0)) == ALIAS
+    assert call(o=opts(self_=1, gradient=1)) == ENUM  # the gradient has its own entry point
