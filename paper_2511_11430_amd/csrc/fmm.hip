@@ -52,6 +52,8 @@ constexpr int kMaxTerms = (kMaxOrder + 1) * (kMaxOrder + 2) * (kMaxOrder + 3) / 
 // terms per lane in the kernels whose 256 lanes own the terms t = lane + 256 j
 constexpr int kSlots = (kMaxTerms + 255) / 256;  // 7
 constexpr int kMaxLevel = 10;
+// how far the M2L's batches of eight scalar loads can read past a cell's last moment
+constexpr int kM2lOverrun = 8;
 constexpr int kNearTile = 256;
 constexpr int kOffsets = 343;  // [-3, 3]^3
 constexpr double kInv4Pi = 0.0795774715459476678844418816862571810;
@@ -480,6 +482,9 @@ __global__ __launch_bounds__(256) void k_fmm_p2m(const T* __restrict__ xs, const
         if (t >= nt) break;
         for (int d = 0; d < 3; ++d) lv.M[(int64_t(cell) * 3 + d) * nt + t] = acc[j][d];
     }
+    // the M2L's batched reads run up to kM2lOverrun terms past a cell's last moment: after the
+    // level's last cell they find zeros, not memory that no cell writes
+    if (cell == *count - 1 && int(threadIdx.x) < kM2lOverrun) lv.M[int64_t(cell + 1) * 3 * nt + threadIdx.x] = 0.0;
 }
 
 // One axis of a separable Taylor shift of 3 x nt coefficients (mpos order, [3][nt]) held in
@@ -570,6 +575,8 @@ __global__ __launch_bounds__(256) void k_fmm_m2m(FmmLevel par, FmmLevel chi, con
         if (t >= nt) break;
         for (int d = 0; d < 3; ++d) par.M[(int64_t(cell) * 3 + d) * nt + t] = acc[j][d];
     }
+    // zeros after the level's last cell for the M2L's batched reads (as in k_fmm_p2m)
+    if (cell == *count - 1 && int(threadIdx.x) < kM2lOverrun) par.M[int64_t(cell + 1) * 3 * nt + threadIdx.x] = 0.0;
 }
 
 // ---------------------------------------------------------------- M2L and L2L
@@ -685,8 +692,10 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
         const CDouble M0 = (CDouble)(lv.M + int64_t(src) * 3 * nt);
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j) {
-            // 8 steps per batch of scalar loads (reads up to 7 entries past the prefix, inside
-            // the workspace; they are not used)
+            // 8 steps per batch of scalar loads, which may read up to 7 terms past a lane's
+            // prefix; those lanes multiply by the zero.  Past a cell's first two components the
+            // reads find the next component's moments, past the third the next cell's, or the
+            // zeros that the moments' writers leave after the level's last cell: always finite.
             for (int s0 = 0; s0 < smax[j]; s0 += 8) {
                 int ks[8];
                 double m[3][8];
@@ -1212,7 +1221,7 @@ Layout layout(int64_t n, int level, int order, size_t es) {
         y.first[l] = take(size_t(y.cap[l] + 1) * 4);
         y.pstart[l] = take(size_t(y.cap[l] + 1) * 4);
         y.parent[l] = take(size_t(y.cap[l]) * 4);
-        y.M[l] = take(size_t(y.cap[l]) * 3 * nt * sizeof(double));
+        y.M[l] = take((size_t(y.cap[l]) * 3 * nt + kM2lOverrun) * sizeof(double));
         y.L[l] = take(size_t(y.cap[l]) * 3 * nt * sizeof(double));
     }
     y.total = o;
