@@ -580,6 +580,16 @@ __global__ __launch_bounds__(256) void k_fmm_m2m(FmmLevel par, FmmLevel chi, con
 }
 
 // ---------------------------------------------------------------- M2L and L2L
+// LDS of one M2L group in doubles: the (p + 1)^3 grid and its zero; with MLDS also the source
+// cell's moments (3 nt, and kM2lOverrun zeros after them) and the grid index of every term (nt,
+// and kM2lOverrun more, as ints).  At least 3 nt for the group's sums at the end.
+__host__ __device__ inline int m2l_group_doubles(int p, bool mlds) {
+    const int nt = nterms(p);
+    int g = (p + 1) * (p + 1) * (p + 1) + 1;
+    if (mlds) g += 3 * nt + kM2lOverrun + (nt + kM2lOverrun + 1) / 2;
+    return g > 3 * nt ? g : 3 * nt;
+}
+
 typedef __attribute__((address_space(4))) const double* CDouble;
 typedef __attribute__((address_space(4))) const uint32_t* CUint;
 
@@ -596,8 +606,10 @@ typedef __attribute__((address_space(4))) const uint32_t* CUint;
 // uniform (scalar loads), and a lane past its prefix reads the zero.  Per lane and k: one LDS
 // read and three FMAs.  The groups' sums are added in group order at the end (deterministic).
 // Low orders take several 256-lane groups (interactions in parallel); high orders, whose grids
-// fill the LDS, one group of up to 1024 lanes (terms in parallel).
-template <int SLOTS>
+// fill the LDS, one group of up to 1024 lanes (terms in parallel), which (MLDS) also stages the
+// source cell's moments and the terms' grid indices in LDS, so that the walk over k reads
+// LDS (in order, pipelined) instead of waiting on a batch of scalar loads every eight steps.
+template <int SLOTS, bool MLDS>
 __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __restrict__ count, int l,
                                                   const double* __restrict__ box, int p,
                                                   const uint32_t* __restrict__ terms, const double* __restrict__ dtab,
@@ -610,9 +622,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
     // the group is uniform over each wavefront (groups of whole wavefronts)
     const int grp = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / glanes), gt = int(threadIdx.x) % glanes;
     const int gsize = (p + 1) * (p + 1) * (p + 1) + 1;  // grid + the zero
-    const int gstride = gsize > 3 * nt ? gsize : 3 * nt;
+    const int gstride = m2l_group_doubles(p, MLDS);
     extern __shared__ double sDyn[];                    // ngroup grids; reused for the final sum
     double* sDg = sDyn + grp * gstride;
+    double* sM = sDg + gsize;                                   // MLDS: [3][nt] + zeros
+    int32_t* sG = reinterpret_cast<int32_t*>(sM + 3 * nt + kM2lOverrun);  // MLDS: [nt] + zeros
     __shared__ int32_t cand[216];
     __shared__ int32_t list_src[216];
     __shared__ int32_t list_off[216];
@@ -655,6 +669,10 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
     const CUint gidx = (CUint)(terms + kMaxTerms);
     const int zero_at = gsize - 1;  // the staging never writes there
     if (gt == 0) sDg[zero_at] = 0.0;
+    if constexpr (MLDS) {
+        for (int t = gt; t < nt + kM2lOverrun; t += glanes) sG[t] = t < nt ? int(terms[kMaxTerms + t]) : 0;
+        if (gt < kM2lOverrun) sM[3 * nt + gt] = 0.0;
+    }
     int nb[SLOTS], cnt[SLOTS], smax[SLOTS], deg[SLOTS];
     double acc[SLOTS][3];
 #pragma unroll
@@ -685,6 +703,10 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
                 const uint32_t k = terms[t];
                 sDg[terms[kMaxTerms + t]] = D[t] * sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
             }
+            if constexpr (MLDS) {
+                const double* Ms = lv.M + int64_t(list_src[e]) * 3 * nt;
+                for (int t = gt; t < 3 * nt; t += glanes) sM[t] = Ms[t];
+            }
         }
         __syncthreads();
         if (!has) continue;
@@ -701,10 +723,17 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
                 double m[3][8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    ks[i] = int(gidx[s0 + i]);
-                    m[0][i] = M0[s0 + i];
-                    m[1][i] = M0[nt + s0 + i];
-                    m[2][i] = M0[2 * nt + s0 + i];
+                    if constexpr (MLDS) {  // the same reads from LDS (its zeros past the ends)
+                        ks[i] = sG[s0 + i];
+                        m[0][i] = sM[s0 + i];
+                        m[1][i] = sM[nt + s0 + i];
+                        m[2][i] = sM[2 * nt + s0 + i];
+                    } else {
+                        ks[i] = int(gidx[s0 + i]);
+                        m[0][i] = M0[s0 + i];
+                        m[1][i] = M0[nt + s0 + i];
+                        m[2][i] = M0[2 * nt + s0 + i];
+                    }
                 }
                 // lanes past their prefix read the zero after the grid (no branch, so that the
                 // eight reads are in flight together)
@@ -1296,8 +1325,7 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     // M2L: as many groups of 256 lanes as 60 KiB of LDS allow (at most 4), each holding its grid
     // (or its 3 nt sums at the end if those are larger); where fewer than two fit, one group of
     // as many wavefronts as the terms fill (up to 1024 lanes, at most two terms per lane)
-    const size_t m2l_cells = size_t(p + 1) * (p + 1) * (p + 1) + 1;
-    const size_t m2l_grid = (m2l_cells > size_t(3 * nterms(p)) ? m2l_cells : size_t(3 * nterms(p))) * sizeof(double);
+    const size_t m2l_grid = size_t(m2l_group_doubles(p, false)) * sizeof(double);
     int m2l_groups = int((60 * 1024) / m2l_grid);
     m2l_groups = m2l_groups > 4 ? 4 : m2l_groups;
     int m2l_gsize = 256;
@@ -1310,7 +1338,8 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     // every term has a lane: 5 per lane in 256-lane groups (two or more groups fit only while
     // 3 nt doubles take at most 30 KiB, nt <= 1280), 2 per lane in the single group
     if (nterms(p) > (m2l_gsize == 256 ? 5 : 2) * m2l_gsize) return hipErrorInvalidValue;
-    const size_t m2l_lds = size_t(m2l_groups) * m2l_grid;
+    const size_t m2l_lds = m2l_gsize == 256 ? size_t(m2l_groups) * m2l_grid
+                                            : size_t(m2l_group_doubles(p, true)) * sizeof(double);
     const size_t shift_lds = size_t(6 * nterms(p)) * sizeof(double);  // M2M and L2L: two 3 nt buffers
     if (level >= 2) {
         hipLaunchKernelGGL(k_fmm_dtab, dim3(kOffsets), dim3(256), 0, st, p, terms, dtab);
@@ -1325,10 +1354,10 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
         }
         for (int l = 2; l <= level; ++l) {
             if (m2l_gsize == 256)
-                hipLaunchKernelGGL(k_fmm_m2l<5>, dim3(unsigned(y.cap[l])), dim3(256 * m2l_groups), m2l_lds, st, lv[l],
+                hipLaunchKernelGGL((k_fmm_m2l<5, false>), dim3(unsigned(y.cap[l])), dim3(256 * m2l_groups), m2l_lds, st, lv[l],
                                counts + l, l, box, p, terms, dtab, m2l_gsize);
             else
-                hipLaunchKernelGGL(k_fmm_m2l<2>, dim3(unsigned(y.cap[l])), dim3(m2l_gsize), m2l_lds, st, lv[l],
+                hipLaunchKernelGGL((k_fmm_m2l<2, true>), dim3(unsigned(y.cap[l])), dim3(m2l_gsize), m2l_lds, st, lv[l],
                                counts + l, l, box, p, terms, dtab, m2l_gsize);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if (l >= 3) {
