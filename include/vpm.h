@@ -28,7 +28,8 @@
  *    ld >= the item count.  Scalars per item (sigma, segment circulation) are [n].
  *  - dtype VPM_F64: every float array is double and the sums run in FP64.
  *    dtype VPM_F32C: every float array is float; pair arithmetic is FP32 and each target's
- *    sums are carried as compensated (two-sum) FP32 pairs across source tiles.
+ *    sums are carried as compensated FP32 pairs (hi, lo) across source chunks (TwoSum, or
+ *    FastTwoSum with the error carried forward in the particle forward kernel).
  *  - Units are SI: x in m, Gamma in m^3/s, sigma in m, segment circulation in m^2/s.
  *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*; NULL = the null
  *    stream).  Results are valid once the stream is synchronised.  Calls that overlap in

@@ -5,16 +5,24 @@
 //  - Each workgroup owns WG*K consecutive targets of one particle set; lane l holds targets
 //    l, l+WG, ..., l+(K-1)WG (coalesced loads and stores for every k).
 //  - Sources stream through LDS in tiles of WG particles.  Each lane stages one source and
-//    precomputes what every pair needs (x, Gamma, 1/sigma and the far-field cut), so the
-//    inner loop reads a source with two 16-byte LDS loads that all lanes share (broadcast),
-//    and uses it for K register-resident targets.
+//    precomputes what every pair needs (x, Gamma, -Gamma_z and the far-field cut; 1/sigma in
+//    an array of its own that only in-core pairs read), so the inner loop reads a source with
+//    two LDS loads that all lanes share (broadcast), and uses it for K register-resident
+//    targets.
+//  - Sign-folded cross product: a cross-product component is a difference of two products,
+//    which as one multiply-add needs a negated operand (the longer three-operand encoding,
+//    which issues slower).  The pair holds r' = (r_x, -r_y, r_z), v' = (v_x, -v_y, -v_z) and
+//    the staged -Gamma_z instead, with which each component is a multiply and an
+//    accumulating multiply-add; the sums then hold some components negated, and the
+//    epilogue restores their signs (an exact operation).
 //  - A pair takes the point-vortex weights (s^-3, s^-5) unless it lies inside RHO_FAR cores,
 //    where the in-core weights replace them (series or erf/exp; core_weights).  The branch is
 //    skipped by a whole wavefront when none of its lanes is in a core, which is the common case
 //    for spatially ordered wakes.
 //  - FP32 (VPM_F32C): each target's 9 partial sums (u, A = sum G Gamma_j, B) are plain FP32
-//    within chunks of 128 sources and folded into (hi, lo) two-sum pairs after every chunk, so
-//    the error does not grow with N.  The per-target epilogue runs in FP64.
+//    within chunks of 256 sources and folded into compensated (hi, lo) pairs after every
+//    chunk (Dekker's FastTwoSum, its error carried into the next chunk as in Kahan's
+//    summation), so the error does not grow with N.  The per-target epilogue runs in FP64.
 //  - FP64 (VPM_F64): the same schedule with K = 1 and plain FP64 sums.
 //  - Gradient mode adds the velocity gradient du/dx (nine more FP32 sums per target) for the
 //    sub-grid model; the stretching then comes from the same sums.
@@ -39,10 +47,25 @@ namespace vpm {
 
 template <typename T>
 struct SrcTile {
-    // p = (x, y, z, 1/sigma), q = (Gamma_x, Gamma_y, Gamma_z, cut) with cut = RHO_FAR^2 sigma^2
-    // for the source rule and RHO_FAR^2 sigma^2 / 2 for the symmetric rule.
+    // p = (x, y, z, -Gamma_z), q = (Gamma_x, Gamma_y, Gamma_z, cut) with cut = RHO_FAR^2
+    // sigma^2 for the source rule and RHO_FAR^2 sigma^2 / 2 for the symmetric rule; 1/sigma
+    // is staged apart.
     using V4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
 };
+
+// Signs that the held partial sums carry relative to the sums they stand for (the
+// sign-folded cross product): u' = (u_x, -u_y, -u_z); transposed B' = (B_x, -B_y, B_z)
+// (B = sum w r); classical B' = (B_x, -B_y, -B_z) (B = sum w v); gradient H'_ab = s_a t_b H_ab
+// with s = (+, -, -) from v and t = (+, -, +) from r.
+__host__ __device__ constexpr double held_sign(int mode, int c) {
+    return c == 1 || c == 2 ? -1.0
+         : c < 6 ? 1.0
+         : mode == kModeTransposed ? (c == 7 ? -1.0 : 1.0)
+         : mode == kModeClassical ? (c == 7 || c == 8 ? -1.0 : 1.0)
+         : mode == kModeGradient && c < 15
+             ? ((c - 6) / 3 == 0 ? 1.0 : -1.0) * ((c - 6) % 3 == 1 ? -1.0 : 1.0)
+             : 1.0;
+}
 
 // One pair: accumulate into the tile partials of one target.
 // Keeps a value opaque to the optimiser so that what is computed from it inside a rarely
@@ -56,22 +79,28 @@ __device__ __forceinline__ double opaque(double v) {
     return v;
 }
 
-// One pair: accumulate into the partial sums p[] of one target.  Layout of p:
-//   velocity:               u = p[0..2]
-//   transposed / classical: u = p[0..2], A = p[3..5], B = p[6..8]
-//   gradient:               u = p[0..2], A = p[3..5] (pairs outside the cores),
-//                           H = p[6..14] = sum Hn v r^T (row-major, v = Gamma_j x r),
+// One pair: accumulate into the partial sums p[] of one target.  Layout of p (held signs as
+// held_sign gives them):
+//   velocity:               u' = p[0..2]
+//   transposed / classical: u' = p[0..2], A = p[3..5], B' = p[6..8]
+//   gradient:               u' = p[0..2], A = p[3..5] (pairs outside the cores),
+//                           H' = p[6..14] = sum Hn v' r'^T (row-major, v = Gamma_j x r),
 //                           A_core = p[15..17], C = p[18..20] = sum over in-core pairs of G Gamma_i x Gamma_j
+// (px, py, pz, nqz) = (x_j, -Gamma_j,z), (qx, qy, qz, qw) = (Gamma_j, cut_j); ngi1 = -Gamma_i,y,
+// ngi2 = -Gamma_i,z; isig_j = 1/sigma_j, read only for in-core pairs under the source rule.
+// The point-vortex parts of A and B (transposed and classical) go to pab[3..8], which is p or
+// a second set of sums (the odd sources of tiles near the targets).
 template <typename T, int MODE, bool SYM, bool CHECK, bool NEAR>
-__device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, const T pw, const T qx,
-                                         const T qy, const T qz, const T qw, const T xi0,
-                                         const T xi1, const T xi2, const T gi0, const T gi1,
-                                         const T gi2, const T cut_i, const int64_t jglob,
-                                         const int64_t ex, T* p) {
+__device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, const T nqz, const T qx,
+                                         const T qy, const T qz, const T qw, const T* isig_j,
+                                         const T xi0, const T xi1, const T xi2, const T gi0,
+                                         const T gi1, const T gi2, const T ngi1, const T ngi2,
+                                         const T cut_i, const int64_t jglob, const int64_t ex, T* p,
+                                         T* pab) {
     const T rx = xi0 - px;
-    const T ry = xi1 - py;
+    const T ryn = py - xi1;  // -r_y
     const T rz = xi2 - pz;
-    const T s2 = rx * rx + ry * ry + rz * rz;
+    const T s2 = rx * rx + ryn * ryn + rz * rz;
     const T rinv = rsqrt_fast(s2);
     const T rinv2 = rinv * rinv;
     T G = rinv2 * rinv;
@@ -80,13 +109,13 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
     const T cut = SYM ? (qw + cut_i) : qw;
     // NEAR is false for source tiles that lie entirely outside every core of this block.
     if (NEAR && s2 < cut) {
-        // source rule: pw = 1/sigma_j; symmetric rule: 1/sigma_ij^2 = RHO_FAR^2 / cut
+        // source rule: 1/sigma_j; symmetric rule: 1/sigma_ij^2 = RHO_FAR^2 / cut
         T isig, isig2;
         if (SYM) {
             isig2 = T(Prec<T>::kFarRho2) * rcp_fast(opaque(cut));
             isig = sqrt_fast(isig2);
         } else {
-            isig = opaque(pw);
+            isig = *isig_j;
             isig2 = isig * isig;
         }
         core_weights_call(s2, isig, isig2, G, Hn);
@@ -113,8 +142,9 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
             } else {
                 const T f = (MODE == kModeTransposed ? T(-1.0 / 3.0) : T(1.0 / 3.0)) * G;
                 p[6] += f * cx;
-                p[7] += f * cy;
-                p[8] += f * cz;
+                p[7] -= f * cy;
+                if (MODE == kModeTransposed) p[8] += f * cz;
+                else p[8] -= f * cz;
             }
             Ga = T(0);
         } else {
@@ -127,38 +157,40 @@ __device__ __forceinline__ void pair_fwd(const T px, const T py, const T pz, con
             Ga = T(0);
         }
     }
-    const T vx = qy * rz - qz * ry;
-    const T vy = qz * rx - qx * rz;
-    const T vz = qx * ry - qy * rx;
+    // v' = (v_x, -v_y, -v_z), each a multiply and an accumulating multiply-add
+    const T vx = qy * rz + qz * ryn;
+    const T vyn = nqz * rx + qx * rz;
+    const T vzn = qx * ryn + qy * rx;
     p[0] += G * vx;
-    p[1] += G * vy;
-    p[2] += G * vz;
+    p[1] += G * vyn;
+    p[2] += G * vzn;
     if (MODE != kModeVelocity) {
-        p[3] += Ga * qx;
-        p[4] += Ga * qy;
-        p[5] += Ga * qz;
+        if (MODE == kModeGradient) pab = p;
+        pab[3] += Ga * qx;
+        pab[4] += Ga * qy;
+        pab[5] += Ga * qz;
         if (MODE == kModeTransposed) {
-            const T tau = gi0 * vx + gi1 * vy + gi2 * vz;
+            const T tau = gi0 * vx + ngi1 * vyn + ngi2 * vzn;
             const T w = Hn * tau;
-            p[6] += w * rx;
-            p[7] += w * ry;
-            p[8] += w * rz;
+            pab[6] += w * rx;
+            pab[7] += w * ryn;
+            pab[8] += w * rz;
         } else if (MODE == kModeClassical) {
-            const T rg = rx * gi0 + ry * gi1 + rz * gi2;
+            const T rg = rx * gi0 + ryn * ngi1 + rz * gi2;
             const T w = Hn * rg;
-            p[6] += w * vx;
-            p[7] += w * vy;
-            p[8] += w * vz;
+            pab[6] += w * vx;
+            pab[7] += w * vyn;
+            pab[8] += w * vzn;
         } else {
-            const T hx = Hn * vx, hy = Hn * vy, hz = Hn * vz;
+            const T hx = Hn * vx, hy = Hn * vyn, hz = Hn * vzn;
             p[6] += hx * rx;
-            p[7] += hx * ry;
+            p[7] += hx * ryn;
             p[8] += hx * rz;
             p[9] += hy * rx;
-            p[10] += hy * ry;
+            p[10] += hy * ryn;
             p[11] += hy * rz;
             p[12] += hz * rx;
-            p[13] += hz * ry;
+            p[13] += hz * ryn;
             p[14] += hz * rz;
         }
     }
@@ -246,7 +278,7 @@ struct FwdBlock {
     // Process targets [t0, t1) (at most WG*K of them) against sources [s0, s1) of one set.
     // self_shift: with self evaluation, target t is source t + self_shift (else ignored).
     static __device__ void run(const FwdArgs& a, int64_t s0, int64_t s1, int64_t t0, int64_t t1,
-                               int64_t self_shift, V4* lp, V4* lq, T* box_scratch, int chunk_id) {
+                               int64_t self_shift, V4* lp, V4* lq, T* ls, T* box_scratch, int chunk_id) {
         const T* __restrict__ xs = static_cast<const T*>(a.xs);
         const T* __restrict__ gs = static_cast<const T*>(a.gs);
         const T* __restrict__ ss = static_cast<const T*>(a.ss);
@@ -256,7 +288,7 @@ struct FwdBlock {
         const int tid = threadIdx.x;
         const T far2 = T(Prec<T>::kFarRho2);
 
-        T xi[K][3], gi[K][3], cut_i[K];
+        T xi[K][3], gi[K][3], ngi[K][2], cut_i[K];
         int64_t ex[K];
         bool valid[K];
 #pragma unroll
@@ -274,6 +306,9 @@ struct FwdBlock {
             } else {
                 gi[k][0] = gi[k][1] = gi[k][2] = T(0);
             }
+            // (kept opaque so that the products stay plain multiplies by a register)
+            ngi[k][0] = opaque(-gi[k][1]);
+            ngi[k][1] = opaque(-gi[k][2]);
             if (SYM) {
                 const T sg = st[tt];
                 cut_i[k] = T(0.5) * far2 * sg * sg;
@@ -308,6 +343,7 @@ struct FwdBlock {
         }
 
         T acc[K][kNacc];   // tile partials
+        T acc2[K][kNacc];  // A and B of the odd sources of near tiles (kDual)
         T hi[K][kNacc];    // compensated totals (FP32 path)
         T lo[K][kNacc];
 #pragma unroll
@@ -315,6 +351,7 @@ struct FwdBlock {
 #pragma unroll
             for (int c = 0; c < kNacc; ++c) {
                 acc[k][c] = T(0);
+                acc2[k][c] = T(0);
                 hi[k][c] = T(0);
                 lo[k][c] = T(0);
             }
@@ -330,13 +367,14 @@ struct FwdBlock {
                 p.x = xs[j];
                 p.y = xs[a.lds + j];
                 p.z = xs[2 * a.lds + j];
-                p.w = T(1) / sg;
                 q.x = gs[j];
                 q.y = gs[a.lds + j];
                 q.z = gs[2 * a.lds + j];
                 q.w = SYM ? T(0.5) * far2 * sg * sg : far2 * sg * sg;
+                p.w = -q.z;
                 lp[tid] = p;
                 lq[tid] = q;
+                ls[tid] = T(1) / sg;
                 slo[0] = shi[0] = p.x;
                 slo[1] = shi[1] = p.y;
                 slo[2] = shi[2] = p.z;
@@ -365,11 +403,11 @@ struct FwdBlock {
             }
             const bool near = d2 < (SYM ? tcut + bcut : tcut);
             if (check) {
-                if (near) tile<true, true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc, hi, lo);
-                else tile<true, false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc, hi, lo);
+                if (near) tile<true, true>(lp, lq, ls, cnt, j0, xi, gi, ngi, cut_i, ex, acc, acc2, hi, lo);
+                else tile<true, false>(lp, lq, ls, cnt, j0, xi, gi, ngi, cut_i, ex, acc, acc2, hi, lo);
             } else {
-                if (near) tile<false, true>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc, hi, lo);
-                else tile<false, false>(lp, lq, cnt, j0, xi, gi, cut_i, ex, acc, hi, lo);
+                if (near) tile<false, true>(lp, lq, ls, cnt, j0, xi, gi, ngi, cut_i, ex, acc, acc2, hi, lo);
+                else tile<false, false>(lp, lq, ls, cnt, j0, xi, gi, ngi, cut_i, ex, acc, acc2, hi, lo);
             }
         }
 
@@ -381,7 +419,7 @@ struct FwdBlock {
             double tot[kNacc];
 #pragma unroll
             for (int c = 0; c < kNacc; ++c)
-                tot[c] = kComp ? double(hi[k][c]) + double(lo[k][c]) : double(acc[k][c]);
+                tot[c] = held_sign(MODE, c) * (kComp ? double(hi[k][c]) + double(lo[k][c]) : double(acc[k][c]));
             if (chunk_id >= 0) {
 #pragma unroll
                 for (int c = 0; c < kNacc; ++c) a.part[(int64_t(chunk_id) * kNacc + c) * a.tgt_end + t] = tot[c];
@@ -393,41 +431,73 @@ struct FwdBlock {
 
     // FP32 partials are folded into the (hi, lo) pairs every kFold sources: the in-chunk FP32
     // sum error grows with the chunk length and is amplified in Gamma_i x A when neighbouring
-    // strengths are nearly parallel (vortex filaments).
-    static constexpr int kFold = 128;
+    // strengths are nearly parallel (vortex filaments).  A chunk of 256 is one whole tile of
+    // the 256-lane shapes, whose pair loop then needs no chunk loop around it (91 instead of
+    // 109 VGPRs, five wavefronts per SIMD instead of four).  In tiles near the targets, where
+    // the large terms are, the odd sources add their A and B into a second set of sums, so
+    // that each FP32 sum there runs over 128 terms (one target per lane, outside the gradient
+    // mode: the register budget of the other shapes has no room for it).
+    static constexpr int kFold = 256;
+    static constexpr bool kDual = kComp && K == 1 && MODE != kModeGradient && MODE != kModeVelocity;
 
-    static __device__ __forceinline__ void fold(T (&acc)[K][kNacc], T (&hi)[K][kNacc], T (&lo)[K][kNacc]) {
+    // One fold: y = acc + lo (the chunk and the error carried from the previous fold); the
+    // FastTwoSum of (hi, y) gives hi + y = t + e exactly whenever |hi| >= |y| (and when hi = 0),
+    // and e becomes the new lo.  A chunk that outweighs the sum so far loses at most the
+    // rounding of that one addition, as a plain FP32 sum would.  Five instructions per sum
+    // against eight for the branch-free TwoSum.
+    static __device__ __forceinline__ void fold(T (&acc)[K][kNacc], T (&acc2)[K][kNacc], T (&hi)[K][kNacc],
+                                                T (&lo)[K][kNacc]) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int c = 0; c < kNacc; ++c) {
-                T s, e;
-                two_sum(hi[k][c], acc[k][c], s, e);
-                hi[k][c] = s;
-                lo[k][c] += e;
+                const bool two = kDual && c >= 3 && c < 9;
+                const T y = (two ? acc[k][c] + acc2[k][c] : acc[k][c]) + lo[k][c];
+                const T t = hi[k][c] + y;
+                lo[k][c] = y - (t - hi[k][c]);
+                hi[k][c] = t;
                 acc[k][c] = T(0);
+                if (two) acc2[k][c] = T(0);
             }
     }
 
     template <bool CHECK, bool NEAR>
-    static __device__ __forceinline__ void tile(const V4* lp, const V4* lq, int cnt, int64_t j0,
-                                                T (&xi)[K][3], T (&gi)[K][3], T (&cut_i)[K],
-                                                int64_t (&ex)[K], T (&acc)[K][kNacc], T (&hi)[K][kNacc],
-                                                T (&lo)[K][kNacc]) {
+    static __device__ __forceinline__ void tile(const V4* lp, const V4* lq, const T* ls, int cnt, int64_t j0,
+                                                T (&xi)[K][3], T (&gi)[K][3], T (&ngi)[K][2], T (&cut_i)[K],
+                                                int64_t (&ex)[K], T (&acc)[K][kNacc], T (&acc2)[K][kNacc],
+                                                T (&hi)[K][kNacc], T (&lo)[K][kNacc]) {
         for (int c0 = 0; c0 < cnt; c0 += kFold) {
             const int c1 = (cnt - c0) < kFold ? cnt : c0 + kFold;
+            int jj = c0;
+            if constexpr (kDual && NEAR) {
+                // sources in pairs: the even one into acc, the odd one's A and B into acc2
+#pragma unroll U / 2
+                for (; jj + 1 < c1; jj += 2) {
+                    const V4 p = lp[jj], q = lq[jj];
+                    const V4 p2 = lp[jj + 1], q2 = lq[jj + 1];
+                    pair_fwd<T, MODE, SYM, CHECK, NEAR>(p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, ls + jj,
+                                                        xi[0][0], xi[0][1], xi[0][2], gi[0][0], gi[0][1],
+                                                        gi[0][2], ngi[0][0], ngi[0][1], cut_i[0], j0 + jj,
+                                                        ex[0], &acc[0][0], &acc[0][0]);
+                    pair_fwd<T, MODE, SYM, CHECK, NEAR>(p2.x, p2.y, p2.z, p2.w, q2.x, q2.y, q2.z, q2.w,
+                                                        ls + jj + 1, xi[0][0], xi[0][1], xi[0][2], gi[0][0],
+                                                        gi[0][1], gi[0][2], ngi[0][0], ngi[0][1], cut_i[0],
+                                                        j0 + jj + 1, ex[0], &acc[0][0], &acc2[0][0]);
+                }
+            }
 #pragma unroll U
-            for (int jj = c0; jj < c1; ++jj) {
+            for (; jj < c1; ++jj) {
                 const V4 p = lp[jj];
                 const V4 q = lq[jj];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    pair_fwd<T, MODE, SYM, CHECK, NEAR>(p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, xi[k][0],
-                                                        xi[k][1], xi[k][2], gi[k][0], gi[k][1], gi[k][2],
-                                                        cut_i[k], j0 + jj, ex[k], &acc[k][0]);
+                    pair_fwd<T, MODE, SYM, CHECK, NEAR>(p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, ls + jj,
+                                                        xi[k][0], xi[k][1], xi[k][2], gi[k][0], gi[k][1],
+                                                        gi[k][2], ngi[k][0], ngi[k][1], cut_i[k], j0 + jj,
+                                                        ex[k], &acc[k][0], &acc[k][0]);
                 }
             }
-            if constexpr (kComp) fold(acc, hi, lo);
+            if constexpr (kComp) fold(acc, acc2, hi, lo);
         }
     }
 };
@@ -438,6 +508,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd(FwdArgs a) {
     using B = FwdBlock<T, K, WG, MODE, SYM, U>;
     __shared__ typename B::V4 lp[WG];
     __shared__ typename B::V4 lq[WG];
+    __shared__ T ls[WG];
     __shared__ T box[7 * (WG / 64)];
     const int64_t t0 = a.tgt_begin + int64_t(blockIdx.x) * (WG * K);
     int64_t t1 = t0 + WG * K;
@@ -449,7 +520,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd(FwdArgs a) {
         s0 = a.src_begin + int64_t(blockIdx.y) * a.chunk;
         s1 = s0 + a.chunk < a.src_end ? s0 + a.chunk : a.src_end;
     }
-    B::run(a, s0, s1, t0, t1, a.src_begin - a.tgt_begin, lp, lq, box, chunk_id);
+    B::run(a, s0, s1, t0, t1, a.src_begin - a.tgt_begin, lp, lq, ls, box, chunk_id);
 }
 
 // Adds the per-chunk FP64 partials of every target in chunk order and stores the result.
@@ -481,6 +552,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd_batched(FwdArgs a, BatchQueue b
     using B = FwdBlock<T, K, WG, MODE, SYM, U>;
     __shared__ typename B::V4 lp[WG];
     __shared__ typename B::V4 lq[WG];
+    __shared__ T ls[WG];
     __shared__ T box[7 * (WG / 64)];
     __shared__ int item_s;
     for (;;) {
@@ -496,7 +568,7 @@ __global__ __launch_bounds__(WG) void k_pair_fwd_batched(FwdArgs a, BatchQueue b
         const int64_t t0 = tb0 + int64_t(it.y) * (WG * K);
         int64_t t1 = t0 + WG * K;
         if (t1 > tb1) t1 = tb1;
-        B::run(a, s0, s1, t0, t1, s0 - tb0, lp, lq, box, -1);
+        B::run(a, s0, s1, t0, t1, s0 - tb0, lp, lq, ls, box, -1);
     }
 }
 

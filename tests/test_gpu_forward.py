@@ -272,7 +272,7 @@ def test_permutation_invariance(kind, gpu):
     perm = np.random.default_rng(9).permutation(x.shape[1])
     u1, d1 = vpm.vpm_eval_velocity_stretching(dev_(x, kind), dev_(g, kind), dev_(s, kind))
     u2, d2 = vpm.vpm_eval_velocity_stretching(dev_(x[:, perm], kind), dev_(g[:, perm], kind), dev_(s[perm], kind))
-    tight = 1e-13 if kind == "f64" else 1e-6  # measured 1.1e-7 (u), 2.3e-7 (dgamma)
+    tight = 1e-13 if kind == "f64" else 1e-6  # measured 1.6e-7 (u), 2.2e-7 (dgamma)
     eu, ed = rel_l2(host(u2), host(u1)[:, perm]), rel_l2(host(d2), host(d1)[:, perm])
     say(f"permutation {kind}: rel-L2 u {eu:.2e} dgamma {ed:.2e}")
     assert eu <= tight and ed <= tight
