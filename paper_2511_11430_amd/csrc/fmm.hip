@@ -939,6 +939,16 @@ __global__ __launch_bounds__(256) void k_fmm_l2p(NearArgs a, double* __restrict_
             for (int e = 0; e < 3; ++e) far[(6 + 3 * c + e) * n + q] = J[c][e];
 }
 
+// Keeps a value opaque to the optimiser (emits no instruction).
+__device__ __forceinline__ float opaque_reg(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ double opaque_reg(double v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // One near-field pair.  Sums (as the direct kernel's):
 //   plain:    U = sum G v (v = Gamma_j x r), A = sum G Gamma_j outside the cores,
 //             B = sum Hn tau r (transposed, tau = Gamma_i . v) or sum Hn (r . Gamma_i) v
@@ -946,78 +956,99 @@ __global__ __launch_bounds__(256) void k_fmm_l2p(NearArgs a, double* __restrict_
 //             classical sign is folded in);
 //   gradient: U, A outside the cores, H = sum Hn v r^T (row-major), A of the in-core pairs,
 //             C = sum over in-core pairs of G Gamma_i x Gamma_j.
-template <typename T, bool CLASSICAL, bool GRAD, bool MAYCORE>
-__device__ __forceinline__ void near_pair(T xi, T yi, T zi, T gxi, T gyi, T gzi, T sxj, T syj, T szj, T gxj, T gyj,
-                                          T gzj, T isj, T isj2, T cutj, T* acc) {
-    const T rx = xi - sxj, ry = yi - syj, rz = zi - szj;
-    const T s2 = rx * rx + ry * ry + rz * rz;
-    const T vx = gyj * rz - gzj * ry, vy = gzj * rx - gxj * rz, vz = gxj * ry - gyj * rx;
+// Sign-folded cross product (as in the direct kernel): the pair holds r' = (r_x, -r_y, r_z)
+// and v' = (v_x, -v_y, -v_z), each component of v' a multiply and an accumulating
+// multiply-add with the staged -Gamma_j,z, so no multiply-add needs a negated operand; the
+// sums then hold some components negated (near_held_sign), which the epilogue undoes.
+// p = (x_j, -Gamma_j,z), q = (Gamma_j, cut_j), w = (1/sigma_j, 1/sigma_j^2) (read only in a
+// core); ngyi = -Gamma_i,y, ngzi = -Gamma_i,z.
+template <typename T, bool CLASSICAL, bool GRAD, bool MAYCORE, typename V4, typename V2>
+__device__ __forceinline__ void near_pair(T xi, T yi, T zi, T gxi, T gyi, T gzi, T ngyi, T ngzi, const V4& p,
+                                          const V4& q, const V2* w, T* acc) {
+    const T rx = xi - p.x, ryn = p.y - yi, rz = zi - p.z;
+    const T s2 = rx * rx + ryn * ryn + rz * rz;
+    const T vx = q.y * rz + q.z * ryn, vyn = p.w * rx + q.x * rz, vzn = q.x * ryn + q.y * rx;
     const T inv = rsqrt_fast(s2);
     const T inv2 = inv * inv;
     T G = inv * inv2, Hn = G * inv2;
     bool core = false;
     if constexpr (MAYCORE) {
-        core = s2 < cutj;
-        if (core) core_weights_call(s2, isj, isj2, G, Hn);
+        core = s2 < q.w;
+        if (core) {
+            const V2 iw = *w;
+            core_weights_call(s2, iw.x, iw.y, G, Hn);
+        }
     }
     acc[0] += G * vx;
-    acc[1] += G * vy;
-    acc[2] += G * vz;
+    acc[1] += G * vyn;
+    acc[2] += G * vzn;
     if constexpr (GRAD) {
-        const T hx = Hn * vx, hy = Hn * vy, hz = Hn * vz;
+        const T hx = Hn * vx, hy = Hn * vyn, hz = Hn * vzn;
         acc[6] += hx * rx;
-        acc[7] += hx * ry;
+        acc[7] += hx * ryn;
         acc[8] += hx * rz;
         acc[9] += hy * rx;
-        acc[10] += hy * ry;
+        acc[10] += hy * ryn;
         acc[11] += hy * rz;
         acc[12] += hz * rx;
-        acc[13] += hz * ry;
+        acc[13] += hz * ryn;
         acc[14] += hz * rz;
         if constexpr (MAYCORE) {
             // A of the in-core pairs and A outside the cores go to different sums; the weights
             // are selected rather than the destinations (a selected destination becomes an
             // indexed array in scratch memory)
             const T Gc = core ? G : T(0), Go = core ? T(0) : G;
-            acc[3] += Go * gxj;
-            acc[4] += Go * gyj;
-            acc[5] += Go * gzj;
-            acc[15] += Gc * gxj;
-            acc[16] += Gc * gyj;
-            acc[17] += Gc * gzj;
+            acc[3] += Go * q.x;
+            acc[4] += Go * q.y;
+            acc[5] += Go * q.z;
+            acc[15] += Gc * q.x;
+            acc[16] += Gc * q.y;
+            acc[17] += Gc * q.z;
             if (core) {
-                acc[18] += G * (gyi * gzj - gzi * gyj);
-                acc[19] += G * (gzi * gxj - gxi * gzj);
-                acc[20] += G * (gxi * gyj - gyi * gxj);
+                acc[18] += G * (gyi * q.z - gzi * q.y);
+                acc[19] += G * (gzi * q.x - gxi * q.z);
+                acc[20] += G * (gxi * q.y - gyi * q.x);
             }
         } else {
-            acc[3] += G * gxj;
-            acc[4] += G * gyj;
-            acc[5] += G * gzj;
+            acc[3] += G * q.x;
+            acc[4] += G * q.y;
+            acc[5] += G * q.z;
         }
     } else {
-        const T w = CLASSICAL ? Hn * (rx * gxi + ry * gyi + rz * gzi) : Hn * (gxi * vx + gyi * vy + gzi * vz);
+        const T wgt = CLASSICAL ? Hn * (rx * gxi + ryn * ngyi + rz * gzi) : Hn * (gxi * vx + ngyi * vyn + ngzi * vzn);
         if constexpr (!CLASSICAL) {
-            acc[6] += w * rx;
-            acc[7] += w * ry;
-            acc[8] += w * rz;
+            acc[6] += wgt * rx;
+            acc[7] += wgt * ryn;
+            acc[8] += wgt * rz;
         } else {
-            acc[6] += w * vx;
-            acc[7] += w * vy;
-            acc[8] += w * vz;
+            acc[6] += wgt * vx;
+            acc[7] += wgt * vyn;
+            acc[8] += wgt * vzn;
         }
         if (MAYCORE && core) {
             // transposed: G Gamma_i x Gamma_j, classical: G Gamma_j x Gamma_i, into B x -1/3
             const T f = G * T(CLASSICAL ? 1.0 / 3.0 : -1.0 / 3.0);
-            acc[6] += f * (gyi * gzj - gzi * gyj);
-            acc[7] += f * (gzi * gxj - gxi * gzj);
-            acc[8] += f * (gxi * gyj - gyi * gxj);
+            acc[6] += f * (gyi * q.z - gzi * q.y);
+            acc[7] -= f * (gzi * q.x - gxi * q.z);
+            if constexpr (CLASSICAL) acc[8] -= f * (gxi * q.y - gyi * q.x);
+            else acc[8] += f * (gxi * q.y - gyi * q.x);
         } else {
-            acc[3] += G * gxj;
-            acc[4] += G * gyj;
-            acc[5] += G * gzj;
+            acc[3] += G * q.x;
+            acc[4] += G * q.y;
+            acc[5] += G * q.z;
         }
     }
+}
+
+// Signs that the near-field sums hold relative to the sums they stand for (near_pair):
+// U' = (U_x, -U_y, -U_z); transposed B' = (B_x, -B_y, B_z); classical B' = (B_x, -B_y, -B_z);
+// gradient H'_ab = s_a t_b H_ab with s = (+, -, -) from v and t = (+, -, +) from r.
+__device__ constexpr double near_held_sign(bool classical, bool grad, int c) {
+    return c == 1 || c == 2 ? -1.0
+         : c < 6 ? 1.0
+         : grad ? (c < 15 ? ((c - 6) / 3 == 0 ? 1.0 : -1.0) * ((c - 6) % 3 == 1 ? -1.0 : 1.0) : 1.0)
+         : classical ? (c == 7 || c == 8 ? -1.0 : 1.0)
+         : (c == 7 ? -1.0 : 1.0);
 }
 
 // Near field of one work item: the exact Gaussian pair sum over the 27 neighbouring leaves.
@@ -1045,7 +1076,11 @@ __global__ __launch_bounds__(256, GRAD ? 4 : 1) void k_fmm_near(NearArgs a) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int wq0 = t0 + 64 * wv;  // first target of this wavefront
 
-    __shared__ T sx[3][kNearTile], sg[3][kNearTile], sis[kNearTile], sis2[kNearTile], scut[kNearTile];
+    using V4 = typename std::conditional<kComp, float4, double4>::type;
+    using V2 = typename std::conditional<kComp, float2, double2>::type;
+    // per source: (x, -Gamma_z), (Gamma, cut) and (1/sigma, 1/sigma^2)
+    __shared__ V4 sp[kNearTile], sq[kNearTile];
+    __shared__ V2 sw[kNearTile];
     __shared__ T sbox[4][7];
     __shared__ int32_t nb_lo[27], nb_hi[27];
     int ic[3];
@@ -1064,6 +1099,8 @@ __global__ __launch_bounds__(256, GRAD ? 4 : 1) void k_fmm_near(NearArgs a) {
 
     const T xi = xs[qq], yi = xs[n + qq], zi = xs[2 * n + qq];
     const T gxi = gs[qq], gyi = gs[n + qq], gzi = gs[2 * n + qq];
+    // (kept opaque so that their products stay plain multiplies by a register)
+    const T ngyi = opaque_reg(-gyi), ngzi = opaque_reg(-gzi);
     // box of this wavefront's targets (lanes past the end repeat the item's first target)
     T tlo[3], thi[3], tcut;
     {
@@ -1082,17 +1119,14 @@ __global__ __launch_bounds__(256, GRAD ? 4 : 1) void k_fmm_near(NearArgs a) {
                 const bool has = int(threadIdx.x) < cnt;
                 const int j = has ? j0 + threadIdx.x : j0;
                 T pl[3];
-                for (int d = 0; d < 3; ++d) {
-                    pl[d] = xs[d * n + j];
-                    sx[d][threadIdx.x] = pl[d];
-                    sg[d][threadIdx.x] = gs[d * n + j];
-                }
+                for (int d = 0; d < 3; ++d) pl[d] = xs[d * n + j];
                 const T sj = ss[j];
                 const T is = T(1) / sj;
-                sis[threadIdx.x] = is;
-                sis2[threadIdx.x] = is * is;
                 const T cut = Prec<T>::kFarRho2 * sj * sj;
-                scut[threadIdx.x] = cut;
+                const T g0 = gs[j], g1 = gs[n + j], g2 = gs[2 * n + j];
+                sp[threadIdx.x] = V4{pl[0], pl[1], pl[2], -g2};
+                sq[threadIdx.x] = V4{g0, g1, g2, cut};
+                sw[threadIdx.x] = V2{is, is * is};
                 // subtile box of this wavefront's 64 staged sources (past the end: the tile's
                 // first source again, which only makes the box larger)
                 T blo[3], bhi[3], bcut;
@@ -1120,22 +1154,20 @@ __global__ __launch_bounds__(256, GRAD ? 4 : 1) void k_fmm_near(NearArgs a) {
                 const bool self_sub = j0 + jb < wq0 + 64 && j0 + je > wq0;
                 if (d2 >= sbox[sub][6]) {
                     // every pair of this wavefront and subtile is outside the cores
+#pragma unroll 2
                     for (int jj = jb; jj < je; ++jj)
-                        near_pair<T, CLASSICAL, GRAD, false>(xi, yi, zi, gxi, gyi, gzi, sx[0][jj], sx[1][jj],
-                                                             sx[2][jj], sg[0][jj], sg[1][jj], sg[2][jj], T(0), T(0),
-                                                             T(0), acc);
+                        near_pair<T, CLASSICAL, GRAD, false>(xi, yi, zi, gxi, gyi, gzi, ngyi, ngzi, sp[jj], sq[jj],
+                                                             sw + jj, acc);
                 } else if (self_sub) {
                     for (int jj = jb; jj < je; ++jj) {
                         if (j0 + jj == qq) continue;  // self pair
-                        near_pair<T, CLASSICAL, GRAD, true>(xi, yi, zi, gxi, gyi, gzi, sx[0][jj], sx[1][jj],
-                                                            sx[2][jj], sg[0][jj], sg[1][jj], sg[2][jj], sis[jj],
-                                                            sis2[jj], scut[jj], acc);
+                        near_pair<T, CLASSICAL, GRAD, true>(xi, yi, zi, gxi, gyi, gzi, ngyi, ngzi, sp[jj], sq[jj],
+                                                            sw + jj, acc);
                     }
                 } else {
                     for (int jj = jb; jj < je; ++jj)
-                        near_pair<T, CLASSICAL, GRAD, true>(xi, yi, zi, gxi, gyi, gzi, sx[0][jj], sx[1][jj],
-                                                            sx[2][jj], sg[0][jj], sg[1][jj], sg[2][jj], sis[jj],
-                                                            sis2[jj], scut[jj], acc);
+                        near_pair<T, CLASSICAL, GRAD, true>(xi, yi, zi, gxi, gyi, gzi, ngyi, ngzi, sp[jj], sq[jj],
+                                                            sw + jj, acc);
                 }
             }
             if constexpr (kComp) {
@@ -1153,7 +1185,8 @@ __global__ __launch_bounds__(256, GRAD ? 4 : 1) void k_fmm_near(NearArgs a) {
     if (!valid) return;
     double S[NA];
 #pragma unroll
-    for (int c = 0; c < NA; ++c) S[c] = kComp ? double(hi[c]) + double(lo[c]) : double(acc[c]);
+    for (int c = 0; c < NA; ++c)
+        S[c] = near_held_sign(CLASSICAL, GRAD, c) * (kComp ? double(hi[c]) + double(lo[c]) : double(acc[c]));
     const double Gi[3] = {double(gxi), double(gyi), double(gzi)};
     double u[3] = {S[0] * kInv4Pi, S[1] * kInv4Pi, S[2] * kInv4Pi};
     double dgv[3];
