@@ -972,11 +972,22 @@ __device__ __forceinline__ void near_pair(T xi, T yi, T zi, T gxi, T gyi, T gzi,
     const T inv2 = inv * inv;
     T G = inv * inv2, Hn = G * inv2;
     bool core = false;
+    T Ga = G;  // weight of Gamma_j in A (plain mode)
     if constexpr (MAYCORE) {
         core = s2 < q.w;
         if (core) {
             const V2 iw = *w;
             core_weights_call(s2, iw.x, iw.y, G, Hn);
+            if constexpr (!GRAD) {
+                // transposed: G Gamma_i x Gamma_j, classical: G Gamma_j x Gamma_i, into B x -1/3
+                // (held signs as B'), and nothing into A
+                const T f = G * T(CLASSICAL ? 1.0 / 3.0 : -1.0 / 3.0);
+                acc[6] += f * (gyi * q.z - gzi * q.y);
+                acc[7] -= f * (gzi * q.x - gxi * q.z);
+                if constexpr (CLASSICAL) acc[8] -= f * (gxi * q.y - gyi * q.x);
+                else acc[8] += f * (gxi * q.y - gyi * q.x);
+                Ga = T(0);
+            }
         }
     }
     acc[0] += G * vx;
@@ -1025,18 +1036,9 @@ __device__ __forceinline__ void near_pair(T xi, T yi, T zi, T gxi, T gyi, T gzi,
             acc[7] += wgt * vyn;
             acc[8] += wgt * vzn;
         }
-        if (MAYCORE && core) {
-            // transposed: G Gamma_i x Gamma_j, classical: G Gamma_j x Gamma_i, into B x -1/3
-            const T f = G * T(CLASSICAL ? 1.0 / 3.0 : -1.0 / 3.0);
-            acc[6] += f * (gyi * q.z - gzi * q.y);
-            acc[7] -= f * (gzi * q.x - gxi * q.z);
-            if constexpr (CLASSICAL) acc[8] -= f * (gxi * q.y - gyi * q.x);
-            else acc[8] += f * (gxi * q.y - gyi * q.x);
-        } else {
-            acc[3] += G * q.x;
-            acc[4] += G * q.y;
-            acc[5] += G * q.z;
-        }
+        acc[3] += Ga * q.x;
+        acc[4] += Ga * q.y;
+        acc[5] += Ga * q.z;
     }
 }
 
