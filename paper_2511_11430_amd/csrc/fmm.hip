@@ -590,6 +590,133 @@ __host__ __device__ inline int m2l_group_doubles(int p, bool mlds) {
     return g > 3 * nt ? g : 3 * nt;
 }
 
+// Work units of the high-order M2L (orders whose grid fills the LDS, one group per cell).
+// The terms n are cut into blocks of 64 (one wavefront's lanes, in degree order); block b's
+// lanes walk the same k, up to the prefix length of its lowest-degree term.  Those walks are
+// very uneven (at order 18 from 1330 steps for the first block down to 1), so each block's walk
+// is cut into pieces, and the pieces are dealt to the wavefronts longest first (each to the
+// least loaded wavefront with a free slot).  A piece is (block, k0, k1); the partial sums of a
+// block's pieces are added in k order at the end.  Built on the host, passed by value.
+constexpr int kUnitWaves = 16;                       // 1024 lanes
+constexpr int kUnitSlots = 4;                        // pieces per wavefront
+constexpr int kMaxUnits = kUnitWaves * kUnitSlots;   // 64
+constexpr int kMaxBlocks = (kMaxTerms + 63) / 64;    // 28
+struct M2lUnits {
+    int16_t blk[kMaxUnits], k0[kMaxUnits], k1[kMaxUnits];  // pieces, sorted by (block, k0)
+    int8_t wave_unit[kMaxUnits];                            // [wave * kUnitSlots + slot]: piece or -1
+    int16_t first[kMaxBlocks + 1];                          // pieces of block b: [first[b], first[b + 1])
+    int32_t n;                                              // number of pieces
+};
+
+// Degree of term t in the degree order (terms of degree d: (d + 1)(d + 2)/2 of them).
+inline int term_degree_host(int t) {
+    int d = 0;
+    while (t >= (d + 1) * (d + 2) / 2) {
+        t -= (d + 1) * (d + 2) / 2;
+        ++d;
+    }
+    return d;
+}
+
+// Returns false when the order's walks do not fit kUnitWaves x kUnitSlots pieces.
+inline bool m2l_units(int p, M2lUnits& u) {
+    const int nt = nterms(p);
+    const int nblk = (nt + 63) / 64;
+    if (nblk > kMaxBlocks) return false;
+    int steps[kMaxBlocks];
+    int smax = 0;
+    for (int b = 0; b < nblk; ++b) {
+        steps[b] = nterms(p - term_degree_host(64 * b));
+        smax = steps[b] > smax ? steps[b] : smax;
+    }
+    struct Piece { int len, b, k0, k1; };
+    long best = -1;
+    for (int umax = 8; umax <= smax + 8; umax += 8) {
+        Piece pc[kMaxUnits];
+        int np = 0;
+        bool fits = true;
+        for (int b = 0; b < nblk && fits; ++b) {
+            const int parts = (steps[b] + umax - 1) / umax;
+            int len = (steps[b] + parts - 1) / parts;
+            len = (len + 7) / 8 * 8;
+            for (int k = 0; k < steps[b]; k += len) {
+                if (np == kMaxUnits) {
+                    fits = false;
+                    break;
+                }
+                const int k1 = k + len < steps[b] ? k + len : steps[b];
+                pc[np++] = Piece{k1 - k, b, k, k1};
+            }
+        }
+        if (!fits) continue;
+        // longest first; ties in (block, k0) order
+        for (int i = 1; i < np; ++i)
+            for (int j = i; j > 0; --j) {
+                const Piece& a = pc[j - 1];
+                const Piece& c = pc[j];
+                const bool swap = c.len > a.len || (c.len == a.len && (c.b < a.b || (c.b == a.b && c.k0 < a.k0)));
+                if (!swap) break;
+                const Piece t = pc[j - 1];
+                pc[j - 1] = pc[j];
+                pc[j] = t;
+            }
+        long load[kUnitWaves] = {};
+        int cnt[kUnitWaves] = {};
+        int owner[kMaxUnits], slot[kMaxUnits];
+        for (int i = 0; i < np && fits; ++i) {
+            int w = -1;
+            for (int c = 0; c < kUnitWaves; ++c)
+                if (cnt[c] < kUnitSlots && (w < 0 || load[c] < load[w])) w = c;
+            if (w < 0) {
+                fits = false;
+                break;
+            }
+            owner[i] = w;
+            slot[i] = cnt[w]++;
+            load[w] += pc[i].len;
+        }
+        if (!fits) continue;
+        // wavefronts share a SIMD four ways (wavefront w on SIMD w % 4)
+        long score = 0;
+        for (int sm = 0; sm < 4; ++sm) {
+            long l = 0;
+            for (int w = sm; w < kUnitWaves; w += 4) l += load[w];
+            score = l > score ? l : score;
+        }
+        if (best >= 0 && score >= best) continue;
+        best = score;
+        // store sorted by (block, k0)
+        int order[kMaxUnits];
+        for (int i = 0; i < np; ++i) order[i] = i;
+        for (int i = 1; i < np; ++i)
+            for (int j = i; j > 0; --j) {
+                const Piece& a = pc[order[j - 1]];
+                const Piece& c = pc[order[j]];
+                if (c.b < a.b || (c.b == a.b && c.k0 < a.k0)) {
+                    const int t = order[j - 1];
+                    order[j - 1] = order[j];
+                    order[j] = t;
+                } else {
+                    break;
+                }
+            }
+        for (int i = 0; i < kMaxUnits; ++i) u.wave_unit[i] = -1;
+        for (int i = 0; i < np; ++i) {
+            const Piece& c = pc[order[i]];
+            u.blk[i] = int16_t(c.b);
+            u.k0[i] = int16_t(c.k0);
+            u.k1[i] = int16_t(c.k1);
+            u.wave_unit[owner[order[i]] * kUnitSlots + slot[order[i]]] = int8_t(i);
+        }
+        for (int b = 0, i = 0; b <= nblk; ++b) {
+            while (i < np && u.blk[i] < b) ++i;
+            u.first[b] = int16_t(i);
+        }
+        u.n = np;
+    }
+    return best >= 0;
+}
+
 typedef __attribute__((address_space(4))) const double* CDouble;
 typedef __attribute__((address_space(4))) const uint32_t* CUint;
 
@@ -605,15 +732,17 @@ typedef __attribute__((address_space(4))) const uint32_t* CUint;
 // degree order, so the lanes of a wavefront walk the same k, whose M_k and grid index are
 // uniform (scalar loads), and a lane past its prefix reads the zero.  Per lane and k: one LDS
 // read and three FMAs.  The groups' sums are added in group order at the end (deterministic).
-// Low orders take several 256-lane groups (interactions in parallel); high orders, whose grids
-// fill the LDS, one group of up to 1024 lanes (terms in parallel), which (MLDS) also stages the
-// source cell's moments and the terms' grid indices in LDS, so that the walk over k reads
-// LDS (in order, pipelined) instead of waiting on a batch of scalar loads every eight steps.
+// Low orders take several 256-lane groups (interactions in parallel).  High orders, whose grids
+// fill the LDS, take one group of kUnitWaves wavefronts (MLDS), which also stages the source
+// cell's moments and the terms' grid indices in LDS, so that the walk over k reads LDS (in
+// order, pipelined) instead of waiting on a batch of scalar loads every eight steps; there the
+// walks of the blocks of 64 terms are cut into pieces dealt evenly to the wavefronts
+// (M2lUnits), and each term adds its pieces' partial sums in k order at the end.
 template <int SLOTS, bool MLDS>
 __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __restrict__ count, int l,
                                                   const double* __restrict__ box, int p,
                                                   const uint32_t* __restrict__ terms, const double* __restrict__ dtab,
-                                                  int glanes) {
+                                                  int glanes, const M2lUnits units) {
     const int cell = blockIdx.x;
     const int ncell = *count;
     if (cell >= ncell) return;
@@ -673,98 +802,174 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l(FmmLevel lv, const int32_t* __
         for (int t = gt; t < nt + kM2lOverrun; t += glanes) sG[t] = t < nt ? int(terms[kMaxTerms + t]) : 0;
         if (gt < kM2lOverrun) sM[3 * nt + gt] = 0.0;
     }
-    int nb[SLOTS], cnt[SLOTS], smax[SLOTS], deg[SLOTS];
-    double acc[SLOTS][3];
+    if constexpr (MLDS) {
+        // one group of kUnitWaves wavefronts; wavefront w walks the pieces units.wave_unit[w][.]
+        const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = int(threadIdx.x) & 63;
+        int uid[kUnitSlots], nb[kUnitSlots], lim[kUnitSlots], k0[kUnitSlots], k1[kUnitSlots];
+        double acc[kUnitSlots][3];
 #pragma unroll
-    for (int j = 0; j < SLOTS; ++j) {
-        const int t = gt + glanes * j;
-        nb[j] = 0;
-        cnt[j] = 0;
-        deg[j] = 0;
-        if (t < nt) {
-            const uint32_t k = terms[t];
-            deg[j] = int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16);
-            nb[j] = int(terms[kMaxTerms + t]);
-            cnt[j] = nterms(p - deg[j]);
-        }
-        // lane 0 of the wavefront owns its lowest degree, hence the longest prefix
-        smax[j] = __builtin_amdgcn_readfirstlane(cnt[j]);
-        for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
-    }
-    __syncthreads();
-    const int rounds = (nlist + ngroup - 1) / ngroup;
-    for (int r = 0; r < rounds; ++r) {
-        const int e = r * ngroup + grp;
-        const bool has = e < nlist;
-        __syncthreads();
-        if (has) {
-            const double* D = dtab + int64_t(list_off[e]) * nt;
-            for (int t = gt; t < nt; t += glanes) {
-                const uint32_t k = terms[t];
-                sDg[terms[kMaxTerms + t]] = D[t] * sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
+        for (int j = 0; j < kUnitSlots; ++j) {
+            uid[j] = units.wave_unit[wave * kUnitSlots + j];
+            nb[j] = 0;
+            lim[j] = 0;
+            k0[j] = 0;
+            k1[j] = 0;
+            if (uid[j] >= 0) {
+                k0[j] = units.k0[uid[j]];
+                k1[j] = units.k1[uid[j]];
+                const int t = 64 * int(units.blk[uid[j]]) + lane;
+                if (t < nt) {
+                    const uint32_t k = terms[t];
+                    const int dg = int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16);
+                    nb[j] = int(terms[kMaxTerms + t]);
+                    const int c = nterms(p - dg);
+                    lim[j] = c < k1[j] ? c : k1[j];
+                }
             }
-            if constexpr (MLDS) {
+            for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
+        }
+        __syncthreads();
+        for (int e = 0; e < nlist; ++e) {
+            __syncthreads();
+            {
+                const double* D = dtab + int64_t(list_off[e]) * nt;
+                for (int t = gt; t < nt; t += glanes) {
+                    const uint32_t k = terms[t];
+                    sDg[terms[kMaxTerms + t]] = D[t] * sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
+                }
                 const double* Ms = lv.M + int64_t(list_src[e]) * 3 * nt;
                 for (int t = gt; t < 3 * nt; t += glanes) sM[t] = Ms[t];
             }
-        }
-        __syncthreads();
-        if (!has) continue;
-        const int src = __builtin_amdgcn_readfirstlane(list_src[e]);
-        const CDouble M0 = (CDouble)(lv.M + int64_t(src) * 3 * nt);
+            __syncthreads();
 #pragma unroll
-        for (int j = 0; j < SLOTS; ++j) {
-            // 8 steps per batch of scalar loads, which may read up to 7 terms past a lane's
-            // prefix; those lanes multiply by the zero.  Past a cell's first two components the
-            // reads find the next component's moments, past the third the next cell's, or the
-            // zeros that the moments' writers leave after the level's last cell: always finite.
-            for (int s0 = 0; s0 < smax[j]; s0 += 8) {
-                int ks[8];
-                double m[3][8];
+            for (int j = 0; j < kUnitSlots; ++j) {
+                // the piece's k range in batches of eight: the batch may read up to seven terms
+                // past k1 (into the zeros after the staged moments and grid indices), and lanes
+                // past their own limit read the zero after the grid
+                for (int s0 = k0[j]; s0 < k1[j]; s0 += 8) {
+                    int ks[8];
+                    double m[3][8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    if constexpr (MLDS) {  // the same reads from LDS (its zeros past the ends)
+                    for (int i = 0; i < 8; ++i) {
                         ks[i] = sG[s0 + i];
                         m[0][i] = sM[s0 + i];
                         m[1][i] = sM[nt + s0 + i];
                         m[2][i] = sM[2 * nt + s0 + i];
-                    } else {
+                    }
+                    double Dv[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) Dv[i] = sDg[s0 + i < lim[j] ? nb[j] + ks[i] : zero_at];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        acc[j][0] += Dv[i] * m[0][i];
+                        acc[j][1] += Dv[i] * m[1][i];
+                        acc[j][2] += Dv[i] * m[2][i];
+                    }
+                }
+            }
+        }
+        // each piece's partial sums through LDS (64 lanes x 3 per piece), then every term adds
+        // its block's pieces in k order
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kUnitSlots; ++j)
+            if (uid[j] >= 0)
+                for (int d = 0; d < 3; ++d) sDyn[(uid[j] * 64 + lane) * 3 + d] = acc[j][d];
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 3 * nt; idx += blockDim.x) {
+            const int d = idx / nt, t = idx - d * nt;
+            const int b = t >> 6, ln = t & 63;
+            double v = 0.0;
+            for (int q = units.first[b]; q < units.first[b + 1]; ++q) v += sDyn[(q * 64 + ln) * 3 + d];
+            const uint32_t k = terms[t];
+            const int dg = int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16);
+            const double f = ((dg & 1) ? -kInv4Pi : kInv4Pi) / w;
+            lv.L[(int64_t(cell) * 3 + d) * nt + t] = v * f;
+        }
+        return;
+    } else {
+        int nb[SLOTS], cnt[SLOTS], smax[SLOTS], deg[SLOTS];
+        double acc[SLOTS][3];
+#pragma unroll
+        for (int j = 0; j < SLOTS; ++j) {
+            const int t = gt + glanes * j;
+            nb[j] = 0;
+            cnt[j] = 0;
+            deg[j] = 0;
+            if (t < nt) {
+                const uint32_t k = terms[t];
+                deg[j] = int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16);
+                nb[j] = int(terms[kMaxTerms + t]);
+                cnt[j] = nterms(p - deg[j]);
+            }
+            // lane 0 of the wavefront owns its lowest degree, hence the longest prefix
+            smax[j] = __builtin_amdgcn_readfirstlane(cnt[j]);
+            for (int d = 0; d < 3; ++d) acc[j][d] = 0.0;
+        }
+        __syncthreads();
+        const int rounds = (nlist + ngroup - 1) / ngroup;
+        for (int r = 0; r < rounds; ++r) {
+            const int e = r * ngroup + grp;
+            const bool has = e < nlist;
+            __syncthreads();
+            if (has) {
+                const double* D = dtab + int64_t(list_off[e]) * nt;
+                for (int t = gt; t < nt; t += glanes) {
+                    const uint32_t k = terms[t];
+                    sDg[terms[kMaxTerms + t]] = D[t] * sc[int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16)];
+                }
+            }
+            __syncthreads();
+            if (!has) continue;
+            const int src = __builtin_amdgcn_readfirstlane(list_src[e]);
+            const CDouble M0 = (CDouble)(lv.M + int64_t(src) * 3 * nt);
+#pragma unroll
+            for (int j = 0; j < SLOTS; ++j) {
+                // 8 steps per batch of scalar loads, which may read up to 7 terms past a lane's
+                // prefix; those lanes multiply by the zero.  Past a cell's first two components the
+                // reads find the next component's moments, past the third the next cell's, or the
+                // zeros that the moments' writers leave after the level's last cell: always finite.
+                for (int s0 = 0; s0 < smax[j]; s0 += 8) {
+                    int ks[8];
+                    double m[3][8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
                         ks[i] = int(gidx[s0 + i]);
                         m[0][i] = M0[s0 + i];
                         m[1][i] = M0[nt + s0 + i];
                         m[2][i] = M0[2 * nt + s0 + i];
                     }
-                }
-                // lanes past their prefix read the zero after the grid (no branch, so that the
-                // eight reads are in flight together)
-                double Dv[8];
+                    // lanes past their prefix read the zero after the grid (no branch, so that the
+                    // eight reads are in flight together)
+                    double Dv[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) Dv[i] = sDg[s0 + i < cnt[j] ? nb[j] + ks[i] : zero_at];
+                    for (int i = 0; i < 8; ++i) Dv[i] = sDg[s0 + i < cnt[j] ? nb[j] + ks[i] : zero_at];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    acc[j][0] += Dv[i] * m[0][i];
-                    acc[j][1] += Dv[i] * m[1][i];
-                    acc[j][2] += Dv[i] * m[2][i];
+                    for (int i = 0; i < 8; ++i) {
+                        acc[j][0] += Dv[i] * m[0][i];
+                        acc[j][1] += Dv[i] * m[1][i];
+                        acc[j][2] += Dv[i] * m[2][i];
+                    }
                 }
             }
         }
-    }
-    // add the groups' sums in group order through LDS (3 nt doubles per group)
-    __syncthreads();
-    for (int j = 0; j < SLOTS; ++j) {
-        const int t = gt + glanes * j;
-        if (t >= nt) break;
-        for (int d = 0; d < 3; ++d) sDyn[(grp * 3 + d) * nt + t] = acc[j][d];
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < 3 * nt; idx += blockDim.x) {
-        const int d = idx / nt, t = idx - d * nt;
-        double v = 0.0;
-        for (int g2 = 0; g2 < ngroup; ++g2) v += sDyn[(g2 * 3 + d) * nt + t];
-        const uint32_t k = terms[t];
-        const int dg = int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16);
-        const double f = ((dg & 1) ? -kInv4Pi : kInv4Pi) / w;
-        lv.L[(int64_t(cell) * 3 + d) * nt + t] = v * f;
+        // add the groups' sums in group order through LDS (3 nt doubles per group)
+        __syncthreads();
+        for (int j = 0; j < SLOTS; ++j) {
+            const int t = gt + glanes * j;
+            if (t >= nt) break;
+            for (int d = 0; d < 3; ++d) sDyn[(grp * 3 + d) * nt + t] = acc[j][d];
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 3 * nt; idx += blockDim.x) {
+            const int d = idx / nt, t = idx - d * nt;
+            double v = 0.0;
+            for (int g2 = 0; g2 < ngroup; ++g2) v += sDyn[(g2 * 3 + d) * nt + t];
+            const uint32_t k = terms[t];
+            const int dg = int(k & 0xff) + int((k >> 8) & 0xff) + int(k >> 16);
+            const double f = ((dg & 1) ? -kInv4Pi : kInv4Pi) / w;
+            lv.L[(int64_t(cell) * 3 + d) * nt + t] = v * f;
+        }
     }
 }
 
@@ -1359,22 +1564,26 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // M2L: as many groups of 256 lanes as 60 KiB of LDS allow (at most 4), each holding its grid
     // (or its 3 nt sums at the end if those are larger); where fewer than two fit, one group of
-    // as many wavefronts as the terms fill (up to 1024 lanes, at most two terms per lane)
+    // kUnitWaves wavefronts that share the terms' walks in balanced pieces (m2l_units)
     const size_t m2l_grid = size_t(m2l_group_doubles(p, false)) * sizeof(double);
     int m2l_groups = int((60 * 1024) / m2l_grid);
     m2l_groups = m2l_groups > 4 ? 4 : m2l_groups;
     int m2l_gsize = 256;
+    M2lUnits units{};
+    size_t m2l_lds = size_t(m2l_groups) * m2l_grid;
     if (m2l_groups < 2) {
         m2l_groups = 1;
-        const int half = (nterms(p) + 1) / 2;  // two terms per lane
-        m2l_gsize = ((half + 63) / 64) * 64;
-        m2l_gsize = m2l_gsize < 256 ? 256 : (m2l_gsize > 1024 ? 1024 : m2l_gsize);
+        m2l_gsize = 64 * kUnitWaves;
+        if (!m2l_units(p, units)) return hipErrorInvalidValue;
+        // the group's grid, moments and indices, or the pieces' partial sums at the end
+        const size_t grid = size_t(m2l_group_doubles(p, true));
+        const size_t sums = size_t(units.n) * 64 * 3;
+        m2l_lds = (grid > sums ? grid : sums) * sizeof(double);
+    } else if (nterms(p) > 5 * m2l_gsize) {
+        // every term has a lane: 5 per lane in 256-lane groups (two or more groups fit only
+        // while 3 nt doubles take at most 30 KiB, nt <= 1280)
+        return hipErrorInvalidValue;
     }
-    // every term has a lane: 5 per lane in 256-lane groups (two or more groups fit only while
-    // 3 nt doubles take at most 30 KiB, nt <= 1280), 2 per lane in the single group
-    if (nterms(p) > (m2l_gsize == 256 ? 5 : 2) * m2l_gsize) return hipErrorInvalidValue;
-    const size_t m2l_lds = m2l_gsize == 256 ? size_t(m2l_groups) * m2l_grid
-                                            : size_t(m2l_group_doubles(p, true)) * sizeof(double);
     const size_t shift_lds = size_t(6 * nterms(p)) * sizeof(double);  // M2M and L2L: two 3 nt buffers
     if (level >= 2) {
         hipLaunchKernelGGL(k_fmm_dtab, dim3(kOffsets), dim3(256), 0, st, p, terms, dtab);
@@ -1390,10 +1599,10 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
         for (int l = 2; l <= level; ++l) {
             if (m2l_gsize == 256)
                 hipLaunchKernelGGL((k_fmm_m2l<5, false>), dim3(unsigned(y.cap[l])), dim3(256 * m2l_groups), m2l_lds, st, lv[l],
-                               counts + l, l, box, p, terms, dtab, m2l_gsize);
+                               counts + l, l, box, p, terms, dtab, m2l_gsize, units);
             else
                 hipLaunchKernelGGL((k_fmm_m2l<2, true>), dim3(unsigned(y.cap[l])), dim3(m2l_gsize), m2l_lds, st, lv[l],
-                               counts + l, l, box, p, terms, dtab, m2l_gsize);
+                               counts + l, l, box, p, terms, dtab, m2l_gsize, units);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if (l >= 3) {
                 hipLaunchKernelGGL(k_fmm_l2l, dim3(unsigned(y.cap[l])), dim3(256), shift_lds, st, lv[l], lv[l - 1],

@@ -22,11 +22,11 @@ def _wake(n, kind, seed_n=None):
 
 
 @pytest.mark.parametrize("kind", KINDS)
-# orders 1 and 2: the M2L's per-group sums outgrow its LDS grid; 14 to 20: one group per
-# workgroup (above 16: more than four terms per lane, grids beyond 64 KiB); depth 7: mostly
-# single-particle leaves
+# orders 1 and 2: the M2L's per-group sums outgrow its LDS grid; 15 to 20: one group per
+# workgroup whose wavefronts share the terms' walks in pieces (every such order, grids beyond
+# 64 KiB from 18 on); depth 7: mostly single-particle leaves
 @pytest.mark.parametrize("level,order", [(2, 4), (3, 8), (4, 6), (4, 12), (6, 5), (3, 1), (3, 2), (3, 16), (5, 14),
-                                         (7, 3), (3, 18), (2, 20), (3, 20)])
+                                         (7, 3), (3, 18), (2, 20), (3, 20), (2, 15), (2, 17), (2, 19)])
 def test_fmm_matches_oracle_fmm(kind, level, order, gpu):
     x, g, s = _wake(4999, kind)
     say(f"fmm {kind} level={level} order={order}")
