@@ -1068,80 +1068,100 @@ struct NearArgs {
 // Far field at the targets of one work item from their leaf's local expansion (FP64):
 // far[0..2] = curl psi, far[3..5] = J^T Gamma_i (transposed) or J Gamma_i (classical),
 // far[6..14] = J (row-major) when the gradient is wanted.
+// Two targets per lane (the item's targets t0 + tid and t0 + tid + 128, 128 lanes): every
+// coefficient read from LDS (a broadcast, all lanes walk the same terms) serves both, which
+// halves the LDS traffic that bounds this kernel (27 reads per term and target before).
+constexpr int kL2pLanes = 128;
 template <typename T, bool CLASSICAL>
-__global__ __launch_bounds__(256) void k_fmm_l2p(NearArgs a, double* __restrict__ far) {
+__global__ __launch_bounds__(kL2pLanes) void k_fmm_l2p(NearArgs a, double* __restrict__ far) {
     const int item = blockIdx.x;
     if (item >= *a.nitems) return;
     const T* __restrict__ xs = static_cast<const T*>(a.xs);
     const T* __restrict__ gs = static_cast<const T*>(a.gs);
     const int64_t n = a.n;
     const int leaf = a.item_leaf[item];
-    const int q = a.item_t0[item] + int(threadIdx.x);
+    const int q0 = a.item_t0[item] + int(threadIdx.x);
+    const int qend = a.leaf.pstart[leaf + 1];
     const int nt = nterms(a.p);
     extern __shared__ double sLx[];  // the leaf's expansion, [3][nt] (dynamic: 3 nt doubles)
-    for (int t = threadIdx.x; t < nt; t += 256)
+    for (int t = threadIdx.x; t < nt; t += kL2pLanes)
         for (int d = 0; d < 3; ++d) sLx[d * nt + t] = a.leaf.L[(int64_t(leaf) * 3 + d) * nt + t];
     __syncthreads();
-    if (q >= a.leaf.pstart[leaf + 1]) return;
+    if (q0 >= qend) return;
     int ic[3];
     cell_coords(a.leaf.code[leaf], ic);
-    double av[3];
-    for (int d = 0; d < 3; ++d) av[d] = double(xs[d * n + q]) - cell_centre(a.box, d, ic[d], a.level);
-    double gp[3][3], hp[6][3];  // d_b psi_c; d_e d_b psi_c for (e, b) in xx yy zz xy xz yz
-    for (int b = 0; b < 3; ++b)
-        for (int c = 0; c < 3; ++c) gp[b][c] = 0.0;
-    for (int m = 0; m < 6; ++m)
-        for (int c = 0; c < 3; ++c) hp[m][c] = 0.0;
+    // the second target repeats the first where the item ends (computed, not written)
+    const int qs[2] = {q0, q0 + kL2pLanes < qend ? q0 + kL2pLanes : q0};
+    double av[2][3];
+    for (int r = 0; r < 2; ++r)
+        for (int d = 0; d < 3; ++d) av[r][d] = double(xs[d * n + qs[r]]) - cell_centre(a.box, d, ic[d], a.level);
+    double gp[2][3][3], hp[2][6][3];  // d_b psi_c; d_e d_b psi_c for (e, b) in xx yy zz xy xz yz
+    for (int r = 0; r < 2; ++r) {
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) gp[r][b][c] = 0.0;
+        for (int m = 0; m < 6; ++m)
+            for (int c = 0; c < 3; ++c) hp[r][m][c] = 0.0;
+    }
     const int p = a.p;
-    double px = 1.0;
+    double px[2] = {1.0, 1.0};
     for (int n0 = 0; n0 <= p - 1; ++n0) {
-        double pxy = px;
+        double pxy[2] = {px[0], px[1]};
         for (int n1 = 0; n1 <= p - 1 - n0; ++n1) {
-            double mono = pxy;
+            double mono[2] = {pxy[0], pxy[1]};
             for (int n2 = 0; n2 <= p - 1 - n0 - n1; ++n2) {
                 const int i0 = mpos(n0 + 1, n1, n2), i1 = mpos(n0, n1 + 1, n2), i2 = mpos(n0, n1, n2 + 1);
                 for (int c = 0; c < 3; ++c) {
-                    gp[0][c] += sLx[c * nt + i0] * mono;
-                    gp[1][c] += sLx[c * nt + i1] * mono;
-                    gp[2][c] += sLx[c * nt + i2] * mono;
+                    const double l0 = sLx[c * nt + i0], l1 = sLx[c * nt + i1], l2 = sLx[c * nt + i2];
+                    for (int r = 0; r < 2; ++r) {
+                        gp[r][0][c] += l0 * mono[r];
+                        gp[r][1][c] += l1 * mono[r];
+                        gp[r][2][c] += l2 * mono[r];
+                    }
                 }
                 if (n0 + n1 + n2 <= p - 2) {
                     const int h[6] = {mpos(n0 + 2, n1, n2), mpos(n0, n1 + 2, n2), mpos(n0, n1, n2 + 2),
                                       mpos(n0 + 1, n1 + 1, n2), mpos(n0 + 1, n1, n2 + 1), mpos(n0, n1 + 1, n2 + 1)};
                     for (int m = 0; m < 6; ++m)
-                        for (int c = 0; c < 3; ++c) hp[m][c] += sLx[c * nt + h[m]] * mono;
+                        for (int c = 0; c < 3; ++c) {
+                            const double lv = sLx[c * nt + h[m]];
+                            for (int r = 0; r < 2; ++r) hp[r][m][c] += lv * mono[r];
+                        }
                 }
-                mono = mono * av[2] * kInvInt[n2 + 1];
+                for (int r = 0; r < 2; ++r) mono[r] = mono[r] * av[r][2] * kInvInt[n2 + 1];
             }
-            pxy = pxy * av[1] * kInvInt[n1 + 1];
+            for (int r = 0; r < 2; ++r) pxy[r] = pxy[r] * av[r][1] * kInvInt[n1 + 1];
         }
-        px = px * av[0] * kInvInt[n0 + 1];
+        for (int r = 0; r < 2; ++r) px[r] = px[r] * av[r][0] * kInvInt[n0 + 1];
     }
-    auto H = [&](int e, int b, int c) -> double {
-        if (e == b) return hp[e][c];
-        const int lo2 = e < b ? e : b, hi2 = e < b ? b : e;
-        const int m = (lo2 == 0 && hi2 == 1) ? 3 : ((lo2 == 0 && hi2 == 2) ? 4 : 5);
-        return hp[m][c];
-    };
-    // u_a = eps_abc d_b psi_c;  J_ae = eps_abc d_e d_b psi_c
-    far[q] = gp[1][2] - gp[2][1];
-    far[n + q] = gp[2][0] - gp[0][2];
-    far[2 * n + q] = gp[0][1] - gp[1][0];
-    double J[3][3];
-    for (int e = 0; e < 3; ++e) {
-        J[0][e] = H(e, 1, 2) - H(e, 2, 1);
-        J[1][e] = H(e, 2, 0) - H(e, 0, 2);
-        J[2][e] = H(e, 0, 1) - H(e, 1, 0);
+    for (int r = 0; r < 2; ++r) {
+        const int q = qs[r];
+        if (r == 1 && q == q0) break;  // no second target in this lane
+        auto H = [&](int e, int b, int c) -> double {
+            if (e == b) return hp[r][e][c];
+            const int lo2 = e < b ? e : b, hi2 = e < b ? b : e;
+            const int m = (lo2 == 0 && hi2 == 1) ? 3 : ((lo2 == 0 && hi2 == 2) ? 4 : 5);
+            return hp[r][m][c];
+        };
+        // u_a = eps_abc d_b psi_c;  J_ae = eps_abc d_e d_b psi_c
+        far[q] = gp[r][1][2] - gp[r][2][1];
+        far[n + q] = gp[r][2][0] - gp[r][0][2];
+        far[2 * n + q] = gp[r][0][1] - gp[r][1][0];
+        double J[3][3];
+        for (int e = 0; e < 3; ++e) {
+            J[0][e] = H(e, 1, 2) - H(e, 2, 1);
+            J[1][e] = H(e, 2, 0) - H(e, 0, 2);
+            J[2][e] = H(e, 0, 1) - H(e, 1, 0);
+        }
+        const double Gi[3] = {double(gs[q]), double(gs[n + q]), double(gs[2 * n + q])};
+        for (int c = 0; c < 3; ++c) {
+            double sum = 0.0;
+            for (int b = 0; b < 3; ++b) sum += (CLASSICAL ? J[c][b] : J[b][c]) * Gi[b];
+            far[(3 + c) * n + q] = sum;
+        }
+        if (a.grad)
+            for (int c = 0; c < 3; ++c)
+                for (int e = 0; e < 3; ++e) far[(6 + 3 * c + e) * n + q] = J[c][e];
     }
-    const double Gi[3] = {double(gs[q]), double(gs[n + q]), double(gs[2 * n + q])};
-    for (int c = 0; c < 3; ++c) {
-        double sum = 0.0;
-        for (int b = 0; b < 3; ++b) sum += (CLASSICAL ? J[c][b] : J[b][c]) * Gi[b];
-        far[(3 + c) * n + q] = sum;
-    }
-    if (a.grad)
-        for (int c = 0; c < 3; ++c)
-            for (int e = 0; e < 3; ++e) far[(6 + 3 * c + e) * n + q] = J[c][e];
 }
 
 // Keeps a value opaque to the optimiser (emits no instruction).
@@ -1638,9 +1658,9 @@ hipError_t run_fmm(int64_t n, const T* x, const T* g, const T* sg, int64_t ld, i
         double* far = reinterpret_cast<double*>(ws + y.far);
         const size_t l2p_lds = size_t(3 * nterms(p)) * sizeof(double);
         if (classical)
-            hipLaunchKernelGGL((k_fmm_l2p<T, true>), dim3(grid), dim3(256), l2p_lds, st, na, far);
+            hipLaunchKernelGGL((k_fmm_l2p<T, true>), dim3(grid), dim3(kL2pLanes), l2p_lds, st, na, far);
         else
-            hipLaunchKernelGGL((k_fmm_l2p<T, false>), dim3(grid), dim3(256), l2p_lds, st, na, far);
+            hipLaunchKernelGGL((k_fmm_l2p<T, false>), dim3(grid), dim3(kL2pLanes), l2p_lds, st, na, far);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         na.far = far;
     }
