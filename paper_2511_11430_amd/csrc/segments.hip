@@ -9,8 +9,12 @@
 // Identities used per pair: r1 x r2 = r0 x r1 and r0 . r2 = r0 . r1 - |r0|^2.
 //
 // Schedule: like the particle kernel, K targets per lane, segment tiles staged in LDS with
-// per-segment constants (Gamma / (4 pi |r0|^2), r0, |r0|^2, the degeneracy threshold), and
-// FP32 tile partials folded into two-sum pairs (VPM_F32C) or plain FP64 sums (VPM_F64).
+// per-segment constants (Gamma / (4 pi |r0|^2), r0, |r0|^2, 1/|r0|^2, -r0_y, -r0_z, the
+// degeneracy threshold), and FP32 tile partials folded into two-sum pairs (VPM_F32C) or plain
+// FP64 sums (VPM_F64).  As in the particle kernel, the cross product is sign-folded: with
+// r1' = (r1_x, -r1_y, r1_z) and the staged -r0_y, -r0_z every component of
+// c' = (c_x, -c_y, -c_z) and the dot product r0 . r1 are multiplies and accumulating
+// multiply-adds, and the sums hold u_y and u_z negated until the epilogue.
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
@@ -42,7 +46,7 @@ __global__ __launch_bounds__(WG) void k_segments(SegArgs a) {
     constexpr bool kComp = std::is_same<T, float>::value;
     __shared__ V4<T> l0[WG];  // (ax, ay, az, coef)   coef = Gamma / (4 pi |r0|^2)  (rc == 0: Gamma/(4 pi))
     __shared__ V4<T> l1[WG];  // (r0x, r0y, r0z, |r0|^2)
-    __shared__ T l2[WG];      // eps^2 for the arms
+    __shared__ V4<T> l2[WG];  // (eps^2 for the arms, 1/|r0|^2, -r0y, -r0z)
     const T* __restrict__ A = static_cast<const T*>(a.a);
     const T* __restrict__ B = static_cast<const T*>(a.b);
     const T* __restrict__ Gs = static_cast<const T*>(a.gam);
@@ -94,27 +98,34 @@ __global__ __launch_bounds__(WG) void k_segments(SegArgs a) {
             q.x = r0x; q.y = r0y; q.z = r0z; q.w = dead ? T(1) : L02;
             l0[tid] = p;
             l1[tid] = q;
-            l2[tid] = eps * eps;
+            V4<T> e;
+            e.x = eps * eps;
+            e.y = T(1) / q.w;
+            e.z = -r0y;
+            e.w = -r0z;
+            l2[tid] = e;
         }
         __syncthreads();
 #pragma unroll 2
         for (int jj = 0; jj < cnt; ++jj) {
             const V4<T> p = l0[jj];
             const V4<T> q = l1[jj];
-            const T eps2 = l2[jj];
-            const T inv_l02 = T(1) / q.w;
+            const V4<T> e = l2[jj];
+            const T eps2 = e.x;
+            const T inv_l02 = e.y;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const T r1x = P[k][0] - p.x, r1y = P[k][1] - p.y, r1z = P[k][2] - p.z;
-                const T r2x = r1x - q.x, r2y = r1y - q.y, r2z = r1z - q.z;
-                // r1 x r2 = r0 x r1
-                const T cx = q.y * r1z - q.z * r1y;
-                const T cy = q.z * r1x - q.x * r1z;
-                const T cz = q.x * r1y - q.y * r1x;
-                const T c2 = cx * cx + cy * cy + cz * cz;
-                const T l1s = r1x * r1x + r1y * r1y + r1z * r1z;
-                const T l2s = r2x * r2x + r2y * r2y + r2z * r2z;
-                const T d1 = q.x * r1x + q.y * r1y + q.z * r1z;
+                // r1' = (r1_x, -r1_y, r1_z), r2' likewise
+                const T r1x = P[k][0] - p.x, r1yn = p.y - P[k][1], r1z = P[k][2] - p.z;
+                const T r2x = r1x - q.x, r2yn = r1yn + q.y, r2z = r1z - q.z;
+                // r1 x r2 = r0 x r1, held as c' = (c_x, -c_y, -c_z)
+                const T cx = q.y * r1z + q.z * r1yn;
+                const T cyn = q.x * r1z + e.w * r1x;
+                const T czn = q.y * r1x + q.x * r1yn;
+                const T c2 = cx * cx + cyn * cyn + czn * czn;
+                const T l1s = r1x * r1x + r1yn * r1yn + r1z * r1z;
+                const T l2s = r2x * r2x + r2yn * r2yn + r2z * r2z;
+                const T d1 = q.x * r1x + e.z * r1yn + q.z * r1z;
                 const T d2 = d1 - q.w;
                 const T D = d1 * rsqrt_fast(l1s) - d2 * rsqrt_fast(l2s);
                 T f;
@@ -125,8 +136,8 @@ __global__ __launch_bounds__(WG) void k_segments(SegArgs a) {
                 }
                 f = (l1s < eps2 || l2s < eps2) ? T(0) : f;
                 acc[k][0] += f * cx;
-                acc[k][1] += f * cy;
-                acc[k][2] += f * cz;
+                acc[k][1] += f * cyn;
+                acc[k][2] += f * czn;
             }
         }
         if constexpr (kComp) {
@@ -149,7 +160,8 @@ __global__ __launch_bounds__(WG) void k_segments(SegArgs a) {
         const int64_t t = t0 + tid + int64_t(k) * WG;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double v = kComp ? double(hi[k][c]) + double(lo[k][c]) : double(acc[k][c]);
+            // (the sums hold u_y and u_z negated)
+            const double v = (c == 0 ? 1.0 : -1.0) * (kComp ? double(hi[k][c]) + double(lo[k][c]) : double(acc[k][c]));
             T* dst = U + c * a.ldo + t;
             *dst = a.accumulate ? T(double(*dst) + v) : T(v);
         }
