@@ -26,6 +26,8 @@ namespace {
 
 template <typename T>
 using V4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
+template <typename T>
+using V2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
 
 // VN: 0 = no core (rc == 0), 1, 2 = Vatistas exponent, 3 = general exponent n.
 template <typename T, int VN>
@@ -359,7 +361,7 @@ __device__ __forceinline__ void seg_pair(const S (&P)[3], const V4<T>& p, const 
 // Stages one tile of segments in LDS (shared by the gradient and adjoint kernels).
 template <typename T, int WG, int VN>
 __device__ __forceinline__ void stage_segments(const SegArgs& a, int64_t j0, int cnt, V4<T>* l0, V4<T>* l1,
-                                               T* l2) {
+                                               V2<T>* l2) {
     const int tid = threadIdx.x;
     if (tid < cnt) {
         const T* __restrict__ A = static_cast<const T*>(a.a);
@@ -380,7 +382,10 @@ __device__ __forceinline__ void stage_segments(const SegArgs& a, int64_t j0, int
         q.x = r0x; q.y = r0y; q.z = r0z; q.w = dead ? T(1) : L02;
         l0[tid] = p;
         l1[tid] = q;
-        l2[tid] = eps * eps;
+        V2<T> e;
+        e.x = eps * eps;
+        e.y = T(1) / q.w;
+        l2[tid] = e;
     }
 }
 
@@ -417,7 +422,7 @@ __global__ __launch_bounds__(WG) void k_segments_grad(SegArgs a) {
     constexpr int kSlots = WG / LPT;  // targets per workgroup and K
     __shared__ V4<T> l0[WG];
     __shared__ V4<T> l1[WG];
-    __shared__ T l2[WG];
+    __shared__ V2<T> l2[WG];  // (eps^2 for the arms, 1/|r0|^2)
     const T* __restrict__ X = static_cast<const T*>(a.xt);
     const int tid = threadIdx.x / LPT, q = threadIdx.x % LPT;
     const int64_t t0 = int64_t(blockIdx.x) * (kSlots * K);
@@ -450,8 +455,8 @@ __global__ __launch_bounds__(WG) void k_segments_grad(SegArgs a) {
         for (int jj = q; jj < cnt; jj += LPT) {
             const V4<T> p = l0[jj];
             const V4<T> q = l1[jj];
-            const T eps2 = l2[jj];
-            const T inv_l02 = T(1) / q.w;
+            const T eps2 = l2[jj].x;
+            const T inv_l02 = l2[jj].y;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 T f, c[3], g[3];
@@ -538,7 +543,7 @@ __global__ __launch_bounds__(WG) void k_segments_vjp(SegArgs a) {
     using S = Dl<T>;
     __shared__ V4<T> l0[WG];
     __shared__ V4<T> l1[WG];
-    __shared__ T l2[WG];
+    __shared__ V2<T> l2[WG];  // (eps^2 for the arms, 1/|r0|^2)
     const T* __restrict__ X = static_cast<const T*>(a.xt);
     const T* __restrict__ Gt = static_cast<const T*>(a.gt);
     const T* __restrict__ Ub = static_cast<const T*>(a.ub);
@@ -576,8 +581,8 @@ __global__ __launch_bounds__(WG) void k_segments_vjp(SegArgs a) {
         for (int jj = 0; jj < cnt; ++jj) {
             const V4<T> p = l0[jj];
             const V4<T> q = l1[jj];
-            const T eps2 = l2[jj];
-            const T inv_l02 = T(1) / q.w;
+            const T eps2 = l2[jj].x;
+            const T inv_l02 = l2[jj].y;
             S f, c[3], g[3];
             seg_pair<S, T, VN>(P, p, q, eps2, inv_l02, rc2n, inv_n, n_f, f, c, g);
             acc[0] += c[0].v * g[0].v;
